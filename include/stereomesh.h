@@ -1,0 +1,235 @@
+/*
+ * stereomesh.h -- C ABI of the MI355X (gfx950) implementation of the iterative
+ * piecewise-planar stereo method of Pillai, Ramalingam and Leonard, "High-Performance
+ * and Tunable Stereo Reconstruction" (ICRA 2016).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - Pointers are DEVICE pointers unless marked [host]. Every buffer is owned by the
+ *   caller; the library keeps no pointer after a call returns, but work it enqueued
+ *   reads and writes the buffers until the stream has been synchronised.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream). Calls are
+ *   asynchronous on that stream except sm_triangulate (host only) and sm_solve
+ *   (which synchronises the stream once per triangulation).
+ * - Images are row-major uint8 with a row pitch `stride` >= W bytes; every per-pixel
+ *   output array is row-major with pitch W elements.
+ * - Every argument is checked before anything is enqueued; a violation returns
+ *   SM_ERR_ARG and enqueues nothing. An output whose capacity `cap` is too small for
+ *   the worst case returns SM_ERR_CAPACITY (and, for host outputs, the required count).
+ *   A failing HIP call returns SM_ERR_HIP. sm_last_error() describes the last non-OK
+ *   status of the calling thread. No C++ exception crosses this interface.
+ * - The library allocates no device memory. sm_solve takes a caller-owned workspace;
+ *   host-side staging (pinned) and triangulation state are cached per thread.
+ * - Degenerate scenes are not errors: fewer than three supports, or only collinear
+ *   ones, give zero triangles, an all-NaN interpolation and an empty mask.
+ * - Image sizes are limited to 3 <= W, H <= 8192 (exact 64-bit geometric predicates).
+ */
+#ifndef STEREOMESH_H
+#define STEREOMESH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SM_OK = 0,
+  SM_ERR_ARG = -1,       /* invalid argument; nothing was enqueued                    */
+  SM_ERR_CAPACITY = -2,  /* an output capacity is below the worst case               */
+  SM_ERR_HIP = -3,       /* a HIP runtime call failed (message in sm_last_error)     */
+  SM_ERR_INTERNAL = -4   /* an internal invariant failed                              */
+} sm_status;
+
+/* Support point s = (u, v, d): pixel coordinates and disparity (Sec. III-A). The
+ * disparity is a float because supports added by resampling carry the interpolated
+ * disparity of their pixel (Alg. 3 records D_it into C_g). 8 bytes. */
+typedef struct {
+  int16_t u, v;
+  float d;
+} sm_support;
+
+/* Triangle of the Delaunay mesh G(S) as three indices into the support array;
+ * counter-clockwise in (u, v) (orient > 0), i0 = the vertex with the smallest (v, u). */
+typedef struct {
+  int32_t i0, i1, i2;
+} sm_tri;
+
+/* Method parameters (the globals of the paper's Table I). */
+typedef struct {
+  int32_t d_min, d_max;        /* searched disparities, inclusive; 0 <= d_min <= d_max <= 255   */
+  int32_t census_w, census_h;  /* census window, odd, >= 3, census_w*census_h - 1 <= 64          */
+  int32_t support_step;        /* pitch of the initial support-candidate grid, px, >= 1          */
+  int32_t n_iters;             /* n_iters of Alg. 1, 1..8                                       */
+  int32_t t_hi;                /* upper cost threshold (Hamming); mask = C_f < t_hi, <= 64      */
+  int32_t t_lo;                /* lower cost threshold (Hamming), 0 <= t_lo <= t_hi             */
+  int32_t grad_thr;            /* Omega_I: L1 central-difference gradient >= grad_thr, >= 0     */
+  int32_t lr_tol;              /* left-right check: |d_LR - d| <= lr_tol, >= 0                  */
+  int32_t uniqueness;          /* reject when a disparity >= 2 away costs < best + uniqueness;
+                                  0 disables the test                                          */
+  int32_t sz_occ0;             /* initial occupancy-grid size (32 in Alg. 1), 1..1024           */
+} sm_params;
+
+/* Per-solve statistics. `timing` is an input: when non-zero, sm_solve records HIP
+ * events around every kernel launch on `stream` and reports device time per stage
+ * (summed over iterations) in stage_us and per-launch counts in stage_launches.
+ * Stage index: 0 census, 1 support matching (initial), 2 interpolation,
+ * 3 validation, 4 resampling (cells, re-matching, compaction), 5 host triangulation
+ * (wall time), 6 host<->device copies and waits (wall time), 7 whole solve (wall). */
+#define SM_STAGES 8
+typedef struct {
+  int32_t timing;                       /* [in]  non-zero: collect stage_us          */
+  int32_t n_support[8];                 /* [out] |S_it| per iteration                 */
+  int32_t n_tris[8];                    /* [out] |G(S_it)| per iteration              */
+  int64_t n_valid;                      /* [out] pixels in the final mask             */
+  float stage_us[SM_STAGES];            /* [out] see above                            */
+  int32_t stage_launches[SM_STAGES];    /* [out] kernel launches per stage            */
+} sm_stats;
+
+/*
+ * sm_census -- census words of one image and, optionally, its high-gradient set.
+ *   Census window match of the cost-evaluation section (Sec. III-C, Zabih and
+ *   Woodfill's census): bit k of the word of pixel p is 1 iff window neighbour k is
+ *   strictly darker than p; neighbours in row-major window order, centre skipped,
+ *   k = 0 the least significant bit. High-gradient subset Omega_I (Sec. III):
+ *   |I(u+1,v) - I(u-1,v)| + |I(u,v+1) - I(u,v-1)| >= grad_thr.
+ *   img      [H][stride] uint8 image.
+ *   census   [H][W] uint64 out; 0 where the window does not fit (u < rx, u >= W-rx,
+ *            v < ry, v >= H-ry with rx = (census_w-1)/2, ry = (census_h-1)/2).
+ *   omega    [H][W] uint8 out, 1 = in Omega_I (only where the window fits); may be NULL.
+ */
+sm_status sm_census(const uint8_t* img, int32_t W, int32_t H, int32_t stride,
+                    int32_t census_w, int32_t census_h, int32_t grad_thr,
+                    uint64_t* census, uint8_t* omega, void* stream);
+
+/*
+ * sm_match_support -- sparse epipolar matching of support candidates (Sec. III-A,
+ *   "SparseStereo" of Alg. 1 and "SparseEpipolarStereo" of Alg. 4).
+ *   For candidate (u, v): d* = argmin over d in [d_min, d_max] with u - d >= rx of
+ *   Hamming(cL(u,v), cR(u-d,v)), ties to the smallest d. Rejected when no d is
+ *   admissible, when cost(d*) >= t_hi, when (uniqueness = m > 0) an admissible d with
+ *   |d - d*| >= 2 costs < cost(d*) + m, or when the right-to-left argmin d' from
+ *   u - d* (over d with u - d* + d <= W-1-rx, ties to the smallest d) has
+ *   |d' - d*| > lr_tol. Candidates whose census window does not fit are rejected.
+ *   cL, cR   [H][W] census words of the left / right image (sm_census).
+ *   omega    [H][W] Omega_I of the left image; required when cand_uv is NULL.
+ *   cand_uv  [n_cand][2] int16 (u, v) candidates, or NULL for the grid
+ *            (support_step/2 + i*support_step, support_step/2 + j*support_step) in raster
+ *            order, restricted to Omega_I (then n_cand is ignored).
+ *   out      [cap] accepted supports (u, v, float(d*)) in candidate order.
+ *            cap must be >= the number of candidates (the worst case), else
+ *            SM_ERR_CAPACITY; out[] beyond the accepted count is scratch.
+ *   n_out    [1] int32 out: number of accepted supports.
+ */
+sm_status sm_match_support(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
+                           int32_t W, int32_t H, const int16_t* cand_uv, int32_t n_cand,
+                           const sm_params* p /* [host] */, sm_support* out, int32_t cap,
+                           int32_t* n_out, void* stream);
+
+/* Number of candidates of the support grid (the capacity sm_match_support needs
+ * when cand_uv is NULL). Host only. */
+int32_t sm_grid_candidates(int32_t W, int32_t H, int32_t support_step);
+
+/*
+ * sm_triangulate -- Delaunay triangulation G(S) of the support pixels (Sec. III-A).
+ *   Exact integer predicates; cocircular ties resolved by symbolic perturbation of
+ *   the lifting z = u^2 + v^2 + eps_i, a smaller raster position (v, u) getting the
+ *   larger eps, which makes the triangulation unique. A pixel that occurs more than
+ *   once is represented by its first occurrence. Synchronous host code.
+ *   S       [host] [n] supports; u, v in [0, 8191].
+ *   tris    [host] [cap] out: triangles, canonical (see sm_tri) and sorted by (i0,i1,i2).
+ *   n_tris  [host] out: triangle count (the required count on SM_ERR_CAPACITY;
+ *           2n - 5 always suffices for n >= 3).
+ */
+sm_status sm_triangulate(const sm_support* S, int32_t n, sm_tri* tris, int32_t cap,
+                         int32_t* n_tris);
+
+/*
+ * sm_interpolate -- DisparityInterpolation (Sec. III-B, Alg. 1): the disparity plane
+ *   of every triangle (Eq. 3, solved through its three supports) evaluated at every
+ *   pixel the triangle owns (the pixel-to-triangle lookup of Sec. III-B).
+ *   Plane: anchor i0 = (u0, v0, d0); with du_k, dv_k the integer offsets of i1, i2
+ *   and det = du1*dv2 - du2*dv1, in float64: a = ((d1-d0)*dv2 - (d2-d0)*dv1)/det,
+ *   b = (du1*(d2-d0) - du2*(d1-d0))/det, each rounded to float32. Pixel (u, v) is owned
+ *   by the triangle containing (u + eps, v + eps^2); there
+ *   D = (d0 + a*float(u-u0)) + b*float(v-v0) in float32 (no fused multiply-add).
+ *   S       [n_support] supports;  T [n_tris] triangles (canonical, as sm_triangulate).
+ *   D_it    [H][W] float32 out; NaN where no triangle owns the pixel.
+ */
+sm_status sm_interpolate(const sm_support* S, int32_t n_support, const sm_tri* T,
+                         int32_t n_tris, int32_t W, int32_t H, float* D_it, void* stream);
+
+/* Number of occupancy cells at grid size sz: ceil(H/sz) * ceil(W/sz). Host only. */
+int32_t sm_cells(int32_t W, int32_t H, int32_t sz_occ);
+
+/*
+ * sm_validate -- CostEvaluation (Alg. 2) and DisparityRefinement (Alg. 3).
+ *   For (u, v) in Omega_I with a finite D_it: d = floor(float32(D_it + 0.5)); when
+ *   d_min <= d <= d_max and u - d >= rx, C_it = Hamming(cL(u,v), cR(u-d,v)), else the
+ *   pixel is not evaluated (C_it = 0xFF). For evaluated pixels: if C_it < C_f then
+ *   D_f = D_it and C_f = C_it. Cells of sz_occ x sz_occ pixels (cell (u/sz, v/sz),
+ *   ceil(W/sz) per row) keep the pixel with the smallest C_it < t_lo (C_g) and the
+ *   one with the largest C_it > t_hi (C_b); ties go to the first pixel in raster order.
+ *   C_it     [H][W] uint8 out (may be NULL).
+ *   D_f, C_f [H][W] float32 / uint8 in-out (start them at 0 and t_hi, Alg. 1).
+ *   cell_g   [sm_cells] uint64 out; key (C_it << 32) | (v*W + u); the "unset" value is
+ *            (t_lo << 32), which no recorded pixel can equal.
+ *   cell_b   [sm_cells] uint64 out; key ((255 - C_it) << 32) | (v*W + u); "unset" is
+ *            ((255 - t_hi) << 32).
+ */
+sm_status sm_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
+                      const float* D_it, int32_t W, int32_t H, const sm_params* p /* [host] */,
+                      int32_t sz_occ, uint8_t* C_it, float* D_f, uint8_t* C_f,
+                      uint64_t* cell_g, uint64_t* cell_b, void* stream);
+
+/*
+ * sm_resample -- SupportResampling (Alg. 4). Cells are visited in raster order: a set
+ *   C_b cell puts its pixel into X, a set C_g cell yields the support
+ *   (u, v, D_it(u, v)); X is matched as in sm_match_support; the new supports are the
+ *   confident ones (cell order) followed by the matched ones (X order), dropping any
+ *   pixel already in S.
+ *   S, n_S   [n_S] current supports (dedup reference).
+ *   occ      [H][W] uint8 scratch (overwritten).
+ *   out      [cap] out: new supports; cap >= 2 * sm_cells(W, H, sz_occ).
+ *   n_out    [1] int32 out: number of new supports.
+ */
+sm_status sm_resample(const uint64_t* cL, const uint64_t* cR, const float* D_it,
+                      const uint64_t* cell_g, const uint64_t* cell_b, int32_t W, int32_t H,
+                      int32_t sz_occ, const sm_params* p /* [host] */,
+                      const sm_support* S, int32_t n_S, uint8_t* occ,
+                      sm_support* out, int32_t cap, int32_t* n_out, void* stream);
+
+/* Workspace sm_solve needs for a W x H frame under p, in bytes (0 on invalid args). */
+size_t sm_solve_workspace_bytes(int32_t W, int32_t H, const sm_params* p /* [host] */);
+
+/*
+ * sm_solve -- Iterative Stereo Reconstruction (Alg. 1) on a rectified pair:
+ *   D_f = 0, C_f = t_hi; S_1 = matched grid supports; G(S_1); then for it = 1..n_iters:
+ *   interpolation, cost evaluation, refinement with sz_occ = max(1, sz_occ0 >> (it-1)),
+ *   and, unless it is the last iteration, resampling and re-triangulation (the new
+ *   supports are inserted into the existing triangulation, which yields the same unique
+ *   triangulation as a rebuild).
+ *   L, R     [H][stride] uint8 left / right images.
+ *   ws       workspace of ws_bytes >= sm_solve_workspace_bytes(W, H, p), 256-byte aligned.
+ *   D_f      [H][W] float32 out (0 where never validated).
+ *   C_f      [H][W] uint8 out.
+ *   mask     [H][W] uint8 out: 1 iff in Omega_I and C_f < t_hi (pixels that passed).
+ *   st       [host] statistics, may be NULL.
+ *   Synchronises `stream` once per triangulation (n_iters times).
+ */
+sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
+                   const sm_params* p /* [host] */, void* ws, size_t ws_bytes, float* D_f,
+                   uint8_t* C_f, uint8_t* mask, sm_stats* st /* [host] */, void* stream);
+
+/* Message of the calling thread's last non-OK status ("" if none). */
+const char* sm_last_error(void);
+
+/* Library version string. */
+const char* sm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STEREOMESH_H */

@@ -1,0 +1,218 @@
+"""Torch-tensor wrappers of the stereomesh C ABI.
+
+PyTorch provides device memory and the current HIP stream; every step of the method
+runs in the library's kernels (or, for the triangulation, its host code). These
+wrappers only allocate outputs, pass pointers and raise on a non-OK status.
+
+Census words are returned as ``torch.int64`` tensors holding the uint64 bit patterns;
+supports live in flat ``uint8`` device buffers of 8-byte records (int16 u, int16 v,
+float32 d) and are converted to NumPy with ``SUPPORT_DTYPE``.
+"""
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check, make_params
+
+SUPPORT_DTYPE = np.dtype([("u", "<i2"), ("v", "<i2"), ("d", "<f4")])
+TRI_DTYPE = np.dtype([("i0", "<i4"), ("i1", "<i4"), ("i2", "<i4")])
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("expected contiguous CUDA (HIP) tensors")
+
+
+def census(img: torch.Tensor, census_w: int, census_h: int, grad_thr: int = 0,
+           with_omega: bool = True, stream=None):
+    """Census words (int64 bit patterns) and Omega_I (uint8) of a uint8 [H, W] image."""
+    _require_cuda(img)
+    H, W = img.shape
+    words = torch.empty((H, W), dtype=torch.int64, device=img.device)
+    omega = torch.empty((H, W), dtype=torch.uint8, device=img.device) if with_omega else None
+    L = _lib.load()
+    check(L.sm_census(img.data_ptr(), W, H, img.stride(0), census_w, census_h, grad_thr,
+                      words.data_ptr(), _ptr(omega), _stream(stream)))
+    return words, omega
+
+
+def new_support_buffer(cap: int, device="cuda") -> torch.Tensor:
+    return torch.empty(max(cap, 1) * 8, dtype=torch.uint8, device=device)
+
+
+def supports_to_numpy(buf: torch.Tensor, n: int) -> np.ndarray:
+    return buf[: n * 8].cpu().numpy().view(SUPPORT_DTYPE).copy()
+
+
+def supports_to_device(S: np.ndarray, device="cuda") -> torch.Tensor:
+    arr = np.ascontiguousarray(S, dtype=SUPPORT_DTYPE)
+    if arr.size == 0:
+        return new_support_buffer(1, device)
+    return torch.from_numpy(arr.view(np.uint8).copy()).to(device)
+
+
+def match_support(cL, cR, omega, params: dict, cand_uv: Optional[np.ndarray] = None,
+                  stream=None):
+    """Matched supports: (device buffer, device int32 count). ``cand_uv`` is an (n, 2)
+    int16 array of (u, v) candidates, or None for the support grid."""
+    _require_cuda(cL, cR, omega)
+    H, W = cL.shape
+    p = make_params(params)
+    L = _lib.load()
+    cand = None
+    if cand_uv is not None:
+        cand = torch.from_numpy(np.ascontiguousarray(cand_uv, dtype=np.int16).reshape(-1, 2)).to(cL.device)
+        n = cand.shape[0]
+    else:
+        n = L.sm_grid_candidates(W, H, p.support_step)
+    out = new_support_buffer(n, cL.device)
+    n_out = torch.zeros(1, dtype=torch.int32, device=cL.device)
+    check(L.sm_match_support(cL.data_ptr(), cR.data_ptr(), _ptr(omega), W, H, _ptr(cand),
+                             n, p, out.data_ptr(), max(n, 1), n_out.data_ptr(), _stream(stream)))
+    return out, n_out
+
+
+def triangulate(S: np.ndarray) -> np.ndarray:
+    """Delaunay triangles (int32 [T, 3]) of host supports (SUPPORT_DTYPE records)."""
+    arr = np.ascontiguousarray(S, dtype=SUPPORT_DTYPE)
+    n = arr.size
+    cap = max(2 * n, 1)
+    tris = np.zeros(cap, dtype=TRI_DTYPE)
+    nt = ctypes_int()
+    L = _lib.load()
+    check(L.sm_triangulate(arr.ctypes.data if n else None, n, tris.ctypes.data, cap, nt))
+    return tris[: nt.value].view(np.int32).reshape(-1, 3).copy()
+
+
+def ctypes_int():
+    import ctypes
+    return ctypes.c_int32(0)
+
+
+def interpolate(S_dev: torch.Tensor, n_support: int, tris: np.ndarray, W: int, H: int,
+                stream=None) -> torch.Tensor:
+    """D_it (float32 [H, W], NaN outside the mesh) from device supports and host triangles."""
+    T = torch.from_numpy(np.ascontiguousarray(tris, dtype=np.int32).reshape(-1)).to(S_dev.device)
+    n_tris = int(T.numel() // 3)
+    D = torch.empty((H, W), dtype=torch.float32, device=S_dev.device)
+    L = _lib.load()
+    check(L.sm_interpolate(S_dev.data_ptr(), n_support, T.data_ptr() if n_tris else None, n_tris,
+                           W, H, D.data_ptr(), _stream(stream)))
+    if stream is not None:
+        T.record_stream(stream)
+    return D
+
+
+def validate(cL, cR, omega, D_it, params: dict, sz_occ: int, D_f, C_f, want_C_it=True,
+             stream=None):
+    """Cost evaluation + refinement; returns (C_it or None, cell_g, cell_b). D_f, C_f are
+    updated in place."""
+    _require_cuda(cL, cR, omega, D_it, D_f, C_f)
+    H, W = cL.shape
+    p = make_params(params)
+    L = _lib.load()
+    n_cells = L.sm_cells(W, H, sz_occ)
+    dev = cL.device
+    C_it = torch.empty((H, W), dtype=torch.uint8, device=dev) if want_C_it else None
+    cell_g = torch.empty(n_cells, dtype=torch.int64, device=dev)
+    cell_b = torch.empty(n_cells, dtype=torch.int64, device=dev)
+    check(L.sm_validate(cL.data_ptr(), cR.data_ptr(), omega.data_ptr(), D_it.data_ptr(), W, H, p,
+                        sz_occ, _ptr(C_it), D_f.data_ptr(), C_f.data_ptr(), cell_g.data_ptr(),
+                        cell_b.data_ptr(), _stream(stream)))
+    return C_it, cell_g, cell_b
+
+
+def resample(cL, cR, D_it, cell_g, cell_b, params: dict, sz_occ: int, S_dev, n_S: int,
+             stream=None):
+    """New supports of Alg. 4: (device buffer, device int32 count)."""
+    _require_cuda(cL, cR, D_it, cell_g, cell_b, S_dev)
+    H, W = cL.shape
+    p = make_params(params)
+    L = _lib.load()
+    cap = 2 * L.sm_cells(W, H, sz_occ)
+    dev = cL.device
+    out = new_support_buffer(cap, dev)
+    occ = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int32, device=dev)
+    check(L.sm_resample(cL.data_ptr(), cR.data_ptr(), D_it.data_ptr(), cell_g.data_ptr(),
+                        cell_b.data_ptr(), W, H, sz_occ, p, S_dev.data_ptr(), n_S, occ.data_ptr(),
+                        out.data_ptr(), max(cap, 1), n_out.data_ptr(), _stream(stream)))
+    return out, n_out
+
+
+@dataclass
+class SolveResult:
+    D_f: torch.Tensor
+    C_f: torch.Tensor
+    mask: torch.Tensor
+    stats: Optional[dict]
+
+
+def stats_dict(st: "_lib.SmStats", n_iters: int) -> dict:
+    return {
+        "n_support": list(st.n_support)[:n_iters],
+        "n_tris": list(st.n_tris)[:n_iters],
+        "n_valid": int(st.n_valid),
+        "stage_us": {k: float(v) for k, v in zip(_lib.STAGES, st.stage_us)},
+        "stage_launches": {k: int(v) for k, v in zip(_lib.STAGES, st.stage_launches)},
+    }
+
+
+class Solver:
+    """Alg. 1 on frames of one size with a workspace allocated once."""
+
+    def __init__(self, W: int, H: int, params: dict, device="cuda"):
+        self.W, self.H = W, H
+        self.params = dict(params)
+        self.p = make_params(params)
+        L = _lib.load()
+        nbytes = L.sm_solve_workspace_bytes(W, H, self.p)
+        if nbytes == 0:
+            raise ValueError("invalid image size or parameters")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = self.ws.data_ptr() + off
+        self.ws_bytes = nbytes
+        self.D_f = torch.empty((H, W), dtype=torch.float32, device=device)
+        self.C_f = torch.empty((H, W), dtype=torch.uint8, device=device)
+        self.mask = torch.empty((H, W), dtype=torch.uint8, device=device)
+        self.st = _lib.SmStats()
+
+    def __call__(self, left: torch.Tensor, right: torch.Tensor, stats=False, timing=False,
+                 stream=None) -> SolveResult:
+        _require_cuda(left, right)
+        if left.shape != (self.H, self.W) or right.shape != (self.H, self.W):
+            raise ValueError("image size differs from the solver's")
+        if left.stride(0) != right.stride(0):
+            raise ValueError("left and right need the same row pitch")
+        L = _lib.load()
+        st = None
+        if stats or timing:
+            self.st.timing = 1 if timing else 0
+            st = self.st
+        check(L.sm_solve(left.data_ptr(), right.data_ptr(), self.W, self.H, left.stride(0), self.p,
+                         self.ws_ptr, self.ws_bytes, self.D_f.data_ptr(), self.C_f.data_ptr(),
+                         self.mask.data_ptr(), st, _stream(stream)))
+        return SolveResult(self.D_f, self.C_f, self.mask,
+                           stats_dict(st, self.p.n_iters) if st is not None else None)
+
+
+def solve(left: torch.Tensor, right: torch.Tensor, params: dict, stats=False) -> SolveResult:
+    H, W = left.shape
+    s = Solver(W, H, params, device=left.device)
+    r = s(left, right, stats=stats)
+    return SolveResult(r.D_f.clone(), r.C_f.clone(), r.mask.clone(), r.stats)

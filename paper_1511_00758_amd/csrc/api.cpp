@@ -1,0 +1,462 @@
+// C ABI of the stereomesh library (declarations and contracts in stereomesh.h):
+// argument checking, launch sequencing, host triangulation and the Alg. 1 loop.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "delaunay.hpp"
+#include "kernels.hpp"
+#include "sm_common.hpp"
+#include "stereomesh.h"
+
+namespace sm {
+
+std::string& last_error() {
+  static thread_local std::string msg;
+  return msg;
+}
+
+sm_status fail(sm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  last_error() = buf;
+  return st;
+}
+
+sm_status check_params(const sm_params* p) {
+  if (!p) return fail(SM_ERR_ARG, "params is NULL");
+  if (p->d_min < 0 || p->d_max < p->d_min || p->d_max > 255)
+    return fail(SM_ERR_ARG, "need 0 <= d_min <= d_max <= 255 (got %d, %d)", p->d_min, p->d_max);
+  if (!census_ok(p->census_w, p->census_h))
+    return fail(SM_ERR_ARG, "census window %dx%d: odd sides in [3, 9], at most 64 bits", p->census_w,
+                p->census_h);
+  if (p->support_step < 1) return fail(SM_ERR_ARG, "support_step must be >= 1");
+  if (p->n_iters < 1 || p->n_iters > 8) return fail(SM_ERR_ARG, "n_iters must be in [1, 8]");
+  if (p->t_hi < 0 || p->t_hi > 64 || p->t_lo < 0 || p->t_lo > p->t_hi)
+    return fail(SM_ERR_ARG, "need 0 <= t_lo <= t_hi <= 64 (got %d, %d)", p->t_lo, p->t_hi);
+  if (p->grad_thr < 0) return fail(SM_ERR_ARG, "grad_thr must be >= 0");
+  if (p->lr_tol < 0) return fail(SM_ERR_ARG, "lr_tol must be >= 0");
+  if (p->uniqueness < 0 || p->uniqueness > 64) return fail(SM_ERR_ARG, "uniqueness must be in [0, 64]");
+  if (p->sz_occ0 < 1 || p->sz_occ0 > 1024) return fail(SM_ERR_ARG, "sz_occ0 must be in [1, 1024]");
+  return SM_OK;
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------------
+// Per-thread host state of sm_solve: pinned staging, triangulation, timing events.
+// Never freed (lives as long as the thread); no HIP call happens at teardown.
+// ---------------------------------------------------------------------------------
+struct StageTimer {
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, int>> marks;  // (stage, event index of the begin event)
+  int used = 0;
+};
+
+struct ThreadCtx {
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t copy_done = nullptr;  // last host-to-device copy out of `pinned`
+  bool copy_pending = false;
+  Delaunay dl;
+  std::vector<sm_tri> tris;
+  StageTimer timer;
+};
+
+ThreadCtx& ctx() {
+  static thread_local ThreadCtx* c = new ThreadCtx();
+  return *c;
+}
+
+sm_status ensure_pinned(ThreadCtx& c, size_t bytes) {
+  // a previous solve of this thread (possibly on another stream) may still be reading
+  // the staging buffer
+  if (c.copy_pending) {
+    SM_HIP(hipEventSynchronize(c.copy_done));
+    c.copy_pending = false;
+  }
+  if (!c.copy_done) SM_HIP(hipEventCreateWithFlags(&c.copy_done, hipEventDisableTiming));
+  if (c.pinned_bytes >= bytes) return SM_OK;
+  if (c.pinned) SM_HIP(hipHostFree(c.pinned));
+  c.pinned = nullptr;
+  c.pinned_bytes = 0;
+  size_t want = std::max<size_t>(bytes, 1 << 16);
+  SM_HIP(hipHostMalloc(&c.pinned, want, hipHostMallocDefault));
+  c.pinned_bytes = want;
+  return SM_OK;
+}
+
+struct Timer {
+  StageTimer& t;
+  hipStream_t s;
+  bool on;
+  Timer(StageTimer& tt, hipStream_t ss, bool enabled) : t(tt), s(ss), on(enabled) {
+    t.used = 0;
+    t.marks.clear();
+  }
+  sm_status event(hipEvent_t* out) {
+    if ((size_t)t.used == t.pool.size()) {
+      hipEvent_t e;
+      SM_HIP(hipEventCreate(&e));
+      t.pool.push_back(e);
+    }
+    *out = t.pool[t.used++];
+    return SM_OK;
+  }
+  sm_status begin(int stage) {
+    if (!on) return SM_OK;
+    hipEvent_t e;
+    SM_TRY(event(&e));
+    t.marks.emplace_back(stage, t.used - 1);
+    SM_HIP(hipEventRecord(e, s));
+    return SM_OK;
+  }
+  sm_status end() {
+    if (!on) return SM_OK;
+    hipEvent_t e;
+    SM_TRY(event(&e));
+    SM_HIP(hipEventRecord(e, s));
+    return SM_OK;
+  }
+  // after the stream has been synchronised
+  sm_status collect(sm_stats* st) {
+    if (!on || !st) return SM_OK;
+    for (auto& m : t.marks) {
+      float ms = 0.f;
+      SM_HIP(hipEventElapsedTime(&ms, t.pool[m.second], t.pool[m.second + 1]));
+      st->stage_us[m.first] += ms * 1000.f;
+      st->stage_launches[m.first] += 1;
+    }
+    return SM_OK;
+  }
+};
+
+using clk = std::chrono::steady_clock;
+inline float us_since(clk::time_point t0) {
+  return std::chrono::duration<float, std::micro>(clk::now() - t0).count();
+}
+
+// Workspace layout of sm_solve (256-byte aligned sub-buffers).
+struct Layout {
+  size_t cL, cR, omega, occ, D_it, cell_g, cell_b, S, T, counters, total;
+  int32_t n_grid, S_cap, T_cap, cells_max;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
+  Layout L{};
+  const size_t npx = (size_t)W * H;
+  L.n_grid = grid_count(W, H, p.support_step);
+  L.cells_max = cells_of(W, H, occ_size(p, p.n_iters));
+  int64_t scap = L.n_grid;
+  for (int it = 1; it < p.n_iters; ++it) scap += 2 * (int64_t)cells_of(W, H, occ_size(p, it));
+  L.S_cap = (int32_t)std::max<int64_t>(scap, 1);
+  L.T_cap = std::max<int32_t>(2 * L.S_cap, 1);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.cL = take(npx * 8);
+  L.cR = take(npx * 8);
+  L.omega = take(npx);
+  L.occ = take(npx);
+  L.D_it = take(npx * 4);
+  L.cell_g = take((size_t)L.cells_max * 8);
+  L.cell_b = take((size_t)L.cells_max * 8);
+  L.S = take((size_t)L.S_cap * sizeof(sm_support));
+  L.T = take((size_t)L.T_cap * sizeof(sm_tri));
+  L.counters = take(64);
+  L.total = o;
+  return L;
+}
+
+sm_status check_image_args(int32_t W, int32_t H) {
+  if (!dims_ok(W, H)) return fail(SM_ERR_ARG, "image size %dx%d outside [3, 8192]^2", W, H);
+  return SM_OK;
+}
+
+}  // namespace
+}  // namespace sm
+
+using namespace sm;
+
+extern "C" {
+
+const char* sm_last_error(void) { return last_error().c_str(); }
+
+const char* sm_version(void) { return "stereomesh 0.1 gfx950"; }
+
+int32_t sm_grid_candidates(int32_t W, int32_t H, int32_t support_step) {
+  if (W <= 0 || H <= 0 || support_step < 1) return 0;
+  return grid_count(W, H, support_step);
+}
+
+int32_t sm_cells(int32_t W, int32_t H, int32_t sz_occ) {
+  if (W <= 0 || H <= 0 || sz_occ < 1) return 0;
+  return cells_of(W, H, sz_occ);
+}
+
+sm_status sm_census(const uint8_t* img, int32_t W, int32_t H, int32_t stride, int32_t census_w,
+                    int32_t census_h, int32_t grad_thr, uint64_t* census, uint8_t* omega,
+                    void* stream) {
+  last_error().clear();
+  SM_TRY(check_image_args(W, H));
+  if (!img || !census) return fail(SM_ERR_ARG, "img and census must be non-NULL");
+  if (stride < W) return fail(SM_ERR_ARG, "stride %d < W %d", stride, W);
+  if (!census_ok(census_w, census_h)) return fail(SM_ERR_ARG, "bad census window %dx%d", census_w, census_h);
+  if (grad_thr < 0) return fail(SM_ERR_ARG, "grad_thr must be >= 0");
+  CensusJob j{img, stride, census, omega};
+  SM_HIP(launch_census(&j, 1, W, H, census_w, census_h, grad_thr, nullptr, nullptr, 0, nullptr,
+                       (hipStream_t)stream));
+  return SM_OK;
+}
+
+sm_status sm_match_support(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega, int32_t W,
+                           int32_t H, const int16_t* cand_uv, int32_t n_cand, const sm_params* p,
+                           sm_support* out, int32_t cap, int32_t* n_out, void* stream) {
+  last_error().clear();
+  SM_TRY(check_image_args(W, H));
+  SM_TRY(check_params(p));
+  if (!cL || !cR || !out || !n_out) return fail(SM_ERR_ARG, "cL, cR, out and n_out must be non-NULL");
+  int32_t n;
+  if (cand_uv) {
+    if (n_cand < 0) return fail(SM_ERR_ARG, "n_cand must be >= 0");
+    n = n_cand;
+  } else {
+    if (!omega) return fail(SM_ERR_ARG, "omega is required for grid candidates");
+    n = grid_count(W, H, p->support_step);
+  }
+  if (cap < n) return fail(SM_ERR_CAPACITY, "cap %d < %d candidates", cap, n);
+  hipStream_t s = (hipStream_t)stream;
+  if (cand_uv) SM_HIP(launch_list_slots(cand_uv, n, out, s));
+  else SM_HIP(launch_grid_slots(omega, W, H, p->support_step, out, n, s));
+  SM_HIP(launch_match(cL, cR, W, H, *p, out, n, s));
+  SM_HIP(launch_compact(out, n, n_out, nullptr, W, s));
+  return SM_OK;
+}
+
+sm_status sm_triangulate(const sm_support* S, int32_t n, sm_tri* tris, int32_t cap, int32_t* n_tris) {
+  last_error().clear();
+  if (n < 0 || (n > 0 && !S) || !n_tris) return fail(SM_ERR_ARG, "bad support array / count");
+  try {
+    Delaunay dl;
+    for (int32_t i = 0; i < n; ++i)
+      if (!dl.insert(S[i].u, S[i].v, i))
+        return fail(SM_ERR_ARG, "support %d at (%d, %d) outside [0, 8191]^2", i, S[i].u, S[i].v);
+    std::vector<sm_tri> out;
+    dl.emit(out, true);
+    *n_tris = (int32_t)out.size();
+    if ((int32_t)out.size() > cap) return fail(SM_ERR_CAPACITY, "need %zu triangles, cap %d", out.size(), cap);
+    if (!out.empty()) std::memcpy(tris, out.data(), out.size() * sizeof(sm_tri));
+  } catch (const std::bad_alloc&) {
+    return fail(SM_ERR_INTERNAL, "out of host memory");
+  } catch (...) {
+    return fail(SM_ERR_INTERNAL, "unexpected exception in triangulation");
+  }
+  return SM_OK;
+}
+
+sm_status sm_interpolate(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
+                         int32_t W, int32_t H, float* D_it, void* stream) {
+  last_error().clear();
+  SM_TRY(check_image_args(W, H));
+  if (!D_it) return fail(SM_ERR_ARG, "D_it must be non-NULL");
+  if (n_tris < 0 || n_support < 0) return fail(SM_ERR_ARG, "negative count");
+  if (n_tris > 0 && (!S || !T)) return fail(SM_ERR_ARG, "S and T must be non-NULL");
+  SM_HIP(launch_interpolate(S, n_support, T, n_tris, W, H, D_it, (hipStream_t)stream));
+  return SM_OK;
+}
+
+sm_status sm_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega, const float* D_it,
+                      int32_t W, int32_t H, const sm_params* p, int32_t sz_occ, uint8_t* C_it,
+                      float* D_f, uint8_t* C_f, uint64_t* cell_g, uint64_t* cell_b, void* stream) {
+  last_error().clear();
+  SM_TRY(check_image_args(W, H));
+  SM_TRY(check_params(p));
+  if (!cL || !cR || !omega || !D_it || !D_f || !C_f || !cell_g || !cell_b)
+    return fail(SM_ERR_ARG, "only C_it may be NULL");
+  if (sz_occ < 1 || sz_occ > 8192) return fail(SM_ERR_ARG, "sz_occ must be in [1, 8192]");
+  SM_HIP(launch_validate(cL, cR, omega, D_it, W, H, *p, sz_occ, C_it, D_f, C_f, cell_g, cell_b, nullptr,
+                         nullptr, (hipStream_t)stream));
+  return SM_OK;
+}
+
+sm_status sm_resample(const uint64_t* cL, const uint64_t* cR, const float* D_it, const uint64_t* cell_g,
+                      const uint64_t* cell_b, int32_t W, int32_t H, int32_t sz_occ, const sm_params* p,
+                      const sm_support* S, int32_t n_S, uint8_t* occ, sm_support* out, int32_t cap,
+                      int32_t* n_out, void* stream) {
+  last_error().clear();
+  SM_TRY(check_image_args(W, H));
+  SM_TRY(check_params(p));
+  if (!cL || !cR || !D_it || !cell_g || !cell_b || !occ || !out || !n_out)
+    return fail(SM_ERR_ARG, "only S may be NULL (when n_S == 0)");
+  if (n_S < 0 || (n_S > 0 && !S)) return fail(SM_ERR_ARG, "bad support array / count");
+  if (sz_occ < 1 || sz_occ > 8192) return fail(SM_ERR_ARG, "sz_occ must be in [1, 8192]");
+  const int32_t cells = cells_of(W, H, sz_occ);
+  if (cap < 2 * cells) return fail(SM_ERR_CAPACITY, "cap %d < 2 * %d cells", cap, cells);
+  hipStream_t s = (hipStream_t)stream;
+  SM_HIP(launch_mark(S, n_S, occ, W, H, s));
+  SM_HIP(launch_resample_cells(cell_g, cell_b, D_it, W, H, sz_occ, *p, out, s));
+  SM_HIP(launch_match(cL, cR, W, H, *p, out + cells, cells, s));
+  SM_HIP(launch_compact(out, 2 * cells, n_out, occ, W, s));
+  return SM_OK;
+}
+
+size_t sm_solve_workspace_bytes(int32_t W, int32_t H, const sm_params* p) {
+  if (!dims_ok(W, H) || check_params(p) != SM_OK) return 0;
+  return layout_of(W, H, *p).total;
+}
+
+sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
+                   const sm_params* p, void* ws, size_t ws_bytes, float* D_f, uint8_t* C_f,
+                   uint8_t* mask, sm_stats* st, void* stream) {
+  last_error().clear();
+  SM_TRY(check_image_args(W, H));
+  SM_TRY(check_params(p));
+  if (!L || !R || !ws || !D_f || !C_f || !mask) return fail(SM_ERR_ARG, "only st may be NULL");
+  if (stride < W) return fail(SM_ERR_ARG, "stride %d < W %d", stride, W);
+  if (((uintptr_t)ws & 255u) != 0) return fail(SM_ERR_ARG, "workspace must be 256-byte aligned");
+  const Layout Lo = layout_of(W, H, *p);
+  if (ws_bytes < Lo.total) return fail(SM_ERR_CAPACITY, "workspace %zu < %zu bytes", ws_bytes, Lo.total);
+  const auto t_start = clk::now();
+  hipStream_t s = (hipStream_t)stream;
+  ThreadCtx& c = ctx();
+  const bool timing = st && st->timing;
+  if (st) {
+    const int32_t keep = st->timing;
+    std::memset(st, 0, sizeof(*st));
+    st->timing = keep;
+  }
+  uint8_t* base = (uint8_t*)ws;
+  uint64_t* cL = (uint64_t*)(base + Lo.cL);
+  uint64_t* cR = (uint64_t*)(base + Lo.cR);
+  uint8_t* omega = base + Lo.omega;
+  uint8_t* occ = base + Lo.occ;
+  float* D_it = (float*)(base + Lo.D_it);
+  uint64_t* cell_g = (uint64_t*)(base + Lo.cell_g);
+  uint64_t* cell_b = (uint64_t*)(base + Lo.cell_b);
+  sm_support* Sd = (sm_support*)(base + Lo.S);
+  sm_tri* Td = (sm_tri*)(base + Lo.T);
+  int32_t* counters = (int32_t*)(base + Lo.counters);
+  unsigned long long* n_valid = (unsigned long long*)(base + Lo.counters + 32);
+  const size_t stage_bytes =
+      std::max((size_t)Lo.S_cap * sizeof(sm_support), (size_t)Lo.T_cap * sizeof(sm_tri)) + 64;
+  SM_TRY(ensure_pinned(c, stage_bytes));
+  int32_t* h_count = (int32_t*)c.pinned;
+  sm_support* h_S = (sm_support*)((uint8_t*)c.pinned + 64);
+  sm_tri* h_T = (sm_tri*)((uint8_t*)c.pinned + 64);
+  Timer tm(c.timer, s, timing);
+  float us_host = 0.f, us_xfer = 0.f;
+
+  // census of both images; D_f = 0, C_f = t_hi, occupancy cleared (Alg. 1 initialisation)
+  SM_TRY(tm.begin(0));
+  CensusJob jobs[2] = {{L, stride, cL, omega}, {R, stride, cR, nullptr}};
+  SM_HIP(launch_census(jobs, 2, W, H, p->census_w, p->census_h, p->grad_thr, D_f, C_f, p->t_hi, occ, s));
+  SM_TRY(tm.end());
+  SM_HIP(launch_zero(counters, 64, s));
+
+  // S_1 = SparseStereo(I_l, I_r) over the candidate grid
+  SM_TRY(tm.begin(1));
+  SM_HIP(launch_grid_slots(omega, W, H, p->support_step, Sd, Lo.n_grid, s));
+  SM_HIP(launch_match(cL, cR, W, H, *p, Sd, Lo.n_grid, s));
+  SM_HIP(launch_compact(Sd, Lo.n_grid, &counters[0], occ, W, s));
+  SM_TRY(tm.end());
+
+  auto t0 = clk::now();
+  SM_HIP(hipMemcpyAsync(h_count, &counters[0], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SM_HIP(hipMemcpyAsync(h_S, Sd, (size_t)std::max(Lo.n_grid, 1) * sizeof(sm_support), hipMemcpyDeviceToHost, s));
+  SM_HIP(hipStreamSynchronize(s));
+  us_xfer += us_since(t0);
+  int32_t n_S = *h_count;
+  if (n_S < 0 || n_S > Lo.n_grid) return fail(SM_ERR_INTERNAL, "support count %d out of range", n_S);
+
+  int32_t n_T = 0;
+  auto triangulate_and_upload = [&](int32_t from, int32_t to) -> sm_status {
+    auto th = clk::now();
+    try {
+      if (from == 0) c.dl.reset();
+      for (int32_t i = from; i < to; ++i)
+        if (!c.dl.insert(h_S[i - from].u, h_S[i - from].v, i))
+          return fail(SM_ERR_INTERNAL, "support outside range");
+      c.tris.clear();
+      c.dl.emit(c.tris, false);
+    } catch (...) {
+      return fail(SM_ERR_INTERNAL, "host triangulation failed");
+    }
+    n_T = (int32_t)c.tris.size();
+    if (n_T > Lo.T_cap) return fail(SM_ERR_INTERNAL, "triangle capacity exceeded");
+    us_host += us_since(th);
+    auto tx = clk::now();
+    // the staging buffer is free again: the supports it held were consumed above
+    if (n_T > 0) {
+      std::memcpy(h_T, c.tris.data(), (size_t)n_T * sizeof(sm_tri));
+      SM_HIP(hipMemcpyAsync(Td, h_T, (size_t)n_T * sizeof(sm_tri), hipMemcpyHostToDevice, s));
+      SM_HIP(hipEventRecord(c.copy_done, s));
+      c.copy_pending = true;
+    }
+    us_xfer += us_since(tx);
+    return SM_OK;
+  };
+  SM_TRY(triangulate_and_upload(0, n_S));
+
+  for (int it = 1; it <= p->n_iters; ++it) {
+    const int32_t sz = occ_size(*p, it);
+    const bool last = it == p->n_iters;
+    if (st) {
+      st->n_support[it - 1] = n_S;
+      st->n_tris[it - 1] = n_T;
+    }
+    SM_TRY(tm.begin(2));
+    SM_HIP(launch_interpolate(Sd, n_S, Td, n_T, W, H, D_it, s));
+    SM_TRY(tm.end());
+    SM_TRY(tm.begin(3));
+    SM_HIP(launch_validate(cL, cR, omega, D_it, W, H, *p, sz, nullptr, D_f, C_f, cell_g, cell_b,
+                           last ? mask : nullptr, last ? n_valid : nullptr, s));
+    SM_TRY(tm.end());
+    if (last) break;
+    // S_it+1 = SupportResampling(C_g, C_b, S_it), appended in place after S_it
+    const int32_t cells = cells_of(W, H, sz);
+    if (n_S + 2 * cells > Lo.S_cap) return fail(SM_ERR_INTERNAL, "support capacity exceeded");
+    sm_support* region = Sd + n_S;
+    SM_TRY(tm.begin(4));
+    SM_HIP(launch_resample_cells(cell_g, cell_b, D_it, W, H, sz, *p, region, s));
+    SM_HIP(launch_match(cL, cR, W, H, *p, region + cells, cells, s));
+    SM_HIP(launch_compact(region, 2 * cells, &counters[1], occ, W, s));
+    SM_TRY(tm.end());
+    t0 = clk::now();
+    SM_HIP(hipMemcpyAsync(h_count, &counters[1], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SM_HIP(hipMemcpyAsync(h_S, region, (size_t)2 * cells * sizeof(sm_support), hipMemcpyDeviceToHost, s));
+    SM_HIP(hipStreamSynchronize(s));
+    us_xfer += us_since(t0);
+    const int32_t n_new = *h_count;
+    if (n_new < 0 || n_new > 2 * cells) return fail(SM_ERR_INTERNAL, "resample count %d out of range", n_new);
+    SM_TRY(triangulate_and_upload(n_S, n_S + n_new));
+    n_S += n_new;
+  }
+  if (st) {
+    t0 = clk::now();
+    unsigned long long nv = 0;
+    SM_HIP(hipMemcpyAsync(h_count, n_valid, sizeof(nv), hipMemcpyDeviceToHost, s));
+    SM_HIP(hipStreamSynchronize(s));
+    std::memcpy(&nv, h_count, sizeof(nv));
+    us_xfer += us_since(t0);
+    st->n_valid = (int64_t)nv;
+    SM_TRY(tm.collect(st));
+    st->stage_us[5] = us_host;
+    st->stage_us[6] = us_xfer;
+    st->stage_us[7] = us_since(t_start);
+  }
+  return SM_OK;
+}
+
+}  // extern "C"

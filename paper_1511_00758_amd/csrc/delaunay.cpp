@@ -1,0 +1,310 @@
+// Host Delaunay triangulation of support pixels (see delaunay.hpp).
+#include "delaunay.hpp"
+
+#include <algorithm>
+
+namespace sm {
+
+namespace {
+inline int sgn(int64_t x) { return (x > 0) - (x < 0); }
+}  // namespace
+
+void Delaunay::reset() {
+  px_.clear();
+  py_.clear();
+  ext_.clear();
+  tri_.clear();
+  alive_.clear();
+  free_.clear();
+  stamp_.clear();
+  pending_.clear();
+  gen_ = 0;
+  hint_ = -1;
+  n_solid_ = 0;
+  started_ = false;
+}
+
+int64_t Delaunay::orient(int32_t a, int32_t b, int32_t c) const {
+  const int64_t ax = px_[a], ay = py_[a];
+  return (int64_t(px_[b]) - ax) * (int64_t(py_[c]) - ay) - (int64_t(py_[b]) - ay) * (int64_t(px_[c]) - ax);
+}
+
+int64_t Delaunay::orient_pt(int32_t a, int32_t b, int64_t x, int64_t y) const {
+  const int64_t ax = px_[a], ay = py_[a];
+  return (int64_t(px_[b]) - ax) * (y - ay) - (int64_t(py_[b]) - ay) * (x - ax);
+}
+
+// Sign of det[[u, v, u^2+v^2, 1]] over rows a, b, c, d (> 0: d strictly inside the
+// circle of counter-clockwise a, b, c). Zero determinants take the sign of the
+// derivative with respect to the highest-priority lifted height that does not vanish:
+// d/dz_a = +orient(b,c,d), d/dz_b = -orient(a,c,d), d/dz_c = +orient(a,b,d),
+// d/dz_d = -orient(a,b,c); priority = smaller (v, u).
+int Delaunay::incircle_sos(int32_t a, int32_t b, int32_t c, int32_t d) const {
+  const int64_t dx = px_[d], dy = py_[d];
+  const int64_t adx = px_[a] - dx, ady = py_[a] - dy;
+  const int64_t bdx = px_[b] - dx, bdy = py_[b] - dy;
+  const int64_t cdx = px_[c] - dx, cdy = py_[c] - dy;
+  const int64_t al = adx * adx + ady * ady;
+  const int64_t bl = bdx * bdx + bdy * bdy;
+  const int64_t cl = cdx * cdx + cdy * cdy;
+  const int64_t det = adx * (bdy * cl - cdy * bl) - ady * (bdx * cl - cdx * bl) + al * (bdx * cdy - cdx * bdy);
+  if (det != 0) return sgn(det);
+  int32_t ids[4] = {a, b, c, d};
+  // order by priority (smaller (v, u) first); insertion sort of 4
+  int ord[4] = {0, 1, 2, 3};
+  auto key = [&](int k) { return (int64_t(py_[ids[k]]) << 16) | int64_t(px_[ids[k]]); };
+  for (int i = 1; i < 4; ++i)
+    for (int j = i; j > 0 && key(ord[j]) < key(ord[j - 1]); --j) std::swap(ord[j], ord[j - 1]);
+  for (int k = 0; k < 4; ++k) {
+    int64_t cof;
+    switch (ord[k]) {
+      case 0: cof = orient(b, c, d); break;
+      case 1: cof = -orient(a, c, d); break;
+      case 2: cof = orient(a, b, d); break;
+      default: cof = -orient(a, b, c); break;
+    }
+    if (cof != 0) return sgn(cof);
+  }
+  return 0;  // unreachable for a non-degenerate triangle a, b, c
+}
+
+bool Delaunay::conflict(int32_t t, int32_t p) const {
+  const Tri& T = tri_[t];
+  if (T.v[2] != kGhost) return incircle_sos(T.v[0], T.v[1], T.v[2], p) > 0;
+  // ghost (y, x, ghost): solid hull edge x -> y with the interior on its left
+  const int32_t y = T.v[0], x = T.v[1];
+  const int64_t o = orient(x, y, p);
+  if (o < 0) return true;
+  if (o > 0) return false;
+  const int64_t ux = px_[x], uy = py_[x], wx = px_[y], wy = py_[y], qx = px_[p], qy = py_[p];
+  const int64_t d1 = (qx - ux) * (wx - ux) + (qy - uy) * (wy - uy);
+  const int64_t d2 = (qx - wx) * (ux - wx) + (qy - wy) * (uy - wy);
+  return d1 > 0 && d2 > 0;
+}
+
+int32_t Delaunay::alloc_tri() {
+  int32_t t;
+  if (!free_.empty()) {
+    t = free_.back();
+    free_.pop_back();
+    alive_[t] = 1;
+  } else {
+    t = (int32_t)tri_.size();
+    tri_.push_back(Tri{});
+    alive_.push_back(1);
+    stamp_.push_back(0);
+  }
+  return t;
+}
+
+void Delaunay::free_tri(int32_t t) {
+  alive_[t] = 0;
+  free_.push_back(t);
+}
+
+void Delaunay::start(int32_t a, int32_t b, int32_t c) {
+  if (orient(a, b, c) < 0) std::swap(b, c);
+  const int32_t s = alloc_tri();
+  const int32_t g0 = alloc_tri(), g1 = alloc_tri(), g2 = alloc_tri();
+  // solid (a, b, c); edges opposite a: b->c, opposite b: c->a, opposite c: a->b
+  tri_[s] = Tri{{a, b, c}, {g0, g1, g2}};
+  // ghost across b->c is (c, b, G); across c->a is (a, c, G); across a->b is (b, a, G)
+  tri_[g0] = Tri{{c, b, kGhost}, {0, 0, s}};
+  tri_[g1] = Tri{{a, c, kGhost}, {0, 0, s}};
+  tri_[g2] = Tri{{b, a, kGhost}, {0, 0, s}};
+  // ghost (y, x, G): nb[0] across x->G, nb[1] across G->y
+  // g0 = (c, b): x->G is b->G, shared with the ghost whose edge is G->b: g2 = (b, a)
+  tri_[g0].nb[0] = g2;
+  tri_[g0].nb[1] = g1;  // G->c shared with c->G of g1 = (a, c)
+  tri_[g1].nb[0] = g0;  // c->G shared with G->c of g0
+  tri_[g1].nb[1] = g2;  // G->a shared with a->G of g2 = (b, a)
+  tri_[g2].nb[0] = g1;  // a->G shared with G->a of g1
+  tri_[g2].nb[1] = g0;  // G->b shared with b->G of g0
+  n_solid_ = 1;
+  hint_ = s;
+  started_ = true;
+}
+
+int32_t Delaunay::locate(int32_t p, bool* dup) {
+  *dup = false;
+  int32_t t = hint_;
+  if (t < 0 || !alive_[t]) {
+    for (t = 0; t < (int32_t)tri_.size() && !alive_[t]; ++t) {
+    }
+  }
+  if (tri_[t].v[2] == kGhost) t = tri_[t].nb[2];
+  const int64_t x = px_[p], y = py_[p];
+  const size_t limit = 4 * tri_.size() + 64;
+  for (size_t step = 0; step < limit; ++step) {
+    const Tri& T = tri_[t];
+    if (T.v[2] == kGhost) return t;  // entered across a hull edge with p strictly outside
+    rng_ ^= rng_ << 13;
+    rng_ ^= rng_ >> 17;
+    rng_ ^= rng_ << 5;
+    const int r = (int)(rng_ % 3u);
+    int next = -1;
+    for (int k = 0; k < 3; ++k) {
+      const int i = (r + k) % 3;
+      if (orient_pt(T.v[(i + 1) % 3], T.v[(i + 2) % 3], x, y) < 0) {
+        next = T.nb[i];
+        break;
+      }
+    }
+    if (next < 0) {  // p inside or on the boundary of T
+      for (int k = 0; k < 3; ++k)
+        if (px_[T.v[k]] == x && py_[T.v[k]] == y) *dup = true;
+      return t;
+    }
+    t = next;
+  }
+  // fallback (not expected): scan for any conflicting triangle
+  for (int32_t s = 0; s < (int32_t)tri_.size(); ++s) {
+    if (!alive_[s]) continue;
+    const Tri& T = tri_[s];
+    if (T.v[2] != kGhost)
+      for (int k = 0; k < 3; ++k)
+        if (px_[T.v[k]] == x && py_[T.v[k]] == y) {
+          *dup = true;
+          return s;
+        }
+    if (conflict(s, p)) return s;
+  }
+  return -1;
+}
+
+bool Delaunay::insert_point(int32_t p) {
+  bool dup = false;
+  const int32_t t0 = locate(p, &dup);
+  if (dup || t0 < 0) return false;  // duplicate pixel
+  // flood the hole
+  if (++gen_ == 0x7fffffffu) {
+    std::fill(stamp_.begin(), stamp_.end(), 0u);
+    gen_ = 1;
+  }
+  const uint32_t in_hole = 2 * gen_, outside = 2 * gen_ + 1;
+  hole_.clear();
+  bnd_.clear();
+  stack_.clear();
+  stack_.push_back(t0);
+  stamp_[t0] = in_hole;
+  while (!stack_.empty()) {
+    const int32_t t = stack_.back();
+    stack_.pop_back();
+    hole_.push_back(t);
+    for (int i = 0; i < 3; ++i) {
+      const int32_t n = tri_[t].nb[i];
+      if (stamp_[n] == in_hole) continue;
+      bool in = false;
+      if (stamp_[n] != outside) {
+        in = conflict(n, p);
+        stamp_[n] = in ? in_hole : outside;
+      }
+      if (in) {
+        stack_.push_back(n);
+      } else {
+        bnd_.push_back(Edge{tri_[t].v[(i + 1) % 3], tri_[t].v[(i + 2) % 3], n});
+      }
+    }
+  }
+  // fan around p: one triangle per boundary edge a->b
+  newt_.clear();
+  for (const Edge& e : bnd_) {
+    const int32_t t = alloc_tri();
+    newt_.push_back(t);
+    Tri T;
+    // (a, b, p) rotated so a ghost vertex, if any, sits in slot 2
+    if (e.b == kGhost) T.v[0] = p, T.v[1] = e.a, T.v[2] = kGhost;
+    else if (e.a == kGhost) T.v[0] = e.b, T.v[1] = p, T.v[2] = kGhost;
+    else T.v[0] = e.a, T.v[1] = e.b, T.v[2] = p;
+    T.nb[0] = T.nb[1] = T.nb[2] = -1;
+    // across a->b: the outside neighbour
+    for (int i = 0; i < 3; ++i)
+      if (T.v[(i + 1) % 3] == e.a && T.v[(i + 2) % 3] == e.b) T.nb[i] = e.out;
+    tri_[t] = T;
+    Tri& O = tri_[e.out];
+    for (int i = 0; i < 3; ++i)
+      if (O.v[(i + 1) % 3] == e.b && O.v[(i + 2) % 3] == e.a) O.nb[i] = t;
+  }
+  // link the fan: triangle of edge a->b meets the triangle of edge b->c across b-p
+  const size_t m = bnd_.size();
+  for (size_t j = 0; j < m; ++j) {
+    const int32_t b = bnd_[j].b;
+    for (size_t k = 0; k < m; ++k) {
+      if (bnd_[k].a != b) continue;
+      const int32_t t1 = newt_[j], t2 = newt_[k];
+      Tri& A = tri_[t1];
+      Tri& B = tri_[t2];
+      for (int i = 0; i < 3; ++i)
+        if (A.v[(i + 1) % 3] == b && A.v[(i + 2) % 3] == p) A.nb[i] = t2;
+      for (int i = 0; i < 3; ++i)
+        if (B.v[(i + 1) % 3] == p && B.v[(i + 2) % 3] == b) B.nb[i] = t1;
+      break;
+    }
+  }
+  int32_t solid_removed = 0, solid_added = 0;
+  for (int32_t t : hole_) {
+    if (tri_[t].v[2] != kGhost) ++solid_removed;
+    free_tri(t);
+  }
+  for (int32_t t : newt_)
+    if (tri_[t].v[2] != kGhost) {
+      ++solid_added;
+      hint_ = t;
+    }
+  n_solid_ += solid_added - solid_removed;
+  return true;
+}
+
+bool Delaunay::insert(int32_t u, int32_t v, int32_t ext) {
+  if (u < 0 || v < 0 || u > 8191 || v > 8191) return false;
+  const int32_t p = (int32_t)px_.size();
+  px_.push_back(u);
+  py_.push_back(v);
+  ext_.push_back(ext);
+  if (started_) {
+    if (!insert_point(p)) {  // duplicate: drop the new copy, the first occurrence stays
+      px_.pop_back();
+      py_.pop_back();
+      ext_.pop_back();
+    }
+    return true;
+  }
+  // before the first triangle: keep the points while they are collinear
+  for (int32_t q : pending_)
+    if (px_[q] == u && py_[q] == v) {
+      px_.pop_back();
+      py_.pop_back();
+      ext_.pop_back();
+      return true;
+    }
+  if (pending_.size() >= 2 && orient(pending_[0], pending_[1], p) != 0) {
+    start(pending_[0], pending_[1], p);
+    for (size_t k = 2; k < pending_.size(); ++k) insert_point(pending_[k]);
+    pending_.clear();
+    return true;
+  }
+  pending_.push_back(p);
+  return true;
+}
+
+void Delaunay::emit(std::vector<sm_tri>& out, bool sorted) const {
+  const size_t base = out.size();
+  for (size_t t = 0; t < tri_.size(); ++t) {
+    if (!alive_[t] || tri_[t].v[2] == kGhost) continue;
+    const Tri& T = tri_[t];
+    int k = 0;
+    for (int i = 1; i < 3; ++i) {
+      const int32_t a = T.v[i], b = T.v[k];
+      if (py_[a] < py_[b] || (py_[a] == py_[b] && px_[a] < px_[b])) k = i;
+    }
+    out.push_back(sm_tri{ext_[T.v[k]], ext_[T.v[(k + 1) % 3]], ext_[T.v[(k + 2) % 3]]});
+  }
+  if (sorted)
+    std::sort(out.begin() + base, out.end(), [](const sm_tri& x, const sm_tri& y) {
+      if (x.i0 != y.i0) return x.i0 < y.i0;
+      if (x.i1 != y.i1) return x.i1 < y.i1;
+      return x.i2 < y.i2;
+    });
+}
+
+}  // namespace sm

@@ -1,0 +1,578 @@
+// Device kernels of the stereomesh library for gfx950 (CDNA4, wave64).
+//
+// All per-pixel work is integer or IEEE float with fused multiply-add disabled
+// (-ffp-contract=off plus explicit _rn intrinsics where rounding order matters), so
+// every output is reproducible bit for bit.
+#include "kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+namespace sm {
+
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    uint32_t y = __shfl_xor(x, off, kWave);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+
+__device__ __forceinline__ int ceil_div_pos(int n, int d) {  // d > 0
+  return n >= 0 ? (n + d - 1) / d : -((-n) / d);
+}
+
+// ------------------------------------------------------------------------------------
+// Census words + Omega_I (+ optional initialisation of D_f, C_f and the occupancy map).
+// Tile of 64 x 16 output pixels per 256-thread block, staged in LDS with its halo.
+// ------------------------------------------------------------------------------------
+constexpr int kTW = 64, kTH = 16;
+
+struct CensusArgs {
+  CensusJob job[2];
+  int32_t W, H, grad_thr, t_hi;
+  float* D_f;
+  uint8_t* C_f;
+  uint8_t* occ;
+};
+
+template <int RX, int RY>
+__global__ __launch_bounds__(256) void k_census(CensusArgs a) {
+  constexpr int PW = kTW + 2 * RX, PH = kTH + 2 * RY;
+  __shared__ uint8_t tile[PH * PW];
+  const CensusJob jb = a.job[blockIdx.z];
+  const int W = a.W, H = a.H;
+  const int gx0 = blockIdx.x * kTW - RX, gy0 = blockIdx.y * kTH - RY;
+  for (int i = threadIdx.y * kTW + threadIdx.x; i < PH * PW; i += 256) {
+    int ty = i / PW, tx = i - ty * PW;
+    int gx = min(max(gx0 + tx, 0), W - 1), gy = min(max(gy0 + ty, 0), H - 1);
+    tile[i] = jb.img[(size_t)gy * jb.stride + gx];
+  }
+  __syncthreads();
+  const int u = blockIdx.x * kTW + threadIdx.x;
+  if (u >= W) return;
+#pragma unroll
+  for (int r = 0; r < kTH / 4; ++r) {
+    const int ly = threadIdx.y + 4 * r;
+    const int v = blockIdx.y * kTH + ly;
+    if (v >= H) break;
+    const size_t idx = (size_t)v * W + u;
+    const bool valid = u >= RX && u < W - RX && v >= RY && v < H - RY;
+    const uint8_t* c = &tile[(ly + RY) * PW + threadIdx.x + RX];
+    uint32_t lo = 0, hi = 0;
+    const uint32_t cv = c[0];
+#pragma unroll
+    for (int dy = -RY; dy <= RY; ++dy) {
+#pragma unroll
+      for (int dx = -RX; dx <= RX; ++dx) {
+        constexpr int kCenter = RY * (2 * RX + 1) + RX;
+        const int pos = (dy + RY) * (2 * RX + 1) + (dx + RX);
+        if (pos == kCenter) continue;
+        const int k = pos < kCenter ? pos : pos - 1;
+        const uint32_t bit = (uint32_t)c[dy * PW + dx] < cv;
+        if (k < 32) lo |= bit << k;
+        else hi |= bit << (k - 32);
+      }
+    }
+    const uint64_t word = valid ? ((uint64_t)hi << 32 | lo) : 0ull;
+    jb.census[idx] = word;
+    if (jb.omega) {
+      uint8_t om = 0;
+      if (valid) {
+        const int gxx = abs((int)c[1] - (int)c[-1]);
+        const int gyy = abs((int)c[PW] - (int)c[-PW]);
+        om = (gxx + gyy) >= a.grad_thr;
+      }
+      jb.omega[idx] = om;
+    }
+    if (blockIdx.z == 0) {
+      if (a.D_f) a.D_f[idx] = 0.0f;
+      if (a.C_f) a.C_f[idx] = (uint8_t)a.t_hi;
+      if (a.occ) a.occ[idx] = 0;
+    }
+  }
+}
+
+template <int RX, int RY>
+hipError_t census_launch(const CensusArgs& a, int n_jobs, hipStream_t s) {
+  dim3 grid((a.W + kTW - 1) / kTW, (a.H + kTH - 1) / kTH, n_jobs);
+  hipLaunchKernelGGL((k_census<RX, RY>), grid, dim3(kTW, 4, 1), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// Candidate slots
+// ------------------------------------------------------------------------------------
+__global__ void k_grid_slots(const uint8_t* omega, int W, int step, int gw, sm_support* slots, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int gy = i / gw, gx = i - gy * gw;
+  const int u = step / 2 + gx * step, v = step / 2 + gy * step;
+  sm_support s;
+  s.u = (int16_t)u;
+  s.v = (int16_t)v;
+  s.d = omega[(size_t)v * W + u] ? kPending : kRejected;
+  slots[i] = s;
+}
+
+__global__ void k_list_slots(const int16_t* uv, int n, sm_support* slots) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  sm_support s;
+  s.u = uv[2 * i];
+  s.v = uv[2 * i + 1];
+  s.d = kPending;
+  slots[i] = s;
+}
+
+// ------------------------------------------------------------------------------------
+// Epipolar matching: one wave per candidate, lanes over disparities (up to 4 chunks of
+// 64), wave-shuffle argmin over packed (cost << 8 | d) keys.
+// ------------------------------------------------------------------------------------
+struct MatchArgs {
+  const uint64_t* cL;
+  const uint64_t* cR;
+  int32_t W, H, rx, ry, d_min, d_max, t_hi, uniq, lr_tol;
+  sm_support* slots;
+  int32_t n;
+};
+
+__global__ __launch_bounds__(256) void k_match(MatchArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (slot >= a.n) return;
+  const sm_support s = a.slots[slot];
+  if (s.d != kPending) return;
+  const int u = s.u, v = s.v, W = a.W;
+  if (u < a.rx || u >= W - a.rx || v < a.ry || v >= a.H - a.ry) {
+    if (lane == 0) a.slots[slot].d = kRejected;
+    return;
+  }
+  const uint64_t* rowL = a.cL + (size_t)v * W;
+  const uint64_t* rowR = a.cR + (size_t)v * W;
+  const uint64_t wl = rowL[u];
+  uint32_t cost[4];
+  uint32_t best = 0xffffffffu;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int d = a.d_min + lane + kWave * c;
+    const bool ok = d <= a.d_max && u - d >= a.rx;
+    const uint32_t cs = ok ? (uint32_t)__popcll(wl ^ rowR[u - d]) : 0xffu;
+    cost[c] = cs;
+    const uint32_t key = ok ? (cs << 8 | (uint32_t)d) : 0xffffffffu;
+    best = key < best ? key : best;
+  }
+  best = wave_min_u32(best);
+  bool accept = best != 0xffffffffu;
+  const int dstar = (int)(best & 0xffu);
+  const uint32_t cstar = best >> 8;
+  accept = accept && cstar < (uint32_t)a.t_hi;
+  if (accept && a.uniq > 0) {
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int d = a.d_min + lane + kWave * c;
+      const bool ok = d <= a.d_max && u - d >= a.rx;
+      const int dd = d - dstar;
+      bad |= ok && (dd >= 2 || dd <= -2) && cost[c] < cstar + (uint32_t)a.uniq;
+    }
+    accept = __ballot(bad) == 0ull;
+  }
+  if (accept) {
+    const int ur = u - dstar;
+    const uint64_t wr = rowR[ur];
+    uint32_t best2 = 0xffffffffu;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int d = a.d_min + lane + kWave * c;
+      const bool ok = d <= a.d_max && ur + d <= W - 1 - a.rx;
+      const uint32_t key = ok ? ((uint32_t)__popcll(wr ^ rowL[ur + d]) << 8 | (uint32_t)d) : 0xffffffffu;
+      best2 = key < best2 ? key : best2;
+    }
+    best2 = wave_min_u32(best2);
+    const int dlr = (int)(best2 & 0xffu);
+    const int diff = dlr - dstar;
+    accept = (diff <= a.lr_tol && -diff <= a.lr_tol);
+  }
+  if (lane == 0) a.slots[slot].d = accept ? (float)dstar : kRejected;
+}
+
+// ------------------------------------------------------------------------------------
+// Order-preserving in-place compaction (one 1024-thread workgroup).
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_compact(sm_support* slots, int n, int* n_out, uint8_t* occ,
+                                                  int W) {
+  __shared__ int wsum[16];
+  __shared__ int wofs[16];
+  __shared__ int total;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  int base = 0;
+  for (int start = 0; start < n; start += 1024) {
+    const int i = start + threadIdx.x;
+    sm_support s;
+    bool keep = false;
+    if (i < n) {
+      s = slots[i];
+      keep = s.d != kPending && s.d != kRejected;
+      if (keep && occ) keep = occ[(size_t)s.v * W + s.u] == 0;
+    }
+    const unsigned long long m = __ballot(keep);
+    const int pre = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int acc = 0;
+      for (int k = 0; k < 16; ++k) {
+        wofs[k] = acc;
+        acc += wsum[k];
+      }
+      total = acc;
+    }
+    __syncthreads();
+    if (keep) {
+      slots[base + wofs[w] + pre] = s;
+      if (occ) occ[(size_t)s.v * W + s.u] = 1;
+    }
+    base += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *n_out = base;
+}
+
+__global__ void k_fill_u8(uint8_t* p, size_t n, uint8_t val) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = val;
+}
+
+__global__ void k_fill_f32(float* p, size_t n, float val) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = val;
+}
+
+__global__ void k_mark(const sm_support* S, int n, uint8_t* occ, int W, int H) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int u = S[i].u, v = S[i].v;
+  if (u >= 0 && u < W && v >= 0 && v < H) occ[(size_t)v * W + u] = 1;
+}
+
+// ------------------------------------------------------------------------------------
+// Plane fit + rasterisation: one wave per triangle, one lane per pixel row. Each row's
+// owned span is solved exactly from the three edge functions (ownership of the
+// perturbed point (u + eps, v + eps^2)), then the plane is evaluated along it.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_raster(const sm_support* S, int n_support, const sm_tri* T,
+                                                int n_tris, int W, int H, float* D) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= n_tris) return;
+  const sm_tri tr = T[t];
+  if ((unsigned)tr.i0 >= (unsigned)n_support || (unsigned)tr.i1 >= (unsigned)n_support ||
+      (unsigned)tr.i2 >= (unsigned)n_support)
+    return;  // malformed triangle: owns nothing
+  const sm_support s0 = S[tr.i0], s1 = S[tr.i1], s2 = S[tr.i2];
+  const int u0 = s0.u, v0 = s0.v, u1 = s1.u, v1 = s1.v, u2 = s2.u, v2 = s2.v;
+  if ((unsigned)(u0 | v0 | u1 | v1 | u2 | v2) > 8191u) return;  // outside the supported range
+  const int du1 = u1 - u0, dv1 = v1 - v0, du2 = u2 - u0, dv2 = v2 - v0;
+  const int det = du1 * dv2 - du2 * dv1;
+  if (det <= 0) return;
+  const double e1 = __dadd_rn((double)s1.d, -(double)s0.d);
+  const double e2 = __dadd_rn((double)s2.d, -(double)s0.d);
+  const double ddet = (double)det;
+  const double pa = __ddiv_rn(__dadd_rn(__dmul_rn(e1, (double)dv2), -__dmul_rn(e2, (double)dv1)), ddet);
+  const double pb = __ddiv_rn(__dadd_rn(__dmul_rn((double)du1, e2), -__dmul_rn((double)du2, e1)), ddet);
+  const float a = (float)pa, b = (float)pb, d0 = s0.d;
+  const int ax[3] = {u0, u1, u2}, ay[3] = {v0, v1, v2};
+  const int vmin = max(min(v0, min(v1, v2)), 0), vmax = min(max(v0, max(v1, v2)), H - 1);
+  const int umin = max(min(u0, min(u1, u2)), 0), umax = min(max(u0, max(u1, u2)), W - 1);
+  for (int v = vmin + lane; v <= vmax; v += kWave) {
+    int lo = umin, hi = umax;
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      const int xa = ax[e], ya = ay[e], xb = ax[(e + 1) % 3], yb = ay[(e + 1) % 3];
+      const int dy = yb - ya;
+      const int K = (xb - xa) * (v - ya);
+      if (dy == 0) {
+        if (!(K > 0 || (K == 0 && xb > xa))) hi = lo - 1;
+      } else if (dy < 0) {  // E = K + |dy| (u - xa) >= 0 (tie counts as inside)
+        lo = max(lo, xa + ceil_div_pos(-K, -dy));
+      } else {              // E = K - dy (u - xa) > 0
+        hi = min(hi, xa + ceil_div_pos(K, dy) - 1);
+      }
+    }
+    float* row = D + (size_t)v * W;
+    const float tv = __fmul_rn(b, (float)(v - v0));
+    for (int u = lo; u <= hi; ++u) row[u] = __fadd_rn(__fadd_rn(d0, __fmul_rn(a, (float)(u - u0))), tv);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Cost evaluation + refinement. 64 x 4 pixels per block; one wave = 64 consecutive
+// pixels of a row. Cell winners: segmented wave min of packed keys, then one 64-bit
+// atomicMin per (wave, cell); the key order makes the result independent of timing.
+// ------------------------------------------------------------------------------------
+struct ValidateArgs {
+  const uint64_t* cL;
+  const uint64_t* cR;
+  const uint8_t* omega;
+  const float* D_it;
+  int32_t W, H, rx, d_min, d_max, t_lo, t_hi, sz, Wc;
+  uint8_t* C_it;
+  float* D_f;
+  uint8_t* C_f;
+  uint64_t* cell_g;
+  uint64_t* cell_b;
+  uint8_t* mask;
+  unsigned long long* n_valid;
+};
+
+__global__ void k_cells_init(uint64_t* g, uint64_t* b, int n, uint64_t ginit, uint64_t binit) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    g[i] = ginit;
+    b[i] = binit;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_validate(ValidateArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int u = blockIdx.x * kWave + lane;
+  const int v = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (v >= a.H) return;  // wave-uniform
+  const bool in = u < a.W;
+  const size_t idx = (size_t)v * a.W + u;
+  uint32_t cost = 0xffu;
+  float D = 0.0f;
+  bool om = false;
+  if (in) {
+    om = a.omega[idx] != 0;
+    if (om) {
+      D = a.D_it[idx];
+      if (isfinite(D)) {
+        const float f = floorf(__fadd_rn(D, 0.5f));
+        if (f >= (float)a.d_min && f <= (float)a.d_max) {
+          const int d = (int)f;
+          if (u - d >= a.rx) cost = (uint32_t)__popcll(a.cL[idx] ^ a.cR[idx - d]);
+        }
+      }
+    }
+    if (a.C_it) a.C_it[idx] = (uint8_t)cost;
+    uint32_t cf = a.C_f[idx];
+    if (cost != 0xffu && cost < cf) {
+      a.D_f[idx] = D;
+      a.C_f[idx] = (uint8_t)cost;
+      cf = cost;
+    }
+    if (a.mask) {
+      const bool mk = om && cf < (uint32_t)a.t_hi;
+      a.mask[idx] = mk;
+      const unsigned long long bm = __ballot(mk);
+      if (lane == 0 && bm) atomicAdd(a.n_valid, (unsigned long long)__popcll(bm));
+    }
+  }
+  const uint64_t none = ~0ull;
+  uint64_t kg = (in && cost < (uint32_t)a.t_lo) ? ((uint64_t)cost << 32 | (uint64_t)idx) : none;
+  uint64_t kb = (in && cost != 0xffu && cost > (uint32_t)a.t_hi)
+                    ? ((uint64_t)(255u - cost) << 32 | (uint64_t)idx) : none;
+  if (__ballot(kg != none || kb != none) == 0ull) return;  // wave-uniform
+  const int seg = in ? u / a.sz : 0x7fffffff;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint64_t og = __shfl_down(kg, off, kWave);
+    const uint64_t ob = __shfl_down(kb, off, kWave);
+    const int os = __shfl_down(seg, off, kWave);
+    if (lane + off < kWave && os == seg) {
+      kg = og < kg ? og : kg;
+      kb = ob < kb ? ob : kb;
+    }
+  }
+  const int prev = __shfl_up(seg, 1, kWave);
+  if (in && (lane == 0 || prev != seg)) {
+    const size_t cell = (size_t)(v / a.sz) * a.Wc + seg;
+    if (kg != none) atomicMin((unsigned long long*)&a.cell_g[cell], (unsigned long long)kg);
+    if (kb != none) atomicMin((unsigned long long*)&a.cell_b[cell], (unsigned long long)kb);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Resampling: cells -> confident supports and X candidates.
+// ------------------------------------------------------------------------------------
+__global__ void k_resample_cells(const uint64_t* cell_g, const uint64_t* cell_b, const float* D_it,
+                                 int W, int n_cells, uint64_t ginit, uint64_t binit, sm_support* slots) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cells) return;
+  const uint64_t g = cell_g[c], b = cell_b[c];
+  sm_support sg, sb;
+  if (g != ginit) {
+    const uint32_t idx = (uint32_t)g;
+    sg.u = (int16_t)(idx % (uint32_t)W);
+    sg.v = (int16_t)(idx / (uint32_t)W);
+    sg.d = D_it[idx];
+  } else {
+    sg.u = sg.v = 0;
+    sg.d = kRejected;
+  }
+  if (b != binit) {
+    const uint32_t idx = (uint32_t)b;
+    sb.u = (int16_t)(idx % (uint32_t)W);
+    sb.v = (int16_t)(idx / (uint32_t)W);
+    sb.d = kPending;
+  } else {
+    sb.u = sb.v = 0;
+    sb.d = kRejected;
+  }
+  slots[c] = sg;
+  slots[n_cells + c] = sb;
+}
+
+inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(bytes, 256)), dim3(256), 0, s, (uint8_t*)p, bytes,
+                     (uint8_t)0);
+  return hipGetLastError();
+}
+
+hipError_t launch_census(const CensusJob* jobs, int n_jobs, int32_t W, int32_t H, int32_t cw,
+                         int32_t ch, int32_t grad_thr, float* D_f, uint8_t* C_f, int32_t t_hi,
+                         uint8_t* occ, hipStream_t s) {
+  CensusArgs a{};
+  for (int i = 0; i < n_jobs; ++i) a.job[i] = jobs[i];
+  a.W = W;
+  a.H = H;
+  a.grad_thr = grad_thr;
+  a.t_hi = t_hi;
+  a.D_f = D_f;
+  a.C_f = C_f;
+  a.occ = occ;
+  const int rx = (cw - 1) / 2, ry = (ch - 1) / 2;
+#define SM_CENSUS_CASE(X, Y) \
+  if (rx == X && ry == Y) return census_launch<X, Y>(a, n_jobs, s);
+  SM_CENSUS_CASE(1, 1) SM_CENSUS_CASE(1, 2) SM_CENSUS_CASE(1, 3) SM_CENSUS_CASE(1, 4)
+  SM_CENSUS_CASE(2, 1) SM_CENSUS_CASE(2, 2) SM_CENSUS_CASE(2, 3) SM_CENSUS_CASE(2, 4)
+  SM_CENSUS_CASE(3, 1) SM_CENSUS_CASE(3, 2) SM_CENSUS_CASE(3, 3) SM_CENSUS_CASE(3, 4)
+  SM_CENSUS_CASE(4, 1) SM_CENSUS_CASE(4, 2) SM_CENSUS_CASE(4, 3)
+#undef SM_CENSUS_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_grid_slots(const uint8_t* omega, int32_t W, int32_t H, int32_t step,
+                             sm_support* slots, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int h = step / 2;
+  const int gw = (W - 1 - h) / step + 1;
+  hipLaunchKernelGGL(k_grid_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, omega, W, step, gw,
+                     slots, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_list_slots(const int16_t* uv, int32_t n, sm_support* slots, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_list_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, uv, n, slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_match(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
+                        const sm_params& p, sm_support* slots, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  MatchArgs a;
+  a.cL = cL;
+  a.cR = cR;
+  a.W = W;
+  a.H = H;
+  a.rx = (p.census_w - 1) / 2;
+  a.ry = (p.census_h - 1) / 2;
+  a.d_min = p.d_min;
+  a.d_max = p.d_max;
+  a.t_hi = p.t_hi;
+  a.uniq = p.uniqueness;
+  a.lr_tol = p.lr_tol;
+  a.slots = slots;
+  a.n = n;
+  hipLaunchKernelGGL(k_match, dim3(blocks_for(n, 4)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(sm_support* slots, int32_t n, int32_t* n_out, uint8_t* occ, int32_t W,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, slots, n, n_out, occ, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark(const sm_support* S, int32_t n, uint8_t* occ, int32_t W, int32_t H,
+                       hipStream_t s) {
+  const size_t npx = (size_t)W * H;
+  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(npx, 256)), dim3(256), 0, s, occ, npx, (uint8_t)0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n <= 0) return e;
+  hipLaunchKernelGGL(k_mark, dim3(blocks_for(n, 256)), dim3(256), 0, s, S, n, occ, W, H);
+  return hipGetLastError();
+}
+
+hipError_t launch_interpolate(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
+                              int32_t W, int32_t H, float* D_it, hipStream_t s) {
+  const size_t npx = (size_t)W * H;
+  hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(npx, 256)), dim3(256), 0, s, D_it, npx,
+                     __builtin_nanf(""));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n_tris <= 0) return e;
+  hipLaunchKernelGGL(k_raster, dim3(blocks_for(n_tris, 4)), dim3(256), 0, s, S, n_support, T, n_tris, W,
+                     H, D_it);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
+                           const float* D_it, int32_t W, int32_t H, const sm_params& p,
+                           int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f, uint64_t* cell_g,
+                           uint64_t* cell_b, uint8_t* mask, unsigned long long* n_valid,
+                           hipStream_t s) {
+  const int Wc = (W + sz - 1) / sz, Hc = (H + sz - 1) / sz;
+  const int n_cells = Wc * Hc;
+  const uint64_t ginit = (uint64_t)p.t_lo << 32, binit = (uint64_t)(255 - p.t_hi) << 32;
+  hipLaunchKernelGGL(k_cells_init, dim3(blocks_for(n_cells, 256)), dim3(256), 0, s, cell_g, cell_b,
+                     n_cells, ginit, binit);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  ValidateArgs a;
+  a.cL = cL;
+  a.cR = cR;
+  a.omega = omega;
+  a.D_it = D_it;
+  a.W = W;
+  a.H = H;
+  a.rx = (p.census_w - 1) / 2;
+  a.d_min = p.d_min;
+  a.d_max = p.d_max;
+  a.t_lo = p.t_lo;
+  a.t_hi = p.t_hi;
+  a.sz = sz;
+  a.Wc = Wc;
+  a.C_it = C_it;
+  a.D_f = D_f;
+  a.C_f = C_f;
+  a.cell_g = cell_g;
+  a.cell_b = cell_b;
+  a.mask = mask;
+  a.n_valid = n_valid;
+  hipLaunchKernelGGL(k_validate, dim3(blocks_for(W, kWave), blocks_for(H, 4)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_resample_cells(const uint64_t* cell_g, const uint64_t* cell_b,
+                                 const float* D_it, int32_t W, int32_t H, int32_t sz,
+                                 const sm_params& p, sm_support* slots, hipStream_t s) {
+  const int n_cells = ((W + sz - 1) / sz) * ((H + sz - 1) / sz);
+  const uint64_t ginit = (uint64_t)p.t_lo << 32, binit = (uint64_t)(255 - p.t_hi) << 32;
+  hipLaunchKernelGGL(k_resample_cells, dim3(blocks_for(n_cells, 256)), dim3(256), 0, s, cell_g,
+                     cell_b, D_it, W, n_cells, ginit, binit, slots);
+  return hipGetLastError();
+}
+
+}  // namespace sm

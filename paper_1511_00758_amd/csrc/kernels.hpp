@@ -1,0 +1,69 @@
+// Launchers of the stereomesh device kernels (gfx950). Internal header: every
+// launcher only enqueues work on `stream` and returns the launch status; argument
+// checking happens in the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "stereomesh.h"
+
+namespace sm {
+
+// Marker values in sm_support::d for candidate slots (real disparities are >= 0).
+constexpr float kPending = -1.0f;   // candidate waiting to be matched
+constexpr float kRejected = -2.0f;  // empty slot / rejected candidate
+
+struct CensusJob {
+  const uint8_t* img;
+  int32_t stride;
+  uint64_t* census;
+  uint8_t* omega;  // may be null
+};
+
+// Census words (+ Omega_I) of one or two images of the same size in one launch.
+// When D_f / C_f / occ are non-null they are initialised (0, t_hi, 0) on the way.
+hipError_t launch_census(const CensusJob* jobs, int n_jobs, int32_t W, int32_t H, int32_t cw,
+                         int32_t ch, int32_t grad_thr, float* D_f, uint8_t* C_f, int32_t t_hi,
+                         uint8_t* occ, hipStream_t s);
+
+// Candidate slots: grid nodes (omega-filtered) or an explicit (u, v) list.
+hipError_t launch_grid_slots(const uint8_t* omega, int32_t W, int32_t H, int32_t step,
+                             sm_support* slots, int32_t n, hipStream_t s);
+hipError_t launch_list_slots(const int16_t* uv, int32_t n, sm_support* slots, hipStream_t s);
+
+// Epipolar matching with left-right check of every pending slot, in place.
+hipError_t launch_match(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
+                        const sm_params& p, sm_support* slots, int32_t n, hipStream_t s);
+
+// Order-preserving in-place compaction of slots with d >= 0 (and, when `occ` is
+// non-null, whose pixel is not yet occupied; kept pixels are then marked).
+hipError_t launch_compact(sm_support* slots, int32_t n, int32_t* n_out, uint8_t* occ,
+                          int32_t W, hipStream_t s);
+
+// Occupancy map of a support list (cleared first).
+hipError_t launch_mark(const sm_support* S, int32_t n, uint8_t* occ, int32_t W, int32_t H,
+                       hipStream_t s);
+
+// D_it: NaN fill, then per-triangle plane + rasterisation.
+hipError_t launch_interpolate(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
+                              int32_t W, int32_t H, float* D_it, hipStream_t s);
+
+// Zero `bytes` bytes (a kernel, so the call is safe inside captured graphs).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+// Cell keys reset, then cost evaluation + refinement (+ final mask when non-null).
+hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
+                           const float* D_it, int32_t W, int32_t H, const sm_params& p,
+                           int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f, uint64_t* cell_g,
+                           uint64_t* cell_b, uint8_t* mask, unsigned long long* n_valid,
+                           hipStream_t s);
+
+// Cells -> slots: confident supports at slots[0, cells), X candidates at
+// slots[cells, 2 cells).
+hipError_t launch_resample_cells(const uint64_t* cell_g, const uint64_t* cell_b,
+                                 const float* D_it, int32_t W, int32_t H, int32_t sz,
+                                 const sm_params& p, sm_support* slots, hipStream_t s);
+
+}  // namespace sm

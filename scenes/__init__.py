@@ -266,7 +266,7 @@ def make_rect_scene(W, H, seed, n_rects=19, dlo=2.0, dhi=124.0, flat_frac=0.05,
     """Background plane plus ``n_rects`` slanted rectangles (sides 40-200 px, scaled
     with the image width) and untextured patches covering about ``flat_frac``."""
     rng = np.random.default_rng(seed)
-    scale = max(1.0, W / 640.0)
+    scale = W / 640.0
     bg_d = (dlo, min(dhi, dlo + 0.25 * (dhi - dlo)))
     a, b, c = _plane_in_range(rng, (0, 0, W, H), bg_d[0], bg_d[1], 0.03)
     surfaces = [_surface(rng, W, H, a, b, c, (-INF, -INF, INF, INF))]

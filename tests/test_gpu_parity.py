@@ -1,0 +1,391 @@
+"""GPU parity: every C-ABI stage against the CPU oracle on identical seeded inputs.
+
+Bit-exact for census words, Omega_I, matches, costs, cells, supports and masks; the
+float32 interpolated disparity within 1e-3 px (it is expected to be bit-exact, since
+both sides follow the same rounding recipe).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import scenes
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+TOL_PX = 1e-3
+
+
+def _api():
+    from paper_1511_00758_amd import api
+    return api
+
+
+def _note(*a):
+    print("[gpu-parity]", *a, file=sys.stderr, flush=True)
+
+
+def _u64(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+def _to_dev(a: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _supports_list(arr):
+    return [(int(s["u"]), int(s["v"]), float(s["d"])) for s in arr]
+
+
+# ----------------------------------------------------------------------------------
+# census
+# ----------------------------------------------------------------------------------
+CENSUS_CASES = [
+    ("c1", 1, None, 5, 5), ("c2", 2, None, 7, 7), ("c3", 3, None, 7, 7),
+    ("rand_3x3", None, (37, 29), 3, 3), ("rand_9x7", None, (70, 21), 9, 7),
+    ("rand_7x9", None, (33, 40), 7, 9), ("tiny_3x3", None, (3, 3), 3, 3),
+    ("tiny_5x5", None, (5, 6), 5, 5), ("ragged", None, (131, 67), 5, 3),
+]
+
+
+@pytest.mark.parametrize("name,cfg,size,cw,ch", CENSUS_CASES)
+def test_census_parity(name, cfg, size, cw, ch):
+    _note("census", name)
+    api = _api()
+    if cfg is not None:
+        sc = scenes.make_scene(cfg, scenes.seed_of(cfg, 3))
+        imgs = (sc.left, sc.right)
+    else:
+        imgs = scenes.random_pair(size[0], size[1], seed=size[0] * 7 + cw)
+    for img in imgs:
+        words, valid = oracle.census(img, cw, ch)
+        om = oracle.high_gradient(img, valid, 16)
+        g_words, g_om = api.census(_to_dev(img), cw, ch, 16)
+        torch.cuda.synchronize()
+        assert (_u64(g_words) == words).all()
+        assert (g_om.cpu().numpy().astype(bool) == om).all()
+
+
+def test_census_row_pitch():
+    api = _api()
+    l, _ = scenes.random_pair(61, 17, 4)
+    big = np.zeros((17, 96), np.uint8)
+    big[:, :61] = l
+    t = _to_dev(big)[:, :61]          # a view with pitch 96
+    words, _ = oracle.census(l, 5, 5)
+    L = api._lib.load()
+    out = torch.empty((17, 61), dtype=torch.int64, device=DEV)
+    api.check(L.sm_census(t.data_ptr(), 61, 17, 96, 5, 5, 0, out.data_ptr(), None,
+                          torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert (_u64(out) == words).all()
+
+
+# ----------------------------------------------------------------------------------
+# matching
+# ----------------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def frames():
+    out = {}
+    for cfg, frame in ((1, 0), (2, 0), (3, 0)):
+        sc = scenes.make_scene(cfg, scenes.seed_of(cfg, frame))
+        p = oracle.Params.from_dict(sc.params)
+        _note("oracle solve", cfg, frame)
+        tr = oracle.solve(sc.left, sc.right, p, trace=True)
+        out[cfg] = (sc, p, tr)
+    return out
+
+
+def _dev_census(sc, p):
+    api = _api()
+    cL, om = api.census(_to_dev(sc.left), p.census_w, p.census_h, p.grad_thr)
+    cR, _ = api.census(_to_dev(sc.right), p.census_w, p.census_h, p.grad_thr, with_omega=False)
+    return cL, cR, om
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_match_grid_parity(frames, cfg):
+    _note("match grid", cfg)
+    api = _api()
+    sc, p, tr = frames[cfg]
+    cL, cR, om = _dev_census(sc, p)
+    buf, n = api.match_support(cL, cR, om, sc.params)
+    got = _supports_list(api.supports_to_numpy(buf, int(n.item())))
+    assert got == tr["iters"][0]["S"]
+
+
+@pytest.mark.parametrize("variant", [dict(uniqueness=0), dict(uniqueness=4, lr_tol=0),
+                                     dict(d_min=20, d_max=20), dict(d_min=0, d_max=255),
+                                     dict(t_hi=3, t_lo=1), dict(d_min=7, d_max=70)])
+def test_match_list_parity(frames, variant):
+    """Explicit candidate lists (every valid pixel of a band), parameter variants."""
+    _note("match list", variant)
+    api = _api()
+    sc, _, tr = frames[2]
+    prm = dict(sc.params)
+    prm.update(variant)
+    p = oracle.Params.from_dict(prm)
+    cL_np, cR_np = tr["cL"], tr["cR"]
+    rng = np.random.default_rng(1)
+    rx, ry = p.rx, p.ry
+    H, W = cL_np.shape
+    us = rng.integers(rx, W - rx, size=3000)
+    vs = rng.integers(ry, H - ry, size=3000)
+    cands = list(zip(us.tolist(), vs.tolist()))
+    exp = oracle.sparse_stereo(cL_np, cR_np, cands, p)
+    cL = _to_dev(cL_np.view(np.int64))
+    cR = _to_dev(cR_np.view(np.int64))
+    buf, n = api.match_support(cL, cR, None, prm, cand_uv=np.array(cands, np.int16))
+    got = _supports_list(api.supports_to_numpy(buf, int(n.item())))
+    assert got == exp
+
+
+def test_match_border_candidates_rejected(frames):
+    api = _api()
+    sc, p, tr = frames[1]
+    cL, cR, _ = _dev_census(sc, p)
+    H, W = sc.left.shape
+    cands = np.array([(0, 50), (1, 50), (W - 1, 50), (100, 0), (100, H - 1), (100, 1)], np.int16)
+    buf, n = api.match_support(cL, cR, None, sc.params, cand_uv=cands)
+    assert int(n.item()) == 0
+
+
+# ----------------------------------------------------------------------------------
+# interpolation
+# ----------------------------------------------------------------------------------
+def _interp_compare(S, tris, W, H):
+    api = _api()
+    exp = oracle.interpolate(S, tris, W, H)
+    arr = np.zeros(len(S), dtype=api.SUPPORT_DTYPE)
+    for i, s in enumerate(S):
+        arr[i] = (s[0], s[1], s[2])
+    S_dev = api.supports_to_device(arr, DEV)
+    got = api.interpolate(S_dev, len(S), np.array(tris, np.int32).reshape(-1, 3), W, H).cpu().numpy()
+    nan_e, nan_g = np.isnan(exp), np.isnan(got)
+    assert (nan_e == nan_g).all()
+    diff = np.abs(got[~nan_e] - exp[~nan_e])
+    assert diff.max(initial=0.0) <= TOL_PX
+    return (diff == 0).mean() if diff.size else 1.0
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_interpolate_parity_frames(frames, cfg):
+    _note("interpolate", cfg)
+    sc, p, tr = frames[cfg]
+    H, W = sc.left.shape
+    for it in tr["iters"]:
+        exact = _interp_compare(it["S"], it["tris"], W, H)
+        assert exact == 1.0
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_interpolate_parity_random_float_supports(seed):
+    rng = np.random.default_rng(seed)
+    W, H = 203, 151
+    pts = list({(int(rng.integers(0, W)), int(rng.integers(0, H))) for _ in range(400)})
+    S = [(u, v, float(np.float32(rng.uniform(-0.4, 255)))) for (u, v) in pts]
+    tris = oracle.triangulate(S, W)
+    assert _interp_compare(S, tris, W, H) == 1.0
+
+
+def test_interpolate_supports_outside_image():
+    """Hull larger than the image: rows and columns are clipped."""
+    W, H = 64, 40
+    S = [(0, 0, 5.0), (200, 0, 9.0), (0, 100, 1.0), (150, 90, 30.0), (30, 20, 12.5)]
+    tris = oracle.triangulate(S, 8192)
+    assert _interp_compare(S, tris, W, H) == 1.0
+
+
+def test_interpolate_no_triangles():
+    api = _api()
+    D = api.interpolate(api.new_support_buffer(1, DEV), 0, np.zeros((0, 3), np.int32), 17, 9)
+    assert torch.isnan(D).all()
+
+
+# ----------------------------------------------------------------------------------
+# validation + refinement
+# ----------------------------------------------------------------------------------
+def _decode(keys: np.ndarray, W, init, bad):
+    out = {}
+    for c, k in enumerate(keys.view(np.uint64).tolist()):
+        if k == init:
+            continue
+        cost = (k >> 32)
+        idx = k & 0xffffffff
+        out[c] = (idx % W, idx // W, 255 - cost if bad else cost)
+    return out
+
+
+def _oracle_cells(cells):
+    out = {}
+    Wc = len(cells[0])
+    for cy, row in enumerate(cells):
+        for cx, cell in enumerate(row):
+            if cell.set:
+                out[cy * Wc + cx] = (cell.u, cell.v, cell.cost)
+    return out
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_validate_parity(frames, cfg):
+    _note("validate", cfg)
+    api = _api()
+    sc, p, tr = frames[cfg]
+    H, W = sc.left.shape
+    cL = _to_dev(tr["cL"].view(np.int64))
+    cR = _to_dev(tr["cR"].view(np.int64))
+    om = _to_dev(tr["omega"].astype(np.uint8))
+    D_f = torch.zeros((H, W), dtype=torch.float32, device=DEV)
+    C_f = torch.full((H, W), p.t_hi, dtype=torch.uint8, device=DEV)
+    for it in tr["iters"]:
+        C_it, g, b = api.validate(cL, cR, om, _to_dev(it["D_it"]), sc.params, it["sz_occ"], D_f, C_f)
+        torch.cuda.synchronize()
+        assert (C_it.cpu().numpy() == it["C_it"]).all()
+        assert (C_f.cpu().numpy() == it["C_f"]).all()
+        assert (D_f.cpu().numpy().view(np.uint32) == it["D_f"].view(np.uint32)).all()
+        assert _decode(g.cpu().numpy(), W, p.t_lo << 32, False) == _oracle_cells(it["Cg"])
+        assert _decode(b.cpu().numpy(), W, (255 - p.t_hi) << 32, True) == _oracle_cells(it["Cb"])
+
+
+@pytest.mark.parametrize("sz", [1, 3, 7, 24, 64, 100])
+def test_validate_cells_any_size(frames, sz):
+    """Cell sizes that are not powers of two and cells wider than a wave."""
+    api = _api()
+    sc, p, tr = frames[1]
+    H, W = sc.left.shape
+    it = tr["iters"][0]
+    D_f0 = np.zeros((H, W), np.float32)
+    C_f0 = np.full((H, W), p.t_hi, np.uint8)
+    Cg, Cb = oracle.disparity_refinement(it["D_it"], it["C_it"], D_f0, C_f0, p, sz)
+    D_f = torch.zeros((H, W), dtype=torch.float32, device=DEV)
+    C_f = torch.full((H, W), p.t_hi, dtype=torch.uint8, device=DEV)
+    _, g, b = api.validate(_to_dev(tr["cL"].view(np.int64)), _to_dev(tr["cR"].view(np.int64)),
+                           _to_dev(tr["omega"].astype(np.uint8)), _to_dev(it["D_it"]), sc.params, sz,
+                           D_f, C_f, want_C_it=False)
+    assert _decode(g.cpu().numpy(), W, p.t_lo << 32, False) == _oracle_cells(Cg)
+    assert _decode(b.cpu().numpy(), W, (255 - p.t_hi) << 32, True) == _oracle_cells(Cb)
+
+
+# ----------------------------------------------------------------------------------
+# resampling
+# ----------------------------------------------------------------------------------
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_resample_parity(frames, cfg):
+    _note("resample", cfg)
+    api = _api()
+    sc, p, tr = frames[cfg]
+    H, W = sc.left.shape
+    cL = _to_dev(tr["cL"].view(np.int64))
+    cR = _to_dev(tr["cR"].view(np.int64))
+    om = _to_dev(tr["omega"].astype(np.uint8))
+    D_f = torch.zeros((H, W), dtype=torch.float32, device=DEV)
+    C_f = torch.full((H, W), p.t_hi, dtype=torch.uint8, device=DEV)
+    for k, it in enumerate(tr["iters"][:-1]):
+        D_it = _to_dev(it["D_it"])
+        _, g, b = api.validate(cL, cR, om, D_it, sc.params, it["sz_occ"], D_f, C_f, want_C_it=False)
+        S = it["S"]
+        arr = np.array([(s[0], s[1], s[2]) for s in S], dtype=api.SUPPORT_DTYPE)
+        buf, n = api.resample(cL, cR, D_it, g, b, sc.params, it["sz_occ"],
+                              api.supports_to_device(arr, DEV), len(S))
+        got = _supports_list(api.supports_to_numpy(buf, int(n.item())))
+        assert got == tr["iters"][k + 1]["S"][len(S):]
+
+
+# ----------------------------------------------------------------------------------
+# end to end
+# ----------------------------------------------------------------------------------
+def _solve_gpu(sc, params, timing=False):
+    api = _api()
+    H, W = sc.left.shape
+    s = api.Solver(W, H, params, device=DEV)
+    r = s(_to_dev(sc.left), _to_dev(sc.right), stats=True, timing=timing)
+    torch.cuda.synchronize()
+    return r.D_f.cpu().numpy(), r.C_f.cpu().numpy(), r.mask.cpu().numpy(), r.stats
+
+
+def _compare_solve(sc, p, res, tr):
+    D_f, C_f, mask, st = res
+    assert st["n_support"] == [len(it["S"]) for it in tr["iters"]]
+    assert st["n_tris"] == [len(it["tris"]) for it in tr["iters"]]
+    assert (C_f == tr["C_f"]).all()
+    assert (mask.astype(bool) == tr["mask"]).all()
+    assert np.abs(D_f - tr["D_f"]).max() <= TOL_PX
+    assert (D_f.view(np.uint32) == tr["D_f"].view(np.uint32)).all()
+    assert st["n_valid"] == int(tr["mask"].sum())
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_solve_parity(frames, cfg):
+    _note("solve", cfg)
+    sc, p, tr = frames[cfg]
+    _compare_solve(sc, p, _solve_gpu(sc, sc.params), tr)
+
+
+@pytest.mark.parametrize("cfg,frame", [(1, 5), (2, 7)])
+def test_solve_parity_more_seeds(cfg, frame):
+    _note("solve seed", cfg, frame)
+    sc = scenes.make_scene(cfg, scenes.seed_of(cfg, frame))
+    p = oracle.Params.from_dict(sc.params)
+    _compare_solve(sc, p, _solve_gpu(sc, sc.params), oracle.solve(sc.left, sc.right, p, trace=True))
+
+
+@pytest.mark.parametrize("tau", [8, 16])
+def test_solve_parity_threshold_sweep(tau):
+    """The driving workload's threshold sweep (the 12 case is covered above)."""
+    _note("solve tau", tau)
+    sc = scenes.make_scene(3, scenes.seed_of(3, 1), t_hi=tau, t_lo=tau // 2)
+    p = oracle.Params.from_dict(sc.params)
+    _compare_solve(sc, p, _solve_gpu(sc, sc.params), oracle.solve(sc.left, sc.right, p, trace=True))
+
+
+EDGE_CASES = [
+    ("deep_iters_sz_to_1", (96, 72), dict(n_iters=7, census_w=5, census_h=5, d_max=31, t_hi=8, t_lo=4)),
+    ("sz24_non_pow2", (130, 90), dict(n_iters=4, sz_occ0=24, census_w=5, census_h=5, d_max=40,
+                                      t_hi=8, t_lo=4)),
+    ("census_3x3", (100, 80), dict(n_iters=3, census_w=3, census_h=3, t_hi=3, t_lo=1, d_max=40)),
+    ("census_9x7", (100, 80), dict(n_iters=2, census_w=9, census_h=7, t_hi=16, t_lo=8, d_max=40)),
+    ("dense_grad0", (120, 64), dict(n_iters=3, grad_thr=0, census_w=5, census_h=5, t_hi=8, t_lo=4,
+                                    d_max=40)),
+    ("single_disparity", (90, 60), dict(n_iters=2, d_min=12, d_max=12, census_w=5, census_h=5,
+                                        t_hi=10, t_lo=5)),
+    ("wide_range_256", (300, 60), dict(n_iters=2, d_min=0, d_max=255, census_w=7, census_h=7,
+                                       t_hi=12, t_lo=6)),
+    ("step_7", (111, 77), dict(n_iters=2, support_step=7, census_w=5, census_h=5, d_max=40, t_hi=8,
+                               t_lo=4)),
+]
+
+
+@pytest.mark.parametrize("name,size,over", EDGE_CASES)
+def test_solve_edge_cases(name, size, over):
+    _note("solve edge", name)
+    W, H = size
+    sc = scenes.make_rect_scene(W, H, seed=W + H, n_rects=4, dlo=2.0, dhi=min(30.0, over.get("d_max", 63)))
+    prm = scenes.params_of(2)
+    prm.update(over)
+    p = oracle.Params.from_dict(prm)
+    _compare_solve(sc, p, _solve_gpu(sc, prm), oracle.solve(sc.left, sc.right, p, trace=True))
+
+
+def test_solve_constant_and_tiny_images():
+    for (W, H) in ((3, 3), (5, 5), (9, 4), (40, 30)):
+        img = np.full((H, W), 90, np.uint8)
+        prm = scenes.params_of(1)
+        p = oracle.Params.from_dict(prm)
+        sc = scenes.Scene(img, img, np.zeros((H, W), np.float32), np.ones((H, W), bool),
+                          np.ones((H, W), bool), prm)
+        D_f, C_f, mask, st = _solve_gpu(sc, prm)
+        tr = oracle.solve(img, img, p)
+        assert not mask.any() and (C_f == tr["C_f"]).all() and (D_f == 0).all()
+        assert st["n_support"][0] == 0 and st["n_tris"][0] == 0
+
+
+def test_solve_deterministic(frames):
+    sc, p, tr = frames[2]
+    a = _solve_gpu(sc, sc.params)
+    b = _solve_gpu(sc, sc.params, timing=True)
+    for x, y in zip(a[:3], b[:3]):
+        assert (x.view(np.uint8) == y.view(np.uint8)).all()
+    assert b[3]["stage_launches"]["census"] == 1 and b[3]["stage_us"]["validate"] > 0
