@@ -71,13 +71,27 @@ typedef struct {
   int32_t sz_occ0;             /* initial occupancy-grid size (32 in Alg. 1), 1..1024           */
 } sm_params;
 
-/* Per-solve statistics. `timing` is an input: when non-zero, sm_solve records HIP
- * events around every kernel launch on `stream` and reports device time per stage
- * (summed over iterations) in stage_us and per-launch counts in stage_launches.
- * Stage index: 0 census, 1 support matching (initial), 2 interpolation,
- * 3 validation, 4 resampling (cells, re-matching, compaction), 5 host triangulation
- * (wall time), 6 host<->device copies and waits (wall time), 7 whole solve (wall). */
-#define SM_STAGES 8
+/* Per-solve statistics. `timing` is an input: when non-zero, sm_solve records a pair of
+ * HIP events on `stream` around every kernel launch and reports, per kernel, the summed
+ * device time (stage_us) and the launch count (stage_launches); the host stages report
+ * wall time. Indices are the sm_stage values. */
+typedef enum {
+  SM_ST_CENSUS = 0,          /* census + Omega_I of both images (and output initialisation) */
+  SM_ST_GRID = 1,            /* support-grid candidate slots                                 */
+  SM_ST_MATCH = 2,           /* epipolar matching of the initial candidates                  */
+  SM_ST_COMPACT = 3,         /* order-preserving compaction of matched / resampled supports   */
+  SM_ST_FILL = 4,            /* NaN fill of D_it                                             */
+  SM_ST_RASTER = 5,          /* plane fit + per-triangle rasterisation                       */
+  SM_ST_CELLS_INIT = 6,      /* occupancy-cell reset                                         */
+  SM_ST_VALIDATE = 7,        /* cost evaluation + refinement                                 */
+  SM_ST_RESAMPLE_CELLS = 8,  /* cells -> confident supports and re-match candidates          */
+  SM_ST_REMATCH = 9,         /* epipolar matching of the resampled candidates                */
+  SM_ST_ZERO = 10,           /* counter reset                                                */
+  SM_ST_HOST_TRI = 12,       /* host triangulation (wall time)                               */
+  SM_ST_HOST_COPY = 13,      /* host<->device copies and waits (wall time)                   */
+  SM_ST_TOTAL = 14           /* whole sm_solve call (wall time)                              */
+} sm_stage;
+#define SM_STAGES 16
 typedef struct {
   int32_t timing;                       /* [in]  non-zero: collect stage_us          */
   int32_t n_support[8];                 /* [out] |S_it| per iteration                 */

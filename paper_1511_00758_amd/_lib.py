@@ -15,8 +15,11 @@ c_vp, c_size = ctypes.c_void_p, ctypes.c_size_t
 SM_OK, SM_ERR_ARG, SM_ERR_CAPACITY, SM_ERR_HIP, SM_ERR_INTERNAL = 0, -1, -2, -3, -4
 STATUS_NAMES = {0: "SM_OK", -1: "SM_ERR_ARG", -2: "SM_ERR_CAPACITY", -3: "SM_ERR_HIP",
                 -4: "SM_ERR_INTERNAL"}
-STAGES = ("census", "match", "interpolate", "validate", "resample", "host_triangulate",
-          "host_copies", "total")
+# sm_stage indices of sm_stats.stage_us / stage_launches
+STAGES = {"census": 0, "grid_slots": 1, "match": 2, "compact": 3, "nan_fill": 4, "raster": 5,
+          "cells_init": 6, "validate": 7, "resample_cells": 8, "rematch": 9, "zero": 10,
+          "host_triangulate": 12, "host_copies": 13, "total": 14}
+N_STAGES = 16
 
 
 class SmSupport(ctypes.Structure):
@@ -37,7 +40,8 @@ class SmParams(ctypes.Structure):
 
 class SmStats(ctypes.Structure):
     _fields_ = [("timing", c_i32), ("n_support", c_i32 * 8), ("n_tris", c_i32 * 8),
-                ("n_valid", c_i64), ("stage_us", c_f32 * 8), ("stage_launches", c_i32 * 8)]
+                ("n_valid", c_i64), ("stage_us", c_f32 * N_STAGES),
+                ("stage_launches", c_i32 * N_STAGES)]
 
 
 EXPORTS = ("sm_census", "sm_match_support", "sm_grid_candidates", "sm_triangulate",

@@ -167,8 +167,8 @@ def stats_dict(st: "_lib.SmStats", n_iters: int) -> dict:
         "n_support": list(st.n_support)[:n_iters],
         "n_tris": list(st.n_tris)[:n_iters],
         "n_valid": int(st.n_valid),
-        "stage_us": {k: float(v) for k, v in zip(_lib.STAGES, st.stage_us)},
-        "stage_launches": {k: int(v) for k, v in zip(_lib.STAGES, st.stage_launches)},
+        "stage_us": {k: float(st.stage_us[i]) for k, i in _lib.STAGES.items()},
+        "stage_launches": {k: int(st.stage_launches[i]) for k, i in _lib.STAGES.items()},
     }
 
 

@@ -67,6 +67,7 @@ struct ThreadCtx {
   bool copy_pending = false;
   Delaunay dl;
   std::vector<sm_tri> tris;
+  std::vector<int32_t> bu, bv, bext;
   StageTimer timer;
 };
 
@@ -249,10 +250,27 @@ sm_status sm_triangulate(const sm_support* S, int32_t n, sm_tri* tris, int32_t c
   last_error().clear();
   if (n < 0 || (n > 0 && !S) || !n_tris) return fail(SM_ERR_ARG, "bad support array / count");
   try {
-    Delaunay dl;
     for (int32_t i = 0; i < n; ++i)
-      if (!dl.insert(S[i].u, S[i].v, i))
+      if (S[i].u < 0 || S[i].v < 0 || S[i].u > 8191 || S[i].v > 8191)
         return fail(SM_ERR_ARG, "support %d at (%d, %d) outside [0, 8191]^2", i, S[i].u, S[i].v);
+    // keep the first occurrence of every pixel (the insertion order is randomised below)
+    std::vector<uint64_t> key(n);
+    for (int32_t i = 0; i < n; ++i)
+      key[i] = ((uint64_t)(uint16_t)S[i].v << 48) | ((uint64_t)(uint16_t)S[i].u << 32) | (uint32_t)i;
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> u, v, ext;
+    u.reserve(n);
+    v.reserve(n);
+    ext.reserve(n);
+    for (int32_t k = 0; k < n; ++k) {
+      if (k > 0 && (key[k] >> 32) == (key[k - 1] >> 32)) continue;
+      const int32_t i = (int32_t)(key[k] & 0xffffffffu);
+      u.push_back(S[i].u);
+      v.push_back(S[i].v);
+      ext.push_back(i);
+    }
+    Delaunay dl;
+    dl.insert_many(u.data(), v.data(), ext.data(), (int32_t)u.size());
     std::vector<sm_tri> out;
     dl.emit(out, true);
     *n_tris = (int32_t)out.size();
@@ -359,16 +377,22 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   float us_host = 0.f, us_xfer = 0.f;
 
   // census of both images; D_f = 0, C_f = t_hi, occupancy cleared (Alg. 1 initialisation)
-  SM_TRY(tm.begin(0));
   CensusJob jobs[2] = {{L, stride, cL, omega}, {R, stride, cR, nullptr}};
+  SM_TRY(tm.begin(SM_ST_CENSUS));
   SM_HIP(launch_census(jobs, 2, W, H, p->census_w, p->census_h, p->grad_thr, D_f, C_f, p->t_hi, occ, s));
   SM_TRY(tm.end());
+  SM_TRY(tm.begin(SM_ST_ZERO));
   SM_HIP(launch_zero(counters, 64, s));
+  SM_TRY(tm.end());
 
   // S_1 = SparseStereo(I_l, I_r) over the candidate grid
-  SM_TRY(tm.begin(1));
+  SM_TRY(tm.begin(SM_ST_GRID));
   SM_HIP(launch_grid_slots(omega, W, H, p->support_step, Sd, Lo.n_grid, s));
+  SM_TRY(tm.end());
+  SM_TRY(tm.begin(SM_ST_MATCH));
   SM_HIP(launch_match(cL, cR, W, H, *p, Sd, Lo.n_grid, s));
+  SM_TRY(tm.end());
+  SM_TRY(tm.begin(SM_ST_COMPACT));
   SM_HIP(launch_compact(Sd, Lo.n_grid, &counters[0], occ, W, s));
   SM_TRY(tm.end());
 
@@ -385,9 +409,17 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     auto th = clk::now();
     try {
       if (from == 0) c.dl.reset();
-      for (int32_t i = from; i < to; ++i)
-        if (!c.dl.insert(h_S[i - from].u, h_S[i - from].v, i))
-          return fail(SM_ERR_INTERNAL, "support outside range");
+      const int32_t m = to - from;
+      c.bu.resize(m);
+      c.bv.resize(m);
+      c.bext.resize(m);
+      for (int32_t k = 0; k < m; ++k) {
+        c.bu[k] = h_S[k].u;
+        c.bv[k] = h_S[k].v;
+        c.bext[k] = from + k;
+      }
+      if (!c.dl.insert_many(c.bu.data(), c.bv.data(), c.bext.data(), m))
+        return fail(SM_ERR_INTERNAL, "support outside range");
       c.tris.clear();
       c.dl.emit(c.tris, false);
     } catch (...) {
@@ -416,21 +448,33 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
       st->n_support[it - 1] = n_S;
       st->n_tris[it - 1] = n_T;
     }
-    SM_TRY(tm.begin(2));
-    SM_HIP(launch_interpolate(Sd, n_S, Td, n_T, W, H, D_it, s));
+    SM_TRY(tm.begin(SM_ST_FILL));
+    SM_HIP(launch_fill_nan(D_it, (size_t)W * H, s));
     SM_TRY(tm.end());
-    SM_TRY(tm.begin(3));
-    SM_HIP(launch_validate(cL, cR, omega, D_it, W, H, *p, sz, nullptr, D_f, C_f, cell_g, cell_b,
-                           last ? mask : nullptr, last ? n_valid : nullptr, s));
+    if (n_T > 0) {
+      SM_TRY(tm.begin(SM_ST_RASTER));
+      SM_HIP(launch_raster(Sd, n_S, Td, n_T, W, H, D_it, s));
+      SM_TRY(tm.end());
+    }
+    SM_TRY(tm.begin(SM_ST_CELLS_INIT));
+    SM_HIP(launch_cells_init(cell_g, cell_b, W, H, sz, *p, s));
+    SM_TRY(tm.end());
+    SM_TRY(tm.begin(SM_ST_VALIDATE));
+    SM_HIP(launch_validate_only(cL, cR, omega, D_it, W, H, *p, sz, nullptr, D_f, C_f, cell_g, cell_b,
+                                last ? mask : nullptr, last ? n_valid : nullptr, s));
     SM_TRY(tm.end());
     if (last) break;
     // S_it+1 = SupportResampling(C_g, C_b, S_it), appended in place after S_it
     const int32_t cells = cells_of(W, H, sz);
     if (n_S + 2 * cells > Lo.S_cap) return fail(SM_ERR_INTERNAL, "support capacity exceeded");
     sm_support* region = Sd + n_S;
-    SM_TRY(tm.begin(4));
+    SM_TRY(tm.begin(SM_ST_RESAMPLE_CELLS));
     SM_HIP(launch_resample_cells(cell_g, cell_b, D_it, W, H, sz, *p, region, s));
+    SM_TRY(tm.end());
+    SM_TRY(tm.begin(SM_ST_REMATCH));
     SM_HIP(launch_match(cL, cR, W, H, *p, region + cells, cells, s));
+    SM_TRY(tm.end());
+    SM_TRY(tm.begin(SM_ST_COMPACT));
     SM_HIP(launch_compact(region, 2 * cells, &counters[1], occ, W, s));
     SM_TRY(tm.end());
     t0 = clk::now();
@@ -452,9 +496,9 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     us_xfer += us_since(t0);
     st->n_valid = (int64_t)nv;
     SM_TRY(tm.collect(st));
-    st->stage_us[5] = us_host;
-    st->stage_us[6] = us_xfer;
-    st->stage_us[7] = us_since(t_start);
+    st->stage_us[SM_ST_HOST_TRI] = us_host;
+    st->stage_us[SM_ST_HOST_COPY] = us_xfer;
+    st->stage_us[SM_ST_TOTAL] = us_since(t_start);
   }
   return SM_OK;
 }

@@ -7,6 +7,25 @@ namespace sm {
 
 namespace {
 inline int sgn(int64_t x) { return (x > 0) - (x < 0); }
+
+// Index of (x, y) along a Hilbert curve over [0, 8192)^2.
+inline uint32_t hilbert(uint32_t x, uint32_t y) {
+  uint32_t d = 0;
+  for (uint32_t s = 1u << 12; s > 0; s >>= 1) {
+    const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+    d += s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = s - 1 - (x & (s - 1));
+        y = s - 1 - (y & (s - 1));
+      }
+      const uint32_t t = x;
+      x = y;
+      y = t;
+    }
+  }
+  return d;
+}
 }  // namespace
 
 void Delaunay::reset() {
@@ -284,6 +303,34 @@ bool Delaunay::insert(int32_t u, int32_t v, int32_t ext) {
     return true;
   }
   pending_.push_back(p);
+  return true;
+}
+
+bool Delaunay::insert_many(const int32_t* u, const int32_t* v, const int32_t* ext, int32_t n) {
+  for (int32_t i = 0; i < n; ++i)
+    if (u[i] < 0 || v[i] < 0 || u[i] > 8191 || v[i] > 8191) return false;
+  // round of point i: random, with round k holding about half of the points of round k+1
+  order_.resize(n);
+  uint32_t r = 0x2545f491u;
+  for (int32_t i = 0; i < n; ++i) {
+    r ^= r << 13;
+    r ^= r >> 17;
+    r ^= r << 5;
+    uint32_t round = 0;  // number of leading coin flips that came up heads, capped
+    uint32_t bits = r;
+    while ((bits & 1u) && round < 20) {
+      ++round;
+      bits >>= 1;
+    }
+    // rare high rounds go first; within a round, Hilbert order; then the input index
+    order_[i] = (((uint64_t)(31 - round)) << 58) | ((uint64_t)hilbert((uint32_t)u[i], (uint32_t)v[i]) << 26) |
+                (uint64_t)i;
+  }
+  std::sort(order_.begin(), order_.end());
+  for (int32_t k = 0; k < n; ++k) {
+    const int32_t i = (int32_t)(order_[k] & ((1u << 26) - 1));
+    insert(u[i], v[i], ext[i]);
+  }
   return true;
 }
 

@@ -30,6 +30,11 @@ class Delaunay {
   // point are skipped (the first occurrence stays). Returns false if a point lies
   // outside [0, 8191]^2.
   bool insert(int32_t u, int32_t v, int32_t ext);
+  // Inserts n points in a biased randomised insertion order (random rounds of doubling
+  // size, each round in Hilbert-curve order): short walks and small holes whatever
+  // the input order. Returns false if a point lies outside [0, 8191]^2 (nothing is
+  // inserted then).
+  bool insert_many(const int32_t* u, const int32_t* v, const int32_t* ext, int32_t n);
   // Appends the solid triangles as external indices, counter-clockwise, first
   // vertex = smallest (v, u). Sorted by (i0, i1, i2) when `sorted`.
   void emit(std::vector<sm_tri>& out, bool sorted) const;
@@ -51,6 +56,7 @@ class Delaunay {
   struct Edge { int32_t a, b, out; };
   std::vector<Edge> bnd_;
   std::vector<int32_t> newt_;
+  std::vector<uint64_t> order_;
   uint32_t gen_ = 0;
   int32_t hint_ = -1;
   int32_t n_solid_ = 0;

@@ -516,30 +516,41 @@ hipError_t launch_mark(const sm_support* S, int32_t n, uint8_t* occ, int32_t W, 
   return hipGetLastError();
 }
 
-hipError_t launch_interpolate(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
-                              int32_t W, int32_t H, float* D_it, hipStream_t s) {
-  const size_t npx = (size_t)W * H;
-  hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(npx, 256)), dim3(256), 0, s, D_it, npx,
-                     __builtin_nanf(""));
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || n_tris <= 0) return e;
+hipError_t launch_fill_nan(float* D, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, D, n, __builtin_nanf(""));
+  return hipGetLastError();
+}
+
+hipError_t launch_raster(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
+                         int32_t W, int32_t H, float* D_it, hipStream_t s) {
+  if (n_tris <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_raster, dim3(blocks_for(n_tris, 4)), dim3(256), 0, s, S, n_support, T, n_tris, W,
                      H, D_it);
   return hipGetLastError();
 }
 
-hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
-                           const float* D_it, int32_t W, int32_t H, const sm_params& p,
-                           int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f, uint64_t* cell_g,
-                           uint64_t* cell_b, uint8_t* mask, unsigned long long* n_valid,
-                           hipStream_t s) {
-  const int Wc = (W + sz - 1) / sz, Hc = (H + sz - 1) / sz;
-  const int n_cells = Wc * Hc;
+hipError_t launch_interpolate(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
+                              int32_t W, int32_t H, float* D_it, hipStream_t s) {
+  hipError_t e = launch_fill_nan(D_it, (size_t)W * H, s);
+  if (e != hipSuccess) return e;
+  return launch_raster(S, n_support, T, n_tris, W, H, D_it, s);
+}
+
+hipError_t launch_cells_init(uint64_t* cell_g, uint64_t* cell_b, int32_t W, int32_t H, int32_t sz,
+                             const sm_params& p, hipStream_t s) {
+  const int n_cells = ((W + sz - 1) / sz) * ((H + sz - 1) / sz);
   const uint64_t ginit = (uint64_t)p.t_lo << 32, binit = (uint64_t)(255 - p.t_hi) << 32;
   hipLaunchKernelGGL(k_cells_init, dim3(blocks_for(n_cells, 256)), dim3(256), 0, s, cell_g, cell_b,
                      n_cells, ginit, binit);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
+                                const float* D_it, int32_t W, int32_t H, const sm_params& p,
+                                int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f,
+                                uint64_t* cell_g, uint64_t* cell_b, uint8_t* mask,
+                                unsigned long long* n_valid, hipStream_t s) {
   ValidateArgs a;
   a.cL = cL;
   a.cR = cR;
@@ -553,7 +564,7 @@ hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t
   a.t_lo = p.t_lo;
   a.t_hi = p.t_hi;
   a.sz = sz;
-  a.Wc = Wc;
+  a.Wc = (W + sz - 1) / sz;
   a.C_it = C_it;
   a.D_f = D_f;
   a.C_f = C_f;
@@ -563,6 +574,17 @@ hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t
   a.n_valid = n_valid;
   hipLaunchKernelGGL(k_validate, dim3(blocks_for(W, kWave), blocks_for(H, 4)), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
+                           const float* D_it, int32_t W, int32_t H, const sm_params& p,
+                           int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f, uint64_t* cell_g,
+                           uint64_t* cell_b, uint8_t* mask, unsigned long long* n_valid,
+                           hipStream_t s) {
+  hipError_t e = launch_cells_init(cell_g, cell_b, W, H, sz, p, s);
+  if (e != hipSuccess) return e;
+  return launch_validate_only(cL, cR, omega, D_it, W, H, p, sz, C_it, D_f, C_f, cell_g, cell_b, mask,
+                              n_valid, s);
 }
 
 hipError_t launch_resample_cells(const uint64_t* cell_g, const uint64_t* cell_b,
