@@ -456,9 +456,6 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
       SM_HIP(launch_raster(Sd, n_S, Td, n_T, W, H, D_it, s));
       SM_TRY(tm.end());
     }
-    SM_TRY(tm.begin(SM_ST_CELLS_INIT));
-    SM_HIP(launch_cells_init(cell_g, cell_b, W, H, sz, *p, s));
-    SM_TRY(tm.end());
     SM_TRY(tm.begin(SM_ST_VALIDATE));
     SM_HIP(launch_validate_only(cL, cR, omega, D_it, W, H, *p, sz, nullptr, D_f, C_f, cell_g, cell_b,
                                 last ? mask : nullptr, last ? n_valid : nullptr, s));

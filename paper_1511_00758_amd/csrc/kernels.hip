@@ -311,16 +311,24 @@ __global__ __launch_bounds__(256) void k_raster(const sm_support* S, int n_suppo
 }
 
 // ------------------------------------------------------------------------------------
-// Cost evaluation + refinement. 64 x 4 pixels per block; one wave = 64 consecutive
-// pixels of a row. Cell winners: segmented wave min of packed keys, then one 64-bit
-// atomicMin per (wave, cell); the key order makes the result independent of timing.
+// Cost evaluation + refinement. Each 256-thread workgroup owns whole occupancy cells: a
+// tile of cpr cells side by side (cpr = max(1, 64 / sz), TW = cpr * sz columns) and one
+// cell row (TH = sz rows; for sz < 4, TH = sz * (4 / sz) rows = several cell rows, one
+// wave per row). Lanes walk the tile's columns, waves its rows; every thread's pixels lie
+// in one cell, so each thread keeps one running minimum per cell array, followed by a
+// segmented shuffle minimum across lanes and a minimum across the waves of the same cell
+// row through LDS. Cell keys are then written with plain stores (no atomics, no reset
+// pass): the packed (cost, raster index) order makes the result the first-in-raster-
+// order winner of the sequential definition.
 // ------------------------------------------------------------------------------------
 struct ValidateArgs {
   const uint64_t* cL;
   const uint64_t* cR;
   const uint8_t* omega;
   const float* D_it;
-  int32_t W, H, rx, d_min, d_max, t_lo, t_hi, sz, Wc;
+  int32_t W, H, rx, d_min, d_max, t_lo, t_hi;
+  int32_t sz, Wc, Hc, cpr, TW, TH, crows;
+  uint64_t ginit, binit;
   uint8_t* C_it;
   float* D_f;
   uint8_t* C_f;
@@ -330,71 +338,94 @@ struct ValidateArgs {
   unsigned long long* n_valid;
 };
 
-__global__ void k_cells_init(uint64_t* g, uint64_t* b, int n, uint64_t ginit, uint64_t binit) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) {
-    g[i] = ginit;
-    b[i] = binit;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_validate(ValidateArgs a) {
+  __shared__ uint64_t sg[4][kWave];
+  __shared__ uint64_t sb[4][kWave];
+  __shared__ unsigned int s_valid;
   const int lane = threadIdx.x & (kWave - 1);
-  const int u = blockIdx.x * kWave + lane;
-  const int v = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (v >= a.H) return;  // wave-uniform
-  const bool in = u < a.W;
-  const size_t idx = (size_t)v * a.W + u;
-  uint32_t cost = 0xffu;
-  float D = 0.0f;
-  bool om = false;
-  if (in) {
-    om = a.omega[idx] != 0;
-    if (om) {
-      D = a.D_it[idx];
-      if (isfinite(D)) {
-        const float f = floorf(__fadd_rn(D, 0.5f));
-        if (f >= (float)a.d_min && f <= (float)a.d_max) {
-          const int d = (int)f;
-          if (u - d >= a.rx) cost = (uint32_t)__popcll(a.cL[idx] ^ a.cR[idx - d]);
+  const int w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_valid = 0;
+  const int x0 = blockIdx.x * a.TW, y0 = blockIdx.y * a.TH;
+  const uint64_t none = ~0ull;
+  uint64_t kg = none, kb = none;
+  unsigned int nvalid = 0;
+  for (int r = w; r < a.TH; r += 4) {
+    const int v = y0 + r;
+    if (v >= a.H) break;
+    for (int c = lane; c < a.TW; c += kWave) {
+      const int u = x0 + c;
+      if (u >= a.W) break;
+      const size_t idx = (size_t)v * a.W + u;
+      uint32_t cost = 0xffu;
+      float D = 0.0f;
+      const bool om = a.omega[idx] != 0;
+      if (om) {
+        D = a.D_it[idx];
+        if (isfinite(D)) {
+          const float f = floorf(__fadd_rn(D, 0.5f));
+          if (f >= (float)a.d_min && f <= (float)a.d_max) {
+            const int d = (int)f;
+            if (u - d >= a.rx) cost = (uint32_t)__popcll(a.cL[idx] ^ a.cR[idx - d]);
+          }
         }
       }
-    }
-    if (a.C_it) a.C_it[idx] = (uint8_t)cost;
-    uint32_t cf = a.C_f[idx];
-    if (cost != 0xffu && cost < cf) {
-      a.D_f[idx] = D;
-      a.C_f[idx] = (uint8_t)cost;
-      cf = cost;
-    }
-    if (a.mask) {
-      const bool mk = om && cf < (uint32_t)a.t_hi;
-      a.mask[idx] = mk;
-      const unsigned long long bm = __ballot(mk);
-      if (lane == 0 && bm) atomicAdd(a.n_valid, (unsigned long long)__popcll(bm));
+      if (a.C_it) a.C_it[idx] = (uint8_t)cost;
+      uint32_t cf = a.C_f[idx];
+      if (cost < cf) {  // never true for 0xff: C_f <= t_hi <= 64
+        a.D_f[idx] = D;
+        a.C_f[idx] = (uint8_t)cost;
+        cf = cost;
+      }
+      if (a.mask) {
+        const bool mk = om && cf < (uint32_t)a.t_hi;
+        a.mask[idx] = mk;
+        nvalid += mk;
+      }
+      if (cost < (uint32_t)a.t_lo) {
+        const uint64_t k = (uint64_t)cost << 32 | (uint64_t)idx;
+        kg = k < kg ? k : kg;
+      } else if (cost != 0xffu && cost > (uint32_t)a.t_hi) {
+        const uint64_t k = (uint64_t)(255u - cost) << 32 | (uint64_t)idx;
+        kb = k < kb ? k : kb;
+      }
     }
   }
-  const uint64_t none = ~0ull;
-  uint64_t kg = (in && cost < (uint32_t)a.t_lo) ? ((uint64_t)cost << 32 | (uint64_t)idx) : none;
-  uint64_t kb = (in && cost != 0xffu && cost > (uint32_t)a.t_hi)
-                    ? ((uint64_t)(255u - cost) << 32 | (uint64_t)idx) : none;
-  if (__ballot(kg != none || kb != none) == 0ull) return;  // wave-uniform
-  const int seg = in ? u / a.sz : 0x7fffffff;
+  // segmented minimum over lanes of the same cell column (segments of sz lanes)
+  const int seg = a.sz <= kWave ? lane / a.sz : 0;
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
     const uint64_t og = __shfl_down(kg, off, kWave);
     const uint64_t ob = __shfl_down(kb, off, kWave);
-    const int os = __shfl_down(seg, off, kWave);
-    if (lane + off < kWave && os == seg) {
+    const int ol = lane + off;
+    if (ol < kWave && (a.sz <= kWave ? ol / a.sz : 0) == seg) {
       kg = og < kg ? og : kg;
       kb = ob < kb ? ob : kb;
     }
   }
-  const int prev = __shfl_up(seg, 1, kWave);
-  if (in && (lane == 0 || prev != seg)) {
-    const size_t cell = (size_t)(v / a.sz) * a.Wc + seg;
-    if (kg != none) atomicMin((unsigned long long*)&a.cell_g[cell], (unsigned long long)kg);
-    if (kb != none) atomicMin((unsigned long long*)&a.cell_b[cell], (unsigned long long)kb);
+  sg[w][lane] = kg;
+  sb[w][lane] = kb;
+  __syncthreads();  // s_valid initialised, keys visible
+  if (a.mask && nvalid) atomicAdd(&s_valid, nvalid);
+  // thread (w, lane): cell row w of the tile, cell column seg (segment heads only)
+  const bool head = lane == 0 || (a.sz <= kWave && (lane - 1) / a.sz != seg);
+  if (w < a.crows && head && seg < a.cpr) {
+    const int cy = blockIdx.y * a.crows + w, cx = blockIdx.x * a.cpr + seg;
+    if (cy < a.Hc && cx < a.Wc) {
+      uint64_t g = a.ginit, b = a.binit;
+      // waves whose rows belong to cell row w
+      const int w_lo = a.crows == 1 ? 0 : w * a.sz;
+      const int w_hi = a.crows == 1 ? 4 : w * a.sz + a.sz;
+      for (int q = w_lo; q < w_hi; ++q) {
+        g = sg[q][lane] < g ? sg[q][lane] : g;
+        b = sb[q][lane] < b ? sb[q][lane] : b;
+      }
+      a.cell_g[(size_t)cy * a.Wc + cx] = g;
+      a.cell_b[(size_t)cy * a.Wc + cx] = b;
+    }
+  }
+  if (a.mask) {
+    __syncthreads();
+    if (threadIdx.x == 0 && s_valid) atomicAdd(a.n_valid, (unsigned long long)s_valid);
   }
 }
 
@@ -537,15 +568,6 @@ hipError_t launch_interpolate(const sm_support* S, int32_t n_support, const sm_t
   return launch_raster(S, n_support, T, n_tris, W, H, D_it, s);
 }
 
-hipError_t launch_cells_init(uint64_t* cell_g, uint64_t* cell_b, int32_t W, int32_t H, int32_t sz,
-                             const sm_params& p, hipStream_t s) {
-  const int n_cells = ((W + sz - 1) / sz) * ((H + sz - 1) / sz);
-  const uint64_t ginit = (uint64_t)p.t_lo << 32, binit = (uint64_t)(255 - p.t_hi) << 32;
-  hipLaunchKernelGGL(k_cells_init, dim3(blocks_for(n_cells, 256)), dim3(256), 0, s, cell_g, cell_b,
-                     n_cells, ginit, binit);
-  return hipGetLastError();
-}
-
 hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
                                 const float* D_it, int32_t W, int32_t H, const sm_params& p,
                                 int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f,
@@ -565,6 +587,13 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
   a.t_hi = p.t_hi;
   a.sz = sz;
   a.Wc = (W + sz - 1) / sz;
+  a.Hc = (H + sz - 1) / sz;
+  a.cpr = sz <= kWave ? kWave / sz : 1;
+  a.TW = a.cpr * sz;
+  a.crows = sz >= 4 ? 1 : 4 / sz;
+  a.TH = a.crows * sz;
+  a.ginit = (uint64_t)p.t_lo << 32;
+  a.binit = (uint64_t)(255 - p.t_hi) << 32;
   a.C_it = C_it;
   a.D_f = D_f;
   a.C_f = C_f;
@@ -572,7 +601,8 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
   a.cell_b = cell_b;
   a.mask = mask;
   a.n_valid = n_valid;
-  hipLaunchKernelGGL(k_validate, dim3(blocks_for(W, kWave), blocks_for(H, 4)), dim3(256), 0, s, a);
+  dim3 grid(blocks_for(W, a.TW), blocks_for(H, a.TH));
+  hipLaunchKernelGGL(k_validate, grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -581,8 +611,6 @@ hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t
                            int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f, uint64_t* cell_g,
                            uint64_t* cell_b, uint8_t* mask, unsigned long long* n_valid,
                            hipStream_t s) {
-  hipError_t e = launch_cells_init(cell_g, cell_b, W, H, sz, p, s);
-  if (e != hipSuccess) return e;
   return launch_validate_only(cL, cR, omega, D_it, W, H, p, sz, C_it, D_f, C_f, cell_g, cell_b, mask,
                               n_valid, s);
 }

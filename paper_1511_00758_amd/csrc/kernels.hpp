@@ -54,8 +54,6 @@ hipError_t launch_interpolate(const sm_support* S, int32_t n_support, const sm_t
 hipError_t launch_fill_nan(float* D, size_t n, hipStream_t s);
 hipError_t launch_raster(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
                          int32_t W, int32_t H, float* D_it, hipStream_t s);
-hipError_t launch_cells_init(uint64_t* cell_g, uint64_t* cell_b, int32_t W, int32_t H, int32_t sz,
-                             const sm_params& p, hipStream_t s);
 hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
                                 const float* D_it, int32_t W, int32_t H, const sm_params& p,
                                 int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f,
@@ -65,7 +63,7 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
 // Zero `bytes` bytes (a kernel, so the call is safe inside captured graphs).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
-// Cell keys reset, then cost evaluation + refinement (+ final mask when non-null).
+// Cost evaluation + refinement; writes every cell key (+ final mask when non-null).
 hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
                            const float* D_it, int32_t W, int32_t H, const sm_params& p,
                            int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f, uint64_t* cell_g,
