@@ -76,17 +76,12 @@ typedef struct {
  * device time (stage_us) and the launch count (stage_launches); the host stages report
  * wall time. Indices are the sm_stage values. */
 typedef enum {
-  SM_ST_CENSUS = 0,          /* census + Omega_I of both images (and output initialisation) */
-  SM_ST_GRID = 1,            /* support-grid candidate slots                                 */
-  SM_ST_MATCH = 2,           /* epipolar matching of the initial candidates                  */
-  SM_ST_COMPACT = 3,         /* order-preserving compaction of matched / resampled supports   */
-  SM_ST_FILL = 4,            /* NaN fill of D_it                                             */
-  SM_ST_RASTER = 5,          /* plane fit + per-triangle rasterisation                       */
-  SM_ST_CELLS_INIT = 6,      /* occupancy-cell reset                                         */
-  SM_ST_VALIDATE = 7,        /* cost evaluation + refinement                                 */
-  SM_ST_RESAMPLE_CELLS = 8,  /* cells -> confident supports and re-match candidates          */
-  SM_ST_REMATCH = 9,         /* epipolar matching of the resampled candidates                */
-  SM_ST_ZERO = 10,           /* counter reset                                                */
+  SM_ST_CENSUS = 0,          /* census + Omega_I of both images, per-frame initialisation     */
+  SM_ST_MATCH = 1,           /* epipolar matching of the support-grid candidates              */
+  SM_ST_COMPACT = 2,         /* order-preserving compaction of matched / resampled supports   */
+  SM_ST_RASTER = 3,          /* plane fit + per-triangle rasterisation (interpolation)        */
+  SM_ST_VALIDATE = 4,        /* cost evaluation + refinement                                 */
+  SM_ST_REMATCH = 5,         /* resampling: cells -> confident supports + re-matched pixels  */
   SM_ST_HOST_TRI = 12,       /* host triangulation (wall time)                               */
   SM_ST_HOST_COPY = 13,      /* host<->device copies and waits (wall time)                   */
   SM_ST_TOTAL = 14           /* whole sm_solve call (wall time)                              */

@@ -16,8 +16,7 @@ SM_OK, SM_ERR_ARG, SM_ERR_CAPACITY, SM_ERR_HIP, SM_ERR_INTERNAL = 0, -1, -2, -3,
 STATUS_NAMES = {0: "SM_OK", -1: "SM_ERR_ARG", -2: "SM_ERR_CAPACITY", -3: "SM_ERR_HIP",
                 -4: "SM_ERR_INTERNAL"}
 # sm_stage indices of sm_stats.stage_us / stage_launches
-STAGES = {"census": 0, "grid_slots": 1, "match": 2, "compact": 3, "nan_fill": 4, "raster": 5,
-          "cells_init": 6, "validate": 7, "resample_cells": 8, "rematch": 9, "zero": 10,
+STAGES = {"census": 0, "match": 1, "compact": 2, "raster": 3, "validate": 4, "rematch": 5,
           "host_triangulate": 12, "host_copies": 13, "total": 14}
 N_STAGES = 16
 

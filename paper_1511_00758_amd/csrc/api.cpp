@@ -111,19 +111,23 @@ struct Timer {
     *out = t.pool[t.used++];
     return SM_OK;
   }
+  // arms an event pair that the next launch records around its kernel
   sm_status begin(int stage) {
     if (!on) return SM_OK;
-    hipEvent_t e;
-    SM_TRY(event(&e));
-    t.marks.emplace_back(stage, t.used - 1);
-    SM_HIP(hipEventRecord(e, s));
+    hipEvent_t e0, e1;
+    SM_TRY(event(&e0));
+    SM_TRY(event(&e1));
+    t.marks.emplace_back(stage, t.used - 2);
+    set_launch_events(e0, e1);
     return SM_OK;
   }
   sm_status end() {
     if (!on) return SM_OK;
-    hipEvent_t e;
-    SM_TRY(event(&e));
-    SM_HIP(hipEventRecord(e, s));
+    if (launch_events_pending()) {  // nothing was launched: forget the mark
+      set_launch_events(nullptr, nullptr);
+      t.marks.pop_back();
+      t.used -= 2;
+    }
     return SM_OK;
   }
   // after the stream has been synchronised
@@ -157,8 +161,9 @@ Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
   const size_t npx = (size_t)W * H;
   L.n_grid = grid_count(W, H, p.support_step);
   L.cells_max = cells_of(W, H, occ_size(p, p.n_iters));
-  int64_t scap = L.n_grid;
-  for (int it = 1; it < p.n_iters; ++it) scap += 2 * (int64_t)cells_of(W, H, occ_size(p, it));
+  // each slot region is followed by one header slot that receives its count
+  int64_t scap = L.n_grid + 1;
+  for (int it = 1; it < p.n_iters; ++it) scap += 2 * (int64_t)cells_of(W, H, occ_size(p, it)) + 1;
   L.S_cap = (int32_t)std::max<int64_t>(scap, 1);
   L.T_cap = std::max<int32_t>(2 * L.S_cap, 1);
   size_t o = 0;
@@ -218,7 +223,7 @@ sm_status sm_census(const uint8_t* img, int32_t W, int32_t H, int32_t stride, in
   if (grad_thr < 0) return fail(SM_ERR_ARG, "grad_thr must be >= 0");
   CensusJob j{img, stride, census, omega};
   SM_HIP(launch_census(&j, 1, W, H, census_w, census_h, grad_thr, nullptr, nullptr, 0, nullptr,
-                       (hipStream_t)stream));
+                       nullptr, (hipStream_t)stream));
   return SM_OK;
 }
 
@@ -242,7 +247,7 @@ sm_status sm_match_support(const uint64_t* cL, const uint64_t* cR, const uint8_t
   if (cand_uv) SM_HIP(launch_list_slots(cand_uv, n, out, s));
   else SM_HIP(launch_grid_slots(omega, W, H, p->support_step, out, n, s));
   SM_HIP(launch_match(cL, cR, W, H, *p, out, n, s));
-  SM_HIP(launch_compact(out, n, n_out, nullptr, W, s));
+  SM_HIP(launch_compact(out, n, n_out, nullptr, W, nullptr, s));
   return SM_OK;
 }
 
@@ -324,9 +329,8 @@ sm_status sm_resample(const uint64_t* cL, const uint64_t* cR, const float* D_it,
   if (cap < 2 * cells) return fail(SM_ERR_CAPACITY, "cap %d < 2 * %d cells", cap, cells);
   hipStream_t s = (hipStream_t)stream;
   SM_HIP(launch_mark(S, n_S, occ, W, H, s));
-  SM_HIP(launch_resample_cells(cell_g, cell_b, D_it, W, H, sz_occ, *p, out, s));
-  SM_HIP(launch_match(cL, cR, W, H, *p, out + cells, cells, s));
-  SM_HIP(launch_compact(out, 2 * cells, n_out, occ, W, s));
+  SM_HIP(launch_resample(cL, cR, cell_g, cell_b, D_it, W, H, sz_occ, *p, out, s));
+  SM_HIP(launch_compact(out, 2 * cells, n_out, occ, W, nullptr, s));
   return SM_OK;
 }
 
@@ -376,32 +380,38 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   Timer tm(c.timer, s, timing);
   float us_host = 0.f, us_xfer = 0.f;
 
-  // census of both images; D_f = 0, C_f = t_hi, occupancy cleared (Alg. 1 initialisation)
+  // census of both images, fused with the per-frame initialisation: D_f = 0,
+  // C_f = t_hi (Alg. 1), occupancy cleared, D_it = NaN (coverage only grows over the
+  // iterations, S_it being a subset of S_it+1, so one fill per frame suffices), the
+  // support-grid candidate slots and the counters
   CensusJob jobs[2] = {{L, stride, cL, omega}, {R, stride, cR, nullptr}};
+  CensusExtras ex;
+  ex.D_nan = D_it;
+  ex.grid_slots = Sd;
+  ex.step = p->support_step;
+  ex.gw = Lo.n_grid > 0 ? (W - 1 - p->support_step / 2) / p->support_step + 1 : 0;
+  ex.zero = counters;
+  ex.n_zero = 16;
   SM_TRY(tm.begin(SM_ST_CENSUS));
-  SM_HIP(launch_census(jobs, 2, W, H, p->census_w, p->census_h, p->grad_thr, D_f, C_f, p->t_hi, occ, s));
-  SM_TRY(tm.end());
-  SM_TRY(tm.begin(SM_ST_ZERO));
-  SM_HIP(launch_zero(counters, 64, s));
+  SM_HIP(launch_census(jobs, 2, W, H, p->census_w, p->census_h, p->grad_thr, D_f, C_f, p->t_hi, occ, &ex,
+                       s));
   SM_TRY(tm.end());
 
-  // S_1 = SparseStereo(I_l, I_r) over the candidate grid
-  SM_TRY(tm.begin(SM_ST_GRID));
-  SM_HIP(launch_grid_slots(omega, W, H, p->support_step, Sd, Lo.n_grid, s));
-  SM_TRY(tm.end());
+  // S_1 = SparseStereo(I_l, I_r) over the candidate grid; the count lands in the slot
+  // after the candidates so that one copy brings both back
   SM_TRY(tm.begin(SM_ST_MATCH));
   SM_HIP(launch_match(cL, cR, W, H, *p, Sd, Lo.n_grid, s));
   SM_TRY(tm.end());
   SM_TRY(tm.begin(SM_ST_COMPACT));
-  SM_HIP(launch_compact(Sd, Lo.n_grid, &counters[0], occ, W, s));
+  SM_HIP(launch_compact(Sd, Lo.n_grid, &counters[0], occ, W, (int32_t*)(Sd + Lo.n_grid), s));
   SM_TRY(tm.end());
 
   auto t0 = clk::now();
-  SM_HIP(hipMemcpyAsync(h_count, &counters[0], sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  SM_HIP(hipMemcpyAsync(h_S, Sd, (size_t)std::max(Lo.n_grid, 1) * sizeof(sm_support), hipMemcpyDeviceToHost, s));
+  SM_HIP(hipMemcpyAsync(h_S, Sd, (size_t)(Lo.n_grid + 1) * sizeof(sm_support), hipMemcpyDeviceToHost, s));
   SM_HIP(hipStreamSynchronize(s));
   us_xfer += us_since(t0);
-  int32_t n_S = *h_count;
+  int32_t n_S;
+  std::memcpy(&n_S, &h_S[Lo.n_grid], sizeof(int32_t));
   if (n_S < 0 || n_S > Lo.n_grid) return fail(SM_ERR_INTERNAL, "support count %d out of range", n_S);
 
   int32_t n_T = 0;
@@ -448,9 +458,6 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
       st->n_support[it - 1] = n_S;
       st->n_tris[it - 1] = n_T;
     }
-    SM_TRY(tm.begin(SM_ST_FILL));
-    SM_HIP(launch_fill_nan(D_it, (size_t)W * H, s));
-    SM_TRY(tm.end());
     if (n_T > 0) {
       SM_TRY(tm.begin(SM_ST_RASTER));
       SM_HIP(launch_raster(Sd, n_S, Td, n_T, W, H, D_it, s));
@@ -463,23 +470,20 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     if (last) break;
     // S_it+1 = SupportResampling(C_g, C_b, S_it), appended in place after S_it
     const int32_t cells = cells_of(W, H, sz);
-    if (n_S + 2 * cells > Lo.S_cap) return fail(SM_ERR_INTERNAL, "support capacity exceeded");
+    if (n_S + 2 * cells + 1 > Lo.S_cap) return fail(SM_ERR_INTERNAL, "support capacity exceeded");
     sm_support* region = Sd + n_S;
-    SM_TRY(tm.begin(SM_ST_RESAMPLE_CELLS));
-    SM_HIP(launch_resample_cells(cell_g, cell_b, D_it, W, H, sz, *p, region, s));
-    SM_TRY(tm.end());
     SM_TRY(tm.begin(SM_ST_REMATCH));
-    SM_HIP(launch_match(cL, cR, W, H, *p, region + cells, cells, s));
+    SM_HIP(launch_resample(cL, cR, cell_g, cell_b, D_it, W, H, sz, *p, region, s));
     SM_TRY(tm.end());
     SM_TRY(tm.begin(SM_ST_COMPACT));
-    SM_HIP(launch_compact(region, 2 * cells, &counters[1], occ, W, s));
+    SM_HIP(launch_compact(region, 2 * cells, &counters[1], occ, W, (int32_t*)(region + 2 * cells), s));
     SM_TRY(tm.end());
     t0 = clk::now();
-    SM_HIP(hipMemcpyAsync(h_count, &counters[1], sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    SM_HIP(hipMemcpyAsync(h_S, region, (size_t)2 * cells * sizeof(sm_support), hipMemcpyDeviceToHost, s));
+    SM_HIP(hipMemcpyAsync(h_S, region, (size_t)(2 * cells + 1) * sizeof(sm_support), hipMemcpyDeviceToHost, s));
     SM_HIP(hipStreamSynchronize(s));
     us_xfer += us_since(t0);
-    const int32_t n_new = *h_count;
+    int32_t n_new;
+    std::memcpy(&n_new, &h_S[2 * cells], sizeof(int32_t));
     if (n_new < 0 || n_new > 2 * cells) return fail(SM_ERR_INTERNAL, "resample count %d out of range", n_new);
     SM_TRY(triangulate_and_upload(n_S, n_S + n_new));
     n_S += n_new;

@@ -29,9 +29,10 @@ inline uint32_t hilbert(uint32_t x, uint32_t y) {
 }  // namespace
 
 void Delaunay::reset() {
-  px_.clear();
-  py_.clear();
+  pt_.clear();
   ext_.clear();
+  vstamp_.clear();
+  vfan_.clear();
   tri_.clear();
   alive_.clear();
   free_.clear();
@@ -44,13 +45,13 @@ void Delaunay::reset() {
 }
 
 int64_t Delaunay::orient(int32_t a, int32_t b, int32_t c) const {
-  const int64_t ax = px_[a], ay = py_[a];
-  return (int64_t(px_[b]) - ax) * (int64_t(py_[c]) - ay) - (int64_t(py_[b]) - ay) * (int64_t(px_[c]) - ax);
+  const Pt A = pt_[a], B = pt_[b], C = pt_[c];
+  return int64_t(B.x - A.x) * int64_t(C.y - A.y) - int64_t(B.y - A.y) * int64_t(C.x - A.x);
 }
 
 int64_t Delaunay::orient_pt(int32_t a, int32_t b, int64_t x, int64_t y) const {
-  const int64_t ax = px_[a], ay = py_[a];
-  return (int64_t(px_[b]) - ax) * (y - ay) - (int64_t(py_[b]) - ay) * (x - ax);
+  const Pt A = pt_[a], B = pt_[b];
+  return int64_t(B.x - A.x) * (y - A.y) - int64_t(B.y - A.y) * (x - A.x);
 }
 
 // Sign of det[[u, v, u^2+v^2, 1]] over rows a, b, c, d (> 0: d strictly inside the
@@ -59,10 +60,10 @@ int64_t Delaunay::orient_pt(int32_t a, int32_t b, int64_t x, int64_t y) const {
 // d/dz_a = +orient(b,c,d), d/dz_b = -orient(a,c,d), d/dz_c = +orient(a,b,d),
 // d/dz_d = -orient(a,b,c); priority = smaller (v, u).
 int Delaunay::incircle_sos(int32_t a, int32_t b, int32_t c, int32_t d) const {
-  const int64_t dx = px_[d], dy = py_[d];
-  const int64_t adx = px_[a] - dx, ady = py_[a] - dy;
-  const int64_t bdx = px_[b] - dx, bdy = py_[b] - dy;
-  const int64_t cdx = px_[c] - dx, cdy = py_[c] - dy;
+  const Pt D = pt_[d], A = pt_[a], B = pt_[b], C = pt_[c];
+  const int64_t adx = A.x - D.x, ady = A.y - D.y;
+  const int64_t bdx = B.x - D.x, bdy = B.y - D.y;
+  const int64_t cdx = C.x - D.x, cdy = C.y - D.y;
   const int64_t al = adx * adx + ady * ady;
   const int64_t bl = bdx * bdx + bdy * bdy;
   const int64_t cl = cdx * cdx + cdy * cdy;
@@ -71,7 +72,7 @@ int Delaunay::incircle_sos(int32_t a, int32_t b, int32_t c, int32_t d) const {
   int32_t ids[4] = {a, b, c, d};
   // order by priority (smaller (v, u) first); insertion sort of 4
   int ord[4] = {0, 1, 2, 3};
-  auto key = [&](int k) { return (int64_t(py_[ids[k]]) << 16) | int64_t(px_[ids[k]]); };
+  auto key = [&](int k) { return (int64_t(pt_[ids[k]].y) << 16) | int64_t(pt_[ids[k]].x); };
   for (int i = 1; i < 4; ++i)
     for (int j = i; j > 0 && key(ord[j]) < key(ord[j - 1]); --j) std::swap(ord[j], ord[j - 1]);
   for (int k = 0; k < 4; ++k) {
@@ -95,7 +96,7 @@ bool Delaunay::conflict(int32_t t, int32_t p) const {
   const int64_t o = orient(x, y, p);
   if (o < 0) return true;
   if (o > 0) return false;
-  const int64_t ux = px_[x], uy = py_[x], wx = px_[y], wy = py_[y], qx = px_[p], qy = py_[p];
+  const int64_t ux = pt_[x].x, uy = pt_[x].y, wx = pt_[y].x, wy = pt_[y].y, qx = pt_[p].x, qy = pt_[p].y;
   const int64_t d1 = (qx - ux) * (wx - ux) + (qy - uy) * (wy - uy);
   const int64_t d2 = (qx - wx) * (ux - wx) + (qy - wy) * (uy - wy);
   return d1 > 0 && d2 > 0;
@@ -152,26 +153,19 @@ int32_t Delaunay::locate(int32_t p, bool* dup) {
     }
   }
   if (tri_[t].v[2] == kGhost) t = tri_[t].nb[2];
-  const int64_t x = px_[p], y = py_[p];
+  const int64_t x = pt_[p].x, y = pt_[p].y;
   const size_t limit = 4 * tri_.size() + 64;
+  // visibility walk: it cannot cycle in a (perturbed) Delaunay triangulation
   for (size_t step = 0; step < limit; ++step) {
     const Tri& T = tri_[t];
     if (T.v[2] == kGhost) return t;  // entered across a hull edge with p strictly outside
-    rng_ ^= rng_ << 13;
-    rng_ ^= rng_ >> 17;
-    rng_ ^= rng_ << 5;
-    const int r = (int)(rng_ % 3u);
     int next = -1;
-    for (int k = 0; k < 3; ++k) {
-      const int i = (r + k) % 3;
-      if (orient_pt(T.v[(i + 1) % 3], T.v[(i + 2) % 3], x, y) < 0) {
-        next = T.nb[i];
-        break;
-      }
-    }
+    if (orient_pt(T.v[1], T.v[2], x, y) < 0) next = T.nb[0];
+    else if (orient_pt(T.v[2], T.v[0], x, y) < 0) next = T.nb[1];
+    else if (orient_pt(T.v[0], T.v[1], x, y) < 0) next = T.nb[2];
     if (next < 0) {  // p inside or on the boundary of T
       for (int k = 0; k < 3; ++k)
-        if (px_[T.v[k]] == x && py_[T.v[k]] == y) *dup = true;
+        if (pt_[T.v[k]].x == x && pt_[T.v[k]].y == y) *dup = true;
       return t;
     }
     t = next;
@@ -182,7 +176,7 @@ int32_t Delaunay::locate(int32_t p, bool* dup) {
     const Tri& T = tri_[s];
     if (T.v[2] != kGhost)
       for (int k = 0; k < 3; ++k)
-        if (px_[T.v[k]] == x && py_[T.v[k]] == y) {
+        if (pt_[T.v[k]].x == x && pt_[T.v[k]].y == y) {
           *dup = true;
           return s;
         }
@@ -198,6 +192,7 @@ bool Delaunay::insert_point(int32_t p) {
   // flood the hole
   if (++gen_ == 0x7fffffffu) {
     std::fill(stamp_.begin(), stamp_.end(), 0u);
+    std::fill(vstamp_.begin(), vstamp_.end(), 0u);
     gen_ = 1;
   }
   const uint32_t in_hole = 2 * gen_, outside = 2 * gen_ + 1;
@@ -225,7 +220,8 @@ bool Delaunay::insert_point(int32_t p) {
       }
     }
   }
-  // fan around p: one triangle per boundary edge a->b
+  // fan around p: one triangle per boundary edge a->b; the triangle of edge a->b is
+  // remembered at its start vertex a, so its two fan neighbours are found in O(1)
   newt_.clear();
   for (const Edge& e : bnd_) {
     const int32_t t = alloc_tri();
@@ -243,22 +239,25 @@ bool Delaunay::insert_point(int32_t p) {
     Tri& O = tri_[e.out];
     for (int i = 0; i < 3; ++i)
       if (O.v[(i + 1) % 3] == e.b && O.v[(i + 2) % 3] == e.a) O.nb[i] = t;
-  }
-  // link the fan: triangle of edge a->b meets the triangle of edge b->c across b-p
-  const size_t m = bnd_.size();
-  for (size_t j = 0; j < m; ++j) {
-    const int32_t b = bnd_[j].b;
-    for (size_t k = 0; k < m; ++k) {
-      if (bnd_[k].a != b) continue;
-      const int32_t t1 = newt_[j], t2 = newt_[k];
-      Tri& A = tri_[t1];
-      Tri& B = tri_[t2];
-      for (int i = 0; i < 3; ++i)
-        if (A.v[(i + 1) % 3] == b && A.v[(i + 2) % 3] == p) A.nb[i] = t2;
-      for (int i = 0; i < 3; ++i)
-        if (B.v[(i + 1) % 3] == p && B.v[(i + 2) % 3] == b) B.nb[i] = t1;
-      break;
+    if (e.a == kGhost) {
+      ghost_fan_ = t;
+    } else {
+      vstamp_[e.a] = gen_;
+      vfan_[e.a] = t;
     }
+  }
+  // link the fan: the triangle of edge a->b meets the triangle of edge b->c across b-p
+  for (size_t j = 0; j < bnd_.size(); ++j) {
+    const int32_t b = bnd_[j].b;
+    const int32_t t1 = newt_[j];
+    const int32_t t2 = b == kGhost ? ghost_fan_ : (vstamp_[b] == gen_ ? vfan_[b] : -1);
+    if (t2 < 0) continue;  // cannot happen: the hole boundary is a closed cycle
+    Tri& A = tri_[t1];
+    Tri& B = tri_[t2];
+    for (int i = 0; i < 3; ++i)
+      if (A.v[(i + 1) % 3] == b && A.v[(i + 2) % 3] == p) A.nb[i] = t2;
+    for (int i = 0; i < 3; ++i)
+      if (B.v[(i + 1) % 3] == p && B.v[(i + 2) % 3] == b) B.nb[i] = t1;
   }
   int32_t solid_removed = 0, solid_added = 0;
   for (int32_t t : hole_) {
@@ -276,24 +275,25 @@ bool Delaunay::insert_point(int32_t p) {
 
 bool Delaunay::insert(int32_t u, int32_t v, int32_t ext) {
   if (u < 0 || v < 0 || u > 8191 || v > 8191) return false;
-  const int32_t p = (int32_t)px_.size();
-  px_.push_back(u);
-  py_.push_back(v);
+  const int32_t p = (int32_t)pt_.size();
+  pt_.push_back(Pt{u, v});
   ext_.push_back(ext);
+  vstamp_.push_back(0);
+  vfan_.push_back(-1);
+  auto drop_last = [&]() {
+    pt_.pop_back();
+    ext_.pop_back();
+    vstamp_.pop_back();
+    vfan_.pop_back();
+  };
   if (started_) {
-    if (!insert_point(p)) {  // duplicate: drop the new copy, the first occurrence stays
-      px_.pop_back();
-      py_.pop_back();
-      ext_.pop_back();
-    }
+    if (!insert_point(p)) drop_last();  // duplicate: the first occurrence stays
     return true;
   }
   // before the first triangle: keep the points while they are collinear
   for (int32_t q : pending_)
-    if (px_[q] == u && py_[q] == v) {
-      px_.pop_back();
-      py_.pop_back();
-      ext_.pop_back();
+    if (pt_[q].x == u && pt_[q].y == v) {
+      drop_last();
       return true;
     }
   if (pending_.size() >= 2 && orient(pending_[0], pending_[1], p) != 0) {
@@ -341,8 +341,8 @@ void Delaunay::emit(std::vector<sm_tri>& out, bool sorted) const {
     const Tri& T = tri_[t];
     int k = 0;
     for (int i = 1; i < 3; ++i) {
-      const int32_t a = T.v[i], b = T.v[k];
-      if (py_[a] < py_[b] || (py_[a] == py_[b] && px_[a] < px_[b])) k = i;
+      const Pt a = pt_[T.v[i]], b = pt_[T.v[k]];
+      if (a.y < b.y || (a.y == b.y && a.x < b.x)) k = i;
     }
     out.push_back(sm_tri{ext_[T.v[k]], ext_[T.v[(k + 1) % 3]], ext_[T.v[(k + 2) % 3]]});
   }

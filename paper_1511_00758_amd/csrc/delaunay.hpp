@@ -38,7 +38,7 @@ class Delaunay {
   // Appends the solid triangles as external indices, counter-clockwise, first
   // vertex = smallest (v, u). Sorted by (i0, i1, i2) when `sorted`.
   void emit(std::vector<sm_tri>& out, bool sorted) const;
-  int32_t n_points() const { return (int32_t)px_.size(); }
+  int32_t n_points() const { return (int32_t)pt_.size(); }
   int32_t n_solid() const { return n_solid_; }
 
  private:
@@ -46,7 +46,14 @@ class Delaunay {
     int32_t v[3];   // vertices (local point ids); v[2] == kGhost for ghost triangles
     int32_t nb[3];  // nb[i]: triangle across the edge opposite v[i]
   };
-  std::vector<int32_t> px_, py_, ext_;
+  struct Pt {
+    int32_t x, y;
+  };
+  std::vector<Pt> pt_;
+  std::vector<int32_t> ext_;
+  std::vector<uint32_t> vstamp_;   // per point: generation of the fan triangle starting there
+  std::vector<int32_t> vfan_;      // per point: that fan triangle
+  int32_t ghost_fan_ = -1;         // fan triangle starting at the ghost vertex
   std::vector<Tri> tri_;
   std::vector<uint8_t> alive_;
   std::vector<int32_t> free_;
@@ -60,7 +67,6 @@ class Delaunay {
   uint32_t gen_ = 0;
   int32_t hint_ = -1;
   int32_t n_solid_ = 0;
-  uint32_t rng_ = 0x9e3779b9u;
   bool started_ = false;
 
   int32_t alloc_tri();

@@ -5,9 +5,33 @@
 // every output is reproducible bit for bit.
 #include "kernels.hpp"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 namespace sm {
+
+// Event pair armed by the host layer for the next launch of this thread: the kernel
+// is then dispatched with hipExtLaunchKernelGGL, which timestamps the kernel itself.
+namespace {
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+}  // namespace
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop) {
+  g_ev_start = start;
+  g_ev_stop = stop;
+}
+bool launch_events_pending() { return g_ev_start != nullptr; }
+
+#define SM_LAUNCH(kernel, grid, block, shmem, stream, ...)                                  \
+  do {                                                                                     \
+    if (g_ev_start) {                                                                      \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, g_ev_start, g_ev_stop, 0u,  \
+                            __VA_ARGS__);                                                  \
+      g_ev_start = g_ev_stop = nullptr;                                                    \
+    } else {                                                                               \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                  \
+    }                                                                                      \
+  } while (0)
 
 namespace {
 
@@ -38,6 +62,7 @@ struct CensusArgs {
   float* D_f;
   uint8_t* C_f;
   uint8_t* occ;
+  CensusExtras x;
 };
 
 template <int RX, int RY>
@@ -54,12 +79,11 @@ __global__ __launch_bounds__(256) void k_census(CensusArgs a) {
   }
   __syncthreads();
   const int u = blockIdx.x * kTW + threadIdx.x;
-  if (u >= W) return;
 #pragma unroll
   for (int r = 0; r < kTH / 4; ++r) {
     const int ly = threadIdx.y + 4 * r;
     const int v = blockIdx.y * kTH + ly;
-    if (v >= H) break;
+    if (v >= H || u >= W) break;
     const size_t idx = (size_t)v * W + u;
     const bool valid = u >= RX && u < W - RX && v >= RY && v < H - RY;
     const uint8_t* c = &tile[(ly + RY) * PW + threadIdx.x + RX];
@@ -93,14 +117,32 @@ __global__ __launch_bounds__(256) void k_census(CensusArgs a) {
       if (a.D_f) a.D_f[idx] = 0.0f;
       if (a.C_f) a.C_f[idx] = (uint8_t)a.t_hi;
       if (a.occ) a.occ[idx] = 0;
+      if (a.x.D_nan) a.x.D_nan[idx] = __builtin_nanf("");
+      if (a.x.grid_slots) {  // support-grid candidate at this pixel
+        const int h = a.x.step / 2;
+        const int gu = u - h, gv = v - h;
+        if (gu >= 0 && gv >= 0 && gu % a.x.step == 0 && gv % a.x.step == 0) {
+          const bool cand = valid && jb.omega &&
+                            (abs((int)c[1] - (int)c[-1]) + abs((int)c[PW] - (int)c[-PW])) >= a.grad_thr;
+          sm_support sp;
+          sp.u = (int16_t)u;
+          sp.v = (int16_t)v;
+          sp.d = cand ? kPending : kRejected;
+          a.x.grid_slots[(gv / a.x.step) * a.x.gw + gu / a.x.step] = sp;
+        }
+      }
     }
+  }
+  if (a.x.zero && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+    const int t = threadIdx.y * kTW + threadIdx.x;
+    if (t < a.x.n_zero) a.x.zero[t] = 0;
   }
 }
 
 template <int RX, int RY>
 hipError_t census_launch(const CensusArgs& a, int n_jobs, hipStream_t s) {
   dim3 grid((a.W + kTW - 1) / kTW, (a.H + kTH - 1) / kTH, n_jobs);
-  hipLaunchKernelGGL((k_census<RX, RY>), grid, dim3(kTW, 4, 1), 0, s, a);
+  SM_LAUNCH((k_census<RX, RY>), grid, dim3(kTW, 4, 1), 0, s, a);
   return hipGetLastError();
 }
 
@@ -141,17 +183,10 @@ struct MatchArgs {
   int32_t n;
 };
 
-__global__ __launch_bounds__(256) void k_match(MatchArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (slot >= a.n) return;
-  const sm_support s = a.slots[slot];
-  if (s.d != kPending) return;
-  const int u = s.u, v = s.v, W = a.W;
-  if (u < a.rx || u >= W - a.rx || v < a.ry || v >= a.H - a.ry) {
-    if (lane == 0) a.slots[slot].d = kRejected;
-    return;
-  }
+// Matches left pixel (u, v) (inside the census-valid region); every lane of the wave
+// must call it with the same (u, v). Returns d* or -1 when rejected.
+__device__ int match_one(const MatchArgs& a, int u, int v, int lane) {
+  const int W = a.W;
   const uint64_t* rowL = a.cL + (size_t)v * W;
   const uint64_t* rowR = a.cR + (size_t)v * W;
   const uint64_t wl = rowL[u];
@@ -167,11 +202,11 @@ __global__ __launch_bounds__(256) void k_match(MatchArgs a) {
     best = key < best ? key : best;
   }
   best = wave_min_u32(best);
-  bool accept = best != 0xffffffffu;
+  if (best == 0xffffffffu) return -1;  // no admissible disparity
   const int dstar = (int)(best & 0xffu);
   const uint32_t cstar = best >> 8;
-  accept = accept && cstar < (uint32_t)a.t_hi;
-  if (accept && a.uniq > 0) {
+  if (cstar >= (uint32_t)a.t_hi) return -1;
+  if (a.uniq > 0) {
     bool bad = false;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -180,32 +215,79 @@ __global__ __launch_bounds__(256) void k_match(MatchArgs a) {
       const int dd = d - dstar;
       bad |= ok && (dd >= 2 || dd <= -2) && cost[c] < cstar + (uint32_t)a.uniq;
     }
-    accept = __ballot(bad) == 0ull;
+    if (__ballot(bad) != 0ull) return -1;
   }
-  if (accept) {
-    const int ur = u - dstar;
-    const uint64_t wr = rowR[ur];
-    uint32_t best2 = 0xffffffffu;
+  // left-right check from the matched right pixel
+  const int ur = u - dstar;
+  const uint64_t wr = rowR[ur];
+  uint32_t best2 = 0xffffffffu;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int d = a.d_min + lane + kWave * c;
-      const bool ok = d <= a.d_max && ur + d <= W - 1 - a.rx;
-      const uint32_t key = ok ? ((uint32_t)__popcll(wr ^ rowL[ur + d]) << 8 | (uint32_t)d) : 0xffffffffu;
-      best2 = key < best2 ? key : best2;
-    }
-    best2 = wave_min_u32(best2);
-    const int dlr = (int)(best2 & 0xffu);
-    const int diff = dlr - dstar;
-    accept = (diff <= a.lr_tol && -diff <= a.lr_tol);
+  for (int c = 0; c < 4; ++c) {
+    const int d = a.d_min + lane + kWave * c;
+    const bool ok = d <= a.d_max && ur + d <= W - 1 - a.rx;
+    const uint32_t key = ok ? ((uint32_t)__popcll(wr ^ rowL[ur + d]) << 8 | (uint32_t)d) : 0xffffffffu;
+    best2 = key < best2 ? key : best2;
   }
-  if (lane == 0) a.slots[slot].d = accept ? (float)dstar : kRejected;
+  best2 = wave_min_u32(best2);
+  const int diff = (int)(best2 & 0xffu) - dstar;
+  return (diff <= a.lr_tol && -diff <= a.lr_tol) ? dstar : -1;
+}
+
+__device__ __forceinline__ bool match_inside(const MatchArgs& a, int u, int v) {
+  return u >= a.rx && u < a.W - a.rx && v >= a.ry && v < a.H - a.ry;
+}
+
+__global__ __launch_bounds__(256) void k_match(MatchArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (slot >= a.n) return;
+  const sm_support s = a.slots[slot];
+  if (s.d != kPending) return;
+  const int d = match_inside(a, s.u, s.v) ? match_one(a, s.u, s.v, lane) : -1;
+  if (lane == 0) a.slots[slot].d = d >= 0 ? (float)d : kRejected;
+}
+
+// Resampling (Alg. 4) fused with the re-match: one wave per cell. Slot c receives the
+// confident support of cell c, slot n_cells + c its re-matched invalid pixel.
+__global__ __launch_bounds__(256) void k_rematch_cells(MatchArgs a, const uint64_t* cell_g,
+                                                       const uint64_t* cell_b, const float* D_it,
+                                                       int n_cells, uint64_t ginit, uint64_t binit) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n_cells) return;
+  const uint64_t g = cell_g[c], b = cell_b[c];
+  if (lane == 0) {
+    sm_support sg;
+    if (g != ginit) {
+      const uint32_t idx = (uint32_t)g;
+      sg.u = (int16_t)(idx % (uint32_t)a.W);
+      sg.v = (int16_t)(idx / (uint32_t)a.W);
+      sg.d = D_it[idx];
+    } else {
+      sg.u = sg.v = 0;
+      sg.d = kRejected;
+    }
+    a.slots[c] = sg;
+  }
+  sm_support sb;
+  sb.u = sb.v = 0;
+  sb.d = kRejected;
+  if (b != binit) {
+    const uint32_t idx = (uint32_t)b;
+    const int u = (int)(idx % (uint32_t)a.W), v = (int)(idx / (uint32_t)a.W);
+    sb.u = (int16_t)u;
+    sb.v = (int16_t)v;
+    const int d = match_inside(a, u, v) ? match_one(a, u, v, lane) : -1;
+    if (d >= 0) sb.d = (float)d;
+  }
+  if (lane == 0) a.slots[n_cells + c] = sb;
 }
 
 // ------------------------------------------------------------------------------------
 // Order-preserving in-place compaction (one 1024-thread workgroup).
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_compact(sm_support* slots, int n, int* n_out, uint8_t* occ,
-                                                  int W) {
+                                                  int W, int* header) {
   __shared__ int wsum[16];
   __shared__ int wofs[16];
   __shared__ int total;
@@ -240,7 +322,10 @@ __global__ __launch_bounds__(1024) void k_compact(sm_support* slots, int n, int*
     base += total;
     __syncthreads();
   }
-  if (threadIdx.x == 0) *n_out = base;
+  if (threadIdx.x == 0) {
+    *n_out = base;
+    if (header) *header = base;
+  }
 }
 
 __global__ void k_fill_u8(uint8_t* p, size_t n, uint8_t val) {
@@ -311,15 +396,17 @@ __global__ __launch_bounds__(256) void k_raster(const sm_support* S, int n_suppo
 }
 
 // ------------------------------------------------------------------------------------
-// Cost evaluation + refinement. Each 256-thread workgroup owns whole occupancy cells: a
-// tile of cpr cells side by side (cpr = max(1, 64 / sz), TW = cpr * sz columns) and one
-// cell row (TH = sz rows; for sz < 4, TH = sz * (4 / sz) rows = several cell rows, one
-// wave per row). Lanes walk the tile's columns, waves its rows; every thread's pixels lie
-// in one cell, so each thread keeps one running minimum per cell array, followed by a
-// segmented shuffle minimum across lanes and a minimum across the waves of the same cell
-// row through LDS. Cell keys are then written with plain stores (no atomics, no reset
-// pass): the packed (cost, raster index) order makes the result the first-in-raster-
-// order winner of the sequential definition.
+// Cost evaluation + refinement. Each 1024-thread workgroup (16 waves) owns whole
+// occupancy cells: a tile of cpr cells side by side (cpr = max(1, 64 / sz),
+// TW = cpr * sz columns) and crows cell rows (crows = max(1, 16 / sz), TH = crows * sz
+// rows). Lanes walk the tile's columns, waves its rows; every thread's pixels lie in
+// one cell, so each thread keeps one running minimum per cell array, followed by a
+// segmented shuffle minimum across lanes and a minimum across the waves of the same
+// cell row through LDS. Cell keys are then written with plain stores (no atomics, no
+// reset pass): the packed (cost, raster index) order makes the result the
+// first-in-raster-order winner of the sequential definition. The loads that do not
+// depend on the pixel's disparity are issued together, so a pixel costs two dependent
+// memory round trips.
 // ------------------------------------------------------------------------------------
 struct ValidateArgs {
   const uint64_t* cL;
@@ -338,9 +425,11 @@ struct ValidateArgs {
   unsigned long long* n_valid;
 };
 
-__global__ __launch_bounds__(256) void k_validate(ValidateArgs a) {
-  __shared__ uint64_t sg[4][kWave];
-  __shared__ uint64_t sb[4][kWave];
+constexpr int kValWaves = 16;
+
+__global__ __launch_bounds__(1024) void k_validate(ValidateArgs a) {
+  __shared__ uint64_t sg[kValWaves][kWave];
+  __shared__ uint64_t sb[kValWaves][kWave];
   __shared__ unsigned int s_valid;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x >> 6;
@@ -349,30 +438,29 @@ __global__ __launch_bounds__(256) void k_validate(ValidateArgs a) {
   const uint64_t none = ~0ull;
   uint64_t kg = none, kb = none;
   unsigned int nvalid = 0;
-  for (int r = w; r < a.TH; r += 4) {
+  for (int r = w; r < a.TH; r += kValWaves) {
     const int v = y0 + r;
     if (v >= a.H) break;
     for (int c = lane; c < a.TW; c += kWave) {
       const int u = x0 + c;
       if (u >= a.W) break;
       const size_t idx = (size_t)v * a.W + u;
-      uint32_t cost = 0xffu;
-      float D = 0.0f;
+      // independent loads first
       const bool om = a.omega[idx] != 0;
-      if (om) {
-        D = a.D_it[idx];
-        if (isfinite(D)) {
-          const float f = floorf(__fadd_rn(D, 0.5f));
-          if (f >= (float)a.d_min && f <= (float)a.d_max) {
-            const int d = (int)f;
-            if (u - d >= a.rx) cost = (uint32_t)__popcll(a.cL[idx] ^ a.cR[idx - d]);
-          }
+      const float Dv = a.D_it[idx];
+      const uint64_t wl = a.cL[idx];
+      uint32_t cf = a.C_f[idx];
+      uint32_t cost = 0xffu;
+      if (om && isfinite(Dv)) {
+        const float f = floorf(__fadd_rn(Dv, 0.5f));
+        if (f >= (float)a.d_min && f <= (float)a.d_max) {
+          const int d = (int)f;
+          if (u - d >= a.rx) cost = (uint32_t)__popcll(wl ^ a.cR[idx - d]);
         }
       }
       if (a.C_it) a.C_it[idx] = (uint8_t)cost;
-      uint32_t cf = a.C_f[idx];
       if (cost < cf) {  // never true for 0xff: C_f <= t_hi <= 64
-        a.D_f[idx] = D;
+        a.D_f[idx] = Dv;
         a.C_f[idx] = (uint8_t)cost;
         cf = cost;
       }
@@ -412,9 +500,10 @@ __global__ __launch_bounds__(256) void k_validate(ValidateArgs a) {
     const int cy = blockIdx.y * a.crows + w, cx = blockIdx.x * a.cpr + seg;
     if (cy < a.Hc && cx < a.Wc) {
       uint64_t g = a.ginit, b = a.binit;
-      // waves whose rows belong to cell row w
+      // the waves whose rows belong to cell row w: rows w*sz .. w*sz+sz-1 are handled by
+      // waves (row mod 16); with crows > 1 every wave holds rows of one cell row only
       const int w_lo = a.crows == 1 ? 0 : w * a.sz;
-      const int w_hi = a.crows == 1 ? 4 : w * a.sz + a.sz;
+      const int w_hi = a.crows == 1 ? kValWaves : w * a.sz + a.sz;
       for (int q = w_lo; q < w_hi; ++q) {
         g = sg[q][lane] < g ? sg[q][lane] : g;
         b = sb[q][lane] < b ? sb[q][lane] : b;
@@ -429,52 +518,41 @@ __global__ __launch_bounds__(256) void k_validate(ValidateArgs a) {
   }
 }
 
-// ------------------------------------------------------------------------------------
-// Resampling: cells -> confident supports and X candidates.
-// ------------------------------------------------------------------------------------
-__global__ void k_resample_cells(const uint64_t* cell_g, const uint64_t* cell_b, const float* D_it,
-                                 int W, int n_cells, uint64_t ginit, uint64_t binit, sm_support* slots) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_cells) return;
-  const uint64_t g = cell_g[c], b = cell_b[c];
-  sm_support sg, sb;
-  if (g != ginit) {
-    const uint32_t idx = (uint32_t)g;
-    sg.u = (int16_t)(idx % (uint32_t)W);
-    sg.v = (int16_t)(idx / (uint32_t)W);
-    sg.d = D_it[idx];
-  } else {
-    sg.u = sg.v = 0;
-    sg.d = kRejected;
-  }
-  if (b != binit) {
-    const uint32_t idx = (uint32_t)b;
-    sb.u = (int16_t)(idx % (uint32_t)W);
-    sb.v = (int16_t)(idx / (uint32_t)W);
-    sb.d = kPending;
-  } else {
-    sb.u = sb.v = 0;
-    sb.d = kRejected;
-  }
-  slots[c] = sg;
-  slots[n_cells + c] = sb;
-}
-
 inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
 
+static MatchArgs match_args(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
+                            const sm_params& p, sm_support* slots, int32_t n) {
+  MatchArgs a;
+  a.cL = cL;
+  a.cR = cR;
+  a.W = W;
+  a.H = H;
+  a.rx = (p.census_w - 1) / 2;
+  a.ry = (p.census_h - 1) / 2;
+  a.d_min = p.d_min;
+  a.d_max = p.d_max;
+  a.t_hi = p.t_hi;
+  a.uniq = p.uniqueness;
+  a.lr_tol = p.lr_tol;
+  a.slots = slots;
+  a.n = n;
+  return a;
+}
+
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
   if (bytes == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(bytes, 256)), dim3(256), 0, s, (uint8_t*)p, bytes,
+  SM_LAUNCH(k_fill_u8, dim3(blocks_for(bytes, 256)), dim3(256), 0, s, (uint8_t*)p, bytes,
                      (uint8_t)0);
   return hipGetLastError();
 }
 
 hipError_t launch_census(const CensusJob* jobs, int n_jobs, int32_t W, int32_t H, int32_t cw,
                          int32_t ch, int32_t grad_thr, float* D_f, uint8_t* C_f, int32_t t_hi,
-                         uint8_t* occ, hipStream_t s) {
+                         uint8_t* occ, const CensusExtras* extras, hipStream_t s) {
   CensusArgs a{};
+  if (extras) a.x = *extras;
   for (int i = 0; i < n_jobs; ++i) a.job[i] = jobs[i];
   a.W = W;
   a.H = H;
@@ -499,64 +577,51 @@ hipError_t launch_grid_slots(const uint8_t* omega, int32_t W, int32_t H, int32_t
   if (n <= 0) return hipSuccess;
   const int h = step / 2;
   const int gw = (W - 1 - h) / step + 1;
-  hipLaunchKernelGGL(k_grid_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, omega, W, step, gw,
+  SM_LAUNCH(k_grid_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, omega, W, step, gw,
                      slots, n);
   return hipGetLastError();
 }
 
 hipError_t launch_list_slots(const int16_t* uv, int32_t n, sm_support* slots, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_list_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, uv, n, slots);
+  SM_LAUNCH(k_list_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, uv, n, slots);
   return hipGetLastError();
 }
 
 hipError_t launch_match(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
                         const sm_params& p, sm_support* slots, int32_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  MatchArgs a;
-  a.cL = cL;
-  a.cR = cR;
-  a.W = W;
-  a.H = H;
-  a.rx = (p.census_w - 1) / 2;
-  a.ry = (p.census_h - 1) / 2;
-  a.d_min = p.d_min;
-  a.d_max = p.d_max;
-  a.t_hi = p.t_hi;
-  a.uniq = p.uniqueness;
-  a.lr_tol = p.lr_tol;
-  a.slots = slots;
-  a.n = n;
-  hipLaunchKernelGGL(k_match, dim3(blocks_for(n, 4)), dim3(256), 0, s, a);
+  const MatchArgs a = match_args(cL, cR, W, H, p, slots, n);
+  SM_LAUNCH(k_match, dim3(blocks_for(n, 4)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
 hipError_t launch_compact(sm_support* slots, int32_t n, int32_t* n_out, uint8_t* occ, int32_t W,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, slots, n, n_out, occ, W);
+                          int32_t* header, hipStream_t s) {
+  SM_LAUNCH(k_compact, dim3(1), dim3(1024), 0, s, slots, n, n_out, occ, W, header);
   return hipGetLastError();
 }
 
 hipError_t launch_mark(const sm_support* S, int32_t n, uint8_t* occ, int32_t W, int32_t H,
                        hipStream_t s) {
   const size_t npx = (size_t)W * H;
-  hipLaunchKernelGGL(k_fill_u8, dim3(blocks_for(npx, 256)), dim3(256), 0, s, occ, npx, (uint8_t)0);
+  SM_LAUNCH(k_fill_u8, dim3(blocks_for(npx, 256)), dim3(256), 0, s, occ, npx, (uint8_t)0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n <= 0) return e;
-  hipLaunchKernelGGL(k_mark, dim3(blocks_for(n, 256)), dim3(256), 0, s, S, n, occ, W, H);
+  SM_LAUNCH(k_mark, dim3(blocks_for(n, 256)), dim3(256), 0, s, S, n, occ, W, H);
   return hipGetLastError();
 }
 
 hipError_t launch_fill_nan(float* D, size_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, D, n, __builtin_nanf(""));
+  SM_LAUNCH(k_fill_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, D, n, __builtin_nanf(""));
   return hipGetLastError();
 }
 
 hipError_t launch_raster(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
                          int32_t W, int32_t H, float* D_it, hipStream_t s) {
   if (n_tris <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_raster, dim3(blocks_for(n_tris, 4)), dim3(256), 0, s, S, n_support, T, n_tris, W,
+  SM_LAUNCH(k_raster, dim3(blocks_for(n_tris, 4)), dim3(256), 0, s, S, n_support, T, n_tris, W,
                      H, D_it);
   return hipGetLastError();
 }
@@ -590,7 +655,7 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
   a.Hc = (H + sz - 1) / sz;
   a.cpr = sz <= kWave ? kWave / sz : 1;
   a.TW = a.cpr * sz;
-  a.crows = sz >= 4 ? 1 : 4 / sz;
+  a.crows = sz >= kValWaves ? 1 : kValWaves / sz;
   a.TH = a.crows * sz;
   a.ginit = (uint64_t)p.t_lo << 32;
   a.binit = (uint64_t)(255 - p.t_hi) << 32;
@@ -602,7 +667,7 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
   a.mask = mask;
   a.n_valid = n_valid;
   dim3 grid(blocks_for(W, a.TW), blocks_for(H, a.TH));
-  hipLaunchKernelGGL(k_validate, grid, dim3(256), 0, s, a);
+  SM_LAUNCH(k_validate, grid, dim3(kWave * kValWaves), 0, s, a);
   return hipGetLastError();
 }
 
@@ -615,13 +680,14 @@ hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t
                               n_valid, s);
 }
 
-hipError_t launch_resample_cells(const uint64_t* cell_g, const uint64_t* cell_b,
-                                 const float* D_it, int32_t W, int32_t H, int32_t sz,
-                                 const sm_params& p, sm_support* slots, hipStream_t s) {
+hipError_t launch_resample(const uint64_t* cL, const uint64_t* cR, const uint64_t* cell_g,
+                           const uint64_t* cell_b, const float* D_it, int32_t W, int32_t H, int32_t sz,
+                           const sm_params& p, sm_support* slots, hipStream_t s) {
   const int n_cells = ((W + sz - 1) / sz) * ((H + sz - 1) / sz);
   const uint64_t ginit = (uint64_t)p.t_lo << 32, binit = (uint64_t)(255 - p.t_hi) << 32;
-  hipLaunchKernelGGL(k_resample_cells, dim3(blocks_for(n_cells, 256)), dim3(256), 0, s, cell_g,
-                     cell_b, D_it, W, n_cells, ginit, binit, slots);
+  const MatchArgs a = match_args(cL, cR, W, H, p, slots, 2 * n_cells);
+  SM_LAUNCH(k_rematch_cells, dim3(blocks_for(n_cells, 4)), dim3(256), 0, s, a, cell_g, cell_b, D_it,
+            n_cells, ginit, binit);
   return hipGetLastError();
 }
 

@@ -11,6 +11,11 @@
 
 namespace sm {
 
+// Arms a start/stop event pair for the next kernel launch of the calling thread (the
+// events then bracket that kernel's execution); pending tells whether it is unused.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool launch_events_pending();
+
 // Marker values in sm_support::d for candidate slots (real disparities are >= 0).
 constexpr float kPending = -1.0f;   // candidate waiting to be matched
 constexpr float kRejected = -2.0f;  // empty slot / rejected candidate
@@ -22,11 +27,20 @@ struct CensusJob {
   uint8_t* omega;  // may be null
 };
 
+// Per-frame initialisation folded into the census launch (all fields optional).
+struct CensusExtras {
+  float* D_nan = nullptr;             // [H][W] set to NaN
+  sm_support* grid_slots = nullptr;   // support-grid candidate slots (omega-filtered)
+  int32_t step = 1, gw = 0;           // grid pitch, grid nodes per row
+  int32_t* zero = nullptr;            // words set to 0
+  int32_t n_zero = 0;
+};
+
 // Census words (+ Omega_I) of one or two images of the same size in one launch.
 // When D_f / C_f / occ are non-null they are initialised (0, t_hi, 0) on the way.
 hipError_t launch_census(const CensusJob* jobs, int n_jobs, int32_t W, int32_t H, int32_t cw,
                          int32_t ch, int32_t grad_thr, float* D_f, uint8_t* C_f, int32_t t_hi,
-                         uint8_t* occ, hipStream_t s);
+                         uint8_t* occ, const CensusExtras* extras, hipStream_t s);
 
 // Candidate slots: grid nodes (omega-filtered) or an explicit (u, v) list.
 hipError_t launch_grid_slots(const uint8_t* omega, int32_t W, int32_t H, int32_t step,
@@ -37,10 +51,11 @@ hipError_t launch_list_slots(const int16_t* uv, int32_t n, sm_support* slots, hi
 hipError_t launch_match(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
                         const sm_params& p, sm_support* slots, int32_t n, hipStream_t s);
 
-// Order-preserving in-place compaction of slots with d >= 0 (and, when `occ` is
-// non-null, whose pixel is not yet occupied; kept pixels are then marked).
+// Order-preserving in-place compaction of non-marker slots (and, when `occ` is
+// non-null, whose pixel is not yet occupied; kept pixels are then marked). The count
+// goes to n_out and, when non-null, also to header.
 hipError_t launch_compact(sm_support* slots, int32_t n, int32_t* n_out, uint8_t* occ,
-                          int32_t W, hipStream_t s);
+                          int32_t W, int32_t* header, hipStream_t s);
 
 // Occupancy map of a support list (cleared first).
 hipError_t launch_mark(const sm_support* S, int32_t n, uint8_t* occ, int32_t W, int32_t H,
@@ -70,10 +85,10 @@ hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t
                            uint64_t* cell_b, uint8_t* mask, unsigned long long* n_valid,
                            hipStream_t s);
 
-// Cells -> slots: confident supports at slots[0, cells), X candidates at
-// slots[cells, 2 cells).
-hipError_t launch_resample_cells(const uint64_t* cell_g, const uint64_t* cell_b,
-                                 const float* D_it, int32_t W, int32_t H, int32_t sz,
-                                 const sm_params& p, sm_support* slots, hipStream_t s);
+// Resampling fused with the re-match: confident supports of the cells at
+// slots[0, cells), re-matched invalid pixels at slots[cells, 2 cells).
+hipError_t launch_resample(const uint64_t* cL, const uint64_t* cR, const uint64_t* cell_g,
+                           const uint64_t* cell_b, const float* D_it, int32_t W, int32_t H, int32_t sz,
+                           const sm_params& p, sm_support* slots, hipStream_t s);
 
 }  // namespace sm
