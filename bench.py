@@ -113,6 +113,84 @@ def cpu_baseline(frames, params, gpu_results, n):
                       f"{dt:.1f} s", "mpx_per_s": round(n * W * H / dt / 1e6, 4)}, ok
 
 
+def roofline_probe(api, params, W=7680, H=4320, reps=20, dev="cuda:0"):
+    """Interpolation and validation on one 7680x4320 frame (a working set far beyond
+    the 256 MB Infinity Cache): a uniform-random texture shifted by 16 px, supports
+    matched on the 10 px grid and triangulated once; each call timed with events."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(7)
+    left = rng.integers(0, 256, size=(H, W), dtype=np.uint8)
+    right = np.empty_like(left)
+    right[:, :W - 16] = left[:, 16:]
+    right[:, W - 16:] = rng.integers(0, 256, size=(H, 16), dtype=np.uint8)
+    L = torch.from_numpy(left).to(dev)
+    R = torch.from_numpy(right).to(dev)
+    cL, om = api.census(L, params["census_w"], params["census_h"], params["grad_thr"])
+    cR, _ = api.census(R, params["census_w"], params["census_h"], params["grad_thr"], with_omega=False)
+    buf, n = api.match_support(cL, cR, om, params)
+    n_s = int(n.item())
+    S = api.supports_to_numpy(buf, n_s)
+    tris = api.triangulate(S)
+    T = torch.from_numpy(np.ascontiguousarray(tris, np.int32).reshape(-1)).to(dev)
+    D = torch.empty((H, W), dtype=torch.float32, device=dev)
+    lib = api._lib.load()
+    stream = torch.cuda.current_stream()
+    n_t = int(T.numel() // 3)
+
+    def interp():
+        api.check(lib.sm_interpolate(buf.data_ptr(), n_s, T.data_ptr(), n_t, W, H, D.data_ptr(),
+                                     stream.cuda_stream))
+
+    sz = 32
+    n_cells = lib.sm_cells(W, H, sz)
+    g = torch.empty(n_cells, dtype=torch.int64, device=dev)
+    b = torch.empty(n_cells, dtype=torch.int64, device=dev)
+    D_f = torch.zeros((H, W), dtype=torch.float32, device=dev)
+    C_f = torch.empty((H, W), dtype=torch.uint8, device=dev)
+    p = api.make_params(params)
+
+    def valid():
+        api.check(lib.sm_validate(cL.data_ptr(), cR.data_ptr(), om.data_ptr(), D.data_ptr(), W, H, p,
+                                  sz, None, D_f.data_ptr(), C_f.data_ptr(), g.data_ptr(), b.data_ptr(),
+                                  stream.cuda_stream))
+
+    out = {}
+    for name, fn, per_px in (("interpolate", interp, 4.0), ("validate", valid, 27.0)):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            if name == "validate":
+                C_f.fill_(params["t_hi"])
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e3)
+        avg = float(np.mean(ts))
+        gbs = W * H * per_px / (avg * 1e-6) / 1e9
+        out[name] = {"avg_us": round(avg, 2), "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                     "algorithmic_per_launch": f"{W}x{H} px x {per_px} B"}
+    out["frame"] = f"{W}x{H}, {n_s} supports, {n_t} triangles, cells {sz}x{sz}"
+    return out
+
+
+def calibrate_copy(mib):
+    """A plain device copy of known size, for scaling the FETCH/WRITE counters."""
+    import torch
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda:0")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": mib << 20, "launches": 5}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,7 +201,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not record per-kernel events in the timed region")
+    ap.add_argument("--no-probe", action="store_true",
+                    help="skip the 7680x4320 interpolation/validation roofline probe")
+    ap.add_argument("--probe-only", action="store_true",
+                    help="only run the 7680x4320 roofline probe")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -144,6 +231,9 @@ def main():
     dev = "cuda:0"
     cfg = 2
     params = scenes.params_of(cfg)
+    if args.probe_only:
+        print(json.dumps({"roofline_probe_7680x4320": roofline_probe(api, params)}))
+        return
     W, H = scenes.CONFIGS[cfg]["W"], scenes.CONFIGS[cfg]["H"]
     frames = []
     for f in range(args.frames):
@@ -208,6 +298,7 @@ def main():
         rr = solver(dframes[i][0], dframes[i][1])
         torch.cuda.synchronize()
         gpu_results.append((rr.D_f.cpu().numpy(), rr.C_f.cpu().numpy(), rr.mask.cpu().numpy()))
+    probe = None if args.no_probe else roofline_probe(api, params)
     cpu = None
     validated = None
     if not args.no_cpu_baseline and args.cpu_frames > 0:
@@ -241,6 +332,7 @@ def main():
         "host_us_per_step": host,
         "roofline": roof,
         "roofline_validate": roof_val,
+        "roofline_probe_7680x4320": probe,
         "cpu_baseline": cpu,
         "paper_context": "paper: ~120 Hz (8.2 ms) VGA, 1 iteration, one i7-3920XM thread; "
                          "19.2 ms at 2 iterations",

@@ -431,7 +431,7 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
       if (!c.dl.insert_many(c.bu.data(), c.bv.data(), c.bext.data(), m))
         return fail(SM_ERR_INTERNAL, "support outside range");
       c.tris.clear();
-      c.dl.emit(c.tris, false);
+      c.dl.emit_banded(c.tris, 3);
     } catch (...) {
       return fail(SM_ERR_INTERNAL, "host triangulation failed");
     }

@@ -355,3 +355,36 @@ void Delaunay::emit(std::vector<sm_tri>& out, bool sorted) const {
 }
 
 }  // namespace sm
+
+namespace sm {
+
+void Delaunay::emit_banded(std::vector<sm_tri>& out, int band_shift) const {
+  int32_t max_band = 0;
+  for (const Pt& q : pt_) max_band = std::max(max_band, q.y >> band_shift);
+  band_count_.assign((size_t)max_band + 2, 0);
+  auto top_of = [&](const Tri& T) {
+    int k = 0;
+    for (int i = 1; i < 3; ++i) {
+      const Pt a = pt_[T.v[i]], b = pt_[T.v[k]];
+      if (a.y < b.y || (a.y == b.y && a.x < b.x)) k = i;
+    }
+    return k;
+  };
+  for (size_t t = 0; t < tri_.size(); ++t) {
+    if (!alive_[t] || tri_[t].v[2] == kGhost) continue;
+    const Tri& T = tri_[t];
+    ++band_count_[(pt_[T.v[top_of(T)]].y >> band_shift) + 1];
+  }
+  for (size_t i = 1; i < band_count_.size(); ++i) band_count_[i] += band_count_[i - 1];
+  const size_t base = out.size();
+  out.resize(base + (size_t)band_count_.back());
+  for (size_t t = 0; t < tri_.size(); ++t) {
+    if (!alive_[t] || tri_[t].v[2] == kGhost) continue;
+    const Tri& T = tri_[t];
+    const int k = top_of(T);
+    const int32_t slot = band_count_[pt_[T.v[k]].y >> band_shift]++;
+    out[base + slot] = sm_tri{ext_[T.v[k]], ext_[T.v[(k + 1) % 3]], ext_[T.v[(k + 2) % 3]]};
+  }
+}
+
+}  // namespace sm

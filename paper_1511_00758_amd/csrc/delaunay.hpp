@@ -38,6 +38,9 @@ class Delaunay {
   // Appends the solid triangles as external indices, counter-clockwise, first
   // vertex = smallest (v, u). Sorted by (i0, i1, i2) when `sorted`.
   void emit(std::vector<sm_tri>& out, bool sorted) const;
+  // Same triangles ordered by the row band (top row >> band_shift) of their first
+  // vertex (a counting sort): spatially coherent work for the rasteriser.
+  void emit_banded(std::vector<sm_tri>& out, int band_shift) const;
   int32_t n_points() const { return (int32_t)pt_.size(); }
   int32_t n_solid() const { return n_solid_; }
 
@@ -64,6 +67,7 @@ class Delaunay {
   std::vector<Edge> bnd_;
   std::vector<int32_t> newt_;
   std::vector<uint64_t> order_;
+  mutable std::vector<int32_t> band_count_;
   uint32_t gen_ = 0;
   int32_t hint_ = -1;
   int32_t n_solid_ = 0;

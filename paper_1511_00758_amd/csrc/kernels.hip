@@ -346,53 +346,112 @@ __global__ void k_mark(const sm_support* S, int n, uint8_t* occ, int W, int H) {
 }
 
 // ------------------------------------------------------------------------------------
-// Plane fit + rasterisation: one wave per triangle, one lane per pixel row. Each row's
-// owned span is solved exactly from the three edge functions (ownership of the
-// perturbed point (u + eps, v + eps^2)), then the plane is evaluated along it.
+// Plane fit + rasterisation. Every triangle's rows are dealt to lanes; each lane solves
+// its row's owned span exactly from the three edge functions (ownership of the
+// perturbed point (u + eps, v + eps^2)) and writes the plane along it. Two layouts:
+//  * k_raster_wave: one wave per triangle, one lane per row (64 rows at a time). Many
+//    short waves: best for small meshes, where the run is launch/latency bound and a
+//    large triangle only delays its own wave.
+//  * k_raster_group: 8 triangles per wave, 8 lanes per triangle taking its rows in
+//    turn. Eight times fewer waves and lanes mostly busy: best for large meshes.
+//    Workgroups are remapped so that each XCD (workgroups are dealt round-robin over
+//    the 8 XCDs) processes one contiguous run of the triangle list: with triangles
+//    ordered by row band, the partial cache lines a run writes stay in one L2.
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_raster(const sm_support* S, int n_support, const sm_tri* T,
-                                                int n_tris, int W, int H, float* D) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= n_tris) return;
+constexpr int kXcds = 8;
+constexpr int kTriPerWave = 8, kRowLanes = kWave / kTriPerWave;
+constexpr int kGroupLayoutMinTris = 16384;
+
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int x = b % kXcds, k = b / kXcds, q = nb / kXcds, r = nb % kXcds;
+  return x * q + min(x, r) + k;
+}
+
+struct RasterTri {
+  int ax[3], ay[3];     // vertices, first = anchor (u0, v0)
+  float a, b, d0;       // plane in anchor form
+  int vmin, vmax, umin, umax;
+  bool ok;
+};
+
+__device__ __forceinline__ RasterTri raster_setup(const sm_support* S, int n_support, const sm_tri* T,
+                                                  int t, int W, int H) {
+  RasterTri r;
+  r.ok = false;
   const sm_tri tr = T[t];
   if ((unsigned)tr.i0 >= (unsigned)n_support || (unsigned)tr.i1 >= (unsigned)n_support ||
       (unsigned)tr.i2 >= (unsigned)n_support)
-    return;  // malformed triangle: owns nothing
+    return r;  // malformed triangle: owns nothing
   const sm_support s0 = S[tr.i0], s1 = S[tr.i1], s2 = S[tr.i2];
   const int u0 = s0.u, v0 = s0.v, u1 = s1.u, v1 = s1.v, u2 = s2.u, v2 = s2.v;
-  if ((unsigned)(u0 | v0 | u1 | v1 | u2 | v2) > 8191u) return;  // outside the supported range
+  if ((unsigned)(u0 | v0 | u1 | v1 | u2 | v2) > 8191u) return r;  // outside the supported range
   const int du1 = u1 - u0, dv1 = v1 - v0, du2 = u2 - u0, dv2 = v2 - v0;
   const int det = du1 * dv2 - du2 * dv1;
-  if (det <= 0) return;
+  if (det <= 0) return r;
   const double e1 = __dadd_rn((double)s1.d, -(double)s0.d);
   const double e2 = __dadd_rn((double)s2.d, -(double)s0.d);
   const double ddet = (double)det;
-  const double pa = __ddiv_rn(__dadd_rn(__dmul_rn(e1, (double)dv2), -__dmul_rn(e2, (double)dv1)), ddet);
-  const double pb = __ddiv_rn(__dadd_rn(__dmul_rn((double)du1, e2), -__dmul_rn((double)du2, e1)), ddet);
-  const float a = (float)pa, b = (float)pb, d0 = s0.d;
-  const int ax[3] = {u0, u1, u2}, ay[3] = {v0, v1, v2};
-  const int vmin = max(min(v0, min(v1, v2)), 0), vmax = min(max(v0, max(v1, v2)), H - 1);
-  const int umin = max(min(u0, min(u1, u2)), 0), umax = min(max(u0, max(u1, u2)), W - 1);
-  for (int v = vmin + lane; v <= vmax; v += kWave) {
-    int lo = umin, hi = umax;
+  r.a = (float)__ddiv_rn(__dadd_rn(__dmul_rn(e1, (double)dv2), -__dmul_rn(e2, (double)dv1)), ddet);
+  r.b = (float)__ddiv_rn(__dadd_rn(__dmul_rn((double)du1, e2), -__dmul_rn((double)du2, e1)), ddet);
+  r.d0 = s0.d;
+  r.ax[0] = u0, r.ax[1] = u1, r.ax[2] = u2;
+  r.ay[0] = v0, r.ay[1] = v1, r.ay[2] = v2;
+  r.vmin = max(min(v0, min(v1, v2)), 0);
+  r.vmax = min(max(v0, max(v1, v2)), H - 1);
+  r.umin = max(min(u0, min(u1, u2)), 0);
+  r.umax = min(max(u0, max(u1, u2)), W - 1);
+  r.ok = r.vmin <= r.vmax && r.umin <= r.umax;
+  return r;
+}
+
+// Owned columns [lo, hi] of row v (empty when hi < lo).
+__device__ __forceinline__ void raster_span(const RasterTri& r, int v, int& lo, int& hi) {
+  lo = r.umin;
+  hi = r.umax;
 #pragma unroll
-    for (int e = 0; e < 3; ++e) {
-      const int xa = ax[e], ya = ay[e], xb = ax[(e + 1) % 3], yb = ay[(e + 1) % 3];
-      const int dy = yb - ya;
-      const int K = (xb - xa) * (v - ya);
-      if (dy == 0) {
-        if (!(K > 0 || (K == 0 && xb > xa))) hi = lo - 1;
-      } else if (dy < 0) {  // E = K + |dy| (u - xa) >= 0 (tie counts as inside)
-        lo = max(lo, xa + ceil_div_pos(-K, -dy));
-      } else {              // E = K - dy (u - xa) > 0
-        hi = min(hi, xa + ceil_div_pos(K, dy) - 1);
-      }
+  for (int e = 0; e < 3; ++e) {
+    const int xa = r.ax[e], ya = r.ay[e], xb = r.ax[(e + 1) % 3], yb = r.ay[(e + 1) % 3];
+    const int dy = yb - ya;
+    const int K = (xb - xa) * (v - ya);
+    if (dy == 0) {
+      if (!(K > 0 || (K == 0 && xb > xa))) hi = lo - 1;
+    } else if (dy < 0) {  // E = K + |dy| (u - xa) >= 0 (tie counts as inside)
+      lo = max(lo, xa + ceil_div_pos(-K, -dy));
+    } else {              // E = K - dy (u - xa) > 0
+      hi = min(hi, xa + ceil_div_pos(K, dy) - 1);
     }
-    float* row = D + (size_t)v * W;
-    const float tv = __fmul_rn(b, (float)(v - v0));
-    for (int u = lo; u <= hi; ++u) row[u] = __fadd_rn(__fadd_rn(d0, __fmul_rn(a, (float)(u - u0))), tv);
   }
+}
+
+// D = (d0 + a * (u - u0)) + b * (v - v0) along the span, each operation rounded.
+__device__ __forceinline__ void raster_row(const RasterTri& r, float* D, int W, int v) {
+  int lo, hi;
+  raster_span(r, v, lo, hi);
+  float* row = D + (size_t)v * W;
+  const float tv = __fmul_rn(r.b, (float)(v - r.ay[0]));
+  for (int u = lo; u <= hi; ++u) row[u] = __fadd_rn(__fadd_rn(r.d0, __fmul_rn(r.a, (float)(u - r.ax[0]))), tv);
+}
+
+__global__ __launch_bounds__(256) void k_raster_wave(const sm_support* S, int n_support, const sm_tri* T,
+                                                     int n_tris, int W, int H, float* D) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= n_tris) return;
+  const RasterTri r = raster_setup(S, n_support, T, t, W, H);
+  if (!r.ok) return;
+  for (int v = r.vmin + lane; v <= r.vmax; v += kWave) raster_row(r, D, W, v);
+}
+
+__global__ __launch_bounds__(256) void k_raster_group(const sm_support* S, int n_support, const sm_tri* T,
+                                                      int n_tris, int W, int H, float* D) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int t = (blk * 4 + (threadIdx.x >> 6)) * kTriPerWave + lane / kRowLanes;
+  const int rl = lane % kRowLanes;
+  if (t >= n_tris) return;  // lanes are independent
+  const RasterTri r = raster_setup(S, n_support, T, t, W, H);
+  if (!r.ok) return;
+  for (int v = r.vmin + rl; v <= r.vmax; v += kRowLanes) raster_row(r, D, W, v);
 }
 
 // ------------------------------------------------------------------------------------
@@ -621,8 +680,13 @@ hipError_t launch_fill_nan(float* D, size_t n, hipStream_t s) {
 hipError_t launch_raster(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
                          int32_t W, int32_t H, float* D_it, hipStream_t s) {
   if (n_tris <= 0) return hipSuccess;
-  SM_LAUNCH(k_raster, dim3(blocks_for(n_tris, 4)), dim3(256), 0, s, S, n_support, T, n_tris, W,
-                     H, D_it);
+  if (n_tris < kGroupLayoutMinTris) {
+    SM_LAUNCH(k_raster_wave, dim3(blocks_for(n_tris, 4)), dim3(256), 0, s, S, n_support, T, n_tris, W,
+              H, D_it);
+  } else {
+    SM_LAUNCH(k_raster_group, dim3(blocks_for(n_tris, 4 * kTriPerWave)), dim3(256), 0, s, S, n_support,
+              T, n_tris, W, H, D_it);
+  }
   return hipGetLastError();
 }
 

@@ -191,6 +191,20 @@ def test_interpolate_parity_random_float_supports(seed):
     assert _interp_compare(S, tris, W, H) == 1.0
 
 
+def test_interpolate_parity_large_mesh():
+    """A mesh of more than 16384 triangles (the rasteriser's grouped layout) over a
+    jittered grid with holes and random float disparities."""
+    rng = np.random.default_rng(3)
+    W, H = 1100, 900
+    pts = [(5 + 10 * i + int(rng.integers(-3, 4)), 5 + 10 * j + int(rng.integers(-3, 4)))
+           for j in range(H // 10) for i in range(W // 10)]
+    keep = rng.random(len(pts)) > 0.08
+    S = [(u, v, float(np.float32(rng.uniform(0, 100)))) for (u, v), k in zip(pts, keep) if k]
+    tris = oracle.triangulate(S, W)
+    assert len(tris) > 16384
+    assert _interp_compare(S, tris, W, H) == 1.0
+
+
 def test_interpolate_supports_outside_image():
     """Hull larger than the image: rows and columns are clipped."""
     W, H = 64, 40
