@@ -157,6 +157,7 @@ def roofline_probe(api, params, W=7680, H=4320, reps=20, dev="cuda:0"):
 
     out = {}
     for name, fn, per_px in (("interpolate", interp, 4.0), ("validate", valid, 27.0)):
+        kernel_name = "raster" if name == "interpolate" else name
         fn()
         torch.cuda.synchronize()
         ts = []
@@ -174,7 +175,10 @@ def roofline_probe(api, params, W=7680, H=4320, reps=20, dev="cuda:0"):
         gbs = W * H * per_px / (avg * 1e-6) / 1e9
         out[name] = {"avg_us": round(avg, 2), "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
-                     "algorithmic_per_launch": f"{W}x{H} px x {per_px} B"}
+                     "algorithmic_per_launch": f"{W}x{H} px x {per_px} B",
+                     "traffic": load_traffic(kernel_name, "probe_7680x4320")}
+    out["interpolate"]["note"] = ("sm_interpolate = NaN fill (4 B/px) + rasterisation; "
+                                  "traffic is the rasteriser kernel alone")
     out["frame"] = f"{W}x{H}, {n_s} supports, {n_t} triangles, cells {sz}x{sz}"
     return out
 
