@@ -183,6 +183,53 @@ def roofline_probe(api, params, W=7680, H=4320, reps=20, dev="cuda:0"):
     return out
 
 
+def batched_runs(api, vga_frames, vga_params, workers=16, batches=12, dev="cuda:0"):
+    """Throughput of sm_solve_batch: (a) the 640x480 workload in batches of 64 frames,
+    (b) the mixed batch of 64 pairs (16 each of 320x240, 640x480, 1242x375, 1280x720,
+    disparity ranges cycling 64/128/192/256; two distinct scenes per size, cycled)."""
+    import numpy as np
+    import torch
+    import scenes
+
+    def run(frames, params_list, maxW, maxH, n_batches):
+        bs = api.BatchSolver(workers, maxW, maxH, params_list, device=dev)
+        outs = None
+        bs(frames)  # warm-up (worker threads, staging)
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(n_batches):
+            outs, st, per = bs(frames, outputs=outs, stats=True)
+            lat += [x[1] for x in per]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        npx = sum(int(f[0].numel()) for f in frames)
+        lat = np.array(lat) / 1e3
+        return {"frames_per_s": round(n_batches * len(frames) / dt, 1),
+                "mpx_per_s": round(n_batches * npx / dt / 1e6, 2),
+                "ms_per_batch": round(dt / n_batches * 1e3, 3),
+                "frame_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                                     "p99": round(float(np.percentile(lat, 99)), 3)},
+                "frames_per_batch": len(frames), "workers": workers}
+
+    d = [(torch.from_numpy(l).to(dev), torch.from_numpy(r).to(dev)) for (l, r) in vga_frames]
+    vga = [(d[i % len(d)][0], d[i % len(d)][1], vga_params) for i in range(64)]
+    out = {"vga_20planes_batch64": run(vga, [vga_params], 640, 480, batches)}
+    sizes = ((320, 240), (640, 480), (1242, 375), (1280, 720))
+    ranges = (64, 128, 192, 256)
+    base = []
+    for si, (W, H) in enumerate(sizes):
+        for k in range(2):
+            dr = ranges[(2 * si + k) % 4]
+            sc = scenes.make_rect_scene(W, H, seed=4000 + 10 * si + k, dlo=2.0, dhi=0.9 * dr)
+            prm = scenes.params_of(4, d_min=0, d_max=dr - 1)
+            base.append((torch.from_numpy(sc.left).to(dev), torch.from_numpy(sc.right).to(dev), prm))
+    mixed = [base[2 * (i % 4) + (i // 4) % 2] for i in range(64)]
+    out["batch64_mixed"] = run(mixed, [b[2] for b in base], 1280, 720, batches)
+    out["batch64_mixed"]["sizes"] = "16 each of 320x240, 640x480, 1242x375, 1280x720"
+    return out
+
+
 def calibrate_copy(mib):
     """A plain device copy of known size, for scaling the FETCH/WRITE counters."""
     import torch
@@ -205,6 +252,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not record per-kernel events in the timed region")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched (sm_solve_batch) throughput runs")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the 7680x4320 interpolation/validation roofline probe")
     ap.add_argument("--probe-only", action="store_true",
@@ -303,6 +352,7 @@ def main():
         torch.cuda.synchronize()
         gpu_results.append((rr.D_f.cpu().numpy(), rr.C_f.cpu().numpy(), rr.mask.cpu().numpy()))
     probe = None if args.no_probe else roofline_probe(api, params)
+    batched = None if args.no_batch else batched_runs(api, frames, params)
     cpu = None
     validated = None
     if not args.no_cpu_baseline and args.cpu_frames > 0:
@@ -337,6 +387,7 @@ def main():
         "roofline": roof,
         "roofline_validate": roof_val,
         "roofline_probe_7680x4320": probe,
+        "batched": batched,
         "cpu_baseline": cpu,
         "paper_context": "paper: ~120 Hz (8.2 ms) VGA, 1 iteration, one i7-3920XM thread; "
                          "19.2 ms at 2 iterations",

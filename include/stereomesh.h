@@ -231,6 +231,37 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
                    const sm_params* p /* [host] */, void* ws, size_t ws_bytes, float* D_f,
                    uint8_t* C_f, uint8_t* mask, sm_stats* st /* [host] */, void* stream);
 
+/* One frame of a batch: inputs, method parameters, outputs (all device pointers). */
+typedef struct {
+  const uint8_t* L;            /* [H][stride] left image                                  */
+  const uint8_t* R;            /* [H][stride] right image                                 */
+  int32_t W, H, stride;
+  sm_params p;                 /* per-frame parameters (sizes and ranges may differ)     */
+  float* D_f;                  /* [H][W] out                                              */
+  uint8_t* C_f;                /* [H][W] out                                              */
+  uint8_t* mask;               /* [H][W] out                                              */
+  sm_status status;            /* [out] status of this frame                              */
+  int32_t worker;              /* [out] worker that solved it                              */
+  float latency_us;            /* [out] wall time of this frame's solve                    */
+} sm_frame;
+
+/*
+ * sm_solve_batch -- Alg. 1 on many independent frames at once: n_workers host threads,
+ *   each with its own stream and workspace, take frames from a shared counter and run
+ *   sm_solve on them, so that the host triangulation of one frame overlaps the kernels
+ *   and triangulations of the others. Each frame's result is identical to sm_solve of
+ *   that frame alone. The workers persist between calls made by the same thread.
+ *   frames     [host] [n] frames; status, worker and latency_us are written.
+ *   streams    [host] [n_workers] hipStream_t per worker (as void*).
+ *   ws, ws_bytes [host] [n_workers] workspace per worker; each must cover
+ *              sm_solve_workspace_bytes of every frame (checked before any work).
+ *   st         [host] statistics summed over frames, may be NULL.
+ *   Returns SM_OK when every frame succeeded, else the first failing frame's status.
+ *   Synchronous: returns when every frame is solved.
+ */
+sm_status sm_solve_batch(sm_frame* frames, int32_t n, void* const* streams, void* const* ws,
+                         const size_t* ws_bytes, int32_t n_workers, sm_stats* st);
+
 /* Message of the calling thread's last non-OK status ("" if none). */
 const char* sm_last_error(void);
 

@@ -43,9 +43,15 @@ class SmStats(ctypes.Structure):
                 ("stage_launches", c_i32 * N_STAGES)]
 
 
+class SmFrame(ctypes.Structure):
+    _fields_ = [("L", c_vp), ("R", c_vp), ("W", c_i32), ("H", c_i32), ("stride", c_i32),
+                ("p", SmParams), ("D_f", c_vp), ("C_f", c_vp), ("mask", c_vp),
+                ("status", c_i32), ("worker", c_i32), ("latency_us", c_f32)]
+
+
 EXPORTS = ("sm_census", "sm_match_support", "sm_grid_candidates", "sm_triangulate",
            "sm_interpolate", "sm_cells", "sm_validate", "sm_resample",
-           "sm_solve_workspace_bytes", "sm_solve", "sm_last_error", "sm_version")
+           "sm_solve_workspace_bytes", "sm_solve", "sm_solve_batch", "sm_last_error", "sm_version")
 
 
 class StereoMeshError(RuntimeError):
@@ -82,6 +88,8 @@ def load():
         "sm_solve_workspace_bytes": (c_size, [c_i32, c_i32, P(SmParams)]),
         "sm_solve": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, P(SmParams), c_vp, c_size, c_vp,
                              c_vp, c_vp, P(SmStats), c_vp]),
+        "sm_solve_batch": (c_i32, [P(SmFrame), c_i32, P(c_vp), P(c_vp), P(c_size), c_i32,
+                                   P(SmStats)]),
         "sm_last_error": (ctypes.c_char_p, []),
         "sm_version": (ctypes.c_char_p, []),
     }

@@ -8,6 +8,7 @@ Census words are returned as ``torch.int64`` tensors holding the uint64 bit patt
 supports live in flat ``uint8`` device buffers of 8-byte records (int16 u, int16 v,
 float32 d) and are converted to NumPy with ``SUPPORT_DTYPE``.
 """
+import ctypes
 from dataclasses import dataclass
 from typing import Optional
 
@@ -216,3 +217,65 @@ def solve(left: torch.Tensor, right: torch.Tensor, params: dict, stats=False) ->
     s = Solver(W, H, params, device=left.device)
     r = s(left, right, stats=stats)
     return SolveResult(r.D_f.clone(), r.C_f.clone(), r.mask.clone(), r.stats)
+
+
+class BatchSolver:
+    """Many frames (sizes and parameters may differ) solved concurrently by
+    ``sm_solve_batch``: ``n_workers`` host workers, each with its own HIP stream and a
+    workspace sized for the largest frame it may get."""
+
+    def __init__(self, n_workers: int, max_W: int, max_H: int, params_list, device="cuda"):
+        L = _lib.load()
+        need = 0
+        for prm in params_list:
+            need = max(need, L.sm_solve_workspace_bytes(max_W, max_H, make_params(prm)))
+        if need == 0:
+            raise ValueError("invalid size or parameters")
+        self.n_workers = n_workers
+        self.device = device
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(n_workers)]
+        self.ws = [torch.empty(need + 256, dtype=torch.uint8, device=device) for _ in range(n_workers)]
+        ptrs = [t.data_ptr() + ((-t.data_ptr()) % 256) for t in self.ws]
+        self._streams = (ctypes.c_void_p * n_workers)(*[s.cuda_stream for s in self.streams])
+        self._ws = (ctypes.c_void_p * n_workers)(*ptrs)
+        self._ws_bytes = (ctypes.c_size_t * n_workers)(*([need] * n_workers))
+        self.ws_bytes = need
+
+    def __call__(self, frames, outputs=None, stats=False, timing=False):
+        """frames: list of (left, right, params) with uint8 [H, W] CUDA tensors. Returns a
+        list of (D_f, C_f, mask) and, with ``stats``, the summed statistics and the
+        per-frame (worker, latency_us)."""
+        n = len(frames)
+        arr = (_lib.SmFrame * max(n, 1))()
+        outs = outputs
+        if outs is None:
+            outs = []
+            for (l, r, prm) in frames:
+                H, W = l.shape
+                outs.append((torch.empty((H, W), dtype=torch.float32, device=l.device),
+                             torch.empty((H, W), dtype=torch.uint8, device=l.device),
+                             torch.empty((H, W), dtype=torch.uint8, device=l.device)))
+        for i, ((l, r, prm), (D, C, M)) in enumerate(zip(frames, outs)):
+            _require_cuda(l, r, D, C, M)
+            H, W = l.shape
+            if r.shape != l.shape or r.stride(0) != l.stride(0):
+                raise ValueError("left and right must have the same shape and pitch")
+            f = arr[i]
+            f.L, f.R, f.W, f.H, f.stride = l.data_ptr(), r.data_ptr(), W, H, l.stride(0)
+            f.p = make_params(prm)
+            f.D_f, f.C_f, f.mask = D.data_ptr(), C.data_ptr(), M.data_ptr()
+        # inputs were produced on the current stream; the workers' streams wait for it
+        cur = torch.cuda.current_stream(self.device)
+        for s in self.streams:
+            s.wait_stream(cur)
+        st = _lib.SmStats()
+        st.timing = 1 if timing else 0
+        L = _lib.load()
+        check(L.sm_solve_batch(arr, n, self._streams, self._ws, self._ws_bytes, self.n_workers,
+                               st if (stats or timing) else None))
+        for s in self.streams:
+            cur.wait_stream(s)
+        if not (stats or timing):
+            return outs
+        per = [(int(arr[i].worker), float(arr[i].latency_us)) for i in range(n)]
+        return outs, stats_dict(st, 8), per

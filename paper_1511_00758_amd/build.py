@@ -27,6 +27,7 @@ HOST_FLAGS = COMMON + ["-ffp-contract=off", "-Wall", "-Wextra"]
 SOURCES = [
     ("kernels.hip", "hip"),
     ("api.cpp", "hip"),
+    ("batch.cpp", "hip"),
     ("delaunay.cpp", "host"),
 ]
 

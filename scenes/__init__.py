@@ -279,10 +279,10 @@ def make_rect_scene(W, H, seed, n_rects=19, dlo=2.0, dhi=124.0, flat_frac=0.05,
         a, b, c = _plane_in_range(rng, rect, dlo, dhi, 0.1)
         surfaces.append(_surface(rng, W, H, a, b, c, rect))
     target = flat_frac * W * H
-    for _attempt in range(200):
-        if flat_frac <= 0:
-            break
-        # measure the visible untextured area of the left view so far
+    if flat_frac > 0:
+        # visibility does not depend on texture: compute the nearest surface once, then
+        # add untextured patches (texture coordinates = left coordinates) until enough
+        # visible pixels are untextured
         vv, uu = np.mgrid[0:H, 0:W].astype(np.float64)
         best_d = np.full((H, W), -INF)
         best_k = np.full((H, W), -1, dtype=np.int64)
@@ -292,17 +292,18 @@ def make_rect_scene(W, H, seed, n_rects=19, dlo=2.0, dhi=124.0, flat_frac=0.05,
             best_d = np.where(m, d, best_d)
             best_k = np.where(m, k, best_k)
         flat = np.zeros((H, W), dtype=bool)
-        for k, s in enumerate(surfaces):
-            m = best_k == k
-            flat[m] = _flat_mask(s, uu[m], vv[m])
-        if flat.sum() >= target:
-            break
-        k = int(rng.integers(0, len(surfaces)))
-        w = rng.uniform(30, 90) * scale
-        h = rng.uniform(30, 90) * scale
-        u0 = rng.uniform(0, W - w)
-        v0 = rng.uniform(0, H - h)
-        surfaces[k].flat.append((u0, v0, u0 + w, v0 + h))
+        for _attempt in range(200):
+            if flat.sum() >= target:
+                break
+            k = int(rng.integers(0, len(surfaces)))
+            w = rng.uniform(30, 90) * scale
+            h = rng.uniform(30, 90) * scale
+            u0 = rng.uniform(0, W - w)
+            v0 = rng.uniform(0, H - h)
+            surfaces[k].flat.append((u0, v0, u0 + w, v0 + h))
+            r0, r1 = int(np.ceil(v0)), int(np.ceil(v0 + h))
+            c0, c1 = int(np.ceil(u0)), int(np.ceil(u0 + w))
+            flat[r0:r1, c0:c1] |= best_k[r0:r1, c0:c1] == k
     l, r, d, vis, tex = render(W, H, surfaces, rng, sigma)
     return Scene(l, r, d, vis, tex, {}, "rects", seed)
 
