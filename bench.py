@@ -230,6 +230,64 @@ def batched_runs(api, vga_frames, vga_params, workers=16, batches=12, dev="cuda:
     return out
 
 
+def serving_run(api, seconds=3.0, n_streams=16, slots=16, budget_gb=12.0, dev="cuda:0"):
+    """16 camera streams (640x480 / 1280x720 / 1920x1080 by stream id mod 3), Poisson
+    arrivals at 30 Hz each, disparities 0-255, 3 iterations, replayed in real time
+    through the continuous-batching server (latency), then all at once (capacity).
+    Latency = completion - arrival, including the host-to-device upload of the pair."""
+    import numpy as np
+    import torch
+    import scenes
+    from paper_1511_00758_amd.serving import StereoServer, StreamSpec, replay
+
+    sizes = ((640, 480), (1280, 720), (1920, 1080))
+    prm = scenes.params_of(5)
+    pairs = {}
+    for si, (W, H) in enumerate(sizes):
+        for k in range(2):
+            sc = scenes.make_rect_scene(W, H, seed=5000 + 10 * si + k, dlo=2.0, dhi=240.0)
+            pairs[(si, k)] = (torch.from_numpy(sc.left).pin_memory(),
+                              torch.from_numpy(sc.right).pin_memory())
+    specs = {s: StreamSpec(sizes[s % 3][0], sizes[s % 3][1], prm) for s in range(n_streams)}
+    # per-frame path, each size alone (reference latency)
+    solo = {}
+    for si, (W, H) in enumerate(sizes):
+        sv = api.Solver(W, H, prm, device=dev)
+        l, r = (t.to(dev) for t in pairs[(si, 0)])
+        sv(l, r)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(10):
+            t0 = time.perf_counter()
+            sv(l, r)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        solo[f"{W}x{H}"] = round(float(np.median(ts)), 3)
+        del sv
+    counter = {s: 0 for s in specs}
+
+    def frames_for(s):
+        counter[s] += 1
+        return pairs[(s % 3, (s // 3 + counter[s]) % 2)]
+
+    out = {"streams": n_streams, "slots": slots, "budget_gb": budget_gb, "rate_hz": 30.0,
+           "solo_latency_ms_p50": solo}
+    for mode, scale in (("realtime", 1.0), ("saturated", 0.0)):
+        server = StereoServer(specs, n_slots=slots, budget_bytes=int(budget_gb * 2**30), device=dev)
+        sched = scenes.stream_schedule(seed=11, n_streams=n_streams, rate_hz=30.0, seconds=seconds)
+        done, wall = replay(server, sched, frames_for, time_scale=scale)
+        lat = np.array([r.latency for r in done if r.t_arrival >= 0.2 * scale * seconds]) * 1e3
+        npx = sum(specs[r.stream].W * specs[r.stream].H for r in done)
+        out[mode] = {"frames": len(done), "wall_s": round(wall, 3),
+                     "frames_per_s": round(len(done) / wall, 1),
+                     "mpx_per_s": round(npx / wall / 1e6, 1),
+                     "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                                    "p99": round(float(np.percentile(lat, 99)), 3)},
+                     "evictions": server.adm.evictions}
+    out["offered_frames_per_s"] = round(n_streams * 30.0, 1)
+    return out
+
+
 def calibrate_copy(mib):
     """A plain device copy of known size, for scaling the FETCH/WRITE counters."""
     import torch
@@ -252,6 +310,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not record per-kernel events in the timed region")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the 16-stream serving run")
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched (sm_solve_batch) throughput runs")
     ap.add_argument("--no-probe", action="store_true",
@@ -353,6 +414,7 @@ def main():
         gpu_results.append((rr.D_f.cpu().numpy(), rr.C_f.cpu().numpy(), rr.mask.cpu().numpy()))
     probe = None if args.no_probe else roofline_probe(api, params)
     batched = None if args.no_batch else batched_runs(api, frames, params)
+    serving = None if args.no_serve else serving_run(api, seconds=args.serve_seconds)
     cpu = None
     validated = None
     if not args.no_cpu_baseline and args.cpu_frames > 0:
@@ -388,6 +450,7 @@ def main():
         "roofline_validate": roof_val,
         "roofline_probe_7680x4320": probe,
         "batched": batched,
+        "serving_16_streams": serving,
         "cpu_baseline": cpu,
         "paper_context": "paper: ~120 Hz (8.2 ms) VGA, 1 iteration, one i7-3920XM thread; "
                          "19.2 ms at 2 iterations",
