@@ -352,14 +352,16 @@ __global__ void k_mark(const sm_support* S, int n, uint8_t* occ, int W, int H) {
 //  * k_raster_wave: one wave per triangle, one lane per row (64 rows at a time). Many
 //    short waves: best for small meshes, where the run is launch/latency bound and a
 //    large triangle only delays its own wave.
-//  * k_raster_group: 8 triangles per wave, 8 lanes per triangle taking its rows in
-//    turn. Eight times fewer waves and lanes mostly busy: best for large meshes.
+//  * k_raster_group: 4 triangles per wave, 16 lanes per triangle taking its rows in
+//    turn (one pass for the typical 10-row triangle of a 10 px support grid); four
+//    times fewer waves and lanes mostly busy: best for large meshes (measured against
+//    2, 8 and 16 triangles per wave).
 //    Workgroups are remapped so that each XCD (workgroups are dealt round-robin over
 //    the 8 XCDs) processes one contiguous run of the triangle list: with triangles
 //    ordered by row band, the partial cache lines a run writes stay in one L2.
 // ------------------------------------------------------------------------------------
 constexpr int kXcds = 8;
-constexpr int kTriPerWave = 8, kRowLanes = kWave / kTriPerWave;
+constexpr int kTriPerWave = 4, kRowLanes = kWave / kTriPerWave;
 constexpr int kGroupLayoutMinTris = 16384;
 
 __device__ __forceinline__ int xcd_block(int b, int nb) {
@@ -484,11 +486,13 @@ struct ValidateArgs {
   unsigned long long* n_valid;
 };
 
-constexpr int kValWaves = 16;
-
-__global__ __launch_bounds__(1024) void k_validate(ValidateArgs a) {
-  __shared__ uint64_t sg[kValWaves][kWave];
-  __shared__ uint64_t sb[kValWaves][kWave];
+// NW waves per block; a tile of cpr x crows cells, each wave taking every NW-th row.
+// The launcher picks NW per frame size: few waves per block (many rows per wave) once
+// the grid alone fills the chip, more waves per block on small frames.
+template <int NW>
+__global__ __launch_bounds__(kWave * NW, 8) void k_validate(ValidateArgs a) {
+  __shared__ uint64_t sg[NW][kWave];
+  __shared__ uint64_t sb[NW][kWave];
   __shared__ unsigned int s_valid;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x >> 6;
@@ -497,43 +501,63 @@ __global__ __launch_bounds__(1024) void k_validate(ValidateArgs a) {
   const uint64_t none = ~0ull;
   uint64_t kg = none, kb = none;
   unsigned int nvalid = 0;
-  for (int r = w; r < a.TH; r += kValWaves) {
-    const int v = y0 + r;
-    if (v >= a.H) break;
+  // two rows (r, r + NW) per step: both rows' loads are in flight together
+  for (int r = w; r < a.TH; r += 2 * NW) {
     for (int c = lane; c < a.TW; c += kWave) {
       const int u = x0 + c;
       if (u >= a.W) break;
-      const size_t idx = (size_t)v * a.W + u;
-      // independent loads first
-      const bool om = a.omega[idx] != 0;
-      const float Dv = a.D_it[idx];
-      const uint64_t wl = a.cL[idx];
-      uint32_t cf = a.C_f[idx];
-      uint32_t cost = 0xffu;
-      if (om && isfinite(Dv)) {
-        const float f = floorf(__fadd_rn(Dv, 0.5f));
-        if (f >= (float)a.d_min && f <= (float)a.d_max) {
-          const int d = (int)f;
-          if (u - d >= a.rx) cost = (uint32_t)__popcll(wl ^ a.cR[idx - d]);
+      uint32_t idx[2];  // W * H <= 2^26
+      bool in[2], om[2];
+      float Dv[2];
+      uint64_t wl[2], wr[2];
+      uint32_t cf[2], cost[2];
+      int dd[2];
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        const int v = y0 + r + k * NW;
+        in[k] = r + k * NW < a.TH && v < a.H;
+        idx[k] = (uint32_t)(in[k] ? v : 0) * (uint32_t)a.W + (uint32_t)u;
+        om[k] = in[k] && a.omega[idx[k]] != 0;
+        Dv[k] = in[k] ? a.D_it[idx[k]] : 0.0f;
+        wl[k] = in[k] ? a.cL[idx[k]] : 0ull;
+        cf[k] = in[k] ? a.C_f[idx[k]] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        dd[k] = -1;
+        if (om[k] && isfinite(Dv[k])) {
+          const float f = floorf(__fadd_rn(Dv[k], 0.5f));
+          if (f >= (float)a.d_min && f <= (float)a.d_max) {
+            const int d = (int)f;
+            if (u - d >= a.rx) dd[k] = d;
+          }
         }
+        wr[k] = dd[k] >= 0 ? a.cR[idx[k] - dd[k]] : 0ull;
       }
-      if (a.C_it) a.C_it[idx] = (uint8_t)cost;
-      if (cost < cf) {  // never true for 0xff: C_f <= t_hi <= 64
-        a.D_f[idx] = Dv;
-        a.C_f[idx] = (uint8_t)cost;
-        cf = cost;
-      }
-      if (a.mask) {
-        const bool mk = om && cf < (uint32_t)a.t_hi;
-        a.mask[idx] = mk;
-        nvalid += mk;
-      }
-      if (cost < (uint32_t)a.t_lo) {
-        const uint64_t k = (uint64_t)cost << 32 | (uint64_t)idx;
-        kg = k < kg ? k : kg;
-      } else if (cost != 0xffu && cost > (uint32_t)a.t_hi) {
-        const uint64_t k = (uint64_t)(255u - cost) << 32 | (uint64_t)idx;
-        kb = k < kb ? k : kb;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        if (!in[k]) continue;
+        cost[k] = dd[k] >= 0 ? (uint32_t)__popcll(wl[k] ^ wr[k]) : 0xffu;
+        const uint32_t i = idx[k];
+        if (a.C_it) a.C_it[i] = (uint8_t)cost[k];
+        uint32_t cfk = cf[k];
+        if (cost[k] < cfk) {  // never true for 0xff: C_f <= t_hi <= 64
+          a.D_f[i] = Dv[k];
+          a.C_f[i] = (uint8_t)cost[k];
+          cfk = cost[k];
+        }
+        if (a.mask) {
+          const bool mk = om[k] && cfk < (uint32_t)a.t_hi;
+          a.mask[i] = mk;
+          nvalid += mk;
+        }
+        if (cost[k] < (uint32_t)a.t_lo) {
+          const uint64_t key = (uint64_t)cost[k] << 32 | (uint64_t)i;
+          kg = key < kg ? key : kg;
+        } else if (cost[k] != 0xffu && cost[k] > (uint32_t)a.t_hi) {
+          const uint64_t key = (uint64_t)(255u - cost[k]) << 32 | (uint64_t)i;
+          kb = key < kb ? key : kb;
+        }
       }
     }
   }
@@ -560,9 +584,9 @@ __global__ __launch_bounds__(1024) void k_validate(ValidateArgs a) {
     if (cy < a.Hc && cx < a.Wc) {
       uint64_t g = a.ginit, b = a.binit;
       // the waves whose rows belong to cell row w: rows w*sz .. w*sz+sz-1 are handled by
-      // waves (row mod 16); with crows > 1 every wave holds rows of one cell row only
+      // waves (row mod NW); with crows > 1 every wave holds rows of one cell row only
       const int w_lo = a.crows == 1 ? 0 : w * a.sz;
-      const int w_hi = a.crows == 1 ? kValWaves : w * a.sz + a.sz;
+      const int w_hi = a.crows == 1 ? NW : w * a.sz + a.sz;
       for (int q = w_lo; q < w_hi; ++q) {
         g = sg[q][lane] < g ? sg[q][lane] : g;
         b = sb[q][lane] < b ? sb[q][lane] : b;
@@ -578,6 +602,10 @@ __global__ __launch_bounds__(1024) void k_validate(ValidateArgs a) {
 }
 
 inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// validate launch shape: 2048 waves is 8 per CU, enough to cover HBM latency
+constexpr int kValMaxWaves = 16;
+constexpr size_t kValMinWaves = 2048;
 
 }  // namespace
 
@@ -719,8 +747,14 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
   a.Hc = (H + sz - 1) / sz;
   a.cpr = sz <= kWave ? kWave / sz : 1;
   a.TW = a.cpr * sz;
-  a.crows = sz >= kValWaves ? 1 : kValWaves / sz;
-  a.TH = a.crows * sz;
+  // smallest block (most rows per wave) whose grid still holds >= kValMinWaves waves
+  int nw = 1;
+  for (;; nw *= 2) {
+    a.crows = sz >= nw ? 1 : nw / sz;
+    a.TH = a.crows * sz;
+    const size_t waves = (size_t)blocks_for(W, a.TW) * blocks_for(H, a.TH) * nw;
+    if (nw == kValMaxWaves || waves >= kValMinWaves) break;
+  }
   a.ginit = (uint64_t)p.t_lo << 32;
   a.binit = (uint64_t)(255 - p.t_hi) << 32;
   a.C_it = C_it;
@@ -731,7 +765,13 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
   a.mask = mask;
   a.n_valid = n_valid;
   dim3 grid(blocks_for(W, a.TW), blocks_for(H, a.TH));
-  SM_LAUNCH(k_validate, grid, dim3(kWave * kValWaves), 0, s, a);
+  switch (nw) {
+    case 1: SM_LAUNCH(k_validate<1>, grid, dim3(kWave * 1), 0, s, a); break;
+    case 2: SM_LAUNCH(k_validate<2>, grid, dim3(kWave * 2), 0, s, a); break;
+    case 4: SM_LAUNCH(k_validate<4>, grid, dim3(kWave * 4), 0, s, a); break;
+    case 8: SM_LAUNCH(k_validate<8>, grid, dim3(kWave * 8), 0, s, a); break;
+    default: SM_LAUNCH(k_validate<16>, grid, dim3(kWave * 16), 0, s, a); break;
+  }
   return hipGetLastError();
 }
 

@@ -283,6 +283,49 @@ def test_validate_cells_any_size(frames, sz):
     assert _decode(b.cpu().numpy(), W, (255 - p.t_hi) << 32, True) == _oracle_cells(Cb)
 
 
+def _low_density_words(rng, H, W, bits):
+    """Census-like words whose bit density grows down the image, so that Hamming costs
+    span 0 .. ~bits/2 and both cell classes (cost < t_lo, cost > t_hi) occur."""
+    rho = np.linspace(0.0, 0.5, H, dtype=np.float64)[:, None, None]
+    on = rng.random((H, W, bits)) < rho
+    weights = (np.uint64(1) << np.arange(bits, dtype=np.uint64))
+    return (on.astype(np.uint64) * weights).sum(axis=2, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("size", [(320, 480), (333, 487)])
+@pytest.mark.parametrize("sz", [1, 2, 4, 8, 16, 32])
+def test_validate_block_shapes(size, sz):
+    """Validation on random inputs at cell sizes whose launches use every block shape
+    (1 to 16 waves per block, picked from the grid size), with ragged right/bottom
+    tiles on the odd frame size. C_it, D_f, C_f and both cell grids are compared
+    element by element with the oracle."""
+    api = _api()
+    W, H = size
+    rng = np.random.default_rng(31 * sz + W)
+    prm = scenes.params_of(2)
+    p = oracle.Params.from_dict(prm)
+    cL = _low_density_words(rng, H, W, 48)
+    cR = _low_density_words(rng, H, W, 48)
+    omega = rng.random((H, W)) < 0.7
+    D_it = rng.uniform(-1.5, p.d_max + 2.0, size=(H, W)).astype(np.float32)
+    D_it[rng.random((H, W)) < 0.1] = np.nan
+    D_f0 = rng.uniform(0, 50, size=(H, W)).astype(np.float32)
+    C_f0 = rng.integers(0, p.t_hi + 1, size=(H, W)).astype(np.uint8)
+    C_exp = oracle.cost_evaluation(cL, cR, omega, D_it, p)
+    D_exp, Cf_exp = D_f0.copy(), C_f0.copy()
+    Cg, Cb = oracle.disparity_refinement(D_it, C_exp, D_exp, Cf_exp, p, sz)
+    assert (C_exp < p.t_lo).any() and ((C_exp > p.t_hi) & (C_exp != 0xFF)).any()
+    D_f, C_f = _to_dev(D_f0), _to_dev(C_f0)
+    C_it, g, b = api.validate(_to_dev(cL.view(np.int64)), _to_dev(cR.view(np.int64)),
+                              _to_dev(omega.astype(np.uint8)), _to_dev(D_it), prm, sz, D_f, C_f)
+    torch.cuda.synchronize()
+    assert (C_it.cpu().numpy() == C_exp).all()
+    assert (C_f.cpu().numpy() == Cf_exp).all()
+    assert (D_f.cpu().numpy().view(np.uint32) == D_exp.view(np.uint32)).all()
+    assert _decode(g.cpu().numpy(), W, p.t_lo << 32, False) == _oracle_cells(Cg)
+    assert _decode(b.cpu().numpy(), W, (255 - p.t_hi) << 32, True) == _oracle_cells(Cb)
+
+
 # ----------------------------------------------------------------------------------
 # resampling
 # ----------------------------------------------------------------------------------
