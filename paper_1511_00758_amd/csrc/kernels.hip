@@ -8,6 +8,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 namespace sm {
 
 // Event pair armed by the host layer for the next launch of this thread: the kernel
@@ -44,10 +46,6 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
     x = y < x ? y : x;
   }
   return x;
-}
-
-__device__ __forceinline__ int ceil_div_pos(int n, int d) {  // d > 0
-  return n >= 0 ? (n + d - 1) / d : -((-n) / d);
 }
 
 // ------------------------------------------------------------------------------------
@@ -346,19 +344,19 @@ __global__ void k_mark(const sm_support* S, int n, uint8_t* occ, int W, int H) {
 }
 
 // ------------------------------------------------------------------------------------
-// Plane fit + rasterisation. Every triangle's rows are dealt to lanes; each lane solves
-// its row's owned span exactly from the three edge functions (ownership of the
-// perturbed point (u + eps, v + eps^2)) and writes the plane along it. Two layouts:
+// Plane fit + rasterisation. Each triangle's rows are dealt to lanes; a lane solves its
+// row's owned span exactly from the three edges (ownership of the perturbed point
+// (u + eps, v + eps^2)) with no branches, and evaluates the plane along it. Two layouts:
 //  * k_raster_wave: one wave per triangle, one lane per row (64 rows at a time). Many
 //    short waves: best for small meshes, where the run is launch/latency bound and a
 //    large triangle only delays its own wave.
 //  * k_raster_group: 4 triangles per wave, 16 lanes per triangle taking its rows in
-//    turn (one pass for the typical 10-row triangle of a 10 px support grid); four
-//    times fewer waves and lanes mostly busy: best for large meshes (measured against
-//    2, 8 and 16 triangles per wave).
+//    turn (one pass for the typical 10-row triangle of a 10 px support grid): best for
+//    large meshes (measured against 2 and 8 triangles per wave, and against staging a
+//    workgroup's pixels in an LDS window written out with 16-byte stores, which cut the
+//    store instructions but lost more to LDS writes and occupancy).
 //    Workgroups are remapped so that each XCD (workgroups are dealt round-robin over
-//    the 8 XCDs) processes one contiguous run of the triangle list: with triangles
-//    ordered by row band, the partial cache lines a run writes stay in one L2.
+//    the 8 XCDs) takes one contiguous run of the triangle list.
 // ------------------------------------------------------------------------------------
 constexpr int kXcds = 8;
 constexpr int kTriPerWave = 4, kRowLanes = kWave / kTriPerWave;
@@ -369,25 +367,39 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return x * q + min(x, r) + k;
 }
 
+// A triangle ready for rasterisation. Row v of the owned region is the column range
+// [lo, hi] = [umin, umax] cut by the three edges. With edge e running from vertex e to
+// vertex e + 1 (dx, dy) and E = dx (v - ya) - dy (u - xa), the perturbed point of pixel
+// (u, v) is on the triangle's side when E > 0; E = 0 is settled by the perturbation:
+// inside for dy < 0, outside for dy > 0, inside for a horizontal edge iff dx > 0. So
+// dy < 0 bounds u below by xa + ceil(-dx (v - ya) / -dy), dy > 0 bounds it above by
+// xa + ceil(dx (v - ya) / dy) - 1, and a horizontal edge admits rows v >= ya (dx > 0)
+// or v < ya (dx < 0), which setup folds into the row range. Each bound is
+// ceil((A v + B) / d) + C with per-edge constants.
 struct RasterTri {
-  int ax[3], ay[3];     // vertices, first = anchor (u0, v0)
+  int A[3], B[3], C[3], d[3];
+  float rc[3];          // 1 / d to within 1 ulp
+  int kind[3];          // 0: lower bound on u, 1: upper bound, 2: none (horizontal edge)
   float a, b, d0;       // plane in anchor form
+  int u0, v0;           // anchor
   int vmin, vmax, umin, umax;
   bool ok;
 };
 
+// Setup of triangle t. Triangles that own nothing (malformed indices, vertices outside
+// [0, 8191], not positively oriented, or outside the image) come back with ok = false.
 __device__ __forceinline__ RasterTri raster_setup(const sm_support* S, int n_support, const sm_tri* T,
                                                   int t, int W, int H) {
-  RasterTri r;
+  RasterTri r = {};
   r.ok = false;
   const sm_tri tr = T[t];
   if ((unsigned)tr.i0 >= (unsigned)n_support || (unsigned)tr.i1 >= (unsigned)n_support ||
       (unsigned)tr.i2 >= (unsigned)n_support)
-    return r;  // malformed triangle: owns nothing
+    return r;
   const sm_support s0 = S[tr.i0], s1 = S[tr.i1], s2 = S[tr.i2];
-  const int u0 = s0.u, v0 = s0.v, u1 = s1.u, v1 = s1.v, u2 = s2.u, v2 = s2.v;
-  if ((unsigned)(u0 | v0 | u1 | v1 | u2 | v2) > 8191u) return r;  // outside the supported range
-  const int du1 = u1 - u0, dv1 = v1 - v0, du2 = u2 - u0, dv2 = v2 - v0;
+  const int x[3] = {s0.u, s1.u, s2.u}, y[3] = {s0.v, s1.v, s2.v};
+  if ((unsigned)(x[0] | y[0] | x[1] | y[1] | x[2] | y[2]) > 8191u) return r;
+  const int du1 = x[1] - x[0], dv1 = y[1] - y[0], du2 = x[2] - x[0], dv2 = y[2] - y[0];
   const int det = du1 * dv2 - du2 * dv1;
   if (det <= 0) return r;
   const double e1 = __dadd_rn((double)s1.d, -(double)s0.d);
@@ -396,42 +408,70 @@ __device__ __forceinline__ RasterTri raster_setup(const sm_support* S, int n_sup
   r.a = (float)__ddiv_rn(__dadd_rn(__dmul_rn(e1, (double)dv2), -__dmul_rn(e2, (double)dv1)), ddet);
   r.b = (float)__ddiv_rn(__dadd_rn(__dmul_rn((double)du1, e2), -__dmul_rn((double)du2, e1)), ddet);
   r.d0 = s0.d;
-  r.ax[0] = u0, r.ax[1] = u1, r.ax[2] = u2;
-  r.ay[0] = v0, r.ay[1] = v1, r.ay[2] = v2;
-  r.vmin = max(min(v0, min(v1, v2)), 0);
-  r.vmax = min(max(v0, max(v1, v2)), H - 1);
-  r.umin = max(min(u0, min(u1, u2)), 0);
-  r.umax = min(max(u0, max(u1, u2)), W - 1);
+  r.u0 = x[0];
+  r.v0 = y[0];
+  int vlo = max(min(y[0], min(y[1], y[2])), 0);
+  int vhi = min(max(y[0], max(y[1], y[2])), H - 1);
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int xa = x[e], ya = y[e], dx = x[(e + 1) % 3] - xa, dy = y[(e + 1) % 3] - ya;
+    if (dy == 0) {
+      if (dx > 0) vlo = max(vlo, ya);
+      else vhi = min(vhi, ya - 1);
+      r.A[e] = 0, r.B[e] = 0, r.C[e] = 0, r.d[e] = 1, r.rc[e] = 1.0f, r.kind[e] = 2;
+    } else if (dy < 0) {
+      r.A[e] = -dx, r.B[e] = dx * ya, r.C[e] = xa, r.d[e] = -dy, r.kind[e] = 0;
+    } else {
+      r.A[e] = dx, r.B[e] = -dx * ya, r.C[e] = xa - 1, r.d[e] = dy, r.kind[e] = 1;
+    }
+    if (dy != 0) r.rc[e] = __builtin_amdgcn_rcpf((float)r.d[e]);
+  }
+  r.vmin = vlo;
+  r.vmax = vhi;
+  r.umin = max(min(x[0], min(x[1], x[2])), 0);
+  r.umax = min(max(x[0], max(x[1], x[2])), W - 1);
   r.ok = r.vmin <= r.vmax && r.umin <= r.umax;
   return r;
 }
 
-// Owned columns [lo, hi] of row v (empty when hi < lo).
+// ceil((A v + B) / d) + C, given |A v + B| < 2^26, 1 <= d <= 8192 and rc = 1/d within
+// 1 ulp: a float estimate (within |q| 2^-22 of the quotient q) corrected once by the
+// exact integer remainder. Exact whenever |q| < 2^18, where the remainder cannot wrap;
+// larger quotients put the bound beyond any 8192-column image, where an estimate off by
+// a few units has the same effect.
+__device__ __forceinline__ int edge_bound(int A, int B, int C, int d, float rc, int v) {
+  const int n = A * v + B;
+  int q = (int)ceilf(__fmul_rn((float)n, rc));
+  const int rem = (int)((unsigned)q * (unsigned)d - (unsigned)n);
+  q += (rem < 0) - (rem >= d);
+  return q + C;
+}
+
+// Owned columns [lo, hi] of row v (empty when hi < lo); no branches, so lanes working on
+// different triangles stay converged.
 __device__ __forceinline__ void raster_span(const RasterTri& r, int v, int& lo, int& hi) {
   lo = r.umin;
   hi = r.umax;
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
-    const int xa = r.ax[e], ya = r.ay[e], xb = r.ax[(e + 1) % 3], yb = r.ay[(e + 1) % 3];
-    const int dy = yb - ya;
-    const int K = (xb - xa) * (v - ya);
-    if (dy == 0) {
-      if (!(K > 0 || (K == 0 && xb > xa))) hi = lo - 1;
-    } else if (dy < 0) {  // E = K + |dy| (u - xa) >= 0 (tie counts as inside)
-      lo = max(lo, xa + ceil_div_pos(-K, -dy));
-    } else {              // E = K - dy (u - xa) > 0
-      hi = min(hi, xa + ceil_div_pos(K, dy) - 1);
-    }
+    const int bound = edge_bound(r.A[e], r.B[e], r.C[e], r.d[e], r.rc[e], v);
+    lo = max(lo, r.kind[e] == 0 ? bound : INT_MIN);
+    hi = min(hi, r.kind[e] == 1 ? bound : INT_MAX);
   }
 }
 
-// D = (d0 + a * (u - u0)) + b * (v - v0) along the span, each operation rounded.
-__device__ __forceinline__ void raster_row(const RasterTri& r, float* D, int W, int v) {
-  int lo, hi;
-  raster_span(r, v, lo, hi);
-  float* row = D + (size_t)v * W;
-  const float tv = __fmul_rn(r.b, (float)(v - r.ay[0]));
-  for (int u = lo; u <= hi; ++u) row[u] = __fadd_rn(__fadd_rn(r.d0, __fmul_rn(r.a, (float)(u - r.ax[0]))), tv);
+// D = (d0 + a * (u - u0)) + b * (v - v0), each operation rounded, along [lo, hi] of row
+// v; (float)(u - u0) is stepped by exact +1 increments (integers below 2^24).
+__device__ __forceinline__ void raster_row(const RasterTri& r, int v, int lo, int hi, float* row) {
+  const float tv = __fmul_rn(r.b, (float)(v - r.v0));
+  float fu = (float)(lo - r.u0);
+  int u = lo;
+  for (; u < hi; u += 2) {
+    row[u] = __fadd_rn(__fadd_rn(r.d0, __fmul_rn(r.a, fu)), tv);
+    row[u + 1] = __fadd_rn(__fadd_rn(r.d0, __fmul_rn(r.a, __fadd_rn(fu, 1.0f))), tv);
+    fu = __fadd_rn(fu, 2.0f);
+  }
+  if (u == hi) row[u] = __fadd_rn(__fadd_rn(r.d0, __fmul_rn(r.a, fu)), tv);
 }
 
 __global__ __launch_bounds__(256) void k_raster_wave(const sm_support* S, int n_support, const sm_tri* T,
@@ -441,7 +481,11 @@ __global__ __launch_bounds__(256) void k_raster_wave(const sm_support* S, int n_
   if (t >= n_tris) return;
   const RasterTri r = raster_setup(S, n_support, T, t, W, H);
   if (!r.ok) return;
-  for (int v = r.vmin + lane; v <= r.vmax; v += kWave) raster_row(r, D, W, v);
+  for (int v = r.vmin + lane; v <= r.vmax; v += kWave) {
+    int lo, hi;
+    raster_span(r, v, lo, hi);
+    raster_row(r, v, lo, hi, D + (size_t)v * W);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_raster_group(const sm_support* S, int n_support, const sm_tri* T,
@@ -453,7 +497,11 @@ __global__ __launch_bounds__(256) void k_raster_group(const sm_support* S, int n
   if (t >= n_tris) return;  // lanes are independent
   const RasterTri r = raster_setup(S, n_support, T, t, W, H);
   if (!r.ok) return;
-  for (int v = r.vmin + rl; v <= r.vmax; v += kRowLanes) raster_row(r, D, W, v);
+  for (int v = r.vmin + rl; v <= r.vmax; v += kRowLanes) {
+    int lo, hi;
+    raster_span(r, v, lo, hi);
+    raster_row(r, v, lo, hi, D + (size_t)v * W);
+  }
 }
 
 // ------------------------------------------------------------------------------------

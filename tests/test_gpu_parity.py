@@ -193,7 +193,8 @@ def test_interpolate_parity_random_float_supports(seed):
 
 def test_interpolate_parity_large_mesh():
     """A mesh of more than 16384 triangles (the rasteriser's grouped layout) over a
-    jittered grid with holes and random float disparities."""
+    jittered grid with holes and random float disparities, in canonical and in shuffled
+    triangle order (ownership does not depend on the order)."""
     rng = np.random.default_rng(3)
     W, H = 1100, 900
     pts = [(5 + 10 * i + int(rng.integers(-3, 4)), 5 + 10 * j + int(rng.integers(-3, 4)))
@@ -202,6 +203,29 @@ def test_interpolate_parity_large_mesh():
     S = [(u, v, float(np.float32(rng.uniform(0, 100)))) for (u, v), k in zip(pts, keep) if k]
     tris = oracle.triangulate(S, W)
     assert len(tris) > 16384
+    assert _interp_compare(S, tris, W, H) == 1.0
+    shuffled = [tris[i] for i in rng.permutation(len(tris))]
+    assert _interp_compare(S, shuffled, W, H) == 1.0
+
+
+@pytest.mark.parametrize("many", [False, True])
+def test_interpolate_parity_extreme_edges(many):
+    """Slivers across an 8192-column frame: edges with dy = 1 and dx ~ 8191 put the
+    column bounds of far rows at quotients beyond 2^18, where the rasteriser's division
+    estimate is only required to land outside the image. With many = True, a grid
+    of small triangles is added so that the grouped layout (> 16384 triangles) runs."""
+    W, H = 8192, 40
+    S = [(0, 0, 1.0), (8191, 1, 50.0), (0, 39, 7.5), (8191, 38, 3.25), (4096, 0, 20.0),
+         (1, 20, 11.0), (8190, 21, 2.5), (4000, 39, 33.0)]
+    if many:
+        rng = np.random.default_rng(11)
+        for j in range(2, 38, 4):
+            for i in range(8, 8184, 7):
+                if rng.random() < 0.9:
+                    S.append((i + int(rng.integers(0, 2)), j, float(np.float32(rng.uniform(0, 60)))))
+    tris = oracle.triangulate(S, W)
+    if many:
+        assert len(tris) > 16384
     assert _interp_compare(S, tris, W, H) == 1.0
 
 
