@@ -8,10 +8,10 @@ namespace sm {
 namespace {
 inline int sgn(int64_t x) { return (x > 0) - (x < 0); }
 
-// Index of (x, y) along a Hilbert curve over [0, 8192)^2.
-inline uint32_t hilbert(uint32_t x, uint32_t y) {
+// Index of cell (x, y) along a Hilbert curve over a 2^order x 2^order grid of cells.
+inline uint32_t hilbert(uint32_t x, uint32_t y, int order) {
   uint32_t d = 0;
-  for (uint32_t s = 1u << 12; s > 0; s >>= 1) {
+  for (uint32_t s = 1u << (order - 1); s > 0; s >>= 1) {
     const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
     d += s * s * ((3u * rx) ^ ry);
     if (ry == 0) {
@@ -309,26 +309,44 @@ bool Delaunay::insert(int32_t u, int32_t v, int32_t ext) {
 bool Delaunay::insert_many(const int32_t* u, const int32_t* v, const int32_t* ext, int32_t n) {
   for (int32_t i = 0; i < n; ++i)
     if (u[i] < 0 || v[i] < 0 || u[i] > 8191 || v[i] > 8191) return false;
-  // round of point i: random, with round k holding about half of the points of round k+1
-  order_.resize(n);
+  // Biased randomised insertion order: point i joins round k with probability 2^-(k+1)
+  // (k = number of trailing one bits of a xorshift draw, capped at 15); rounds are
+  // inserted from the sparsest, each in Hilbert order of 32 px cells. Key = 4 round bits
+  // + 16 cell bits, sorted by a stable 3-pass LSD radix sort (input order within a
+  // cell), so the order costs O(n).
+  constexpr int kCellShift = 5, kOrder = 13 - kCellShift, kCellBits = 2 * kOrder;
+  key_.resize(n);
+  idx_.resize(n);
+  key2_.resize(n);
+  idx2_.resize(n);
   uint32_t r = 0x2545f491u;
   for (int32_t i = 0; i < n; ++i) {
     r ^= r << 13;
     r ^= r >> 17;
     r ^= r << 5;
-    uint32_t round = 0;  // number of leading coin flips that came up heads, capped
-    uint32_t bits = r;
-    while ((bits & 1u) && round < 20) {
-      ++round;
-      bits >>= 1;
-    }
-    // rare high rounds go first; within a round, Hilbert order; then the input index
-    order_[i] = (((uint64_t)(31 - round)) << 58) | ((uint64_t)hilbert((uint32_t)u[i], (uint32_t)v[i]) << 26) |
-                (uint64_t)i;
+    const uint32_t round = std::min<uint32_t>((uint32_t)__builtin_ctz(~r), 15u);
+    const uint32_t cell = hilbert((uint32_t)u[i] >> kCellShift, (uint32_t)v[i] >> kCellShift, kOrder);
+    key_[i] = ((15u - round) << kCellBits) | cell;
+    idx_[i] = i;
   }
-  std::sort(order_.begin(), order_.end());
+  for (int shift = 0; shift < kCellBits + 4; shift += 8) {
+    uint32_t count[257] = {0};
+    for (int32_t i = 0; i < n; ++i) ++count[((key_[i] >> shift) & 255u) + 1];
+    for (int b = 0; b < 256; ++b) count[b + 1] += count[b];
+    for (int32_t i = 0; i < n; ++i) {
+      const uint32_t o = count[(key_[i] >> shift) & 255u]++;
+      key2_[o] = key_[i];
+      idx2_[o] = idx_[i];
+    }
+    key_.swap(key2_);
+    idx_.swap(idx2_);
+  }
+  pt_.reserve(pt_.size() + n);
+  ext_.reserve(ext_.size() + n);
+  vstamp_.reserve(vstamp_.size() + n);
+  vfan_.reserve(vfan_.size() + n);
   for (int32_t k = 0; k < n; ++k) {
-    const int32_t i = (int32_t)(order_[k] & ((1u << 26) - 1));
+    const int32_t i = idx_[k];
     insert(u[i], v[i], ext[i]);
   }
   return true;

@@ -31,8 +31,8 @@ class Delaunay {
   // outside [0, 8191]^2.
   bool insert(int32_t u, int32_t v, int32_t ext);
   // Inserts n points in a biased randomised insertion order (random rounds of doubling
-  // size, each round in Hilbert-curve order): short walks and small holes whatever
-  // the input order. Returns false if a point lies outside [0, 8191]^2 (nothing is
+  // size, each round in Hilbert-curve order of 32 px cells): short walks and small
+  // holes whatever the input order. Returns false if a point lies outside [0, 8191]^2 (nothing is
   // inserted then).
   bool insert_many(const int32_t* u, const int32_t* v, const int32_t* ext, int32_t n);
   // Appends the solid triangles as external indices, counter-clockwise, first
@@ -66,7 +66,8 @@ class Delaunay {
   struct Edge { int32_t a, b, out; };
   std::vector<Edge> bnd_;
   std::vector<int32_t> newt_;
-  std::vector<uint64_t> order_;
+  std::vector<uint32_t> key_, key2_;  // insertion-order keys (radix sort buffers)
+  std::vector<int32_t> idx_, idx2_;
   mutable std::vector<int32_t> band_count_;
   uint32_t gen_ = 0;
   int32_t hint_ = -1;
