@@ -12,6 +12,8 @@ It restates the paper step by step in NumPy / Python integers:
                 high-gradient subset of Sec. III);
 * ``matching``  support candidates and epipolar matching with a left-right check
                 (Sec. III-A, "SparseStereo" / "SparseEpipolarStereo" of Alg. 1 / Alg. 4);
+* ``fast``      FAST keypoints sampled from spatial bins, the paper's own support
+                detector (Sec. III-A), as an alternative to the candidate grid;
 * ``delaunay``  Delaunay triangulation of the supports (Sec. III-A), exact integer
                 predicates with symbolic perturbation for ties;
 * ``interp``    per-triangle disparity planes (Eq. 3) and the pixel-to-triangle
@@ -32,6 +34,7 @@ accuracy against the synthetic ground truth is context, not a pin).
 from .params import Params
 from .census import census, high_gradient
 from .matching import grid_candidates, match_point, sparse_stereo, hamming
+from .fast import CIRCLE, fast_score, keypoints, fast_candidates
 from .delaunay import triangulate, orient, incircle, incircle_sos
 from .interp import plane_of, planes, interpolate
 from .refine import cost_evaluation, disparity_refinement, Cell

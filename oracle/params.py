@@ -16,6 +16,12 @@ class Params:
     lr_tol: int = 1         # allowed |d_LR - d| in the left-right check
     uniqueness: int = 1     # margin: reject if a disparity >= 2 away costs < best + margin
     sz_occ0: int = 32       # initial occupancy-grid size (Alg. 1 initialisation)
+    support_mode: int = 0   # 0: candidate grid; 1: FAST keypoints from spatial bins (Sec. III-A)
+    fast_threshold: int = 16  # FAST: corner when the arc contrast exceeds this
+    fast_bins_x: int = 12   # FAST spatial bins across (12 x 10 in Sec. III-A)
+    fast_bins_y: int = 10   # FAST spatial bins down
+    fast_per_bin: int = 25  # at most this many keypoints per bin
+    levels: int = 1         # disparity levels tested by cost evaluation (1 = Alg. 2; 3 or 5)
 
     @classmethod
     def from_dict(cls, d):

@@ -38,7 +38,13 @@ class Cell:
 
 
 def cost_evaluation(cL, cR, omega, D_it, p) -> np.ndarray:
-    """Alg. 2: C_it uint8 [H, W], 0xFF where not evaluated."""
+    """Alg. 2: C_it uint8 [H, W], 0xFF where not evaluated.
+
+    With ``p.levels`` = L > 1 (the "3-5 disparity levels" of Sec. III-B), the cost of an
+    evaluated pixel is the smallest Hamming distance over the L integer disparities
+    d - k .. d + k (k = (L - 1) / 2) around the rounded d that are themselves admissible
+    (in [d_min, d_max], u - d' >= rx); which pixels are evaluated, and D_it itself, do not
+    change."""
     H, W = cL.shape
     C = np.full((H, W), NOT_EVALUATED, dtype=np.uint8)
     vs, us = np.nonzero(omega & np.isfinite(D_it))
@@ -49,7 +55,17 @@ def cost_evaluation(cL, cR, omega, D_it, p) -> np.ndarray:
     ok = (dint >= p.d_min) & (dint <= p.d_max) & (us - dint >= p.rx)
     vs, us, dint = vs[ok], us[ok], dint[ok]
     x = np.bitwise_xor(cL[vs, us], cR[vs, us - dint])
-    C[vs, us] = np.bitwise_count(x).astype(np.uint8)
+    cost = np.bitwise_count(x).astype(np.int64)
+    k = (getattr(p, "levels", 1) - 1) // 2
+    for delta in range(-k, k + 1):
+        if delta == 0:
+            continue
+        d2 = dint + delta
+        ok2 = (d2 >= p.d_min) & (d2 <= p.d_max) & (us - d2 >= p.rx)
+        c2 = np.full(cost.shape, 255, dtype=np.int64)
+        c2[ok2] = np.bitwise_count(np.bitwise_xor(cL[vs[ok2], us[ok2]], cR[vs[ok2], us[ok2] - d2[ok2]]))
+        cost = np.minimum(cost, c2)
+    C[vs, us] = cost.astype(np.uint8)
     return C
 
 

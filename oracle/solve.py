@@ -12,6 +12,7 @@ which (C_f starting at t_hi) is exactly the set of pixels that passed validation
 import numpy as np
 
 from .census import census, high_gradient
+from .fast import fast_candidates
 from .delaunay import triangulate
 from .interp import interpolate
 from .matching import grid_candidates, sparse_stereo
@@ -38,7 +39,10 @@ def solve(left: np.ndarray, right: np.ndarray, p: Params, trace: bool = False):
     omega = high_gradient(left, valid, p.grad_thr)
     D_f = np.zeros((H, W), dtype=np.float32)
     C_f = np.full((H, W), p.t_hi, dtype=np.uint8)
-    cands = grid_candidates(W, H, p.support_step, omega)
+    if getattr(p, "support_mode", 0) == 1:
+        cands = fast_candidates(left, p.fast_threshold, p.fast_bins_x, p.fast_bins_y, p.fast_per_bin)
+    else:
+        cands = grid_candidates(W, H, p.support_step, omega)
     S = sparse_stereo(cL, cR, cands, p)
     tris = triangulate(S, W)
     out = {"cL": cL, "cR": cR, "omega": omega, "iters": []}
