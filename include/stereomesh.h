@@ -69,6 +69,16 @@ typedef struct {
   int32_t uniqueness;          /* reject when a disparity >= 2 away costs < best + uniqueness;
                                   0 disables the test                                          */
   int32_t sz_occ0;             /* initial occupancy-grid size (32 in Alg. 1), 1..1024           */
+  /* Paper variants (Sec. III-A, III-B); zero-initialising them gives 0 = the grid, which
+     is valid, and levels = 0, which is not: set levels = 1 for Alg. 2 as printed.       */
+  int32_t support_mode;        /* 0: candidate grid of support_step; 1: FAST keypoints from
+                                  spatial bins (sm_fast_candidates)                           */
+  int32_t fast_threshold;      /* FAST: corner when the arc contrast > fast_threshold, 0..254   */
+  int32_t fast_bins_x;         /* FAST: spatial bins across (12 in Sec. III-A), 1..1024         */
+  int32_t fast_bins_y;         /* FAST: spatial bins down (10 in Sec. III-A), 1..1024           */
+  int32_t fast_per_bin;        /* FAST: at most this many keypoints per bin, 1..4096;
+                                  fast_bins_x * fast_bins_y * fast_per_bin <= 2^22            */
+  int32_t levels;              /* disparity levels tested by cost evaluation: 1 (Alg. 2), 3, 5 */
 } sm_params;
 
 /* Per-solve statistics. `timing` is an input: when non-zero, sm_solve records a pair of
@@ -82,6 +92,7 @@ typedef enum {
   SM_ST_RASTER = 3,          /* plane fit + per-triangle rasterisation (interpolation)        */
   SM_ST_VALIDATE = 4,        /* cost evaluation + refinement                                 */
   SM_ST_REMATCH = 5,         /* resampling: cells -> confident supports + re-matched pixels  */
+  SM_ST_FAST = 6,            /* FAST scores + per-bin keypoint selection (support_mode 1)     */
   SM_ST_HOST_TRI = 12,       /* host triangulation (wall time)                               */
   SM_ST_HOST_COPY = 13,      /* host<->device copies and waits (wall time)                   */
   SM_ST_TOTAL = 14           /* whole sm_solve call (wall time)                              */
@@ -141,6 +152,29 @@ sm_status sm_match_support(const uint64_t* cL, const uint64_t* cR, const uint8_t
 int32_t sm_grid_candidates(int32_t W, int32_t H, int32_t support_step);
 
 /*
+ * sm_fast_candidates -- support keypoints by the FAST segment test, sampled from
+ *   spatial bins (Sec. III-A; Rosten and Drummond's FAST-9).
+ *   Circle: the 16 pixels of the radius-3 Bresenham ring, clockwise from the pixel
+ *   straight above p. With diff_k = I(ring_k) - I(p), score(p) = max over the 16 arcs
+ *   of 9 consecutive ring pixels of max(min diff, min -diff) over the arc, floored at 0
+ *   (0 where the ring leaves the image); p is a corner when score > fast_threshold.
+ *   A corner is a keypoint when no 3x3 neighbour scores higher and no neighbour earlier
+ *   in raster order scores the same. Pixel (u, v) lies in bin
+ *   (u * fast_bins_x / W, v * fast_bins_y / H) (integer division); each bin keeps its
+ *   fast_per_bin highest-scoring keypoints (ties to the earlier raster position).
+ *   img      [H][stride] uint8 image (the left image).
+ *   p        [host] parameters; only the fast_* fields are read.
+ *   score    [H][W] uint8 out: score(p) for every pixel (also used as scratch).
+ *   cand_uv  [cap][2] int16 out: (u, v) of the kept keypoints, bins row-major and raster
+ *            order inside a bin; cap >= fast_bins_x * fast_bins_y * fast_per_bin, else
+ *            SM_ERR_CAPACITY. Entries past the count are scratch.
+ *   n_out    [1] int32 out: number of candidates.
+ */
+sm_status sm_fast_candidates(const uint8_t* img, int32_t W, int32_t H, int32_t stride,
+                             const sm_params* p /* [host] */, uint8_t* score, int16_t* cand_uv,
+                             int32_t cap, int32_t* n_out, void* stream);
+
+/*
  * sm_triangulate -- Delaunay triangulation G(S) of the support pixels (Sec. III-A).
  *   Exact integer predicates; cocircular ties resolved by symbolic perturbation of
  *   the lifting z = u^2 + v^2 + eps_i, a smaller raster position (v, u) getting the
@@ -176,7 +210,10 @@ int32_t sm_cells(int32_t W, int32_t H, int32_t sz_occ);
  * sm_validate -- CostEvaluation (Alg. 2) and DisparityRefinement (Alg. 3).
  *   For (u, v) in Omega_I with a finite D_it: d = floor(float32(D_it + 0.5)); when
  *   d_min <= d <= d_max and u - d >= rx, C_it = Hamming(cL(u,v), cR(u-d,v)), else the
- *   pixel is not evaluated (C_it = 0xFF). For evaluated pixels: if C_it < C_f then
+ *   pixel is not evaluated (C_it = 0xFF). With p->levels = L > 1 (the "3-5 disparity
+ *   levels" of Sec. III-B) an evaluated pixel's C_it is the smallest Hamming distance
+ *   over d' in [d - (L-1)/2, d + (L-1)/2] with d_min <= d' <= d_max and u - d' >= rx;
+ *   the evaluated set and D_it are unchanged. For evaluated pixels: if C_it < C_f then
  *   D_f = D_it and C_f = C_it. Cells of sz_occ x sz_occ pixels (cell (u/sz, v/sz),
  *   ceil(W/sz) per row) keep the pixel with the smallest C_it < t_lo (C_g) and the
  *   one with the largest C_it > t_hi (C_b); ties go to the first pixel in raster order.
@@ -214,7 +251,9 @@ size_t sm_solve_workspace_bytes(int32_t W, int32_t H, const sm_params* p /* [hos
 
 /*
  * sm_solve -- Iterative Stereo Reconstruction (Alg. 1) on a rectified pair:
- *   D_f = 0, C_f = t_hi; S_1 = matched grid supports; G(S_1); then for it = 1..n_iters:
+ *   D_f = 0, C_f = t_hi; S_1 = matched support candidates (the grid, or with
+ *   support_mode = 1 the FAST keypoints of sm_fast_candidates); G(S_1); then for
+ *   it = 1..n_iters:
  *   interpolation, cost evaluation, refinement with sz_occ = max(1, sz_occ0 >> (it-1)),
  *   and, unless it is the last iteration, resampling and re-triangulation (the new
  *   supports are inserted into the existing triangulation, which yields the same unique

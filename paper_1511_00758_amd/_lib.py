@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SM_OK", -1: "SM_ERR_ARG", -2: "SM_ERR_CAPACITY", -3: "SM_ERR
                 -4: "SM_ERR_INTERNAL"}
 # sm_stage indices of sm_stats.stage_us / stage_launches
 STAGES = {"census": 0, "match": 1, "compact": 2, "raster": 3, "validate": 4, "rematch": 5,
-          "host_triangulate": 12, "host_copies": 13, "total": 14}
+          "fast": 6, "host_triangulate": 12, "host_copies": 13, "total": 14}
 N_STAGES = 16
 
 
@@ -30,7 +30,11 @@ class SmTri(ctypes.Structure):
 
 
 PARAM_FIELDS = ("d_min", "d_max", "census_w", "census_h", "support_step", "n_iters", "t_hi",
-                "t_lo", "grad_thr", "lr_tol", "uniqueness", "sz_occ0")
+                "t_lo", "grad_thr", "lr_tol", "uniqueness", "sz_occ0", "support_mode",
+                "fast_threshold", "fast_bins_x", "fast_bins_y", "fast_per_bin", "levels")
+# the paper-variant fields default to the grid candidates and Alg. 2's single level
+PARAM_DEFAULTS = {"support_mode": 0, "fast_threshold": 16, "fast_bins_x": 12, "fast_bins_y": 10,
+                  "fast_per_bin": 25, "levels": 1}
 
 
 class SmParams(ctypes.Structure):
@@ -49,7 +53,7 @@ class SmFrame(ctypes.Structure):
                 ("status", c_i32), ("worker", c_i32), ("latency_us", c_f32)]
 
 
-EXPORTS = ("sm_census", "sm_match_support", "sm_grid_candidates", "sm_triangulate",
+EXPORTS = ("sm_census", "sm_match_support", "sm_grid_candidates", "sm_fast_candidates", "sm_triangulate",
            "sm_interpolate", "sm_cells", "sm_validate", "sm_resample",
            "sm_solve_workspace_bytes", "sm_solve", "sm_solve_batch", "sm_last_error", "sm_version")
 
@@ -78,6 +82,8 @@ def load():
         "sm_match_support": (c_i32, [c_vp, c_vp, c_vp, c_i32, c_i32, c_vp, c_i32, P(SmParams),
                                      c_vp, c_i32, c_vp, c_vp]),
         "sm_grid_candidates": (c_i32, [c_i32, c_i32, c_i32]),
+        "sm_fast_candidates": (c_i32, [c_vp, c_i32, c_i32, c_i32, P(SmParams), c_vp, c_vp, c_i32, c_vp,
+                                       c_vp]),
         "sm_triangulate": (c_i32, [c_vp, c_i32, c_vp, c_i32, P(c_i32)]),
         "sm_interpolate": (c_i32, [c_vp, c_i32, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp]),
         "sm_cells": (c_i32, [c_i32, c_i32, c_i32]),
@@ -109,7 +115,8 @@ def check(status):
 
 
 def make_params(d=None, **kw) -> SmParams:
-    vals = dict(d or {})
+    vals = dict(PARAM_DEFAULTS)
+    vals.update(d or {})
     vals.update(kw)
     p = SmParams()
     for f in PARAM_FIELDS:

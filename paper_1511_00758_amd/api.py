@@ -66,18 +66,23 @@ def supports_to_device(S: np.ndarray, device="cuda") -> torch.Tensor:
     return torch.from_numpy(arr.view(np.uint8).copy()).to(device)
 
 
-def match_support(cL, cR, omega, params: dict, cand_uv: Optional[np.ndarray] = None,
-                  stream=None):
+def match_support(cL, cR, omega, params: dict, cand_uv=None, stream=None, n_cand=None):
     """Matched supports: (device buffer, device int32 count). ``cand_uv`` is an (n, 2)
-    int16 array of (u, v) candidates, or None for the support grid."""
+    int16 array or device tensor of (u, v) candidates (the first ``n_cand`` rows when
+    given), or None for the support grid."""
     _require_cuda(cL, cR, omega)
     H, W = cL.shape
     p = make_params(params)
     L = _lib.load()
     cand = None
     if cand_uv is not None:
-        cand = torch.from_numpy(np.ascontiguousarray(cand_uv, dtype=np.int16).reshape(-1, 2)).to(cL.device)
-        n = cand.shape[0]
+        if isinstance(cand_uv, torch.Tensor):
+            cand = cand_uv.reshape(-1, 2)
+            if cand.dtype != torch.int16 or not cand.is_contiguous() or cand.device != cL.device:
+                raise ValueError("cand_uv tensor must be contiguous int16 on the census device")
+        else:
+            cand = torch.from_numpy(np.ascontiguousarray(cand_uv, dtype=np.int16).reshape(-1, 2)).to(cL.device)
+        n = cand.shape[0] if n_cand is None else int(n_cand)
     else:
         n = L.sm_grid_candidates(W, H, p.support_step)
     out = new_support_buffer(n, cL.device)
@@ -85,6 +90,22 @@ def match_support(cL, cR, omega, params: dict, cand_uv: Optional[np.ndarray] = N
     check(L.sm_match_support(cL.data_ptr(), cR.data_ptr(), _ptr(omega), W, H, _ptr(cand),
                              n, p, out.data_ptr(), max(n, 1), n_out.data_ptr(), _stream(stream)))
     return out, n_out
+
+
+def fast_candidates(img, params: dict, stream=None):
+    """FAST keypoints sampled from spatial bins: (score uint8 [H, W], candidates int16
+    [cap, 2] with the first n valid, device int32 n)."""
+    _require_cuda(img)
+    H, W = img.shape
+    p = make_params(params)
+    L = _lib.load()
+    cap = max(p.fast_bins_x * p.fast_bins_y * p.fast_per_bin, 1)
+    score = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    cand = torch.empty((cap, 2), dtype=torch.int16, device=img.device)
+    n_out = torch.zeros(1, dtype=torch.int32, device=img.device)
+    check(L.sm_fast_candidates(img.data_ptr(), W, H, img.stride(0), p, score.data_ptr(),
+                               cand.data_ptr(), cap, n_out.data_ptr(), _stream(stream)))
+    return score, cand, n_out
 
 
 def triangulate(S: np.ndarray) -> np.ndarray:

@@ -45,6 +45,18 @@ sm_status check_params(const sm_params* p) {
   if (p->lr_tol < 0) return fail(SM_ERR_ARG, "lr_tol must be >= 0");
   if (p->uniqueness < 0 || p->uniqueness > 64) return fail(SM_ERR_ARG, "uniqueness must be in [0, 64]");
   if (p->sz_occ0 < 1 || p->sz_occ0 > 1024) return fail(SM_ERR_ARG, "sz_occ0 must be in [1, 1024]");
+  if (p->support_mode != 0 && p->support_mode != 1) return fail(SM_ERR_ARG, "support_mode must be 0 or 1");
+  if (p->levels != 1 && p->levels != 3 && p->levels != 5) return fail(SM_ERR_ARG, "levels must be 1, 3 or 5");
+  if (p->support_mode == 1) SM_TRY(check_fast_params(p));
+  return SM_OK;
+}
+
+sm_status check_fast_params(const sm_params* p) {
+  if (p->fast_threshold < 0 || p->fast_threshold > 254) return fail(SM_ERR_ARG, "fast_threshold must be in [0, 254]");
+  if (p->fast_bins_x < 1 || p->fast_bins_x > 1024 || p->fast_bins_y < 1 || p->fast_bins_y > 1024)
+    return fail(SM_ERR_ARG, "fast_bins_x, fast_bins_y must be in [1, 1024]");
+  if (p->fast_per_bin < 1 || p->fast_per_bin > 4096) return fail(SM_ERR_ARG, "fast_per_bin must be in [1, 4096]");
+  if (fast_slots(*p) > (1 << 22)) return fail(SM_ERR_ARG, "fast_bins_x * fast_bins_y * fast_per_bin exceeds 2^22");
   return SM_OK;
 }
 
@@ -150,8 +162,8 @@ inline float us_since(clk::time_point t0) {
 
 // Workspace layout of sm_solve (256-byte aligned sub-buffers).
 struct Layout {
-  size_t cL, cR, omega, occ, D_it, cell_g, cell_b, S, T, counters, total;
-  int32_t n_grid, S_cap, T_cap, cells_max;
+  size_t cL, cR, omega, occ, D_it, cell_g, cell_b, S, T, counters, score, total;
+  int32_t n_grid, S_cap, T_cap, cells_max;  // n_grid: initial candidate slots (grid or FAST)
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -159,7 +171,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
   Layout L{};
   const size_t npx = (size_t)W * H;
-  L.n_grid = grid_count(W, H, p.support_step);
+  L.n_grid = p.support_mode == 1 ? (int32_t)fast_slots(p) : grid_count(W, H, p.support_step);
   L.cells_max = cells_of(W, H, occ_size(p, p.n_iters));
   // each slot region is followed by one header slot that receives its count
   int64_t scap = L.n_grid + 1;
@@ -182,6 +194,7 @@ Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
   L.S = take((size_t)L.S_cap * sizeof(sm_support));
   L.T = take((size_t)L.T_cap * sizeof(sm_tri));
   L.counters = take(64);
+  L.score = p.support_mode == 1 ? take(npx) : 0;  // FAST scores
   L.total = o;
   return L;
 }
@@ -289,6 +302,23 @@ sm_status sm_triangulate(const sm_support* S, int32_t n, sm_tri* tris, int32_t c
   return SM_OK;
 }
 
+sm_status sm_fast_candidates(const uint8_t* img, int32_t W, int32_t H, int32_t stride, const sm_params* p,
+                             uint8_t* score, int16_t* cand_uv, int32_t cap, int32_t* n_out, void* stream) {
+  last_error().clear();
+  SM_TRY(check_image_args(W, H));
+  if (stride < W) return fail(SM_ERR_ARG, "stride %d < W %d", stride, W);
+  if (!img || !score || !cand_uv || !n_out) return fail(SM_ERR_ARG, "NULL buffer");
+  if (!p) return fail(SM_ERR_ARG, "params is NULL");
+  SM_TRY(check_fast_params(p));
+  const int64_t slots = fast_slots(*p);
+  if (cap < slots) return fail(SM_ERR_CAPACITY, "cap %d < %lld candidate slots", cap, (long long)slots);
+  const hipStream_t s = (hipStream_t)stream;
+  SM_HIP(launch_fast_score(img, stride, W, H, score, s));
+  SM_HIP(launch_fast_select(score, W, H, *p, nullptr, cand_uv, s));
+  SM_HIP(launch_compact_uv(cand_uv, (int32_t)slots, n_out, s));
+  return SM_OK;
+}
+
 sm_status sm_interpolate(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
                          int32_t W, int32_t H, float* D_it, void* stream) {
   last_error().clear();
@@ -385,9 +415,10 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   // iterations, S_it being a subset of S_it+1, so one fill per frame suffices), the
   // support-grid candidate slots and the counters
   CensusJob jobs[2] = {{L, stride, cL, omega}, {R, stride, cR, nullptr}};
+  const bool fast = p->support_mode == 1;
   CensusExtras ex;
   ex.D_nan = D_it;
-  ex.grid_slots = Sd;
+  ex.grid_slots = fast ? nullptr : Sd;
   ex.step = p->support_step;
   ex.gw = Lo.n_grid > 0 ? (W - 1 - p->support_step / 2) / p->support_step + 1 : 0;
   ex.zero = counters;
@@ -397,7 +428,16 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
                        s));
   SM_TRY(tm.end());
 
-  // S_1 = SparseStereo(I_l, I_r) over the candidate grid; the count lands in the slot
+  if (fast) {  // FAST keypoints from spatial bins as the candidates (Sec. III-A)
+    SM_TRY(tm.begin(SM_ST_FAST));
+    SM_HIP(launch_fast_score(L, stride, W, H, base + Lo.score, s));
+    SM_TRY(tm.end());
+    SM_TRY(tm.begin(SM_ST_FAST));
+    SM_HIP(launch_fast_select(base + Lo.score, W, H, *p, Sd, nullptr, s));
+    SM_TRY(tm.end());
+  }
+
+  // S_1 = SparseStereo(I_l, I_r) over the candidates; the count lands in the slot
   // after the candidates so that one copy brings both back
   SM_TRY(tm.begin(SM_ST_MATCH));
   SM_HIP(launch_match(cL, cR, W, H, *p, Sd, Lo.n_grid, s));

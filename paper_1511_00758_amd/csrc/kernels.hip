@@ -170,6 +170,208 @@ __global__ void k_list_slots(const int16_t* uv, int n, sm_support* slots) {
 }
 
 // ------------------------------------------------------------------------------------
+// FAST support keypoints sampled from spatial bins (Sec. III-A).
+//  * k_fast_score: one thread per pixel; the 16 ring differences d_k = I(ring_k) - I(p)
+//    are reduced to the minimum (and maximum) over every arc of 9 by doubling windows
+//    (2, 4, 8, then one more element), score = max over arcs of max(min d, -max d), >= 0.
+//  * k_fast_select: one workgroup per bin. Pass 1 applies the 3x3 suppression and
+//    builds a score histogram of the bin's keypoints; the threshold score s* of the
+//    per_bin-th best keypoint and the number of keypoints at s* still to take follow
+//    from it. Pass 2 walks the bin in raster order in 256-pixel chunks and emits the
+//    keypoints above s* and the first ones at s*, with block prefix sums (wave ballots)
+//    for ranks and output positions, so the output is in raster order.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fast_score(const uint8_t* img, int stride, int W, int H,
+                                                    uint8_t* score) {
+  const int u = blockIdx.x * kWave + (threadIdx.x & (kWave - 1));
+  const int v = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (u >= W || v >= H) return;
+  int best = 0;
+  if (u >= 3 && v >= 3 && u <= W - 4 && v <= H - 4) {
+    // radius-3 Bresenham ring, clockwise from the pixel straight above p
+    constexpr int kDx[16] = {0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3, -3, -3, -2, -1};
+    constexpr int kDy[16] = {-3, -3, -2, -1, 0, 1, 2, 3, 3, 3, 2, 1, 0, -1, -2, -3};
+    const uint8_t* c = img + (size_t)v * stride + u;
+    const int ip = c[0];
+    int d[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) d[k] = (int)c[kDy[k] * stride + kDx[k]] - ip;
+    int lo2[16], hi2[16], lo4[16], hi4[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      lo2[k] = min(d[k], d[(k + 1) & 15]);
+      hi2[k] = max(d[k], d[(k + 1) & 15]);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      lo4[k] = min(lo2[k], lo2[(k + 2) & 15]);
+      hi4[k] = max(hi2[k], hi2[(k + 2) & 15]);
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int lo9 = min(min(lo4[k], lo4[(k + 4) & 15]), d[(k + 8) & 15]);  // arc k .. k+8
+      const int hi9 = max(max(hi4[k], hi4[(k + 4) & 15]), d[(k + 8) & 15]);
+      best = max(best, max(lo9, -hi9));
+    }
+  }
+  score[(size_t)v * W + u] = (uint8_t)best;
+}
+
+struct FastSelectArgs {
+  const uint8_t* score;
+  int32_t W, H, t, bins_x, bins_y, per_bin;
+  sm_support* slots;  // either: per_bin slots per bin, (u, v, kPending) / kRejected
+  int16_t* uv;        // or: per_bin (u, v) pairs per bin, (-1, -1) when empty
+};
+
+// 3x3 suppression: p (a corner, hence at least 3 px inside the image) is a keypoint when
+// earlier raster neighbours score lower and later ones do not score higher.
+__device__ __forceinline__ bool fast_keypoint(const uint8_t* score, int W, int u, int v, int sc, int t) {
+  if (sc <= t) return false;
+  const uint8_t* c = score + (size_t)v * W + u;
+  return c[-W - 1] < sc && c[-W] < sc && c[-W + 1] < sc && c[-1] < sc && c[1] <= sc &&
+         c[W - 1] <= sc && c[W] <= sc && c[W + 1] <= sc;
+}
+
+// Exclusive prefix of `flag` over the 256 threads of the block in thread order, and the
+// block total (4 waves, one LDS slot per wave).
+__device__ __forceinline__ int block_prefix(bool flag, int* wsum, int& total) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  const unsigned long long m = __ballot(flag);
+  const int pre = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) wsum[w] = __popcll(m);
+  __syncthreads();
+  int before = 0;
+  total = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    before += k < w ? wsum[k] : 0;
+    total += wsum[k];
+  }
+  __syncthreads();  // wsum is reused by the next call
+  return before + pre;
+}
+
+__global__ __launch_bounds__(256) void k_fast_select(FastSelectArgs a) {
+  __shared__ int hist[256];
+  __shared__ int wsum[4];
+  __shared__ int s_thr, s_take;
+  const int b = blockIdx.x;
+  const int by = b / a.bins_x, bx = b - by * a.bins_x;
+  // pixels with floor(u * bins_x / W) == bx: u in [ceil(bx W / bins_x), ceil((bx+1) W / bins_x))
+  const int u0 = (int)(((int64_t)bx * a.W + a.bins_x - 1) / a.bins_x);
+  const int u1 = (int)(((int64_t)(bx + 1) * a.W + a.bins_x - 1) / a.bins_x);
+  const int v0 = (int)(((int64_t)by * a.H + a.bins_y - 1) / a.bins_y);
+  const int v1 = (int)(((int64_t)(by + 1) * a.H + a.bins_y - 1) / a.bins_y);
+  const int bw = max(u1 - u0, 0), n = bw * max(v1 - v0, 0);
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const int v = v0 + i / bw, u = u0 + i % bw;
+    const int sc = a.score[(size_t)v * a.W + u];
+    if (fast_keypoint(a.score, a.W, u, v, sc, a.t)) atomicAdd(&hist[sc], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int cum = 0, thr = 0, take = 0;  // default: every keypoint (score >= 1 > 0) is kept
+    for (int sc = 255; sc >= 1; --sc) {
+      if (cum + hist[sc] >= a.per_bin) {
+        thr = sc;
+        take = a.per_bin - cum;
+        break;
+      }
+      cum += hist[sc];
+    }
+    s_thr = thr;
+    s_take = take;
+  }
+  __syncthreads();
+  const int thr = s_thr, take = s_take;
+  const size_t out0 = (size_t)b * a.per_bin;
+  int base_eq = 0, base_sel = 0;
+  for (int start = 0; start < n; start += 256) {  // uniform trip count over the block
+    const int i = start + threadIdx.x;
+    int u = 0, v = 0, sc = 0;
+    bool kp = false;
+    if (i < n) {
+      v = v0 + i / bw;
+      u = u0 + i % bw;
+      sc = a.score[(size_t)v * a.W + u];
+      kp = fast_keypoint(a.score, a.W, u, v, sc, a.t);
+    }
+    const bool eq = kp && sc == thr;
+    int n_eq, n_sel;
+    const int rank = base_eq + block_prefix(eq, wsum, n_eq);
+    const bool sel = kp && (sc > thr || (eq && rank < take));
+    const int pos = base_sel + block_prefix(sel, wsum, n_sel);
+    if (sel) {
+      if (a.slots) {
+        sm_support sp;
+        sp.u = (int16_t)u;
+        sp.v = (int16_t)v;
+        sp.d = kPending;
+        a.slots[out0 + pos] = sp;
+      } else {
+        a.uv[2 * (out0 + pos)] = (int16_t)u;
+        a.uv[2 * (out0 + pos) + 1] = (int16_t)v;
+      }
+    }
+    base_eq += n_eq;
+    base_sel += n_sel;
+  }
+  for (int j = base_sel + threadIdx.x; j < a.per_bin; j += 256) {  // empty slots
+    if (a.slots) {
+      sm_support sp;
+      sp.u = 0;
+      sp.v = 0;
+      sp.d = kRejected;
+      a.slots[out0 + j] = sp;
+    } else {
+      a.uv[2 * (out0 + j)] = -1;
+      a.uv[2 * (out0 + j) + 1] = -1;
+    }
+  }
+}
+
+// Order-preserving in-place compaction of (u, v) pairs with u >= 0 (one workgroup).
+__global__ __launch_bounds__(1024) void k_compact_uv(int16_t* uv, int n, int* n_out) {
+  __shared__ int wsum[16];
+  __shared__ int wofs[16];
+  __shared__ int total;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  int base = 0;
+  for (int start = 0; start < n; start += 1024) {
+    const int i = start + threadIdx.x;
+    int16_t u = -1, v = -1;
+    if (i < n) {
+      u = uv[2 * i];
+      v = uv[2 * i + 1];
+    }
+    const bool keep = u >= 0;
+    const unsigned long long m = __ballot(keep);
+    const int pre = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[w] = __popcll(m);
+    __syncthreads();  // every read of this chunk happened before any write below
+    if (threadIdx.x == 0) {
+      int acc = 0;
+      for (int k = 0; k < 16; ++k) {
+        wofs[k] = acc;
+        acc += wsum[k];
+      }
+      total = acc;
+    }
+    __syncthreads();
+    if (keep) {
+      uv[2 * (base + wofs[w] + pre)] = u;
+      uv[2 * (base + wofs[w] + pre) + 1] = v;
+    }
+    base += total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *n_out = base;
+}
+
+// ------------------------------------------------------------------------------------
 // Epipolar matching: one wave per candidate, lanes over disparities (up to 4 chunks of
 // 64), wave-shuffle argmin over packed (cost << 8 | d) keys.
 // ------------------------------------------------------------------------------------
@@ -522,7 +724,7 @@ struct ValidateArgs {
   const uint64_t* cR;
   const uint8_t* omega;
   const float* D_it;
-  int32_t W, H, rx, d_min, d_max, t_lo, t_hi;
+  int32_t W, H, rx, d_min, d_max, t_lo, t_hi, levels;
   int32_t sz, Wc, Hc, cpr, TW, TH, crows;
   uint64_t ginit, binit;
   uint8_t* C_it;
@@ -586,6 +788,15 @@ __global__ __launch_bounds__(kWave * NW, 8) void k_validate(ValidateArgs a) {
       for (int k = 0; k < 2; ++k) {
         if (!in[k]) continue;
         cost[k] = dd[k] >= 0 ? (uint32_t)__popcll(wl[k] ^ wr[k]) : 0xffu;
+        if (a.levels > 1 && dd[k] >= 0) {  // neighbouring levels d -+ 1 .. (L-1)/2
+          for (int dl = 1; dl <= (a.levels - 1) >> 1; ++dl) {
+            const int dm = dd[k] - dl, dp = dd[k] + dl;
+            if (dm >= a.d_min)
+              cost[k] = min(cost[k], (uint32_t)__popcll(wl[k] ^ a.cR[idx[k] - dm]));
+            if (dp <= a.d_max && u - dp >= a.rx)
+              cost[k] = min(cost[k], (uint32_t)__popcll(wl[k] ^ a.cR[idx[k] - dp]));
+          }
+        }
         const uint32_t i = idx[k];
         if (a.C_it) a.C_it[i] = (uint8_t)cost[k];
         uint32_t cfk = cf[k];
@@ -717,6 +928,34 @@ hipError_t launch_grid_slots(const uint8_t* omega, int32_t W, int32_t H, int32_t
   return hipGetLastError();
 }
 
+hipError_t launch_fast_score(const uint8_t* img, int32_t stride, int32_t W, int32_t H, uint8_t* score,
+                             hipStream_t s) {
+  SM_LAUNCH(k_fast_score, dim3(blocks_for(W, kWave), blocks_for(H, 4)), dim3(256), 0, s, img, stride, W, H,
+            score);
+  return hipGetLastError();
+}
+
+hipError_t launch_fast_select(const uint8_t* score, int32_t W, int32_t H, const sm_params& p,
+                              sm_support* slots, int16_t* uv, hipStream_t s) {
+  FastSelectArgs a;
+  a.score = score;
+  a.W = W;
+  a.H = H;
+  a.t = p.fast_threshold;
+  a.bins_x = p.fast_bins_x;
+  a.bins_y = p.fast_bins_y;
+  a.per_bin = p.fast_per_bin;
+  a.slots = slots;
+  a.uv = uv;
+  SM_LAUNCH(k_fast_select, dim3((unsigned)(p.fast_bins_x * p.fast_bins_y)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_uv(int16_t* uv, int32_t n, int32_t* n_out, hipStream_t s) {
+  SM_LAUNCH(k_compact_uv, dim3(1), dim3(1024), 0, s, uv, n, n_out);
+  return hipGetLastError();
+}
+
 hipError_t launch_list_slots(const int16_t* uv, int32_t n, sm_support* slots, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   SM_LAUNCH(k_list_slots, dim3(blocks_for(n, 256)), dim3(256), 0, s, uv, n, slots);
@@ -790,6 +1029,7 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
   a.d_max = p.d_max;
   a.t_lo = p.t_lo;
   a.t_hi = p.t_hi;
+  a.levels = p.levels;
   a.sz = sz;
   a.Wc = (W + sz - 1) / sz;
   a.Hc = (H + sz - 1) / sz;

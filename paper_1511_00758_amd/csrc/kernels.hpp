@@ -47,6 +47,16 @@ hipError_t launch_grid_slots(const uint8_t* omega, int32_t W, int32_t H, int32_t
                              sm_support* slots, int32_t n, hipStream_t s);
 hipError_t launch_list_slots(const int16_t* uv, int32_t n, sm_support* slots, hipStream_t s);
 
+// FAST keypoints from spatial bins: the score of every pixel, then per bin the kept
+// keypoints, per_bin slots per bin (bins row-major, raster order inside a bin). Output
+// either as candidate slots (empty ones kRejected) or as (u, v) pairs (empty (-1, -1)),
+// which launch_compact_uv packs in order.
+hipError_t launch_fast_score(const uint8_t* img, int32_t stride, int32_t W, int32_t H, uint8_t* score,
+                             hipStream_t s);
+hipError_t launch_fast_select(const uint8_t* score, int32_t W, int32_t H, const sm_params& p,
+                              sm_support* slots, int16_t* uv, hipStream_t s);
+hipError_t launch_compact_uv(int16_t* uv, int32_t n, int32_t* n_out, hipStream_t s);
+
 // Epipolar matching with left-right check of every pending slot, in place.
 hipError_t launch_match(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
                         const sm_params& p, sm_support* slots, int32_t n, hipStream_t s);

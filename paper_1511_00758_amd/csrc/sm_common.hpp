@@ -40,6 +40,12 @@ inline bool census_ok(int32_t cw, int32_t ch) {
 }
 
 sm_status check_params(const sm_params* p);
+sm_status check_fast_params(const sm_params* p);
+
+// Candidate slots of the FAST detector: fast_per_bin per bin.
+inline int64_t fast_slots(const sm_params& p) {
+  return (int64_t)p.fast_bins_x * p.fast_bins_y * p.fast_per_bin;
+}
 
 inline int32_t occ_size(const sm_params& p, int it) {  // it is 1-based
   int32_t sz = p.sz_occ0;

@@ -105,7 +105,12 @@ FAKE = 0x10000  # never dereferenced: every call below fails argument checks fir
 @pytest.mark.parametrize("kw", [dict(d_min=5, d_max=4), dict(d_max=256), dict(census_w=4),
                                 dict(census_w=9, census_h=9), dict(n_iters=0), dict(n_iters=9),
                                 dict(t_lo=9), dict(t_hi=65), dict(support_step=0),
-                                dict(sz_occ0=0), dict(grad_thr=-1), dict(uniqueness=-1)])
+                                dict(sz_occ0=0), dict(grad_thr=-1), dict(uniqueness=-1),
+                                dict(levels=2), dict(levels=0), dict(levels=7), dict(support_mode=2),
+                                dict(support_mode=1, fast_threshold=255),
+                                dict(support_mode=1, fast_bins_x=0), dict(support_mode=1, fast_bins_y=1025),
+                                dict(support_mode=1, fast_per_bin=0),
+                                dict(support_mode=1, fast_bins_x=1024, fast_bins_y=1024, fast_per_bin=8)])
 def test_bad_params_rejected(kw):
     L = _lib.load()
     p = _params(**kw)
@@ -136,3 +141,25 @@ def test_bad_sizes_and_pointers_rejected():
     assert ws > 64 * 48 * 22
     assert L.sm_solve(FAKE, FAKE, 64, 48, 64, p, FAKE, ws - 1, FAKE, FAKE, FAKE, None, None) == _lib.SM_ERR_CAPACITY
     assert L.sm_solve(FAKE, FAKE, 64, 48, 64, p, FAKE + 8, ws, FAKE, FAKE, FAKE, None, None) == _lib.SM_ERR_ARG
+
+
+def test_fast_candidates_rejects_bad_arguments():
+    L = _lib.load()
+    p = _params(fast_bins_x=4, fast_bins_y=3, fast_per_bin=5)
+    n = 4 * 3 * 5
+    ok = L.sm_fast_candidates
+    assert ok(FAKE, 64, 48, 64, p, FAKE, FAKE, n - 1, FAKE, None) == _lib.SM_ERR_CAPACITY
+    assert ok(FAKE, 64, 48, 63, p, FAKE, FAKE, n, FAKE, None) == _lib.SM_ERR_ARG      # stride < W
+    assert ok(None, 64, 48, 64, p, FAKE, FAKE, n, FAKE, None) == _lib.SM_ERR_ARG
+    assert ok(FAKE, 64, 48, 64, p, None, FAKE, n, FAKE, None) == _lib.SM_ERR_ARG      # score scratch
+    assert ok(FAKE, 2, 48, 64, p, FAKE, FAKE, n, FAKE, None) == _lib.SM_ERR_ARG
+    assert ok(FAKE, 64, 48, 64, _params(fast_threshold=300), FAKE, FAKE, n, FAKE, None) == _lib.SM_ERR_ARG
+    assert L.sm_last_error()
+
+
+def test_fast_mode_workspace_holds_the_bin_slots_and_scores():
+    L = _lib.load()
+    grid = L.sm_solve_workspace_bytes(640, 480, _params())
+    fast = L.sm_solve_workspace_bytes(640, 480, _params(support_mode=1, fast_per_bin=400))
+    # 12 x 10 bins x 400 slots of 8 bytes (vs 3072 grid slots) plus 1 B/px of scores
+    assert fast - grid >= 640 * 480 + (120 * 400 - 3072) * 8
