@@ -185,13 +185,54 @@ def roofline_probe(api, params, W=7680, H=4320, reps=20, dev="cuda:0"):
     t_fill = timed(fill_only)
     t_interp = timed(interp)  # leaves the interpolated D in place for the validation
     t_valid = timed(valid, before=lambda: C_f.fill_(params["t_hi"]))
-    out = {"interpolate": entry(t_interp, 4.0, None), "nan_fill": entry(t_fill, 4.0, "nan_fill"),
+    fast_prm = dict(params, support_mode=1)
+
+    def fast():
+        api.fast_candidates(L, fast_prm, stream=stream)
+
+    t_fast = timed(fast)
+    out = {"fast_candidates": entry(t_fast, 2.0, None),
+           "interpolate": entry(t_interp, 4.0, None), "nan_fill": entry(t_fill, 4.0, "nan_fill"),
            "raster": entry(max(t_interp - t_fill, 1e-3), 4.0, "raster"),
            "validate": entry(t_valid, 27.0, "validate")}
+    out["fast_candidates"]["note"] = ("sm_fast_candidates, 12 x 10 bins, <= 25 per bin: score "
+                                      "(1 B read + 1 B written per px) + bin selection + compaction")
     out["interpolate"]["note"] = "sm_interpolate = NaN fill (4 B/px) + rasterisation"
     out["raster"]["note"] = ("rasteriser alone: sm_interpolate minus a call with no triangles "
                              "(NaN fill only); every pixel of this frame is covered")
     out["frame"] = f"{W}x{H}, {n_s} supports, {n_t} triangles, cells {sz}x{sz}"
+    return out
+
+
+def variant_runs(api, dframes, params, W, H, steps=100, warmup=10, dev="cuda:0"):
+    """The paper variants on the 640x480 workload, plain per-frame path: FAST supports
+    from 12 x 10 bins (threshold 16, at most 25 per bin) instead of the 10 px grid, and
+    3-level cost evaluation, alone and together."""
+    import numpy as np
+    import torch
+    out = {}
+    for name, over in (("fast_supports", dict(support_mode=1)), ("levels3", dict(levels=3)),
+                       ("fast_supports_levels3", dict(support_mode=1, levels=3))):
+        prm = dict(params, **over)
+        solver = api.Solver(W, H, prm, device=dev)
+        for k in range(warmup):
+            solver(*dframes[k % len(dframes)], stats=True, timing=True)
+        torch.cuda.synchronize()
+        acc, cnt, n_valid, n_sup = {}, {}, 0, 0
+        t0 = time.perf_counter()
+        for k in range(steps):
+            st = solver(*dframes[k % len(dframes)], stats=True, timing=True).stats
+            n_valid += st["n_valid"]
+            n_sup += st["n_support"][0]
+            for kname in ("fast", "validate", "match"):
+                acc[kname] = acc.get(kname, 0.0) + st["stage_us"][kname]
+                cnt[kname] = cnt.get(kname, 0) + st["stage_launches"][kname]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"frames_per_s": round(steps / dt, 2), "mpx_per_s": round(steps * W * H / dt / 1e6, 2),
+                     "semi_dense_mpx_per_s": round(n_valid / dt / 1e6, 2),
+                     "initial_supports_per_frame": round(n_sup / steps, 1),
+                     "kernel_us_per_frame": {k: round(acc[k] / steps, 2) for k in acc if cnt[k]}}
     return out
 
 
@@ -329,6 +370,8 @@ def main():
                     help="skip the batched (sm_solve_batch) throughput runs")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the 7680x4320 interpolation/validation roofline probe")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the FAST-support / 3-level variants of the 640x480 workload")
     ap.add_argument("--probe-only", action="store_true",
                     help="only run the 7680x4320 roofline probe")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -425,6 +468,7 @@ def main():
         torch.cuda.synchronize()
         gpu_results.append((rr.D_f.cpu().numpy(), rr.C_f.cpu().numpy(), rr.mask.cpu().numpy()))
     probe = None if args.no_probe else roofline_probe(api, params)
+    variants = None if args.no_variants else variant_runs(api, dframes, params, W, H)
     batched = None if args.no_batch else batched_runs(api, frames, params)
     serving = None if args.no_serve else serving_run(api, seconds=args.serve_seconds)
     cpu = None
@@ -461,6 +505,7 @@ def main():
         "roofline": roof,
         "roofline_validate": roof_val,
         "roofline_probe_7680x4320": probe,
+        "paper_variants": variants,
         "batched": batched,
         "serving_16_streams": serving,
         "cpu_baseline": cpu,

@@ -174,12 +174,13 @@ __global__ void k_list_slots(const int16_t* uv, int n, sm_support* slots) {
 //  * k_fast_score: one thread per pixel; the 16 ring differences d_k = I(ring_k) - I(p)
 //    are reduced to the minimum (and maximum) over every arc of 9 by doubling windows
 //    (2, 4, 8, then one more element), score = max over arcs of max(min d, -max d), >= 0.
-//  * k_fast_select: one workgroup per bin. Pass 1 applies the 3x3 suppression and
-//    builds a score histogram of the bin's keypoints; the threshold score s* of the
-//    per_bin-th best keypoint and the number of keypoints at s* still to take follow
-//    from it. Pass 2 walks the bin in raster order in 256-pixel chunks and emits the
-//    keypoints above s* and the first ones at s*, with block prefix sums (wave ballots)
-//    for ranks and output positions, so the output is in raster order.
+//  * k_fast_select: one 1024-thread workgroup per bin. Pass 1 applies the 3x3
+//    suppression and builds a score histogram of the bin's keypoints; the threshold
+//    score s* of the per_bin-th best keypoint and the number of keypoints at s* to take
+//    follow from it. Pass 2 walks the bin in raster order in 1024-pixel chunks (stopping
+//    once the bin is full) and emits the keypoints above s* and the first ones at s*,
+//    with block prefix sums (wave ballots) for ranks and output positions, so the
+//    output is in raster order.
 // ------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_fast_score(const uint8_t* img, int stride, int W, int H,
                                                     uint8_t* score) {
@@ -233,28 +234,35 @@ __device__ __forceinline__ bool fast_keypoint(const uint8_t* score, int W, int u
          c[W - 1] <= sc && c[W] <= sc && c[W + 1] <= sc;
 }
 
-// Exclusive prefix of `flag` over the 256 threads of the block in thread order, and the
-// block total (4 waves, one LDS slot per wave).
-__device__ __forceinline__ int block_prefix(bool flag, int* wsum, int& total) {
+constexpr int kFastThreads = 1024, kFastWaves = kFastThreads / kWave;
+
+// Exclusive prefixes of two flags over the block's threads in thread order, and their
+// block totals (one LDS slot per wave and flag, one barrier pair for both).
+__device__ __forceinline__ void block_prefix2(bool f0, bool f1, int2* wsum, int& p0, int& p1, int& t0,
+                                              int& t1) {
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
-  const unsigned long long m = __ballot(flag);
-  const int pre = __popcll(m & ((1ull << lane) - 1ull));
-  if (lane == 0) wsum[w] = __popcll(m);
+  const unsigned long long m0 = __ballot(f0), m1 = __ballot(f1);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  if (lane == 0) wsum[w] = make_int2(__popcll(m0), __popcll(m1));
   __syncthreads();
-  int before = 0;
-  total = 0;
+  int b0 = 0, b1 = 0;
+  t0 = t1 = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    before += k < w ? wsum[k] : 0;
-    total += wsum[k];
+  for (int k = 0; k < kFastWaves; ++k) {
+    const int2 c = wsum[k];
+    b0 += k < w ? c.x : 0;
+    b1 += k < w ? c.y : 0;
+    t0 += c.x;
+    t1 += c.y;
   }
   __syncthreads();  // wsum is reused by the next call
-  return before + pre;
+  p0 = b0 + __popcll(m0 & below);
+  p1 = b1 + __popcll(m1 & below);
 }
 
-__global__ __launch_bounds__(256) void k_fast_select(FastSelectArgs a) {
+__global__ __launch_bounds__(kFastThreads) void k_fast_select(FastSelectArgs a) {
   __shared__ int hist[256];
-  __shared__ int wsum[4];
+  __shared__ int2 wsum[kFastWaves];
   __shared__ int s_thr, s_take;
   const int b = blockIdx.x;
   const int by = b / a.bins_x, bx = b - by * a.bins_x;
@@ -264,32 +272,48 @@ __global__ __launch_bounds__(256) void k_fast_select(FastSelectArgs a) {
   const int v0 = (int)(((int64_t)by * a.H + a.bins_y - 1) / a.bins_y);
   const int v1 = (int)(((int64_t)(by + 1) * a.H + a.bins_y - 1) / a.bins_y);
   const int bw = max(u1 - u0, 0), n = bw * max(v1 - v0, 0);
-  hist[threadIdx.x] = 0;
+  if (threadIdx.x < 256) hist[threadIdx.x] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += 256) {
+  for (int i = threadIdx.x; i < n; i += kFastThreads) {
     const int v = v0 + i / bw, u = u0 + i % bw;
     const int sc = a.score[(size_t)v * a.W + u];
     if (fast_keypoint(a.score, a.W, u, v, sc, a.t)) atomicAdd(&hist[sc], 1);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int cum = 0, thr = 0, take = 0;  // default: every keypoint (score >= 1 > 0) is kept
-    for (int sc = 255; sc >= 1; --sc) {
-      if (cum + hist[sc] >= a.per_bin) {
-        thr = sc;
-        take = a.per_bin - cum;
-        break;
-      }
-      cum += hist[sc];
+  __syncthreads();  // histogram complete
+  if (threadIdx.x == 0) {  // default: every keypoint (score >= 1 > 0) is kept
+    s_thr = 0;
+    s_take = 0;
+  }
+  // at_least = number of keypoints scoring >= sc, for sc = 255 - threadIdx.x: an
+  // inclusive scan over the histogram read backwards (4 waves of shuffles + LDS)
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+  const int sc_t = 255 - threadIdx.x;
+  int h = 0, at_least = 0;
+  if (threadIdx.x < 256) {
+    h = hist[sc_t];
+    at_least = h;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const int o = __shfl_up(at_least, off, kWave);
+      if (lane >= off) at_least += o;
     }
-    s_thr = thr;
-    s_take = take;
+    if (lane == kWave - 1) wsum[w] = make_int2(at_least, 0);
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    for (int k = 0; k < w; ++k) at_least += wsum[k].x;
+    // the score of the per_bin-th best keypoint: the only sc with
+    // at_least(sc + 1) < per_bin <= at_least(sc)
+    if (at_least >= a.per_bin && at_least - h < a.per_bin) {
+      s_thr = sc_t;
+      s_take = a.per_bin - (at_least - h);
+    }
   }
   __syncthreads();
   const int thr = s_thr, take = s_take;
   const size_t out0 = (size_t)b * a.per_bin;
   int base_eq = 0, base_sel = 0;
-  for (int start = 0; start < n; start += 256) {  // uniform trip count over the block
+  for (int start = 0; start < n && base_sel < a.per_bin; start += kFastThreads) {  // block-uniform
     const int i = start + threadIdx.x;
     int u = 0, v = 0, sc = 0;
     bool kp = false;
@@ -299,11 +323,17 @@ __global__ __launch_bounds__(256) void k_fast_select(FastSelectArgs a) {
       sc = a.score[(size_t)v * a.W + u];
       kp = fast_keypoint(a.score, a.W, u, v, sc, a.t);
     }
-    const bool eq = kp && sc == thr;
-    int n_eq, n_sel;
-    const int rank = base_eq + block_prefix(eq, wsum, n_eq);
-    const bool sel = kp && (sc > thr || (eq && rank < take));
-    const int pos = base_sel + block_prefix(sel, wsum, n_sel);
+    // keypoints above the threshold are all kept; at the threshold, the first `take` in
+    // raster order (their rank needs the prefix of the at-threshold flags)
+    const bool above = kp && sc > thr, eq = kp && sc == thr;
+    int p_above, p_eq, n_above, n_eq;
+    block_prefix2(above, eq, wsum, p_above, p_eq, n_above, n_eq);
+    const int rank = base_eq + p_eq;
+    const bool eq_sel = eq && rank < take;
+    // output position: kept keypoints before this one in raster order
+    const int eq_before = min(max(take - base_eq, 0), p_eq);  // kept at-threshold ones before i
+    const bool sel = above || eq_sel;
+    const int pos = base_sel + p_above + eq_before;
     if (sel) {
       if (a.slots) {
         sm_support sp;
@@ -316,10 +346,10 @@ __global__ __launch_bounds__(256) void k_fast_select(FastSelectArgs a) {
         a.uv[2 * (out0 + pos) + 1] = (int16_t)v;
       }
     }
+    base_sel += n_above + min(max(take - base_eq, 0), n_eq);
     base_eq += n_eq;
-    base_sel += n_sel;
   }
-  for (int j = base_sel + threadIdx.x; j < a.per_bin; j += 256) {  // empty slots
+  for (int j = base_sel + threadIdx.x; j < a.per_bin; j += kFastThreads) {  // empty slots
     if (a.slots) {
       sm_support sp;
       sp.u = 0;
@@ -947,7 +977,7 @@ hipError_t launch_fast_select(const uint8_t* score, int32_t W, int32_t H, const 
   a.per_bin = p.fast_per_bin;
   a.slots = slots;
   a.uv = uv;
-  SM_LAUNCH(k_fast_select, dim3((unsigned)(p.fast_bins_x * p.fast_bins_y)), dim3(256), 0, s, a);
+  SM_LAUNCH(k_fast_select, dim3((unsigned)(p.fast_bins_x * p.fast_bins_y)), dim3(kFastThreads), 0, s, a);
   return hipGetLastError();
 }
 
