@@ -237,7 +237,8 @@ def variant_runs(api, dframes, params, W, H, steps=100, warmup=10, dev="cuda:0")
 
 
 def batched_runs(api, vga_frames, vga_params, workers=16, batches=12, dev="cuda:0"):
-    """Throughput of sm_solve_batch: (a) the 640x480 workload in batches of 64 frames,
+    """Throughput of sm_solve_batch (concurrent per-frame solves) and sm_solve_many (one
+    launch per stage over the batch): (a) the 640x480 workload in batches of 64 frames,
     (b) the mixed batch of 64 pairs (16 each of 320x240, 640x480, 1242x375, 1280x720,
     disparity ranges cycling 64/128/192/256; two distinct scenes per size, cycled)."""
     import numpy as np
@@ -280,6 +281,29 @@ def batched_runs(api, vga_frames, vga_params, workers=16, batches=12, dev="cuda:
     mixed = [base[2 * (i % 4) + (i // 4) % 2] for i in range(64)]
     out["batch64_mixed"] = run(mixed, [b[2] for b in base], 1280, 720, batches)
     out["batch64_mixed"]["sizes"] = "16 each of 320x240, 640x480, 1242x375, 1280x720"
+
+    def run_many(frames, n_batches):
+        ms = api.ManySolver(workers, device=dev)
+        outs = ms(frames)  # warm-up (workspace, staging, worker threads)
+        torch.cuda.synchronize()
+        acc = {}
+        t0 = time.perf_counter()
+        for _ in range(n_batches):
+            outs, st = ms(frames, outputs=outs, stats=True, timing=True)
+            for k, v in st["stage_us"].items():
+                acc[k] = acc.get(k, 0.0) + v
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        npx = sum(int(f[0].numel()) for f in frames)
+        return {"frames_per_s": round(n_batches * len(frames) / dt, 1),
+                "mpx_per_s": round(n_batches * npx / dt / 1e6, 2),
+                "ms_per_batch": round(dt / n_batches * 1e3, 3),
+                "frames_per_batch": len(frames), "host_threads": workers,
+                "us_per_batch": {k: round(v / n_batches, 1) for k, v in acc.items() if v > 0}}
+
+    # stage-batched: one launch per stage over the 64 frames (sm_solve_many)
+    out["vga_20planes_batch64_stage_batched"] = run_many(vga, batches)
+    out["batch64_mixed_stage_batched"] = run_many(mixed, batches)
     return out
 
 

@@ -301,6 +301,24 @@ typedef struct {
 sm_status sm_solve_batch(sm_frame* frames, int32_t n, void* const* streams, void* const* ws,
                          const size_t* ws_bytes, int32_t n_workers, sm_stats* st);
 
+/*
+ * sm_solve_many -- Alg. 1 on many independent frames at once, stage by stage: each
+ *   stage (census, matching, compaction, rasterisation, validation, resampling) is one
+ *   kernel launch over all frames, which may differ in size and parameters; between the
+ *   stages that need them, the frames' triangulations run on n_threads host workers.
+ *   Every frame's D_f, C_f and mask are bit-identical to its own sm_solve. Frames must
+ *   use the support grid (p.support_mode = 0). Frames with fewer iterations drop out of
+ *   the later launches.
+ *   frames   [host] [n] frames (status, worker = 0 and latency_us = whole call are written).
+ *   ws       one workspace of ws_bytes >= sm_solve_many_workspace_bytes(frames, n),
+ *            256-byte aligned, holding every frame's buffers and the batch staging.
+ *   st       [host] statistics summed over frames (one launch counted per stage launch).
+ *   Synchronises `stream` once per triangulation round (max n_iters times).
+ */
+size_t sm_solve_many_workspace_bytes(const sm_frame* frames /* [host] */, int32_t n);
+sm_status sm_solve_many(sm_frame* frames /* [host] */, int32_t n, void* ws, size_t ws_bytes,
+                        int32_t n_threads, sm_stats* st /* [host] */, void* stream);
+
 /* Message of the calling thread's last non-OK status ("" if none). */
 const char* sm_last_error(void);
 

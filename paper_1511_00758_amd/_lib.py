@@ -55,7 +55,8 @@ class SmFrame(ctypes.Structure):
 
 EXPORTS = ("sm_census", "sm_match_support", "sm_grid_candidates", "sm_fast_candidates", "sm_triangulate",
            "sm_interpolate", "sm_cells", "sm_validate", "sm_resample",
-           "sm_solve_workspace_bytes", "sm_solve", "sm_solve_batch", "sm_last_error", "sm_version")
+           "sm_solve_workspace_bytes", "sm_solve", "sm_solve_batch", "sm_solve_many_workspace_bytes",
+           "sm_solve_many", "sm_last_error", "sm_version")
 
 
 class StereoMeshError(RuntimeError):
@@ -96,6 +97,8 @@ def load():
                              c_vp, c_vp, P(SmStats), c_vp]),
         "sm_solve_batch": (c_i32, [P(SmFrame), c_i32, P(c_vp), P(c_vp), P(c_size), c_i32,
                                    P(SmStats)]),
+        "sm_solve_many_workspace_bytes": (c_size, [P(SmFrame), c_i32]),
+        "sm_solve_many": (c_i32, [P(SmFrame), c_i32, c_vp, c_size, c_i32, P(SmStats), c_vp]),
         "sm_last_error": (ctypes.c_char_p, []),
         "sm_version": (ctypes.c_char_p, []),
     }

@@ -300,3 +300,55 @@ class BatchSolver:
             return outs
         per = [(int(arr[i].worker), float(arr[i].latency_us)) for i in range(n)]
         return outs, stats_dict(st, 8), per
+
+
+class ManySolver:
+    """Many frames (sizes and parameters may differ) solved stage by stage by
+    ``sm_solve_many``: one launch per stage over all frames, host triangulations on
+    ``n_threads`` workers. The workspace grows to the largest batch seen."""
+
+    def __init__(self, n_threads: int = 16, device="cuda"):
+        self.n_threads = n_threads
+        self.device = device
+        self.ws = None
+        self.ws_bytes = 0
+
+    def _frames(self, frames, outs):
+        n = len(frames)
+        arr = (_lib.SmFrame * max(n, 1))()
+        for i, ((l, r, prm), (D, C, M)) in enumerate(zip(frames, outs)):
+            _require_cuda(l, r, D, C, M)
+            H, W = l.shape
+            if r.shape != l.shape or r.stride(0) != l.stride(0):
+                raise ValueError("left and right must have the same shape and pitch")
+            f = arr[i]
+            f.L, f.R, f.W, f.H, f.stride = l.data_ptr(), r.data_ptr(), W, H, l.stride(0)
+            f.p = make_params(prm)
+            f.D_f, f.C_f, f.mask = D.data_ptr(), C.data_ptr(), M.data_ptr()
+        return arr
+
+    def __call__(self, frames, outputs=None, stats=False, timing=False, stream=None):
+        """frames: list of (left, right, params) with uint8 [H, W] CUDA tensors. Returns a
+        list of (D_f, C_f, mask) and, with ``stats``, the summed statistics."""
+        n = len(frames)
+        outs = outputs
+        if outs is None:
+            outs = [(torch.empty(l.shape, dtype=torch.float32, device=l.device),
+                     torch.empty(l.shape, dtype=torch.uint8, device=l.device),
+                     torch.empty(l.shape, dtype=torch.uint8, device=l.device)) for (l, _, _) in frames]
+        arr = self._frames(frames, outs)
+        L = _lib.load()
+        need = L.sm_solve_many_workspace_bytes(arr, n) if n else 0
+        if n and need == 0:
+            raise ValueError("invalid frame sizes or parameters: " + L.sm_last_error().decode(errors="replace"))
+        if need > self.ws_bytes:
+            self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+            self.ws_bytes = need
+        ptr = self.ws.data_ptr() + ((-self.ws.data_ptr()) % 256) if self.ws is not None else None
+        st = _lib.SmStats()
+        st.timing = 1 if timing else 0
+        check(L.sm_solve_many(arr, n, ptr, self.ws_bytes, self.n_threads,
+                              st if (stats or timing) else None, _stream(stream)))
+        if not (stats or timing):
+            return outs
+        return outs, stats_dict(st, 8)

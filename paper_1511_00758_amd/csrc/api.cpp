@@ -161,12 +161,13 @@ inline float us_since(clk::time_point t0) {
 }
 
 // Workspace layout of sm_solve (256-byte aligned sub-buffers).
-struct Layout {
-  size_t cL, cR, omega, occ, D_it, cell_g, cell_b, S, T, counters, score, total;
-  int32_t n_grid, S_cap, T_cap, cells_max;  // n_grid: initial candidate slots (grid or FAST)
-};
+sm_status check_image_args(int32_t W, int32_t H) {
+  if (!dims_ok(W, H)) return fail(SM_ERR_ARG, "image size %dx%d outside [3, 8192]^2", W, H);
+  return SM_OK;
+}
 
-inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+}  // namespace
+
 
 Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
   Layout L{};
@@ -199,12 +200,6 @@ Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
   return L;
 }
 
-sm_status check_image_args(int32_t W, int32_t H) {
-  if (!dims_ok(W, H)) return fail(SM_ERR_ARG, "image size %dx%d outside [3, 8192]^2", W, H);
-  return SM_OK;
-}
-
-}  // namespace
 }  // namespace sm
 
 using namespace sm;

@@ -8,11 +8,14 @@
 #include <condition_variable>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
 
+#include "delaunay.hpp"
+#include "kernels.hpp"
 #include "sm_common.hpp"
 #include "stereomesh.h"
 
@@ -175,5 +178,384 @@ extern "C" sm_status sm_solve_batch(sm_frame* frames, int32_t n, void* const* st
     }
   }
   if (first_bad >= 0) return fail(frames[first_bad].status, "frame %d: %s", first_bad, first_msg.c_str());
+  return SM_OK;
+}
+
+// =====================================================================================
+// sm_solve_many: stage-batched solve. Every stage of Alg. 1 is one launch over all
+// frames (mixed sizes and parameters); the host triangulations of the frames run on a
+// worker pool between the stages that need them.
+// =====================================================================================
+namespace sm {
+namespace {
+
+struct ManyPlan {
+  std::vector<Layout> lay;
+  std::vector<size_t> base;      // workspace offset of each frame
+  std::vector<int32_t> pack_off;  // staging slot offset of each frame (header + capacity)
+  std::vector<int32_t> pack_cap;
+  std::vector<int32_t> groups;   // distinct (rx << 8 | ry) census windows
+  size_t desc_off = 0, off_off = 0, tri_off = 0, pack_dev = 0, total = 0;
+  int32_t pack_slots = 0, tri_cap = 0, n_off_arrays = 0;
+};
+
+constexpr int kOffArrays = 5;  // match, raster, validate, rematch, + one per census group
+
+sm_status plan_many(const sm_frame* frames, int32_t n, ManyPlan& P) {
+  P = ManyPlan{};
+  size_t o = 0;
+  std::map<int32_t, int> grp;
+  for (int32_t f = 0; f < n; ++f) {
+    const sm_frame& fr = frames[f];
+    if (!dims_ok(fr.W, fr.H)) return fail(SM_ERR_ARG, "frame %d: size %dx%d outside [3, 8192]^2", f, fr.W, fr.H);
+    if (fr.stride < fr.W) return fail(SM_ERR_ARG, "frame %d: stride < W", f);
+    if (!fr.L || !fr.R || !fr.D_f || !fr.C_f || !fr.mask) return fail(SM_ERR_ARG, "frame %d: NULL buffer", f);
+    const sm_status ps = check_params(&fr.p);
+    if (ps != SM_OK) return fail(ps, "frame %d: %s", f, last_error().c_str());
+    if (fr.p.support_mode != 0)
+      return fail(SM_ERR_ARG, "frame %d: sm_solve_many takes grid supports only (support_mode 0)", f);
+    const Layout L = layout_of(fr.W, fr.H, fr.p);
+    P.lay.push_back(L);
+    P.base.push_back(o);
+    o = align256(o + L.total);
+    int32_t cap = L.n_grid;
+    for (int it = 1; it < fr.p.n_iters; ++it) cap = std::max(cap, 2 * cells_of(fr.W, fr.H, occ_size(fr.p, it)));
+    P.pack_off.push_back(P.pack_slots);
+    P.pack_cap.push_back(cap);
+    P.pack_slots += cap + 1;
+    P.tri_cap += L.T_cap;
+    const int32_t key = ((fr.p.census_w - 1) / 2) << 8 | ((fr.p.census_h - 1) / 2);
+    if (!grp.count(key)) {
+      grp[key] = (int)P.groups.size();
+      P.groups.push_back(key);
+    }
+  }
+  P.n_off_arrays = kOffArrays - 1 + (int)P.groups.size();
+  P.desc_off = o;
+  o += (size_t)n * sizeof(BatchFrame);
+  P.off_off = o;
+  o += (size_t)P.n_off_arrays * (n + 1) * sizeof(int32_t);
+  P.tri_off = align256(o);  // desc + offsets + triangles go up in one copy
+  o = P.tri_off + (size_t)P.tri_cap * sizeof(sm_tri);
+  P.pack_dev = align256(o);
+  o = P.pack_dev + (size_t)P.pack_slots * sizeof(sm_support);
+  P.total = align256(o);
+  return SM_OK;
+}
+
+struct ManyCtx {
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  std::vector<Delaunay> dl;
+  std::vector<std::vector<sm_tri>> tris;
+  std::vector<std::vector<int32_t>> bu, bv, bext;
+  std::vector<hipEvent_t> ev;
+};
+
+ManyCtx& many_ctx() {
+  static thread_local ManyCtx* c = new ManyCtx();
+  return *c;
+}
+
+}  // namespace
+}  // namespace sm
+
+extern "C" size_t sm_solve_many_workspace_bytes(const sm_frame* frames, int32_t n) {
+  if (n <= 0 || !frames) return 0;
+  ManyPlan P;
+  if (plan_many(frames, n, P) != SM_OK) return 0;
+  return P.total;
+}
+
+extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int32_t n_threads,
+                                   sm_stats* st, void* stream) {
+  last_error().clear();
+  if (n < 0 || (n > 0 && !frames)) return fail(SM_ERR_ARG, "bad frame array / count");
+  if (n == 0) return SM_OK;
+  if (n_threads < 1 || n_threads > 256) return fail(SM_ERR_ARG, "n_threads must be in [1, 256]");
+  ManyPlan P;
+  SM_TRY(plan_many(frames, n, P));
+  if (!ws || ((uintptr_t)ws & 255u)) return fail(SM_ERR_ARG, "workspace missing or not 256-byte aligned");
+  if (ws_bytes < P.total) return fail(SM_ERR_CAPACITY, "workspace %zu < %zu bytes", ws_bytes, P.total);
+  const hipStream_t s = (hipStream_t)stream;
+  const bool timing = st && st->timing;
+  if (st) {
+    const int32_t keep = st->timing;
+    std::memset(st, 0, sizeof(*st));
+    st->timing = keep;
+  }
+  const auto t_start = std::chrono::steady_clock::now();
+  ManyCtx& c = many_ctx();
+  // pinned staging: [desc | offsets | triangles] (uploaded together), then [packed supports]
+  const size_t up_bytes = P.pack_dev - P.desc_off;
+  const size_t pin_need = up_bytes + (size_t)P.pack_slots * sizeof(sm_support);
+  if (c.pinned_bytes < pin_need) {
+    if (c.pinned) SM_HIP(hipHostFree(c.pinned));
+    c.pinned = nullptr;
+    c.pinned_bytes = 0;
+    SM_HIP(hipHostMalloc(&c.pinned, pin_need, hipHostMallocDefault));
+    c.pinned_bytes = pin_need;
+  }
+  if ((int32_t)c.dl.size() < n) {
+    c.dl.resize(n);
+    c.tris.resize(n);
+    c.bu.resize(n);
+    c.bv.resize(n);
+    c.bext.resize(n);
+  }
+  uint8_t* base = (uint8_t*)ws;
+  uint8_t* hp = (uint8_t*)c.pinned;
+  BatchFrame* hF = (BatchFrame*)hp;
+  int32_t* hoff = (int32_t*)(hp + (P.off_off - P.desc_off));
+  sm_tri* hT = (sm_tri*)(hp + (P.tri_off - P.desc_off));
+  sm_support* hpack = (sm_support*)(hp + up_bytes);
+  const BatchFrame* dF = (const BatchFrame*)(base + P.desc_off);
+  const int32_t* doff = (const int32_t*)(base + P.off_off);
+  sm_tri* dT = (sm_tri*)(base + P.tri_off);
+  sm_support* dpack = (sm_support*)(base + P.pack_dev);
+  auto off_arr = [&](int k) { return hoff + (size_t)k * (n + 1); };
+  auto doff_arr = [&](int k) { return doff + (size_t)k * (n + 1); };
+  enum { kMatch = 0, kRaster = 1, kValidate = 2, kRematch = 3, kCensus0 = 4 };
+
+  // stage timing: an armed event pair per launch, summed after the final synchronisation
+  std::vector<std::pair<int, int>> marks;
+  int used = 0;
+  auto arm = [&](int stage) -> sm_status {
+    if (!timing) return SM_OK;
+    while ((int)c.ev.size() < used + 2) {
+      hipEvent_t e;
+      SM_HIP(hipEventCreate(&e));
+      c.ev.push_back(e);
+    }
+    set_launch_events(c.ev[used], c.ev[used + 1]);
+    marks.push_back({stage, used});
+    used += 2;
+    return SM_OK;
+  };
+  float us_host = 0.f, us_xfer = 0.f;
+  auto since = [](std::chrono::steady_clock::time_point t) {
+    return std::chrono::duration<float, std::micro>(std::chrono::steady_clock::now() - t).count();
+  };
+
+  // static frame descriptors
+  for (int32_t f = 0; f < n; ++f) {
+    const sm_frame& fr = frames[f];
+    const Layout& L = P.lay[f];
+    uint8_t* b = base + P.base[f];
+    BatchFrame& d = hF[f];
+    std::memset(&d, 0, sizeof(d));
+    d.L = fr.L;
+    d.R = fr.R;
+    d.W = fr.W;
+    d.H = fr.H;
+    d.stride = fr.stride;
+    d.p = fr.p;
+    d.cL = (uint64_t*)(b + L.cL);
+    d.cR = (uint64_t*)(b + L.cR);
+    d.omega = b + L.omega;
+    d.occ = b + L.occ;
+    d.D_it = (float*)(b + L.D_it);
+    d.cell_g = (uint64_t*)(b + L.cell_g);
+    d.cell_b = (uint64_t*)(b + L.cell_b);
+    d.S = (sm_support*)(b + L.S);
+    d.counters = (int32_t*)(b + L.counters);
+    d.n_valid = (unsigned long long*)(b + L.counters + 32);
+    d.D_f = fr.D_f;
+    d.C_f = fr.C_f;
+    d.mask = fr.mask;
+    d.n_grid = L.n_grid;
+    d.gw = L.n_grid > 0 ? (fr.W - 1 - fr.p.support_step / 2) / fr.p.support_step + 1 : 0;
+    d.sz = occ_size(fr.p, 1);
+    d.pack = dpack + P.pack_off[f];
+    d.pack_cap = L.n_grid;
+  }
+  // census (one launch per census window) + grid matching offsets
+  for (size_t g = 0; g < P.groups.size(); ++g) {
+    int32_t* o = off_arr(kCensus0 + (int)g);
+    o[0] = 0;
+    for (int32_t f = 0; f < n; ++f) {
+      const int32_t key = ((frames[f].p.census_w - 1) / 2) << 8 | ((frames[f].p.census_h - 1) / 2);
+      o[f + 1] = o[f] + (key == P.groups[g] ? 2 * census_tiles(frames[f].W, frames[f].H) : 0);
+    }
+  }
+  {
+    int32_t* o = off_arr(kMatch);
+    o[0] = 0;
+    for (int32_t f = 0; f < n; ++f) o[f + 1] = o[f] + P.lay[f].n_grid;
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  SM_HIP(hipMemcpyAsync(base + P.desc_off, hp, P.tri_off - P.desc_off, hipMemcpyHostToDevice, s));
+  us_xfer += since(t0);
+  for (size_t g = 0; g < P.groups.size(); ++g) {
+    SM_TRY(arm(SM_ST_CENSUS));
+    SM_HIP(launch_batch_census(dF, doff_arr(kCensus0 + (int)g), n, off_arr(kCensus0 + (int)g)[n], P.groups[g] >> 8,
+                               P.groups[g] & 255, s));
+  }
+  SM_TRY(arm(SM_ST_MATCH));
+  SM_HIP(launch_batch_match(dF, doff_arr(kMatch), n, off_arr(kMatch)[n], s));
+  SM_TRY(arm(SM_ST_COMPACT));
+  SM_HIP(launch_batch_compact(dF, n, 0, s));
+  SM_TRY(arm(SM_ST_COMPACT));
+  SM_HIP(launch_batch_pack(dF, n, 0, s));
+
+  std::vector<int32_t> n_S(n, 0), iters(n);
+  int max_iters = 0;
+  for (int32_t f = 0; f < n; ++f) max_iters = std::max(max_iters, iters[f] = frames[f].p.n_iters);
+  std::atomic<int32_t> next(0);
+  std::atomic<int32_t> bad(-1);
+  // new supports (staged by k_batch_pack) into frame f's mesh; from == 0 starts the mesh
+  auto triangulate = [&](int32_t f, bool first) {
+    const sm_support* src = hpack + P.pack_off[f];
+    int32_t cnt;
+    std::memcpy(&cnt, src, sizeof(cnt));
+    if (cnt < 0 || cnt > P.pack_cap[f]) {
+      bad = f;
+      return;
+    }
+    try {
+      if (first) c.dl[f].reset();
+      c.bu[f].resize(cnt);
+      c.bv[f].resize(cnt);
+      c.bext[f].resize(cnt);
+      for (int32_t k = 0; k < cnt; ++k) {
+        c.bu[f][k] = src[1 + k].u;
+        c.bv[f][k] = src[1 + k].v;
+        c.bext[f][k] = n_S[f] + k;
+      }
+      if (!c.dl[f].insert_many(c.bu[f].data(), c.bv[f].data(), c.bext[f].data(), cnt)) bad = f;
+      c.tris[f].clear();
+      c.dl[f].emit_banded(c.tris[f], 3);
+    } catch (...) {
+      bad = f;
+    }
+    n_S[f] += cnt;
+  };
+  std::vector<int32_t> todo;
+  auto run_host = [&](bool first) -> sm_status {
+    auto t1 = std::chrono::steady_clock::now();
+    SM_HIP(hipMemcpyAsync(hpack, dpack, (size_t)P.pack_slots * sizeof(sm_support), hipMemcpyDeviceToHost, s));
+    SM_HIP(hipStreamSynchronize(s));
+    us_xfer += since(t1);
+    auto th = std::chrono::steady_clock::now();
+    next = 0;
+    const int32_t m = (int32_t)todo.size();
+    auto body = [&](int) {
+      for (;;) {
+        const int32_t i = next.fetch_add(1);
+        if (i >= m) break;
+        triangulate(todo[i], first);
+      }
+    };
+    try {
+      pool().run(std::max(1, std::min(n_threads, m)), body);
+    } catch (...) {
+      return fail(SM_ERR_INTERNAL, "could not start triangulation workers");
+    }
+    us_host += since(th);
+    if (bad >= 0) return fail(SM_ERR_INTERNAL, "frame %d: triangulation input out of range", (int)bad);
+    return SM_OK;
+  };
+  todo.clear();
+  for (int32_t f = 0; f < n; ++f) todo.push_back(f);
+  SM_TRY(run_host(true));
+
+  for (int it = 1; it <= max_iters; ++it) {
+    // iteration state, offsets and the triangles of every active frame
+    int32_t toff = 0;
+    int32_t* o_r = off_arr(kRaster);
+    int32_t* o_v = off_arr(kValidate);
+    int32_t* o_m = off_arr(kRematch);
+    o_r[0] = o_v[0] = o_m[0] = 0;
+    std::vector<uint8_t> active(n, 0);
+    bool resample = false;
+    for (int32_t f = 0; f < n; ++f) {
+      BatchFrame& d = hF[f];
+      const bool act = it <= iters[f];
+      active[f] = act;
+      d.n_S = n_S[f];
+      d.sz = occ_size(frames[f].p, std::min(it, iters[f]));
+      d.last = act && it == iters[f];
+      d.n_T = act ? (int32_t)c.tris[f].size() : 0;
+      if (d.n_T > P.lay[f].T_cap) return fail(SM_ERR_INTERNAL, "frame %d: triangle capacity exceeded", f);
+      d.T = dT + toff;
+      if (d.n_T) std::memcpy(hT + toff, c.tris[f].data(), (size_t)d.n_T * sizeof(sm_tri));
+      toff += d.n_T;
+      const bool rs = act && it < iters[f];
+      d.region_n = rs ? 2 * cells_of(d.W, d.H, d.sz) : 0;
+      if (rs && n_S[f] + d.region_n + 1 > P.lay[f].S_cap)
+        return fail(SM_ERR_INTERNAL, "frame %d: support capacity exceeded", f);
+      d.region = rs ? d.S + n_S[f] : nullptr;
+      d.pack_cap = d.region_n;
+      resample |= rs;
+      if (st && act && it <= 8) {
+        st->n_support[it - 1] += n_S[f];
+        st->n_tris[it - 1] += d.n_T;
+      }
+      o_r[f + 1] = o_r[f] + d.n_T;
+      o_m[f + 1] = o_m[f] + (rs ? d.region_n / 2 : 0);
+    }
+    struct VCtx {
+      const BatchFrame* F;
+      const uint8_t* act;
+      int32_t n;
+    } vc{hF, active.data(), n};
+    const int nw = validate_pick_nw(
+        [](int w, void* x) {
+          const VCtx& q = *(const VCtx*)x;
+          int64_t tot = 0;
+          for (int32_t f = 0; f < q.n; ++f)
+            if (q.act[f]) tot += (int64_t)validate_blocks(q.F[f].W, q.F[f].H, q.F[f].sz, w) * w;
+          return tot;
+        },
+        &vc);
+    for (int32_t f = 0; f < n; ++f)
+      o_v[f + 1] = o_v[f] + (active[f] ? validate_blocks(hF[f].W, hF[f].H, hF[f].sz, nw) : 0);
+    t0 = std::chrono::steady_clock::now();
+    SM_HIP(hipMemcpyAsync(base + P.desc_off, hp, (P.tri_off - P.desc_off) + (size_t)toff * sizeof(sm_tri),
+                          hipMemcpyHostToDevice, s));
+    us_xfer += since(t0);
+    SM_TRY(arm(SM_ST_RASTER));
+    SM_HIP(launch_batch_raster(dF, doff_arr(kRaster), n, o_r[n], s));
+    SM_TRY(arm(SM_ST_VALIDATE));
+    SM_HIP(launch_batch_validate(dF, doff_arr(kValidate), n, o_v[n], nw, s));
+    if (!resample) break;
+    SM_TRY(arm(SM_ST_REMATCH));
+    SM_HIP(launch_batch_rematch(dF, doff_arr(kRematch), n, o_m[n], s));
+    SM_TRY(arm(SM_ST_COMPACT));
+    SM_HIP(launch_batch_compact(dF, n, 1, s));
+    SM_TRY(arm(SM_ST_COMPACT));
+    SM_HIP(launch_batch_pack(dF, n, 1, s));
+    todo.clear();
+    for (int32_t f = 0; f < n; ++f)
+      if (hF[f].region_n > 0) todo.push_back(f);
+    SM_TRY(run_host(false));
+  }
+  if (st) {
+    // validated-pixel counts: every frame's counter, gathered on the host
+    t0 = std::chrono::steady_clock::now();
+    std::vector<unsigned long long> nv(n);
+    for (int32_t f = 0; f < n; ++f)
+      SM_HIP(hipMemcpyAsync(&nv[f], hF[f].n_valid, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    SM_HIP(hipStreamSynchronize(s));
+    us_xfer += since(t0);
+    for (int32_t f = 0; f < n; ++f) st->n_valid += (int64_t)nv[f];
+    for (const auto& mk : marks) {
+      float ms = 0.f;
+      SM_HIP(hipEventElapsedTime(&ms, c.ev[mk.second], c.ev[mk.second + 1]));
+      st->stage_us[mk.first] += ms * 1e3f;
+      st->stage_launches[mk.first] += 1;
+    }
+    st->stage_us[SM_ST_HOST_TRI] = us_host;
+    st->stage_us[SM_ST_HOST_COPY] = us_xfer;
+  } else {
+    SM_HIP(hipStreamSynchronize(s));
+  }
+  for (int32_t f = 0; f < n; ++f) {
+    frames[f].status = SM_OK;
+    frames[f].worker = 0;
+  }
+  const float total_us = since(t_start);
+  for (int32_t f = 0; f < n; ++f) frames[f].latency_us = total_us;
+  if (st) st->stage_us[SM_ST_TOTAL] = total_us;
   return SM_OK;
 }

@@ -63,24 +63,25 @@ struct CensusArgs {
   CensusExtras x;
 };
 
+// One 64 x 16 output tile (bx, by) of image `job` (0 = left: also Omega_I and the
+// per-frame initialisation). `tile` is the block's LDS staging area.
 template <int RX, int RY>
-__global__ __launch_bounds__(256) void k_census(CensusArgs a) {
+__device__ __forceinline__ void census_block(const CensusArgs& a, int job, int bx, int by, uint8_t* tile) {
   constexpr int PW = kTW + 2 * RX, PH = kTH + 2 * RY;
-  __shared__ uint8_t tile[PH * PW];
-  const CensusJob jb = a.job[blockIdx.z];
+  const CensusJob jb = a.job[job];
   const int W = a.W, H = a.H;
-  const int gx0 = blockIdx.x * kTW - RX, gy0 = blockIdx.y * kTH - RY;
+  const int gx0 = bx * kTW - RX, gy0 = by * kTH - RY;
   for (int i = threadIdx.y * kTW + threadIdx.x; i < PH * PW; i += 256) {
     int ty = i / PW, tx = i - ty * PW;
     int gx = min(max(gx0 + tx, 0), W - 1), gy = min(max(gy0 + ty, 0), H - 1);
     tile[i] = jb.img[(size_t)gy * jb.stride + gx];
   }
   __syncthreads();
-  const int u = blockIdx.x * kTW + threadIdx.x;
+  const int u = bx * kTW + threadIdx.x;
 #pragma unroll
   for (int r = 0; r < kTH / 4; ++r) {
     const int ly = threadIdx.y + 4 * r;
-    const int v = blockIdx.y * kTH + ly;
+    const int v = by * kTH + ly;
     if (v >= H || u >= W) break;
     const size_t idx = (size_t)v * W + u;
     const bool valid = u >= RX && u < W - RX && v >= RY && v < H - RY;
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(256) void k_census(CensusArgs a) {
       }
       jb.omega[idx] = om;
     }
-    if (blockIdx.z == 0) {
+    if (job == 0) {
       if (a.D_f) a.D_f[idx] = 0.0f;
       if (a.C_f) a.C_f[idx] = (uint8_t)a.t_hi;
       if (a.occ) a.occ[idx] = 0;
@@ -131,10 +132,16 @@ __global__ __launch_bounds__(256) void k_census(CensusArgs a) {
       }
     }
   }
-  if (a.x.zero && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0) {
+  if (a.x.zero && bx == 0 && by == 0 && job == 0) {
     const int t = threadIdx.y * kTW + threadIdx.x;
     if (t < a.x.n_zero) a.x.zero[t] = 0;
   }
+}
+
+template <int RX, int RY>
+__global__ __launch_bounds__(256) void k_census(CensusArgs a) {
+  __shared__ uint8_t tile[(kTH + 2 * RY) * (kTW + 2 * RX)];
+  census_block<RX, RY>(a, blockIdx.z, blockIdx.x, blockIdx.y, tile);
 }
 
 template <int RX, int RY>
@@ -467,24 +474,26 @@ __device__ __forceinline__ bool match_inside(const MatchArgs& a, int u, int v) {
   return u >= a.rx && u < a.W - a.rx && v >= a.ry && v < a.H - a.ry;
 }
 
-__global__ __launch_bounds__(256) void k_match(MatchArgs a) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (slot >= a.n) return;
+// Matches candidate slot `slot` if it is pending (the whole wave calls it).
+__device__ __forceinline__ void match_slot(const MatchArgs& a, int slot, int lane) {
   const sm_support s = a.slots[slot];
   if (s.d != kPending) return;
   const int d = match_inside(a, s.u, s.v) ? match_one(a, s.u, s.v, lane) : -1;
   if (lane == 0) a.slots[slot].d = d >= 0 ? (float)d : kRejected;
 }
 
+__global__ __launch_bounds__(256) void k_match(MatchArgs a) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (slot >= a.n) return;
+  match_slot(a, slot, lane);
+}
+
 // Resampling (Alg. 4) fused with the re-match: one wave per cell. Slot c receives the
 // confident support of cell c, slot n_cells + c its re-matched invalid pixel.
-__global__ __launch_bounds__(256) void k_rematch_cells(MatchArgs a, const uint64_t* cell_g,
-                                                       const uint64_t* cell_b, const float* D_it,
-                                                       int n_cells, uint64_t ginit, uint64_t binit) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= n_cells) return;
+__device__ __forceinline__ void rematch_cell(const MatchArgs& a, const uint64_t* cell_g, const uint64_t* cell_b,
+                                             const float* D_it, int n_cells, uint64_t ginit, uint64_t binit,
+                                             int c, int lane) {
   const uint64_t g = cell_g[c], b = cell_b[c];
   if (lane == 0) {
     sm_support sg;
@@ -513,11 +522,20 @@ __global__ __launch_bounds__(256) void k_rematch_cells(MatchArgs a, const uint64
   if (lane == 0) a.slots[n_cells + c] = sb;
 }
 
+__global__ __launch_bounds__(256) void k_rematch_cells(MatchArgs a, const uint64_t* cell_g,
+                                                       const uint64_t* cell_b, const float* D_it,
+                                                       int n_cells, uint64_t ginit, uint64_t binit) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= n_cells) return;
+  rematch_cell(a, cell_g, cell_b, D_it, n_cells, ginit, binit, c, lane);
+}
+
 // ------------------------------------------------------------------------------------
 // Order-preserving in-place compaction (one 1024-thread workgroup).
 // ------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_compact(sm_support* slots, int n, int* n_out, uint8_t* occ,
-                                                  int W, int* header) {
+__device__ __forceinline__ void compact_block(sm_support* slots, int n, int* n_out, uint8_t* occ, int W,
+                                              int* header) {
   __shared__ int wsum[16];
   __shared__ int wofs[16];
   __shared__ int total;
@@ -556,6 +574,11 @@ __global__ __launch_bounds__(1024) void k_compact(sm_support* slots, int n, int*
     *n_out = base;
     if (header) *header = base;
   }
+}
+
+__global__ __launch_bounds__(1024) void k_compact(sm_support* slots, int n, int* n_out, uint8_t* occ,
+                                                  int W, int* header) {
+  compact_block(slots, n, n_out, occ, W, header);
 }
 
 __global__ void k_fill_u8(uint8_t* p, size_t n, uint8_t val) {
@@ -706,11 +729,9 @@ __device__ __forceinline__ void raster_row(const RasterTri& r, int v, int lo, in
   if (u == hi) row[u] = __fadd_rn(__fadd_rn(r.d0, __fmul_rn(r.a, fu)), tv);
 }
 
-__global__ __launch_bounds__(256) void k_raster_wave(const sm_support* S, int n_support, const sm_tri* T,
-                                                     int n_tris, int W, int H, float* D) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= n_tris) return;
+// Triangle t by one wave, one lane per row.
+__device__ __forceinline__ void raster_tri_wave(const sm_support* S, int n_support, const sm_tri* T, int t,
+                                                int W, int H, float* D, int lane) {
   const RasterTri r = raster_setup(S, n_support, T, t, W, H);
   if (!r.ok) return;
   for (int v = r.vmin + lane; v <= r.vmax; v += kWave) {
@@ -718,6 +739,14 @@ __global__ __launch_bounds__(256) void k_raster_wave(const sm_support* S, int n_
     raster_span(r, v, lo, hi);
     raster_row(r, v, lo, hi, D + (size_t)v * W);
   }
+}
+
+__global__ __launch_bounds__(256) void k_raster_wave(const sm_support* S, int n_support, const sm_tri* T,
+                                                     int n_tris, int W, int H, float* D) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= n_tris) return;
+  raster_tri_wave(S, n_support, T, t, W, H, D, lane);
 }
 
 __global__ __launch_bounds__(256) void k_raster_group(const sm_support* S, int n_support, const sm_tri* T,
@@ -770,14 +799,14 @@ struct ValidateArgs {
 // The launcher picks NW per frame size: few waves per block (many rows per wave) once
 // the grid alone fills the chip, more waves per block on small frames.
 template <int NW>
-__global__ __launch_bounds__(kWave * NW, 8) void k_validate(ValidateArgs a) {
+__device__ __forceinline__ void validate_block(const ValidateArgs& a, int bx, int by) {
   __shared__ uint64_t sg[NW][kWave];
   __shared__ uint64_t sb[NW][kWave];
   __shared__ unsigned int s_valid;
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x >> 6;
   if (threadIdx.x == 0) s_valid = 0;
-  const int x0 = blockIdx.x * a.TW, y0 = blockIdx.y * a.TH;
+  const int x0 = bx * a.TW, y0 = by * a.TH;
   const uint64_t none = ~0ull;
   uint64_t kg = none, kb = none;
   unsigned int nvalid = 0;
@@ -869,7 +898,7 @@ __global__ __launch_bounds__(kWave * NW, 8) void k_validate(ValidateArgs a) {
   // thread (w, lane): cell row w of the tile, cell column seg (segment heads only)
   const bool head = lane == 0 || (a.sz <= kWave && (lane - 1) / a.sz != seg);
   if (w < a.crows && head && seg < a.cpr) {
-    const int cy = blockIdx.y * a.crows + w, cx = blockIdx.x * a.cpr + seg;
+    const int cy = by * a.crows + w, cx = bx * a.cpr + seg;
     if (cy < a.Hc && cx < a.Wc) {
       uint64_t g = a.ginit, b = a.binit;
       // the waves whose rows belong to cell row w: rows w*sz .. w*sz+sz-1 are handled by
@@ -890,6 +919,11 @@ __global__ __launch_bounds__(kWave * NW, 8) void k_validate(ValidateArgs a) {
   }
 }
 
+template <int NW>
+__global__ __launch_bounds__(kWave * NW, 8) void k_validate(ValidateArgs a) {
+  validate_block<NW>(a, blockIdx.x, blockIdx.y);
+}
+
 inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // validate launch shape: 2048 waves is 8 per CU, enough to cover HBM latency
@@ -898,8 +932,8 @@ constexpr size_t kValMinWaves = 2048;
 
 }  // namespace
 
-static MatchArgs match_args(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
-                            const sm_params& p, sm_support* slots, int32_t n) {
+__host__ __device__ inline MatchArgs match_args(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
+                                                const sm_params& p, sm_support* slots, int32_t n) {
   MatchArgs a;
   a.cL = cL;
   a.cR = cR;
@@ -1042,11 +1076,12 @@ hipError_t launch_interpolate(const sm_support* S, int32_t n_support, const sm_t
   return launch_raster(S, n_support, T, n_tris, W, H, D_it, s);
 }
 
-hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
-                                const float* D_it, int32_t W, int32_t H, const sm_params& p,
-                                int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f,
-                                uint64_t* cell_g, uint64_t* cell_b, uint8_t* mask,
-                                unsigned long long* n_valid, hipStream_t s) {
+// Validation arguments of one frame for blocks of nw waves.
+__host__ __device__ inline ValidateArgs validate_args(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
+                                                      const float* D_it, int32_t W, int32_t H, const sm_params& p,
+                                                      int32_t sz, int nw, uint8_t* C_it, float* D_f, uint8_t* C_f,
+                                                      uint64_t* cell_g, uint64_t* cell_b, uint8_t* mask,
+                                                      unsigned long long* n_valid) {
   ValidateArgs a;
   a.cL = cL;
   a.cR = cR;
@@ -1065,14 +1100,8 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
   a.Hc = (H + sz - 1) / sz;
   a.cpr = sz <= kWave ? kWave / sz : 1;
   a.TW = a.cpr * sz;
-  // smallest block (most rows per wave) whose grid still holds >= kValMinWaves waves
-  int nw = 1;
-  for (;; nw *= 2) {
-    a.crows = sz >= nw ? 1 : nw / sz;
-    a.TH = a.crows * sz;
-    const size_t waves = (size_t)blocks_for(W, a.TW) * blocks_for(H, a.TH) * nw;
-    if (nw == kValMaxWaves || waves >= kValMinWaves) break;
-  }
+  a.crows = sz >= nw ? 1 : nw / sz;
+  a.TH = a.crows * sz;
   a.ginit = (uint64_t)p.t_lo << 32;
   a.binit = (uint64_t)(255 - p.t_hi) << 32;
   a.C_it = C_it;
@@ -1082,6 +1111,38 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
   a.cell_b = cell_b;
   a.mask = mask;
   a.n_valid = n_valid;
+  return a;
+}
+
+int32_t validate_blocks(int32_t W, int32_t H, int32_t sz, int nw) {
+  const int cpr = sz <= kWave ? kWave / sz : 1;
+  const int crows = sz >= nw ? 1 : nw / sz;
+  return (int32_t)(blocks_for(W, cpr * sz) * blocks_for(H, crows * sz));
+}
+
+int validate_pick_nw(int64_t (*waves)(int nw, void* ctx), void* ctx) {
+  int nw = 1;
+  while (nw < kValMaxWaves && waves(nw, ctx) < (int64_t)kValMinWaves) nw *= 2;
+  return nw;
+}
+
+hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
+                                const float* D_it, int32_t W, int32_t H, const sm_params& p,
+                                int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f,
+                                uint64_t* cell_g, uint64_t* cell_b, uint8_t* mask,
+                                unsigned long long* n_valid, hipStream_t s) {
+  // smallest block (most rows per wave) whose grid still holds >= kValMinWaves waves
+  struct Ctx {
+    int32_t W, H, sz;
+  } c{W, H, sz};
+  const int nw = validate_pick_nw(
+      [](int w, void* x) {
+        const Ctx& q = *(const Ctx*)x;
+        return (int64_t)validate_blocks(q.W, q.H, q.sz, w) * w;
+      },
+      &c);
+  const ValidateArgs a = validate_args(cL, cR, omega, D_it, W, H, p, sz, nw, C_it, D_f, C_f, cell_g, cell_b,
+                                       mask, n_valid);
   dim3 grid(blocks_for(W, a.TW), blocks_for(H, a.TH));
   switch (nw) {
     case 1: SM_LAUNCH(k_validate<1>, grid, dim3(kWave * 1), 0, s, a); break;
@@ -1110,6 +1171,176 @@ hipError_t launch_resample(const uint64_t* cL, const uint64_t* cR, const uint64_
   const MatchArgs a = match_args(cL, cR, W, H, p, slots, 2 * n_cells);
   SM_LAUNCH(k_rematch_cells, dim3(blocks_for(n_cells, 4)), dim3(256), 0, s, a, cell_g, cell_b, D_it,
             n_cells, ginit, binit);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// Stage-batched kernels: the single-frame device functions above, with work units
+// (blocks or waves) mapped to frames by a binary search over the offset array.
+// ------------------------------------------------------------------------------------
+namespace {
+
+__device__ __forceinline__ int frame_of(const int32_t* off, int n, int unit) {
+  int lo = 0, hi = n;  // the last f with off[f] <= unit (frames owning no units are skipped)
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= unit) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <int RX, int RY>
+__global__ __launch_bounds__(256) void k_batch_census(const BatchFrame* F, const int32_t* off, int n) {
+  __shared__ uint8_t tile[(kTH + 2 * RY) * (kTW + 2 * RX)];
+  const int f = frame_of(off, n, blockIdx.x);
+  const BatchFrame& fr = F[f];
+  const int local = blockIdx.x - off[f];
+  const int tx = (fr.W + kTW - 1) / kTW, ty = (fr.H + kTH - 1) / kTH;
+  const int job = local / (tx * ty), t = local - job * tx * ty;
+  CensusArgs a{};
+  a.job[0] = CensusJob{fr.L, fr.stride, fr.cL, fr.omega};
+  a.job[1] = CensusJob{fr.R, fr.stride, fr.cR, nullptr};
+  a.W = fr.W;
+  a.H = fr.H;
+  a.grad_thr = fr.p.grad_thr;
+  a.t_hi = fr.p.t_hi;
+  a.D_f = fr.D_f;
+  a.C_f = fr.C_f;
+  a.occ = fr.occ;
+  a.x.D_nan = fr.D_it;
+  a.x.grid_slots = fr.S;
+  a.x.step = fr.p.support_step;
+  a.x.gw = fr.gw;
+  a.x.zero = fr.counters;
+  a.x.n_zero = 16;
+  census_block<RX, RY>(a, job, t % tx, t / tx, tile);
+}
+
+__global__ __launch_bounds__(256) void k_batch_match(const BatchFrame* F, const int32_t* off, int n, int total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int unit = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (unit >= total) return;
+  const int f = frame_of(off, n, unit);
+  const BatchFrame& fr = F[f];
+  const MatchArgs a = match_args(fr.cL, fr.cR, fr.W, fr.H, fr.p, fr.S, fr.n_grid);
+  match_slot(a, unit - off[f], lane);
+}
+
+__global__ __launch_bounds__(1024) void k_batch_compact(const BatchFrame* F, int mode) {
+  const BatchFrame& fr = F[blockIdx.x];
+  if (mode == 0) {
+    compact_block(fr.S, fr.n_grid, &fr.counters[0], fr.occ, fr.W, (int32_t*)(fr.S + fr.n_grid));
+  } else if (fr.region_n > 0) {
+    compact_block(fr.region, fr.region_n, &fr.counters[1], fr.occ, fr.W, (int32_t*)(fr.region + fr.region_n));
+  }
+}
+
+// Header slot (count) + the compacted supports of frame blockIdx.x into its staging.
+__global__ __launch_bounds__(256) void k_batch_pack(const BatchFrame* F, int mode) {
+  const BatchFrame& fr = F[blockIdx.x];
+  const sm_support* src = mode == 0 ? fr.S : fr.region;
+  const int n_slots = mode == 0 ? fr.n_grid : fr.region_n;
+  if (!fr.pack || (mode == 1 && n_slots == 0)) return;
+  const int count = min(*(const int32_t*)(src + n_slots), fr.pack_cap);
+  if (threadIdx.x == 0) *(int32_t*)fr.pack = count;
+  for (int i = threadIdx.x; i < count; i += 256) fr.pack[1 + i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void k_batch_raster(const BatchFrame* F, const int32_t* off, int n, int total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int unit = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (unit >= total) return;
+  const int f = frame_of(off, n, unit);
+  const BatchFrame& fr = F[f];
+  raster_tri_wave(fr.S, fr.n_S, fr.T, unit - off[f], fr.W, fr.H, fr.D_it, lane);
+}
+
+template <int NW>
+__global__ __launch_bounds__(kWave * NW, 8) void k_batch_validate(const BatchFrame* F, const int32_t* off, int n) {
+  const int f = frame_of(off, n, blockIdx.x);
+  const BatchFrame& fr = F[f];
+  const ValidateArgs a = validate_args(fr.cL, fr.cR, fr.omega, fr.D_it, fr.W, fr.H, fr.p, fr.sz, NW, nullptr,
+                                       fr.D_f, fr.C_f, fr.cell_g, fr.cell_b, fr.last ? fr.mask : nullptr,
+                                       fr.last ? fr.n_valid : nullptr);
+  const int local = blockIdx.x - off[f];
+  const int gx = (fr.W + a.TW - 1) / a.TW;
+  validate_block<NW>(a, local % gx, local / gx);
+}
+
+__global__ __launch_bounds__(256) void k_batch_rematch(const BatchFrame* F, const int32_t* off, int n, int total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int unit = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (unit >= total) return;
+  const int f = frame_of(off, n, unit);
+  const BatchFrame& fr = F[f];
+  const int n_cells = fr.region_n / 2;
+  const MatchArgs a = match_args(fr.cL, fr.cR, fr.W, fr.H, fr.p, fr.region, fr.region_n);
+  rematch_cell(a, fr.cell_g, fr.cell_b, fr.D_it, n_cells, (uint64_t)fr.p.t_lo << 32,
+               (uint64_t)(255 - fr.p.t_hi) << 32, unit - off[f], lane);
+}
+
+}  // namespace
+
+int32_t census_tiles(int32_t W, int32_t H) { return (int32_t)(blocks_for(W, kTW) * blocks_for(H, kTH)); }
+
+hipError_t launch_batch_census(const BatchFrame* F, const int32_t* off, int32_t n, int32_t total, int rx, int ry,
+                               hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+#define SM_BATCH_CENSUS_CASE(X, Y)                                                                     \
+  if (rx == X && ry == Y) {                                                                            \
+    SM_LAUNCH((k_batch_census<X, Y>), dim3((unsigned)total), dim3(kTW, 4, 1), 0, s, F, off, (int)n); \
+    return hipGetLastError();                                                                          \
+  }
+  SM_BATCH_CENSUS_CASE(1, 1) SM_BATCH_CENSUS_CASE(1, 2) SM_BATCH_CENSUS_CASE(1, 3) SM_BATCH_CENSUS_CASE(1, 4)
+  SM_BATCH_CENSUS_CASE(2, 1) SM_BATCH_CENSUS_CASE(2, 2) SM_BATCH_CENSUS_CASE(2, 3) SM_BATCH_CENSUS_CASE(2, 4)
+  SM_BATCH_CENSUS_CASE(3, 1) SM_BATCH_CENSUS_CASE(3, 2) SM_BATCH_CENSUS_CASE(3, 3) SM_BATCH_CENSUS_CASE(3, 4)
+  SM_BATCH_CENSUS_CASE(4, 1) SM_BATCH_CENSUS_CASE(4, 2) SM_BATCH_CENSUS_CASE(4, 3)
+#undef SM_BATCH_CENSUS_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_match(const BatchFrame* F, const int32_t* off, int32_t n, int32_t total, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  SM_LAUNCH(k_batch_match, dim3(blocks_for(total, 4)), dim3(256), 0, s, F, off, (int)n, (int)total);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_compact(const BatchFrame* F, int32_t n, int mode, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  SM_LAUNCH(k_batch_compact, dim3((unsigned)n), dim3(1024), 0, s, F, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_pack(const BatchFrame* F, int32_t n, int mode, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  SM_LAUNCH(k_batch_pack, dim3((unsigned)n), dim3(256), 0, s, F, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_raster(const BatchFrame* F, const int32_t* off, int32_t n, int32_t total, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  SM_LAUNCH(k_batch_raster, dim3(blocks_for(total, 4)), dim3(256), 0, s, F, off, (int)n, (int)total);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_validate(const BatchFrame* F, const int32_t* off, int32_t n, int32_t total, int nw,
+                                 hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  const dim3 grid((unsigned)total);
+  switch (nw) {
+    case 1: SM_LAUNCH(k_batch_validate<1>, grid, dim3(kWave * 1), 0, s, F, off, (int)n); break;
+    case 2: SM_LAUNCH(k_batch_validate<2>, grid, dim3(kWave * 2), 0, s, F, off, (int)n); break;
+    case 4: SM_LAUNCH(k_batch_validate<4>, grid, dim3(kWave * 4), 0, s, F, off, (int)n); break;
+    case 8: SM_LAUNCH(k_batch_validate<8>, grid, dim3(kWave * 8), 0, s, F, off, (int)n); break;
+    default: SM_LAUNCH(k_batch_validate<16>, grid, dim3(kWave * 16), 0, s, F, off, (int)n); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_rematch(const BatchFrame* F, const int32_t* off, int32_t n, int32_t total, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  SM_LAUNCH(k_batch_rematch, dim3(blocks_for(total, 4)), dim3(256), 0, s, F, off, (int)n, (int)total);
   return hipGetLastError();
 }
 

@@ -101,4 +101,54 @@ hipError_t launch_resample(const uint64_t* cL, const uint64_t* cR, const uint64_
                            const uint64_t* cell_b, const float* D_it, int32_t W, int32_t H, int32_t sz,
                            const sm_params& p, sm_support* slots, hipStream_t s);
 
+// ---------------------------------------------------------------------------------
+// Stage-batched solve of many frames: every stage is one launch over all frames. The
+// batched kernels read per-frame arguments from a device array of BatchFrame and map
+// their work units (blocks or waves) to frames through a prefix array `off` of n + 1
+// entries (off[0] = 0, frame f owns units off[f] .. off[f+1]-1).
+// ---------------------------------------------------------------------------------
+struct BatchFrame {
+  const uint8_t* L;
+  const uint8_t* R;
+  int32_t W, H, stride;
+  sm_params p;
+  uint64_t* cL;
+  uint64_t* cR;
+  uint8_t* omega;
+  uint8_t* occ;
+  float* D_it;
+  uint64_t* cell_g;
+  uint64_t* cell_b;
+  sm_support* S;
+  int32_t* counters;
+  unsigned long long* n_valid;
+  float* D_f;
+  uint8_t* C_f;
+  uint8_t* mask;
+  int32_t n_grid, gw;        // grid candidate slots, grid nodes per row
+  // state of the current iteration, rewritten before its launches
+  const sm_tri* T;
+  int32_t n_T, n_S, sz, last;  // last: this iteration writes the mask
+  sm_support* region;          // resampling output (2 * cells slots + one header slot)
+  int32_t region_n;            // 2 * cells, 0 when the frame does not resample
+  sm_support* pack;            // host-bound staging: header slot + up to pack_cap supports
+  int32_t pack_cap;
+};
+
+int32_t census_tiles(int32_t W, int32_t H);
+int32_t validate_blocks(int32_t W, int32_t H, int32_t sz, int nw);
+// smallest block size (waves) whose batched grid still holds enough waves
+int validate_pick_nw(int64_t (*waves)(int nw, void* ctx), void* ctx);
+
+hipError_t launch_batch_census(const BatchFrame* F, const int32_t* off, int32_t n, int32_t total, int rx, int ry,
+                               hipStream_t s);
+hipError_t launch_batch_match(const BatchFrame* F, const int32_t* off, int32_t n, int32_t total, hipStream_t s);
+// mode 0: the grid slots S[0, n_grid); mode 1: the resampling region. One workgroup per frame.
+hipError_t launch_batch_compact(const BatchFrame* F, int32_t n, int mode, hipStream_t s);
+hipError_t launch_batch_pack(const BatchFrame* F, int32_t n, int mode, hipStream_t s);
+hipError_t launch_batch_raster(const BatchFrame* F, const int32_t* off, int32_t n, int32_t total, hipStream_t s);
+hipError_t launch_batch_validate(const BatchFrame* F, const int32_t* off, int32_t n, int32_t total, int nw,
+                                 hipStream_t s);
+hipError_t launch_batch_rematch(const BatchFrame* F, const int32_t* off, int32_t n, int32_t total, hipStream_t s);
+
 }  // namespace sm

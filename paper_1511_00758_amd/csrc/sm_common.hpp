@@ -63,4 +63,12 @@ inline int32_t grid_count(int32_t W, int32_t H, int32_t step) {
   return ((W - 1 - h) / step + 1) * ((H - 1 - h) / step + 1);
 }
 
+// Workspace of one sm_solve frame: byte offsets of its buffers (see sm_solve).
+struct Layout {
+  size_t cL, cR, omega, occ, D_it, cell_g, cell_b, S, T, counters, score, total;
+  int32_t n_grid, S_cap, T_cap, cells_max;  // n_grid: initial candidate slots (grid or FAST)
+};
+Layout layout_of(int32_t W, int32_t H, const sm_params& p);  // p must have passed check_params
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
 }  // namespace sm
