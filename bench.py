@@ -394,6 +394,8 @@ def main():
                     help="skip the batched (sm_solve_batch) throughput runs")
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the 7680x4320 interpolation/validation roofline probe")
+    ap.add_argument("--time-all", action="store_true",
+                    help="time every kernel of the solve with events (default: validate and raster)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FAST-support / 3-level variants of the 640x480 workload")
     ap.add_argument("--probe-only", action="store_true",
@@ -434,7 +436,9 @@ def main():
         frames.append((sc.left, sc.right))
     dframes = [(torch.from_numpy(l).to(dev), torch.from_numpy(r).to(dev)) for (l, r) in frames]
     solver = api.Solver(W, H, params, device=dev)
-    timing = not args.no_timing
+    # live per-kernel timing of the roofline kernels (events around every launch would
+    # slow the whole frame by ~10%; --time-all times every kernel)
+    timing = False if args.no_timing else (True if args.time_all else ("validate", "raster"))
 
     for k in range(args.warmup):
         l, r = dframes[k % len(dframes)]

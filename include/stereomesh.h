@@ -82,9 +82,12 @@ typedef struct {
 } sm_params;
 
 /* Per-solve statistics. `timing` is an input: when non-zero, sm_solve records a pair of
- * HIP events on `stream` around every kernel launch and reports, per kernel, the summed
+ * HIP events on `stream` around kernel launches and reports, per kernel stage, the summed
  * device time (stage_us) and the launch count (stage_launches); the host stages report
- * wall time. Indices are the sm_stage values. */
+ * wall time. Indices are the sm_stage values. timing = SM_TIME_SELECTED | (1 << stage)
+ * | ... times only the listed stages (fewer events in the way of the rest); any other
+ * non-zero value times every kernel. */
+#define SM_TIME_SELECTED 0x40000000
 typedef enum {
   SM_ST_CENSUS = 0,          /* census + Omega_I of both images, per-frame initialisation     */
   SM_ST_MATCH = 1,           /* epipolar matching of the support-grid candidates              */

@@ -19,6 +19,19 @@ STATUS_NAMES = {0: "SM_OK", -1: "SM_ERR_ARG", -2: "SM_ERR_CAPACITY", -3: "SM_ERR
 STAGES = {"census": 0, "match": 1, "compact": 2, "raster": 3, "validate": 4, "rematch": 5,
           "fast": 6, "host_triangulate": 12, "host_copies": 13, "total": 14}
 N_STAGES = 16
+TIME_SELECTED = 0x40000000
+
+
+def timing_flag(timing) -> int:
+    """sm_stats.timing from True/False or an iterable of stage names to time alone."""
+    if timing is True:
+        return 1
+    if not timing:
+        return 0
+    flag = TIME_SELECTED
+    for name in timing:
+        flag |= 1 << STAGES[name]
+    return flag
 
 
 class SmSupport(ctypes.Structure):

@@ -224,7 +224,7 @@ class Solver:
         L = _lib.load()
         st = None
         if stats or timing:
-            self.st.timing = 1 if timing else 0
+            self.st.timing = _lib.timing_flag(timing)
             st = self.st
         check(L.sm_solve(left.data_ptr(), right.data_ptr(), self.W, self.H, left.stride(0), self.p,
                          self.ws_ptr, self.ws_bytes, self.D_f.data_ptr(), self.C_f.data_ptr(),
@@ -290,7 +290,7 @@ class BatchSolver:
         for s in self.streams:
             s.wait_stream(cur)
         st = _lib.SmStats()
-        st.timing = 1 if timing else 0
+        st.timing = _lib.timing_flag(timing)
         L = _lib.load()
         check(L.sm_solve_batch(arr, n, self._streams, self._ws, self._ws_bytes, self.n_workers,
                                st if (stats or timing) else None))
@@ -346,7 +346,7 @@ class ManySolver:
             self.ws_bytes = need
         ptr = self.ws.data_ptr() + ((-self.ws.data_ptr()) % 256) if self.ws is not None else None
         st = _lib.SmStats()
-        st.timing = 1 if timing else 0
+        st.timing = _lib.timing_flag(timing)
         check(L.sm_solve_many(arr, n, ptr, self.ws_bytes, self.n_threads,
                               st if (stats or timing) else None, _stream(stream)))
         if not (stats or timing):

@@ -110,7 +110,9 @@ struct Timer {
   StageTimer& t;
   hipStream_t s;
   bool on;
-  Timer(StageTimer& tt, hipStream_t ss, bool enabled) : t(tt), s(ss), on(enabled) {
+  uint32_t stages;  // bit k: time the kernels of stage k
+  Timer(StageTimer& tt, hipStream_t ss, int32_t timing) : t(tt), s(ss), on(timing != 0) {
+    stages = (timing & SM_TIME_SELECTED) ? (uint32_t)timing & 0xffffu : 0xffffu;
     t.used = 0;
     t.marks.clear();
   }
@@ -125,7 +127,7 @@ struct Timer {
   }
   // arms an event pair that the next launch records around its kernel
   sm_status begin(int stage) {
-    if (!on) return SM_OK;
+    if (!on || !(stages >> stage & 1u)) return SM_OK;
     hipEvent_t e0, e1;
     SM_TRY(event(&e0));
     SM_TRY(event(&e1));
@@ -135,7 +137,7 @@ struct Timer {
   }
   sm_status end() {
     if (!on) return SM_OK;
-    if (launch_events_pending()) {  // nothing was launched: forget the mark
+    if (launch_events_pending()) {  // nothing was launched (or not timed): forget the mark
       set_launch_events(nullptr, nullptr);
       t.marks.pop_back();
       t.used -= 2;
@@ -378,7 +380,7 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   const auto t_start = clk::now();
   hipStream_t s = (hipStream_t)stream;
   ThreadCtx& c = ctx();
-  const bool timing = st && st->timing;
+  const int32_t timing = st ? st->timing : 0;
   if (st) {
     const int32_t keep = st->timing;
     std::memset(st, 0, sizeof(*st));

@@ -278,7 +278,8 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
   if (!ws || ((uintptr_t)ws & 255u)) return fail(SM_ERR_ARG, "workspace missing or not 256-byte aligned");
   if (ws_bytes < P.total) return fail(SM_ERR_CAPACITY, "workspace %zu < %zu bytes", ws_bytes, P.total);
   const hipStream_t s = (hipStream_t)stream;
-  const bool timing = st && st->timing;
+  const int32_t timing = st ? st->timing : 0;
+  const uint32_t timed = (timing & SM_TIME_SELECTED) ? (uint32_t)timing & 0xffffu : 0xffffu;
   if (st) {
     const int32_t keep = st->timing;
     std::memset(st, 0, sizeof(*st));
@@ -321,7 +322,7 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
   std::vector<std::pair<int, int>> marks;
   int used = 0;
   auto arm = [&](int stage) -> sm_status {
-    if (!timing) return SM_OK;
+    if (!timing || !(timed >> stage & 1u)) return SM_OK;
     while ((int)c.ev.size() < used + 2) {
       hipEvent_t e;
       SM_HIP(hipEventCreate(&e));
