@@ -44,6 +44,23 @@ void Delaunay::reset() {
   started_ = false;
 }
 
+// Rotates the solid triangle (a, b, c) cyclically (orientation kept) so that its vertex
+// with the smallest (y, x) comes first: the triangle is then stored in the orientation
+// the output uses, and emitting it needs no search.
+void Delaunay::rotate_top(int32_t& a, int32_t& b, int32_t& c) const {
+  const Pt A = pt_[a], B = pt_[b], C = pt_[c];
+  const bool b_lt_a = B.y < A.y || (B.y == A.y && B.x < A.x);
+  const bool c_lt_a = C.y < A.y || (C.y == A.y && C.x < A.x);
+  const bool c_lt_b = C.y < B.y || (C.y == B.y && C.x < B.x);
+  if (b_lt_a && !c_lt_b) {  // b first
+    const int32_t t = a;
+    a = b, b = c, c = t;
+  } else if (c_lt_a && c_lt_b) {  // c first
+    const int32_t t = c;
+    c = b, b = a, a = t;
+  }
+}
+
 int64_t Delaunay::orient(int32_t a, int32_t b, int32_t c) const {
   const Pt A = pt_[a], B = pt_[b], C = pt_[c];
   return int64_t(B.x - A.x) * int64_t(C.y - A.y) - int64_t(B.y - A.y) * int64_t(C.x - A.x);
@@ -124,6 +141,7 @@ void Delaunay::free_tri(int32_t t) {
 
 void Delaunay::start(int32_t a, int32_t b, int32_t c) {
   if (orient(a, b, c) < 0) std::swap(b, c);
+  rotate_top(a, b, c);
   const int32_t s = alloc_tri();
   const int32_t g0 = alloc_tri(), g1 = alloc_tri(), g2 = alloc_tri();
   // solid (a, b, c); edges opposite a: b->c, opposite b: c->a, opposite c: a->b
@@ -230,7 +248,11 @@ bool Delaunay::insert_point(int32_t p) {
     // (a, b, p) rotated so a ghost vertex, if any, sits in slot 2
     if (e.b == kGhost) T.v[0] = p, T.v[1] = e.a, T.v[2] = kGhost;
     else if (e.a == kGhost) T.v[0] = e.b, T.v[1] = p, T.v[2] = kGhost;
-    else T.v[0] = e.a, T.v[1] = e.b, T.v[2] = p;
+    else {
+      int32_t a = e.a, b = e.b, c = p;
+      rotate_top(a, b, c);
+      T.v[0] = a, T.v[1] = b, T.v[2] = c;
+    }
     T.nb[0] = T.nb[1] = T.nb[2] = -1;
     // across a->b: the outside neighbour
     for (int i = 0; i < 3; ++i)
@@ -356,13 +378,8 @@ void Delaunay::emit(std::vector<sm_tri>& out, bool sorted) const {
   const size_t base = out.size();
   for (size_t t = 0; t < tri_.size(); ++t) {
     if (!alive_[t] || tri_[t].v[2] == kGhost) continue;
-    const Tri& T = tri_[t];
-    int k = 0;
-    for (int i = 1; i < 3; ++i) {
-      const Pt a = pt_[T.v[i]], b = pt_[T.v[k]];
-      if (a.y < b.y || (a.y == b.y && a.x < b.x)) k = i;
-    }
-    out.push_back(sm_tri{ext_[T.v[k]], ext_[T.v[(k + 1) % 3]], ext_[T.v[(k + 2) % 3]]});
+    const Tri& T = tri_[t];  // stored with its top vertex first
+    out.push_back(sm_tri{ext_[T.v[0]], ext_[T.v[1]], ext_[T.v[2]]});
   }
   if (sorted)
     std::sort(out.begin() + base, out.end(), [](const sm_tri& x, const sm_tri& y) {
@@ -380,18 +397,9 @@ void Delaunay::emit_banded(std::vector<sm_tri>& out, int band_shift) const {
   int32_t max_band = 0;
   for (const Pt& q : pt_) max_band = std::max(max_band, q.y >> band_shift);
   band_count_.assign((size_t)max_band + 2, 0);
-  auto top_of = [&](const Tri& T) {
-    int k = 0;
-    for (int i = 1; i < 3; ++i) {
-      const Pt a = pt_[T.v[i]], b = pt_[T.v[k]];
-      if (a.y < b.y || (a.y == b.y && a.x < b.x)) k = i;
-    }
-    return k;
-  };
   for (size_t t = 0; t < tri_.size(); ++t) {
     if (!alive_[t] || tri_[t].v[2] == kGhost) continue;
-    const Tri& T = tri_[t];
-    ++band_count_[(pt_[T.v[top_of(T)]].y >> band_shift) + 1];
+    ++band_count_[(pt_[tri_[t].v[0]].y >> band_shift) + 1];  // v[0] is the top vertex
   }
   for (size_t i = 1; i < band_count_.size(); ++i) band_count_[i] += band_count_[i - 1];
   const size_t base = out.size();
@@ -399,9 +407,8 @@ void Delaunay::emit_banded(std::vector<sm_tri>& out, int band_shift) const {
   for (size_t t = 0; t < tri_.size(); ++t) {
     if (!alive_[t] || tri_[t].v[2] == kGhost) continue;
     const Tri& T = tri_[t];
-    const int k = top_of(T);
-    const int32_t slot = band_count_[pt_[T.v[k]].y >> band_shift]++;
-    out[base + slot] = sm_tri{ext_[T.v[k]], ext_[T.v[(k + 1) % 3]], ext_[T.v[(k + 2) % 3]]};
+    const int32_t slot = band_count_[pt_[T.v[0]].y >> band_shift]++;
+    out[base + slot] = sm_tri{ext_[T.v[0]], ext_[T.v[1]], ext_[T.v[2]]};
   }
 }
 

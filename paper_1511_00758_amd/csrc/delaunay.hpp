@@ -82,6 +82,7 @@ class Delaunay {
   bool insert_point(int32_t p);
   int incircle_sos(int32_t a, int32_t b, int32_t c, int32_t d) const;
   int64_t orient(int32_t a, int32_t b, int32_t c) const;
+  void rotate_top(int32_t& a, int32_t& b, int32_t& c) const;
   int64_t orient_pt(int32_t a, int32_t b, int64_t x, int64_t y) const;
 };
 
