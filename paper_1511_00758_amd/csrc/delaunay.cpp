@@ -328,9 +328,7 @@ bool Delaunay::insert(int32_t u, int32_t v, int32_t ext) {
   return true;
 }
 
-bool Delaunay::insert_many(const int32_t* u, const int32_t* v, const int32_t* ext, int32_t n) {
-  for (int32_t i = 0; i < n; ++i)
-    if (u[i] < 0 || v[i] < 0 || u[i] > 8191 || v[i] > 8191) return false;
+void Delaunay::order_points(const int32_t* u, const int32_t* v, int32_t n) {
   // Biased randomised insertion order: point i joins round k with probability 2^-(k+1)
   // (k = number of trailing one bits of a xorshift draw, capped at 15); rounds are
   // inserted from the sparsest, each in Hilbert order of 32 px cells. Key = 4 round bits
@@ -363,6 +361,12 @@ bool Delaunay::insert_many(const int32_t* u, const int32_t* v, const int32_t* ex
     key_.swap(key2_);
     idx_.swap(idx2_);
   }
+}
+
+bool Delaunay::insert_many(const int32_t* u, const int32_t* v, const int32_t* ext, int32_t n) {
+  for (int32_t i = 0; i < n; ++i)
+    if (u[i] < 0 || v[i] < 0 || u[i] > 8191 || v[i] > 8191) return false;
+  order_points(u, v, n);
   pt_.reserve(pt_.size() + n);
   ext_.reserve(ext_.size() + n);
   vstamp_.reserve(vstamp_.size() + n);

@@ -74,6 +74,7 @@ class Delaunay {
   int32_t n_solid_ = 0;
   bool started_ = false;
 
+  void order_points(const int32_t* u, const int32_t* v, int32_t n);
   int32_t alloc_tri();
   void free_tri(int32_t t);
   bool conflict(int32_t t, int32_t p) const;
