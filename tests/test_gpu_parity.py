@@ -484,3 +484,18 @@ def test_solve_selected_stage_timing(frames):
     assert st["stage_launches"]["validate"] == p.n_iters and st["stage_launches"]["raster"] == p.n_iters
     assert st["stage_launches"]["census"] == 0 and st["stage_launches"]["match"] == 0
     assert st["stage_us"]["validate"] > 0 and st["stage_us"]["census"] == 0
+
+
+def test_solve_parity_1080p_serving_frame():
+    """The largest frame of the serving workload at its full size (1920x1080, d 0-255,
+    3 iterations), end to end against the oracle (the oracle takes about a minute)."""
+    _note("solve 1920x1080 (oracle ~1 min)")
+    sc = scenes.make_rect_scene(1920, 1080, seed=5020, dlo=2.0, dhi=240.0)
+    prm = scenes.params_of(5)
+    p = oracle.Params.from_dict(prm)
+    D_f, C_f, mask, st = _solve_gpu(sc, prm)
+    ref = oracle.solve(sc.left, sc.right, p)
+    assert (C_f == ref["C_f"]).all()
+    assert (mask.astype(bool) == ref["mask"]).all()
+    assert (D_f.view(np.uint32) == ref["D_f"].view(np.uint32)).all()
+    assert st["n_valid"] == int(ref["mask"].sum())
