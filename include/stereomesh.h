@@ -79,6 +79,10 @@ typedef struct {
   int32_t fast_per_bin;        /* FAST: at most this many keypoints per bin, 1..4096;
                                   fast_bins_x * fast_bins_y * fast_per_bin <= 2^22            */
   int32_t levels;              /* disparity levels tested by cost evaluation: 1 (Alg. 2), 3, 5 */
+  int32_t host_mesh;           /* sm_solve: 0 = the tessellations after the first insert the new
+                                  supports into the mesh kept in device memory (the first one,
+                                  and any the device cannot finish, run on the host); 1 = every
+                                  tessellation on the host. Same triangles either way.        */
 } sm_params;
 
 /* Per-solve statistics. `timing` is an input: when non-zero, sm_solve records a pair of
@@ -96,6 +100,7 @@ typedef enum {
   SM_ST_VALIDATE = 4,        /* cost evaluation + refinement                                 */
   SM_ST_REMATCH = 5,         /* resampling: cells -> confident supports + re-matched pixels  */
   SM_ST_FAST = 6,            /* FAST scores + per-bin keypoint selection (support_mode 1)     */
+  SM_ST_MESH = 7,            /* device Delaunay insertion of resampled supports (iters >= 2)   */
   SM_ST_HOST_TRI = 12,       /* host triangulation (wall time)                               */
   SM_ST_HOST_COPY = 13,      /* host<->device copies and waits (wall time)                   */
   SM_ST_TOTAL = 14           /* whole sm_solve call (wall time)                              */
@@ -108,6 +113,8 @@ typedef struct {
   int64_t n_valid;                      /* [out] pixels in the final mask             */
   float stage_us[SM_STAGES];            /* [out] see above                            */
   int32_t stage_launches[SM_STAGES];    /* [out] kernel launches per stage            */
+  int32_t mesh_device;                  /* [out] tessellations done on the device      */
+  int32_t mesh_fallback;                /* [out] device tessellations redone on the host */
 } sm_stats;
 
 /*

@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "SM_OK", -1: "SM_ERR_ARG", -2: "SM_ERR_CAPACITY", -3: "SM_ERR
                 -4: "SM_ERR_INTERNAL"}
 # sm_stage indices of sm_stats.stage_us / stage_launches
 STAGES = {"census": 0, "match": 1, "compact": 2, "raster": 3, "validate": 4, "rematch": 5,
-          "fast": 6, "host_triangulate": 12, "host_copies": 13, "total": 14}
+          "fast": 6, "mesh": 7, "host_triangulate": 12, "host_copies": 13, "total": 14}
 N_STAGES = 16
 TIME_SELECTED = 0x40000000
 
@@ -44,10 +44,10 @@ class SmTri(ctypes.Structure):
 
 PARAM_FIELDS = ("d_min", "d_max", "census_w", "census_h", "support_step", "n_iters", "t_hi",
                 "t_lo", "grad_thr", "lr_tol", "uniqueness", "sz_occ0", "support_mode",
-                "fast_threshold", "fast_bins_x", "fast_bins_y", "fast_per_bin", "levels")
+                "fast_threshold", "fast_bins_x", "fast_bins_y", "fast_per_bin", "levels", "host_mesh")
 # the paper-variant fields default to the grid candidates and Alg. 2's single level
 PARAM_DEFAULTS = {"support_mode": 0, "fast_threshold": 16, "fast_bins_x": 12, "fast_bins_y": 10,
-                  "fast_per_bin": 25, "levels": 1}
+                  "fast_per_bin": 25, "levels": 1, "host_mesh": 0}
 
 
 class SmParams(ctypes.Structure):
@@ -57,7 +57,8 @@ class SmParams(ctypes.Structure):
 class SmStats(ctypes.Structure):
     _fields_ = [("timing", c_i32), ("n_support", c_i32 * 8), ("n_tris", c_i32 * 8),
                 ("n_valid", c_i64), ("stage_us", c_f32 * N_STAGES),
-                ("stage_launches", c_i32 * N_STAGES)]
+                ("stage_launches", c_i32 * N_STAGES), ("mesh_device", c_i32),
+                ("mesh_fallback", c_i32)]
 
 
 class SmFrame(ctypes.Structure):

@@ -191,6 +191,8 @@ def stats_dict(st: "_lib.SmStats", n_iters: int) -> dict:
         "n_valid": int(st.n_valid),
         "stage_us": {k: float(st.stage_us[i]) for k, i in _lib.STAGES.items()},
         "stage_launches": {k: int(st.stage_launches[i]) for k, i in _lib.STAGES.items()},
+        "mesh_device": int(st.mesh_device),
+        "mesh_fallback": int(st.mesh_fallback),
     }
 
 

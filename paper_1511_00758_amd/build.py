@@ -28,6 +28,7 @@ SOURCES = [
     ("kernels.hip", "hip"),
     ("api.cpp", "hip"),
     ("batch.cpp", "hip"),
+    ("mesh.hip", "hip"),
     ("delaunay.cpp", "host"),
 ]
 

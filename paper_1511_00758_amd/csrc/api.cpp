@@ -47,6 +47,7 @@ sm_status check_params(const sm_params* p) {
   if (p->sz_occ0 < 1 || p->sz_occ0 > 1024) return fail(SM_ERR_ARG, "sz_occ0 must be in [1, 1024]");
   if (p->support_mode != 0 && p->support_mode != 1) return fail(SM_ERR_ARG, "support_mode must be 0 or 1");
   if (p->levels != 1 && p->levels != 3 && p->levels != 5) return fail(SM_ERR_ARG, "levels must be 1, 3 or 5");
+  if (p->host_mesh != 0 && p->host_mesh != 1) return fail(SM_ERR_ARG, "host_mesh must be 0 or 1");
   if (p->support_mode == 1) SM_TRY(check_fast_params(p));
   return SM_OK;
 }
@@ -198,6 +199,14 @@ Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
   L.T = take((size_t)L.T_cap * sizeof(sm_tri));
   L.counters = take(64);
   L.score = p.support_mode == 1 ? take(npx) : 0;  // FAST scores
+  // device mesh of the tessellations after the first (records of the whole frame)
+  L.mesh_on = p.n_iters >= 2 && p.host_mesh == 0;
+  if (L.mesh_on) {
+    L.mpcap = 0;
+    for (int it = 1; it < p.n_iters; ++it) L.mpcap = std::max(L.mpcap, 2 * cells_of(W, H, occ_size(p, it)));
+    L.mstatus = take(64);
+    L.mwork = take(mesh_work_bytes(W, H, L.S_cap, L.mpcap));
+  }
   L.total = o;
   return L;
 }
@@ -398,12 +407,17 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   sm_tri* Td = (sm_tri*)(base + Lo.T);
   int32_t* counters = (int32_t*)(base + Lo.counters);
   unsigned long long* n_valid = (unsigned long long*)(base + Lo.counters + 32);
-  const size_t stage_bytes =
-      std::max((size_t)Lo.S_cap * sizeof(sm_support), (size_t)Lo.T_cap * sizeof(sm_tri)) + 64;
-  SM_TRY(ensure_pinned(c, stage_bytes));
+  // pinned staging: [counts | supports or triangles | exported mesh | mesh status]
+  const MeshWork mw = Lo.mesh_on ? mesh_work_at(base + Lo.mwork, W, H, Lo.S_cap, Lo.mpcap) : MeshWork{};
+  const size_t st_main = align256(std::max((size_t)Lo.S_cap * sizeof(sm_support), (size_t)Lo.T_cap * sizeof(sm_tri)));
+  const size_t st_mesh = Lo.mesh_on ? align256((size_t)mw.cap * 12) : 0;
+  SM_TRY(ensure_pinned(c, 256 + st_main + 2 * st_mesh + 64));
   int32_t* h_count = (int32_t*)c.pinned;
-  sm_support* h_S = (sm_support*)((uint8_t*)c.pinned + 64);
-  sm_tri* h_T = (sm_tri*)((uint8_t*)c.pinned + 64);
+  sm_support* h_S = (sm_support*)((uint8_t*)c.pinned + 256);
+  sm_tri* h_T = (sm_tri*)((uint8_t*)c.pinned + 256);
+  int32_t* h_mtv = (int32_t*)((uint8_t*)c.pinned + 256 + st_main);
+  int32_t* h_mtnb = (int32_t*)((uint8_t*)c.pinned + 256 + st_main + st_mesh);
+  int32_t* h_mstatus = (int32_t*)((uint8_t*)c.pinned + 256 + st_main + 2 * st_mesh);
   Timer tm(c.timer, s, timing);
   float us_host = 0.f, us_xfer = 0.f;
 
@@ -452,7 +466,9 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   if (n_S < 0 || n_S > Lo.n_grid) return fail(SM_ERR_INTERNAL, "support count %d out of range", n_S);
 
   int32_t n_T = 0;
+  int32_t host_upto = 0;  // supports S[0, host_upto) are in the host triangulation c.dl
   auto triangulate_and_upload = [&](int32_t from, int32_t to) -> sm_status {
+    host_upto = to;
     auto th = clk::now();
     try {
       if (from == 0) c.dl.reset();
@@ -488,6 +504,28 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   };
   SM_TRY(triangulate_and_upload(0, n_S));
 
+  // the tessellations after the first insert their supports into the mesh kept in device
+  // memory (the triangulation is unique, so the triangles are the host's)
+  int32_t* d_mstatus = Lo.mesh_on ? (int32_t*)(base + Lo.mstatus) : nullptr;
+  bool mesh_dev = false;
+  if (Lo.mesh_on) {
+    auto th = clk::now();
+    const int32_t n_rec = c.dl.export_mesh(h_mtv, h_mtnb, mw.cap);
+    us_host += us_since(th);
+    if (n_rec < 0) return fail(SM_ERR_INTERNAL, "mesh capacity exceeded");
+    if (n_rec > 0) {  // else fewer than three independent supports so far: stay on the host
+      for (int k = 0; k < 8; ++k) h_mstatus[k] = 0;
+      h_mstatus[kMeshRecords] = n_rec;
+      h_mstatus[kMeshFresh] = 1;
+      SM_HIP(hipMemcpyAsync(mw.tv, h_mtv, (size_t)n_rec * 12, hipMemcpyHostToDevice, s));
+      SM_HIP(hipMemcpyAsync(mw.tnb, h_mtnb, (size_t)n_rec * 12, hipMemcpyHostToDevice, s));
+      SM_HIP(hipMemcpyAsync(d_mstatus, h_mstatus, 32, hipMemcpyHostToDevice, s));
+      SM_HIP(hipEventRecord(c.copy_done, s));
+      c.copy_pending = true;
+      mesh_dev = true;
+    }
+  }
+
   for (int it = 1; it <= p->n_iters; ++it) {
     const int32_t sz = occ_size(*p, it);
     const bool last = it == p->n_iters;
@@ -515,6 +553,46 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     SM_TRY(tm.begin(SM_ST_COMPACT));
     SM_HIP(launch_compact(region, 2 * cells, &counters[1], occ, W, (int32_t*)(region + 2 * cells), s));
     SM_TRY(tm.end());
+    if (mesh_dev) {
+      MeshJob job;
+      job.S = Sd;
+      job.p0 = n_S;
+      job.n_new = (const int32_t*)(region + 2 * cells);
+      job.status = d_mstatus;
+      job.T = Td;
+      job.T_cap = Lo.T_cap;
+      job.W = W;
+      job.H = H;
+      job.w = mw;
+      SM_TRY(tm.begin(SM_ST_MESH));
+      SM_HIP(launch_mesh_insert(job, s));
+      SM_TRY(tm.end());
+      t0 = clk::now();
+      SM_HIP(hipMemcpyAsync(h_mstatus, d_mstatus, 32, hipMemcpyDeviceToHost, s));
+      SM_HIP(hipStreamSynchronize(s));
+      us_xfer += us_since(t0);
+      const int32_t n_new = h_mstatus[kMeshNew];
+      if (n_new < 0 || n_new > 2 * cells) return fail(SM_ERR_INTERNAL, "resample count %d out of range", n_new);
+      if (h_mstatus[kMeshErr] == 0) {
+        n_T = h_mstatus[kMeshTris];
+        if (n_T < 0 || n_T > Lo.T_cap) return fail(SM_ERR_INTERNAL, "device triangle count %d out of range", n_T);
+        n_S += n_new;
+        if (st) ++st->mesh_device;
+        continue;
+      }
+      // the device could not finish (capacity, or a support outside the mesh): bring every
+      // support the host has not seen and triangulate on the host from here on
+      if (st) ++st->mesh_fallback;
+      mesh_dev = false;
+      t0 = clk::now();
+      const int32_t m = n_S + n_new - host_upto;
+      SM_HIP(hipMemcpyAsync(h_S, Sd + host_upto, (size_t)m * sizeof(sm_support), hipMemcpyDeviceToHost, s));
+      SM_HIP(hipStreamSynchronize(s));
+      us_xfer += us_since(t0);
+      SM_TRY(triangulate_and_upload(host_upto, n_S + n_new));
+      n_S += n_new;
+      continue;
+    }
     t0 = clk::now();
     SM_HIP(hipMemcpyAsync(h_S, region, (size_t)(2 * cells + 1) * sizeof(sm_support), hipMemcpyDeviceToHost, s));
     SM_HIP(hipStreamSynchronize(s));

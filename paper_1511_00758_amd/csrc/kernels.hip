@@ -23,6 +23,12 @@ void set_launch_events(hipEvent_t start, hipEvent_t stop) {
   g_ev_stop = stop;
 }
 bool launch_events_pending() { return g_ev_start != nullptr; }
+bool take_launch_events(hipEvent_t* start, hipEvent_t* stop) {
+  *start = g_ev_start;
+  *stop = g_ev_stop;
+  g_ev_start = g_ev_stop = nullptr;
+  return *start != nullptr;
+}
 
 #define SM_LAUNCH(kernel, grid, block, shmem, stream, ...)                                  \
   do {                                                                                     \

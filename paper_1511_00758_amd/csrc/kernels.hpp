@@ -15,6 +15,8 @@ namespace sm {
 // events then bracket that kernel's execution); pending tells whether it is unused.
 void set_launch_events(hipEvent_t start, hipEvent_t stop);
 bool launch_events_pending();
+// Hands the armed pair to a launcher outside kernels.hip (and disarms it); false if none.
+bool take_launch_events(hipEvent_t* start, hipEvent_t* stop);
 
 // Marker values in sm_support::d for candidate slots (real disparities are >= 0).
 constexpr float kPending = -1.0f;   // candidate waiting to be matched
@@ -100,6 +102,55 @@ hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t
 hipError_t launch_resample(const uint64_t* cL, const uint64_t* cR, const uint64_t* cell_g,
                            const uint64_t* cell_b, const float* D_it, int32_t W, int32_t H, int32_t sz,
                            const sm_params& p, sm_support* slots, hipStream_t s);
+
+// ---------------------------------------------------------------------------------
+// Device Delaunay insertion (mesh.hip): the supports S[p0, p0 + n_new) join the mesh of
+// the frame, whose records (the host triangulation's form, vertices as support indices,
+// ghosts included) stay in the MeshWork arrays from one tessellation to the next; the
+// solid triangles of the result go to T, top vertex first. One 1024-thread workgroup per
+// job.
+// ---------------------------------------------------------------------------------
+struct MeshWork {  // per-frame arrays: records [cap], new points [pcap], coordinates [S_cap]
+  int32_t *tv, *tnb, *own, *kids, *dead, *fk, *fs, *fj, *work0, *work1;
+  uint64_t *vote, *fkey;
+  int32_t *ploc, *pk, *psib, *pend0, *pend1;
+  uint64_t* pkey;
+  int32_t* uv;    // packed coordinates when they do not fit in LDS
+  int32_t* hint;  // location hints, one per 16 x 16 px cell
+  int32_t cap, pcap, S_cap;
+};
+
+// Mesh status words (device, 8 x int32):
+//   [0] records in use (in/out; the host writes the count of an exported mesh)
+//   [1] triangles written to T (out)
+//   [2] error code (out; 0 = ok, else the records are unusable and the caller
+//       triangulates on the host)
+//   [3] rounds used so far by the frame (in/out; keys of later rounds must be lower)
+//   [4] number of new supports read from n_new (out)
+//   [5] 1 when records [0, [0]) were just written by the host (in; cleared)
+enum { kMeshRecords = 0, kMeshTris = 1, kMeshErr = 2, kMeshRounds = 3, kMeshNew = 4, kMeshFresh = 5 };
+
+struct MeshJob {
+  const sm_support* S;
+  int32_t p0;             // first new support
+  const int32_t* n_new;   // device count of new supports
+  int32_t* status;        // device [8]
+  sm_tri* T;
+  int32_t T_cap;
+  int32_t W, H;
+  MeshWork w;
+};
+
+// Record capacity for a frame of at most S_cap supports (about 5 records per support are
+// used; a frame that needs more falls back to the host), bytes of its MeshWork, and the
+// carving of a 256-byte aligned block of that size.
+int32_t mesh_work_cap(int32_t S_cap);
+size_t mesh_work_bytes(int32_t W, int32_t H, int32_t S_cap, int32_t pcap);
+MeshWork mesh_work_at(void* base, int32_t W, int32_t H, int32_t S_cap, int32_t pcap);
+
+hipError_t launch_mesh_insert(const MeshJob& job, hipStream_t s);
+// one workgroup per job of the device array `jobs`
+hipError_t launch_mesh_insert_many(const MeshJob* jobs, int32_t n, hipStream_t s);
 
 // ---------------------------------------------------------------------------------
 // Stage-batched solve of many frames: every stage is one launch over all frames. The

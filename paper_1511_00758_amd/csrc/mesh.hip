@@ -1,0 +1,315 @@
+// Device Delaunay insertion of the resampled supports (tessellation of Sec. III-A for the
+// iterations after the first, Alg. 1): the mesh of a frame stays in device memory between
+// iterations, so the supports, the mesh and the triangles never cross to the host.
+//
+// One 1024-thread workgroup runs the whole insertion of a frame (the per-item steps are in
+// mesh_core.hpp): packed coordinates into LDS, location hints, a visibility walk per new
+// point, rounds of propose / execute separated by workgroup barriers, then the output of
+// the live solid triangles. The records of a VGA frame (a few thousand) stay in L2; the
+// rounds are latency-bound (a dozen per tessellation, most of them with a few dozen items)
+// and one workgroup per frame lets a batch of frames share the chip.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "mesh_core.hpp"
+
+namespace sm {
+
+namespace {
+
+constexpr int kMeshThreads = 1024;
+constexpr int kHintShift = 4;        // 16 x 16 px hint cells
+constexpr int kHintBoxCells = 64;    // a record marks every cell of its box up to this many
+constexpr int32_t kUvLds = 32768;    // supports whose coordinates fit in LDS (128 KiB)
+
+// Atomics of the per-item steps. Votes are read and written only with atomics at device
+// scope, so that no stale L1 line is ever read; counters and the error code live in LDS.
+struct DevA {
+  __device__ static void vote_min(uint64_t* p, uint64_t v) {
+    atomicMin((unsigned long long*)p, (unsigned long long)v);
+  }
+  __device__ static uint64_t vote_get(const uint64_t* p) {
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __device__ static void vote_set(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __device__ static int32_t push(int32_t* n, int32_t k) { return atomicAdd(n, k); }
+  __device__ static void fail(int32_t* err, int32_t code) { atomicCAS(err, 0, code); }
+};
+
+__device__ void mesh_insert_block(const MeshJob& a) {
+  using namespace mesh;
+  __shared__ int32_t s_uv[kUvLds];
+  __shared__ int32_t s_np[2], s_nw[2], s_nrec, s_err, s_any, s_ntri;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const MeshWork& w = a.w;
+  // every thread reads the same control words, so the early exits below are uniform
+  const int32_t n_rec0 = a.status[kMeshRecords];
+  const int32_t base_round = a.status[kMeshRounds];
+  const bool fresh = a.status[kMeshFresh] != 0;
+  const int32_t n_new = *a.n_new;
+  const int32_t n_pts = a.p0 + n_new;
+  __syncthreads();
+  if (tid == 0) {
+    a.status[kMeshNew] = n_new;
+    a.status[kMeshFresh] = 0;
+  }
+  if (n_rec0 <= 0 || n_rec0 > w.cap || n_new < 0 || n_new > w.pcap || a.p0 < 3 || n_pts > w.S_cap ||
+      base_round < 0 || base_round >= kMaxRounds) {
+    if (tid == 0) a.status[kMeshErr] = kErrCapacity;
+    return;
+  }
+  if (tid == 0) {
+    s_np[0] = n_new;
+    s_nw[0] = 0;
+    s_np[1] = s_nw[1] = 0;
+    s_nrec = n_rec0;
+    s_err = 0;
+    s_any = -1;
+    s_ntri = 0;
+  }
+  const int32_t gw = (a.W + 15) >> kHintShift, gh = (a.H + 15) >> kHintShift;
+  int32_t* uv = n_pts <= kUvLds ? s_uv : w.uv;
+  Mesh m;
+  m.uv = uv;
+  m.tv = w.tv;
+  m.tnb = w.tnb;
+  m.own = w.own;
+  m.kids = w.kids;
+  m.dead = w.dead;
+  m.vote = w.vote;
+  m.fk = w.fk;
+  m.fs = w.fs;
+  m.fj = w.fj;
+  m.fkey = w.fkey;
+  m.cap = w.cap;
+  m.p0 = a.p0;
+  m.ploc = w.ploc;
+  m.pk = w.pk;
+  m.psib = w.psib;
+  m.pkey = w.pkey;
+  __syncthreads();
+
+  // packed coordinates (range-checked: the predicates are exact for [0, 8191]); records
+  // just written by the host are checked and initialised; hints cleared
+  for (int32_t p = tid; p < n_pts; p += kMeshThreads) {
+    const sm_support P = a.S[p];
+    if (P.u < 0 || P.v < 0 || P.u >= a.W || P.v >= a.H) {
+      DevA::fail(&s_err, kErrIndex);
+      uv[p] = 0;
+    } else {
+      uv[p] = pack_uv(P.u, P.v);
+    }
+  }
+  if (fresh) {
+    for (int32_t t = tid; t < n_rec0; t += kMeshThreads) {
+      bool ok = true;
+      for (int k = 0; k < 3; ++k) {
+        const int32_t v = w.tv[3 * t + k], nb = w.tnb[3 * t + k];
+        ok &= (v >= 0 && v < a.p0) || (k == 2 && v == kGhost);
+        ok &= nb >= 0 && nb < n_rec0;
+      }
+      if (!ok) DevA::fail(&s_err, kErrIndex);
+      w.dead[t] = 0;
+      DevA::vote_set(&w.vote[t], ~0ull);
+    }
+  }
+  for (int32_t c = tid; c < gw * gh; c += kMeshThreads) w.hint[c] = -1;
+  __syncthreads();
+
+  // hints: every cell of a live solid record's bounding box (the vertex cells of a record
+  // whose box is large) points at it
+  if (s_err == 0) {
+    for (int32_t t = tid; t < n_rec0; t += kMeshThreads) {
+      if (w.dead[t] || w.tv[3 * t + 2] == kGhost) continue;
+      const P2 A = xy(m, w.tv[3 * t]), B = xy(m, w.tv[3 * t + 1]), C = xy(m, w.tv[3 * t + 2]);
+      const int x0 = min(min(A.x, B.x), C.x) >> kHintShift, x1 = max(max(A.x, B.x), C.x) >> kHintShift;
+      const int y0 = min(min(A.y, B.y), C.y) >> kHintShift, y1 = max(max(A.y, B.y), C.y) >> kHintShift;
+      if ((x1 - x0 + 1) * (y1 - y0 + 1) <= kHintBoxCells) {
+        for (int y = y0; y <= y1; ++y)
+          for (int x = x0; x <= x1; ++x) w.hint[y * gw + x] = t;
+      } else {
+        w.hint[(A.y >> kHintShift) * gw + (A.x >> kHintShift)] = t;
+        w.hint[(B.y >> kHintShift) * gw + (B.x >> kHintShift)] = t;
+        w.hint[(C.y >> kHintShift) * gw + (C.x >> kHintShift)] = t;
+      }
+      atomicMax(&s_any, t);
+    }
+  }
+  __syncthreads();
+
+  // locate every new point by a visibility walk from the hint of its cell
+  if (s_err == 0 && s_any >= 0) {
+    for (int32_t i = tid; i < n_new; i += kMeshThreads) {
+      const P2 q = xy(m, a.p0 + i);
+      int32_t h = w.hint[(q.y >> kHintShift) * gw + (q.x >> kHintShift)];
+      if (h < 0) h = s_any;
+      const int32_t t = walk(m, h, q, n_rec0, n_rec0 + 16);
+      if (t < 0) {
+        DevA::fail(&s_err, t == -2 ? kErrOutside : kErrWalk);
+        continue;
+      }
+      w.ploc[i] = t;
+      w.pk[i] = kInside;
+      w.pend0[i] = i;
+    }
+  } else if (tid == 0 && s_any < 0) {
+    DevA::fail(&s_err, kErrIndex);
+  }
+
+  // rounds of propose / execute; the control values are read between two barriers, so
+  // that every thread takes the same decision before any thread can change them
+  int cur = 0, round = 0;
+  for (;; ++round) {
+    __syncthreads();
+    const int32_t np = s_np[cur], nw = s_nw[cur], n_rec = s_nrec, err = s_err;
+    __syncthreads();
+    if (err != 0 || np + nw == 0) break;
+    const int32_t gr = base_round + round;
+    if (gr >= kMaxRounds) {
+      if (tid == 0) s_err = kErrRounds;
+      break;
+    }
+    int32_t* pend = cur ? w.pend1 : w.pend0;
+    int32_t* work = cur ? w.work1 : w.work0;
+    int32_t* pend_next = cur ? w.pend0 : w.pend1;
+    int32_t* work_next = cur ? w.work0 : w.work1;
+    for (int32_t it = tid; it < np + nw; it += kMeshThreads) {
+      if (it < np) propose_point<DevA>(m, pend[it], gr, n_rec, &s_err);
+      else propose_flip<DevA>(m, work[it - np], gr, n_rec, &s_err);
+    }
+    if (tid == 0) s_np[cur ^ 1] = s_nw[cur ^ 1] = 0;  // last read before the previous round's work
+    __syncthreads();
+    if (s_err == 0) {  // items only: no barrier depends on this test
+      for (int32_t it = tid; it < np + nw; it += kMeshThreads) {
+        if (it < np)
+          execute_point<DevA>(m, pend[it], &s_nrec, pend_next, &s_np[cur ^ 1], w.pcap, work_next,
+                              &s_nw[cur ^ 1], w.cap, &s_err);
+        else
+          execute_flip<DevA>(m, work[it - np], &s_nrec, work_next, &s_nw[cur ^ 1], w.cap, &s_err);
+      }
+    }
+    cur ^= 1;
+  }
+  __syncthreads();
+  if (s_err != 0) {
+    if (tid == 0) {
+      a.status[kMeshErr] = s_err;
+      a.status[kMeshRounds] = base_round + round;
+    }
+    return;
+  }
+
+  // output: live solid records, one atomic per wave for their slots
+  const int32_t n_rec = s_nrec;
+  for (int32_t t0 = 0; t0 < n_rec; t0 += kMeshThreads) {
+    const int32_t t = t0 + tid;
+    const bool out = t < n_rec && !w.dead[t] && w.tv[3 * t + 2] != kGhost;
+    const unsigned long long mask = __ballot(out);
+    int slot = 0;
+    if (lane == 0 && mask) slot = atomicAdd(&s_ntri, __popcll(mask));
+    slot = __shfl(slot, 0) + __popcll(mask & ((1ull << lane) - 1ull));
+    if (out) {
+      if (slot < a.T_cap) a.T[slot] = top_first(m, t);
+      else DevA::fail(&s_err, kErrCapacity);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a.status[kMeshRecords] = n_rec;
+    a.status[kMeshTris] = s_ntri;
+    a.status[kMeshErr] = s_err;
+    a.status[kMeshRounds] = base_round + round;
+  }
+}
+
+__global__ __launch_bounds__(kMeshThreads) void k_mesh_insert(MeshJob a) { mesh_insert_block(a); }
+
+__global__ __launch_bounds__(kMeshThreads) void k_mesh_insert_many(const MeshJob* jobs) {
+  mesh_insert_block(jobs[blockIdx.x]);
+}
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Carve {
+  size_t o = 0;
+  uint8_t* base = nullptr;
+  template <class T>
+  T* take(size_t n) {
+    T* p = base ? (T*)(base + o) : nullptr;
+    o = align256(o + n * sizeof(T));
+    return p;
+  }
+};
+
+MeshWork carve(Carve& c, int32_t W, int32_t H, int32_t S_cap, int32_t pcap) {
+  MeshWork w;
+  const int32_t cap = mesh_work_cap(S_cap);
+  const size_t nc = (size_t)cap, np = (size_t)pcap;
+  w.tv = c.take<int32_t>(3 * nc);
+  w.tnb = c.take<int32_t>(3 * nc);
+  w.own = c.take<int32_t>(3 * nc);
+  w.kids = c.take<int32_t>(4 * nc);
+  w.dead = c.take<int32_t>(nc);
+  w.fk = c.take<int32_t>(nc);
+  w.fs = c.take<int32_t>(nc);
+  w.fj = c.take<int32_t>(nc);
+  w.work0 = c.take<int32_t>(nc);
+  w.work1 = c.take<int32_t>(nc);
+  w.vote = c.take<uint64_t>(nc);
+  w.fkey = c.take<uint64_t>(nc);
+  w.ploc = c.take<int32_t>(np);
+  w.pk = c.take<int32_t>(np);
+  w.psib = c.take<int32_t>(np);
+  w.pend0 = c.take<int32_t>(np);
+  w.pend1 = c.take<int32_t>(np);
+  w.pkey = c.take<uint64_t>(np);
+  w.uv = c.take<int32_t>((size_t)S_cap);
+  w.hint = c.take<int32_t>((size_t)((W + 15) >> kHintShift) * ((H + 15) >> kHintShift));
+  w.cap = cap;
+  w.pcap = pcap;
+  w.S_cap = S_cap;
+  return w;
+}
+
+}  // namespace
+
+int32_t mesh_work_cap(int32_t S_cap) {
+  const int64_t cap = 8 * (int64_t)S_cap + 4096;
+  return (int32_t)(cap > (1 << 30) ? (1 << 30) : cap);
+}
+
+size_t mesh_work_bytes(int32_t W, int32_t H, int32_t S_cap, int32_t pcap) {
+  Carve c;
+  carve(c, W, H, S_cap, pcap);
+  return c.o;
+}
+
+MeshWork mesh_work_at(void* base, int32_t W, int32_t H, int32_t S_cap, int32_t pcap) {
+  Carve c;
+  c.base = (uint8_t*)base;
+  return carve(c, W, H, S_cap, pcap);
+}
+
+hipError_t launch_mesh_insert(const MeshJob& job, hipStream_t s) {
+  hipEvent_t e0, e1;
+  if (take_launch_events(&e0, &e1))
+    hipExtLaunchKernelGGL(k_mesh_insert, dim3(1), dim3(kMeshThreads), 0, s, e0, e1, 0u, job);
+  else
+    hipLaunchKernelGGL(k_mesh_insert, dim3(1), dim3(kMeshThreads), 0, s, job);
+  return hipGetLastError();
+}
+
+hipError_t launch_mesh_insert_many(const MeshJob* jobs, int32_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipEvent_t e0, e1;
+  if (take_launch_events(&e0, &e1))
+    hipExtLaunchKernelGGL(k_mesh_insert_many, dim3((unsigned)n), dim3(kMeshThreads), 0, s, e0, e1, 0u, jobs);
+  else
+    hipLaunchKernelGGL(k_mesh_insert_many, dim3((unsigned)n), dim3(kMeshThreads), 0, s, jobs);
+  return hipGetLastError();
+}
+
+}  // namespace sm

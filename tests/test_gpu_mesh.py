@@ -1,0 +1,108 @@
+"""Device mesh insertion (the tessellations after the first, Sec. III-A / Alg. 1) against the
+host triangulation: the perturbed Delaunay triangulation is unique, so a solve whose later
+tessellations run on the device must give the same triangle counts and bit-identical
+outputs as one that triangulates every iteration on the host; the solve parity tests
+compare the device path with the oracle as well."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import scenes
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _note(*a):
+    print("[gpu-mesh]", *a, file=sys.stderr, flush=True)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _solve(sc, prm):
+    from paper_1511_00758_amd import api
+    H, W = sc.left.shape
+    r = api.Solver(W, H, prm, device=DEV)(_dev(sc.left), _dev(sc.right), stats=True)
+    torch.cuda.synchronize()
+    return r.D_f.cpu().numpy(), r.C_f.cpu().numpy(), r.mask.cpu().numpy(), r.stats
+
+
+def _check(sc, prm):
+    dev = _solve(sc, dict(prm, host_mesh=0))
+    host = _solve(sc, dict(prm, host_mesh=1))
+    n_iters = prm["n_iters"]
+    assert dev[3]["n_support"] == host[3]["n_support"]
+    assert dev[3]["n_tris"] == host[3]["n_tris"]
+    for a, b in zip(dev[:3], host[:3]):
+        assert (a.view(np.uint8) == b.view(np.uint8)).all()
+    assert host[3]["mesh_device"] == 0
+    assert dev[3]["mesh_fallback"] == 0
+    if dev[3]["n_tris"][0] > 0:
+        assert dev[3]["mesh_device"] == n_iters - 1
+    return dev[3]
+
+
+@pytest.mark.parametrize("cfg,frame", [(2, 0), (2, 1), (2, 2), (3, 0), (3, 2)])
+def test_device_mesh_equals_host(cfg, frame):
+    _note("scene", cfg, frame)
+    sc = scenes.make_scene(cfg, scenes.seed_of(cfg, frame))
+    _check(sc, sc.params)
+
+
+@pytest.mark.parametrize("n_iters,sz0", [(5, 32), (7, 16), (8, 8)])
+def test_device_mesh_deep_iterations(n_iters, sz0):
+    """Many iterations down to 1 px cells: dense batches of new supports, many of them in
+    the same triangle and on shared edges."""
+    _note("deep", n_iters, sz0)
+    sc = scenes.make_rect_scene(200, 150, seed=n_iters * 31 + sz0, n_rects=8, dlo=2.0, dhi=40.0)
+    prm = dict(scenes.params_of(2), n_iters=n_iters, sz_occ0=sz0, d_max=63, t_hi=10, t_lo=8)
+    st = _check(sc, prm)
+    assert st["n_support"][-1] > st["n_support"][0]
+
+
+def test_device_mesh_loose_thresholds():
+    """t_lo = t_hi: every validated cell with a good pixel adds a support, so the later
+    batches are large and tie-heavy (supports on a regular lattice of cells)."""
+    _note("loose")
+    sc = scenes.make_scene(2, scenes.seed_of(2, 4), t_hi=24, t_lo=24)
+    _check(sc, sc.params)
+
+
+def test_device_mesh_fast_supports():
+    """Irregular first mesh: FAST keypoints from spatial bins instead of the grid."""
+    _note("fast")
+    sc = scenes.make_scene(2, scenes.seed_of(2, 5))
+    _check(sc, dict(sc.params, support_mode=1, fast_threshold=12))
+
+
+@pytest.mark.parametrize("W,H", [(1280, 720), (1920, 1080)])
+def test_device_mesh_serving_sizes(W, H):
+    """The serving workload's larger frames (d 0-255, 3 iterations): tens of thousands of
+    supports in the last tessellation."""
+    _note("serving", W, H)
+    sc = scenes.make_rect_scene(W, H, seed=W + 7, dlo=2.0, dhi=240.0)
+    st = _check(sc, scenes.params_of(5))
+    assert st["n_support"][-1] > 10000 or W < 1920
+
+
+def test_device_mesh_repeated_solves_reuse_workspace():
+    """One solver, frames of different content in a row: nothing of the previous frame's
+    mesh survives in the workspace."""
+    from paper_1511_00758_amd import api
+    _note("reuse")
+    frames = [scenes.make_scene(2, scenes.seed_of(2, f)) for f in (6, 7, 6)]
+    H, W = frames[0].left.shape
+    solver = api.Solver(W, H, frames[0].params, device=DEV)
+    outs = []
+    for sc in frames:
+        r = solver(_dev(sc.left), _dev(sc.right), stats=True)
+        torch.cuda.synchronize()
+        outs.append((r.D_f.cpu().numpy().copy(), r.stats["n_tris"]))
+    ref = _solve(frames[0], dict(frames[0].params, host_mesh=1))
+    assert outs[0][1] == ref[3]["n_tris"] == outs[2][1]
+    assert (outs[0][0].view(np.uint32) == ref[0].view(np.uint32)).all()
+    assert (outs[2][0].view(np.uint32) == outs[0][0].view(np.uint32)).all()

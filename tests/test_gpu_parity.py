@@ -396,6 +396,10 @@ def _compare_solve(sc, p, res, tr):
     assert np.abs(D_f - tr["D_f"]).max() <= TOL_PX
     assert (D_f.view(np.uint32) == tr["D_f"].view(np.uint32)).all()
     assert st["n_valid"] == int(tr["mask"].sum())
+    # every tessellation after the first ran on the device once the first mesh existed
+    assert st["mesh_fallback"] == 0
+    if p.n_iters >= 2 and len(tr["iters"][0]["tris"]) > 0:
+        assert st["mesh_device"] == p.n_iters - 1
 
 
 @pytest.mark.parametrize("cfg", [1, 2, 3])
