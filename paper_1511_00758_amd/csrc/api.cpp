@@ -508,21 +508,19 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   // memory (the triangulation is unique, so the triangles are the host's)
   int32_t* d_mstatus = Lo.mesh_on ? (int32_t*)(base + Lo.mstatus) : nullptr;
   bool mesh_dev = false;
+  int32_t mesh_init = 0;  // records of the exported mesh, read by the first device insertion
   if (Lo.mesh_on) {
     auto th = clk::now();
     const int32_t n_rec = c.dl.export_mesh(h_mtv, h_mtnb, mw.cap);
     us_host += us_since(th);
     if (n_rec < 0) return fail(SM_ERR_INTERNAL, "mesh capacity exceeded");
     if (n_rec > 0) {  // else fewer than three independent supports so far: stay on the host
-      for (int k = 0; k < 8; ++k) h_mstatus[k] = 0;
-      h_mstatus[kMeshRecords] = n_rec;
-      h_mstatus[kMeshFresh] = 1;
       SM_HIP(hipMemcpyAsync(mw.tv, h_mtv, (size_t)n_rec * 12, hipMemcpyHostToDevice, s));
       SM_HIP(hipMemcpyAsync(mw.tnb, h_mtnb, (size_t)n_rec * 12, hipMemcpyHostToDevice, s));
-      SM_HIP(hipMemcpyAsync(d_mstatus, h_mstatus, 32, hipMemcpyHostToDevice, s));
       SM_HIP(hipEventRecord(c.copy_done, s));
       c.copy_pending = true;
       mesh_dev = true;
+      mesh_init = n_rec;
     }
   }
 
@@ -558,7 +556,12 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
       job.S = Sd;
       job.p0 = n_S;
       job.n_new = (const int32_t*)(region + 2 * cells);
+      job.init_tv = mw.tv;
+      job.init_tnb = mw.tnb;
+      job.init_n = mesh_init;
+      mesh_init = 0;
       job.status = d_mstatus;
+      job.status_copy = nullptr;
       job.T = Td;
       job.T_cap = Lo.T_cap;
       job.W = W;

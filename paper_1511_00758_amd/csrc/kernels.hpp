@@ -121,20 +121,23 @@ struct MeshWork {  // per-frame arrays: records [cap], new points [pcap], coordi
 };
 
 // Mesh status words (device, 8 x int32):
-//   [0] records in use (in/out; the host writes the count of an exported mesh)
-//   [1] triangles written to T (out)
-//   [2] error code (out; 0 = ok, else the records are unusable and the caller
-//       triangulates on the host)
-//   [3] rounds used so far by the frame (in/out; keys of later rounds must be lower)
-//   [4] number of new supports read from n_new (out)
-//   [5] 1 when records [0, [0]) were just written by the host (in; cleared)
-enum { kMeshRecords = 0, kMeshTris = 1, kMeshErr = 2, kMeshRounds = 3, kMeshNew = 4, kMeshFresh = 5 };
+//   [0] records in use
+//   [1] triangles written to T
+//   [2] error code (0 = ok, else the records are unusable and the caller triangulates on
+//       the host)
+//   [3] rounds used so far by the frame (keys of later rounds must bid lower)
+//   [4] number of new supports read from n_new
+enum { kMeshRecords = 0, kMeshTris = 1, kMeshErr = 2, kMeshRounds = 3, kMeshNew = 4 };
 
 struct MeshJob {
   const sm_support* S;
-  int32_t p0;             // first new support
-  const int32_t* n_new;   // device count of new supports
-  int32_t* status;        // device [8]
+  int32_t p0;               // first new support
+  const int32_t* n_new;     // device count of new supports
+  const int32_t* init_tv;   // init_n > 0: the frame's first mesh (records in host form) to
+  const int32_t* init_tnb;  //   start from, vertices < p0; may alias w.tv / w.tnb
+  int32_t init_n;
+  int32_t* status;          // device [8], read (unless init_n > 0) and written
+  int32_t* status_copy;     // nullable: device [8], a copy of the words written
   sm_tri* T;
   int32_t T_cap;
   int32_t W, H;

@@ -46,19 +46,22 @@ __device__ void mesh_insert_block(const MeshJob& a) {
   const int tid = threadIdx.x, lane = tid & 63;
   const MeshWork& w = a.w;
   // every thread reads the same control words, so the early exits below are uniform
-  const int32_t n_rec0 = a.status[kMeshRecords];
-  const int32_t base_round = a.status[kMeshRounds];
-  const bool fresh = a.status[kMeshFresh] != 0;
+  const bool fresh = a.init_n > 0;
+  const int32_t n_rec0 = fresh ? a.init_n : a.status[kMeshRecords];
+  const int32_t base_round = fresh ? 0 : a.status[kMeshRounds];
   const int32_t n_new = *a.n_new;
   const int32_t n_pts = a.p0 + n_new;
+  auto finish = [&](int32_t n_rec, int32_t n_tri, int32_t err, int32_t rounds) {  // thread 0
+    const int32_t words[8] = {n_rec, n_tri, err, rounds, n_new, 0, 0, 0};
+    for (int k = 0; k < 8; ++k) {
+      a.status[k] = words[k];
+      if (a.status_copy) a.status_copy[k] = words[k];
+    }
+  };
   __syncthreads();
-  if (tid == 0) {
-    a.status[kMeshNew] = n_new;
-    a.status[kMeshFresh] = 0;
-  }
   if (n_rec0 <= 0 || n_rec0 > w.cap || n_new < 0 || n_new > w.pcap || a.p0 < 3 || n_pts > w.S_cap ||
       base_round < 0 || base_round >= kMaxRounds) {
-    if (tid == 0) a.status[kMeshErr] = kErrCapacity;
+    if (tid == 0) finish(n_rec0, 0, kErrCapacity, base_round);
     return;
   }
   if (tid == 0) {
@@ -107,9 +110,11 @@ __device__ void mesh_insert_block(const MeshJob& a) {
     for (int32_t t = tid; t < n_rec0; t += kMeshThreads) {
       bool ok = true;
       for (int k = 0; k < 3; ++k) {
-        const int32_t v = w.tv[3 * t + k], nb = w.tnb[3 * t + k];
+        const int32_t v = a.init_tv[3 * t + k], nb = a.init_tnb[3 * t + k];
         ok &= (v >= 0 && v < a.p0) || (k == 2 && v == kGhost);
         ok &= nb >= 0 && nb < n_rec0;
+        w.tv[3 * t + k] = v;
+        w.tnb[3 * t + k] = nb;
       }
       if (!ok) DevA::fail(&s_err, kErrIndex);
       w.dead[t] = 0;
@@ -195,10 +200,7 @@ __device__ void mesh_insert_block(const MeshJob& a) {
   }
   __syncthreads();
   if (s_err != 0) {
-    if (tid == 0) {
-      a.status[kMeshErr] = s_err;
-      a.status[kMeshRounds] = base_round + round;
-    }
+    if (tid == 0) finish(s_nrec, 0, s_err, base_round + round);
     return;
   }
 
@@ -217,12 +219,7 @@ __device__ void mesh_insert_block(const MeshJob& a) {
     }
   }
   __syncthreads();
-  if (tid == 0) {
-    a.status[kMeshRecords] = n_rec;
-    a.status[kMeshTris] = s_ntri;
-    a.status[kMeshErr] = s_err;
-    a.status[kMeshRounds] = base_round + round;
-  }
+  if (tid == 0) finish(n_rec, s_ntri, s_err, base_round + round);
 }
 
 __global__ __launch_bounds__(kMeshThreads) void k_mesh_insert(MeshJob a) { mesh_insert_block(a); }

@@ -140,8 +140,9 @@ __host__ __device__ inline int incircle_sos(P2 a, P2 b, P2 c, P2 d) {
   return cof > 0 ? 1 : (cof < 0 ? -1 : 0);
 }
 
-// Bid of round r: newer rounds bid lower than every older bid left in vote[]; flips (cls 0)
-// go before splits (cls 1); then the priority, then the id, which makes keys unique.
+// Bid of round r: newer rounds bid lower than every older bid left in vote[]; splits (cls 0)
+// go before flips (cls 1), which inserts the points in fewer rounds; then the priority,
+// then the id, which makes keys unique.
 __host__ __device__ inline uint64_t make_key(int32_t round, int32_t cls, uint32_t prio, uint32_t id) {
   return ((uint64_t)(4095 - round) << 52) | ((uint64_t)cls << 51) | ((uint64_t)(prio & 0x7ffffu) << 32) | id;
 }
@@ -247,7 +248,7 @@ __host__ __device__ inline void propose_point(const Mesh& m, int32_t i, int32_t 
   const int64_t cy = (int64_t)V0.y + V1.y + V2.y - 3 * q.y;
   const uint64_t d2 = (uint64_t)(cx * cx + cy * cy);
   const uint32_t prio = d2 >= (1ull << 31) ? 0x7ffffu : (uint32_t)(d2 >> 12);
-  const uint64_t key = make_key(round, 1, prio, (uint32_t)i);
+  const uint64_t key = make_key(round, 0, prio, (uint32_t)i);
   m.pkey[i] = key;
   if (zeros == 0) {
     m.pk[i] = kInside;
@@ -292,7 +293,7 @@ __host__ __device__ inline void propose_flip(const Mesh& m, int32_t t, int32_t r
   else if (c2 != kGhost && incircle_sos(V0, V1, V2, xy(m, sel3(j2, c0, c1, c2))) > 0) bid = 2;
   if (bid < 0) return;
   const int32_t sb = sel3(bid, s0, s1, s2);
-  const uint64_t key = make_key(round, 0, 0, (uint32_t)(3 * t + bid));
+  const uint64_t key = make_key(round, 1, 0, (uint32_t)(3 * t + bid));
   m.fk[t] = bid;
   m.fs[t] = sb;
   m.fj[t] = sel3(bid, j0, j1, j2);

@@ -109,3 +109,33 @@ def test_many_rejects_fast_frames_before_work(mixed):
     l, r, prm = mixed[2]
     with pytest.raises((_lib.StereoMeshError, ValueError)):
         api.ManySolver(2, device=DEV)([(_dev(l), _dev(r), prm), (_dev(l), _dev(r), dict(prm, support_mode=1))])
+
+
+def test_many_device_mesh_equals_host_mesh(mixed):
+    """The later tessellations of a batch inserted on the device (one workgroup per frame,
+    one launch per iteration) give the same outputs as host triangulation, also with
+    device and host frames mixed in one batch."""
+    from paper_1511_00758_amd import api
+    ms = api.ManySolver(8, device=DEV)
+    runs = {}
+    for mode in ("device", "host", "mixed"):
+        _note("many mesh", mode)
+        frames = []
+        for i, (l, r, prm) in enumerate(mixed):
+            hm = {"device": 0, "host": 1, "mixed": i % 2}[mode]
+            frames.append((_dev(l), _dev(r), dict(prm, host_mesh=hm)))
+        outs, st = ms(frames, stats=True, timing=True)
+        torch.cuda.synchronize()
+        runs[mode] = ([tuple(t.cpu().numpy() for t in o) for o in outs], st)
+    dev_out, dev_st = runs["device"]
+    for mode in ("host", "mixed"):
+        out, st = runs[mode]
+        assert st["n_tris"] == dev_st["n_tris"] and st["n_support"] == dev_st["n_support"]
+        for a, b in zip(dev_out, out):
+            assert (a[0].view(np.uint32) == b[0].view(np.uint32)).all()
+            assert (a[1] == b[1]).all() and (a[2] == b[2]).all()
+    # every multi-iteration frame with a first mesh inserted its later supports on the device
+    expect = sum(prm["n_iters"] - 1 for (l, r, prm) in mixed if prm["n_iters"] >= 2 and l.std() > 0)
+    assert dev_st["mesh_device"] == expect and dev_st["mesh_fallback"] == 0
+    assert runs["host"][1]["mesh_device"] == 0
+    assert dev_st["stage_launches"]["mesh"] == 2
