@@ -10,6 +10,7 @@
 
 #include "delaunay.hpp"
 #include "kernels.hpp"
+#include "mesh.hpp"
 #include "sm_common.hpp"
 #include "stereomesh.h"
 

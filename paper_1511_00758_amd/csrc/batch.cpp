@@ -16,6 +16,7 @@
 
 #include "delaunay.hpp"
 #include "kernels.hpp"
+#include "mesh.hpp"
 #include "pool.hpp"
 #include "sm_common.hpp"
 #include "stereomesh.h"

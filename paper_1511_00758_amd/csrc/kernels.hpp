@@ -104,58 +104,6 @@ hipError_t launch_resample(const uint64_t* cL, const uint64_t* cR, const uint64_
                            const sm_params& p, sm_support* slots, hipStream_t s);
 
 // ---------------------------------------------------------------------------------
-// Device Delaunay insertion (mesh.hip): the supports S[p0, p0 + n_new) join the mesh of
-// the frame, whose records (the host triangulation's form, vertices as support indices,
-// ghosts included) stay in the MeshWork arrays from one tessellation to the next; the
-// solid triangles of the result go to T, top vertex first. One 1024-thread workgroup per
-// job.
-// ---------------------------------------------------------------------------------
-struct MeshWork {  // per-frame arrays: records [cap], new points [pcap], coordinates [S_cap]
-  int32_t *tv, *tnb, *own, *kids, *dead, *fk, *fs, *fj, *work0, *work1;
-  uint64_t *vote, *fkey;
-  int32_t *ploc, *pk, *psib, *pend0, *pend1;
-  uint64_t* pkey;
-  int32_t* uv;    // packed coordinates when they do not fit in LDS
-  int32_t* hint;  // location hints, one per 16 x 16 px cell
-  int32_t cap, pcap, S_cap;
-};
-
-// Mesh status words (device, 8 x int32):
-//   [0] records in use
-//   [1] triangles written to T
-//   [2] error code (0 = ok, else the records are unusable and the caller triangulates on
-//       the host)
-//   [3] rounds used so far by the frame (keys of later rounds must bid lower)
-//   [4] number of new supports read from n_new
-enum { kMeshRecords = 0, kMeshTris = 1, kMeshErr = 2, kMeshRounds = 3, kMeshNew = 4 };
-
-struct MeshJob {
-  const sm_support* S;
-  int32_t p0;               // first new support
-  const int32_t* n_new;     // device count of new supports
-  const int32_t* init_tv;   // init_n > 0: the frame's first mesh (records in host form) to
-  const int32_t* init_tnb;  //   start from, vertices < p0; may alias w.tv / w.tnb
-  int32_t init_n;
-  int32_t* status;          // device [8], read (unless init_n > 0) and written
-  int32_t* status_copy;     // nullable: device [8], a copy of the words written
-  sm_tri* T;
-  int32_t T_cap;
-  int32_t W, H;
-  MeshWork w;
-};
-
-// Record capacity for a frame of at most S_cap supports (about 5 records per support are
-// used; a frame that needs more falls back to the host), bytes of its MeshWork, and the
-// carving of a 256-byte aligned block of that size.
-int32_t mesh_work_cap(int32_t S_cap);
-size_t mesh_work_bytes(int32_t W, int32_t H, int32_t S_cap, int32_t pcap);
-MeshWork mesh_work_at(void* base, int32_t W, int32_t H, int32_t S_cap, int32_t pcap);
-
-hipError_t launch_mesh_insert(const MeshJob& job, hipStream_t s);
-// one workgroup per job of the device array `jobs`
-hipError_t launch_mesh_insert_many(const MeshJob* jobs, int32_t n, hipStream_t s);
-
-// ---------------------------------------------------------------------------------
 // Stage-batched solve of many frames: every stage is one launch over all frames. The
 // batched kernels read per-frame arguments from a device array of BatchFrame and map
 // their work units (blocks or waves) to frames through a prefix array `off` of n + 1

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "mesh.hpp"
 #include "mesh_core.hpp"
 
 namespace sm {
