@@ -43,10 +43,21 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def algorithmic_work(kernel, W, H, p, n_iters, launches):
+def algorithmic_work(kernel, W, H, p, n_iters, launches, stats=None):
     """Algorithmic work of ONE launch of ``kernel`` on a W x H frame (average over the
     launches of one solve), as (bound, amount, unit_scale, unit, per_unit_note)."""
     npx = W * H
+    if kernel == "mesh":
+        # one insertion (tessellations 2..n): the supports read (8 B each), the live mesh
+        # records read and written once (tv + tnb, 24 B each, about one per triangle) and
+        # the triangles written (12 B each); a single workgroup whose rounds are bound by
+        # dependent-load latency, so the fraction of HBM peak is tiny by construction
+        if not stats or n_iters < 2:
+            return None
+        per = [8.0 * stats["n_support"][k] + 60.0 * stats["n_tris"][k] for k in range(1, n_iters)]
+        amount = sum(per) / len(per)
+        return "hbm", amount, 1e9, "GB/s", (f"mean over tessellations 2..{n_iters}: 8 B x supports + "
+                                            f"(2 x 24 + 12) B x triangles = {amount / 1e3:.1f} kB")
     bits = p["census_w"] * p["census_h"] - 1
     if kernel == "census":
         # 2 images x (1 B read + 8 B census word written) -- but compute-bound:
@@ -64,8 +75,8 @@ def algorithmic_work(kernel, W, H, p, n_iters, launches):
     return None
 
 
-def roofline_for(kernel, avg_us, W, H, p, n_iters, launches, traffic=None):
-    work = algorithmic_work(kernel, W, H, p, n_iters, launches)
+def roofline_for(kernel, avg_us, W, H, p, n_iters, launches, traffic=None, stats=None):
+    work = algorithmic_work(kernel, W, H, p, n_iters, launches, stats)
     if work is None or avg_us <= 0:
         return None
     bound, amount, scale, unit, note = work
@@ -395,7 +406,7 @@ def main():
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the 7680x4320 interpolation/validation roofline probe")
     ap.add_argument("--time-all", action="store_true",
-                    help="time every kernel of the solve with events (default: validate and raster)")
+                    help="time every kernel of the solve with events (default: validate, raster and the mesh insertion)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FAST-support / 3-level variants of the 640x480 workload")
     ap.add_argument("--probe-only", action="store_true",
@@ -438,7 +449,7 @@ def main():
     solver = api.Solver(W, H, params, device=dev)
     # live per-kernel timing of the roofline kernels (events around every launch would
     # slow the whole frame by ~10%; --time-all times every kernel)
-    timing = False if args.no_timing else (True if args.time_all else ("validate", "raster"))
+    timing = False if args.no_timing else (True if args.time_all else ("validate", "raster", "mesh"))
 
     for k in range(args.warmup):
         l, r = dframes[k % len(dframes)]
@@ -482,7 +493,7 @@ def main():
         dom = max(kernels, key=lambda k: kernels[k]["us_per_step"])
         roof = roofline_for(dom, kernels[dom]["avg_us"], W, H, params, params["n_iters"],
                             kernels[dom]["launches_per_step"],
-                            traffic=load_traffic(dom, "vga_20planes"))
+                            traffic=load_traffic(dom, "vga_20planes"), stats=st)
         # the validation kernel, whose roofline the design targets, reported beside it
         if "validate" in kernels and dom != "validate":
             roof_val = roofline_for("validate", kernels["validate"]["avg_us"], W, H, params,

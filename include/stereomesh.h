@@ -299,7 +299,10 @@ typedef struct {
  *   each with its own stream and workspace, take frames from a shared counter and run
  *   sm_solve on them, so that the host triangulation of one frame overlaps the kernels
  *   and triangulations of the others. Each frame's result is identical to sm_solve of
- *   that frame alone. The workers persist between calls made by the same thread.
+ *   that frame alone. The workers persist between calls made by the same thread. With
+ *   more than one worker the frames triangulate on the host (p.host_mesh is taken as 1:
+ *   a device insertion is one long single-workgroup kernel per tessellation, and those of
+ *   many streams would serialise on the device's hardware queues).
  *   frames     [host] [n] frames; status, worker and latency_us are written.
  *   streams    [host] [n_workers] hipStream_t per worker (as void*).
  *   ws, ws_bytes [host] [n_workers] workspace per worker; each must cover

@@ -71,7 +71,11 @@ extern "C" sm_status sm_solve_batch(sm_frame* frames, int32_t n, void* const* st
       sm_stats one;
       std::memset(&one, 0, sizeof(one));
       one.timing = wst[k].timing;
-      f.status = sm_solve(f.L, f.R, f.W, f.H, f.stride, &f.p, ws[k], ws_bytes[k], f.D_f, f.C_f, f.mask,
+      // concurrent workers triangulate on the host: a device insertion is one long
+      // single-workgroup kernel, and those of many streams serialise on the hardware queues
+      sm_params p = f.p;
+      if (workers > 1) p.host_mesh = 1;
+      f.status = sm_solve(f.L, f.R, f.W, f.H, f.stride, &p, ws[k], ws_bytes[k], f.D_f, f.C_f, f.mask,
                           st ? &one : nullptr, streams[k]);
       f.worker = k;
       f.latency_us = std::chrono::duration<float, std::micro>(std::chrono::steady_clock::now() - t0).count();

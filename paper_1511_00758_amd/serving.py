@@ -120,14 +120,19 @@ class StereoServer:
     ``specs[stream]`` gives each camera stream's frame size and method parameters.
     ``on_done(req, D_f, C_f, mask)`` is called on the worker thread after the frame's
     outputs are complete (device tensors of the stream's resident state, valid until
-    that stream's next frame)."""
+    that stream's next frame). ``device_mesh`` False (the default) triangulates every
+    tessellation on the host: slots overlap that with other frames' kernels, whereas a
+    device insertion is one long single-workgroup kernel per tessellation and those of
+    many slots would serialise on the device's hardware queues."""
 
     def __init__(self, specs: Dict[int, StreamSpec], n_slots: int, budget_bytes: int,
-                 device="cuda:0", on_done=None):
+                 device="cuda:0", on_done=None, device_mesh: bool = False):
         import torch
         from . import api
         self._torch = torch
         self._api = api
+        specs = {s: StreamSpec(sp.W, sp.H, dict(sp.params, host_mesh=0 if device_mesh else 1))
+                 for s, sp in specs.items()}
         self.specs = specs
         self.device = device
         self.on_done = on_done
