@@ -24,8 +24,13 @@ constexpr int kHintShift = 4;        // 16 x 16 px hint cells
 constexpr int kHintBoxCells = 64;    // a record marks every cell of its box up to this many
 constexpr int32_t kUvLds = 32768;    // supports whose coordinates fit in LDS (128 KiB)
 
+// Packed coordinates of the frame's supports when they fit (one workgroup per CU).
+__shared__ int32_t g_uv[kUvLds];
+
 // Atomics of the per-item steps. Votes are read and written only with atomics at device
 // scope, so that no stale L1 line is ever read; counters and the error code live in LDS.
+// Coordinates come from LDS (kLds) or from the global copy.
+template <bool kLds>
 struct DevA {
   __device__ static void vote_min(uint64_t* p, uint64_t v) {
     atomicMin((unsigned long long*)p, (unsigned long long)v);
@@ -38,11 +43,13 @@ struct DevA {
   }
   __device__ static int32_t push(int32_t* n, int32_t k) { return atomicAdd(n, k); }
   __device__ static void fail(int32_t* err, int32_t code) { atomicCAS(err, 0, code); }
+  __device__ static int32_t uv(const mesh::Mesh& m, int32_t p) { return kLds ? g_uv[p] : m.uv[p]; }
 };
 
-__device__ void mesh_insert_block(const MeshJob& a) {
+template <bool kLds>
+__device__ void mesh_insert_block(const MeshJob& a, int32_t n_new) {
   using namespace mesh;
-  __shared__ int32_t s_uv[kUvLds];
+  using DA = DevA<kLds>;
   __shared__ int32_t s_np[2], s_nw[2], s_nrec, s_err, s_any, s_ntri;
   const int tid = threadIdx.x, lane = tid & 63;
   const MeshWork& w = a.w;
@@ -50,7 +57,6 @@ __device__ void mesh_insert_block(const MeshJob& a) {
   const bool fresh = a.init_n > 0;
   const int32_t n_rec0 = fresh ? a.init_n : a.status[kMeshRecords];
   const int32_t base_round = fresh ? 0 : a.status[kMeshRounds];
-  const int32_t n_new = *a.n_new;
   const int32_t n_pts = a.p0 + n_new;
   auto finish = [&](int32_t n_rec, int32_t n_tri, int32_t err, int32_t rounds) {  // thread 0
     const int32_t words[8] = {n_rec, n_tri, err, rounds, n_new, 0, 0, 0};
@@ -75,9 +81,9 @@ __device__ void mesh_insert_block(const MeshJob& a) {
     s_ntri = 0;
   }
   const int32_t gw = (a.W + 15) >> kHintShift, gh = (a.H + 15) >> kHintShift;
-  int32_t* uv = n_pts <= kUvLds ? s_uv : w.uv;
+  int32_t* uv = kLds ? g_uv : w.uv;
   Mesh m;
-  m.uv = uv;
+  m.uv = w.uv;
   m.tv = w.tv;
   m.tnb = w.tnb;
   m.own = w.own;
@@ -101,7 +107,7 @@ __device__ void mesh_insert_block(const MeshJob& a) {
   for (int32_t p = tid; p < n_pts; p += kMeshThreads) {
     const sm_support P = a.S[p];
     if (P.u < 0 || P.v < 0 || P.u >= a.W || P.v >= a.H) {
-      DevA::fail(&s_err, kErrIndex);
+      DA::fail(&s_err, kErrIndex);
       uv[p] = 0;
     } else {
       uv[p] = pack_uv(P.u, P.v);
@@ -117,9 +123,9 @@ __device__ void mesh_insert_block(const MeshJob& a) {
         w.tv[3 * t + k] = v;
         w.tnb[3 * t + k] = nb;
       }
-      if (!ok) DevA::fail(&s_err, kErrIndex);
+      if (!ok) DA::fail(&s_err, kErrIndex);
       w.dead[t] = 0;
-      DevA::vote_set(&w.vote[t], ~0ull);
+      DA::vote_set(&w.vote[t], ~0ull);
     }
   }
   for (int32_t c = tid; c < gw * gh; c += kMeshThreads) w.hint[c] = -1;
@@ -130,7 +136,7 @@ __device__ void mesh_insert_block(const MeshJob& a) {
   if (s_err == 0) {
     for (int32_t t = tid; t < n_rec0; t += kMeshThreads) {
       if (w.dead[t] || w.tv[3 * t + 2] == kGhost) continue;
-      const P2 A = xy(m, w.tv[3 * t]), B = xy(m, w.tv[3 * t + 1]), C = xy(m, w.tv[3 * t + 2]);
+      const P2 A = xy<DA>(m, w.tv[3 * t]), B = xy<DA>(m, w.tv[3 * t + 1]), C = xy<DA>(m, w.tv[3 * t + 2]);
       const int x0 = min(min(A.x, B.x), C.x) >> kHintShift, x1 = max(max(A.x, B.x), C.x) >> kHintShift;
       const int y0 = min(min(A.y, B.y), C.y) >> kHintShift, y1 = max(max(A.y, B.y), C.y) >> kHintShift;
       if ((x1 - x0 + 1) * (y1 - y0 + 1) <= kHintBoxCells) {
@@ -149,12 +155,12 @@ __device__ void mesh_insert_block(const MeshJob& a) {
   // locate every new point by a visibility walk from the hint of its cell
   if (s_err == 0 && s_any >= 0) {
     for (int32_t i = tid; i < n_new; i += kMeshThreads) {
-      const P2 q = xy(m, a.p0 + i);
+      const P2 q = xy<DA>(m, a.p0 + i);
       int32_t h = w.hint[(q.y >> kHintShift) * gw + (q.x >> kHintShift)];
       if (h < 0) h = s_any;
-      const int32_t t = walk(m, h, q, n_rec0, n_rec0 + 16);
+      const int32_t t = walk<DA>(m, h, q, n_rec0, n_rec0 + 16);
       if (t < 0) {
-        DevA::fail(&s_err, t == -2 ? kErrOutside : kErrWalk);
+        DA::fail(&s_err, t == -2 ? kErrOutside : kErrWalk);
         continue;
       }
       w.ploc[i] = t;
@@ -162,7 +168,7 @@ __device__ void mesh_insert_block(const MeshJob& a) {
       w.pend0[i] = i;
     }
   } else if (tid == 0 && s_any < 0) {
-    DevA::fail(&s_err, kErrIndex);
+    DA::fail(&s_err, kErrIndex);
   }
 
   // rounds of propose / execute; the control values are read between two barriers, so
@@ -183,18 +189,18 @@ __device__ void mesh_insert_block(const MeshJob& a) {
     int32_t* pend_next = cur ? w.pend0 : w.pend1;
     int32_t* work_next = cur ? w.work0 : w.work1;
     for (int32_t it = tid; it < np + nw; it += kMeshThreads) {
-      if (it < np) propose_point<DevA>(m, pend[it], gr, n_rec, &s_err);
-      else propose_flip<DevA>(m, work[it - np], gr, n_rec, &s_err);
+      if (it < np) propose_point<DA>(m, pend[it], gr, n_rec, &s_err);
+      else propose_flip<DA>(m, work[it - np], gr, n_rec, &s_err);
     }
     if (tid == 0) s_np[cur ^ 1] = s_nw[cur ^ 1] = 0;  // last read before the previous round's work
     __syncthreads();
     if (s_err == 0) {  // items only: no barrier depends on this test
       for (int32_t it = tid; it < np + nw; it += kMeshThreads) {
         if (it < np)
-          execute_point<DevA>(m, pend[it], &s_nrec, pend_next, &s_np[cur ^ 1], w.pcap, work_next,
+          execute_point<DA>(m, pend[it], &s_nrec, pend_next, &s_np[cur ^ 1], w.pcap, work_next,
                               &s_nw[cur ^ 1], w.cap, &s_err);
         else
-          execute_flip<DevA>(m, work[it - np], &s_nrec, work_next, &s_nw[cur ^ 1], w.cap, &s_err);
+          execute_flip<DA>(m, work[it - np], &s_nrec, work_next, &s_nw[cur ^ 1], w.cap, &s_err);
       }
     }
     cur ^= 1;
@@ -215,18 +221,24 @@ __device__ void mesh_insert_block(const MeshJob& a) {
     if (lane == 0 && mask) slot = atomicAdd(&s_ntri, __popcll(mask));
     slot = __shfl(slot, 0) + __popcll(mask & ((1ull << lane) - 1ull));
     if (out) {
-      if (slot < a.T_cap) a.T[slot] = top_first(m, t);
-      else DevA::fail(&s_err, kErrCapacity);
+      if (slot < a.T_cap) a.T[slot] = top_first<DA>(m, t);
+      else DA::fail(&s_err, kErrCapacity);
     }
   }
   __syncthreads();
   if (tid == 0) finish(n_rec, s_ntri, s_err, base_round + round);
 }
 
-__global__ __launch_bounds__(kMeshThreads) void k_mesh_insert(MeshJob a) { mesh_insert_block(a); }
+__device__ void mesh_insert(const MeshJob& a) {
+  const int32_t n_new = *a.n_new;  // the same for every thread: the branch is uniform
+  if ((int64_t)a.p0 + n_new <= kUvLds) mesh_insert_block<true>(a, n_new);
+  else mesh_insert_block<false>(a, n_new);
+}
+
+__global__ __launch_bounds__(kMeshThreads) void k_mesh_insert(MeshJob a) { mesh_insert(a); }
 
 __global__ __launch_bounds__(kMeshThreads) void k_mesh_insert_many(const MeshJob* jobs) {
-  mesh_insert_block(jobs[blockIdx.x]);
+  mesh_insert(jobs[blockIdx.x]);
 }
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -275,8 +287,8 @@ MeshWork carve(Carve& c, int32_t W, int32_t H, int32_t S_cap, int32_t pcap) {
 }  // namespace
 
 int32_t mesh_work_cap(int32_t S_cap) {
-  const int64_t cap = 8 * (int64_t)S_cap + 4096;
-  return (int32_t)(cap > (1 << 30) ? (1 << 30) : cap);
+  const int64_t cap = 8 * (int64_t)S_cap + 4096;  // work-list entries keep record ids below 2^28
+  return (int32_t)(cap > (1 << 28) ? (1 << 28) : cap);
 }
 
 size_t mesh_work_bytes(int32_t W, int32_t H, int32_t S_cap, int32_t pcap) {

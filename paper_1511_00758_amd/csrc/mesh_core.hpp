@@ -15,7 +15,12 @@
 //   execute  every bid that holds all its triangles is carried out: a point splits its
 //            triangle 1 -> 3 or its edge 2 -> 4 (on a hull edge the ghost splits into two
 //            ghosts), an illegal edge is flipped; the other bidders retry in the next round
-//            and the new solid triangles join the work list.
+//            and the new solid triangles join the work list with the edges they must test.
+// Edges that cannot be illegal are not tested: the spokes of a 1 -> 3 split (the new
+// point lies inside the old circumcircle, so each spoke's opposite vertex lies outside the
+// circle through the spoke's triangle) and the new diagonal of a flip. An edge's status
+// changes only when one of its two triangles is replaced, and every other edge of a new
+// triangle is tested, so no illegal edge is missed.
 // Keys carry the round number (a newer round bids lower than anything left in vote[]), so
 // votes need no clearing; the smallest key of a round holds all its triangles, so every
 // round makes progress. Rounds end when no point is pending and no edge is illegal: every
@@ -91,8 +96,10 @@ struct P2 {
 __host__ __device__ inline int nxt(int k) { return k == 2 ? 0 : k + 1; }
 __host__ __device__ inline int prv(int k) { return k == 0 ? 2 : k - 1; }
 __host__ __device__ inline int sgn64(int64_t x) { return (x > 0) - (x < 0); }
+// Coordinates of vertex p, read through the policy A (LDS or global on the device).
+template <class A>
 __host__ __device__ inline P2 xy(const Mesh& m, int32_t p) {
-  const int32_t w = m.uv[p];
+  const int32_t w = A::uv(m, p);
   return P2{w & 0xffff, (int32_t)((uint32_t)w >> 16)};
 }
 __host__ __device__ inline int32_t pack_uv(int32_t u, int32_t v) { return u | (v << 16); }
@@ -111,6 +118,16 @@ __host__ __device__ inline int32_t orient(P2 a, P2 b, P2 q) {
 // smallest raster position (v, u)) first: d/dz_a = +orient(b, c, d), d/dz_b = -orient(a, c, d),
 // d/dz_c = +orient(a, b, d), d/dz_d = -orient(a, b, c).
 __host__ __device__ inline int incircle_sos(P2 a, P2 b, P2 c, P2 d) {
+  {  // filter: in double the minors are exact (< 2^41) and the determinant is off by <= 7
+    const double fadx = a.x - d.x, fady = a.y - d.y, fbdx = b.x - d.x, fbdy = b.y - d.y;
+    const double fcdx = c.x - d.x, fcdy = c.y - d.y;
+    const double fal = fadx * fadx + fady * fady, fbl = fbdx * fbdx + fbdy * fbdy;
+    const double fcl = fcdx * fcdx + fcdy * fcdy;
+    const double fdet = fadx * (fbdy * fcl - fcdy * fbl) - fady * (fbdx * fcl - fcdx * fbl) +
+                        fal * (fbdx * fcdy - fcdx * fbdy);
+    if (fdet > 64.0) return 1;
+    if (fdet < -64.0) return -1;
+  }
   const int64_t adx = a.x - d.x, ady = a.y - d.y;
   const int64_t bdx = b.x - d.x, bdy = b.y - d.y;
   const int64_t cdx = c.x - d.x, cdy = c.y - d.y;
@@ -177,14 +194,16 @@ __host__ __device__ inline int32_t resolve(const Mesh& m, int32_t t, int k, int3
 }
 
 // True when point q lies in the closed solid record t.
+template <class A>
 __host__ __device__ inline bool contains(const Mesh& m, int32_t t, P2 q) {
   const int32_t* v = m.tv + 3 * t;
   if (v[2] == kGhost) return false;
-  const P2 A = xy(m, v[0]), B = xy(m, v[1]), C = xy(m, v[2]);
-  return orient(B, C, q) >= 0 && orient(C, A, q) >= 0 && orient(A, B, q) >= 0;
+  const P2 P = xy<A>(m, v[0]), B = xy<A>(m, v[1]), C = xy<A>(m, v[2]);
+  return orient(B, C, q) >= 0 && orient(C, P, q) >= 0 && orient(P, B, q) >= 0;
 }
 
 // The live record containing point q, starting from record t (possibly dead), or -1.
+template <class A>
 __host__ __device__ inline int32_t locate_live(const Mesh& m, int32_t t, P2 q, int32_t n_rec) {
   while (true) {
     if (!rec_ok(t, n_rec)) return -1;
@@ -193,7 +212,7 @@ __host__ __device__ inline int32_t locate_live(const Mesh& m, int32_t t, P2 q, i
     for (int c = 0; c < 4 && next < 0; ++c) {
       const int32_t k = m.kids[4 * t + c];
       if (k < 0) break;
-      if (k > t && rec_ok(k, n_rec) && contains(m, k, q)) next = k;
+      if (k > t && rec_ok(k, n_rec) && contains<A>(m, k, q)) next = k;
     }
     t = next;
   }
@@ -202,16 +221,17 @@ __host__ __device__ inline int32_t locate_live(const Mesh& m, int32_t t, P2 q, i
 // Visibility walk from live record t to a solid record whose closed interior holds q.
 // Returns the record, -1 on an error, -2 when q lies outside the hull. The walk ends in a
 // Delaunay mesh; max_steps guards against a broken one.
+template <class A>
 __host__ __device__ inline int32_t walk(const Mesh& m, int32_t t, P2 q, int32_t n_rec, int32_t max_steps) {
   for (int32_t step = 0; step < max_steps; ++step) {
     if (!rec_ok(t, n_rec)) return -1;
     const int32_t* v = m.tv + 3 * t;
     if (v[2] == kGhost) return -2;
-    const P2 A = xy(m, v[0]), B = xy(m, v[1]), C = xy(m, v[2]);
+    const P2 P = xy<A>(m, v[0]), B = xy<A>(m, v[1]), C = xy<A>(m, v[2]);
     int k;
     if (orient(B, C, q) < 0) k = 0;
-    else if (orient(C, A, q) < 0) k = 1;
-    else if (orient(A, B, q) < 0) k = 2;
+    else if (orient(C, P, q) < 0) k = 1;
+    else if (orient(P, B, q) < 0) k = 2;
     else return t;
     t = resolve(m, t, k, n_rec);
   }
@@ -225,16 +245,17 @@ __host__ __device__ inline int32_t walk(const Mesh& m, int32_t t, P2 q, int32_t 
 //   static void vote_set(uint64_t* p, uint64_t v);   store read by later vote_min / vote_get
 //   static int32_t push(int32_t* n, int32_t k);      atomic add, returns the old value
 //   static void fail(int32_t* err, int32_t code);    records an error
+//   static int32_t uv(const Mesh& m, int32_t p);     packed coordinates of vertex p
 
 // propose, pending point p0 + i.
 template <class A>
 __host__ __device__ inline void propose_point(const Mesh& m, int32_t i, int32_t round, int32_t n_rec, int32_t* err) {
-  const P2 q = xy(m, m.p0 + i);
-  const int32_t t = locate_live(m, m.ploc[i], q, n_rec);
+  const P2 q = xy<A>(m, m.p0 + i);
+  const int32_t t = locate_live<A>(m, m.ploc[i], q, n_rec);
   if (t < 0) return A::fail(err, kErrLocate);
   m.ploc[i] = t;
   const int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
-  const P2 V0 = xy(m, v0), V1 = xy(m, v1), V2 = xy(m, v2);
+  const P2 V0 = xy<A>(m, v0), V1 = xy<A>(m, v1), V2 = xy<A>(m, v2);
   const int32_t o0 = orient(V1, V2, q), o1 = orient(V2, V0, q), o2 = orient(V0, V1, q);
   if (o0 < 0 || o1 < 0 || o2 < 0) return A::fail(err, kErrLocate);
   const int zeros = (o0 == 0) + (o1 == 0) + (o2 == 0);
@@ -263,43 +284,39 @@ __host__ __device__ inline void propose_point(const Mesh& m, int32_t i, int32_t 
   A::vote_min(&m.vote[s], key);
 }
 
-// propose, work-list record t: bid for a flip of its first illegal edge, if any. Writes the
-// resolved links back into t and its live neighbours. The three neighbours are read
-// together (their loads do not wait on each other).
+// Work-list entries: record << 3 | mask of the edge slots still to test.
+__host__ __device__ inline int32_t work_entry(int32_t t, int32_t mask) { return (t << 3) | mask; }
+
 template <class A>
-__host__ __device__ inline void propose_flip(const Mesh& m, int32_t t, int32_t round, int32_t n_rec, int32_t* err) {
+__host__ __device__ inline void propose_flip(const Mesh& m, int32_t e, int32_t round, int32_t n_rec, int32_t* err) {
+  const int32_t t = e >> 3, mask = e & 7;
   m.fk[t] = -1;
   if (m.dead[t]) return;
   const int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
   if (v2 == kGhost) return;
-  const int32_t r0 = m.tnb[3 * t], r1 = m.tnb[3 * t + 1], r2 = m.tnb[3 * t + 2];
-  const int32_t s0 = follow(m, r0, v1, v2, n_rec), s1 = follow(m, r1, v2, v0, n_rec), s2 = follow(m, r2, v0, v1, n_rec);
-  if (s0 < 0 || s1 < 0 || s2 < 0) return A::fail(err, kErrLink);
-  const int32_t a0 = m.tv[3 * s0], a1 = m.tv[3 * s0 + 1], a2 = m.tv[3 * s0 + 2];
-  const int32_t b0 = m.tv[3 * s1], b1 = m.tv[3 * s1 + 1], b2 = m.tv[3 * s1 + 2];
-  const int32_t c0 = m.tv[3 * s2], c1 = m.tv[3 * s2 + 1], c2 = m.tv[3 * s2 + 2];
-  const int j0 = edge_slot3(a0, a1, a2, v2, v1), j1 = edge_slot3(b0, b1, b2, v0, v2), j2 = edge_slot3(c0, c1, c2, v1, v0);
-  if (j0 < 0 || j1 < 0 || j2 < 0) return A::fail(err, kErrLink);
-  if (s0 != r0) m.tnb[3 * t] = s0;
-  if (s1 != r1) m.tnb[3 * t + 1] = s1;
-  if (s2 != r2) m.tnb[3 * t + 2] = s2;
-  m.tnb[3 * s0 + j0] = t;
-  m.tnb[3 * s1 + j1] = t;
-  m.tnb[3 * s2 + j2] = t;
-  const P2 V0 = xy(m, v0), V1 = xy(m, v1), V2 = xy(m, v2);
-  int bid = -1;
-  if (a2 != kGhost && incircle_sos(V0, V1, V2, xy(m, sel3(j0, a0, a1, a2))) > 0) bid = 0;
-  else if (b2 != kGhost && incircle_sos(V0, V1, V2, xy(m, sel3(j1, b0, b1, b2))) > 0) bid = 1;
-  else if (c2 != kGhost && incircle_sos(V0, V1, V2, xy(m, sel3(j2, c0, c1, c2))) > 0) bid = 2;
-  if (bid < 0) return;
-  const int32_t sb = sel3(bid, s0, s1, s2);
-  const uint64_t key = make_key(round, 1, 0, (uint32_t)(3 * t + bid));
-  m.fk[t] = bid;
-  m.fs[t] = sb;
-  m.fj[t] = sel3(bid, j0, j1, j2);
-  m.fkey[t] = key;
-  A::vote_min(&m.vote[t], key);
-  A::vote_min(&m.vote[sb], key);
+  const P2 V0 = xy<A>(m, v0), V1 = xy<A>(m, v1), V2 = xy<A>(m, v2);
+  for (int k = 0; k < 3; ++k) {
+    if (!(mask >> k & 1)) continue;
+    const int32_t x = sel3(nxt(k), v0, v1, v2), y = sel3(prv(k), v0, v1, v2);
+    const int32_t raw = m.tnb[3 * t + k];
+    const int32_t s = follow(m, raw, x, y, n_rec);
+    if (s < 0) return A::fail(err, kErrLink);
+    const int32_t w0 = m.tv[3 * s], w1 = m.tv[3 * s + 1], w2 = m.tv[3 * s + 2];
+    const int j = edge_slot3(w0, w1, w2, y, x);
+    if (j < 0) return A::fail(err, kErrLink);
+    if (s != raw) m.tnb[3 * t + k] = s;
+    m.tnb[3 * s + j] = t;
+    if (w2 != kGhost && incircle_sos(V0, V1, V2, xy<A>(m, sel3(j, w0, w1, w2))) > 0) {
+      const uint64_t key = make_key(round, 1, 0, (uint32_t)(3 * t + k));
+      m.fk[t] = k;
+      m.fs[t] = s;
+      m.fj[t] = j;
+      m.fkey[t] = key;
+      A::vote_min(&m.vote[t], key);
+      A::vote_min(&m.vote[s], key);
+      return;
+    }
+  }
 }
 
 // Writes new record id = (a, b, c) with links (n0, n1, n2), alive, unvoted.
@@ -326,24 +343,26 @@ __host__ __device__ inline void retire(const Mesh& m, int32_t t, int32_t own0, i
   m.dead[t] = 1;
 }
 
-// Allocates n records and queues the solid ones (mask bit c: record base + c) for the
-// flip test of the next round. Returns the first id, or -1 on an error.
+// Allocates n records and queues those with edges to test (bits 3c..3c+2 of tests: the
+// edge slots of record base + c) for the next round. Returns the first id, or -1.
 template <class A>
-__host__ __device__ inline int32_t alloc(const Mesh& m, int n, unsigned solid_mask, int32_t* n_rec, int32_t* work,
+__host__ __device__ inline int32_t alloc(const Mesh& m, int n, unsigned tests, int32_t* n_rec, int32_t* work,
                                          int32_t* n_work, int32_t work_cap, int32_t* err) {
   const int32_t base = A::push(n_rec, n);
   if (base + n > m.cap) {
     A::fail(err, kErrCapacity);
     return -1;
   }
-  const int32_t at = A::push(n_work, __builtin_popcount(solid_mask));
-  if (at + __builtin_popcount(solid_mask) > work_cap) {
+  int queued = 0;
+  for (int c = 0; c < n; ++c) queued += (tests >> (3 * c) & 7u) != 0;
+  const int32_t at = A::push(n_work, queued);
+  if (at + queued > work_cap) {
     A::fail(err, kErrList);
     return -1;
   }
   int32_t q = at;
   for (int c = 0; c < n; ++c)
-    if (solid_mask >> c & 1u) work[q++] = base + c;
+    if (tests >> (3 * c) & 7u) work[q++] = work_entry(base + c, (int32_t)(tests >> (3 * c) & 7u));
   return base;
 }
 
@@ -367,8 +386,9 @@ __host__ __device__ inline void execute_point(const Mesh& m, int32_t i, int32_t*
   const int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
   const int32_t n0 = m.tnb[3 * t], n1 = m.tnb[3 * t + 1], n2 = m.tnb[3 * t + 2];
   if (k == kInside) {
-    // c_i = (v_i, v_i+1, p): its edge opposite p is the old edge opposite v_i-1
-    const int32_t b = alloc<A>(m, 3, 7u, n_rec, work, n_work, work_cap, err);
+    // c_i = (v_i, v_i+1, p): its edge opposite p is the old edge opposite v_i-1, the only
+    // one to test (slot 2)
+    const int32_t b = alloc<A>(m, 3, 0444u, n_rec, work, n_work, work_cap, err);
     if (b < 0) return;
     put<A>(m, b, v0, v1, p, b + 1, b + 2, n2);
     put<A>(m, b + 1, v1, v2, p, b + 2, b, n0);
@@ -386,7 +406,7 @@ __host__ __device__ inline void execute_point(const Mesh& m, int32_t i, int32_t*
     if (j < 0) return A::fail(err, kErrLink);
     const int32_t d = sel3(j, w0, w1, w2), s_bd = sel3(nxt(j), z0, z1, z2), s_dc = sel3(prv(j), z0, z1, z2);
     const bool hull = d == kGhost;
-    const int32_t r = alloc<A>(m, 4, hull ? 3u : 15u, n_rec, work, n_work, work_cap, err);
+    const int32_t r = alloc<A>(m, 4, hull ? 077u : 07777u, n_rec, work, n_work, work_cap, err);
     if (r < 0) return;
     // r = (a, b, p), r+1 = (a, p, c), r+2 = (d, c, p), r+3 = (d, p, b); with d the ghost,
     // r+2 and r+3 are stored rotated so that the ghost sits in slot 2
@@ -411,8 +431,9 @@ __host__ __device__ inline void execute_point(const Mesh& m, int32_t i, int32_t*
 
 // execute, work-list record t: flip if its bid holds both records, else retry.
 template <class A>
-__host__ __device__ inline void execute_flip(const Mesh& m, int32_t t, int32_t* n_rec, int32_t* work_next,
+__host__ __device__ inline void execute_flip(const Mesh& m, int32_t e, int32_t* n_rec, int32_t* work_next,
                                              int32_t* n_next, int32_t work_cap, int32_t* err) {
+  const int32_t t = e >> 3;
   const int k = m.fk[t];
   if (k < 0) return;
   const int32_t s = m.fs[t];
@@ -421,7 +442,7 @@ __host__ __device__ inline void execute_flip(const Mesh& m, int32_t t, int32_t* 
   if (A::vote_get(&m.vote[t]) != key || A::vote_get(&m.vote[s]) != key) {
     const int32_t at = A::push(n_next, 1);
     if (at >= work_cap) return A::fail(err, kErrList);
-    work_next[at] = t;
+    work_next[at] = e;
     return;
   }
   const int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
@@ -431,9 +452,10 @@ __host__ __device__ inline void execute_flip(const Mesh& m, int32_t t, int32_t* 
   const int32_t a = sel3(k, v0, v1, v2), b = sel3(nxt(k), v0, v1, v2), c = sel3(prv(k), v0, v1, v2);
   const int32_t d = sel3(j, w0, w1, w2);
   const int32_t s_bd = sel3(nxt(j), z0, z1, z2), s_dc = sel3(prv(j), z0, z1, z2);
-  const int32_t r = alloc<A>(m, 2, 3u, n_rec, work_next, n_next, work_cap, err);
+  // (a, b, d) and (a, d, c) replace (a, b, c) and (c, b, d); their shared edge (a, d)
+  // passes by construction: r tests slots 0 and 2, r + 1 slots 0 and 1
+  const int32_t r = alloc<A>(m, 2, 035u, n_rec, work_next, n_next, work_cap, err);
   if (r < 0) return;
-  // (a, b, d) and (a, d, c) replace (a, b, c) and (c, b, d)
   put<A>(m, r, a, b, d, s_bd, r + 1, sel3(prv(k), n0, n1, n2));
   put<A>(m, r + 1, a, d, c, s_dc, sel3(nxt(k), n0, n1, n2), r);
   auto own_t = [&](int x) { return x == k ? -1 : (x == nxt(k) ? r + 1 : r); };
@@ -443,11 +465,12 @@ __host__ __device__ inline void execute_flip(const Mesh& m, int32_t t, int32_t* 
 }
 
 // Solid record t as an output triangle: counter-clockwise, first vertex = smallest (v, u).
+template <class A>
 __host__ __device__ inline sm_tri top_first(const Mesh& m, int32_t t) {
   int32_t a = m.tv[3 * t], b = m.tv[3 * t + 1], c = m.tv[3 * t + 2];
-  const P2 A = xy(m, a), B = xy(m, b), C = xy(m, c);
-  const bool b_lt_a = B.y < A.y || (B.y == A.y && B.x < A.x);
-  const bool c_lt_a = C.y < A.y || (C.y == A.y && C.x < A.x);
+  const P2 P = xy<A>(m, a), B = xy<A>(m, b), C = xy<A>(m, c);
+  const bool b_lt_a = B.y < P.y || (B.y == P.y && B.x < P.x);
+  const bool c_lt_a = C.y < P.y || (C.y == P.y && C.x < P.x);
   const bool c_lt_b = C.y < B.y || (C.y == B.y && C.x < B.x);
   if (b_lt_a && !c_lt_b) {
     const int32_t x = a;

@@ -1,0 +1,162 @@
+// Sequential driver of the device mesh insertion steps (paper_1511_00758_amd/csrc/
+// mesh_core.hpp) for the CPU tests: the first batch of points is triangulated by the host
+// Delaunay and exported; every later batch is inserted by the same per-item propose /
+// execute steps the GPU kernel runs, one item after another in a shuffled order (the GPU
+// runs them concurrently; any order must give the same mesh). Prints the solid triangles,
+// top vertex first, after every batch.
+//
+// stdin:  W H n_batches, then per batch: count, then count lines "u v"
+// stdout: per batch: "batch k n_tris status", then n_tris lines "i0 i1 i2" (sorted)
+#define __host__
+#define __device__
+#include <algorithm>
+#include <cstdio>
+#include <random>
+#include <vector>
+
+#include "delaunay.hpp"
+#include "mesh_core.hpp"
+
+using namespace sm;
+using namespace sm::mesh;
+
+namespace {
+
+struct Seq {
+  static void vote_min(uint64_t* p, uint64_t v) { *p = v < *p ? v : *p; }
+  static uint64_t vote_get(const uint64_t* p) { return *p; }
+  static void vote_set(uint64_t* p, uint64_t v) { *p = v; }
+  static int32_t push(int32_t* n, int32_t k) {
+    const int32_t o = *n;
+    *n += k;
+    return o;
+  }
+  static void fail(int32_t* err, int32_t code) {
+    if (!*err) *err = code;
+  }
+  static int32_t uv(const Mesh& m, int32_t p) { return m.uv[p]; }
+};
+
+struct Arrays {
+  std::vector<int32_t> tv, tnb, own, kids, dead, fk, fs, fj, work[2], pend[2], ploc, pk, psib, uv;
+  std::vector<uint64_t> vote, fkey, pkey;
+};
+
+}  // namespace
+
+int main() {
+  int W, H, nb;
+  if (scanf("%d %d %d", &W, &H, &nb) != 3) return 2;
+  std::vector<sm_support> S;
+  std::vector<std::pair<int32_t, int32_t>> range;
+  for (int b = 0; b < nb; ++b) {
+    int n;
+    if (scanf("%d", &n) != 1) return 2;
+    const int32_t p0 = (int32_t)S.size();
+    for (int i = 0; i < n; ++i) {
+      int u, v;
+      if (scanf("%d %d", &u, &v) != 2) return 2;
+      S.push_back(sm_support{(int16_t)u, (int16_t)v, 0.f});
+    }
+    range.push_back({p0, (int32_t)S.size()});
+  }
+  const int32_t n_all = (int32_t)S.size();
+  const int32_t cap = 16 * n_all + 1024;
+  Arrays a;
+  a.tv.assign(3 * (size_t)cap, 0);
+  a.tnb.assign(3 * (size_t)cap, 0);
+  a.own.assign(3 * (size_t)cap, -1);
+  a.kids.assign(4 * (size_t)cap, -1);
+  a.dead.assign(cap, 0);
+  a.fk.assign(cap, -1);
+  a.fs.assign(cap, 0);
+  a.fj.assign(cap, 0);
+  a.vote.assign(cap, ~0ull);
+  a.fkey.assign(cap, 0);
+  for (int k = 0; k < 2; ++k) a.work[k].assign(cap, 0);
+  a.uv.resize(n_all);
+  for (int32_t p = 0; p < n_all; ++p) a.uv[p] = pack_uv(S[p].u, S[p].v);
+  Mesh m{a.uv.data(), a.tv.data(), a.tnb.data(), a.own.data(), a.kids.data(), a.dead.data(), a.vote.data(),
+         a.fk.data(), a.fs.data(), a.fj.data(), a.fkey.data(), cap, 0, nullptr, nullptr, nullptr, nullptr};
+  std::mt19937 rng(12345);
+  int32_t n_rec = 0, round_base = 0;
+  for (int b = 0; b < nb; ++b) {
+    const int32_t p0 = range[b].first, n_new = range[b].second - p0;
+    int status = 0;
+    if (b == 0) {
+      Delaunay dl;
+      std::vector<int32_t> u, v, e;
+      for (int32_t p = 0; p < n_new; ++p) {
+        u.push_back(S[p].u);
+        v.push_back(S[p].v);
+        e.push_back(p);
+      }
+      dl.insert_many(u.data(), v.data(), e.data(), n_new);
+      n_rec = dl.export_mesh(a.tv.data(), a.tnb.data(), cap);
+      if (n_rec <= 0) status = 100;
+    } else if (n_rec > 0) {
+      m.p0 = p0;
+      a.ploc.assign(n_new, 0);
+      a.pk.assign(n_new, kInside);
+      a.psib.assign(n_new, 0);
+      a.pkey.assign(n_new, 0);
+      for (int k = 0; k < 2; ++k) a.pend[k].assign(n_new + 1, 0);
+      m.ploc = a.ploc.data();
+      m.pk = a.pk.data();
+      m.psib = a.psib.data();
+      m.pkey = a.pkey.data();
+      int32_t start = -1;  // any live solid record
+      for (int32_t t = 0; t < n_rec && start < 0; ++t)
+        if (!a.dead[t] && a.tv[3 * t + 2] != kGhost) start = t;
+      int32_t err = 0;
+      for (int32_t i = 0; i < n_new && !err; ++i) {
+        const int32_t t = walk<Seq>(m, start, xy<Seq>(m, p0 + i), n_rec, n_rec + 16);
+        if (t < 0) err = t == -2 ? kErrOutside : kErrWalk;
+        a.ploc[i] = t;
+        a.pend[0][i] = i;
+      }
+      int32_t np = n_new, nw = 0, cur = 0, round = 0;
+      std::vector<int32_t> order;
+      for (; !err && np + nw > 0; ++round) {
+        if (round_base + round >= kMaxRounds) {
+          err = kErrRounds;
+          break;
+        }
+        order.resize(np + nw);
+        for (int32_t k = 0; k < np + nw; ++k) order[k] = k;
+        std::shuffle(order.begin(), order.end(), rng);
+        for (int32_t k : order) {
+          if (k < np) propose_point<Seq>(m, a.pend[cur][k], round_base + round, n_rec, &err);
+          else propose_flip<Seq>(m, a.work[cur][k - np], round_base + round, n_rec, &err);
+        }
+        if (err) break;
+        std::shuffle(order.begin(), order.end(), rng);
+        int32_t np2 = 0, nw2 = 0;
+        for (int32_t k : order) {
+          if (k < np)
+            execute_point<Seq>(m, a.pend[cur][k], &n_rec, a.pend[cur ^ 1].data(), &np2, n_new,
+                               a.work[cur ^ 1].data(), &nw2, cap, &err);
+          else
+            execute_flip<Seq>(m, a.work[cur][k - np], &n_rec, a.work[cur ^ 1].data(), &nw2, cap, &err);
+        }
+        cur ^= 1;
+        np = np2;
+        nw = nw2;
+      }
+      round_base += round;
+      status = err;
+    }
+    std::vector<sm_tri> out;
+    if (status == 0)
+      for (int32_t t = 0; t < n_rec; ++t)
+        if (!a.dead[t] && a.tv[3 * t + 2] != kGhost) out.push_back(top_first<Seq>(m, t));
+    std::sort(out.begin(), out.end(), [](const sm_tri& x, const sm_tri& y) {
+      if (x.i0 != y.i0) return x.i0 < y.i0;
+      if (x.i1 != y.i1) return x.i1 < y.i1;
+      return x.i2 < y.i2;
+    });
+    printf("batch %d %zu %d\n", b, out.size(), status);
+    for (const sm_tri& t : out) printf("%d %d %d\n", t.i0, t.i1, t.i2);
+  }
+  return 0;
+}
