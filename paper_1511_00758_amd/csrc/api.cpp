@@ -201,9 +201,9 @@ Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
   L.counters = take(64);
   L.score = p.support_mode == 1 ? take(npx) : 0;  // FAST scores
   // device mesh of the tessellations after the first (records of the whole frame)
-  L.mesh_on = p.n_iters >= 2 && p.host_mesh == 0;
+  L.mesh_on = p.host_mesh == 0 && (p.n_iters >= 2 || p.support_mode == 0);
   if (L.mesh_on) {
-    L.mpcap = 0;
+    L.mpcap = 1;
     for (int it = 1; it < p.n_iters; ++it) L.mpcap = std::max(L.mpcap, 2 * cells_of(W, H, occ_size(p, it)));
     L.mstatus = take(64);
     L.mwork = take(mesh_work_bytes(W, H, L.S_cap, L.mpcap));
@@ -458,15 +458,63 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   SM_HIP(launch_compact(Sd, Lo.n_grid, &counters[0], occ, W, (int32_t*)(Sd + Lo.n_grid), s));
   SM_TRY(tm.end());
 
-  auto t0 = clk::now();
-  SM_HIP(hipMemcpyAsync(h_S, Sd, (size_t)(Lo.n_grid + 1) * sizeof(sm_support), hipMemcpyDeviceToHost, s));
-  SM_HIP(hipStreamSynchronize(s));
-  us_xfer += us_since(t0);
-  int32_t n_S;
-  std::memcpy(&n_S, &h_S[Lo.n_grid], sizeof(int32_t));
-  if (n_S < 0 || n_S > Lo.n_grid) return fail(SM_ERR_INTERNAL, "support count %d out of range", n_S);
+  int32_t* d_mstatus = Lo.mesh_on ? (int32_t*)(base + Lo.mstatus) : nullptr;
+  bool mesh_dev = false;  // the frame's mesh lives on the device
+  int32_t mesh_init = 0;  // records of an exported host mesh, read by the first device insertion
+  auto mesh_job = [&](int32_t start, int32_t p0, const int32_t* n_new) {
+    MeshJob job;
+    job.S = Sd;
+    job.start = start;
+    job.p0 = p0;
+    job.n_new = n_new;
+    job.init_tv = mw.tv;
+    job.init_tnb = mw.tnb;
+    job.init_n = start ? 0 : mesh_init;
+    job.status = d_mstatus;
+    job.status_copy = nullptr;
+    job.T = Td;
+    job.T_cap = Lo.T_cap;
+    job.W = W;
+    job.H = H;
+    job.w = mw;
+    return job;
+  };
 
-  int32_t n_T = 0;
+  // S_1 and its mesh: with the grid candidates the compacted supports are in raster order
+  // and the first mesh is built on the device; else (FAST candidates, host_mesh, or a
+  // frame the device cannot mesh) the supports come to the host
+  auto t0 = clk::now();
+  int32_t n_S = -1, n_T = 0;
+  if (Lo.mesh_on && !fast) {
+    SM_TRY(tm.begin(SM_ST_MESH));
+    SM_HIP(launch_mesh_insert(mesh_job(1, 0, (const int32_t*)(Sd + Lo.n_grid)), s));
+    SM_TRY(tm.end());
+    t0 = clk::now();
+    SM_HIP(hipMemcpyAsync(h_mstatus, d_mstatus, 32, hipMemcpyDeviceToHost, s));
+    SM_HIP(hipStreamSynchronize(s));
+    us_xfer += us_since(t0);
+    n_S = h_mstatus[kMeshNew];
+    if (n_S < 0 || n_S > Lo.n_grid) return fail(SM_ERR_INTERNAL, "support count %d out of range", n_S);
+    if (h_mstatus[kMeshErr] == 0) {
+      n_T = h_mstatus[kMeshTris];
+      if (n_T < 0 || n_T > Lo.T_cap) return fail(SM_ERR_INTERNAL, "device triangle count %d out of range", n_T);
+      mesh_dev = true;
+      if (st) ++st->mesh_device;
+    } else {
+      if (st && h_mstatus[kMeshErr] != kMeshErrNoMesh) ++st->mesh_fallback;
+      t0 = clk::now();
+      if (n_S > 0) SM_HIP(hipMemcpyAsync(h_S, Sd, (size_t)n_S * sizeof(sm_support), hipMemcpyDeviceToHost, s));
+      SM_HIP(hipStreamSynchronize(s));
+      us_xfer += us_since(t0);
+    }
+  } else {
+    SM_HIP(hipMemcpyAsync(h_S, Sd, (size_t)(Lo.n_grid + 1) * sizeof(sm_support), hipMemcpyDeviceToHost, s));
+    SM_HIP(hipStreamSynchronize(s));
+    us_xfer += us_since(t0);
+    std::memcpy(&n_S, &h_S[Lo.n_grid], sizeof(int32_t));
+    if (n_S < 0 || n_S > Lo.n_grid) return fail(SM_ERR_INTERNAL, "support count %d out of range", n_S);
+  }
+
   int32_t host_upto = 0;  // supports S[0, host_upto) are in the host triangulation c.dl
   auto triangulate_and_upload = [&](int32_t from, int32_t to) -> sm_status {
     host_upto = to;
@@ -503,14 +551,12 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     us_xfer += us_since(tx);
     return SM_OK;
   };
-  SM_TRY(triangulate_and_upload(0, n_S));
+  if (!mesh_dev) SM_TRY(triangulate_and_upload(0, n_S));
 
   // the tessellations after the first insert their supports into the mesh kept in device
-  // memory (the triangulation is unique, so the triangles are the host's)
-  int32_t* d_mstatus = Lo.mesh_on ? (int32_t*)(base + Lo.mstatus) : nullptr;
-  bool mesh_dev = false;
-  int32_t mesh_init = 0;  // records of the exported mesh, read by the first device insertion
-  if (Lo.mesh_on) {
+  // memory (the triangulation is unique, so the triangles are the host's); a host mesh
+  // goes up once
+  if (Lo.mesh_on && !mesh_dev && p->n_iters >= 2) {
     auto th = clk::now();
     const int32_t n_rec = c.dl.export_mesh(h_mtv, h_mtnb, mw.cap);
     us_host += us_since(th);
@@ -553,21 +599,8 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     SM_HIP(launch_compact(region, 2 * cells, &counters[1], occ, W, (int32_t*)(region + 2 * cells), s));
     SM_TRY(tm.end());
     if (mesh_dev) {
-      MeshJob job;
-      job.S = Sd;
-      job.p0 = n_S;
-      job.n_new = (const int32_t*)(region + 2 * cells);
-      job.init_tv = mw.tv;
-      job.init_tnb = mw.tnb;
-      job.init_n = mesh_init;
+      const MeshJob job = mesh_job(0, n_S, (const int32_t*)(region + 2 * cells));
       mesh_init = 0;
-      job.status = d_mstatus;
-      job.status_copy = nullptr;
-      job.T = Td;
-      job.T_cap = Lo.T_cap;
-      job.W = W;
-      job.H = H;
-      job.w = mw;
       SM_TRY(tm.begin(SM_ST_MESH));
       SM_HIP(launch_mesh_insert(job, s));
       SM_TRY(tm.end());

@@ -14,6 +14,7 @@
 #include "kernels.hpp"
 #include "mesh.hpp"
 #include "mesh_core.hpp"
+#include "mesh_start.hpp"
 
 namespace sm {
 
@@ -44,19 +45,45 @@ struct DevA {
   __device__ static int32_t push(int32_t* n, int32_t k) { return atomicAdd(n, k); }
   __device__ static void fail(int32_t* err, int32_t code) { atomicCAS(err, 0, code); }
   __device__ static int32_t uv(const mesh::Mesh& m, int32_t p) { return kLds ? g_uv[p] : m.uv[p]; }
+  __device__ static uint64_t cas64(uint64_t* p, uint64_t expected, uint64_t desired) {
+    return atomicCAS((unsigned long long*)p, (unsigned long long)expected, (unsigned long long)desired);
+  }
 };
+
+// Exclusive block-wide prefix sum of one count per thread (every thread calls it).
+__device__ void block_scan1(int v, int* wsum, int& excl, int& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int x = __shfl_up(inc, d);
+    if (lane >= d) inc += x;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int before = 0;
+  total = 0;
+  for (int k = 0; k < kMeshThreads / 64; ++k) {
+    before += k < w ? wsum[k] : 0;
+    total += wsum[k];
+  }
+  __syncthreads();  // wsum is free again
+  excl = before + inc - v;
+}
 
 template <bool kLds>
 __device__ void mesh_insert_block(const MeshJob& a, int32_t n_new) {
   using namespace mesh;
   using DA = DevA<kLds>;
   __shared__ int32_t s_np[2], s_nw[2], s_nrec, s_err, s_any, s_ntri;
+  __shared__ int s_wsum[kMeshThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63;
   const MeshWork& w = a.w;
   // every thread reads the same control words, so the early exits below are uniform
-  const bool fresh = a.init_n > 0;
-  const int32_t n_rec0 = fresh ? a.init_n : a.status[kMeshRecords];
-  const int32_t base_round = fresh ? 0 : a.status[kMeshRounds];
+  const bool start = a.start != 0;
+  const bool fresh = !start && a.init_n > 0;
+  const int32_t n_rec0 = start ? 0 : (fresh ? a.init_n : a.status[kMeshRecords]);
+  const int32_t base_round = start || fresh ? 0 : a.status[kMeshRounds];
   const int32_t n_pts = a.p0 + n_new;
   auto finish = [&](int32_t n_rec, int32_t n_tri, int32_t err, int32_t rounds) {  // thread 0
     const int32_t words[8] = {n_rec, n_tri, err, rounds, n_new, 0, 0, 0};
@@ -66,13 +93,15 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t n_new) {
     }
   };
   __syncthreads();
-  if (n_rec0 <= 0 || n_rec0 > w.cap || n_new < 0 || n_new > w.pcap || a.p0 < 3 || n_pts > w.S_cap ||
-      base_round < 0 || base_round >= kMaxRounds) {
-    if (tid == 0) finish(n_rec0, 0, kErrCapacity, base_round);
+  const bool bad = start ? (a.p0 != 0 || n_new < 0 || n_pts > w.S_cap)
+                         : (n_rec0 <= 0 || n_rec0 > w.cap || n_new < 0 || n_new > w.pcap || a.p0 < 3 ||
+                            n_pts > w.S_cap || base_round < 0 || base_round >= kMaxRounds);
+  if (bad || (start && n_new < 3)) {
+    if (tid == 0) finish(n_rec0, 0, bad ? kErrCapacity : kMeshErrNoMesh, base_round);
     return;
   }
   if (tid == 0) {
-    s_np[0] = n_new;
+    s_np[0] = start ? 0 : n_new;
     s_nw[0] = 0;
     s_np[1] = s_nw[1] = 0;
     s_nrec = n_rec0;
@@ -129,11 +158,79 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t n_new) {
     }
   }
   for (int32_t c = tid; c < gw * gh; c += kMeshThreads) w.hint[c] = -1;
+  if (start) {
+    for (int32_t h = tid; h < w.hcap; h += kMeshThreads) w.hkeys[h] = kEmptyEdge;
+    for (int32_t i = tid; i < n_new; i += kMeshThreads) w.gh_start[i] = w.gh_end[i] = -1;
+  }
   __syncthreads();
+
+  if (start) {  // the first mesh: rows, ladders, pockets, links (mesh_start.hpp)
+    Start st;
+    st.n = n_new;
+    st.row_first = w.row_first;
+    st.strip_base = w.strip_base;
+    st.gh_start = w.gh_start;
+    st.gh_end = w.gh_end;
+    st.stack = w.stack;
+    st.keys = w.hkeys;
+    st.vals = w.hvals;
+    st.hcap = w.hcap;
+    // rows: each thread scans a contiguous run of supports
+    const int32_t per = (n_new + kMeshThreads - 1) / kMeshThreads;
+    const int32_t lo = min(tid * per, n_new), hi = min(lo + per, n_new);
+    int cnt = 0;
+    for (int32_t i = lo; i < hi; ++i) cnt += row_starts<DA>(m, i, &s_err);
+    int base, n_rows;
+    block_scan1(cnt, s_wsum, base, n_rows);
+    for (int32_t i = lo; i < hi; ++i)
+      if (row_starts<DA>(m, i, &s_err)) w.row_first[base++] = i;
+    __syncthreads();
+    if (n_rows < 2 || s_err != 0) {  // uniform: read after the barrier, nothing writes s_err here
+      if (tid == 0) finish(0, 0, s_err != 0 ? s_err : kMeshErrNoMesh, 0);
+      return;
+    }
+    // strips: ladder sizes, their prefix sums, the ladders
+    const int32_t ns = n_rows - 1;
+    const int32_t per2 = (ns + kMeshThreads - 1) / kMeshThreads;
+    const int32_t lo2 = min(tid * per2, ns), hi2 = min(lo2 + per2, ns);
+    int cnt2 = 0;
+    for (int32_t r = lo2; r < hi2; ++r) cnt2 += ladder_size(st, r, n_rows);
+    int base2, n_ladder;
+    block_scan1(cnt2, s_wsum, base2, n_ladder);
+    for (int32_t r = lo2; r < hi2; ++r) {
+      w.strip_base[r] = base2;
+      base2 += ladder_size(st, r, n_rows);
+    }
+    if (tid == 0) s_nrec = n_ladder;
+    __syncthreads();
+    for (int32_t r = tid; r < ns; r += kMeshThreads) ladder<DA>(m, st, r, n_rows);
+    __syncthreads();
+    // hull pockets: the two side chains on two waves
+    if (tid == 0) pockets<DA>(m, st, 1, n_rows, &s_nrec, &s_err);
+    if (tid == 64) pockets<DA>(m, st, 0, n_rows, &s_nrec, &s_err);
+    __syncthreads();
+    const int32_t n_solid = s_nrec;
+    if (n_solid == 0 || s_err != 0) {  // every support on one line (or a full array)
+      if (tid == 0) finish(0, 0, s_err != 0 ? s_err : kMeshErrNoMesh, 0);
+      return;
+    }
+    for (int32_t e = tid; e < 3 * n_solid; e += kMeshThreads) edge_insert<DA>(m, st, e / 3, e % 3, &s_err);
+    __syncthreads();
+    for (int32_t e = tid; e < 3 * n_solid; e += kMeshThreads) edge_link<DA>(m, st, e / 3, e % 3, &s_nrec, &s_err);
+    __syncthreads();
+    const int32_t n_all = min(s_nrec, w.cap);
+    for (int32_t g = n_solid + tid; g < n_all; g += kMeshThreads) ghost_link<DA>(m, st, g, &s_err);
+    for (int32_t t = tid; t < n_all; t += kMeshThreads) {
+      w.dead[t] = 0;
+      DA::vote_set(&w.vote[t], ~0ull);
+    }
+    for (int32_t t = tid; t < n_solid; t += kMeshThreads) w.work0[t] = work_entry(t, 7);  // test every edge
+    if (tid == 0) s_nw[0] = n_solid;
+  }
 
   // hints: every cell of a live solid record's bounding box (the vertex cells of a record
   // whose box is large) points at it
-  if (s_err == 0) {
+  if (!start && s_err == 0) {
     for (int32_t t = tid; t < n_rec0; t += kMeshThreads) {
       if (w.dead[t] || w.tv[3 * t + 2] == kGhost) continue;
       const P2 A = xy<DA>(m, w.tv[3 * t]), B = xy<DA>(m, w.tv[3 * t + 1]), C = xy<DA>(m, w.tv[3 * t + 2]);
@@ -153,7 +250,8 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t n_new) {
   __syncthreads();
 
   // locate every new point by a visibility walk from the hint of its cell
-  if (s_err == 0 && s_any >= 0) {
+  if (start) {
+  } else if (s_err == 0 && s_any >= 0) {
     for (int32_t i = tid; i < n_new; i += kMeshThreads) {
       const P2 q = xy<DA>(m, a.p0 + i);
       int32_t h = w.hint[(q.y >> kHintShift) * gw + (q.x >> kHintShift)];
@@ -278,9 +376,19 @@ MeshWork carve(Carve& c, int32_t W, int32_t H, int32_t S_cap, int32_t pcap) {
   w.pkey = c.take<uint64_t>(np);
   w.uv = c.take<int32_t>((size_t)S_cap);
   w.hint = c.take<int32_t>((size_t)((W + 15) >> kHintShift) * ((H + 15) >> kHintShift));
+  int32_t hcap = 1024;
+  while (hcap < 16 * (int64_t)S_cap && hcap < (1 << 28)) hcap <<= 1;  // 6 directed edges per support, load <= 3/8
+  w.row_first = c.take<int32_t>((size_t)S_cap + 1);
+  w.strip_base = c.take<int32_t>((size_t)S_cap + 1);
+  w.gh_start = c.take<int32_t>((size_t)S_cap);
+  w.gh_end = c.take<int32_t>((size_t)S_cap);
+  w.stack = c.take<int32_t>(2 * (size_t)S_cap + 2);
+  w.hkeys = c.take<uint64_t>((size_t)hcap);
+  w.hvals = c.take<int32_t>((size_t)hcap);
   w.cap = cap;
   w.pcap = pcap;
   w.S_cap = S_cap;
+  w.hcap = hcap;
   return w;
 }
 

@@ -23,7 +23,12 @@ struct MeshWork {  // per-frame arrays: records [cap], new points [pcap], coordi
   uint64_t* pkey;
   int32_t* uv;    // packed coordinates when they do not fit in LDS
   int32_t* hint;  // location hints, one per 16 x 16 px cell
-  int32_t cap, pcap, S_cap;
+  // first mesh built on the device: rows, strips, hull ghosts per vertex, chain stacks,
+  // edge hash table (hcap entries, a power of two)
+  int32_t *row_first, *strip_base, *gh_start, *gh_end, *stack;
+  uint64_t* hkeys;
+  int32_t* hvals;
+  int32_t cap, pcap, S_cap, hcap;
 };
 
 // Mesh status words (device, 8 x int32):
@@ -34,9 +39,14 @@ struct MeshWork {  // per-frame arrays: records [cap], new points [pcap], coordi
 //   [3] rounds used so far by the frame (keys of later rounds must bid lower)
 //   [4] number of new supports read from n_new
 enum { kMeshRecords = 0, kMeshTris = 1, kMeshErr = 2, kMeshRounds = 3, kMeshNew = 4 };
+// error code of a first mesh that cannot exist (fewer than two rows of supports: no
+// triangle, or all supports collinear); the host path handles that frame
+constexpr int32_t kMeshErrNoMesh = 10;
 
 struct MeshJob {
   const sm_support* S;
+  int32_t start;            // 1: build the frame's first mesh from S[0, *n_new) (sorted by
+                            //    raster position, p0 = 0), then flip it to Delaunay
   int32_t p0;               // first new support
   const int32_t* n_new;     // device count of new supports
   const int32_t* init_tv;   // init_n > 0: the frame's first mesh (records in host form) to

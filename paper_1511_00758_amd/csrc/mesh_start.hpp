@@ -1,0 +1,176 @@
+// A first mesh built on the device from supports sorted by raster position (the grid
+// supports after compaction are): a valid triangulation of their convex hull, which the
+// Lawson flips of mesh_core.hpp then turn into the perturbed Delaunay triangulation.
+//
+//   rows     every distinct v is a row; rows are contiguous runs of the sorted supports,
+//            increasing u inside a row
+//   ladders  between two consecutive rows (two horizontal lines) the points are joined by
+//            a ladder: walking both rows left to right, each step adds the triangle of the
+//            next point of one row and the current point of the other (always valid
+//            between parallel lines); strip r holds |row r| + |row r+1| - 2 triangles
+//   pockets  the left ends of the rows (bottom to top) and the right ends (top to bottom)
+//            are the side chains of the boundary; a stack scan fills every reflex vertex
+//            with a triangle, so the boundary becomes the convex hull (collinear points on
+//            it stay vertices, as in the host triangulation); the corners at the first and
+//            last rows are always convex
+//   links    every directed edge goes into a hash table; an edge whose reverse is absent
+//            is a hull edge and gets a ghost triangle; ghosts link to the ghosts of the
+//            hull edges before and after them
+//
+// The per-item steps below are shared by the kernel and the CPU tests; atomics come from
+// the same policy class as in mesh_core.hpp, plus
+//   static uint64_t cas64(uint64_t* p, uint64_t expected, uint64_t desired);  returns old
+#pragma once
+
+#include <cstdint>
+
+#include "mesh_core.hpp"
+
+namespace sm {
+namespace mesh {
+
+constexpr uint64_t kEmptyEdge = ~0ull;
+constexpr int32_t kErrOrder = 9;  // supports not strictly increasing in (v, u)
+
+struct Start {
+  int32_t n;           // supports S[0, n)
+  int32_t* row_first;  // [n] first support of row r
+  int32_t* strip_base; // [n] first record of strip r
+  int32_t* gh_start;   // [n] ghost of the hull edge starting at vertex x, -1
+  int32_t* gh_end;     // [n] ghost of the hull edge ending at vertex x, -1
+  int32_t* stack;      // [2][n] chain scans (left, right)
+  uint64_t* keys;      // [hcap] directed edges (x + 1) << 32 | (y + 1)
+  int32_t* vals;       // [hcap] 3 * record + slot
+  int32_t hcap;        // power of two
+};
+
+__host__ __device__ inline uint64_t raster_key(P2 p) { return ((uint64_t)p.y << 16) | (uint64_t)p.x; }
+
+// rows: true when support i starts a row; flags an order error.
+template <class A>
+__host__ __device__ inline bool row_starts(const Mesh& m, int32_t i, int32_t* err) {
+  if (i == 0) return true;
+  const P2 a = xy<A>(m, i - 1), b = xy<A>(m, i);
+  if (raster_key(a) >= raster_key(b)) A::fail(err, kErrOrder);
+  return a.y != b.y;
+}
+
+__host__ __device__ inline int32_t ladder_size(const Start& st, int32_t r, int32_t n_rows) {
+  const int32_t a0 = st.row_first[r], a1 = st.row_first[r + 1];
+  const int32_t b1 = r + 2 < n_rows ? st.row_first[r + 2] : st.n;
+  return (a1 - a0 - 1) + (b1 - a1 - 1);
+}
+
+// ladders: the triangles of strip r (rows r and r + 1) from record strip_base[r] on,
+// counter-clockwise; their links are filled in later.
+template <class A>
+__host__ __device__ inline void ladder(const Mesh& m, const Start& st, int32_t r, int32_t n_rows) {
+  int32_t i = st.row_first[r], j = st.row_first[r + 1];
+  const int32_t i_end = j - 1, j_end = (r + 2 < n_rows ? st.row_first[r + 2] : st.n) - 1;
+  int32_t t = st.strip_base[r];
+  while (i < i_end || j < j_end) {
+    const bool step_a = i < i_end && (j == j_end || xy<A>(m, i + 1).x <= xy<A>(m, j + 1).x);
+    if (step_a) {  // (A_i, A_i+1, B_j)
+      m.tv[3 * t] = i, m.tv[3 * t + 1] = i + 1, m.tv[3 * t + 2] = j;
+      ++i;
+    } else {       // (A_i, B_j+1, B_j)
+      m.tv[3 * t] = i, m.tv[3 * t + 1] = j + 1, m.tv[3 * t + 2] = j;
+      ++j;
+    }
+    ++t;
+  }
+}
+
+// pockets: scan of one side chain (side 0: row starts, bottom to top; side 1: row ends,
+// top to bottom); each reflex vertex gets the triangle (previous, next, vertex). Records
+// come from n_rec. Returns false on a capacity error.
+template <class A>
+__host__ __device__ inline bool pockets(const Mesh& m, const Start& st, int side, int32_t n_rows, int32_t* n_rec,
+                                        int32_t* err) {
+  int32_t* stk = st.stack + (side ? st.n : 0);
+  int32_t top = 0;
+  for (int32_t q = 0; q < n_rows; ++q) {
+    const int32_t r = side ? q : n_rows - 1 - q;
+    const int32_t p = side ? (r + 1 < n_rows ? st.row_first[r + 1] : st.n) - 1 : st.row_first[r];
+    while (top >= 2 && orient(xy<A>(m, stk[top - 2]), xy<A>(m, stk[top - 1]), xy<A>(m, p)) < 0) {
+      const int32_t t = A::push(n_rec, 1);
+      if (t >= m.cap) {
+        A::fail(err, kErrCapacity);
+        return false;
+      }
+      m.tv[3 * t] = stk[top - 2], m.tv[3 * t + 1] = p, m.tv[3 * t + 2] = stk[top - 1];
+      --top;
+    }
+    stk[top++] = p;
+  }
+  return true;
+}
+
+__host__ __device__ inline uint64_t edge_key(int32_t x, int32_t y) {
+  return ((uint64_t)(uint32_t)(x + 1) << 32) | (uint32_t)(y + 1);
+}
+
+__host__ __device__ inline uint32_t edge_hash(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  return (uint32_t)k;
+}
+
+// links, first pass: the directed edge in slot k of solid record t into the table.
+template <class A>
+__host__ __device__ inline void edge_insert(const Mesh& m, const Start& st, int32_t t, int k, int32_t* err) {
+  const uint64_t key = edge_key(m.tv[3 * t + nxt(k)], m.tv[3 * t + prv(k)]);
+  uint32_t h = edge_hash(key) & (uint32_t)(st.hcap - 1);
+  for (int32_t probe = 0; probe < st.hcap; ++probe) {
+    const uint64_t old = A::cas64(&st.keys[h], kEmptyEdge, key);
+    if (old == kEmptyEdge) {
+      st.vals[h] = 3 * t + k;
+      return;
+    }
+    if (old == key) return A::fail(err, kErrLink);  // an edge twice: not a triangulation
+    h = (h + 1) & (uint32_t)(st.hcap - 1);
+  }
+  A::fail(err, kErrCapacity);
+}
+
+// links, second pass: the neighbour across slot k of solid record t, or a new ghost when
+// the reverse edge is absent (a hull edge x -> y gets the ghost (y, x, ghost)).
+template <class A>
+__host__ __device__ inline void edge_link(const Mesh& m, const Start& st, int32_t t, int k, int32_t* n_rec,
+                                          int32_t* err) {
+  const int32_t x = m.tv[3 * t + nxt(k)], y = m.tv[3 * t + prv(k)];
+  const uint64_t key = edge_key(y, x);
+  uint32_t h = edge_hash(key) & (uint32_t)(st.hcap - 1);
+  for (int32_t probe = 0; probe < st.hcap; ++probe) {
+    const uint64_t cur = A::vote_get(&st.keys[h]);  // written by atomics
+    if (cur == key) {
+      m.tnb[3 * t + k] = st.vals[h] / 3;
+      return;
+    }
+    if (cur == kEmptyEdge) break;
+    h = (h + 1) & (uint32_t)(st.hcap - 1);
+  }
+  const int32_t g = A::push(n_rec, 1);
+  if (g >= m.cap) return A::fail(err, kErrCapacity);
+  m.tv[3 * g] = y, m.tv[3 * g + 1] = x, m.tv[3 * g + 2] = kGhost;
+  m.tnb[3 * g + 2] = t;
+  m.tnb[3 * t + k] = g;
+  if (st.gh_start[x] >= 0 || st.gh_end[y] >= 0) return A::fail(err, kErrLink);  // not a simple hull
+  st.gh_start[x] = g;
+  st.gh_end[y] = g;
+}
+
+// links, third pass: ghost g = (y, x, ghost) of hull edge x -> y links, across (x, ghost),
+// to the ghost of the hull edge ending at x and, across (ghost, y), to the one starting at y.
+template <class A>
+__host__ __device__ inline void ghost_link(const Mesh& m, const Start& st, int32_t g, int32_t* err) {
+  const int32_t y = m.tv[3 * g], x = m.tv[3 * g + 1];
+  const int32_t before = st.gh_end[x], after = st.gh_start[y];
+  if (before < 0 || after < 0) return A::fail(err, kErrLink);
+  m.tnb[3 * g] = before;
+  m.tnb[3 * g + 1] = after;
+}
+
+}  // namespace mesh
+}  // namespace sm

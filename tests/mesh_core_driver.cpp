@@ -1,11 +1,12 @@
-// Sequential driver of the device mesh insertion steps (paper_1511_00758_amd/csrc/
-// mesh_core.hpp) for the CPU tests: the first batch of points is triangulated by the host
-// Delaunay and exported; every later batch is inserted by the same per-item propose /
-// execute steps the GPU kernel runs, one item after another in a shuffled order (the GPU
-// runs them concurrently; any order must give the same mesh). Prints the solid triangles,
-// top vertex first, after every batch.
+// Sequential driver of the device mesh steps (paper_1511_00758_amd/csrc/mesh_core.hpp,
+// mesh_start.hpp) for the CPU tests. The first batch of points is triangulated either by
+// the host Delaunay and exported (mode 0) or by the device start steps (rows, ladders,
+// pockets, edge links, then Lawson flips; mode 1, points sorted by (v, u)); every later
+// batch is inserted by the same per-item propose / execute steps the GPU kernel runs, one
+// item after another in a shuffled order (the GPU runs them concurrently; any order must
+// give the same mesh). Prints the solid triangles, top vertex first, after every batch.
 //
-// stdin:  W H n_batches, then per batch: count, then count lines "u v"
+// stdin:  W H n_batches mode, then per batch: count, then count lines "u v"
 // stdout: per batch: "batch k n_tris status", then n_tris lines "i0 i1 i2" (sorted)
 #define __host__
 #define __device__
@@ -16,6 +17,7 @@
 
 #include "delaunay.hpp"
 #include "mesh_core.hpp"
+#include "mesh_start.hpp"
 
 using namespace sm;
 using namespace sm::mesh;
@@ -35,6 +37,11 @@ struct Seq {
     if (!*err) *err = code;
   }
   static int32_t uv(const Mesh& m, int32_t p) { return m.uv[p]; }
+  static uint64_t cas64(uint64_t* p, uint64_t expected, uint64_t desired) {
+    const uint64_t o = *p;
+    if (o == expected) *p = desired;
+    return o;
+  }
 };
 
 struct Arrays {
@@ -45,8 +52,8 @@ struct Arrays {
 }  // namespace
 
 int main() {
-  int W, H, nb;
-  if (scanf("%d %d %d", &W, &H, &nb) != 3) return 2;
+  int W, H, nb, mode;
+  if (scanf("%d %d %d %d", &W, &H, &nb, &mode) != 4) return 2;
   std::vector<sm_support> S;
   std::vector<std::pair<int32_t, int32_t>> range;
   for (int b = 0; b < nb; ++b) {
@@ -80,10 +87,91 @@ int main() {
          a.fk.data(), a.fs.data(), a.fj.data(), a.fkey.data(), cap, 0, nullptr, nullptr, nullptr, nullptr};
   std::mt19937 rng(12345);
   int32_t n_rec = 0, round_base = 0;
+  // rounds of propose / execute over np pending points (pend[0]) and nw work entries (work[0])
+  auto rounds = [&](int32_t np, int32_t nw, int32_t err) -> int32_t {
+    const int32_t pcap = std::max<int32_t>(np, 1);
+    int32_t cur = 0, round = 0;
+    std::vector<int32_t> order;
+    for (; !err && np + nw > 0; ++round) {
+      if (round_base + round >= kMaxRounds) {
+        err = kErrRounds;
+        break;
+      }
+      order.resize(np + nw);
+      for (int32_t k = 0; k < np + nw; ++k) order[k] = k;
+      std::shuffle(order.begin(), order.end(), rng);
+      for (int32_t k : order) {
+        if (k < np) propose_point<Seq>(m, a.pend[cur][k], round_base + round, n_rec, &err);
+        else propose_flip<Seq>(m, a.work[cur][k - np], round_base + round, n_rec, &err);
+      }
+      if (err) break;
+      std::shuffle(order.begin(), order.end(), rng);
+      int32_t np2 = 0, nw2 = 0;
+      for (int32_t k : order) {
+        if (k < np)
+          execute_point<Seq>(m, a.pend[cur][k], &n_rec, a.pend[cur ^ 1].data(), &np2, pcap, a.work[cur ^ 1].data(),
+                             &nw2, cap, &err);
+        else
+          execute_flip<Seq>(m, a.work[cur][k - np], &n_rec, a.work[cur ^ 1].data(), &nw2, cap, &err);
+      }
+      cur ^= 1;
+      np = np2;
+      nw = nw2;
+    }
+    round_base += round;
+    fprintf(stderr, "rounds %d records %d\n", round, n_rec);
+    return err;
+  };
   for (int b = 0; b < nb; ++b) {
     const int32_t p0 = range[b].first, n_new = range[b].second - p0;
     int status = 0;
-    if (b == 0) {
+    if (b == 0 && mode == 1) {
+      // device start: rows, ladders, pockets, links, then flips of every solid triangle
+      const int32_t n = n_new;
+      std::vector<int32_t> row_first(n + 1), strip_base(n + 1), gh_start(n, -1), gh_end(n, -1), stk(2 * n + 2);
+      int32_t hcap = 1;
+      while (hcap < 16 * n + 64) hcap <<= 1;
+      std::vector<uint64_t> keys(hcap, kEmptyEdge);
+      std::vector<int32_t> vals(hcap, 0);
+      Start st{n, row_first.data(), strip_base.data(), gh_start.data(), gh_end.data(), stk.data(), keys.data(),
+               vals.data(), hcap};
+      int32_t err = 0, n_rows = 0;
+      for (int32_t i = 0; i < n; ++i)
+        if (row_starts<Seq>(m, i, &err)) row_first[n_rows++] = i;
+      if (!err && n_rows >= 2) {
+        int32_t base = 0;
+        for (int32_t r = 0; r + 1 < n_rows; ++r) {
+          strip_base[r] = base;
+          base += ladder_size(st, r, n_rows);
+        }
+        std::vector<int32_t> order;
+        for (int32_t r = 0; r + 1 < n_rows; ++r) order.push_back(r);
+        std::shuffle(order.begin(), order.end(), rng);
+        for (int32_t r : order) ladder<Seq>(m, st, r, n_rows);
+        n_rec = base;
+        pockets<Seq>(m, st, 1, n_rows, &n_rec, &err);
+        pockets<Seq>(m, st, 0, n_rows, &n_rec, &err);
+        const int32_t n_solid = n_rec;
+        order.clear();
+        for (int32_t e = 0; e < 3 * n_solid; ++e) order.push_back(e);
+        std::shuffle(order.begin(), order.end(), rng);
+        for (int32_t e : order) edge_insert<Seq>(m, st, e / 3, e % 3, &err);
+        std::shuffle(order.begin(), order.end(), rng);
+        for (int32_t e : order) edge_link<Seq>(m, st, e / 3, e % 3, &n_rec, &err);
+        for (int32_t g = n_solid; g < n_rec; ++g) ghost_link<Seq>(m, st, g, &err);
+        for (int32_t t = 0; t < n_rec; ++t) a.dead[t] = 0, a.vote[t] = ~0ull;
+        int32_t nw = 0;
+        for (int32_t t = 0; t < n_solid; ++t) a.work[0][nw++] = work_entry(t, 7);
+        if (!err) {
+          m.p0 = n;
+          err = rounds(0, nw, err);
+        }
+      } else if (!err) {
+        err = 100;  // fewer than two rows: no triangle
+      }
+      status = err;
+      if (err) n_rec = 0;
+    } else if (b == 0) {
       Delaunay dl;
       std::vector<int32_t> u, v, e;
       for (int32_t p = 0; p < n_new; ++p) {
@@ -115,35 +203,8 @@ int main() {
         a.ploc[i] = t;
         a.pend[0][i] = i;
       }
-      int32_t np = n_new, nw = 0, cur = 0, round = 0;
-      std::vector<int32_t> order;
-      for (; !err && np + nw > 0; ++round) {
-        if (round_base + round >= kMaxRounds) {
-          err = kErrRounds;
-          break;
-        }
-        order.resize(np + nw);
-        for (int32_t k = 0; k < np + nw; ++k) order[k] = k;
-        std::shuffle(order.begin(), order.end(), rng);
-        for (int32_t k : order) {
-          if (k < np) propose_point<Seq>(m, a.pend[cur][k], round_base + round, n_rec, &err);
-          else propose_flip<Seq>(m, a.work[cur][k - np], round_base + round, n_rec, &err);
-        }
-        if (err) break;
-        std::shuffle(order.begin(), order.end(), rng);
-        int32_t np2 = 0, nw2 = 0;
-        for (int32_t k : order) {
-          if (k < np)
-            execute_point<Seq>(m, a.pend[cur][k], &n_rec, a.pend[cur ^ 1].data(), &np2, n_new,
-                               a.work[cur ^ 1].data(), &nw2, cap, &err);
-          else
-            execute_flip<Seq>(m, a.work[cur][k - np], &n_rec, a.work[cur ^ 1].data(), &nw2, cap, &err);
-        }
-        cur ^= 1;
-        np = np2;
-        nw = nw2;
-      }
-      round_base += round;
+      int32_t err2 = rounds(n_new, 0, err);
+      err = err2;
       status = err;
     }
     std::vector<sm_tri> out;

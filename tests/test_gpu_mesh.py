@@ -1,8 +1,9 @@
-"""Device mesh insertion (the tessellations after the first, Sec. III-A / Alg. 1) against the
-host triangulation: the perturbed Delaunay triangulation is unique, so a solve whose later
-tessellations run on the device must give the same triangle counts and bit-identical
-outputs as one that triangulates every iteration on the host; the solve parity tests
-compare the device path with the oracle as well."""
+"""Device meshes (Sec. III-A / Alg. 1: the first mesh built on the device from the grid
+supports, the later tessellations inserted into it) against the host triangulation: the
+perturbed Delaunay triangulation is unique, so a solve whose tessellations run on the
+device must give the same triangle counts and bit-identical outputs as one that
+triangulates every iteration on the host; the solve parity tests compare the device path
+with the oracle as well."""
 import sys
 
 import numpy as np
@@ -41,8 +42,8 @@ def _check(sc, prm):
         assert (a.view(np.uint8) == b.view(np.uint8)).all()
     assert host[3]["mesh_device"] == 0
     assert dev[3]["mesh_fallback"] == 0
-    if dev[3]["n_tris"][0] > 0:
-        assert dev[3]["mesh_device"] == n_iters - 1
+    if dev[3]["n_tris"][0] > 0:  # grid supports: every tessellation on the device
+        assert dev[3]["mesh_device"] == (n_iters if prm.get("support_mode", 0) == 0 else n_iters - 1)
     return dev[3]
 
 

@@ -396,10 +396,11 @@ def _compare_solve(sc, p, res, tr):
     assert np.abs(D_f - tr["D_f"]).max() <= TOL_PX
     assert (D_f.view(np.uint32) == tr["D_f"].view(np.uint32)).all()
     assert st["n_valid"] == int(tr["mask"].sum())
-    # every tessellation after the first ran on the device once the first mesh existed
+    # with grid supports every tessellation ran on the device; with FAST supports every one
+    # after the first (once the first mesh existed)
     assert st["mesh_fallback"] == 0
-    if p.n_iters >= 2 and len(tr["iters"][0]["tris"]) > 0:
-        assert st["mesh_device"] == p.n_iters - 1
+    if len(tr["iters"][0]["tris"]) > 0:
+        assert st["mesh_device"] == (p.n_iters if p.support_mode == 0 else p.n_iters - 1)
 
 
 @pytest.mark.parametrize("cfg", [1, 2, 3])

@@ -159,7 +159,8 @@ def test_fast_candidates_rejects_bad_arguments():
 
 def test_fast_mode_workspace_holds_the_bin_slots_and_scores():
     L = _lib.load()
-    grid = L.sm_solve_workspace_bytes(640, 480, _params())
-    fast = L.sm_solve_workspace_bytes(640, 480, _params(support_mode=1, fast_per_bin=400))
+    # (host meshes on both sides: grid frames otherwise also hold the device mesh buffers)
+    grid = L.sm_solve_workspace_bytes(640, 480, _params(host_mesh=1))
+    fast = L.sm_solve_workspace_bytes(640, 480, _params(support_mode=1, fast_per_bin=400, host_mesh=1))
     # 12 x 10 bins x 400 slots of 8 bytes (vs 3072 grid slots) plus 1 B/px of scores
     assert fast - grid >= 640 * 480 + (120 * 400 - 3072) * 8

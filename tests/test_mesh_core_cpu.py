@@ -29,8 +29,8 @@ def driver(tmp_path_factory):
     return out
 
 
-def _run(driver, W, H, batches):
-    lines = [f"{W} {H} {len(batches)}"]
+def _run(driver, W, H, batches, mode=0):
+    lines = [f"{W} {H} {len(batches)} {mode}"]
     for b in batches:
         lines.append(str(len(b)))
         lines += [f"{u} {v}" for (u, v) in b]
@@ -111,3 +111,21 @@ def test_device_insertion_steps_equal_oracle(driver, name, W, H, batches):
         assert status == 0
         ref = oracle.triangulate([(u, v) for (u, v) in pts], W)
         assert tris == [tuple(t) for t in ref], name
+
+
+@pytest.mark.parametrize("name,W,H,batches", _cases(), ids=[c[0] for c in _cases()])
+def test_device_start_mesh_equals_oracle(driver, name, W, H, batches):
+    """The first batch built on the device from supports in raster order (rows, ladders,
+    hull pockets, edge links, Lawson flips), then the later batches inserted."""
+    first = sorted(batches[0], key=lambda p: (p[1], p[0]))
+    if len({p[1] for p in first}) < 2:
+        pytest.skip("one row: no triangle")
+    batches = [first] + batches[1:]
+    got = _run(driver, W, H, batches, mode=1)
+    pts = []
+    for b, (status, tris) in zip(batches, got):
+        pts += b
+        assert status == 0, name
+        ref = oracle.triangulate([(u, v) for (u, v) in pts], W)
+        assert tris == [tuple(t) for t in ref], name
+
