@@ -138,12 +138,10 @@ struct ManyPlan {
   std::vector<int32_t> pack_off;  // staging slot offset of each frame (header + capacity)
   std::vector<int32_t> pack_cap;
   std::vector<int32_t> groups;   // distinct (rx << 8 | ry) census windows
-  // device-mesh frames: their triangles (tdev_off, in triangles) and their exported first
-  // mesh (exp_off, in records; exp_cap records each)
-  std::vector<int32_t> tdev_off, exp_off, exp_cap;
-  size_t desc_off = 0, off_off = 0, job_off = 0, tri_off = 0, pack_dev = 0, tdev = 0, exp_dev = 0, mstat = 0,
-         total = 0;
-  int32_t pack_slots = 0, tri_cap = 0, n_off_arrays = 0, tdev_cap = 0, exp_total = 0;
+  // device-mesh frames: their triangles (tdev_off, in triangles)
+  std::vector<int32_t> tdev_off;
+  size_t desc_off = 0, off_off = 0, job_off = 0, tri_off = 0, pack_dev = 0, tdev = 0, mstat = 0, total = 0;
+  int32_t pack_slots = 0, tri_cap = 0, n_off_arrays = 0, tdev_cap = 0;
 };
 
 constexpr int kOffArrays = 5;  // match, raster, validate, rematch, + one per census group
@@ -172,12 +170,7 @@ sm_status plan_many(const sm_frame* frames, int32_t n, ManyPlan& P) {
     P.pack_slots += cap + 1;
     P.tri_cap += L.T_cap;
     P.tdev_off.push_back(P.tdev_cap);
-    P.exp_off.push_back(P.exp_total);
-    P.exp_cap.push_back(L.mesh_on ? 3 * L.n_grid + 8 : 0);
-    if (L.mesh_on) {
-      P.tdev_cap += L.T_cap;
-      P.exp_total += 3 * L.n_grid + 8;
-    }
+    if (L.mesh_on) P.tdev_cap += L.T_cap;
     const int32_t key = ((fr.p.census_w - 1) / 2) << 8 | ((fr.p.census_h - 1) / 2);
     if (!grp.count(key)) {
       grp[key] = (int)P.groups.size();
@@ -197,8 +190,6 @@ sm_status plan_many(const sm_frame* frames, int32_t n, ManyPlan& P) {
   o = P.pack_dev + (size_t)P.pack_slots * sizeof(sm_support);
   P.tdev = align256(o);
   o = P.tdev + (size_t)P.tdev_cap * sizeof(sm_tri);
-  P.exp_dev = align256(o);  // exported meshes: tv of all frames, then tnb of all frames
-  o = P.exp_dev + (size_t)P.exp_total * 24;
   P.mstat = align256(o);
   o = P.mstat + (size_t)n * 32;
   P.total = align256(o);
@@ -250,11 +241,10 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
   const auto t_start = std::chrono::steady_clock::now();
   ManyCtx& c = many_ctx();
   // pinned staging: [desc | offsets | mesh jobs | triangles] (uploaded together), then
-  // [packed supports], [exported first meshes], [mesh status words]
+  // [packed supports], [mesh status words]
   const size_t up_bytes = P.pack_dev - P.desc_off;
   const size_t pack_bytes = align256((size_t)P.pack_slots * sizeof(sm_support));
-  const size_t exp_bytes = align256((size_t)P.exp_total * 24);
-  const size_t pin_need = up_bytes + pack_bytes + exp_bytes + (size_t)n * 32;
+  const size_t pin_need = up_bytes + pack_bytes + (size_t)n * 32;
   if (c.pinned_bytes < pin_need) {
     if (c.pinned) SM_HIP(hipHostFree(c.pinned));
     c.pinned = nullptr;
@@ -275,12 +265,10 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
   int32_t* hoff = (int32_t*)(hp + (P.off_off - P.desc_off));
   sm_tri* hT = (sm_tri*)(hp + (P.tri_off - P.desc_off));
   sm_support* hpack = (sm_support*)(hp + up_bytes);
-  int32_t* hexp = (int32_t*)(hp + up_bytes + pack_bytes);
-  int32_t* hmstat = (int32_t*)(hp + up_bytes + pack_bytes + exp_bytes);
+  int32_t* hmstat = (int32_t*)(hp + up_bytes + pack_bytes);
   MeshJob* hjobs = (MeshJob*)(hp + (P.job_off - P.desc_off));
   const MeshJob* djobs = (const MeshJob*)(base + P.job_off);
   sm_tri* dTdev = (sm_tri*)(base + P.tdev);
-  int32_t* dexp = (int32_t*)(base + P.exp_dev);
   int32_t* dmstat = (int32_t*)(base + P.mstat);
   const BatchFrame* dF = (const BatchFrame*)(base + P.desc_off);
   const int32_t* doff = (const int32_t*)(base + P.off_off);
@@ -339,7 +327,7 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     d.n_grid = L.n_grid;
     d.gw = L.n_grid > 0 ? (fr.W - 1 - fr.p.support_step / 2) / fr.p.support_step + 1 : 0;
     d.sz = occ_size(fr.p, 1);
-    d.pack = dpack + P.pack_off[f];
+    d.pack = L.mesh_on ? nullptr : dpack + P.pack_off[f];  // device-mesh frames keep their supports
     d.pack_cap = L.n_grid;
   }
   // census (one launch per census window) + grid matching offsets
@@ -356,6 +344,37 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     o[0] = 0;
     for (int32_t f = 0; f < n; ++f) o[f + 1] = o[f] + P.lay[f].n_grid;
   }
+  // frames whose meshes live on the device (grid supports, host_mesh = 0): the first mesh is
+  // built by one launch over them right after compaction; job j's status words come back
+  // in one copy
+  std::vector<uint8_t> mesh_dev(n, 0), job_start;
+  std::vector<int32_t> host_upto(n, 0), nT_dev(n, 0), job_frame;
+  auto add_job = [&](int32_t f, int32_t start, int32_t p0, const int32_t* n_new) {
+    const Layout& L = P.lay[f];
+    uint8_t* b = base + P.base[f];
+    MeshJob& jb = hjobs[job_frame.size()];
+    jb.S = hF[f].S;
+    jb.start = start;
+    jb.p0 = p0;
+    jb.n_new = n_new;
+    jb.init_tv = nullptr;
+    jb.init_tnb = nullptr;
+    jb.init_n = 0;
+    jb.status = (int32_t*)(b + L.mstatus);
+    jb.status_copy = dmstat + 8 * job_frame.size();
+    jb.T = dTdev + P.tdev_off[f];
+    jb.T_cap = L.T_cap;
+    jb.W = hF[f].W;
+    jb.H = hF[f].H;
+    jb.w = mesh_work_at(b + L.mwork, hF[f].W, hF[f].H, L.S_cap, L.mpcap);
+    job_frame.push_back(f);
+    job_start.push_back((uint8_t)start);
+  };
+  for (int32_t f = 0; f < n; ++f)
+    if (P.lay[f].mesh_on) {
+      mesh_dev[f] = 1;
+      add_job(f, 1, 0, (const int32_t*)(hF[f].S + hF[f].n_grid));
+    }
   auto t0 = std::chrono::steady_clock::now();
   SM_HIP(hipMemcpyAsync(base + P.desc_off, hp, P.tri_off - P.desc_off, hipMemcpyHostToDevice, s));
   us_xfer += since(t0);
@@ -370,6 +389,10 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
   SM_HIP(launch_batch_compact(dF, n, 0, s));
   SM_TRY(arm(SM_ST_COMPACT));
   SM_HIP(launch_batch_pack(dF, n, 0, s));
+  if (!job_frame.empty()) {
+    SM_TRY(arm(SM_ST_MESH));
+    SM_HIP(launch_mesh_insert_many(djobs, (int32_t)job_frame.size(), s));
+  }
 
   std::vector<int32_t> n_S(n, 0), iters(n);
   int max_iters = 0;
@@ -404,10 +427,6 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     n_S[f] += cnt;
   };
   std::vector<int32_t> todo;
-  // frames whose later tessellations run on the device: the count of their mesh insertions
-  // in flight (jobs), the triangles of their last insertion, the supports their host mesh holds
-  std::vector<uint8_t> mesh_dev(n, 0);
-  std::vector<int32_t> init_n(n, 0), host_upto(n, 0), nT_dev(n, 0), job_frame;
   // the frame's supports S[host_upto, upto) into its host mesh (after a device error)
   auto host_catch_up = [&](int32_t f, int32_t upto) -> sm_status {
     const int32_t m = upto - host_upto[f];
@@ -418,6 +437,7 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     us_xfer += since(t1);
     auto th = std::chrono::steady_clock::now();
     try {
+      if (host_upto[f] == 0) c.dl[f].reset();
       std::vector<int32_t> u(m), v(m), e(m);
       for (int32_t k = 0; k < m; ++k) {
         u[k] = tmp[k].u;
@@ -447,8 +467,8 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
       const int32_t f = job_frame[j];
       const int32_t* w = hmstat + 8 * j;
       const int32_t n_new = w[kMeshNew];
-      if (n_new < 0 || n_new > hF[f].region_n) return fail(SM_ERR_INTERNAL, "frame %d: resample count %d", f, n_new);
-      init_n[f] = 0;
+      const int32_t n_max = job_start[j] ? hF[f].n_grid : hF[f].region_n;
+      if (n_new < 0 || n_new > n_max) return fail(SM_ERR_INTERNAL, "frame %d: support count %d", f, n_new);
       if (w[kMeshErr] == 0) {
         if (w[kMeshTris] < 0 || w[kMeshTris] > P.lay[f].T_cap)
           return fail(SM_ERR_INTERNAL, "frame %d: device triangle count %d", f, w[kMeshTris]);
@@ -457,14 +477,15 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
         if (st) ++st->mesh_device;
         continue;
       }
-      // the device could not finish this frame: its host mesh takes every support since
-      // the first tessellation, and the frame stays on the host
+      // the device could not finish this frame (or found no mesh in its first supports): its
+      // host mesh takes every support so far, and the frame stays on the host
       mesh_dev[f] = 0;
-      if (st) ++st->mesh_fallback;
+      if (st && w[kMeshErr] != kMeshErrNoMesh) ++st->mesh_fallback;
       SM_TRY(host_catch_up(f, n_S[f] + n_new));
       n_S[f] += n_new;
     }
     job_frame.clear();
+    job_start.clear();
     if (todo.empty()) return SM_OK;
     auto th = std::chrono::steady_clock::now();
     next = 0;
@@ -486,36 +507,9 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     return SM_OK;
   };
   todo.clear();
-  for (int32_t f = 0; f < n; ++f) todo.push_back(f);
+  for (int32_t f = 0; f < n; ++f)
+    if (!mesh_dev[f]) todo.push_back(f);
   SM_TRY(run_host(true));
-  {  // first meshes of the device-mesh frames go up in one copy
-    auto th = std::chrono::steady_clock::now();
-    bool any = false;
-    for (int32_t f = 0; f < n; ++f) {
-      host_upto[f] = n_S[f];
-      if (!P.lay[f].mesh_on) continue;
-      int32_t r = 0;
-      try {
-        r = c.dl[f].export_mesh(hexp + 3 * (size_t)P.exp_off[f], hexp + 3 * ((size_t)P.exp_total + P.exp_off[f]),
-                                P.exp_cap[f]);
-      } catch (...) {
-        return fail(SM_ERR_INTERNAL, "frame %d: mesh export failed", f);
-      }
-      if (r < 0) return fail(SM_ERR_INTERNAL, "frame %d: mesh capacity exceeded", f);
-      if (r > 0) {  // else fewer than three independent supports: the frame stays on the host
-        mesh_dev[f] = 1;
-        init_n[f] = r;
-        any = true;
-      }
-    }
-    us_host += since(th);
-    if (any) {
-      auto t1 = std::chrono::steady_clock::now();
-      SM_HIP(hipMemcpyAsync(dexp, hexp, (size_t)P.exp_total * 24, hipMemcpyHostToDevice, s));
-      us_xfer += since(t1);
-    }
-  }
-
   for (int it = 1; it <= max_iters; ++it) {
     // iteration state, offsets and the triangles of every active frame
     int32_t toff = 0;
@@ -532,7 +526,7 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
       d.n_S = n_S[f];
       d.sz = occ_size(frames[f].p, std::min(it, iters[f]));
       d.last = act && it == iters[f];
-      if (mesh_dev[f] && it >= 2) {  // triangles written by the device insertion
+      if (mesh_dev[f]) {  // triangles written by the device
         d.n_T = act ? nT_dev[f] : 0;
         d.T = dTdev + P.tdev_off[f];
       } else {
@@ -549,25 +543,8 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
       d.region = rs ? d.S + n_S[f] : nullptr;
       d.pack_cap = d.region_n;
       d.pack = mesh_dev[f] ? nullptr : dpack + P.pack_off[f];
-      if (rs && mesh_dev[f]) {  // this iteration's resampled supports join the device mesh
-        const Layout& L = P.lay[f];
-        uint8_t* b = base + P.base[f];
-        MeshJob& jb = hjobs[job_frame.size()];
-        jb.S = d.S;
-        jb.p0 = n_S[f];
-        jb.n_new = (const int32_t*)(d.region + d.region_n);
-        jb.init_n = init_n[f];
-        jb.init_tv = dexp + 3 * (size_t)P.exp_off[f];
-        jb.init_tnb = dexp + 3 * ((size_t)P.exp_total + P.exp_off[f]);
-        jb.status = (int32_t*)(b + L.mstatus);
-        jb.status_copy = dmstat + 8 * job_frame.size();
-        jb.T = dTdev + P.tdev_off[f];
-        jb.T_cap = L.T_cap;
-        jb.W = d.W;
-        jb.H = d.H;
-        jb.w = mesh_work_at(b + L.mwork, d.W, d.H, L.S_cap, L.mpcap);
-        job_frame.push_back(f);
-      }
+      if (rs && mesh_dev[f])  // this iteration's resampled supports join the device mesh
+        add_job(f, 0, n_S[f], (const int32_t*)(d.region + d.region_n));
       resample |= rs;
       if (st && act && it <= 8) {
         st->n_support[it - 1] += n_S[f];
