@@ -318,7 +318,7 @@ def batched_runs(api, vga_frames, vga_params, workers=16, batches=12, dev="cuda:
     return out
 
 
-def serving_run(api, seconds=3.0, n_streams=16, slots=16, budget_gb=12.0, dev="cuda:0"):
+def serving_run(api, seconds=3.0, n_streams=16, slots=8, budget_gb=12.0, dev="cuda:0", device_mesh=True):
     """16 camera streams (640x480 / 1280x720 / 1920x1080 by stream id mod 3), Poisson
     arrivals at 30 Hz each, disparities 0-255, 3 iterations, replayed in real time
     through the continuous-batching server (latency), then all at once (capacity).
@@ -359,9 +359,10 @@ def serving_run(api, seconds=3.0, n_streams=16, slots=16, budget_gb=12.0, dev="c
         return pairs[(s % 3, (s // 3 + counter[s]) % 2)]
 
     out = {"streams": n_streams, "slots": slots, "budget_gb": budget_gb, "rate_hz": 30.0,
-           "solo_latency_ms_p50": solo}
+           "meshes": "device" if device_mesh else "host", "solo_latency_ms_p50": solo}
     for mode, scale in (("realtime", 1.0), ("saturated", 0.0)):
-        server = StereoServer(specs, n_slots=slots, budget_bytes=int(budget_gb * 2**30), device=dev)
+        server = StereoServer(specs, n_slots=slots, budget_bytes=int(budget_gb * 2**30), device=dev,
+                              device_mesh=device_mesh)
         sched = scenes.stream_schedule(seed=11, n_streams=n_streams, rate_hz=30.0, seconds=seconds)
         done, wall = replay(server, sched, frames_for, time_scale=scale)
         lat = np.array([r.latency for r in done if r.t_arrival >= 0.2 * scale * seconds]) * 1e3

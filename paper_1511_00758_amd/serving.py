@@ -120,13 +120,14 @@ class StereoServer:
     ``specs[stream]`` gives each camera stream's frame size and method parameters.
     ``on_done(req, D_f, C_f, mask)`` is called on the worker thread after the frame's
     outputs are complete (device tensors of the stream's resident state, valid until
-    that stream's next frame). ``device_mesh`` False (the default) triangulates every
-    tessellation on the host: slots overlap that with other frames' kernels, whereas a
-    device insertion is one long single-workgroup kernel per tessellation and those of
-    many slots would serialise on the device's hardware queues."""
+    that stream's next frame). ``device_mesh`` True (the default) keeps every
+    tessellation on the GPU; each is one long single-workgroup kernel, so with many more
+    slots than the device's hardware queues they wait on each other, and False
+    (triangulation on the host, overlapped with other frames' kernels) can serve more
+    frames per second there."""
 
     def __init__(self, specs: Dict[int, StreamSpec], n_slots: int, budget_bytes: int,
-                 device="cuda:0", on_done=None, device_mesh: bool = False):
+                 device="cuda:0", on_done=None, device_mesh: bool = True):
         import torch
         from . import api
         self._torch = torch
