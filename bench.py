@@ -48,15 +48,15 @@ def algorithmic_work(kernel, W, H, p, n_iters, launches, stats=None):
     launches of one solve), as (bound, amount, unit_scale, unit, per_unit_note)."""
     npx = W * H
     if kernel == "mesh":
-        # one insertion (tessellations 2..n): the supports read (8 B each), the live mesh
-        # records read and written once (tv + tnb, 24 B each, about one per triangle) and
-        # the triangles written (12 B each); a single workgroup whose rounds are bound by
-        # dependent-load latency, so the fraction of HBM peak is tiny by construction
-        if not stats or n_iters < 2:
+        # one tessellation (the first mesh or an insertion): the supports read (8 B each),
+        # the live mesh records read and written once (tv + tnb, 24 B each, about one per
+        # triangle) and the triangles written (12 B each); a single workgroup whose rounds
+        # are bound by instruction issue, so the fraction of HBM peak is tiny by construction
+        if not stats:
             return None
-        per = [8.0 * stats["n_support"][k] + 60.0 * stats["n_tris"][k] for k in range(1, n_iters)]
+        per = [8.0 * stats["n_support"][k] + 60.0 * stats["n_tris"][k] for k in range(n_iters)]
         amount = sum(per) / len(per)
-        return "hbm", amount, 1e9, "GB/s", (f"mean over tessellations 2..{n_iters}: 8 B x supports + "
+        return "hbm", amount, 1e9, "GB/s", (f"mean over tessellations 1..{n_iters}: 8 B x supports + "
                                             f"(2 x 24 + 12) B x triangles = {amount / 1e3:.1f} kB")
     bits = p["census_w"] * p["census_h"] - 1
     if kernel == "census":

@@ -274,7 +274,10 @@ size_t sm_solve_workspace_bytes(int32_t W, int32_t H, const sm_params* p /* [hos
  *   C_f      [H][W] uint8 out.
  *   mask     [H][W] uint8 out: 1 iff in Omega_I and C_f < t_hi (pixels that passed).
  *   st       [host] statistics, may be NULL.
- *   Synchronises `stream` once per triangulation (n_iters times).
+ *   Synchronisation: with grid candidates and device meshes (host_mesh = 0) the counts
+ *   stay on the device and `stream` is synchronised once, at the end of the frame (a frame
+ *   whose device mesh fails is solved again with host meshes, counted in
+ *   st->mesh_fallback); otherwise once per triangulation (n_iters times).
  */
 sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
                    const sm_params* p /* [host] */, void* ws, size_t ws_bytes, float* D_f,

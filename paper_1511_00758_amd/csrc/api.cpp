@@ -205,7 +205,7 @@ Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
   if (L.mesh_on) {
     L.mpcap = 1;
     for (int it = 1; it < p.n_iters; ++it) L.mpcap = std::max(L.mpcap, 2 * cells_of(W, H, occ_size(p, it)));
-    L.mstatus = take(64);
+    L.mstatus = take(kMeshStatusWords * sizeof(int32_t));
     L.mwork = take(mesh_work_bytes(W, H, L.S_cap, L.mpcap));
   }
   L.total = o;
@@ -412,7 +412,7 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   const MeshWork mw = Lo.mesh_on ? mesh_work_at(base + Lo.mwork, W, H, Lo.S_cap, Lo.mpcap) : MeshWork{};
   const size_t st_main = align256(std::max((size_t)Lo.S_cap * sizeof(sm_support), (size_t)Lo.T_cap * sizeof(sm_tri)));
   const size_t st_mesh = Lo.mesh_on ? align256((size_t)mw.cap * 12) : 0;
-  SM_TRY(ensure_pinned(c, 256 + st_main + 2 * st_mesh + 64));
+  SM_TRY(ensure_pinned(c, 256 + st_main + 2 * st_mesh + kMeshStatusWords * sizeof(int32_t)));
   int32_t* h_count = (int32_t*)c.pinned;
   sm_support* h_S = (sm_support*)((uint8_t*)c.pinned + 256);
   sm_tri* h_T = (sm_tri*)((uint8_t*)c.pinned + 256);
@@ -470,6 +470,7 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     job.init_tv = mw.tv;
     job.init_tnb = mw.tnb;
     job.init_n = start ? 0 : mesh_init;
+    job.n_new_slot = 0;
     job.status = d_mstatus;
     job.status_copy = nullptr;
     job.T = Td;
@@ -480,40 +481,78 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     return job;
   };
 
-  // S_1 and its mesh: with the grid candidates the compacted supports are in raster order
-  // and the first mesh is built on the device; else (FAST candidates, host_mesh, or a
-  // frame the device cannot mesh) the supports come to the host
-  auto t0 = clk::now();
-  int32_t n_S = -1, n_T = 0;
+  // Grid candidates: the compacted supports are in raster order, the first mesh is built on
+  // the device and every later tessellation inserts into it; the counts stay on the device
+  // (read by the raster, resampling, compaction and mesh kernels), so the frame needs one
+  // synchronisation, at its end. A frame whose device mesh fails is solved again with host
+  // meshes.
   if (Lo.mesh_on && !fast) {
+    const int32_t* counts = d_mstatus;
     SM_TRY(tm.begin(SM_ST_MESH));
     SM_HIP(launch_mesh_insert(mesh_job(1, 0, (const int32_t*)(Sd + Lo.n_grid)), s));
     SM_TRY(tm.end());
-    t0 = clk::now();
-    SM_HIP(hipMemcpyAsync(h_mstatus, d_mstatus, 32, hipMemcpyDeviceToHost, s));
-    SM_HIP(hipStreamSynchronize(s));
-    us_xfer += us_since(t0);
-    n_S = h_mstatus[kMeshNew];
-    if (n_S < 0 || n_S > Lo.n_grid) return fail(SM_ERR_INTERNAL, "support count %d out of range", n_S);
-    if (h_mstatus[kMeshErr] == 0) {
-      n_T = h_mstatus[kMeshTris];
-      if (n_T < 0 || n_T > Lo.T_cap) return fail(SM_ERR_INTERNAL, "device triangle count %d out of range", n_T);
-      mesh_dev = true;
-      if (st) ++st->mesh_device;
-    } else {
-      if (st && h_mstatus[kMeshErr] != kMeshErrNoMesh) ++st->mesh_fallback;
-      t0 = clk::now();
-      if (n_S > 0) SM_HIP(hipMemcpyAsync(h_S, Sd, (size_t)n_S * sizeof(sm_support), hipMemcpyDeviceToHost, s));
-      SM_HIP(hipStreamSynchronize(s));
-      us_xfer += us_since(t0);
+    for (int it = 1; it <= p->n_iters; ++it) {
+      const int32_t sz = occ_size(*p, it);
+      const bool last = it == p->n_iters;
+      SM_TRY(tm.begin(SM_ST_RASTER));
+      SM_HIP(launch_raster(Sd, Lo.S_cap, Td, Lo.T_cap, W, H, D_it, s, counts));
+      SM_TRY(tm.end());
+      SM_TRY(tm.begin(SM_ST_VALIDATE));
+      SM_HIP(launch_validate_only(cL, cR, omega, D_it, W, H, *p, sz, nullptr, D_f, C_f, cell_g, cell_b,
+                                  last ? mask : nullptr, last ? n_valid : nullptr, s));
+      SM_TRY(tm.end());
+      if (last) break;
+      const int32_t cells = cells_of(W, H, sz);
+      SM_TRY(tm.begin(SM_ST_REMATCH));
+      SM_HIP(launch_resample(cL, cR, cell_g, cell_b, D_it, W, H, sz, *p, Sd, s, counts + kMeshSupports, Lo.S_cap));
+      SM_TRY(tm.end());
+      SM_TRY(tm.begin(SM_ST_COMPACT));
+      SM_HIP(launch_compact(Sd, 2 * cells, &counters[1], occ, W, nullptr, s, counts + kMeshSupports, Lo.S_cap));
+      SM_TRY(tm.end());
+      MeshJob job = mesh_job(0, -1, nullptr);
+      job.n_new_slot = 2 * cells;
+      SM_TRY(tm.begin(SM_ST_MESH));
+      SM_HIP(launch_mesh_insert(job, s));
+      SM_TRY(tm.end());
     }
-  } else {
-    SM_HIP(hipMemcpyAsync(h_S, Sd, (size_t)(Lo.n_grid + 1) * sizeof(sm_support), hipMemcpyDeviceToHost, s));
+    auto t1 = clk::now();
+    SM_HIP(hipMemcpyAsync(h_mstatus, d_mstatus, kMeshStatusWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (st) SM_HIP(hipMemcpyAsync(h_count, n_valid, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     SM_HIP(hipStreamSynchronize(s));
-    us_xfer += us_since(t0);
-    std::memcpy(&n_S, &h_S[Lo.n_grid], sizeof(int32_t));
-    if (n_S < 0 || n_S > Lo.n_grid) return fail(SM_ERR_INTERNAL, "support count %d out of range", n_S);
+    us_xfer += us_since(t1);
+    if (h_mstatus[kMeshErr] != 0) {  // the frame again, every tessellation on the host
+      const bool failure = h_mstatus[kMeshErr] != kMeshErrNoMesh;
+      sm_params q = *p;
+      q.host_mesh = 1;
+      const sm_status r = sm_solve(L, R, W, H, stride, &q, ws, ws_bytes, D_f, C_f, mask, st, stream);
+      if (st && failure) ++st->mesh_fallback;
+      return r;
+    }
+    if (st) {
+      for (int k = 0; k < p->n_iters && k < 8; ++k) {
+        st->n_support[k] = h_mstatus[kMeshLog + 2 * k];
+        st->n_tris[k] = h_mstatus[kMeshLog + 2 * k + 1];
+      }
+      st->mesh_device = p->n_iters;
+      unsigned long long nv = 0;
+      std::memcpy(&nv, h_count, sizeof(nv));
+      st->n_valid = (int64_t)nv;
+      SM_TRY(tm.collect(st));
+      st->stage_us[SM_ST_HOST_TRI] = us_host;
+      st->stage_us[SM_ST_HOST_COPY] = us_xfer;
+      st->stage_us[SM_ST_TOTAL] = us_since(t_start);
+    }
+    return SM_OK;
   }
+
+  // FAST candidates or host meshes: the supports come to the host for the first mesh
+  auto t0 = clk::now();
+  int32_t n_S = -1, n_T = 0;
+  SM_HIP(hipMemcpyAsync(h_S, Sd, (size_t)(Lo.n_grid + 1) * sizeof(sm_support), hipMemcpyDeviceToHost, s));
+  SM_HIP(hipStreamSynchronize(s));
+  us_xfer += us_since(t0);
+  std::memcpy(&n_S, &h_S[Lo.n_grid], sizeof(int32_t));
+  if (n_S < 0 || n_S > Lo.n_grid) return fail(SM_ERR_INTERNAL, "support count %d out of range", n_S);
 
   int32_t host_upto = 0;  // supports S[0, host_upto) are in the host triangulation c.dl
   auto triangulate_and_upload = [&](int32_t from, int32_t to) -> sm_status {

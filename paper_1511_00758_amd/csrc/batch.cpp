@@ -360,6 +360,7 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     jb.init_tv = nullptr;
     jb.init_tnb = nullptr;
     jb.init_n = 0;
+    jb.n_new_slot = 0;
     jb.status = (int32_t*)(b + L.mstatus);
     jb.status_copy = dmstat + 8 * job_frame.size();
     jb.T = dTdev + P.tdev_off[f];

@@ -530,10 +530,16 @@ __device__ __forceinline__ void rematch_cell(const MatchArgs& a, const uint64_t*
 
 __global__ __launch_bounds__(256) void k_rematch_cells(MatchArgs a, const uint64_t* cell_g,
                                                        const uint64_t* cell_b, const float* D_it,
-                                                       int n_cells, uint64_t ginit, uint64_t binit) {
+                                                       int n_cells, uint64_t ginit, uint64_t binit,
+                                                       const int32_t* slot_off, int slot_cap) {
   const int lane = threadIdx.x & (kWave - 1);
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= n_cells) return;
+  if (slot_off) {  // region placed after the supports counted on the device
+    const int off = *slot_off;
+    if (off < 0 || (int64_t)off + 2 * n_cells + 1 > slot_cap) return;  // a failed mesh: nothing to add
+    a.slots += off;
+  }
   rematch_cell(a, cell_g, cell_b, D_it, n_cells, ginit, binit, c, lane);
 }
 
@@ -583,7 +589,13 @@ __device__ __forceinline__ void compact_block(sm_support* slots, int n, int* n_o
 }
 
 __global__ __launch_bounds__(1024) void k_compact(sm_support* slots, int n, int* n_out, uint8_t* occ,
-                                                  int W, int* header) {
+                                                  int W, int* header, const int32_t* slot_off, int slot_cap) {
+  if (slot_off) {  // region after the supports counted on the device; its count in the slot after it
+    const int off = *slot_off;
+    if (off < 0 || (int64_t)off + n + 1 > slot_cap) return;  // a failed mesh: nothing to compact
+    slots += off;
+    header = (int*)(slots + n);
+  }
   compact_block(slots, n, n_out, occ, W, header);
 }
 
@@ -622,6 +634,7 @@ __global__ void k_mark(const sm_support* S, int n, uint8_t* occ, int W, int H) {
 constexpr int kXcds = 8;
 constexpr int kTriPerWave = 4, kRowLanes = kWave / kTriPerWave;
 constexpr int kGroupLayoutMinTris = 16384;
+constexpr int kRasterStrideBlocks = 2048;  // 8 per CU
 
 __device__ __forceinline__ int xcd_block(int b, int nb) {
   const int x = b % kXcds, k = b / kXcds, q = nb / kXcds, r = nb % kXcds;
@@ -748,26 +761,36 @@ __device__ __forceinline__ void raster_tri_wave(const sm_support* S, int n_suppo
 }
 
 __global__ __launch_bounds__(256) void k_raster_wave(const sm_support* S, int n_support, const sm_tri* T,
-                                                     int n_tris, int W, int H, float* D) {
+                                                     int n_tris, int W, int H, float* D, const int32_t* counts) {
   const int lane = threadIdx.x & (kWave - 1);
   const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (counts) {  // counts kept on the device: n_tris is then the launch's upper bound
+    n_tris = min(n_tris, counts[kCountTris]);
+    n_support = min(n_support, counts[kCountSupports]);
+  }
   if (t >= n_tris) return;
   raster_tri_wave(S, n_support, T, t, W, H, D, lane);
 }
 
 __global__ __launch_bounds__(256) void k_raster_group(const sm_support* S, int n_support, const sm_tri* T,
-                                                      int n_tris, int W, int H, float* D) {
+                                                      int n_tris, int W, int H, float* D, const int32_t* counts) {
   const int lane = threadIdx.x & (kWave - 1);
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int t = (blk * 4 + (threadIdx.x >> 6)) * kTriPerWave + lane / kRowLanes;
   const int rl = lane % kRowLanes;
-  if (t >= n_tris) return;  // lanes are independent
-  const RasterTri r = raster_setup(S, n_support, T, t, W, H);
-  if (!r.ok) return;
-  for (int v = r.vmin + rl; v <= r.vmax; v += kRowLanes) {
-    int lo, hi;
-    raster_span(r, v, lo, hi);
-    raster_row(r, v, lo, hi, D + (size_t)v * W);
+  if (counts) {  // counts kept on the device: n_tris is then the launch's upper bound
+    n_tris = min(n_tris, counts[kCountTris]);
+    n_support = min(n_support, counts[kCountSupports]);
+  }
+  // lanes are independent; a grid smaller than the triangles strides over them
+  for (int tt = t; tt < n_tris; tt += gridDim.x * 4 * kTriPerWave) {
+    const RasterTri r = raster_setup(S, n_support, T, tt, W, H);
+    if (!r.ok) continue;
+    for (int v = r.vmin + rl; v <= r.vmax; v += kRowLanes) {
+      int lo, hi;
+      raster_span(r, v, lo, hi);
+      raster_row(r, v, lo, hi, D + (size_t)v * W);
+    }
   }
 }
 
@@ -1041,8 +1064,8 @@ hipError_t launch_match(const uint64_t* cL, const uint64_t* cR, int32_t W, int32
 }
 
 hipError_t launch_compact(sm_support* slots, int32_t n, int32_t* n_out, uint8_t* occ, int32_t W,
-                          int32_t* header, hipStream_t s) {
-  SM_LAUNCH(k_compact, dim3(1), dim3(1024), 0, s, slots, n, n_out, occ, W, header);
+                          int32_t* header, hipStream_t s, const int32_t* slot_off, int32_t slot_cap) {
+  SM_LAUNCH(k_compact, dim3(1), dim3(1024), 0, s, slots, n, n_out, occ, W, header, slot_off, (int)slot_cap);
   return hipGetLastError();
 }
 
@@ -1063,14 +1086,17 @@ hipError_t launch_fill_nan(float* D, size_t n, hipStream_t s) {
 }
 
 hipError_t launch_raster(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
-                         int32_t W, int32_t H, float* D_it, hipStream_t s) {
+                         int32_t W, int32_t H, float* D_it, hipStream_t s, const int32_t* counts) {
   if (n_tris <= 0) return hipSuccess;
-  if (n_tris < kGroupLayoutMinTris) {
+  if (counts) {  // the count is known on the device only: a bounded grid of the group layout
+    const unsigned blocks = std::min<unsigned>(blocks_for(n_tris, 4 * kTriPerWave), kRasterStrideBlocks);
+    SM_LAUNCH(k_raster_group, dim3(blocks), dim3(256), 0, s, S, n_support, T, n_tris, W, H, D_it, counts);
+  } else if (n_tris < kGroupLayoutMinTris) {
     SM_LAUNCH(k_raster_wave, dim3(blocks_for(n_tris, 4)), dim3(256), 0, s, S, n_support, T, n_tris, W,
-              H, D_it);
+              H, D_it, counts);
   } else {
     SM_LAUNCH(k_raster_group, dim3(blocks_for(n_tris, 4 * kTriPerWave)), dim3(256), 0, s, S, n_support,
-              T, n_tris, W, H, D_it);
+              T, n_tris, W, H, D_it, counts);
   }
   return hipGetLastError();
 }
@@ -1171,12 +1197,13 @@ hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t
 
 hipError_t launch_resample(const uint64_t* cL, const uint64_t* cR, const uint64_t* cell_g,
                            const uint64_t* cell_b, const float* D_it, int32_t W, int32_t H, int32_t sz,
-                           const sm_params& p, sm_support* slots, hipStream_t s) {
+                           const sm_params& p, sm_support* slots, hipStream_t s, const int32_t* slot_off,
+                           int32_t slot_cap) {
   const int n_cells = ((W + sz - 1) / sz) * ((H + sz - 1) / sz);
   const uint64_t ginit = (uint64_t)p.t_lo << 32, binit = (uint64_t)(255 - p.t_hi) << 32;
   const MatchArgs a = match_args(cL, cR, W, H, p, slots, 2 * n_cells);
   SM_LAUNCH(k_rematch_cells, dim3(blocks_for(n_cells, 4)), dim3(256), 0, s, a, cell_g, cell_b, D_it,
-            n_cells, ginit, binit);
+            n_cells, ginit, binit, slot_off, (int)slot_cap);
   return hipGetLastError();
 }
 

@@ -63,11 +63,19 @@ hipError_t launch_compact_uv(int16_t* uv, int32_t n, int32_t* n_out, hipStream_t
 hipError_t launch_match(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
                         const sm_params& p, sm_support* slots, int32_t n, hipStream_t s);
 
+// Counts kept on the device (the words of a frame's mesh status, mesh.hpp): the triangles
+// of the frame's current mesh and the supports it holds.
+enum { kCountTris = 1, kCountSupports = 5 };
+
 // Order-preserving in-place compaction of non-marker slots (and, when `occ` is
 // non-null, whose pixel is not yet occupied; kept pixels are then marked). The count
-// goes to n_out and, when non-null, also to header.
+// goes to n_out and, when non-null, also to header. With slot_off non-null the slots
+// start *slot_off entries after `slots` (a count on the device) and the count also goes
+// to the slot after the last one; nothing happens unless those n + 1 slots lie below
+// slot_cap.
 hipError_t launch_compact(sm_support* slots, int32_t n, int32_t* n_out, uint8_t* occ,
-                          int32_t W, int32_t* header, hipStream_t s);
+                          int32_t W, int32_t* header, hipStream_t s, const int32_t* slot_off = nullptr,
+                          int32_t slot_cap = 0);
 
 // Occupancy map of a support list (cleared first).
 hipError_t launch_mark(const sm_support* S, int32_t n, uint8_t* occ, int32_t W, int32_t H,
@@ -79,8 +87,10 @@ hipError_t launch_interpolate(const sm_support* S, int32_t n_support, const sm_t
 
 // Single-kernel pieces of the two launchers above (for per-kernel timing).
 hipError_t launch_fill_nan(float* D, size_t n, hipStream_t s);
+// With `counts` non-null, n_tris and n_support are upper bounds and the kernel reads the
+// triangle and support counts from counts[kCountTris], counts[kCountSupports].
 hipError_t launch_raster(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
-                         int32_t W, int32_t H, float* D_it, hipStream_t s);
+                         int32_t W, int32_t H, float* D_it, hipStream_t s, const int32_t* counts = nullptr);
 hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
                                 const float* D_it, int32_t W, int32_t H, const sm_params& p,
                                 int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f,
@@ -98,10 +108,13 @@ hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t
                            hipStream_t s);
 
 // Resampling fused with the re-match: confident supports of the cells at
-// slots[0, cells), re-matched invalid pixels at slots[cells, 2 cells).
+// slots[0, cells), re-matched invalid pixels at slots[cells, 2 cells); with slot_off
+// non-null the slots start *slot_off entries after `slots` (nothing happens unless the
+// 2 cells + 1 slots lie below slot_cap).
 hipError_t launch_resample(const uint64_t* cL, const uint64_t* cR, const uint64_t* cell_g,
                            const uint64_t* cell_b, const float* D_it, int32_t W, int32_t H, int32_t sz,
-                           const sm_params& p, sm_support* slots, hipStream_t s);
+                           const sm_params& p, sm_support* slots, hipStream_t s,
+                           const int32_t* slot_off = nullptr, int32_t slot_cap = 0);
 
 // ---------------------------------------------------------------------------------
 // Stage-batched solve of many frames: every stage is one launch over all frames. The

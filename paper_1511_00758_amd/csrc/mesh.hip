@@ -72,7 +72,7 @@ __device__ void block_scan1(int v, int* wsum, int& excl, int& total) {
 }
 
 template <bool kLds>
-__device__ void mesh_insert_block(const MeshJob& a, int32_t n_new) {
+__device__ void mesh_insert_block(const MeshJob& a, int32_t p0, int32_t n_new) {
   using namespace mesh;
   using DA = DevA<kLds>;
   __shared__ int32_t s_np[2], s_nw[2], s_nrec, s_err, s_any, s_ntri;
@@ -84,17 +84,27 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t n_new) {
   const bool fresh = !start && a.init_n > 0;
   const int32_t n_rec0 = start ? 0 : (fresh ? a.init_n : a.status[kMeshRecords]);
   const int32_t base_round = start || fresh ? 0 : a.status[kMeshRounds];
-  const int32_t n_pts = a.p0 + n_new;
+  const int32_t tess = start || fresh ? 0 : a.status[kMeshTess];
+  const int32_t prior_err = start || fresh ? 0 : a.status[kMeshErr];
+  const int32_t n_pts = p0 + n_new;
   auto finish = [&](int32_t n_rec, int32_t n_tri, int32_t err, int32_t rounds) {  // thread 0
-    const int32_t words[8] = {n_rec, n_tri, err, rounds, n_new, 0, 0, 0};
+    const int32_t words[8] = {n_rec, n_tri, err, rounds, n_new, n_pts, tess + 1, 0};
     for (int k = 0; k < 8; ++k) {
       a.status[k] = words[k];
       if (a.status_copy) a.status_copy[k] = words[k];
     }
+    if (tess >= 0 && tess < 8) {
+      a.status[kMeshLog + 2 * tess] = n_pts;
+      a.status[kMeshLog + 2 * tess + 1] = n_tri;
+    }
   };
   __syncthreads();
-  const bool bad = start ? (a.p0 != 0 || n_new < 0 || n_pts > w.S_cap)
-                         : (n_rec0 <= 0 || n_rec0 > w.cap || n_new < 0 || n_new > w.pcap || a.p0 < 3 ||
+  if (prior_err != 0) {  // an earlier tessellation failed: the frame goes to the host
+    if (tid == 0) finish(n_rec0, 0, prior_err, base_round);
+    return;
+  }
+  const bool bad = start ? (p0 != 0 || n_new < 0 || n_pts > w.S_cap)
+                         : (n_rec0 <= 0 || n_rec0 > w.cap || n_new < 0 || n_new > w.pcap || p0 < 3 ||
                             n_pts > w.S_cap || base_round < 0 || base_round >= kMaxRounds);
   if (bad || (start && n_new < 3)) {
     if (tid == 0) finish(n_rec0, 0, bad ? kErrCapacity : kMeshErrNoMesh, base_round);
@@ -124,7 +134,7 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t n_new) {
   m.fj = w.fj;
   m.fkey = w.fkey;
   m.cap = w.cap;
-  m.p0 = a.p0;
+  m.p0 = p0;
   m.ploc = w.ploc;
   m.pk = w.pk;
   m.psib = w.psib;
@@ -147,7 +157,7 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t n_new) {
       bool ok = true;
       for (int k = 0; k < 3; ++k) {
         const int32_t v = a.init_tv[3 * t + k], nb = a.init_tnb[3 * t + k];
-        ok &= (v >= 0 && v < a.p0) || (k == 2 && v == kGhost);
+        ok &= (v >= 0 && v < p0) || (k == 2 && v == kGhost);
         ok &= nb >= 0 && nb < n_rec0;
         w.tv[3 * t + k] = v;
         w.tnb[3 * t + k] = nb;
@@ -253,7 +263,7 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t n_new) {
   if (start) {
   } else if (s_err == 0 && s_any >= 0) {
     for (int32_t i = tid; i < n_new; i += kMeshThreads) {
-      const P2 q = xy<DA>(m, a.p0 + i);
+      const P2 q = xy<DA>(m, p0 + i);
       int32_t h = w.hint[(q.y >> kHintShift) * gw + (q.x >> kHintShift)];
       if (h < 0) h = s_any;
       const int32_t t = walk<DA>(m, h, q, n_rec0, n_rec0 + 16);
@@ -328,9 +338,17 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t n_new) {
 }
 
 __device__ void mesh_insert(const MeshJob& a) {
-  const int32_t n_new = *a.n_new;  // the same for every thread: the branch is uniform
-  if ((int64_t)a.p0 + n_new <= kUvLds) mesh_insert_block<true>(a, n_new);
-  else mesh_insert_block<false>(a, n_new);
+  // the same for every thread: the branches are uniform
+  int32_t p0 = a.p0, n_new = 0;
+  if (p0 >= 0) {
+    n_new = *a.n_new;
+  } else {  // first new support and its count kept on the device
+    p0 = a.status[kMeshSupports];
+    if (p0 < 3 || p0 >= a.w.S_cap || a.n_new_slot < 0 || (int64_t)p0 + a.n_new_slot >= a.w.S_cap) p0 = 0, n_new = -1;
+    else n_new = *(const int32_t*)(a.S + p0 + a.n_new_slot);
+  }
+  if ((int64_t)p0 + n_new <= kUvLds) mesh_insert_block<true>(a, p0, n_new);
+  else mesh_insert_block<false>(a, p0, n_new);
 }
 
 __global__ __launch_bounds__(kMeshThreads) void k_mesh_insert(MeshJob a) { mesh_insert(a); }

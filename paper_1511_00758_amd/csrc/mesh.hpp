@@ -31,14 +31,18 @@ struct MeshWork {  // per-frame arrays: records [cap], new points [pcap], coordi
   int32_t cap, pcap, S_cap, hcap;
 };
 
-// Mesh status words (device, 8 x int32):
+// Mesh status words (device, kMeshStatusWords x int32), the frame's record of its mesh:
 //   [0] records in use
 //   [1] triangles written to T
 //   [2] error code (0 = ok, else the records are unusable and the caller triangulates on
-//       the host)
+//       the host; a later insertion keeps the code and writes no triangles)
 //   [3] rounds used so far by the frame (keys of later rounds must bid lower)
 //   [4] number of new supports read from n_new
-enum { kMeshRecords = 0, kMeshTris = 1, kMeshErr = 2, kMeshRounds = 3, kMeshNew = 4 };
+//   [5] supports in the mesh so far (p0 + new supports)
+//   [6] tessellations done
+//   [8 + 2k], [9 + 2k] supports and triangles after tessellation k (k < 8)
+enum { kMeshRecords = 0, kMeshTris = 1, kMeshErr = 2, kMeshRounds = 3, kMeshNew = 4, kMeshSupports = 5,
+       kMeshTess = 6, kMeshLog = 8, kMeshStatusWords = 32 };
 // error code of a first mesh that cannot exist (fewer than two rows of supports: no
 // triangle, or all supports collinear); the host path handles that frame
 constexpr int32_t kMeshErrNoMesh = 10;
@@ -47,13 +51,14 @@ struct MeshJob {
   const sm_support* S;
   int32_t start;            // 1: build the frame's first mesh from S[0, *n_new) (sorted by
                             //    raster position, p0 = 0), then flip it to Delaunay
-  int32_t p0;               // first new support
-  const int32_t* n_new;     // device count of new supports
+  int32_t p0;               // first new support; < 0: status[kMeshSupports] (counted on the device)
+  const int32_t* n_new;     // device count of new supports; with p0 < 0 it sits at
+  int32_t n_new_slot;       //   S[p0 + n_new_slot] instead
   const int32_t* init_tv;   // init_n > 0: the frame's first mesh (records in host form) to
   const int32_t* init_tnb;  //   start from, vertices < p0; may alias w.tv / w.tnb
   int32_t init_n;
-  int32_t* status;          // device [8], read (unless init_n > 0) and written
-  int32_t* status_copy;     // nullable: device [8], a copy of the words written
+  int32_t* status;          // device [kMeshStatusWords], read (unless start or init_n > 0) and written
+  int32_t* status_copy;     // nullable: device [8], a copy of words 0..7
   sm_tri* T;
   int32_t T_cap;
   int32_t W, H;
