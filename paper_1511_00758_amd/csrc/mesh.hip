@@ -24,31 +24,55 @@ constexpr int kMeshThreads = 1024;
 constexpr int kHintShift = 4;        // 16 x 16 px hint cells
 constexpr int kHintBoxCells = 64;    // a record marks every cell of its box up to this many
 constexpr int32_t kUvLds = 32768;    // supports whose coordinates fit in LDS (128 KiB)
+constexpr int kEdgeBatch = 4;        // edges a thread has in flight while linking the first mesh
+constexpr int kOutBatch = 2;         // records a thread has in flight in the output
 
 // Packed coordinates of the frame's supports when they fit (one workgroup per CU).
 __shared__ int32_t g_uv[kUvLds];
 
-// Atomics of the per-item steps. Votes are read and written only with atomics at device
-// scope, so that no stale L1 line is ever read; counters and the error code live in LDS.
-// Coordinates come from LDS (kLds) or from the global copy.
+// Atomics of the per-item steps. One workgroup owns a frame's mesh, so every atomic has
+// workgroup scope: it is performed in the L2 of the workgroup's XCD, where the plain
+// accesses of the other waves meet it (device scope would send each one to memory).
+// Counters and the error code live in LDS. Coordinates come from LDS (kLds) or from the
+// global copy.
 template <bool kLds>
 struct DevA {
   __device__ static void vote_min(uint64_t* p, uint64_t v) {
-    atomicMin((unsigned long long*)p, (unsigned long long)v);
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __device__ static uint64_t vote_get(const uint64_t* p) {
-    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(const_cast<uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __device__ static void vote_set(uint64_t* p, uint64_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __device__ static int32_t push(int32_t* n, int32_t k) { return atomicAdd(n, k); }
   __device__ static void fail(int32_t* err, int32_t code) { atomicCAS(err, 0, code); }
   __device__ static int32_t uv(const mesh::Mesh& m, int32_t p) { return kLds ? g_uv[p] : m.uv[p]; }
   __device__ static uint64_t cas64(uint64_t* p, uint64_t expected, uint64_t desired) {
-    return atomicCAS((unsigned long long*)p, (unsigned long long)expected, (unsigned long long)desired);
+    __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+    return expected;  // the value found: desired was stored iff it equals the expected one
   }
 };
+
+// Location hints: every 16 x 16 px cell of live solid record t's bounding box (the cells of
+// its vertices when the box is large) points at it.
+template <class A>
+__device__ void mark_hints(const mesh::Mesh& m, int32_t* hint, int gw, int32_t t, int32_t a, int32_t b, int32_t c) {
+  using namespace mesh;
+  const P2 P = xy<A>(m, a), B = xy<A>(m, b), C = xy<A>(m, c);
+  const int x0 = min(min(P.x, B.x), C.x) >> kHintShift, x1 = max(max(P.x, B.x), C.x) >> kHintShift;
+  const int y0 = min(min(P.y, B.y), C.y) >> kHintShift, y1 = max(max(P.y, B.y), C.y) >> kHintShift;
+  if ((x1 - x0 + 1) * (y1 - y0 + 1) <= kHintBoxCells) {
+    for (int y = y0; y <= y1; ++y)
+      for (int x = x0; x <= x1; ++x) hint[y * gw + x] = t;
+  } else {
+    hint[(P.y >> kHintShift) * gw + (P.x >> kHintShift)] = t;
+    hint[(B.y >> kHintShift) * gw + (B.x >> kHintShift)] = t;
+    hint[(C.y >> kHintShift) * gw + (C.x >> kHintShift)] = t;
+  }
+}
 
 // Exclusive block-wide prefix sum of one count per thread (every thread calls it).
 __device__ void block_scan1(int v, int* wsum, int& excl, int& total) {
@@ -72,10 +96,10 @@ __device__ void block_scan1(int v, int* wsum, int& excl, int& total) {
 }
 
 template <bool kLds>
-__device__ void mesh_insert_block(const MeshJob& a, int32_t p0, int32_t n_new) {
+__device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, int32_t n_new) {
   using namespace mesh;
   using DA = DevA<kLds>;
-  __shared__ int32_t s_np[2], s_nw[2], s_nrec, s_err, s_any, s_ntri;
+  __shared__ int32_t s_np[2], s_nw[2], s_nrec, s_err, s_any, s_ntri, s_next_any;
   __shared__ int s_wsum[kMeshThreads / 64];
   const int tid = threadIdx.x, lane = tid & 63;
   const MeshWork& w = a.w;
@@ -88,7 +112,7 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t p0, int32_t n_new) {
   const int32_t prior_err = start || fresh ? 0 : a.status[kMeshErr];
   const int32_t n_pts = p0 + n_new;
   auto finish = [&](int32_t n_rec, int32_t n_tri, int32_t err, int32_t rounds) {  // thread 0
-    const int32_t words[8] = {n_rec, n_tri, err, rounds, n_new, n_pts, tess + 1, 0};
+    const int32_t words[8] = {n_rec, n_tri, err, rounds, n_new, n_pts, tess + 1, err == 0 ? s_next_any : -1};
     for (int k = 0; k < 8; ++k) {
       a.status[k] = words[k];
       if (a.status_copy) a.status_copy[k] = words[k];
@@ -116,7 +140,9 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t p0, int32_t n_new) {
     s_np[1] = s_nw[1] = 0;
     s_nrec = n_rec0;
     s_err = 0;
-    s_any = -1;
+    // a later tessellation locates its points from the hints the previous one left
+    s_any = start || fresh ? -1 : a.status[kMeshAny];
+    s_next_any = -1;
     s_ntri = 0;
   }
   const int32_t gw = (a.W + 15) >> kHintShift, gh = (a.H + 15) >> kHintShift;
@@ -167,9 +193,15 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t p0, int32_t n_new) {
       DA::vote_set(&w.vote[t], ~0ull);
     }
   }
-  for (int32_t c = tid; c < gw * gh; c += kMeshThreads) w.hint[c] = -1;
+  // the edge table of a first mesh: 16 slots per support (about 6 directed edges each),
+  // within the workspace's table
+  int32_t hcap = 1024;
+  while (hcap < w.hcap && hcap < 16 * (int64_t)n_new) hcap <<= 1;
+  hcap = min(hcap, w.hcap);
+  if (fresh)
+    for (int32_t c = tid; c < gw * gh; c += kMeshThreads) w.hint[c] = -1;
   if (start) {
-    for (int32_t h = tid; h < w.hcap; h += kMeshThreads) w.hkeys[h] = kEmptyEdge;
+    for (int32_t h = tid; h < hcap; h += kMeshThreads) w.hkeys[h] = kEmptyEdge;
     for (int32_t i = tid; i < n_new; i += kMeshThreads) w.gh_start[i] = w.gh_end[i] = -1;
   }
   __syncthreads();
@@ -178,13 +210,14 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t p0, int32_t n_new) {
     Start st;
     st.n = n_new;
     st.row_first = w.row_first;
+    st.row_of = w.row_of;
     st.strip_base = w.strip_base;
     st.gh_start = w.gh_start;
     st.gh_end = w.gh_end;
     st.stack = w.stack;
     st.keys = w.hkeys;
     st.vals = w.hvals;
-    st.hcap = w.hcap;
+    st.hcap = hcap;
     // rows: each thread scans a contiguous run of supports
     const int32_t per = (n_new + kMeshThreads - 1) / kMeshThreads;
     const int32_t lo = min(tid * per, n_new), hi = min(lo + per, n_new);
@@ -192,8 +225,10 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t p0, int32_t n_new) {
     for (int32_t i = lo; i < hi; ++i) cnt += row_starts<DA>(m, i, &s_err);
     int base, n_rows;
     block_scan1(cnt, s_wsum, base, n_rows);
-    for (int32_t i = lo; i < hi; ++i)
+    for (int32_t i = lo; i < hi; ++i) {
       if (row_starts<DA>(m, i, &s_err)) w.row_first[base++] = i;
+      w.row_of[i] = base - 1;
+    }
     __syncthreads();
     if (n_rows < 2 || s_err != 0) {  // uniform: read after the barrier, nothing writes s_err here
       if (tid == 0) finish(0, 0, s_err != 0 ? s_err : kMeshErrNoMesh, 0);
@@ -213,20 +248,75 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t p0, int32_t n_new) {
     }
     if (tid == 0) s_nrec = n_ladder;
     __syncthreads();
-    for (int32_t r = tid; r < ns; r += kMeshThreads) ladder<DA>(m, st, r, n_rows);
+    for (int32_t i = tid; i < n_new; i += kMeshThreads) ladder_point<DA>(m, st, i, n_rows);
+    // hull pockets: the two side chains, one thread each; the row starts and both stacks
+    // sit in LDS after the coordinates when they fit (a branch of its own, so that its
+    // accesses compile to LDS instructions)
+    const bool chain_lds = kLds && (int64_t)n_new + 3 * (int64_t)n_rows <= kUvLds;
+    if (chain_lds)
+      for (int32_t r = tid; r < n_rows; r += kMeshThreads) g_uv[n_new + r] = w.row_first[r];
     __syncthreads();
-    // hull pockets: the two side chains on two waves
-    if (tid == 0) pockets<DA>(m, st, 1, n_rows, &s_nrec, &s_err);
-    if (tid == 64) pockets<DA>(m, st, 0, n_rows, &s_nrec, &s_err);
+    if (chain_lds) {
+      Start sp = st;
+      sp.row_first = g_uv + n_new;
+      sp.stack = g_uv + n_new + n_rows;
+      if (tid == 0) pockets<DA>(m, sp, 1, n_rows, &s_nrec, &s_err);
+      if (tid == 64) pockets<DA>(m, sp, 0, n_rows, &s_nrec, &s_err);
+    } else {
+      if (tid == 0) pockets<DA>(m, st, 1, n_rows, &s_nrec, &s_err);
+      if (tid == 64) pockets<DA>(m, st, 0, n_rows, &s_nrec, &s_err);
+    }
     __syncthreads();
     const int32_t n_solid = s_nrec;
     if (n_solid == 0 || s_err != 0) {  // every support on one line (or a full array)
       if (tid == 0) finish(0, 0, s_err != 0 ? s_err : kMeshErrNoMesh, 0);
       return;
     }
-    for (int32_t e = tid; e < 3 * n_solid; e += kMeshThreads) edge_insert<DA>(m, st, e / 3, e % 3, &s_err);
+    // links: every thread keeps kEdgeBatch first probes in flight (compare-and-swap when
+    // inserting, a load when looking up the reverse edge), then settles them in order
+    const int32_t n_edges = 3 * n_solid;
+    for (int32_t e0 = tid; e0 < n_edges; e0 += kEdgeBatch * kMeshThreads) {
+      uint64_t key[kEdgeBatch], old[kEdgeBatch];
+      uint32_t h[kEdgeBatch];
+#pragma unroll
+      for (int b = 0; b < kEdgeBatch; ++b) {
+        const int32_t e = e0 + b * kMeshThreads;
+        if (e >= n_edges) continue;
+        key[b] = solid_edge_key(m, e / 3, e % 3, false);
+        h[b] = edge_hash(key[b]) & (uint32_t)(hcap - 1);
+        old[b] = DA::cas64(&st.keys[h[b]], kEmptyEdge, key[b]);
+      }
+#pragma unroll
+      for (int b = 0; b < kEdgeBatch; ++b) {
+        const int32_t e = e0 + b * kMeshThreads;
+        if (e < n_edges) edge_insert_from<DA>(st, key[b], e, h[b], old[b], &s_err);
+      }
+    }
     __syncthreads();
-    for (int32_t e = tid; e < 3 * n_solid; e += kMeshThreads) edge_link<DA>(m, st, e / 3, e % 3, &s_nrec, &s_err);
+    for (int32_t e0 = tid; e0 < n_edges; e0 += kEdgeBatch * kMeshThreads) {
+      uint64_t key[kEdgeBatch], cur[kEdgeBatch];
+      uint32_t h[kEdgeBatch];
+      int32_t slot[kEdgeBatch], val[kEdgeBatch];
+#pragma unroll
+      for (int b = 0; b < kEdgeBatch; ++b) {
+        const int32_t e = e0 + b * kMeshThreads;
+        if (e >= n_edges) continue;
+        key[b] = solid_edge_key(m, e / 3, e % 3, true);
+        h[b] = edge_hash(key[b]) & (uint32_t)(hcap - 1);
+        cur[b] = DA::vote_get(&st.keys[h[b]]);
+      }
+#pragma unroll
+      for (int b = 0; b < kEdgeBatch; ++b) {
+        const int32_t e = e0 + b * kMeshThreads;
+        slot[b] = e < n_edges ? edge_find_from<DA>(st, key[b], h[b], cur[b]) : -1;
+        val[b] = slot[b] >= 0 ? st.vals[slot[b]] : 0;
+      }
+#pragma unroll
+      for (int b = 0; b < kEdgeBatch; ++b) {
+        const int32_t e = e0 + b * kMeshThreads;
+        if (e < n_edges) edge_link_to<DA>(m, st, e / 3, e % 3, slot[b], val[b], &s_nrec, &s_err);
+      }
+    }
     __syncthreads();
     const int32_t n_all = min(s_nrec, w.cap);
     for (int32_t g = n_solid + tid; g < n_all; g += kMeshThreads) ghost_link<DA>(m, st, g, &s_err);
@@ -238,22 +328,11 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t p0, int32_t n_new) {
     if (tid == 0) s_nw[0] = n_solid;
   }
 
-  // hints: every cell of a live solid record's bounding box (the vertex cells of a record
-  // whose box is large) points at it
-  if (!start && s_err == 0) {
+  // hints of a mesh from the host (a device mesh leaves its hints in its output)
+  if (fresh && s_err == 0) {
     for (int32_t t = tid; t < n_rec0; t += kMeshThreads) {
       if (w.dead[t] || w.tv[3 * t + 2] == kGhost) continue;
-      const P2 A = xy<DA>(m, w.tv[3 * t]), B = xy<DA>(m, w.tv[3 * t + 1]), C = xy<DA>(m, w.tv[3 * t + 2]);
-      const int x0 = min(min(A.x, B.x), C.x) >> kHintShift, x1 = max(max(A.x, B.x), C.x) >> kHintShift;
-      const int y0 = min(min(A.y, B.y), C.y) >> kHintShift, y1 = max(max(A.y, B.y), C.y) >> kHintShift;
-      if ((x1 - x0 + 1) * (y1 - y0 + 1) <= kHintBoxCells) {
-        for (int y = y0; y <= y1; ++y)
-          for (int x = x0; x <= x1; ++x) w.hint[y * gw + x] = t;
-      } else {
-        w.hint[(A.y >> kHintShift) * gw + (A.x >> kHintShift)] = t;
-        w.hint[(B.y >> kHintShift) * gw + (B.x >> kHintShift)] = t;
-        w.hint[(C.y >> kHintShift) * gw + (C.x >> kHintShift)] = t;
-      }
+      mark_hints<DA>(m, w.hint, gw, t, w.tv[3 * t], w.tv[3 * t + 1], w.tv[3 * t + 2]);
       atomicMax(&s_any, t);
     }
   }
@@ -319,25 +398,51 @@ __device__ void mesh_insert_block(const MeshJob& a, int32_t p0, int32_t n_new) {
     return;
   }
 
-  // output: live solid records, one atomic per wave for their slots
+  // output: live solid records as triangles, and the hints of the next tessellation (the
+  // walks of this one are over). Each thread has kOutBatch records in flight; one atomic
+  // per wave reserves their slots.
+  for (int32_t c = tid; c < gw * gh; c += kMeshThreads) w.hint[c] = -1;
+  __syncthreads();
   const int32_t n_rec = s_nrec;
-  for (int32_t t0 = 0; t0 < n_rec; t0 += kMeshThreads) {
-    const int32_t t = t0 + tid;
-    const bool out = t < n_rec && !w.dead[t] && w.tv[3 * t + 2] != kGhost;
-    const unsigned long long mask = __ballot(out);
+  for (int32_t base = 0; base < n_rec; base += kOutBatch * kMeshThreads) {  // uniform: the wave scans below
+    const int32_t t0 = base + tid;
+    unsigned outm = 0;  // bit b: record t0 + b * kMeshThreads is output
+    int any = -1;
+#pragma unroll
+    for (int b = 0; b < kOutBatch; ++b) {
+      const int32_t t = t0 + b * kMeshThreads;
+      const bool out = t < n_rec && !w.dead[t] && w.tv[3 * t + 2] != kGhost;
+      outm |= (unsigned)out << b;
+      if (out) any = t;
+    }
+    const int cnt = __popc(outm);
+    int inc = cnt;  // inclusive scan over the wave
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int x = __shfl_up(inc, d);
+      if (lane >= d) inc += x;
+    }
     int slot = 0;
-    if (lane == 0 && mask) slot = atomicAdd(&s_ntri, __popcll(mask));
-    slot = __shfl(slot, 0) + __popcll(mask & ((1ull << lane) - 1ull));
-    if (out) {
-      if (slot < a.T_cap) a.T[slot] = top_first<DA>(m, t);
+    if (lane == 63 && inc > 0) slot = atomicAdd(&s_ntri, inc);
+    slot = __shfl(slot, 63) + inc - cnt;
+    const unsigned long long has = __ballot(any >= 0);  // one record per wave suffices
+    if (has && lane == __ffsll((long long)has) - 1) atomicMax(&s_next_any, any);
+#pragma nounroll
+    for (int b = 0; b < kOutBatch; ++b) {
+      if (!(outm >> b & 1u)) continue;
+      const int32_t t = t0 + b * kMeshThreads;
+      const int32_t v0 = w.tv[3 * t], v1 = w.tv[3 * t + 1], v2 = w.tv[3 * t + 2];
+      if (slot < a.T_cap) a.T[slot] = top_first3<DA>(m, v0, v1, v2);
       else DA::fail(&s_err, kErrCapacity);
+      ++slot;
+      mark_hints<DA>(m, w.hint, gw, t, v0, v1, v2);
     }
   }
   __syncthreads();
   if (tid == 0) finish(n_rec, s_ntri, s_err, base_round + round);
 }
 
-__device__ void mesh_insert(const MeshJob& a) {
+__device__ __forceinline__ void mesh_insert(const MeshJob& a) {
   // the same for every thread: the branches are uniform
   int32_t p0 = a.p0, n_new = 0;
   if (p0 >= 0) {
@@ -353,8 +458,32 @@ __device__ void mesh_insert(const MeshJob& a) {
 
 __global__ __launch_bounds__(kMeshThreads) void k_mesh_insert(MeshJob a) { mesh_insert(a); }
 
-__global__ __launch_bounds__(kMeshThreads) void k_mesh_insert_many(const MeshJob* jobs) {
-  mesh_insert(jobs[blockIdx.x]);
+// A pointer read from device memory has no known address space; this one is global, and
+// saying so turns its accesses into global (not flat) instructions.
+template <class T>
+__device__ __forceinline__ T* as_global(T* p) {
+  return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
+__global__ __launch_bounds__(kMeshThreads) void k_mesh_insert_many(const MeshJob* __restrict__ jobs) {
+  MeshJob a = jobs[blockIdx.x];
+  a.S = as_global(a.S);
+  a.n_new = as_global(a.n_new);
+  a.init_tv = as_global(a.init_tv);
+  a.init_tnb = as_global(a.init_tnb);
+  a.status = as_global(a.status);
+  a.status_copy = as_global(a.status_copy);
+  a.T = as_global(a.T);
+  MeshWork& w = a.w;
+  for (int32_t** q : {&w.tv, &w.tnb, &w.own, &w.kids, &w.dead, &w.fk, &w.fs, &w.fj, &w.work0, &w.work1, &w.ploc,
+                      &w.pk, &w.psib, &w.pend0, &w.pend1, &w.uv, &w.hint, &w.row_first, &w.row_of, &w.strip_base,
+                      &w.gh_start, &w.gh_end, &w.stack, &w.hvals})
+    *q = as_global(*q);
+  w.vote = as_global(w.vote);
+  w.fkey = as_global(w.fkey);
+  w.pkey = as_global(w.pkey);
+  w.hkeys = as_global(w.hkeys);
+  mesh_insert(a);
 }
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -397,6 +526,7 @@ MeshWork carve(Carve& c, int32_t W, int32_t H, int32_t S_cap, int32_t pcap) {
   int32_t hcap = 1024;
   while (hcap < 16 * (int64_t)S_cap && hcap < (1 << 28)) hcap <<= 1;  // 6 directed edges per support, load <= 3/8
   w.row_first = c.take<int32_t>((size_t)S_cap + 1);
+  w.row_of = c.take<int32_t>((size_t)S_cap);
   w.strip_base = c.take<int32_t>((size_t)S_cap + 1);
   w.gh_start = c.take<int32_t>((size_t)S_cap);
   w.gh_end = c.take<int32_t>((size_t)S_cap);

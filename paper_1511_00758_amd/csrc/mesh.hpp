@@ -23,9 +23,9 @@ struct MeshWork {  // per-frame arrays: records [cap], new points [pcap], coordi
   uint64_t* pkey;
   int32_t* uv;    // packed coordinates when they do not fit in LDS
   int32_t* hint;  // location hints, one per 16 x 16 px cell
-  // first mesh built on the device: rows, strips, hull ghosts per vertex, chain stacks,
-  // edge hash table (hcap entries, a power of two)
-  int32_t *row_first, *strip_base, *gh_start, *gh_end, *stack;
+  // first mesh built on the device: rows, row of each support, strips, hull ghosts per
+  // vertex, chain stacks, edge hash table (hcap entries, a power of two)
+  int32_t *row_first, *row_of, *strip_base, *gh_start, *gh_end, *stack;
   uint64_t* hkeys;
   int32_t* hvals;
   int32_t cap, pcap, S_cap, hcap;
@@ -40,9 +40,10 @@ struct MeshWork {  // per-frame arrays: records [cap], new points [pcap], coordi
 //   [4] number of new supports read from n_new
 //   [5] supports in the mesh so far (p0 + new supports)
 //   [6] tessellations done
+//   [7] a live solid record (where a point location starts when its cell has no hint)
 //   [8 + 2k], [9 + 2k] supports and triangles after tessellation k (k < 8)
 enum { kMeshRecords = 0, kMeshTris = 1, kMeshErr = 2, kMeshRounds = 3, kMeshNew = 4, kMeshSupports = 5,
-       kMeshTess = 6, kMeshLog = 8, kMeshStatusWords = 32 };
+       kMeshTess = 6, kMeshAny = 7, kMeshLog = 8, kMeshStatusWords = 32 };
 // error code of a first mesh that cannot exist (fewer than two rows of supports: no
 // triangle, or all supports collinear); the host path handles that frame
 constexpr int32_t kMeshErrNoMesh = 10;

@@ -251,10 +251,19 @@ __host__ __device__ inline int32_t walk(const Mesh& m, int32_t t, P2 q, int32_t 
 template <class A>
 __host__ __device__ inline void propose_point(const Mesh& m, int32_t i, int32_t round, int32_t n_rec, int32_t* err) {
   const P2 q = xy<A>(m, m.p0 + i);
-  const int32_t t = locate_live<A>(m, m.ploc[i], q, n_rec);
-  if (t < 0) return A::fail(err, kErrLocate);
-  m.ploc[i] = t;
-  const int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
+  // the last triangle's state, vertices and links in one go (the common case: still live)
+  int32_t t = m.ploc[i];
+  if (!rec_ok(t, n_rec)) return A::fail(err, kErrLocate);
+  const int32_t dt = m.dead[t];
+  int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
+  int32_t n0 = m.tnb[3 * t], n1 = m.tnb[3 * t + 1], n2 = m.tnb[3 * t + 2];
+  if (dt) {
+    t = locate_live<A>(m, t, q, n_rec);
+    if (t < 0) return A::fail(err, kErrLocate);
+    m.ploc[i] = t;
+    v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
+    n0 = m.tnb[3 * t], n1 = m.tnb[3 * t + 1], n2 = m.tnb[3 * t + 2];
+  }
   const P2 V0 = xy<A>(m, v0), V1 = xy<A>(m, v1), V2 = xy<A>(m, v2);
   const int32_t o0 = orient(V1, V2, q), o1 = orient(V2, V0, q), o2 = orient(V0, V1, q);
   if (o0 < 0 || o1 < 0 || o2 < 0) return A::fail(err, kErrLocate);
@@ -276,7 +285,7 @@ __host__ __device__ inline void propose_point(const Mesh& m, int32_t i, int32_t 
     A::vote_min(&m.vote[t], key);
     return;
   }
-  const int32_t s = follow(m, m.tnb[3 * t + k0], sel3(nxt(k0), v0, v1, v2), sel3(prv(k0), v0, v1, v2), n_rec);
+  const int32_t s = follow(m, sel3(k0, n0, n1, n2), sel3(nxt(k0), v0, v1, v2), sel3(prv(k0), v0, v1, v2), n_rec);
   if (s < 0) return A::fail(err, kErrLink);
   m.pk[i] = k0;
   m.psib[i] = s;
@@ -290,30 +299,45 @@ __host__ __device__ inline int32_t work_entry(int32_t t, int32_t mask) { return 
 template <class A>
 __host__ __device__ inline void propose_flip(const Mesh& m, int32_t e, int32_t round, int32_t n_rec, int32_t* err) {
   const int32_t t = e >> 3, mask = e & 7;
-  m.fk[t] = -1;
-  if (m.dead[t]) return;
+  // A round is bound by the latency of dependent loads, so every load is issued as soon
+  // as its address is known: the record with its state and links, then the neighbours
+  // across all edges to test with their state and vertices; the edges are then tested in
+  // slot order, up to the first illegal one.
+  const int32_t dt = m.dead[t];
   const int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
-  if (v2 == kGhost) return;
+  const int32_t raw[3] = {m.tnb[3 * t], m.tnb[3 * t + 1], m.tnb[3 * t + 2]};
+  m.fk[t] = -1;
+  if (dt || v2 == kGhost) return;
+  const int32_t ex[3] = {v1, v2, v0}, ey[3] = {v2, v0, v1};  // edge k = (v[k+1], v[k+2])
+  bool live[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) live[k] = (mask >> k & 1) && rec_ok(raw[k], n_rec) && !m.dead[raw[k]];
+  int32_t s[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) s[k] = !(mask >> k & 1) ? -1 : live[k] ? raw[k] : follow(m, raw[k], ex[k], ey[k], n_rec);
+  int32_t w[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    w[k][0] = w[k][1] = w[k][2] = kGhost;
+    if (s[k] >= 0) w[k][0] = m.tv[3 * s[k]], w[k][1] = m.tv[3 * s[k] + 1], w[k][2] = m.tv[3 * s[k] + 2];
+  }
   const P2 V0 = xy<A>(m, v0), V1 = xy<A>(m, v1), V2 = xy<A>(m, v2);
+#pragma unroll
   for (int k = 0; k < 3; ++k) {
     if (!(mask >> k & 1)) continue;
-    const int32_t x = sel3(nxt(k), v0, v1, v2), y = sel3(prv(k), v0, v1, v2);
-    const int32_t raw = m.tnb[3 * t + k];
-    const int32_t s = follow(m, raw, x, y, n_rec);
-    if (s < 0) return A::fail(err, kErrLink);
-    const int32_t w0 = m.tv[3 * s], w1 = m.tv[3 * s + 1], w2 = m.tv[3 * s + 2];
-    const int j = edge_slot3(w0, w1, w2, y, x);
+    if (s[k] < 0) return A::fail(err, kErrLink);
+    const int j = edge_slot3(w[k][0], w[k][1], w[k][2], ey[k], ex[k]);
     if (j < 0) return A::fail(err, kErrLink);
-    if (s != raw) m.tnb[3 * t + k] = s;
-    m.tnb[3 * s + j] = t;
-    if (w2 != kGhost && incircle_sos(V0, V1, V2, xy<A>(m, sel3(j, w0, w1, w2))) > 0) {
+    if (s[k] != raw[k]) m.tnb[3 * t + k] = s[k];
+    m.tnb[3 * s[k] + j] = t;
+    if (w[k][2] != kGhost && incircle_sos(V0, V1, V2, xy<A>(m, sel3(j, w[k][0], w[k][1], w[k][2]))) > 0) {
       const uint64_t key = make_key(round, 1, 0, (uint32_t)(3 * t + k));
       m.fk[t] = k;
-      m.fs[t] = s;
+      m.fs[t] = s[k];
       m.fj[t] = j;
       m.fkey[t] = key;
       A::vote_min(&m.vote[t], key);
-      A::vote_min(&m.vote[s], key);
+      A::vote_min(&m.vote[s[k]], key);
       return;
     }
   }
@@ -371,21 +395,30 @@ template <class A>
 __host__ __device__ inline void execute_point(const Mesh& m, int32_t i, int32_t* n_rec, int32_t* pend, int32_t* n_pend,
                                               int32_t pend_cap, int32_t* work, int32_t* n_work, int32_t work_cap,
                                               int32_t* err) {
+  // loads issued as soon as their addresses are known: the point's state, then the votes
+  // and the records of its triangles
   const int32_t k = m.pk[i];
-  if (k == kDup || k == kDone) return;
-  const int32_t t = m.ploc[i];
+  const int32_t t = m.ploc[i], s = m.psib[i];
   const uint64_t key = m.pkey[i];
-  const bool won = A::vote_get(&m.vote[t]) == key && (k == kInside || A::vote_get(&m.vote[m.psib[i]]) == key);
-  if (!won) {
+  if (k == kDup || k == kDone) return;
+  const bool edge = k != kInside;
+  const uint64_t vt = A::vote_get(&m.vote[t]);
+  const uint64_t vs = edge ? A::vote_get(&m.vote[s]) : key;
+  const int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
+  const int32_t n0 = m.tnb[3 * t], n1 = m.tnb[3 * t + 1], n2 = m.tnb[3 * t + 2];
+  int32_t w0 = 0, w1 = 0, w2 = 0, z0 = 0, z1 = 0, z2 = 0;
+  if (edge) {
+    w0 = m.tv[3 * s], w1 = m.tv[3 * s + 1], w2 = m.tv[3 * s + 2];
+    z0 = m.tnb[3 * s], z1 = m.tnb[3 * s + 1], z2 = m.tnb[3 * s + 2];
+  }
+  if (vt != key || vs != key) {
     const int32_t at = A::push(n_pend, 1);
     if (at >= pend_cap) return A::fail(err, kErrList);
     pend[at] = i;
     return;
   }
   const int32_t p = m.p0 + i;
-  const int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
-  const int32_t n0 = m.tnb[3 * t], n1 = m.tnb[3 * t + 1], n2 = m.tnb[3 * t + 2];
-  if (k == kInside) {
+  if (!edge) {
     // c_i = (v_i, v_i+1, p): its edge opposite p is the old edge opposite v_i-1, the only
     // one to test (slot 2)
     const int32_t b = alloc<A>(m, 3, 0444u, n_rec, work, n_work, work_cap, err);
@@ -399,9 +432,6 @@ __host__ __device__ inline void execute_point(const Mesh& m, int32_t i, int32_t*
     // slot j opposite d
     const int32_t a = sel3(k, v0, v1, v2), bb = sel3(nxt(k), v0, v1, v2), c = sel3(prv(k), v0, v1, v2);
     const int32_t t_ca = sel3(nxt(k), n0, n1, n2), t_ab = sel3(prv(k), n0, n1, n2);
-    const int32_t s = m.psib[i];
-    const int32_t w0 = m.tv[3 * s], w1 = m.tv[3 * s + 1], w2 = m.tv[3 * s + 2];
-    const int32_t z0 = m.tnb[3 * s], z1 = m.tnb[3 * s + 1], z2 = m.tnb[3 * s + 2];
     const int j = edge_slot3(w0, w1, w2, c, bb);
     if (j < 0) return A::fail(err, kErrLink);
     const int32_t d = sel3(j, w0, w1, w2), s_bd = sel3(nxt(j), z0, z1, z2), s_dc = sel3(prv(j), z0, z1, z2);
@@ -433,22 +463,26 @@ __host__ __device__ inline void execute_point(const Mesh& m, int32_t i, int32_t*
 template <class A>
 __host__ __device__ inline void execute_flip(const Mesh& m, int32_t e, int32_t* n_rec, int32_t* work_next,
                                              int32_t* n_next, int32_t work_cap, int32_t* err) {
+  // loads issued as soon as their addresses are known: the bid with the record, then the
+  // votes and the record across the edge
   const int32_t t = e >> 3;
   const int k = m.fk[t];
-  if (k < 0) return;
   const int32_t s = m.fs[t];
   const int j = m.fj[t];
   const uint64_t key = m.fkey[t];
-  if (A::vote_get(&m.vote[t]) != key || A::vote_get(&m.vote[s]) != key) {
+  const uint64_t vt = A::vote_get(&m.vote[t]);
+  const int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
+  const int32_t n0 = m.tnb[3 * t], n1 = m.tnb[3 * t + 1], n2 = m.tnb[3 * t + 2];
+  if (k < 0) return;
+  const uint64_t vs = A::vote_get(&m.vote[s]);
+  const int32_t w0 = m.tv[3 * s], w1 = m.tv[3 * s + 1], w2 = m.tv[3 * s + 2];
+  const int32_t z0 = m.tnb[3 * s], z1 = m.tnb[3 * s + 1], z2 = m.tnb[3 * s + 2];
+  if (vt != key || vs != key) {
     const int32_t at = A::push(n_next, 1);
     if (at >= work_cap) return A::fail(err, kErrList);
     work_next[at] = e;
     return;
   }
-  const int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
-  const int32_t n0 = m.tnb[3 * t], n1 = m.tnb[3 * t + 1], n2 = m.tnb[3 * t + 2];
-  const int32_t w0 = m.tv[3 * s], w1 = m.tv[3 * s + 1], w2 = m.tv[3 * s + 2];
-  const int32_t z0 = m.tnb[3 * s], z1 = m.tnb[3 * s + 1], z2 = m.tnb[3 * s + 2];
   const int32_t a = sel3(k, v0, v1, v2), b = sel3(nxt(k), v0, v1, v2), c = sel3(prv(k), v0, v1, v2);
   const int32_t d = sel3(j, w0, w1, w2);
   const int32_t s_bd = sel3(nxt(j), z0, z1, z2), s_dc = sel3(prv(j), z0, z1, z2);
@@ -466,8 +500,7 @@ __host__ __device__ inline void execute_flip(const Mesh& m, int32_t e, int32_t* 
 
 // Solid record t as an output triangle: counter-clockwise, first vertex = smallest (v, u).
 template <class A>
-__host__ __device__ inline sm_tri top_first(const Mesh& m, int32_t t) {
-  int32_t a = m.tv[3 * t], b = m.tv[3 * t + 1], c = m.tv[3 * t + 2];
+__host__ __device__ inline sm_tri top_first3(const Mesh& m, int32_t a, int32_t b, int32_t c) {
   const P2 P = xy<A>(m, a), B = xy<A>(m, b), C = xy<A>(m, c);
   const bool b_lt_a = B.y < P.y || (B.y == P.y && B.x < P.x);
   const bool c_lt_a = C.y < P.y || (C.y == P.y && C.x < P.x);
@@ -480,6 +513,10 @@ __host__ __device__ inline sm_tri top_first(const Mesh& m, int32_t t) {
     c = b, b = a, a = x;
   }
   return sm_tri{a, b, c};
+}
+template <class A>
+__host__ __device__ inline sm_tri top_first(const Mesh& m, int32_t t) {
+  return top_first3<A>(m, m.tv[3 * t], m.tv[3 * t + 1], m.tv[3 * t + 2]);
 }
 
 }  // namespace mesh

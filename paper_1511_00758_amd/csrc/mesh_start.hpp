@@ -7,7 +7,9 @@
 //   ladders  between two consecutive rows (two horizontal lines) the points are joined by
 //            a ladder: walking both rows left to right, each step adds the triangle of the
 //            next point of one row and the current point of the other (always valid
-//            between parallel lines); strip r holds |row r| + |row r+1| - 2 triangles
+//            between parallel lines); strip r holds |row r| + |row r+1| - 2 triangles. The
+//            walk is a merge of the two rows by u, so each point finds its own triangle
+//            and its place in the strip by a binary search in the other row
 //   pockets  the left ends of the rows (bottom to top) and the right ends (top to bottom)
 //            are the side chains of the boundary; a stack scan fills every reflex vertex
 //            with a triangle, so the boundary becomes the convex hull (collinear points on
@@ -35,10 +37,11 @@ constexpr int32_t kErrOrder = 9;  // supports not strictly increasing in (v, u)
 struct Start {
   int32_t n;           // supports S[0, n)
   int32_t* row_first;  // [n] first support of row r
+  int32_t* row_of;     // [n] row of support i
   int32_t* strip_base; // [n] first record of strip r
   int32_t* gh_start;   // [n] ghost of the hull edge starting at vertex x, -1
   int32_t* gh_end;     // [n] ghost of the hull edge ending at vertex x, -1
-  int32_t* stack;      // [2][n] chain scans (left, right)
+  int32_t* stack;      // [2][rows] chain scans (left, right)
   uint64_t* keys;      // [hcap] directed edges (x + 1) << 32 | (y + 1)
   int32_t* vals;       // [hcap] 3 * record + slot
   int32_t hcap;        // power of two
@@ -61,23 +64,44 @@ __host__ __device__ inline int32_t ladder_size(const Start& st, int32_t r, int32
   return (a1 - a0 - 1) + (b1 - a1 - 1);
 }
 
-// ladders: the triangles of strip r (rows r and r + 1) from record strip_base[r] on,
-// counter-clockwise; their links are filled in later.
+// Number of supports q in [lo, hi) of one row with u(q) < X (u(q) <= X when inclusive);
+// u increases along a row.
 template <class A>
-__host__ __device__ inline void ladder(const Mesh& m, const Start& st, int32_t r, int32_t n_rows) {
-  int32_t i = st.row_first[r], j = st.row_first[r + 1];
-  const int32_t i_end = j - 1, j_end = (r + 2 < n_rows ? st.row_first[r + 2] : st.n) - 1;
-  int32_t t = st.strip_base[r];
-  while (i < i_end || j < j_end) {
-    const bool step_a = i < i_end && (j == j_end || xy<A>(m, i + 1).x <= xy<A>(m, j + 1).x);
-    if (step_a) {  // (A_i, A_i+1, B_j)
-      m.tv[3 * t] = i, m.tv[3 * t + 1] = i + 1, m.tv[3 * t + 2] = j;
-      ++i;
-    } else {       // (A_i, B_j+1, B_j)
-      m.tv[3 * t] = i, m.tv[3 * t + 1] = j + 1, m.tv[3 * t + 2] = j;
-      ++j;
-    }
-    ++t;
+__host__ __device__ inline int32_t rank_in_row(const Mesh& m, int32_t lo, int32_t hi, int32_t X, bool inclusive) {
+  int32_t a = lo, b = hi;
+  while (a < b) {
+    const int32_t mid = (a + b) >> 1;
+    const int32_t xm = xy<A>(m, mid).x;
+    if (xm < X || (inclusive && xm == X)) a = mid + 1;
+    else b = mid;
+  }
+  return a - lo;
+}
+
+// ladders: support i of row r, unless it starts the row, is the next point of a walk step
+// in both strips it borders. In strip r (rows r, r + 1) it adds (i - 1, i, B) with B the
+// last point of row r + 1 left of it; in strip r - 1 (rows r - 1, r) it adds (A, i, i - 1)
+// with A the last point of row r - 1 at or left of it (on a tie the lower row steps
+// first). Its triangle's place in the strip is the number of steps before it: the points
+// of both rows that come earlier in the merge by u.
+template <class A>
+__host__ __device__ inline void ladder_point(const Mesh& m, const Start& st, int32_t i, int32_t n_rows) {
+  const int32_t r = st.row_of[i];
+  const int32_t a0 = st.row_first[r];
+  if (i == a0) return;
+  const int32_t a1 = r + 1 < n_rows ? st.row_first[r + 1] : st.n;
+  const int32_t X = xy<A>(m, i).x;
+  if (r + 1 < n_rows) {  // the lower row of strip r; its upper row is [a1, b1)
+    const int32_t b1 = r + 2 < n_rows ? st.row_first[r + 2] : st.n;
+    const int32_t rank = rank_in_row<A>(m, a1 + 1, b1, X, false);
+    const int32_t t = st.strip_base[r] + (i - a0 - 1) + rank;
+    m.tv[3 * t] = i - 1, m.tv[3 * t + 1] = i, m.tv[3 * t + 2] = a1 + rank;
+  }
+  if (r >= 1) {  // the upper row of strip r - 1; its lower row is [c0, a0)
+    const int32_t c0 = st.row_first[r - 1];
+    const int32_t rank = rank_in_row<A>(m, c0 + 1, a0, X, true);
+    const int32_t t = st.strip_base[r - 1] + rank + (i - a0 - 1);
+    m.tv[3 * t] = c0 + rank, m.tv[3 * t + 1] = i, m.tv[3 * t + 2] = i - 1;
   }
 }
 
@@ -87,7 +111,7 @@ __host__ __device__ inline void ladder(const Mesh& m, const Start& st, int32_t r
 template <class A>
 __host__ __device__ inline bool pockets(const Mesh& m, const Start& st, int side, int32_t n_rows, int32_t* n_rec,
                                         int32_t* err) {
-  int32_t* stk = st.stack + (side ? st.n : 0);
+  int32_t* stk = st.stack + (side ? n_rows : 0);
   int32_t top = 0;
   for (int32_t q = 0; q < n_rows; ++q) {
     const int32_t r = side ? q : n_rows - 1 - q;
@@ -117,40 +141,59 @@ __host__ __device__ inline uint32_t edge_hash(uint64_t k) {
   return (uint32_t)k;
 }
 
-// links, first pass: the directed edge in slot k of solid record t into the table.
+// links, first pass: the directed edge in slot k of solid record t into the table. The
+// compare-and-swap at the first slot h of its probe sequence may be issued by the caller
+// (old = the key it found), which lets a thread have several edges in flight.
 template <class A>
-__host__ __device__ inline void edge_insert(const Mesh& m, const Start& st, int32_t t, int k, int32_t* err) {
-  const uint64_t key = edge_key(m.tv[3 * t + nxt(k)], m.tv[3 * t + prv(k)]);
-  uint32_t h = edge_hash(key) & (uint32_t)(st.hcap - 1);
-  for (int32_t probe = 0; probe < st.hcap; ++probe) {
-    const uint64_t old = A::cas64(&st.keys[h], kEmptyEdge, key);
+__host__ __device__ inline void edge_insert_from(const Start& st, uint64_t key, int32_t val, uint32_t h, uint64_t old,
+                                                 int32_t* err) {
+  for (int32_t probe = 1;; ++probe) {
     if (old == kEmptyEdge) {
-      st.vals[h] = 3 * t + k;
+      st.vals[h] = val;
       return;
     }
     if (old == key) return A::fail(err, kErrLink);  // an edge twice: not a triangulation
+    if (probe == st.hcap) return A::fail(err, kErrCapacity);
     h = (h + 1) & (uint32_t)(st.hcap - 1);
+    old = A::cas64(&st.keys[h], kEmptyEdge, key);
   }
-  A::fail(err, kErrCapacity);
 }
 
-// links, second pass: the neighbour across slot k of solid record t, or a new ghost when
-// the reverse edge is absent (a hull edge x -> y gets the ghost (y, x, ghost)).
-template <class A>
-__host__ __device__ inline void edge_link(const Mesh& m, const Start& st, int32_t t, int k, int32_t* n_rec,
-                                          int32_t* err) {
+__host__ __device__ inline uint64_t solid_edge_key(const Mesh& m, int32_t t, int k, bool reverse) {
   const int32_t x = m.tv[3 * t + nxt(k)], y = m.tv[3 * t + prv(k)];
-  const uint64_t key = edge_key(y, x);
-  uint32_t h = edge_hash(key) & (uint32_t)(st.hcap - 1);
-  for (int32_t probe = 0; probe < st.hcap; ++probe) {
-    const uint64_t cur = A::vote_get(&st.keys[h]);  // written by atomics
-    if (cur == key) {
-      m.tnb[3 * t + k] = st.vals[h] / 3;
-      return;
-    }
-    if (cur == kEmptyEdge) break;
+  return reverse ? edge_key(y, x) : edge_key(x, y);
+}
+
+template <class A>
+__host__ __device__ inline void edge_insert(const Mesh& m, const Start& st, int32_t t, int k, int32_t* err) {
+  const uint64_t key = solid_edge_key(m, t, k, false);
+  const uint32_t h = edge_hash(key) & (uint32_t)(st.hcap - 1);
+  edge_insert_from<A>(st, key, 3 * t + k, h, A::cas64(&st.keys[h], kEmptyEdge, key), err);
+}
+
+// links, second pass: the slot holding key, probing from slot h whose key cur the caller
+// may have read, or -1 when the key is absent.
+template <class A>
+__host__ __device__ inline int32_t edge_find_from(const Start& st, uint64_t key, uint32_t h, uint64_t cur) {
+  for (int32_t probe = 1;; ++probe) {
+    if (cur == key) return (int32_t)h;
+    if (cur == kEmptyEdge || probe == st.hcap) return -1;
     h = (h + 1) & (uint32_t)(st.hcap - 1);
+    cur = A::vote_get(&st.keys[h]);  // written by atomics
   }
+}
+
+// The neighbour across slot k of solid record t: the record of the reverse edge (val, from
+// its slot in the table), or a new ghost when the reverse edge is absent (slot < 0; a hull
+// edge x -> y gets the ghost (y, x, ghost)).
+template <class A>
+__host__ __device__ inline void edge_link_to(const Mesh& m, const Start& st, int32_t t, int k, int32_t slot,
+                                             int32_t val, int32_t* n_rec, int32_t* err) {
+  if (slot >= 0) {
+    m.tnb[3 * t + k] = val / 3;
+    return;
+  }
+  const int32_t x = m.tv[3 * t + nxt(k)], y = m.tv[3 * t + prv(k)];
   const int32_t g = A::push(n_rec, 1);
   if (g >= m.cap) return A::fail(err, kErrCapacity);
   m.tv[3 * g] = y, m.tv[3 * g + 1] = x, m.tv[3 * g + 2] = kGhost;
@@ -159,6 +202,15 @@ __host__ __device__ inline void edge_link(const Mesh& m, const Start& st, int32_
   if (st.gh_start[x] >= 0 || st.gh_end[y] >= 0) return A::fail(err, kErrLink);  // not a simple hull
   st.gh_start[x] = g;
   st.gh_end[y] = g;
+}
+
+template <class A>
+__host__ __device__ inline void edge_link(const Mesh& m, const Start& st, int32_t t, int k, int32_t* n_rec,
+                                          int32_t* err) {
+  const uint64_t key = solid_edge_key(m, t, k, true);
+  const uint32_t h = edge_hash(key) & (uint32_t)(st.hcap - 1);
+  const int32_t slot = edge_find_from<A>(st, key, h, A::vote_get(&st.keys[h]));
+  edge_link_to<A>(m, st, t, k, slot, slot >= 0 ? st.vals[slot] : 0, n_rec, err);
 }
 
 // links, third pass: ghost g = (y, x, ghost) of hull edge x -> y links, across (x, ghost),

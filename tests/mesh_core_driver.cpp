@@ -128,16 +128,19 @@ int main() {
     if (b == 0 && mode == 1) {
       // device start: rows, ladders, pockets, links, then flips of every solid triangle
       const int32_t n = n_new;
-      std::vector<int32_t> row_first(n + 1), strip_base(n + 1), gh_start(n, -1), gh_end(n, -1), stk(2 * n + 2);
+      std::vector<int32_t> row_first(n + 1), row_of(n), strip_base(n + 1), gh_start(n, -1), gh_end(n, -1),
+          stk(2 * n + 2);
       int32_t hcap = 1;
       while (hcap < 16 * n + 64) hcap <<= 1;
       std::vector<uint64_t> keys(hcap, kEmptyEdge);
       std::vector<int32_t> vals(hcap, 0);
-      Start st{n, row_first.data(), strip_base.data(), gh_start.data(), gh_end.data(), stk.data(), keys.data(),
-               vals.data(), hcap};
+      Start st{n,           row_first.data(), row_of.data(), strip_base.data(), gh_start.data(),
+               gh_end.data(), stk.data(),       keys.data(),   vals.data(),       hcap};
       int32_t err = 0, n_rows = 0;
-      for (int32_t i = 0; i < n; ++i)
+      for (int32_t i = 0; i < n; ++i) {
         if (row_starts<Seq>(m, i, &err)) row_first[n_rows++] = i;
+        row_of[i] = n_rows - 1;
+      }
       if (!err && n_rows >= 2) {
         int32_t base = 0;
         for (int32_t r = 0; r + 1 < n_rows; ++r) {
@@ -145,9 +148,9 @@ int main() {
           base += ladder_size(st, r, n_rows);
         }
         std::vector<int32_t> order;
-        for (int32_t r = 0; r + 1 < n_rows; ++r) order.push_back(r);
+        for (int32_t i = 0; i < n; ++i) order.push_back(i);
         std::shuffle(order.begin(), order.end(), rng);
-        for (int32_t r : order) ladder<Seq>(m, st, r, n_rows);
+        for (int32_t i : order) ladder_point<Seq>(m, st, i, n_rows);
         n_rec = base;
         pockets<Seq>(m, st, 1, n_rows, &n_rec, &err);
         pockets<Seq>(m, st, 0, n_rows, &n_rec, &err);
