@@ -25,7 +25,7 @@ constexpr int kHintShift = 4;        // 16 x 16 px hint cells
 constexpr int kHintBoxCells = 64;    // a record marks every cell of its box up to this many
 constexpr int32_t kUvLds = 32768;    // supports whose coordinates fit in LDS (128 KiB)
 constexpr int kEdgeBatch = 4;        // edges a thread has in flight while linking the first mesh
-constexpr int kOutBatch = 2;         // records a thread has in flight in the output
+constexpr int kOutBatch = 8;         // records a thread has in flight in the output
 
 // Packed coordinates of the frame's supports when they fit (one workgroup per CU).
 __shared__ int32_t g_uv[kUvLds];
@@ -201,7 +201,6 @@ __device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, 
   if (fresh)
     for (int32_t c = tid; c < gw * gh; c += kMeshThreads) w.hint[c] = -1;
   if (start) {
-    for (int32_t h = tid; h < hcap; h += kMeshThreads) w.hkeys[h] = kEmptyEdge;
     for (int32_t i = tid; i < n_new; i += kMeshThreads) w.gh_start[i] = w.gh_end[i] = -1;
   }
   __syncthreads();
@@ -272,52 +271,88 @@ __device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, 
       if (tid == 0) finish(0, 0, s_err != 0 ? s_err : kMeshErrNoMesh, 0);
       return;
     }
-    // links: every thread keeps kEdgeBatch first probes in flight (compare-and-swap when
-    // inserting, a load when looking up the reverse edge), then settles them in order
     const int32_t n_edges = 3 * n_solid;
-    for (int32_t e0 = tid; e0 < n_edges; e0 += kEdgeBatch * kMeshThreads) {
-      uint64_t key[kEdgeBatch], old[kEdgeBatch];
-      uint32_t h[kEdgeBatch];
+    // links by pairing in a table in LDS after the coordinates when it fits, else through
+    // the edge hash table in global memory
+    const int32_t n_even = (n_new + 1) & ~1;  // 8-byte alignment of the table
+    const int32_t tcap = pair_table_size(n_solid, n_new);
+    const bool pairs = kLds && n_new < kPairMaxVertices && n_even + 2 * (int64_t)tcap <= kUvLds;
+    if (pairs) {
+      uint64_t* tab = (uint64_t*)(g_uv + n_even);
+      for (int32_t h = tid; h < tcap; h += kMeshThreads) tab[h] = 0;
+      __syncthreads();
+      // each thread holds kEdgeBatch edges' vertices in flight (the loads take no
+      // conditions: a missing edge reads edge 0)
+      for (int32_t e0 = tid; e0 < n_edges; e0 += kEdgeBatch * kMeshThreads) {
+        int32_t ex[kEdgeBatch], ey[kEdgeBatch];
 #pragma unroll
-      for (int b = 0; b < kEdgeBatch; ++b) {
-        const int32_t e = e0 + b * kMeshThreads;
-        if (e >= n_edges) continue;
-        key[b] = solid_edge_key(m, e / 3, e % 3, false);
-        h[b] = edge_hash(key[b]) & (uint32_t)(hcap - 1);
-        old[b] = DA::cas64(&st.keys[h[b]], kEmptyEdge, key[b]);
-      }
+        for (int b = 0; b < kEdgeBatch; ++b) {
+          const int32_t e = e0 + b * kMeshThreads, ec = e < n_edges ? e : 0;
+          ex[b] = w.tv[3 * (ec / 3) + nxt(ec % 3)];
+          ey[b] = w.tv[3 * (ec / 3) + prv(ec % 3)];
+        }
 #pragma unroll
-      for (int b = 0; b < kEdgeBatch; ++b) {
-        const int32_t e = e0 + b * kMeshThreads;
-        if (e < n_edges) edge_insert_from<DA>(st, key[b], e, h[b], old[b], &s_err);
+        for (int b = 0; b < kEdgeBatch; ++b) {
+          const int32_t e = e0 + b * kMeshThreads;
+          if (e < n_edges) pair_edge<DA>(m, tab, tcap, e / 3, e % 3, ex[b], ey[b], &s_err);
+        }
       }
+      __syncthreads();
+      for (int32_t h = tid; h < tcap; h += kMeshThreads) pair_hull<DA>(m, st, tab[h], &s_nrec, &s_err);
+      __syncthreads();
+    } else {
+      for (int32_t h = tid; h < hcap; h += kMeshThreads) w.hkeys[h] = kEmptyEdge;
+      __syncthreads();
+      // every thread keeps kEdgeBatch first probes in flight (compare-and-swap when
+      // inserting, a load when looking up the reverse edge), then settles them in order
+      // (the loads take no conditions, a missing edge reads edge 0, so that they leave back
+      // to back; only the atomics and the settling look at the range)
+      for (int32_t e0 = tid; e0 < n_edges; e0 += kEdgeBatch * kMeshThreads) {
+        uint64_t key[kEdgeBatch], old[kEdgeBatch];
+        uint32_t h[kEdgeBatch];
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; ++b) {
+          const int32_t e = e0 + b * kMeshThreads, ec = e < n_edges ? e : 0;
+          key[b] = solid_edge_key(m, ec / 3, ec % 3, false);
+        }
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; ++b) h[b] = edge_hash(key[b]) & (uint32_t)(hcap - 1);
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; ++b)
+          old[b] = e0 + b * kMeshThreads < n_edges ? DA::cas64(&st.keys[h[b]], kEmptyEdge, key[b]) : 0;
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; ++b) {
+          const int32_t e = e0 + b * kMeshThreads;
+          if (e < n_edges) edge_insert_from<DA>(st, key[b], e, h[b], old[b], &s_err);
+        }
+      }
+      __syncthreads();
+      for (int32_t e0 = tid; e0 < n_edges; e0 += kEdgeBatch * kMeshThreads) {
+        uint64_t key[kEdgeBatch], cur[kEdgeBatch];
+        uint32_t h[kEdgeBatch];
+        int32_t slot[kEdgeBatch], val[kEdgeBatch];
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; ++b) {
+          const int32_t e = e0 + b * kMeshThreads, ec = e < n_edges ? e : 0;
+          key[b] = solid_edge_key(m, ec / 3, ec % 3, true);
+        }
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; ++b) {
+          h[b] = edge_hash(key[b]) & (uint32_t)(hcap - 1);
+          cur[b] = DA::vote_get(&st.keys[h[b]]);
+        }
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; ++b) slot[b] = edge_find_from<DA>(st, key[b], h[b], cur[b]);
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; ++b) val[b] = st.vals[slot[b] >= 0 ? slot[b] : 0];
+#pragma unroll
+        for (int b = 0; b < kEdgeBatch; ++b) {
+          const int32_t e = e0 + b * kMeshThreads;
+          if (e < n_edges) edge_link_to<DA>(m, st, e / 3, e % 3, slot[b], val[b], &s_nrec, &s_err);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int32_t e0 = tid; e0 < n_edges; e0 += kEdgeBatch * kMeshThreads) {
-      uint64_t key[kEdgeBatch], cur[kEdgeBatch];
-      uint32_t h[kEdgeBatch];
-      int32_t slot[kEdgeBatch], val[kEdgeBatch];
-#pragma unroll
-      for (int b = 0; b < kEdgeBatch; ++b) {
-        const int32_t e = e0 + b * kMeshThreads;
-        if (e >= n_edges) continue;
-        key[b] = solid_edge_key(m, e / 3, e % 3, true);
-        h[b] = edge_hash(key[b]) & (uint32_t)(hcap - 1);
-        cur[b] = DA::vote_get(&st.keys[h[b]]);
-      }
-#pragma unroll
-      for (int b = 0; b < kEdgeBatch; ++b) {
-        const int32_t e = e0 + b * kMeshThreads;
-        slot[b] = e < n_edges ? edge_find_from<DA>(st, key[b], h[b], cur[b]) : -1;
-        val[b] = slot[b] >= 0 ? st.vals[slot[b]] : 0;
-      }
-#pragma unroll
-      for (int b = 0; b < kEdgeBatch; ++b) {
-        const int32_t e = e0 + b * kMeshThreads;
-        if (e < n_edges) edge_link_to<DA>(m, st, e / 3, e % 3, slot[b], val[b], &s_nrec, &s_err);
-      }
-    }
-    __syncthreads();
     const int32_t n_all = min(s_nrec, w.cap);
     for (int32_t g = n_solid + tid; g < n_all; g += kMeshThreads) ghost_link<DA>(m, st, g, &s_err);
     for (int32_t t = tid; t < n_all; t += kMeshThreads) {
@@ -360,8 +395,29 @@ __device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, 
 
   // rounds of propose / execute; the control values are read between two barriers, so
   // that every thread takes the same decision before any thread can change them
+  auto propose_all = [&](int32_t first, int32_t stride, int32_t np, int32_t nw, int32_t n_rec, int32_t gr, int c) {
+    const int32_t* pend = c ? w.pend1 : w.pend0;
+    const int32_t* work = c ? w.work1 : w.work0;
+    for (int32_t it = first; it < np + nw; it += stride) {
+      if (it < np) propose_point<DA>(m, pend[it], gr, n_rec, &s_err);
+      else propose_flip<DA>(m, work[it - np], gr, n_rec, &s_err);
+    }
+  };
+  auto execute_all = [&](int32_t first, int32_t stride, int32_t np, int32_t nw, int c) {
+    const int32_t* pend = c ? w.pend1 : w.pend0;
+    const int32_t* work = c ? w.work1 : w.work0;
+    int32_t* pend_next = c ? w.pend0 : w.pend1;
+    int32_t* work_next = c ? w.work0 : w.work1;
+    for (int32_t it = first; it < np + nw; it += stride) {
+      if (it < np)
+        execute_point<DA>(m, pend[it], &s_nrec, pend_next, &s_np[c ^ 1], w.pcap, work_next, &s_nw[c ^ 1], w.cap,
+                          &s_err);
+      else
+        execute_flip<DA>(m, work[it - np], &s_nrec, work_next, &s_nw[c ^ 1], w.cap, &s_err);
+    }
+  };
   int cur = 0, round = 0;
-  for (;; ++round) {
+  for (;;) {
     __syncthreads();
     const int32_t np = s_np[cur], nw = s_nw[cur], n_rec = s_nrec, err = s_err;
     __syncthreads();
@@ -371,26 +427,12 @@ __device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, 
       if (tid == 0) s_err = kErrRounds;
       break;
     }
-    int32_t* pend = cur ? w.pend1 : w.pend0;
-    int32_t* work = cur ? w.work1 : w.work0;
-    int32_t* pend_next = cur ? w.pend0 : w.pend1;
-    int32_t* work_next = cur ? w.work0 : w.work1;
-    for (int32_t it = tid; it < np + nw; it += kMeshThreads) {
-      if (it < np) propose_point<DA>(m, pend[it], gr, n_rec, &s_err);
-      else propose_flip<DA>(m, work[it - np], gr, n_rec, &s_err);
-    }
+    propose_all(tid, kMeshThreads, np, nw, n_rec, gr, cur);
     if (tid == 0) s_np[cur ^ 1] = s_nw[cur ^ 1] = 0;  // last read before the previous round's work
     __syncthreads();
-    if (s_err == 0) {  // items only: no barrier depends on this test
-      for (int32_t it = tid; it < np + nw; it += kMeshThreads) {
-        if (it < np)
-          execute_point<DA>(m, pend[it], &s_nrec, pend_next, &s_np[cur ^ 1], w.pcap, work_next,
-                              &s_nw[cur ^ 1], w.cap, &s_err);
-        else
-          execute_flip<DA>(m, work[it - np], &s_nrec, work_next, &s_nw[cur ^ 1], w.cap, &s_err);
-      }
-    }
+    if (s_err == 0) execute_all(tid, kMeshThreads, np, nw, cur);  // items only: no barrier depends on this test
     cur ^= 1;
+    ++round;
   }
   __syncthreads();
   if (s_err != 0) {

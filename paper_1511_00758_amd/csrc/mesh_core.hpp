@@ -309,17 +309,22 @@ __host__ __device__ inline void propose_flip(const Mesh& m, int32_t e, int32_t r
   m.fk[t] = -1;
   if (dt || v2 == kGhost) return;
   const int32_t ex[3] = {v1, v2, v0}, ey[3] = {v2, v0, v1};  // edge k = (v[k+1], v[k+2])
-  bool live[3];
+  // loads without conditions (an index outside the records reads record 0, whose value is
+  // then not used), so that they leave back to back
+  int32_t dd[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) live[k] = (mask >> k & 1) && rec_ok(raw[k], n_rec) && !m.dead[raw[k]];
+  for (int k = 0; k < 3; ++k) dd[k] = m.dead[rec_ok(raw[k], n_rec) ? raw[k] : 0];
   int32_t s[3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) s[k] = !(mask >> k & 1) ? -1 : live[k] ? raw[k] : follow(m, raw[k], ex[k], ey[k], n_rec);
+  for (int k = 0; k < 3; ++k) {
+    const bool live = rec_ok(raw[k], n_rec) && !dd[k];
+    s[k] = !(mask >> k & 1) ? -1 : live ? raw[k] : follow(m, raw[k], ex[k], ey[k], n_rec);
+  }
   int32_t w[3][3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    w[k][0] = w[k][1] = w[k][2] = kGhost;
-    if (s[k] >= 0) w[k][0] = m.tv[3 * s[k]], w[k][1] = m.tv[3 * s[k] + 1], w[k][2] = m.tv[3 * s[k] + 2];
+    const int32_t q = s[k] >= 0 ? s[k] : 0;
+    w[k][0] = m.tv[3 * q], w[k][1] = m.tv[3 * q + 1], w[k][2] = m.tv[3 * q + 2];
   }
   const P2 V0 = xy<A>(m, v0), V1 = xy<A>(m, v1), V2 = xy<A>(m, v2);
 #pragma unroll
@@ -402,15 +407,13 @@ __host__ __device__ inline void execute_point(const Mesh& m, int32_t i, int32_t*
   const uint64_t key = m.pkey[i];
   if (k == kDup || k == kDone) return;
   const bool edge = k != kInside;
+  const int32_t sc = edge ? s : t;  // loads without conditions: an interior point reads t twice
   const uint64_t vt = A::vote_get(&m.vote[t]);
-  const uint64_t vs = edge ? A::vote_get(&m.vote[s]) : key;
+  const uint64_t vs = A::vote_get(&m.vote[sc]);
   const int32_t v0 = m.tv[3 * t], v1 = m.tv[3 * t + 1], v2 = m.tv[3 * t + 2];
   const int32_t n0 = m.tnb[3 * t], n1 = m.tnb[3 * t + 1], n2 = m.tnb[3 * t + 2];
-  int32_t w0 = 0, w1 = 0, w2 = 0, z0 = 0, z1 = 0, z2 = 0;
-  if (edge) {
-    w0 = m.tv[3 * s], w1 = m.tv[3 * s + 1], w2 = m.tv[3 * s + 2];
-    z0 = m.tnb[3 * s], z1 = m.tnb[3 * s + 1], z2 = m.tnb[3 * s + 2];
-  }
+  const int32_t w0 = m.tv[3 * sc], w1 = m.tv[3 * sc + 1], w2 = m.tv[3 * sc + 2];
+  const int32_t z0 = m.tnb[3 * sc], z1 = m.tnb[3 * sc + 1], z2 = m.tnb[3 * sc + 2];
   if (vt != key || vs != key) {
     const int32_t at = A::push(n_pend, 1);
     if (at >= pend_cap) return A::fail(err, kErrList);

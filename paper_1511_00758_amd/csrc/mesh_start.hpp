@@ -112,20 +112,34 @@ template <class A>
 __host__ __device__ inline bool pockets(const Mesh& m, const Start& st, int side, int32_t n_rows, int32_t* n_rec,
                                         int32_t* err) {
   int32_t* stk = st.stack + (side ? n_rows : 0);
-  int32_t top = 0;
-  for (int32_t q = 0; q < n_rows; ++q) {
+  auto chain = [&](int32_t q) {  // q-th point of the side chain
     const int32_t r = side ? q : n_rows - 1 - q;
-    const int32_t p = side ? (r + 1 < n_rows ? st.row_first[r + 1] : st.n) - 1 : st.row_first[r];
-    while (top >= 2 && orient(xy<A>(m, stk[top - 2]), xy<A>(m, stk[top - 1]), xy<A>(m, p)) < 0) {
+    return side ? (r + 1 < n_rows ? st.row_first[r + 1] : st.n) - 1 : st.row_first[r];
+  };
+  // the two top entries of the stack stay in registers with their coordinates; the next
+  // chain point and its coordinates are read one step ahead
+  int32_t top = 0, s1 = -1, s2 = -1;
+  P2 c1{0, 0}, c2{0, 0};
+  int32_t p = chain(0);
+  P2 cp = xy<A>(m, p);
+  for (int32_t q = 0; q < n_rows; ++q) {
+    const int32_t p_next = q + 1 < n_rows ? chain(q + 1) : p;
+    const P2 c_next = xy<A>(m, p_next);
+    while (top >= 2 && orient(c2, c1, cp) < 0) {
       const int32_t t = A::push(n_rec, 1);
       if (t >= m.cap) {
         A::fail(err, kErrCapacity);
         return false;
       }
-      m.tv[3 * t] = stk[top - 2], m.tv[3 * t + 1] = p, m.tv[3 * t + 2] = stk[top - 1];
+      m.tv[3 * t] = s2, m.tv[3 * t + 1] = p, m.tv[3 * t + 2] = s1;
       --top;
+      s1 = s2, c1 = c2;
+      if (top >= 2) s2 = stk[top - 2], c2 = xy<A>(m, s2);
     }
     stk[top++] = p;
+    s2 = s1, c2 = c1;
+    s1 = p, c1 = cp;
+    p = p_next, cp = c_next;
   }
   return true;
 }
@@ -211,6 +225,61 @@ __host__ __device__ inline void edge_link(const Mesh& m, const Start& st, int32_
   const uint32_t h = edge_hash(key) & (uint32_t)(st.hcap - 1);
   const int32_t slot = edge_find_from<A>(st, key, h, A::vote_get(&st.keys[h]));
   edge_link_to<A>(m, st, t, k, slot, slot >= 0 ? st.vals[slot] : 0, n_rec, err);
+}
+
+// links by pairing (in LDS on the device, where the table fits): every undirected edge
+// {a, b} has one slot in a table of tcap entries; the first of its two directed edges
+// claims the slot, the second finds it and links both records. Slots nobody paired hold
+// the hull edges. An entry packs the key a << 15 | b (plus one, so that 0 is empty), the
+// record slot 3 * t + k of the claiming edge, its direction and a paired flag.
+constexpr int32_t kPairMaxVertices = 1 << 15;
+
+__host__ __device__ inline uint64_t pair_entry(int32_t x, int32_t y, int32_t val) {
+  const int32_t a = x < y ? x : y, b = x < y ? y : x;
+  const uint64_t key = (((uint64_t)a << 15) | (uint64_t)b) + 1;
+  return (key << 32) | ((uint64_t)(uint32_t)val << 2) | ((uint64_t)(x < y) << 1);
+}
+
+// The directed edge x -> y in slot k of solid record t (x and y read by the caller, which
+// may hold several edges' vertices in flight).
+template <class A>
+__host__ __device__ inline void pair_edge(const Mesh& m, uint64_t* tab, int32_t tcap, int32_t t, int k, int32_t x,
+                                          int32_t y, int32_t* err) {
+  const uint64_t mine = pair_entry(x, y, 3 * t + k);
+  uint32_t h = edge_hash(mine >> 32) & (uint32_t)(tcap - 1);
+  for (int32_t probe = 0; probe < tcap; ++probe) {
+    const uint64_t cur = A::cas64(&tab[h], 0, mine);
+    if (cur == 0) return;  // claimed: the reverse edge links both
+    if ((cur >> 32) == (mine >> 32)) {
+      // a third edge on {a, b}, or two in the same direction: not a triangulation
+      if ((cur & 1u) || ((cur ^ mine) & 2u) == 0) return A::fail(err, kErrLink);
+      if (A::cas64(&tab[h], cur, cur | 1u) != cur) return A::fail(err, kErrLink);
+      const int32_t other = (int32_t)((cur >> 2) & 0x3fffffffu);  // 3 * t' + k'
+      m.tnb[3 * t + k] = other / 3;
+      m.tnb[other] = t;
+      return;
+    }
+    h = (h + 1) & (uint32_t)(tcap - 1);
+  }
+  A::fail(err, kErrCapacity);
+}
+
+// A slot of the table after pairing: an unpaired edge is a hull edge and gets its ghost.
+template <class A>
+__host__ __device__ inline void pair_hull(const Mesh& m, const Start& st, uint64_t e, int32_t* n_rec, int32_t* err) {
+  if (e == 0 || (e & 1u)) return;
+  const int32_t val = (int32_t)((e >> 2) & 0x3fffffffu);
+  edge_link_to<A>(m, st, val / 3, val % 3, -1, 0, n_rec, err);
+}
+
+// Table size for n_solid triangles over n supports: fewer than (3 n_solid + n) / 2
+// undirected edges (each solid triangle has three, each interior edge two solid sides,
+// and fewer than n lie on the hull); the load stays below 3/4.
+__host__ __device__ inline int32_t pair_table_size(int32_t n_solid, int32_t n) {
+  const int64_t edges = (3 * (int64_t)n_solid + n) / 2 + 1;
+  int32_t c = 1024;
+  while ((int64_t)c * 3 < edges * 4 && c < (1 << 26)) c <<= 1;
+  return c;
 }
 
 // links, third pass: ghost g = (y, x, ghost) of hull edge x -> y links, across (x, ghost),

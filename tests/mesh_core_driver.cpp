@@ -1,7 +1,8 @@
 // Sequential driver of the device mesh steps (paper_1511_00758_amd/csrc/mesh_core.hpp,
 // mesh_start.hpp) for the CPU tests. The first batch of points is triangulated either by
 // the host Delaunay and exported (mode 0) or by the device start steps (rows, ladders,
-// pockets, edge links, then Lawson flips; mode 1, points sorted by (v, u)); every later
+// pockets, edge links, then Lawson flips; points sorted by (v, u); mode 1 links through
+// the edge hash table, mode 2 by pairing in a table of undirected edges); every later
 // batch is inserted by the same per-item propose / execute steps the GPU kernel runs, one
 // item after another in a shuffled order (the GPU runs them concurrently; any order must
 // give the same mesh). Prints the solid triangles, top vertex first, after every batch.
@@ -125,7 +126,7 @@ int main() {
   for (int b = 0; b < nb; ++b) {
     const int32_t p0 = range[b].first, n_new = range[b].second - p0;
     int status = 0;
-    if (b == 0 && mode == 1) {
+    if (b == 0 && mode >= 1) {
       // device start: rows, ladders, pockets, links, then flips of every solid triangle
       const int32_t n = n_new;
       std::vector<int32_t> row_first(n + 1), row_of(n), strip_base(n + 1), gh_start(n, -1), gh_end(n, -1),
@@ -157,10 +158,20 @@ int main() {
         const int32_t n_solid = n_rec;
         order.clear();
         for (int32_t e = 0; e < 3 * n_solid; ++e) order.push_back(e);
-        std::shuffle(order.begin(), order.end(), rng);
-        for (int32_t e : order) edge_insert<Seq>(m, st, e / 3, e % 3, &err);
-        std::shuffle(order.begin(), order.end(), rng);
-        for (int32_t e : order) edge_link<Seq>(m, st, e / 3, e % 3, &n_rec, &err);
+        if (mode == 2) {  // links by pairing each undirected edge's two directed edges
+          const int32_t tcap = pair_table_size(n_solid, n);
+          std::vector<uint64_t> tab(tcap, 0);
+          std::shuffle(order.begin(), order.end(), rng);
+          for (int32_t e : order)
+            pair_edge<Seq>(m, tab.data(), tcap, e / 3, e % 3, a.tv[3 * (e / 3) + nxt(e % 3)],
+                           a.tv[3 * (e / 3) + prv(e % 3)], &err);
+          for (int32_t h = 0; h < tcap; ++h) pair_hull<Seq>(m, st, tab[h], &n_rec, &err);
+        } else {  // links through the edge hash table
+          std::shuffle(order.begin(), order.end(), rng);
+          for (int32_t e : order) edge_insert<Seq>(m, st, e / 3, e % 3, &err);
+          std::shuffle(order.begin(), order.end(), rng);
+          for (int32_t e : order) edge_link<Seq>(m, st, e / 3, e % 3, &n_rec, &err);
+        }
         for (int32_t g = n_solid; g < n_rec; ++g) ghost_link<Seq>(m, st, g, &err);
         for (int32_t t = 0; t < n_rec; ++t) a.dead[t] = 0, a.vote[t] = ~0ull;
         int32_t nw = 0;

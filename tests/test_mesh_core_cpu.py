@@ -113,15 +113,17 @@ def test_device_insertion_steps_equal_oracle(driver, name, W, H, batches):
         assert tris == [tuple(t) for t in ref], name
 
 
+@pytest.mark.parametrize("links", ["hash", "pairs"])
 @pytest.mark.parametrize("name,W,H,batches", _cases(), ids=[c[0] for c in _cases()])
-def test_device_start_mesh_equals_oracle(driver, name, W, H, batches):
+def test_device_start_mesh_equals_oracle(driver, name, W, H, batches, links):
     """The first batch built on the device from supports in raster order (rows, ladders,
-    hull pockets, edge links, Lawson flips), then the later batches inserted."""
+    hull pockets, edge links through the hash table or by pairing undirected edges,
+    Lawson flips), then the later batches inserted."""
     first = sorted(batches[0], key=lambda p: (p[1], p[0]))
     if len({p[1] for p in first}) < 2:
         pytest.skip("one row: no triangle")
     batches = [first] + batches[1:]
-    got = _run(driver, W, H, batches, mode=1)
+    got = _run(driver, W, H, batches, mode=1 if links == "hash" else 2)
     pts = []
     for b, (status, tris) in zip(batches, got):
         pts += b
