@@ -32,7 +32,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 39.32 T int32 lane-ops/s
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1511_00758_amd", "csrc", f)
-                  for f in ("kernels.hip", "kernels.hpp")]
+                  for f in ("kernels.hip", "kernels.hpp", "mesh.hip", "mesh.hpp", "mesh_core.hpp", "mesh_start.hpp")]
 
 
 def kernel_source_hash():
