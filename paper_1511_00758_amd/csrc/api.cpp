@@ -199,13 +199,14 @@ Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
   L.S = take((size_t)L.S_cap * sizeof(sm_support));
   L.T = take((size_t)L.T_cap * sizeof(sm_tri));
   L.counters = take(64);
-  L.score = p.support_mode == 1 ? take(npx) : 0;  // FAST scores
-  // device mesh of the tessellations after the first (records of the whole frame)
+  // device mesh of the frame's tessellations; its status words follow the counters, so
+  // that one copy brings both back
   L.mesh_on = p.host_mesh == 0 && (p.n_iters >= 2 || p.support_mode == 0);
+  if (L.mesh_on) L.mstatus = take(kMeshStatusWords * sizeof(int32_t));
+  L.score = p.support_mode == 1 ? take(npx) : 0;  // FAST scores
   if (L.mesh_on) {
     L.mpcap = 1;
     for (int it = 1; it < p.n_iters; ++it) L.mpcap = std::max(L.mpcap, 2 * cells_of(W, H, occ_size(p, it)));
-    L.mstatus = take(kMeshStatusWords * sizeof(int32_t));
     L.mwork = take(mesh_work_bytes(W, H, L.S_cap, L.mpcap));
   }
   L.total = o;
@@ -454,9 +455,12 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   SM_TRY(tm.begin(SM_ST_MATCH));
   SM_HIP(launch_match(cL, cR, W, H, *p, Sd, Lo.n_grid, s));
   SM_TRY(tm.end());
-  SM_TRY(tm.begin(SM_ST_COMPACT));
-  SM_HIP(launch_compact(Sd, Lo.n_grid, &counters[0], occ, W, (int32_t*)(Sd + Lo.n_grid), s));
-  SM_TRY(tm.end());
+  const bool device_path = Lo.mesh_on && !fast;  // grid supports, device meshes
+  if (!device_path) {  // (the device path compacts inside its first mesh kernel)
+    SM_TRY(tm.begin(SM_ST_COMPACT));
+    SM_HIP(launch_compact(Sd, Lo.n_grid, &counters[0], occ, W, (int32_t*)(Sd + Lo.n_grid), s));
+    SM_TRY(tm.end());
+  }
 
   int32_t* d_mstatus = Lo.mesh_on ? (int32_t*)(base + Lo.mstatus) : nullptr;
   bool mesh_dev = false;  // the frame's mesh lives on the device
@@ -471,6 +475,10 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     job.init_tnb = mw.tnb;
     job.init_n = start ? 0 : mesh_init;
     job.n_new_slot = 0;
+    job.last = 0;
+    job.compact_n = 0;
+    job.occ = nullptr;
+    job.compact_count = nullptr;
     job.status = d_mstatus;
     job.status_copy = nullptr;
     job.T = Td;
@@ -482,14 +490,19 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   };
 
   // Grid candidates: the compacted supports are in raster order, the first mesh is built on
-  // the device and every later tessellation inserts into it; the counts stay on the device
-  // (read by the raster, resampling, compaction and mesh kernels), so the frame needs one
-  // synchronisation, at its end. A frame whose device mesh fails is solved again with host
-  // meshes.
-  if (Lo.mesh_on && !fast) {
+  // the device and every later tessellation inserts into it (each mesh kernel first compacts
+  // its new supports); the counts stay on the device (read by the raster, resampling and
+  // mesh kernels), so the frame needs one synchronisation, at its end. A frame whose device
+  // mesh fails is solved again with host meshes.
+  if (device_path) {
     const int32_t* counts = d_mstatus;
     SM_TRY(tm.begin(SM_ST_MESH));
-    SM_HIP(launch_mesh_insert(mesh_job(1, 0, (const int32_t*)(Sd + Lo.n_grid)), s));
+    MeshJob first = mesh_job(1, 0, (const int32_t*)(Sd + Lo.n_grid));
+    first.last = p->n_iters == 1;
+    first.compact_n = Lo.n_grid;  // the matched candidates, compacted by the kernel first
+    first.occ = occ;
+    first.compact_count = &counters[0];
+    SM_HIP(launch_mesh_insert(first, s));
     SM_TRY(tm.end());
     for (int it = 1; it <= p->n_iters; ++it) {
       const int32_t sz = occ_size(*p, it);
@@ -506,20 +519,24 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
       SM_TRY(tm.begin(SM_ST_REMATCH));
       SM_HIP(launch_resample(cL, cR, cell_g, cell_b, D_it, W, H, sz, *p, Sd, s, counts + kMeshSupports, Lo.S_cap));
       SM_TRY(tm.end());
-      SM_TRY(tm.begin(SM_ST_COMPACT));
-      SM_HIP(launch_compact(Sd, 2 * cells, &counters[1], occ, W, nullptr, s, counts + kMeshSupports, Lo.S_cap));
-      SM_TRY(tm.end());
       MeshJob job = mesh_job(0, -1, nullptr);
       job.n_new_slot = 2 * cells;
+      job.compact_n = 2 * cells;  // the resampled supports, compacted by the kernel first
+      job.occ = occ;
+      job.compact_count = &counters[1];
+      job.last = it == p->n_iters - 1;
       SM_TRY(tm.begin(SM_ST_MESH));
       SM_HIP(launch_mesh_insert(job, s));
       SM_TRY(tm.end());
     }
+    // counters (the valid-pixel count) and status words in one copy
     auto t1 = clk::now();
-    SM_HIP(hipMemcpyAsync(h_mstatus, d_mstatus, kMeshStatusWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    if (st) SM_HIP(hipMemcpyAsync(h_count, n_valid, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    const size_t span = Lo.mstatus - Lo.counters + kMeshStatusWords * sizeof(int32_t);
+    uint8_t* h_span = (uint8_t*)h_S;  // free in this path
+    SM_HIP(hipMemcpyAsync(h_span, base + Lo.counters, span, hipMemcpyDeviceToHost, s));
     SM_HIP(hipStreamSynchronize(s));
     us_xfer += us_since(t1);
+    std::memcpy(h_mstatus, h_span + (Lo.mstatus - Lo.counters), kMeshStatusWords * sizeof(int32_t));
     if (h_mstatus[kMeshErr] != 0) {  // the frame again, every tessellation on the host
       const bool failure = h_mstatus[kMeshErr] != kMeshErrNoMesh;
       sm_params q = *p;
@@ -535,7 +552,7 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
       }
       st->mesh_device = p->n_iters;
       unsigned long long nv = 0;
-      std::memcpy(&nv, h_count, sizeof(nv));
+      std::memcpy(&nv, h_span + 32, sizeof(nv));  // n_valid sits 32 bytes into the counters
       st->n_valid = (int64_t)nv;
       SM_TRY(tm.collect(st));
       st->stage_us[SM_ST_HOST_TRI] = us_host;

@@ -361,6 +361,10 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     jb.init_tnb = nullptr;
     jb.init_n = 0;
     jb.n_new_slot = 0;
+    jb.last = 0;
+    jb.compact_n = 0;  // the batched stages compact the supports
+    jb.occ = nullptr;
+    jb.compact_count = nullptr;
     jb.status = (int32_t*)(b + L.mstatus);
     jb.status_copy = dmstat + 8 * job_frame.size();
     jb.T = dTdev + P.tdev_off[f];

@@ -4,6 +4,7 @@
 // (-ffp-contract=off plus explicit _rn intrinsics where rounding order matters), so
 // every output is reproducible bit for bit.
 #include "kernels.hpp"
+#include "compact.hpp"
 
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -546,48 +547,6 @@ __global__ __launch_bounds__(256) void k_rematch_cells(MatchArgs a, const uint64
 // ------------------------------------------------------------------------------------
 // Order-preserving in-place compaction (one 1024-thread workgroup).
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ void compact_block(sm_support* slots, int n, int* n_out, uint8_t* occ, int W,
-                                              int* header) {
-  __shared__ int wsum[16];
-  __shared__ int wofs[16];
-  __shared__ int total;
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
-  int base = 0;
-  for (int start = 0; start < n; start += 1024) {
-    const int i = start + threadIdx.x;
-    sm_support s;
-    bool keep = false;
-    if (i < n) {
-      s = slots[i];
-      keep = s.d != kPending && s.d != kRejected;
-      if (keep && occ) keep = occ[(size_t)s.v * W + s.u] == 0;
-    }
-    const unsigned long long m = __ballot(keep);
-    const int pre = __popcll(m & ((1ull << lane) - 1ull));
-    if (lane == 0) wsum[w] = __popcll(m);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int acc = 0;
-      for (int k = 0; k < 16; ++k) {
-        wofs[k] = acc;
-        acc += wsum[k];
-      }
-      total = acc;
-    }
-    __syncthreads();
-    if (keep) {
-      slots[base + wofs[w] + pre] = s;
-      if (occ) occ[(size_t)s.v * W + s.u] = 1;
-    }
-    base += total;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    *n_out = base;
-    if (header) *header = base;
-  }
-}
-
 __global__ __launch_bounds__(1024) void k_compact(sm_support* slots, int n, int* n_out, uint8_t* occ,
                                                   int W, int* header, const int32_t* slot_off, int slot_cap) {
   if (slot_off) {  // region after the supports counted on the device; its count in the slot after it

@@ -11,6 +11,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include "compact.hpp"
 #include "kernels.hpp"
 #include "mesh.hpp"
 #include "mesh_core.hpp"
@@ -443,7 +444,9 @@ __device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, 
   // output: live solid records as triangles, and the hints of the next tessellation (the
   // walks of this one are over). Each thread has kOutBatch records in flight; one atomic
   // per wave reserves their slots.
-  for (int32_t c = tid; c < gw * gh; c += kMeshThreads) w.hint[c] = -1;
+  const bool hints = a.last == 0;
+  if (hints)
+    for (int32_t c = tid; c < gw * gh; c += kMeshThreads) w.hint[c] = -1;
   __syncthreads();
   const int32_t n_rec = s_nrec;
   for (int32_t base = 0; base < n_rec; base += kOutBatch * kMeshThreads) {  // uniform: the wave scans below
@@ -477,7 +480,7 @@ __device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, 
       if (slot < a.T_cap) a.T[slot] = top_first3<DA>(m, v0, v1, v2);
       else DA::fail(&s_err, kErrCapacity);
       ++slot;
-      mark_hints<DA>(m, w.hint, gw, t, v0, v1, v2);
+      if (hints) mark_hints<DA>(m, w.hint, gw, t, v0, v1, v2);
     }
   }
   __syncthreads();
@@ -487,13 +490,21 @@ __device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, 
 __device__ __forceinline__ void mesh_insert(const MeshJob& a) {
   // the same for every thread: the branches are uniform
   int32_t p0 = a.p0, n_new = 0;
-  if (p0 >= 0) {
-    n_new = *a.n_new;
-  } else {  // first new support and its count kept on the device
+  bool ok = true;
+  if (p0 < 0) {  // first new support and its count kept on the device
     p0 = a.status[kMeshSupports];
-    if (p0 < 3 || p0 >= a.w.S_cap || a.n_new_slot < 0 || (int64_t)p0 + a.n_new_slot >= a.w.S_cap) p0 = 0, n_new = -1;
-    else n_new = *(const int32_t*)(a.S + p0 + a.n_new_slot);
+    ok = p0 >= 3 && p0 < a.w.S_cap && a.n_new_slot >= 0 && (int64_t)p0 + a.n_new_slot < a.w.S_cap;
   }
+  // the supports' compaction first, in place (a frame whose earlier tessellation failed is
+  // solved again on the host: nothing to compact)
+  if (ok && a.compact_n > 0 && (a.start || a.status[kMeshErr] == 0) && (int64_t)p0 + a.compact_n < a.w.S_cap) {
+    sm_support* slots = const_cast<sm_support*>(a.S) + p0;
+    compact_block(slots, a.compact_n, a.compact_count, a.occ, a.W, (int*)(slots + a.compact_n));
+    __syncthreads();
+  }
+  if (!ok) p0 = 0, n_new = -1;
+  else if (a.p0 >= 0) n_new = *a.n_new;
+  else n_new = *(const int32_t*)(a.S + p0 + a.n_new_slot);
   if ((int64_t)p0 + n_new <= kUvLds) mesh_insert_block<true>(a, p0, n_new);
   else mesh_insert_block<false>(a, p0, n_new);
 }
@@ -516,6 +527,8 @@ __global__ __launch_bounds__(kMeshThreads) void k_mesh_insert_many(const MeshJob
   a.status = as_global(a.status);
   a.status_copy = as_global(a.status_copy);
   a.T = as_global(a.T);
+  a.occ = as_global(a.occ);
+  a.compact_count = as_global(a.compact_count);
   MeshWork& w = a.w;
   for (int32_t** q : {&w.tv, &w.tnb, &w.own, &w.kids, &w.dead, &w.fk, &w.fs, &w.fj, &w.work0, &w.work1, &w.ploc,
                       &w.pk, &w.psib, &w.pend0, &w.pend1, &w.uv, &w.hint, &w.row_first, &w.row_of, &w.strip_base,

@@ -55,6 +55,10 @@ struct MeshJob {
   int32_t p0;               // first new support; < 0: status[kMeshSupports] (counted on the device)
   const int32_t* n_new;     // device count of new supports; with p0 < 0 it sits at
   int32_t n_new_slot;       //   S[p0 + n_new_slot] instead
+  int32_t last;             // 1: no tessellation follows (the output writes no location hints)
+  int32_t compact_n;        // > 0: first compact the slots S[p0, p0 + compact_n) in place (the
+  uint8_t* occ;             //   supports' compaction, kernels.hpp, with occupancy occ [H][W]),
+  int32_t* compact_count;   //   their count to *compact_count and to the slot after them
   const int32_t* init_tv;   // init_n > 0: the frame's first mesh (records in host form) to
   const int32_t* init_tnb;  //   start from, vertices < p0; may alias w.tv / w.tnb
   int32_t init_n;
