@@ -140,7 +140,7 @@ struct ManyPlan {
   std::vector<int32_t> groups;   // distinct (rx << 8 | ry) census windows
   // device-mesh frames: their triangles (tdev_off, in triangles)
   std::vector<int32_t> tdev_off;
-  size_t desc_off = 0, off_off = 0, job_off = 0, tri_off = 0, pack_dev = 0, tdev = 0, mstat = 0, total = 0;
+  size_t desc_off = 0, off_off = 0, job_off = 0, tri_off = 0, pack_dev = 0, tdev = 0, mstat = 0, nvalid = 0, total = 0;
   int32_t pack_slots = 0, tri_cap = 0, n_off_arrays = 0, tdev_cap = 0;
 };
 
@@ -190,8 +190,10 @@ sm_status plan_many(const sm_frame* frames, int32_t n, ManyPlan& P) {
   o = P.pack_dev + (size_t)P.pack_slots * sizeof(sm_support);
   P.tdev = align256(o);
   o = P.tdev + (size_t)P.tdev_cap * sizeof(sm_tri);
-  P.mstat = align256(o);
-  o = P.mstat + (size_t)n * 32;
+  P.mstat = align256(o);  // every frame's mesh status words (a copy the mesh kernels keep)
+  o = P.mstat + (size_t)n * kMeshStatusWords * sizeof(int32_t);
+  P.nvalid = align256(o);  // every frame's valid-pixel count, side by side for one read-back
+  o = P.nvalid + (size_t)n * sizeof(unsigned long long);
   P.total = align256(o);
   return SM_OK;
 }
@@ -241,10 +243,14 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
   const auto t_start = std::chrono::steady_clock::now();
   ManyCtx& c = many_ctx();
   // pinned staging: [desc | offsets | mesh jobs | triangles] (uploaded together), then
-  // [packed supports], [mesh status words]
+  // [packed supports], [mesh status words], [valid-pixel counts], and for batches whose
+  // meshes all live on the device one [desc | offsets | mesh jobs] per iteration
   const size_t up_bytes = P.pack_dev - P.desc_off;
   const size_t pack_bytes = align256((size_t)P.pack_slots * sizeof(sm_support));
-  const size_t pin_need = up_bytes + pack_bytes + (size_t)n * 32;
+  const size_t stat_bytes = align256((size_t)n * kMeshStatusWords * sizeof(int32_t));
+  const size_t nv_bytes = align256((size_t)n * sizeof(unsigned long long));
+  const size_t desc_bytes = align256(P.tri_off - P.desc_off);
+  const size_t pin_need = up_bytes + pack_bytes + stat_bytes + nv_bytes + 8 * desc_bytes;
   if (c.pinned_bytes < pin_need) {
     if (c.pinned) SM_HIP(hipHostFree(c.pinned));
     c.pinned = nullptr;
@@ -266,6 +272,9 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
   sm_tri* hT = (sm_tri*)(hp + (P.tri_off - P.desc_off));
   sm_support* hpack = (sm_support*)(hp + up_bytes);
   int32_t* hmstat = (int32_t*)(hp + up_bytes + pack_bytes);
+  unsigned long long* hnv = (unsigned long long*)(hp + up_bytes + pack_bytes + stat_bytes);
+  uint8_t* hstage = hp + up_bytes + pack_bytes + stat_bytes + nv_bytes;
+  unsigned long long* dnv = (unsigned long long*)(base + P.nvalid);
   MeshJob* hjobs = (MeshJob*)(hp + (P.job_off - P.desc_off));
   const MeshJob* djobs = (const MeshJob*)(base + P.job_off);
   sm_tri* dTdev = (sm_tri*)(base + P.tdev);
@@ -320,7 +329,7 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     d.cell_b = (uint64_t*)(b + L.cell_b);
     d.S = (sm_support*)(b + L.S);
     d.counters = (int32_t*)(b + L.counters);
-    d.n_valid = (unsigned long long*)(b + L.counters + 32);
+    d.n_valid = dnv + f;
     d.D_f = fr.D_f;
     d.C_f = fr.C_f;
     d.mask = fr.mask;
@@ -366,7 +375,7 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     jb.occ = nullptr;
     jb.compact_count = nullptr;
     jb.status = (int32_t*)(b + L.mstatus);
-    jb.status_copy = dmstat + 8 * job_frame.size();
+    jb.status_copy = dmstat + (size_t)kMeshStatusWords * f;
     jb.T = dTdev + P.tdev_off[f];
     jb.T_cap = L.T_cap;
     jb.W = hF[f].W;
@@ -382,6 +391,7 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     }
   auto t0 = std::chrono::steady_clock::now();
   SM_HIP(hipMemcpyAsync(base + P.desc_off, hp, P.tri_off - P.desc_off, hipMemcpyHostToDevice, s));
+  SM_HIP(launch_zero(dnv, (size_t)n * sizeof(unsigned long long), s));
   us_xfer += since(t0);
   for (size_t g = 0; g < P.groups.size(); ++g) {
     SM_TRY(arm(SM_ST_CENSUS));
@@ -402,6 +412,157 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
   std::vector<int32_t> n_S(n, 0), iters(n);
   int max_iters = 0;
   for (int32_t f = 0; f < n; ++f) max_iters = std::max(max_iters, iters[f] = frames[f].p.n_iters);
+
+  // Every frame's meshes on the device: the counts stay there too (each frame's mesh status,
+  // read by the raster, resampling and mesh kernels; each mesh kernel first compacts its new
+  // supports), so the batch runs without a synchronisation until its end. Every iteration's
+  // descriptors are staged in a host buffer of their own, since earlier uploads may still be
+  // pending. A frame whose device mesh failed is then solved again alone, with host meshes.
+  bool all_dev = true;
+  for (int32_t f = 0; f < n; ++f) all_dev &= P.lay[f].mesh_on;
+  if (all_dev) {
+    constexpr int32_t kRasterUnits = 1024;  // waves per frame, striding over its triangles
+    for (int it = 1; it <= max_iters; ++it) {
+      uint8_t* h = hstage + (size_t)(it - 1) * desc_bytes;
+      std::memcpy(h, hp, P.tri_off - P.desc_off);  // static descriptors and offsets
+      BatchFrame* F = (BatchFrame*)h;
+      int32_t* ho = (int32_t*)(h + (P.off_off - P.desc_off));
+      MeshJob* J = (MeshJob*)(h + (P.job_off - P.desc_off));
+      int32_t* o_r = ho + (size_t)kRaster * (n + 1);
+      int32_t* o_v = ho + (size_t)kValidate * (n + 1);
+      int32_t* o_m = ho + (size_t)kRematch * (n + 1);
+      o_r[0] = o_v[0] = o_m[0] = 0;
+      std::vector<uint8_t> active(n, 0);
+      int32_t n_jobs = 0;
+      bool resample = false;
+      for (int32_t f = 0; f < n; ++f) {
+        BatchFrame& d = F[f];
+        const Layout& L = P.lay[f];
+        uint8_t* b = base + P.base[f];
+        const bool act = it <= iters[f];
+        active[f] = act;
+        d.sz = occ_size(frames[f].p, std::min(it, iters[f]));
+        d.last = act && it == iters[f];
+        d.counts = (const int32_t*)(b + L.mstatus);
+        d.S_cap = L.S_cap;
+        d.T_cap = L.T_cap;
+        d.T = dTdev + P.tdev_off[f];
+        d.n_T = d.n_S = 0;
+        const bool rs = act && it < iters[f];
+        d.region_n = rs ? 2 * cells_of(d.W, d.H, d.sz) : 0;
+        d.region = nullptr;
+        d.pack = nullptr;
+        d.pack_cap = 0;
+        o_r[f + 1] = o_r[f] + (act ? kRasterUnits : 0);
+        o_m[f + 1] = o_m[f] + d.region_n / 2;
+        if (rs) {  // this iteration's resampled supports, compacted and inserted by the mesh kernel
+          MeshJob& jb = J[n_jobs++];
+          jb = MeshJob{};
+          jb.S = d.S;
+          jb.start = 0;
+          jb.p0 = -1;  // the first new support from the status words
+          jb.n_new = nullptr;
+          jb.n_new_slot = d.region_n;
+          jb.last = it == iters[f] - 1;
+          jb.compact_n = d.region_n;
+          jb.occ = d.occ;
+          jb.compact_count = d.counters + 1;
+          jb.init_tv = jb.init_tnb = nullptr;
+          jb.init_n = 0;
+          jb.status = (int32_t*)(b + L.mstatus);
+          jb.status_copy = dmstat + (size_t)kMeshStatusWords * f;
+          jb.T = dTdev + P.tdev_off[f];
+          jb.T_cap = L.T_cap;
+          jb.W = d.W;
+          jb.H = d.H;
+          jb.w = mesh_work_at(b + L.mwork, d.W, d.H, L.S_cap, L.mpcap);
+        }
+        resample |= rs;
+      }
+      struct VCtx {
+        const BatchFrame* F;
+        const uint8_t* act;
+        int32_t n;
+      } vc{F, active.data(), n};
+      const int nw = validate_pick_nw(
+          [](int w, void* x) {
+            const VCtx& q = *(const VCtx*)x;
+            int64_t tot = 0;
+            for (int32_t f = 0; f < q.n; ++f)
+              if (q.act[f]) tot += (int64_t)validate_blocks(q.F[f].W, q.F[f].H, q.F[f].sz, w) * w;
+            return tot;
+          },
+          &vc);
+      for (int32_t f = 0; f < n; ++f)
+        o_v[f + 1] = o_v[f] + (active[f] ? validate_blocks(F[f].W, F[f].H, F[f].sz, nw) : 0);
+      SM_HIP(hipMemcpyAsync(base + P.desc_off, h, P.tri_off - P.desc_off, hipMemcpyHostToDevice, s));
+      SM_TRY(arm(SM_ST_RASTER));
+      SM_HIP(launch_batch_raster(dF, doff_arr(kRaster), n, o_r[n], s));
+      SM_TRY(arm(SM_ST_VALIDATE));
+      SM_HIP(launch_batch_validate(dF, doff_arr(kValidate), n, o_v[n], nw, s));
+      if (!resample) break;
+      SM_TRY(arm(SM_ST_REMATCH));
+      SM_HIP(launch_batch_rematch(dF, doff_arr(kRematch), n, o_m[n], s));
+      SM_TRY(arm(SM_ST_MESH));
+      SM_HIP(launch_mesh_insert_many(djobs, n_jobs, s));
+    }
+    // one read-back: every frame's status words and valid-pixel count
+    auto t1 = std::chrono::steady_clock::now();
+    SM_HIP(hipMemcpyAsync(hmstat, dmstat, (size_t)n * kMeshStatusWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    SM_HIP(hipMemcpyAsync(hnv, dnv, (size_t)n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    SM_HIP(hipStreamSynchronize(s));
+    us_xfer += since(t1);
+    if (st) {
+      for (const auto& mk : marks) {
+        float ms = 0.f;
+        SM_HIP(hipEventElapsedTime(&ms, c.ev[mk.second], c.ev[mk.second + 1]));
+        st->stage_us[mk.first] += ms * 1e3f;
+        st->stage_launches[mk.first] += 1;
+      }
+    }
+    for (int32_t f = 0; f < n; ++f) {
+      const int32_t* w = hmstat + (size_t)kMeshStatusWords * f;
+      if (w[kMeshErr] != 0) {  // this frame again, alone, every tessellation on the host
+        sm_params q = frames[f].p;
+        q.host_mesh = 1;
+        sm_stats one;
+        std::memset(&one, 0, sizeof(one));
+        const sm_frame& fr = frames[f];
+        const sm_status r = sm_solve(fr.L, fr.R, fr.W, fr.H, fr.stride, &q, base + P.base[f], P.lay[f].total, fr.D_f,
+                                     fr.C_f, fr.mask, &one, stream);
+        if (r != SM_OK) return fail(r, "frame %d: %s", f, last_error().c_str());
+        if (st) {
+          if (w[kMeshErr] != kMeshErrNoMesh) ++st->mesh_fallback;
+          st->n_valid += one.n_valid;
+          for (int k = 0; k < iters[f] && k < 8; ++k) {
+            st->n_support[k] += one.n_support[k];
+            st->n_tris[k] += one.n_tris[k];
+          }
+        }
+        continue;
+      }
+      if (st) {
+        st->n_valid += (int64_t)hnv[f];
+        st->mesh_device += iters[f];
+        for (int k = 0; k < iters[f] && k < 8; ++k) {
+          st->n_support[k] += w[kMeshLog + 2 * k];
+          st->n_tris[k] += w[kMeshLog + 2 * k + 1];
+        }
+      }
+    }
+    if (st) {
+      st->stage_us[SM_ST_HOST_TRI] = us_host;
+      st->stage_us[SM_ST_HOST_COPY] = us_xfer;
+    }
+    for (int32_t f = 0; f < n; ++f) {
+      frames[f].status = SM_OK;
+      frames[f].worker = 0;
+    }
+    const float total_us = since(t_start);
+    for (int32_t f = 0; f < n; ++f) frames[f].latency_us = total_us;
+    if (st) st->stage_us[SM_ST_TOTAL] = total_us;
+    return SM_OK;
+  }
   std::atomic<int32_t> next(0);
   std::atomic<int32_t> bad(-1);
   // new supports (staged by k_batch_pack) into frame f's mesh; from == 0 starts the mesh
@@ -465,12 +626,12 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     if (!todo.empty())
       SM_HIP(hipMemcpyAsync(hpack, dpack, (size_t)P.pack_slots * sizeof(sm_support), hipMemcpyDeviceToHost, s));
     if (!job_frame.empty())
-      SM_HIP(hipMemcpyAsync(hmstat, dmstat, job_frame.size() * 32, hipMemcpyDeviceToHost, s));
+      SM_HIP(hipMemcpyAsync(hmstat, dmstat, (size_t)n * kMeshStatusWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     SM_HIP(hipStreamSynchronize(s));
     us_xfer += since(t1);
     for (size_t j = 0; j < job_frame.size(); ++j) {
       const int32_t f = job_frame[j];
-      const int32_t* w = hmstat + 8 * j;
+      const int32_t* w = hmstat + (size_t)kMeshStatusWords * f;
       const int32_t n_new = w[kMeshNew];
       const int32_t n_max = job_start[j] ? hF[f].n_grid : hF[f].region_n;
       if (n_new < 0 || n_new > n_max) return fail(SM_ERR_INTERNAL, "frame %d: support count %d", f, n_new);
@@ -601,12 +762,10 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
   if (st) {
     // validated-pixel counts: every frame's counter, gathered on the host
     t0 = std::chrono::steady_clock::now();
-    std::vector<unsigned long long> nv(n);
-    for (int32_t f = 0; f < n; ++f)
-      SM_HIP(hipMemcpyAsync(&nv[f], hF[f].n_valid, sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    SM_HIP(hipMemcpyAsync(hnv, dnv, (size_t)n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     SM_HIP(hipStreamSynchronize(s));
     us_xfer += since(t0);
-    for (int32_t f = 0; f < n; ++f) st->n_valid += (int64_t)nv[f];
+    for (int32_t f = 0; f < n; ++f) st->n_valid += (int64_t)hnv[f];
     for (const auto& mk : marks) {
       float ms = 0.f;
       SM_HIP(hipEventElapsedTime(&ms, c.ev[mk.second], c.ev[mk.second + 1]));

@@ -1245,6 +1245,13 @@ __global__ __launch_bounds__(256) void k_batch_raster(const BatchFrame* F, const
   if (unit >= total) return;
   const int f = frame_of(off, n, unit);
   const BatchFrame& fr = F[f];
+  if (fr.counts) {  // the frame's units stride over its triangles (wave-uniform loop)
+    const int units = off[f + 1] - off[f];
+    const int n_T = min(fr.T_cap, fr.counts[kCountTris]);
+    const int n_S = min(fr.S_cap, fr.counts[kCountSupports]);
+    for (int t = unit - off[f]; t < n_T; t += units) raster_tri_wave(fr.S, n_S, fr.T, t, fr.W, fr.H, fr.D_it, lane);
+    return;
+  }
   raster_tri_wave(fr.S, fr.n_S, fr.T, unit - off[f], fr.W, fr.H, fr.D_it, lane);
 }
 
@@ -1267,7 +1274,13 @@ __global__ __launch_bounds__(256) void k_batch_rematch(const BatchFrame* F, cons
   const int f = frame_of(off, n, unit);
   const BatchFrame& fr = F[f];
   const int n_cells = fr.region_n / 2;
-  const MatchArgs a = match_args(fr.cL, fr.cR, fr.W, fr.H, fr.p, fr.region, fr.region_n);
+  sm_support* region = fr.region;
+  if (fr.counts) {  // the region follows the supports counted on the device
+    const int32_t o = fr.counts[kCountSupports];
+    if (o < 0 || (int64_t)o + fr.region_n + 1 > fr.S_cap) return;  // a failed mesh: the frame is redone
+    region = fr.S + o;
+  }
+  const MatchArgs a = match_args(fr.cL, fr.cR, fr.W, fr.H, fr.p, region, fr.region_n);
   rematch_cell(a, fr.cell_g, fr.cell_b, fr.D_it, n_cells, (uint64_t)fr.p.t_lo << 32,
                (uint64_t)(255 - fr.p.t_hi) << 32, unit - off[f], lane);
 }

@@ -148,6 +148,11 @@ struct BatchFrame {
   int32_t region_n;            // 2 * cells, 0 when the frame does not resample
   sm_support* pack;            // host-bound staging: header slot + up to pack_cap supports
   int32_t pack_cap;
+  // counts kept on the device (the frame's mesh status, kCountTris / kCountSupports): when
+  // non-null the raster takes n_T and n_S from it (its units stride over the triangles) and
+  // the resampling region starts at S + counts[kCountSupports]
+  const int32_t* counts;
+  int32_t S_cap, T_cap;
 };
 
 int32_t census_tiles(int32_t W, int32_t H);

@@ -121,6 +121,10 @@ __device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, 
     if (tess >= 0 && tess < 8) {
       a.status[kMeshLog + 2 * tess] = n_pts;
       a.status[kMeshLog + 2 * tess + 1] = n_tri;
+      if (a.status_copy) {
+        a.status_copy[kMeshLog + 2 * tess] = n_pts;
+        a.status_copy[kMeshLog + 2 * tess + 1] = n_tri;
+      }
     }
   };
   __syncthreads();

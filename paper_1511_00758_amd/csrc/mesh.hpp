@@ -63,7 +63,8 @@ struct MeshJob {
   const int32_t* init_tnb;  //   start from, vertices < p0; may alias w.tv / w.tnb
   int32_t init_n;
   int32_t* status;          // device [kMeshStatusWords], read (unless start or init_n > 0) and written
-  int32_t* status_copy;     // nullable: device [8], a copy of words 0..7
+  int32_t* status_copy;     // nullable: device [kMeshStatusWords], a copy of words 0..7 and of
+                            //   the log entries this kernel writes
   sm_tri* T;
   int32_t T_cap;
   int32_t W, H;
