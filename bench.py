@@ -312,9 +312,31 @@ def batched_runs(api, vga_frames, vga_params, workers=16, batches=12, dev="cuda:
                 "frames_per_batch": len(frames), "host_threads": workers,
                 "us_per_batch": {k: round(v / n_batches, 1) for k, v in acc.items() if v > 0}}
 
-    # stage-batched: one launch per stage over the 64 frames (sm_solve_many)
+    def run_graph(frames, n_batches):
+        """The same batch captured once into a HIP graph and replayed (no stage timing)."""
+        ms = api.ManySolver(workers, device=dev)
+        outs, graph = ms.capture(frames)
+        try:
+            graph.run()  # warm-up replay
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(n_batches):
+                graph.run(stats=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        finally:
+            graph.close()
+        npx = sum(int(f[0].numel()) for f in frames)
+        return {"frames_per_s": round(n_batches * len(frames) / dt, 1),
+                "mpx_per_s": round(n_batches * npx / dt / 1e6, 2),
+                "ms_per_batch": round(dt / n_batches * 1e3, 3), "frames_per_batch": len(frames)}
+
+    # stage-batched: one launch per stage over the 64 frames (sm_solve_many), eager with
+    # stage timing, and captured into a HIP graph and replayed
     out["vga_20planes_batch64_stage_batched"] = run_many(vga, batches)
     out["batch64_mixed_stage_batched"] = run_many(mixed, batches)
+    out["vga_20planes_batch64_graph"] = run_graph(vga, batches)
+    out["batch64_mixed_graph"] = run_graph(mixed, batches)
     return out
 
 

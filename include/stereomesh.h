@@ -329,11 +329,40 @@ sm_status sm_solve_batch(sm_frame* frames, int32_t n, void* const* streams, void
  *   ws       one workspace of ws_bytes >= sm_solve_many_workspace_bytes(frames, n),
  *            256-byte aligned, holding every frame's buffers and the batch staging.
  *   st       [host] statistics summed over frames (one launch counted per stage launch).
- *   Synchronises `stream` once per triangulation round (max n_iters times).
+ *   Synchronisation: when every frame keeps its meshes on the device (host_mesh = 0) the
+ *   counts stay on the device and `stream` is synchronised once, at the end (a frame whose
+ *   device mesh failed is then solved again alone with host meshes); otherwise once per
+ *   triangulation round (max n_iters times).
  */
 size_t sm_solve_many_workspace_bytes(const sm_frame* frames /* [host] */, int32_t n);
 sm_status sm_solve_many(sm_frame* frames /* [host] */, int32_t n, void* ws, size_t ws_bytes,
                         int32_t n_threads, sm_stats* st /* [host] */, void* stream);
+
+/*
+ * sm_solve_many_capture -- sm_solve_many whose device work is recorded, from the first
+ *   upload to the last mesh launch, into a HIP graph on `stream`, run once (the frames are
+ *   solved as by sm_solve_many) and returned in *out. Later batches over the same frames
+ *   (same sizes, parameters, image, output and workspace buffers; the image contents may
+ *   change) replay it with sm_many_graph_run, which launches one graph instead of the
+ *   batch's dozens of launches and uploads (the hipGraph-captured iteration loop of the
+ *   batched solve; the stage-batched design is Alg. 1 applied stage by stage). Every frame
+ *   must keep its meshes on the device (host_mesh = 0), so that the batch needs no host
+ *   synchronisation; otherwise SM_ERR_ARG. The graph owns its pinned staging; the
+ *   workspace must stay allocated while the graph lives.
+ *   st       [host] statistics of the first run, may be NULL (no stage timing).
+ *   out      [host] out: the graph, freed by sm_many_graph_destroy; NULL on error.
+ */
+typedef struct sm_many_graph sm_many_graph;
+sm_status sm_solve_many_capture(sm_frame* frames /* [host] */, int32_t n, void* ws, size_t ws_bytes,
+                                sm_stats* st /* [host] */, void* stream, sm_many_graph** out /* [host] */);
+/*
+ * sm_many_graph_run -- replays a captured batch on `stream`, reads back every frame's
+ *   status words and valid-pixel count, solves again alone (with host meshes) a frame whose
+ *   device mesh failed, and fills st (counts only). Synchronises `stream` once. Calls on
+ *   one graph must not overlap.
+ */
+sm_status sm_many_graph_run(sm_many_graph* g, sm_stats* st /* [host] */, void* stream);
+void sm_many_graph_destroy(sm_many_graph* g);
 
 /* Message of the calling thread's last non-OK status ("" if none). */
 const char* sm_last_error(void);

@@ -354,3 +354,61 @@ class ManySolver:
         if not (stats or timing):
             return outs
         return outs, stats_dict(st, 8)
+
+    def capture(self, frames, outputs=None, stream=None):
+        """Solves ``frames`` like ``__call__`` while recording the batch's device work into
+        a HIP graph (``sm_solve_many_capture``); returns ``(outputs, ManyGraph)``. The graph
+        replays the batch over the same tensors (new image contents may be copied into
+        them); every frame must keep its meshes on the device (``host_mesh = 0``). This
+        solver's workspace is then fixed to the graph."""
+        n = len(frames)
+        outs = outputs
+        if outs is None:
+            outs = [(torch.empty(l.shape, dtype=torch.float32, device=l.device),
+                     torch.empty(l.shape, dtype=torch.uint8, device=l.device),
+                     torch.empty(l.shape, dtype=torch.uint8, device=l.device)) for (l, _, _) in frames]
+        arr = self._frames(frames, outs)
+        L = _lib.load()
+        need = L.sm_solve_many_workspace_bytes(arr, n) if n else 0
+        if n and need == 0:
+            raise ValueError("invalid frame sizes or parameters: " + L.sm_last_error().decode(errors="replace"))
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)  # owned by the graph
+        ptr = ws.data_ptr() + ((-ws.data_ptr()) % 256)
+        handle = ctypes.c_void_p()
+        # a capture needs a stream of its own (not the legacy default stream), ordered after
+        # the caller's work and before what the caller does next
+        cur = torch.cuda.current_stream(self.device) if stream is None else stream
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(cur)
+        check(L.sm_solve_many_capture(arr, n, ptr, need, None, _stream(side), ctypes.byref(handle)))
+        cur.wait_stream(side)
+        return outs, ManyGraph(handle, ws, frames, outs)
+
+
+class ManyGraph:
+    """A captured stage-batched solve (``sm_solve_many_capture``). ``run()`` replays it over
+    the tensors it was captured with and returns the summed statistics."""
+
+    def __init__(self, handle, ws, frames, outs):
+        self._h = handle
+        self._keep = (ws, frames, outs)  # the graph reads and writes these buffers
+
+    def run(self, stats=False, stream=None):
+        if self._h is None:
+            raise RuntimeError("graph destroyed")
+        L = _lib.load()
+        st = _lib.SmStats()
+        check(L.sm_many_graph_run(self._h, st if stats else None, _stream(stream)))
+        return stats_dict(st, 8) if stats else None
+
+    def close(self):
+        if self._h is not None:
+            _lib.load().sm_many_graph_destroy(self._h)
+            self._h = None
+            self._keep = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -212,6 +212,83 @@ ManyCtx& many_ctx() {
   return *c;
 }
 
+// A capture of the device work of one batch (sm_solve_many_capture): its own pinned
+// staging, which the graph's copies read on every replay.
+struct GraphBuild {
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // what a replay's read-back needs
+  ManyPlan P;
+  uint8_t* base = nullptr;
+  int32_t* hmstat = nullptr;
+  unsigned long long* hnv = nullptr;
+  std::vector<int32_t> iters;
+};
+
+// Ends a stream capture left open by an early return.
+struct CaptureGuard {
+  hipStream_t s;
+  bool active = false;
+  explicit CaptureGuard(hipStream_t ss) : s(ss) {}
+  ~CaptureGuard() {
+    if (!active) return;
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+  }
+};
+
+// End of a batch whose meshes all live on the device: one read-back of every frame's
+// status words and valid-pixel count, then each frame whose device mesh failed is solved
+// again alone with host meshes (in its own part of the workspace); st gets the counts.
+sm_status finish_device_batch(const sm_frame* frames, int32_t n, const ManyPlan& P, uint8_t* base, int32_t* hmstat,
+                              unsigned long long* hnv, const std::vector<int32_t>& iters, sm_stats* st,
+                              hipStream_t s, float& us_xfer) {
+  const int32_t* dmstat = (const int32_t*)(base + P.mstat);
+  const unsigned long long* dnv = (const unsigned long long*)(base + P.nvalid);
+  auto t1 = std::chrono::steady_clock::now();
+  SM_HIP(hipMemcpyAsync(hmstat, dmstat, (size_t)n * kMeshStatusWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  SM_HIP(hipMemcpyAsync(hnv, dnv, (size_t)n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+  SM_HIP(hipStreamSynchronize(s));
+  us_xfer += std::chrono::duration<float, std::micro>(std::chrono::steady_clock::now() - t1).count();
+  for (int32_t f = 0; f < n; ++f) {
+    const int32_t* w = hmstat + (size_t)kMeshStatusWords * f;
+    if (w[kMeshErr] != 0) {  // this frame again, alone, every tessellation on the host
+      sm_params q = frames[f].p;
+      q.host_mesh = 1;
+      sm_stats one;
+      std::memset(&one, 0, sizeof(one));
+      const sm_frame& fr = frames[f];
+      const sm_status r = sm_solve(fr.L, fr.R, fr.W, fr.H, fr.stride, &q, base + P.base[f], P.lay[f].total, fr.D_f,
+                                   fr.C_f, fr.mask, &one, s);
+      if (r != SM_OK) return fail(r, "frame %d: %s", f, last_error().c_str());
+      if (st) {
+        if (w[kMeshErr] != kMeshErrNoMesh) ++st->mesh_fallback;
+        st->n_valid += one.n_valid;
+        for (int k = 0; k < iters[f] && k < 8; ++k) {
+          st->n_support[k] += one.n_support[k];
+          st->n_tris[k] += one.n_tris[k];
+        }
+      }
+      continue;
+    }
+    if (st) {
+      st->n_valid += (int64_t)hnv[f];
+      st->mesh_device += iters[f];
+      for (int k = 0; k < iters[f] && k < 8; ++k) {
+        st->n_support[k] += w[kMeshLog + 2 * k];
+        st->n_tris[k] += w[kMeshLog + 2 * k + 1];
+      }
+    }
+  }
+  return SM_OK;
+}
+
+sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int32_t n_threads, sm_stats* st,
+                    void* stream, GraphBuild* gb);
+
 }  // namespace
 }  // namespace sm
 
@@ -225,15 +302,26 @@ extern "C" size_t sm_solve_many_workspace_bytes(const sm_frame* frames, int32_t 
 extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int32_t n_threads,
                                    sm_stats* st, void* stream) {
   last_error().clear();
+  return sm::many_impl(frames, n, ws, ws_bytes, n_threads, st, stream, nullptr);
+}
+
+namespace sm {
+namespace {
+
+sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int32_t n_threads, sm_stats* st,
+                    void* stream, GraphBuild* gb) {
   if (n < 0 || (n > 0 && !frames)) return fail(SM_ERR_ARG, "bad frame array / count");
-  if (n == 0) return SM_OK;
+  if (n == 0) return gb ? fail(SM_ERR_ARG, "nothing to capture") : SM_OK;
   if (n_threads < 1 || n_threads > 256) return fail(SM_ERR_ARG, "n_threads must be in [1, 256]");
   ManyPlan P;
   SM_TRY(plan_many(frames, n, P));
   if (!ws || ((uintptr_t)ws & 255u)) return fail(SM_ERR_ARG, "workspace missing or not 256-byte aligned");
   if (ws_bytes < P.total) return fail(SM_ERR_CAPACITY, "workspace %zu < %zu bytes", ws_bytes, P.total);
+  if (gb)
+    for (int32_t f = 0; f < n; ++f)
+      if (!P.lay[f].mesh_on) return fail(SM_ERR_ARG, "frame %d: a captured batch keeps its meshes on the device", f);
   const hipStream_t s = (hipStream_t)stream;
-  const int32_t timing = st ? st->timing : 0;
+  const int32_t timing = st && !gb ? st->timing : 0;  // no timing events inside a capture
   const uint32_t timed = (timing & SM_TIME_SELECTED) ? (uint32_t)timing & 0xffffu : 0xffffu;
   if (st) {
     const int32_t keep = st->timing;
@@ -251,12 +339,14 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
   const size_t nv_bytes = align256((size_t)n * sizeof(unsigned long long));
   const size_t desc_bytes = align256(P.tri_off - P.desc_off);
   const size_t pin_need = up_bytes + pack_bytes + stat_bytes + nv_bytes + 8 * desc_bytes;
-  if (c.pinned_bytes < pin_need) {
-    if (c.pinned) SM_HIP(hipHostFree(c.pinned));
-    c.pinned = nullptr;
-    c.pinned_bytes = 0;
-    SM_HIP(hipHostMalloc(&c.pinned, pin_need, hipHostMallocDefault));
-    c.pinned_bytes = pin_need;
+  void*& pinned = gb ? gb->pinned : c.pinned;  // a capture owns its staging
+  size_t& pinned_bytes = gb ? gb->pinned_bytes : c.pinned_bytes;
+  if (pinned_bytes < pin_need) {
+    if (pinned) SM_HIP(hipHostFree(pinned));
+    pinned = nullptr;
+    pinned_bytes = 0;
+    SM_HIP(hipHostMalloc(&pinned, pin_need, hipHostMallocDefault));
+    pinned_bytes = pin_need;
   }
   if ((int32_t)c.dl.size() < n) {
     c.dl.resize(n);
@@ -266,7 +356,7 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
     c.bext.resize(n);
   }
   uint8_t* base = (uint8_t*)ws;
-  uint8_t* hp = (uint8_t*)c.pinned;
+  uint8_t* hp = (uint8_t*)pinned;
   BatchFrame* hF = (BatchFrame*)hp;
   int32_t* hoff = (int32_t*)(hp + (P.off_off - P.desc_off));
   sm_tri* hT = (sm_tri*)(hp + (P.tri_off - P.desc_off));
@@ -389,6 +479,11 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
       mesh_dev[f] = 1;
       add_job(f, 1, 0, (const int32_t*)(hF[f].S + hF[f].n_grid));
     }
+  CaptureGuard cap(s);
+  if (gb) {  // everything enqueued from here to the last mesh launch goes into the graph
+    SM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    cap.active = true;
+  }
   auto t0 = std::chrono::steady_clock::now();
   SM_HIP(hipMemcpyAsync(base + P.desc_off, hp, P.tri_off - P.desc_off, hipMemcpyHostToDevice, s));
   SM_HIP(launch_zero(dnv, (size_t)n * sizeof(unsigned long long), s));
@@ -506,48 +601,24 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
       SM_TRY(arm(SM_ST_MESH));
       SM_HIP(launch_mesh_insert_many(djobs, n_jobs, s));
     }
-    // one read-back: every frame's status words and valid-pixel count
-    auto t1 = std::chrono::steady_clock::now();
-    SM_HIP(hipMemcpyAsync(hmstat, dmstat, (size_t)n * kMeshStatusWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    SM_HIP(hipMemcpyAsync(hnv, dnv, (size_t)n * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-    SM_HIP(hipStreamSynchronize(s));
-    us_xfer += since(t1);
+    if (gb) {  // the graph of the batch, then its first run
+      cap.active = false;
+      SM_HIP(hipStreamEndCapture(s, &gb->graph));
+      SM_HIP(hipGraphInstantiate(&gb->exec, gb->graph, nullptr, nullptr, 0));
+      SM_HIP(hipGraphLaunch(gb->exec, s));
+      gb->P = P;
+      gb->base = base;
+      gb->hmstat = hmstat;
+      gb->hnv = hnv;
+      gb->iters = iters;
+    }
+    SM_TRY(finish_device_batch(frames, n, P, base, hmstat, hnv, iters, st, s, us_xfer));
     if (st) {
       for (const auto& mk : marks) {
         float ms = 0.f;
         SM_HIP(hipEventElapsedTime(&ms, c.ev[mk.second], c.ev[mk.second + 1]));
         st->stage_us[mk.first] += ms * 1e3f;
         st->stage_launches[mk.first] += 1;
-      }
-    }
-    for (int32_t f = 0; f < n; ++f) {
-      const int32_t* w = hmstat + (size_t)kMeshStatusWords * f;
-      if (w[kMeshErr] != 0) {  // this frame again, alone, every tessellation on the host
-        sm_params q = frames[f].p;
-        q.host_mesh = 1;
-        sm_stats one;
-        std::memset(&one, 0, sizeof(one));
-        const sm_frame& fr = frames[f];
-        const sm_status r = sm_solve(fr.L, fr.R, fr.W, fr.H, fr.stride, &q, base + P.base[f], P.lay[f].total, fr.D_f,
-                                     fr.C_f, fr.mask, &one, stream);
-        if (r != SM_OK) return fail(r, "frame %d: %s", f, last_error().c_str());
-        if (st) {
-          if (w[kMeshErr] != kMeshErrNoMesh) ++st->mesh_fallback;
-          st->n_valid += one.n_valid;
-          for (int k = 0; k < iters[f] && k < 8; ++k) {
-            st->n_support[k] += one.n_support[k];
-            st->n_tris[k] += one.n_tris[k];
-          }
-        }
-        continue;
-      }
-      if (st) {
-        st->n_valid += (int64_t)hnv[f];
-        st->mesh_device += iters[f];
-        for (int k = 0; k < iters[f] && k < 8; ++k) {
-          st->n_support[k] += w[kMeshLog + 2 * k];
-          st->n_tris[k] += w[kMeshLog + 2 * k + 1];
-        }
       }
     }
     if (st) {
@@ -786,3 +857,64 @@ extern "C" sm_status sm_solve_many(sm_frame* frames, int32_t n, void* ws, size_t
   if (st) st->stage_us[SM_ST_TOTAL] = total_us;
   return SM_OK;
 }
+
+}  // namespace
+}  // namespace sm
+
+struct sm_many_graph {
+  sm::GraphBuild gb;
+  std::vector<sm_frame> frames;
+  ~sm_many_graph() {
+    if (gb.exec) (void)hipGraphExecDestroy(gb.exec);
+    if (gb.graph) (void)hipGraphDestroy(gb.graph);
+    if (gb.pinned) (void)hipHostFree(gb.pinned);
+  }
+};
+
+extern "C" sm_status sm_solve_many_capture(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, sm_stats* st,
+                                           void* stream, sm_many_graph** out) {
+  using namespace sm;
+  last_error().clear();
+  if (!out) return fail(SM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  sm_many_graph* g = nullptr;
+  try {
+    g = new sm_many_graph();
+    g->frames.assign(frames, frames + (n > 0 && frames ? n : 0));
+  } catch (...) {
+    delete g;
+    return fail(SM_ERR_INTERNAL, "out of host memory");
+  }
+  const sm_status r = many_impl(frames, n, ws, ws_bytes, 1, st, stream, &g->gb);
+  if (r != SM_OK) {
+    delete g;
+    return r;
+  }
+  *out = g;
+  return SM_OK;
+}
+
+extern "C" sm_status sm_many_graph_run(sm_many_graph* g, sm_stats* st, void* stream) {
+  using namespace sm;
+  last_error().clear();
+  if (!g || !g->gb.exec) return fail(SM_ERR_ARG, "no captured batch");
+  if (st) {
+    const int32_t keep = st->timing;
+    std::memset(st, 0, sizeof(*st));
+    st->timing = keep;
+  }
+  const auto t_start = std::chrono::steady_clock::now();
+  const hipStream_t s = (hipStream_t)stream;
+  SM_HIP(hipGraphLaunch(g->gb.exec, s));
+  float us_xfer = 0.f;
+  SM_TRY(finish_device_batch(g->frames.data(), (int32_t)g->frames.size(), g->gb.P, g->gb.base, g->gb.hmstat,
+                             g->gb.hnv, g->gb.iters, st, s, us_xfer));
+  if (st) {
+    st->stage_us[SM_ST_HOST_COPY] = us_xfer;
+    st->stage_us[SM_ST_TOTAL] =
+        std::chrono::duration<float, std::micro>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  return SM_OK;
+}
+
+extern "C" void sm_many_graph_destroy(sm_many_graph* g) { delete g; }

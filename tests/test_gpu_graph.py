@@ -1,0 +1,74 @@
+"""GPU: a stage-batched solve captured into a HIP graph (sm_solve_many_capture) and replayed
+(sm_many_graph_run). Every replay -- with new image contents copied into the captured input
+buffers, and eager work and synchronisations between the replays -- gives for every frame
+exactly what sm_solve gives for that frame alone."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from test_gpu_many import _mixed, _solo
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _note(*a):
+    print("[gpu-graph]", *a, file=sys.stderr, flush=True)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+# image contents of the successive runs: rows are independent epipolar lines, so flipping
+# both images upside down or shifting both by whole columns gives valid pairs of the same size
+_VIEWS = [lambda a: a, np.flipud, lambda a: np.roll(a, 7, axis=1), lambda a: a]
+
+
+def test_graph_replays_equal_solo():
+    from paper_1511_00758_amd import api
+    mixed = _mixed()
+    Ls = [_dev(l) for (l, _, _) in mixed]
+    Rs = [_dev(r) for (_, r, _) in mixed]
+    ms = api.ManySolver(device=DEV)
+    _note("capture", len(mixed), "frames")
+    outs, graph = ms.capture([(L, R, prm) for L, R, (_, _, prm) in zip(Ls, Rs, mixed)])
+    torch.cuda.synchronize()
+    try:
+        for k, view in enumerate(_VIEWS):
+            if k > 0:
+                for L, R, (l, r, _) in zip(Ls, Rs, mixed):
+                    L.copy_(_dev(view(l)))
+                    R.copy_(_dev(view(r)))
+                # eager work of the program between replays
+                l0, r0, p0 = mixed[0]
+                api.Solver(l0.shape[1], l0.shape[0], p0, device=DEV)(_dev(r0), _dev(l0))
+                torch.cuda.synchronize()
+                _note("replay", k)
+                st = graph.run(stats=True)
+                torch.cuda.synchronize()
+            else:
+                st = None
+            total = 0
+            for i, ((l, r, prm), (D, C, M)) in enumerate(zip(mixed, outs)):
+                sD, sC, sM = _solo(view(l), view(r), prm)
+                assert (D.cpu().numpy().view(np.uint32) == sD.view(np.uint32)).all(), (k, i)
+                assert (C.cpu().numpy() == sC).all(), (k, i)
+                assert (M.cpu().numpy() == sM).all(), (k, i)
+                total += int(sM.sum())
+            if st is not None:
+                assert st["n_valid"] == total
+                assert st["mesh_fallback"] == 0
+    finally:
+        graph.close()
+
+
+def test_graph_capture_needs_device_meshes():
+    from paper_1511_00758_amd import api, _lib
+    mixed = _mixed()[:2]
+    frames = [(_dev(l), _dev(r), dict(prm, host_mesh=i)) for i, (l, r, prm) in enumerate(mixed)]
+    with pytest.raises(_lib.StereoMeshError):
+        api.ManySolver(device=DEV).capture(frames)
