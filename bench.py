@@ -419,6 +419,8 @@ def main():
     ap.add_argument("--frames", type=int, default=8, help="distinct frames cycled")
     ap.add_argument("--cpu-frames", type=int, default=3, help="oracle sample size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch-shape rules (no sm_autotune before timing)")
     ap.add_argument("--no-timing", action="store_true",
                     help="do not record per-kernel events in the timed region")
     ap.add_argument("--no-serve", action="store_true",
@@ -470,6 +472,9 @@ def main():
         frames.append((sc.left, sc.right))
     dframes = [(torch.from_numpy(l).to(dev), torch.from_numpy(r).to(dev)) for (l, r) in frames]
     solver = api.Solver(W, H, params, device=dev)
+    # launch shapes measured on the first frame (sm_autotune) for this size, used by every
+    # later launch of the run (outputs do not depend on them)
+    tuned = None if args.no_autotune else solver.autotune(*dframes[0])
     # live per-kernel timing of the roofline kernels (events around every launch would
     # slow the whole frame by ~10%; --time-all times every kernel)
     timing = False if args.no_timing else (True if args.time_all else ("validate", "raster", "mesh"))
@@ -563,6 +568,7 @@ def main():
                        "p99": round(float(np.percentile(lat_ms, 99)), 4),
                        "max": round(float(lat_ms.max()), 4)},
         "kernels": kernels,
+        "autotune": tuned,
         "host_us_per_step": host,
         "roofline": roof,
         "roofline_validate": roof_val,

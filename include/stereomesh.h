@@ -364,6 +364,21 @@ sm_status sm_solve_many_capture(sm_frame* frames /* [host] */, int32_t n, void* 
 sm_status sm_many_graph_run(sm_many_graph* g, sm_stats* st /* [host] */, void* stream);
 void sm_many_graph_destroy(sm_many_graph* g);
 
+/*
+ * sm_autotune -- measures the tunable launch shapes on one frame and records the fastest
+ *   for its size (used by every later sm_solve / sm_solve_many launch of that size in this
+ *   process; outputs do not depend on them): validation's block size in waves (1, 2, 4, 8
+ *   or 16) for each iteration's cell size, and, for grid supports with device meshes, the
+ *   workgroups of the rasteriser's bounded grid (512 ... 8192). Solves the frame, times
+ *   each candidate over five launches on the solve's buffers, then solves the frame again,
+ *   so that D_f, C_f and mask hold its results. Arguments as sm_solve.
+ *   choices  [host] [9] out: validation waves per iteration (0 past n_iters), then the
+ *            raster workgroups (0 when not tuned).
+ */
+sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
+                      const sm_params* p /* [host] */, void* ws, size_t ws_bytes, float* D_f, uint8_t* C_f,
+                      uint8_t* mask, int32_t* choices /* [host] */, void* stream);
+
 /* Message of the calling thread's last non-OK status ("" if none). */
 const char* sm_last_error(void);
 

@@ -70,7 +70,7 @@ class SmFrame(ctypes.Structure):
 EXPORTS = ("sm_census", "sm_match_support", "sm_grid_candidates", "sm_fast_candidates", "sm_triangulate",
            "sm_interpolate", "sm_cells", "sm_validate", "sm_resample",
            "sm_solve_workspace_bytes", "sm_solve", "sm_solve_batch", "sm_solve_many_workspace_bytes",
-           "sm_solve_many", "sm_solve_many_capture", "sm_many_graph_run", "sm_many_graph_destroy",
+           "sm_solve_many", "sm_solve_many_capture", "sm_many_graph_run", "sm_many_graph_destroy", "sm_autotune",
            "sm_last_error", "sm_version")
 
 
@@ -117,6 +117,8 @@ def load():
         "sm_solve_many_capture": (c_i32, [P(SmFrame), c_i32, c_vp, c_size, P(SmStats), c_vp, P(c_vp)]),
         "sm_many_graph_run": (c_i32, [c_vp, P(SmStats), c_vp]),
         "sm_many_graph_destroy": (None, [c_vp]),
+        "sm_autotune": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, P(SmParams), c_vp, c_size, c_vp, c_vp, c_vp,
+                                P(c_i32), c_vp]),
         "sm_last_error": (ctypes.c_char_p, []),
         "sm_version": (ctypes.c_char_p, []),
     }

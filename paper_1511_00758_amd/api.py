@@ -234,6 +234,21 @@ class Solver:
         return SolveResult(self.D_f, self.C_f, self.mask,
                            stats_dict(st, self.p.n_iters) if st is not None else None)
 
+    def autotune(self, left: torch.Tensor, right: torch.Tensor, stream=None) -> dict:
+        """Measures the tunable launch shapes on this frame (``sm_autotune``) and records the
+        fastest for this size; later solves of the size use them (outputs do not change).
+        Returns the choices; D_f, C_f and mask hold the frame's results."""
+        _require_cuda(left, right)
+        if left.shape != (self.H, self.W) or right.shape != (self.H, self.W):
+            raise ValueError("image size differs from the solver's")
+        L = _lib.load()
+        ch = (ctypes.c_int32 * 9)()
+        check(L.sm_autotune(left.data_ptr(), right.data_ptr(), self.W, self.H, left.stride(0), self.p,
+                            self.ws_ptr, self.ws_bytes, self.D_f.data_ptr(), self.C_f.data_ptr(),
+                            self.mask.data_ptr(), ch, _stream(stream)))
+        n = self.p.n_iters
+        return {"validate_waves": [int(ch[k]) for k in range(min(n, 8))], "raster_blocks": int(ch[8])}
+
 
 def solve(left: torch.Tensor, right: torch.Tensor, params: dict, stats=False) -> SolveResult:
     H, W = left.shape

@@ -712,4 +712,86 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   return SM_OK;
 }
 
+
+// Measured launch shapes for one frame size and parameter set (the autotuner of the
+// batched and per-frame solves): the frame is solved once, then each tunable launch is
+// timed over its candidate shapes on the buffers of that solve, the fastest is recorded
+// for (W, H[, sz]) and later launches of that size use it; the frame is solved again so
+// that D_f, C_f and mask hold its results.
+sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
+                      const sm_params* p, void* ws, size_t ws_bytes, float* D_f, uint8_t* C_f, uint8_t* mask,
+                      int32_t* choices, void* stream) {
+  last_error().clear();
+  SM_TRY(check_image_args(W, H));
+  SM_TRY(check_params(p));
+  if (!choices) return fail(SM_ERR_ARG, "choices is NULL");
+  for (int k = 0; k < 9; ++k) choices[k] = 0;
+  SM_TRY(sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, nullptr, stream));
+  const Layout Lo = layout_of(W, H, *p);
+  uint8_t* base = (uint8_t*)ws;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  SM_HIP(hipEventCreate(&e0));
+  auto done = [&](sm_status r) {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return r;
+  };
+  if (hipEventCreate(&e1) != hipSuccess) return done(fail(SM_ERR_HIP, "hipEventCreate failed"));
+  // mean device time of `reps` launches of fn after one untimed launch, in ms (< 0: error)
+  auto time_it = [&](auto&& fn) -> float {
+    constexpr int reps = 5;
+    if (fn() != hipSuccess) return -1.f;
+    if (hipEventRecord(e0, s) != hipSuccess) return -1.f;
+    for (int r = 0; r < reps; ++r)
+      if (fn() != hipSuccess) return -1.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.f;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
+    return ms / reps;
+  };
+  const uint64_t* cL = (const uint64_t*)(base + Lo.cL);
+  const uint64_t* cR = (const uint64_t*)(base + Lo.cR);
+  const uint8_t* omega = base + Lo.omega;
+  const float* D_it = (const float*)(base + Lo.D_it);
+  uint64_t* cell_g = (uint64_t*)(base + Lo.cell_g);
+  uint64_t* cell_b = (uint64_t*)(base + Lo.cell_b);
+  // validation: block size in waves, per cell size of the iterations
+  for (int it = 1; it <= p->n_iters && it <= 8; ++it) {
+    const int32_t sz = occ_size(*p, it);
+    int best = 0;
+    float best_ms = 0.f;
+    for (int nw : {1, 2, 4, 8, 16}) {
+      const float ms = time_it([&] {
+        return launch_validate_nw(cL, cR, omega, D_it, W, H, *p, sz, nullptr, D_f, C_f, cell_g, cell_b, nullptr,
+                                  nullptr, nw, s);
+      });
+      if (ms < 0.f) return done(fail(SM_ERR_HIP, "validation timing failed"));
+      if (best == 0 || ms < best_ms) best = nw, best_ms = ms;
+    }
+    set_tuned_choice(kTuneValidateWaves, W, H, sz, best);
+    choices[it - 1] = best;
+  }
+  // rasterisation with device counts (grid supports, device meshes): workgroups of the
+  // bounded grid, on the frame's last mesh
+  if (Lo.mesh_on && p->support_mode == 0) {
+    const int32_t* counts = (const int32_t*)(base + Lo.mstatus);
+    const sm_support* Sd = (const sm_support*)(base + Lo.S);
+    const sm_tri* Td = (const sm_tri*)(base + Lo.T);
+    float* D_w = (float*)(base + Lo.D_it);
+    int best = 0;
+    float best_ms = 0.f;
+    for (int blocks : {512, 1024, 2048, 4096, 8192}) {
+      const float ms =
+          time_it([&] { return launch_raster_blocks(Sd, Lo.S_cap, Td, Lo.T_cap, W, H, D_w, s, counts, blocks); });
+      if (ms < 0.f) return done(fail(SM_ERR_HIP, "raster timing failed"));
+      if (best == 0 || ms < best_ms) best = blocks, best_ms = ms;
+    }
+    set_tuned_choice(kTuneRasterBlocks, W, H, 0, best);
+    choices[8] = best;
+  }
+  // the outputs of the frame again (the timed validations refined D_f and C_f)
+  return done(sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, nullptr, stream));
+}
+
 }  // extern "C"

@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace sm {
 
@@ -1044,12 +1047,23 @@ hipError_t launch_fill_nan(float* D, size_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_raster_blocks(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
+                                int32_t W, int32_t H, float* D_it, hipStream_t s, const int32_t* counts,
+                                int32_t max_blocks) {
+  if (n_tris <= 0) return hipSuccess;
+  if (!counts || max_blocks < 1) return hipErrorInvalidValue;
+  const unsigned blocks = std::min<unsigned>(blocks_for(n_tris, 4 * kTriPerWave), (unsigned)max_blocks);
+  SM_LAUNCH(k_raster_group, dim3(blocks), dim3(256), 0, s, S, n_support, T, n_tris, W, H, D_it, counts);
+  return hipGetLastError();
+}
+
 hipError_t launch_raster(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
                          int32_t W, int32_t H, float* D_it, hipStream_t s, const int32_t* counts) {
   if (n_tris <= 0) return hipSuccess;
   if (counts) {  // the count is known on the device only: a bounded grid of the group layout
-    const unsigned blocks = std::min<unsigned>(blocks_for(n_tris, 4 * kTriPerWave), kRasterStrideBlocks);
-    SM_LAUNCH(k_raster_group, dim3(blocks), dim3(256), 0, s, S, n_support, T, n_tris, W, H, D_it, counts);
+    const int32_t tuned = tuned_choice(kTuneRasterBlocks, W, H, 0);
+    return launch_raster_blocks(S, n_support, T, n_tris, W, H, D_it, s, counts,
+                                tuned > 0 ? tuned : kRasterStrideBlocks);
   } else if (n_tris < kGroupLayoutMinTris) {
     SM_LAUNCH(k_raster_wave, dim3(blocks_for(n_tris, 4)), dim3(256), 0, s, S, n_support, T, n_tris, W,
               H, D_it, counts);
@@ -1117,21 +1131,49 @@ int validate_pick_nw(int64_t (*waves)(int nw, void* ctx), void* ctx) {
   return nw;
 }
 
+namespace {
+std::mutex g_tune_m;
+std::map<std::tuple<int, int32_t, int32_t, int32_t>, int32_t> g_tune;
+}  // namespace
+
+int32_t tuned_choice(int kind, int32_t W, int32_t H, int32_t sz) {
+  std::lock_guard<std::mutex> lk(g_tune_m);
+  const auto it = g_tune.find(std::make_tuple(kind, W, H, sz));
+  return it == g_tune.end() ? -1 : it->second;
+}
+
+void set_tuned_choice(int kind, int32_t W, int32_t H, int32_t sz, int32_t value) {
+  std::lock_guard<std::mutex> lk(g_tune_m);
+  g_tune[std::make_tuple(kind, W, H, sz)] = value;
+}
+
 hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
                                 const float* D_it, int32_t W, int32_t H, const sm_params& p,
                                 int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f,
                                 uint64_t* cell_g, uint64_t* cell_b, uint8_t* mask,
                                 unsigned long long* n_valid, hipStream_t s) {
-  // smallest block (most rows per wave) whose grid still holds >= kValMinWaves waves
+  // a measured choice, else the smallest block (most rows per wave) whose grid still
+  // holds >= kValMinWaves waves
   struct Ctx {
     int32_t W, H, sz;
   } c{W, H, sz};
-  const int nw = validate_pick_nw(
-      [](int w, void* x) {
-        const Ctx& q = *(const Ctx*)x;
-        return (int64_t)validate_blocks(q.W, q.H, q.sz, w) * w;
-      },
-      &c);
+  int nw = tuned_choice(kTuneValidateWaves, W, H, sz);
+  if (nw < 0)
+    nw = validate_pick_nw(
+        [](int w, void* x) {
+          const Ctx& q = *(const Ctx*)x;
+          return (int64_t)validate_blocks(q.W, q.H, q.sz, w) * w;
+        },
+        &c);
+  return launch_validate_nw(cL, cR, omega, D_it, W, H, p, sz, C_it, D_f, C_f, cell_g, cell_b, mask, n_valid, nw, s);
+}
+
+hipError_t launch_validate_nw(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
+                              const float* D_it, int32_t W, int32_t H, const sm_params& p,
+                              int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f,
+                              uint64_t* cell_g, uint64_t* cell_b, uint8_t* mask,
+                              unsigned long long* n_valid, int nw, hipStream_t s) {
+  if (nw != 1 && nw != 2 && nw != 4 && nw != 8 && nw != 16) return hipErrorInvalidValue;
   const ValidateArgs a = validate_args(cL, cR, omega, D_it, W, H, p, sz, nw, C_it, D_f, C_f, cell_g, cell_b,
                                        mask, n_valid);
   dim3 grid(blocks_for(W, a.TW), blocks_for(H, a.TH));

@@ -97,6 +97,24 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
                                 uint64_t* cell_g, uint64_t* cell_b, uint8_t* mask,
                                 unsigned long long* n_valid, hipStream_t s);
 
+// Launch shapes measured by sm_autotune, consulted before the built-in rules (a choice
+// changes speed only: every shape gives the same outputs). Keys: the kernel, the frame
+// size and, for validation, the occupancy cell size.
+enum TuneKind { kTuneValidateWaves = 0, kTuneRasterBlocks = 1 };
+int32_t tuned_choice(int kind, int32_t W, int32_t H, int32_t sz);  // -1: none
+void set_tuned_choice(int kind, int32_t W, int32_t H, int32_t sz, int32_t value);
+// Validation with a given block size in waves (1, 2, 4, 8 or 16) instead of the rule.
+hipError_t launch_validate_nw(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
+                              const float* D_it, int32_t W, int32_t H, const sm_params& p,
+                              int32_t sz, uint8_t* C_it, float* D_f, uint8_t* C_f,
+                              uint64_t* cell_g, uint64_t* cell_b, uint8_t* mask,
+                              unsigned long long* n_valid, int nw, hipStream_t s);
+// Rasterisation with device counts (launch_raster's counts form) on at most max_blocks
+// workgroups.
+hipError_t launch_raster_blocks(const sm_support* S, int32_t n_support, const sm_tri* T, int32_t n_tris,
+                                int32_t W, int32_t H, float* D_it, hipStream_t s, const int32_t* counts,
+                                int32_t max_blocks);
+
 // Zero `bytes` bytes (a kernel, so the call is safe inside captured graphs).
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
