@@ -411,7 +411,10 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   unsigned long long* n_valid = (unsigned long long*)(base + Lo.counters + 32);
   // pinned staging: [counts | supports or triangles | exported mesh | mesh status]
   const MeshWork mw = Lo.mesh_on ? mesh_work_at(base + Lo.mwork, W, H, Lo.S_cap, Lo.mpcap) : MeshWork{};
-  const size_t st_main = align256(std::max((size_t)Lo.S_cap * sizeof(sm_support), (size_t)Lo.T_cap * sizeof(sm_tri)));
+  // (a device-mesh frame also reads its counters and status words back through this region)
+  const size_t st_span = Lo.mesh_on ? Lo.mstatus - Lo.counters + kMeshStatusWords * sizeof(int32_t) : 0;
+  const size_t st_main =
+      align256(std::max({(size_t)Lo.S_cap * sizeof(sm_support), (size_t)Lo.T_cap * sizeof(sm_tri), st_span}));
   const size_t st_mesh = Lo.mesh_on ? align256((size_t)mw.cap * 12) : 0;
   SM_TRY(ensure_pinned(c, 256 + st_main + 2 * st_mesh + kMeshStatusWords * sizeof(int32_t)));
   int32_t* h_count = (int32_t*)c.pinned;
