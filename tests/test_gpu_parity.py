@@ -208,6 +208,28 @@ def test_interpolate_parity_large_mesh():
     assert _interp_compare(S, shuffled, W, H) == 1.0
 
 
+def test_interpolate_parity_grid_65536_plus():
+    """More than 65536 triangles: a jittered 8-pixel grid split into two triangles per
+    cell, larger than the image so that the last columns and rows of triangles own
+    nothing, in canonical and in shuffled order."""
+    rng = np.random.default_rng(7)
+    g, nx, ny = 8, 212, 187
+    W, H = 1650, 1460
+    pts = [(4 + g * i + int(rng.integers(-1, 2)), 4 + g * j + int(rng.integers(-1, 2)))
+           for j in range(ny) for i in range(nx)]
+    S = [(u, v, float(np.float32(rng.uniform(0, 200)))) for (u, v) in pts]
+    tris = []
+    for j in range(ny - 1):
+        for i in range(nx - 1):
+            a = j * nx + i
+            tris += [(a, a + 1, a + nx), (a + 1, a + nx + 1, a + nx)]
+    assert len(tris) > 65536
+    _note("interpolate grid", len(tris))
+    assert _interp_compare(S, tris, W, H) == 1.0
+    shuffled = [tris[i] for i in rng.permutation(len(tris))]
+    assert _interp_compare(S, shuffled, W, H) == 1.0
+
+
 @pytest.mark.parametrize("many", [False, True])
 def test_interpolate_parity_extreme_edges(many):
     """Slivers across an 8192-column frame: edges with dy = 1 and dx ~ 8191 put the
