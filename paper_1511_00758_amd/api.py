@@ -26,8 +26,10 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else t.data_ptr()
 
 
-def _stream(stream=None):
+def _stream(stream=None, device_index=None):
     if stream is None:
+        if device_index is not None:  # the raw handle, without building a Stream object
+            return torch._C._cuda_getCurrentRawStream(device_index)
         stream = torch.cuda.current_stream()
     return stream.cuda_stream
 
@@ -184,13 +186,18 @@ class SolveResult:
     stats: Optional[dict]
 
 
+_STAGE_ITEMS = tuple(_lib.STAGES.items())
+
+
 def stats_dict(st: "_lib.SmStats", n_iters: int) -> dict:
+    us = st.stage_us[:]  # one conversion of each ctypes array
+    launches = st.stage_launches[:]
     return {
-        "n_support": list(st.n_support)[:n_iters],
-        "n_tris": list(st.n_tris)[:n_iters],
+        "n_support": st.n_support[:n_iters],
+        "n_tris": st.n_tris[:n_iters],
         "n_valid": int(st.n_valid),
-        "stage_us": {k: float(st.stage_us[i]) for k, i in _lib.STAGES.items()},
-        "stage_launches": {k: int(st.stage_launches[i]) for k, i in _lib.STAGES.items()},
+        "stage_us": {k: us[i] for k, i in _STAGE_ITEMS},
+        "stage_launches": {k: launches[i] for k, i in _STAGE_ITEMS},
         "mesh_device": int(st.mesh_device),
         "mesh_fallback": int(st.mesh_fallback),
     }
@@ -214,23 +221,28 @@ class Solver:
         self.D_f = torch.empty((H, W), dtype=torch.float32, device=device)
         self.C_f = torch.empty((H, W), dtype=torch.uint8, device=device)
         self.mask = torch.empty((H, W), dtype=torch.uint8, device=device)
+        self._out = (self.D_f.data_ptr(), self.C_f.data_ptr(), self.mask.data_ptr())
+        self._dev = self.D_f.device.index
+        self._shape = torch.Size((H, W))
         self.st = _lib.SmStats()
 
     def __call__(self, left: torch.Tensor, right: torch.Tensor, stats=False, timing=False,
                  stream=None) -> SolveResult:
         _require_cuda(left, right)
-        if left.shape != (self.H, self.W) or right.shape != (self.H, self.W):
+        if left.shape != self._shape or right.shape != self._shape:
             raise ValueError("image size differs from the solver's")
-        if left.stride(0) != right.stride(0):
+        if left.device.index != self._dev or right.device.index != self._dev:
+            raise ValueError("images on another device than the solver's")
+        pitch = left.stride(0)
+        if right.stride(0) != pitch:
             raise ValueError("left and right need the same row pitch")
         L = _lib.load()
         st = None
         if stats or timing:
             self.st.timing = _lib.timing_flag(timing)
             st = self.st
-        check(L.sm_solve(left.data_ptr(), right.data_ptr(), self.W, self.H, left.stride(0), self.p,
-                         self.ws_ptr, self.ws_bytes, self.D_f.data_ptr(), self.C_f.data_ptr(),
-                         self.mask.data_ptr(), st, _stream(stream)))
+        check(L.sm_solve(left.data_ptr(), right.data_ptr(), self.W, self.H, pitch, self.p,
+                         self.ws_ptr, self.ws_bytes, *self._out, st, _stream(stream, self._dev)))
         return SolveResult(self.D_f, self.C_f, self.mask,
                            stats_dict(st, self.p.n_iters) if st is not None else None)
 
