@@ -446,8 +446,9 @@ __device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, 
   }
 
   // output: live solid records as triangles, and the hints of the next tessellation (the
-  // walks of this one are over). Each thread has kOutBatch records in flight; one atomic
-  // per wave reserves their slots.
+  // walks of this one are over). Each thread has kOutBatch records in flight, state and
+  // vertices loaded at once (an index past the records reads record 0, not output); one
+  // atomic per wave reserves their slots.
   const bool hints = a.last == 0;
   if (hints)
     for (int32_t c = tid; c < gw * gh; c += kMeshThreads) w.hint[c] = -1;
@@ -457,10 +458,17 @@ __device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, 
     const int32_t t0 = base + tid;
     unsigned outm = 0;  // bit b: record t0 + b * kMeshThreads is output
     int any = -1;
+    int32_t dd[kOutBatch], ov0[kOutBatch], ov1[kOutBatch], ov2[kOutBatch];
+#pragma unroll
+    for (int b = 0; b < kOutBatch; ++b) {
+      const int32_t t = t0 + b * kMeshThreads, tc = t < n_rec ? t : 0;
+      dd[b] = w.dead[tc];
+      ov0[b] = w.tv[3 * tc], ov1[b] = w.tv[3 * tc + 1], ov2[b] = w.tv[3 * tc + 2];
+    }
 #pragma unroll
     for (int b = 0; b < kOutBatch; ++b) {
       const int32_t t = t0 + b * kMeshThreads;
-      const bool out = t < n_rec && !w.dead[t] && w.tv[3 * t + 2] != kGhost;
+      const bool out = t < n_rec && !dd[b] && ov2[b] != kGhost;
       outm |= (unsigned)out << b;
       if (out) any = t;
     }
@@ -478,9 +486,13 @@ __device__ __forceinline__ void mesh_insert_block(const MeshJob& a, int32_t p0, 
     if (has && lane == __ffsll((long long)has) - 1) atomicMax(&s_next_any, any);
 #pragma nounroll
     for (int b = 0; b < kOutBatch; ++b) {
+      // record b's vertices sit in slot 0: the arrays shift down one slot per step, so that
+      // every index is a constant and they stay in registers
+      const int32_t v0 = ov0[0], v1 = ov1[0], v2 = ov2[0];
+#pragma unroll
+      for (int k = 0; k + 1 < kOutBatch; ++k) ov0[k] = ov0[k + 1], ov1[k] = ov1[k + 1], ov2[k] = ov2[k + 1];
       if (!(outm >> b & 1u)) continue;
       const int32_t t = t0 + b * kMeshThreads;
-      const int32_t v0 = w.tv[3 * t], v1 = w.tv[3 * t + 1], v2 = w.tv[3 * t + 2];
       if (slot < a.T_cap) a.T[slot] = top_first3<DA>(m, v0, v1, v2);
       else DA::fail(&s_err, kErrCapacity);
       ++slot;
