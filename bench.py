@@ -337,6 +337,33 @@ def batched_runs(api, vga_frames, vga_params, workers=16, batches=12, dev="cuda:
     out["batch64_mixed_stage_batched"] = run_many(mixed, batches)
     out["vga_20planes_batch64_graph"] = run_graph(vga, batches)
     out["batch64_mixed_graph"] = run_graph(mixed, batches)
+
+    # 256 frames: one mesh workgroup per frame fills all 256 CUs; three frames of the
+    # replayed batch are compared with the per-frame solver
+    vga256 = [(d[i % len(d)][0], d[i % len(d)][1], vga_params) for i in range(256)]
+    ms = api.ManySolver(workers, device=dev)
+    outs, graph = ms.capture(vga256)
+    try:
+        graph.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(batches):
+            graph.run(stats=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        solo = api.Solver(640, 480, vga_params, device=dev)
+        same = True
+        for i in (0, 101, 255):
+            r = solo(vga256[i][0], vga256[i][1])
+            torch.cuda.synchronize()
+            same = same and bool(torch.equal(r.D_f, outs[i][0]) and torch.equal(r.C_f, outs[i][1])
+                                 and torch.equal(r.mask, outs[i][2]))
+    finally:
+        graph.close()
+    out["vga_20planes_batch256_graph"] = {
+        "frames_per_s": round(batches * 256 / dt, 1), "mpx_per_s": round(batches * 256 * 640 * 480 / dt / 1e6, 2),
+        "ms_per_batch": round(dt / batches * 1e3, 3), "frames_per_batch": 256,
+        "sampled_frames_equal_solo": same}
     return out
 
 
