@@ -72,3 +72,30 @@ def test_graph_capture_needs_device_meshes():
     frames = [(_dev(l), _dev(r), dict(prm, host_mesh=i)) for i, (l, r, prm) in enumerate(mixed)]
     with pytest.raises(_lib.StereoMeshError):
         api.ManySolver(device=DEV).capture(frames)
+
+
+def test_graph_256_frames_sampled():
+    """A batch of 256 frames of the 640x480 workload (8 scenes cycled), as many mesh
+    workgroups as the chip has CUs; two replays, sampled frames and the valid-pixel total
+    against the per-frame solver."""
+    from paper_1511_00758_amd import api
+    scs = [scenes.make_scene(2, scenes.seed_of(2, f)) for f in range(8)]
+    pairs = [(_dev(sc.left), _dev(sc.right)) for sc in scs]
+    frames = [(pairs[i % 8][0], pairs[i % 8][1], scs[i % 8].params) for i in range(256)]
+    solo = [_solo(sc.left, sc.right, sc.params) for sc in scs]
+    _note("capture 256 frames")
+    outs, graph = api.ManySolver(device=DEV).capture(frames)
+    try:
+        for rep in range(2):
+            st = graph.run(stats=True)
+            torch.cuda.synchronize()
+            assert st["mesh_fallback"] == 0
+            assert st["n_valid"] == 32 * sum(int(m.sum()) for (_, _, m) in solo)
+            for i in (0, 9, 130, 255):
+                D, C, M = outs[i]
+                sD, sC, sM = solo[i % 8]
+                assert (D.cpu().numpy().view(np.uint32) == sD.view(np.uint32)).all(), (rep, i)
+                assert (C.cpu().numpy() == sC).all(), (rep, i)
+                assert (M.cpu().numpy() == sM).all(), (rep, i)
+    finally:
+        graph.close()
