@@ -9,8 +9,10 @@
  *   caller; the library keeps no pointer after a call returns, but work it enqueued
  *   reads and writes the buffers until the stream has been synchronised.
  * - `stream` is a hipStream_t passed as void* (NULL = the null stream). Calls are
- *   asynchronous on that stream except sm_triangulate (host only) and sm_solve
- *   (which synchronises the stream once per triangulation).
+ *   asynchronous on that stream except sm_triangulate (host only) and the solves:
+ *   sm_solve synchronises the stream once per frame when every tessellation runs on
+ *   the device (the default), once per tessellation with host meshes; the batched
+ *   solves and the autotuner return when their work is done.
  * - Images are row-major uint8 with a row pitch `stride` >= W bytes; every per-pixel
  *   output array is row-major with pitch W elements.
  * - Every argument is checked before anything is enqueued; a violation returns
@@ -79,9 +81,10 @@ typedef struct {
   int32_t fast_per_bin;        /* FAST: at most this many keypoints per bin, 1..4096;
                                   fast_bins_x * fast_bins_y * fast_per_bin <= 2^22            */
   int32_t levels;              /* disparity levels tested by cost evaluation: 1 (Alg. 2), 3, 5 */
-  int32_t host_mesh;           /* sm_solve: 0 = the tessellations after the first insert the new
-                                  supports into the mesh kept in device memory (the first one,
-                                  and any the device cannot finish, run on the host); 1 = every
+  int32_t host_mesh;           /* 0 = every tessellation on the device: the first mesh is built
+                                  there from the matched supports and each later tessellation
+                                  inserts the resampled supports into it (a frame the device
+                                  cannot finish is solved again with host meshes); 1 = every
                                   tessellation on the host. Same triangles either way.        */
 } sm_params;
 
@@ -100,7 +103,7 @@ typedef enum {
   SM_ST_VALIDATE = 4,        /* cost evaluation + refinement                                 */
   SM_ST_REMATCH = 5,         /* resampling: cells -> confident supports + re-matched pixels  */
   SM_ST_FAST = 6,            /* FAST scores + per-bin keypoint selection (support_mode 1)     */
-  SM_ST_MESH = 7,            /* device Delaunay insertion of resampled supports (iters >= 2)   */
+  SM_ST_MESH = 7,            /* device Delaunay tessellations (first mesh and insertions)     */
   SM_ST_HOST_TRI = 12,       /* host triangulation (wall time)                               */
   SM_ST_HOST_COPY = 13,      /* host<->device copies and waits (wall time)                   */
   SM_ST_TOTAL = 14           /* whole sm_solve call (wall time)                              */

@@ -34,16 +34,82 @@ def _stream(stream=None, device_index=None):
     return stream.cuda_stream
 
 
-def _require_cuda(*ts):
-    for t in ts:
-        if t is not None and (not t.is_cuda or not t.is_contiguous()):
-            raise ValueError("expected contiguous CUDA (HIP) tensors")
+# Argument checks run before any pointer reaches the library: the kernels trust the
+# sizes they are given, so a tensor of the wrong dtype, shape or device would be read or
+# written out of bounds. ``dev_type`` is "cuda" in use; the CPU tests pass "cpu" to
+# exercise the same checks without a GPU.
+def check_tensor(t, name, dtype, shape=None, device=None, dev_type="cuda", min_numel=None):
+    """Raises ValueError unless ``t`` is a contiguous tensor of ``dtype`` (and ``shape``,
+    on ``device``, with at least ``min_numel`` elements, when given)."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.device.type != dev_type:
+        raise ValueError(f"{name}: expected a {dev_type} tensor, got one on {t.device}")
+    if device is not None and t.device != torch.device(device):
+        raise ValueError(f"{name}: on {t.device}, expected {torch.device(device)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name}: {t.numel()} elements, need at least {min_numel}")
+
+
+def check_image(t, name="image", shape=None, device=None, dev_type="cuda"):
+    """A uint8 [H, W] image (3 <= W, H <= 8192), contiguous, on ``device`` when given."""
+    if isinstance(t, torch.Tensor) and t.dim() != 2:
+        raise ValueError(f"{name}: expected a 2-D [H, W] image, got shape {tuple(t.shape)}")
+    check_tensor(t, name, torch.uint8, shape, device, dev_type)
+    H, W = t.shape
+    if not (3 <= W <= 8192 and 3 <= H <= 8192):
+        raise ValueError(f"{name}: size {W}x{H} outside [3, 8192]^2")
+
+
+def check_pair(left, right, device=None, dev_type="cuda"):
+    """Left and right uint8 images of one size on one device; returns (H, W)."""
+    check_image(left, "left", None, device, dev_type)
+    check_image(right, "right", tuple(left.shape), left.device if device is None else device, dev_type)
+    return tuple(left.shape)
+
+
+def check_outputs(D, C, M, shape, device, dev_type="cuda"):
+    """Caller-given outputs of one frame: D_f float32, C_f and mask uint8, all [H, W]."""
+    check_tensor(D, "D_f", torch.float32, shape, device, dev_type)
+    check_tensor(C, "C_f", torch.uint8, shape, device, dev_type)
+    check_tensor(M, "mask", torch.uint8, shape, device, dev_type)
+
+
+def check_frames(frames, outs, dev_type="cuda"):
+    """A batch: one output triple per frame, each frame's images and outputs of one size
+    and on one device."""
+    if len(outs) != len(frames):
+        raise ValueError(f"{len(outs)} output triples for {len(frames)} frames")
+    for i, ((l, r, prm), o) in enumerate(zip(frames, outs)):
+        try:
+            shape = check_pair(l, r, None, dev_type)
+            if not isinstance(prm, dict):
+                raise ValueError("parameters must be a dict")
+            if len(o) != 3:
+                raise ValueError("outputs must be (D_f, C_f, mask)")
+            check_outputs(*o, shape, l.device, dev_type)
+        except ValueError as e:
+            raise ValueError(f"frame {i}: {e}") from None
+
+
+def check_census_pair(cL, cR, dev_type="cuda"):
+    """Census words of the left and right image: int64 [H, W], one size, one device."""
+    if isinstance(cL, torch.Tensor) and cL.dim() != 2:
+        raise ValueError(f"cL: expected [H, W] census words, got shape {tuple(cL.shape)}")
+    check_tensor(cL, "cL", torch.int64, None, None, dev_type)
+    check_tensor(cR, "cR", torch.int64, tuple(cL.shape), cL.device, dev_type)
 
 
 def census(img: torch.Tensor, census_w: int, census_h: int, grad_thr: int = 0,
            with_omega: bool = True, stream=None):
     """Census words (int64 bit patterns) and Omega_I (uint8) of a uint8 [H, W] image."""
-    _require_cuda(img)
+    check_image(img, "img")
     H, W = img.shape
     words = torch.empty((H, W), dtype=torch.int64, device=img.device)
     omega = torch.empty((H, W), dtype=torch.uint8, device=img.device) if with_omega else None
@@ -72,8 +138,12 @@ def match_support(cL, cR, omega, params: dict, cand_uv=None, stream=None, n_cand
     """Matched supports: (device buffer, device int32 count). ``cand_uv`` is an (n, 2)
     int16 array or device tensor of (u, v) candidates (the first ``n_cand`` rows when
     given), or None for the support grid."""
-    _require_cuda(cL, cR, omega)
+    check_census_pair(cL, cR)
     H, W = cL.shape
+    if omega is not None:
+        check_tensor(omega, "omega", torch.uint8, (H, W), cL.device)
+    elif cand_uv is None:
+        raise ValueError("omega is required for grid candidates")
     p = make_params(params)
     L = _lib.load()
     cand = None
@@ -85,6 +155,8 @@ def match_support(cL, cR, omega, params: dict, cand_uv=None, stream=None, n_cand
         else:
             cand = torch.from_numpy(np.ascontiguousarray(cand_uv, dtype=np.int16).reshape(-1, 2)).to(cL.device)
         n = cand.shape[0] if n_cand is None else int(n_cand)
+        if not 0 <= n <= cand.shape[0]:
+            raise ValueError(f"n_cand {n} outside [0, {cand.shape[0]}]")
     else:
         n = L.sm_grid_candidates(W, H, p.support_step)
     out = new_support_buffer(n, cL.device)
@@ -97,7 +169,7 @@ def match_support(cL, cR, omega, params: dict, cand_uv=None, stream=None, n_cand
 def fast_candidates(img, params: dict, stream=None):
     """FAST keypoints sampled from spatial bins: (score uint8 [H, W], candidates int16
     [cap, 2] with the first n valid, device int32 n)."""
-    _require_cuda(img)
+    check_image(img, "img")
     H, W = img.shape
     p = make_params(params)
     L = _lib.load()
@@ -130,7 +202,14 @@ def ctypes_int():
 def interpolate(S_dev: torch.Tensor, n_support: int, tris: np.ndarray, W: int, H: int,
                 stream=None) -> torch.Tensor:
     """D_it (float32 [H, W], NaN outside the mesh) from device supports and host triangles."""
-    T = torch.from_numpy(np.ascontiguousarray(tris, dtype=np.int32).reshape(-1)).to(S_dev.device)
+    n_support = int(n_support)
+    if not (3 <= W <= 8192 and 3 <= H <= 8192):
+        raise ValueError(f"size {W}x{H} outside [3, 8192]^2")
+    tri_arr = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    if tri_arr.size and (tri_arr.min() < 0 or tri_arr.max() >= n_support):
+        raise ValueError(f"triangle indices must lie in [0, {n_support})")
+    check_tensor(S_dev, "S_dev", torch.uint8, min_numel=8 * n_support)
+    T = torch.from_numpy(tri_arr.reshape(-1)).to(S_dev.device)
     n_tris = int(T.numel() // 3)
     D = torch.empty((H, W), dtype=torch.float32, device=S_dev.device)
     L = _lib.load()
@@ -145,12 +224,16 @@ def validate(cL, cR, omega, D_it, params: dict, sz_occ: int, D_f, C_f, want_C_it
              stream=None):
     """Cost evaluation + refinement; returns (C_it or None, cell_g, cell_b). D_f, C_f are
     updated in place."""
-    _require_cuda(cL, cR, omega, D_it, D_f, C_f)
+    check_census_pair(cL, cR)
     H, W = cL.shape
+    dev = cL.device
+    check_tensor(omega, "omega", torch.uint8, (H, W), dev)
+    check_tensor(D_it, "D_it", torch.float32, (H, W), dev)
+    check_tensor(D_f, "D_f", torch.float32, (H, W), dev)
+    check_tensor(C_f, "C_f", torch.uint8, (H, W), dev)
     p = make_params(params)
     L = _lib.load()
     n_cells = L.sm_cells(W, H, sz_occ)
-    dev = cL.device
     C_it = torch.empty((H, W), dtype=torch.uint8, device=dev) if want_C_it else None
     cell_g = torch.empty(n_cells, dtype=torch.int64, device=dev)
     cell_b = torch.empty(n_cells, dtype=torch.int64, device=dev)
@@ -163,12 +246,18 @@ def validate(cL, cR, omega, D_it, params: dict, sz_occ: int, D_f, C_f, want_C_it
 def resample(cL, cR, D_it, cell_g, cell_b, params: dict, sz_occ: int, S_dev, n_S: int,
              stream=None):
     """New supports of Alg. 4: (device buffer, device int32 count)."""
-    _require_cuda(cL, cR, D_it, cell_g, cell_b, S_dev)
+    check_census_pair(cL, cR)
     H, W = cL.shape
+    dev = cL.device
     p = make_params(params)
     L = _lib.load()
-    cap = 2 * L.sm_cells(W, H, sz_occ)
-    dev = cL.device
+    n_cells = L.sm_cells(W, H, sz_occ)
+    n_S = int(n_S)
+    check_tensor(D_it, "D_it", torch.float32, (H, W), dev)
+    check_tensor(cell_g, "cell_g", torch.int64, None, dev, min_numel=n_cells)
+    check_tensor(cell_b, "cell_b", torch.int64, None, dev, min_numel=n_cells)
+    check_tensor(S_dev, "S_dev", torch.uint8, None, dev, min_numel=8 * max(n_S, 0))
+    cap = 2 * n_cells
     out = new_support_buffer(cap, dev)
     occ = torch.empty((H, W), dtype=torch.uint8, device=dev)
     n_out = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -228,14 +317,9 @@ class Solver:
 
     def __call__(self, left: torch.Tensor, right: torch.Tensor, stats=False, timing=False,
                  stream=None) -> SolveResult:
-        _require_cuda(left, right)
-        if left.shape != self._shape or right.shape != self._shape:
-            raise ValueError("image size differs from the solver's")
-        if left.device.index != self._dev or right.device.index != self._dev:
-            raise ValueError("images on another device than the solver's")
+        check_image(left, "left", self._shape, self.D_f.device)
+        check_image(right, "right", self._shape, self.D_f.device)
         pitch = left.stride(0)
-        if right.stride(0) != pitch:
-            raise ValueError("left and right need the same row pitch")
         L = _lib.load()
         st = None
         if stats or timing:
@@ -250,9 +334,8 @@ class Solver:
         """Measures the tunable launch shapes on this frame (``sm_autotune``) and records the
         fastest for this size; later solves of the size use them (outputs do not change).
         Returns the choices; D_f, C_f and mask hold the frame's results."""
-        _require_cuda(left, right)
-        if left.shape != (self.H, self.W) or right.shape != (self.H, self.W):
-            raise ValueError("image size differs from the solver's")
+        check_image(left, "left", self._shape, self.D_f.device)
+        check_image(right, "right", self._shape, self.D_f.device)
         L = _lib.load()
         ch = (ctypes.c_int32 * 9)()
         check(L.sm_autotune(left.data_ptr(), right.data_ptr(), self.W, self.H, left.stride(0), self.p,
@@ -305,11 +388,9 @@ class BatchSolver:
                 outs.append((torch.empty((H, W), dtype=torch.float32, device=l.device),
                              torch.empty((H, W), dtype=torch.uint8, device=l.device),
                              torch.empty((H, W), dtype=torch.uint8, device=l.device)))
+        check_frames(frames, outs)
         for i, ((l, r, prm), (D, C, M)) in enumerate(zip(frames, outs)):
-            _require_cuda(l, r, D, C, M)
             H, W = l.shape
-            if r.shape != l.shape or r.stride(0) != l.stride(0):
-                raise ValueError("left and right must have the same shape and pitch")
             f = arr[i]
             f.L, f.R, f.W, f.H, f.stride = l.data_ptr(), r.data_ptr(), W, H, l.stride(0)
             f.p = make_params(prm)
@@ -345,11 +426,9 @@ class ManySolver:
     def _frames(self, frames, outs):
         n = len(frames)
         arr = (_lib.SmFrame * max(n, 1))()
+        check_frames(frames, outs)
         for i, ((l, r, prm), (D, C, M)) in enumerate(zip(frames, outs)):
-            _require_cuda(l, r, D, C, M)
             H, W = l.shape
-            if r.shape != l.shape or r.stride(0) != l.stride(0):
-                raise ValueError("left and right must have the same shape and pitch")
             f = arr[i]
             f.L, f.R, f.W, f.H, f.stride = l.data_ptr(), r.data_ptr(), W, H, l.stride(0)
             f.p = make_params(prm)

@@ -117,17 +117,28 @@ __host__ __device__ inline int32_t orient(P2 a, P2 b, P2 q) {
 // non-vanishing derivative with respect to the perturbed heights, highest priority (the
 // smallest raster position (v, u)) first: d/dz_a = +orient(b, c, d), d/dz_b = -orient(a, c, d),
 // d/dz_c = +orient(a, b, d), d/dz_d = -orient(a, b, c).
+// Floating-point filter of the in-circle determinant: +1 or -1 when the double evaluation
+// proves the sign, 0 when the exact evaluation is needed. Error bound for coordinates in
+// [0, 8191] (differences below 2^13): the lifted lengths (< 2^27), the products of a
+// difference and a length (< 2^40), the 2x2 minors (< 2^41) and the orientation minor
+// (< 2^27) are exact integers in double; each of the three final products is below
+// 4 * 8191^4 < 2^54 and rounds by at most 1; their first sum is below 2^55 and rounds by
+// at most 2, the second below 2^56 and rounds by at most 4. The computed value is thus
+// within 9 of the exact determinant, and a threshold of 64 leaves a wide margin.
+__host__ __device__ inline int incircle_filter(P2 a, P2 b, P2 c, P2 d) {
+  const double fadx = a.x - d.x, fady = a.y - d.y, fbdx = b.x - d.x, fbdy = b.y - d.y;
+  const double fcdx = c.x - d.x, fcdy = c.y - d.y;
+  const double fal = fadx * fadx + fady * fady, fbl = fbdx * fbdx + fbdy * fbdy;
+  const double fcl = fcdx * fcdx + fcdy * fcdy;
+  const double fdet = fadx * (fbdy * fcl - fcdy * fbl) - fady * (fbdx * fcl - fcdx * fbl) +
+                      fal * (fbdx * fcdy - fcdx * fbdy);
+  if (fdet > 64.0) return 1;
+  if (fdet < -64.0) return -1;
+  return 0;
+}
+
 __host__ __device__ inline int incircle_sos(P2 a, P2 b, P2 c, P2 d) {
-  {  // filter: in double the minors are exact (< 2^41) and the determinant is off by <= 7
-    const double fadx = a.x - d.x, fady = a.y - d.y, fbdx = b.x - d.x, fbdy = b.y - d.y;
-    const double fcdx = c.x - d.x, fcdy = c.y - d.y;
-    const double fal = fadx * fadx + fady * fady, fbl = fbdx * fbdx + fbdy * fbdy;
-    const double fcl = fcdx * fcdx + fcdy * fcdy;
-    const double fdet = fadx * (fbdy * fcl - fcdy * fbl) - fady * (fbdx * fcl - fcdx * fbl) +
-                        fal * (fbdx * fcdy - fcdx * fbdy);
-    if (fdet > 64.0) return 1;
-    if (fdet < -64.0) return -1;
-  }
+  if (const int f = incircle_filter(a, b, c, d)) return f;
   const int64_t adx = a.x - d.x, ady = a.y - d.y;
   const int64_t bdx = b.x - d.x, bdy = b.y - d.y;
   const int64_t cdx = c.x - d.x, cdy = c.y - d.y;

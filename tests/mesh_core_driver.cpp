@@ -9,6 +9,8 @@
 //
 // stdin:  W H n_batches mode, then per batch: count, then count lines "u v"
 // stdout: per batch: "batch k n_tris status", then n_tris lines "i0 i1 i2" (sorted)
+// Mode 3 checks the predicates instead: n_batches lines of four points (a, b, c, d); each
+// output line holds the in-circle filter's verdict and the perturbed in-circle sign.
 #define __host__
 #define __device__
 #include <algorithm>
@@ -55,6 +57,15 @@ struct Arrays {
 int main() {
   int W, H, nb, mode;
   if (scanf("%d %d %d %d", &W, &H, &nb, &mode) != 4) return 2;
+  if (mode == 3) {  // predicates: nb lines "ax ay bx by cx cy dx dy" -> "filter sos"
+    for (int k = 0; k < nb; ++k) {
+      P2 q[4];
+      for (auto& p : q)
+        if (scanf("%d %d", &p.x, &p.y) != 2) return 2;
+      printf("%d %d\n", incircle_filter(q[0], q[1], q[2], q[3]), incircle_sos(q[0], q[1], q[2], q[3]));
+    }
+    return 0;
+  }
   std::vector<sm_support> S;
   std::vector<std::pair<int32_t, int32_t>> range;
   for (int b = 0; b < nb; ++b) {

@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 import torch
 
-import oracle
 import scenes
+from oracle_cache import assert_equals_oracle
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -74,16 +74,17 @@ def test_batch_equals_solo(mixed, workers):
 
 
 def test_batch_against_oracle(mixed):
+    """Frames of the concurrent batch against the oracle, the 1280x720 pair with
+    disparities 0-255 included."""
     from paper_1511_00758_amd import api
-    sub = [mixed[0], mixed[1], mixed[7]]
-    bs = api.BatchSolver(3, 320, 240, [f[2] for f in sub], device=DEV)
+    sub = [mixed[0], mixed[1], mixed[6], mixed[7]]
+    assert sub[2][0].shape == (720, 1280) and sub[2][2]["d_max"] == 255
+    bs = api.BatchSolver(3, 1280, 720, [f[2] for f in sub], device=DEV)
     outs = bs([(_dev(l), _dev(r), prm) for (l, r, prm) in sub])
     torch.cuda.synchronize()
     for (l, r, prm), (D, C, M) in zip(sub, outs):
-        ref = oracle.solve(l, r, oracle.Params.from_dict(prm))
-        assert (C.cpu().numpy() == ref["C_f"]).all()
-        assert (M.cpu().numpy().astype(bool) == ref["mask"]).all()
-        assert (D.cpu().numpy().view(np.uint32) == ref["D_f"].view(np.uint32)).all()
+        _note("batch vs oracle", l.shape, prm["d_max"])
+        assert_equals_oracle(D, C, M, l, r, prm, f"(sm_solve_batch, {l.shape})")
 
 
 def test_batch_rejects_bad_frames_before_work(mixed):

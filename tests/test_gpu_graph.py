@@ -1,7 +1,8 @@
 """GPU: a stage-batched solve captured into a HIP graph (sm_solve_many_capture) and replayed
 (sm_many_graph_run). Every replay -- with new image contents copied into the captured input
 buffers, and eager work and synchronisations between the replays -- gives for every frame
-exactly what sm_solve gives for that frame alone."""
+exactly what sm_solve gives for that frame alone, and one frame of every replay equals
+the oracle."""
 import sys
 
 import numpy as np
@@ -9,6 +10,7 @@ import pytest
 import torch
 
 import scenes
+from oracle_cache import assert_equals_oracle
 from test_gpu_many import _mixed, _solo
 
 pytestmark = pytest.mark.gpu
@@ -26,6 +28,8 @@ def _dev(a):
 # image contents of the successive runs: rows are independent epipolar lines, so flipping
 # both images upside down or shifting both by whole columns gives valid pairs of the same size
 _VIEWS = [lambda a: a, np.flipud, lambda a: np.roll(a, 7, axis=1), lambda a: a]
+# the frame of each run that is also compared with the oracle
+_ORACLE_FRAME = [5, 0, 3, 7]
 
 
 def test_graph_replays_equal_solo():
@@ -52,6 +56,11 @@ def test_graph_replays_equal_solo():
                 torch.cuda.synchronize()
             else:
                 st = None
+            # one frame of every run against the oracle (the 1280x720, d 0-255 pair first)
+            i_or = _ORACLE_FRAME[k]
+            l, r, prm = mixed[i_or]
+            _note("replay", k, "frame", i_or, l.shape, "vs oracle")
+            assert_equals_oracle(*outs[i_or], view(l), view(r), prm, f"(graph run {k}, frame {i_or})")
             total = 0
             for i, ((l, r, prm), (D, C, M)) in enumerate(zip(mixed, outs)):
                 sD, sC, sM = _solo(view(l), view(r), prm)

@@ -5,27 +5,18 @@ triangulation of the first batch, and the triangle list after every batch must e
 the oracle's triangulation of all points so far. Covers random sets, lattices (many
 co-circular quadruples: the tie-break of the perturbed in-circle test), points on hull
 edges, duplicates of mesh vertices and several batches."""
-import os
-import shutil
-import subprocess
-
 import numpy as np
 import pytest
 
 import oracle
-
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-CSRC = os.path.join(ROOT, "paper_1511_00758_amd", "csrc")
+from mesh_driver_build import build_driver, run_driver
 
 
 @pytest.fixture(scope="module")
 def driver(tmp_path_factory):
-    if shutil.which("g++") is None:
+    out = build_driver(tmp_path_factory.mktemp("mesh_core"))
+    if out is None:
         pytest.skip("g++ not available")
-    out = str(tmp_path_factory.mktemp("mesh_core") / "mesh_core_driver")
-    cmd = ["g++", "-O2", "-std=c++17", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
-           os.path.join(ROOT, "tests", "mesh_core_driver.cpp"), os.path.join(CSRC, "delaunay.cpp"), "-o", out]
-    subprocess.run(cmd, check=True, capture_output=True)
     return out
 
 
@@ -34,8 +25,7 @@ def _run(driver, W, H, batches, mode=0):
     for b in batches:
         lines.append(str(len(b)))
         lines += [f"{u} {v}" for (u, v) in b]
-    res = subprocess.run([driver], input="\n".join(lines) + "\n", capture_output=True, text=True, check=True)
-    it = iter(res.stdout.split("\n"))
+    it = iter(run_driver(driver, "\n".join(lines) + "\n").split("\n"))
     out = []
     for _ in batches:
         head = next(it).split()
