@@ -213,6 +213,167 @@ Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
   return L;
 }
 
+namespace {
+
+// Device buffers of one frame inside an sm_solve workspace.
+struct FrameBufs {
+  uint64_t *cL, *cR;
+  uint8_t *omega, *occ;
+  float* D_it;
+  uint64_t *cell_g, *cell_b;
+  sm_support* S;
+  sm_tri* T;
+  int32_t* counters;
+  unsigned long long* n_valid;  // 32 bytes into the counters
+  int32_t* mstatus;             // device mesh status words (nullptr without a device mesh)
+  MeshWork mw;
+};
+
+FrameBufs frame_bufs(uint8_t* base, int32_t W, int32_t H, const Layout& Lo) {
+  FrameBufs b;
+  b.cL = (uint64_t*)(base + Lo.cL);
+  b.cR = (uint64_t*)(base + Lo.cR);
+  b.omega = base + Lo.omega;
+  b.occ = base + Lo.occ;
+  b.D_it = (float*)(base + Lo.D_it);
+  b.cell_g = (uint64_t*)(base + Lo.cell_g);
+  b.cell_b = (uint64_t*)(base + Lo.cell_b);
+  b.S = (sm_support*)(base + Lo.S);
+  b.T = (sm_tri*)(base + Lo.T);
+  b.counters = (int32_t*)(base + Lo.counters);
+  b.n_valid = (unsigned long long*)(base + Lo.counters + 32);
+  b.mstatus = Lo.mesh_on ? (int32_t*)(base + Lo.mstatus) : nullptr;
+  b.mw = Lo.mesh_on ? mesh_work_at(base + Lo.mwork, W, H, Lo.S_cap, Lo.mpcap) : MeshWork{};
+  return b;
+}
+
+// Census of both images fused with the per-frame initialisation (D_f = 0, C_f = t_hi as
+// Alg. 1 starts, occupancy cleared, D_it = NaN -- coverage only grows over the
+// iterations, S_it being a subset of S_it+1, so one fill per frame suffices -- the
+// support-grid candidate slots and the counters), the FAST candidates when asked, and
+// S_1 = SparseStereo over the candidates; the match count lands in the slot after the
+// candidates, so that one copy brings both back. `compact` also compacts the matches
+// (the device-mesh path compacts them inside its first mesh kernel instead).
+sm_status enqueue_census_match(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
+                               const sm_params& p, const Layout& Lo, uint8_t* base, const FrameBufs& b,
+                               float* D_f, uint8_t* C_f, bool compact, Timer& tm, hipStream_t s) {
+  CensusJob jobs[2] = {{L, stride, b.cL, b.omega}, {R, stride, b.cR, nullptr}};
+  const bool fast = p.support_mode == 1;
+  CensusExtras ex;
+  ex.D_nan = b.D_it;
+  ex.grid_slots = fast ? nullptr : b.S;
+  ex.step = p.support_step;
+  ex.gw = Lo.n_grid > 0 ? (W - 1 - p.support_step / 2) / p.support_step + 1 : 0;
+  ex.zero = b.counters;
+  ex.n_zero = 16;
+  SM_TRY(tm.begin(SM_ST_CENSUS));
+  SM_HIP(launch_census(jobs, 2, W, H, p.census_w, p.census_h, p.grad_thr, D_f, C_f, p.t_hi, b.occ, &ex, s));
+  SM_TRY(tm.end());
+  if (fast) {  // FAST keypoints from spatial bins as the candidates (Sec. III-A)
+    SM_TRY(tm.begin(SM_ST_FAST));
+    SM_HIP(launch_fast_score(L, stride, W, H, base + Lo.score, s));
+    SM_TRY(tm.end());
+    SM_TRY(tm.begin(SM_ST_FAST));
+    SM_HIP(launch_fast_select(base + Lo.score, W, H, p, b.S, nullptr, s));
+    SM_TRY(tm.end());
+  }
+  SM_TRY(tm.begin(SM_ST_MATCH));
+  SM_HIP(launch_match(b.cL, b.cR, W, H, p, b.S, Lo.n_grid, s));
+  SM_TRY(tm.end());
+  if (compact) {
+    SM_TRY(tm.begin(SM_ST_COMPACT));
+    SM_HIP(launch_compact(b.S, Lo.n_grid, &b.counters[0], b.occ, W, (int32_t*)(b.S + Lo.n_grid), s));
+    SM_TRY(tm.end());
+  }
+  return SM_OK;
+}
+
+// The rest of a frame whose every tessellation runs on the device (grid candidates: the
+// compacted supports are in raster order, the first mesh is built on the device and every
+// later tessellation inserts into it, each mesh kernel first compacting its new supports).
+// The counts stay on the device (read by the raster, resampling and mesh kernels), so
+// nothing here waits for the device; the caller reads the counters and status words back.
+sm_status enqueue_device_meshes(const sm_params& p, int32_t W, int32_t H, const Layout& Lo, const FrameBufs& b,
+                                float* D_f, uint8_t* C_f, uint8_t* mask, Timer& tm, hipStream_t s) {
+  auto mesh_job = [&](int32_t start, int32_t p0, const int32_t* n_new) {
+    MeshJob job;
+    job.S = b.S;
+    job.start = start;
+    job.p0 = p0;
+    job.n_new = n_new;
+    job.init_tv = b.mw.tv;
+    job.init_tnb = b.mw.tnb;
+    job.init_n = 0;
+    job.n_new_slot = 0;
+    job.last = 0;
+    job.compact_n = 0;
+    job.occ = nullptr;
+    job.compact_count = nullptr;
+    job.status = b.mstatus;
+    job.status_copy = nullptr;
+    job.T = b.T;
+    job.T_cap = Lo.T_cap;
+    job.W = W;
+    job.H = H;
+    job.w = b.mw;
+    return job;
+  };
+  const int32_t* counts = b.mstatus;
+  SM_TRY(tm.begin(SM_ST_MESH));
+  MeshJob first = mesh_job(1, 0, (const int32_t*)(b.S + Lo.n_grid));
+  first.last = p.n_iters == 1;
+  first.compact_n = Lo.n_grid;  // the matched candidates, compacted by the kernel first
+  first.occ = b.occ;
+  first.compact_count = &b.counters[0];
+  SM_HIP(launch_mesh_insert(first, s));
+  SM_TRY(tm.end());
+  for (int it = 1; it <= p.n_iters; ++it) {
+    const int32_t sz = occ_size(p, it);
+    const bool last = it == p.n_iters;
+    SM_TRY(tm.begin(SM_ST_RASTER));
+    SM_HIP(launch_raster(b.S, Lo.S_cap, b.T, Lo.T_cap, W, H, b.D_it, s, counts));
+    SM_TRY(tm.end());
+    SM_TRY(tm.begin(SM_ST_VALIDATE));
+    SM_HIP(launch_validate_only(b.cL, b.cR, b.omega, b.D_it, W, H, p, sz, nullptr, D_f, C_f, b.cell_g, b.cell_b,
+                                last ? mask : nullptr, last ? b.n_valid : nullptr, s));
+    SM_TRY(tm.end());
+    if (last) break;
+    const int32_t cells = cells_of(W, H, sz);
+    SM_TRY(tm.begin(SM_ST_REMATCH));
+    SM_HIP(launch_resample(b.cL, b.cR, b.cell_g, b.cell_b, b.D_it, W, H, sz, p, b.S, s, counts + kMeshSupports,
+                           Lo.S_cap));
+    SM_TRY(tm.end());
+    MeshJob job = mesh_job(0, -1, nullptr);
+    job.n_new_slot = 2 * cells;
+    job.compact_n = 2 * cells;  // the resampled supports, compacted by the kernel first
+    job.occ = b.occ;
+    job.compact_count = &b.counters[1];
+    job.last = it == p.n_iters - 1;
+    SM_TRY(tm.begin(SM_ST_MESH));
+    SM_HIP(launch_mesh_insert(job, s));
+    SM_TRY(tm.end());
+  }
+  return SM_OK;
+}
+
+// Bytes from the counters to the end of the mesh status words: one copy brings back the
+// valid-pixel count and the frame's mesh record.
+inline size_t status_span(const Layout& Lo) { return Lo.mstatus - Lo.counters + kMeshStatusWords * sizeof(int32_t); }
+
+// Per-frame counts of a device-mesh frame from its read-back span.
+void device_frame_stats(const sm_params& p, const uint8_t* span, const Layout& Lo, sm_stats* st) {
+  const int32_t* ms = (const int32_t*)(span + (Lo.mstatus - Lo.counters));
+  for (int k = 0; k < p.n_iters && k < 8; ++k) {
+    st->n_support[k] = ms[kMeshLog + 2 * k];
+    st->n_tris[k] = ms[kMeshLog + 2 * k + 1];
+  }
+  st->mesh_device = p.n_iters;
+  unsigned long long nv = 0;
+  std::memcpy(&nv, span + 32, sizeof(nv));  // n_valid sits 32 bytes into the counters
+  st->n_valid = (int64_t)nv;
+}
+
+}  // namespace
 }  // namespace sm
 
 using namespace sm;
@@ -398,21 +559,22 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     st->timing = keep;
   }
   uint8_t* base = (uint8_t*)ws;
-  uint64_t* cL = (uint64_t*)(base + Lo.cL);
-  uint64_t* cR = (uint64_t*)(base + Lo.cR);
-  uint8_t* omega = base + Lo.omega;
-  uint8_t* occ = base + Lo.occ;
-  float* D_it = (float*)(base + Lo.D_it);
-  uint64_t* cell_g = (uint64_t*)(base + Lo.cell_g);
-  uint64_t* cell_b = (uint64_t*)(base + Lo.cell_b);
-  sm_support* Sd = (sm_support*)(base + Lo.S);
-  sm_tri* Td = (sm_tri*)(base + Lo.T);
-  int32_t* counters = (int32_t*)(base + Lo.counters);
-  unsigned long long* n_valid = (unsigned long long*)(base + Lo.counters + 32);
+  const FrameBufs b = frame_bufs(base, W, H, Lo);
+  uint64_t* cL = b.cL;
+  uint64_t* cR = b.cR;
+  uint8_t* omega = b.omega;
+  uint8_t* occ = b.occ;
+  float* D_it = b.D_it;
+  uint64_t* cell_g = b.cell_g;
+  uint64_t* cell_b = b.cell_b;
+  sm_support* Sd = b.S;
+  sm_tri* Td = b.T;
+  int32_t* counters = b.counters;
+  unsigned long long* n_valid = b.n_valid;
   // pinned staging: [counts | supports or triangles | exported mesh | mesh status]
-  const MeshWork mw = Lo.mesh_on ? mesh_work_at(base + Lo.mwork, W, H, Lo.S_cap, Lo.mpcap) : MeshWork{};
+  const MeshWork mw = b.mw;
   // (a device-mesh frame also reads its counters and status words back through this region)
-  const size_t st_span = Lo.mesh_on ? Lo.mstatus - Lo.counters + kMeshStatusWords * sizeof(int32_t) : 0;
+  const size_t st_span = Lo.mesh_on ? status_span(Lo) : 0;
   const size_t st_main =
       align256(std::max({(size_t)Lo.S_cap * sizeof(sm_support), (size_t)Lo.T_cap * sizeof(sm_tri), st_span}));
   const size_t st_mesh = Lo.mesh_on ? align256((size_t)mw.cap * 12) : 0;
@@ -426,46 +588,11 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   Timer tm(c.timer, s, timing);
   float us_host = 0.f, us_xfer = 0.f;
 
-  // census of both images, fused with the per-frame initialisation: D_f = 0,
-  // C_f = t_hi (Alg. 1), occupancy cleared, D_it = NaN (coverage only grows over the
-  // iterations, S_it being a subset of S_it+1, so one fill per frame suffices), the
-  // support-grid candidate slots and the counters
-  CensusJob jobs[2] = {{L, stride, cL, omega}, {R, stride, cR, nullptr}};
   const bool fast = p->support_mode == 1;
-  CensusExtras ex;
-  ex.D_nan = D_it;
-  ex.grid_slots = fast ? nullptr : Sd;
-  ex.step = p->support_step;
-  ex.gw = Lo.n_grid > 0 ? (W - 1 - p->support_step / 2) / p->support_step + 1 : 0;
-  ex.zero = counters;
-  ex.n_zero = 16;
-  SM_TRY(tm.begin(SM_ST_CENSUS));
-  SM_HIP(launch_census(jobs, 2, W, H, p->census_w, p->census_h, p->grad_thr, D_f, C_f, p->t_hi, occ, &ex,
-                       s));
-  SM_TRY(tm.end());
-
-  if (fast) {  // FAST keypoints from spatial bins as the candidates (Sec. III-A)
-    SM_TRY(tm.begin(SM_ST_FAST));
-    SM_HIP(launch_fast_score(L, stride, W, H, base + Lo.score, s));
-    SM_TRY(tm.end());
-    SM_TRY(tm.begin(SM_ST_FAST));
-    SM_HIP(launch_fast_select(base + Lo.score, W, H, *p, Sd, nullptr, s));
-    SM_TRY(tm.end());
-  }
-
-  // S_1 = SparseStereo(I_l, I_r) over the candidates; the count lands in the slot
-  // after the candidates so that one copy brings both back
-  SM_TRY(tm.begin(SM_ST_MATCH));
-  SM_HIP(launch_match(cL, cR, W, H, *p, Sd, Lo.n_grid, s));
-  SM_TRY(tm.end());
   const bool device_path = Lo.mesh_on && !fast;  // grid supports, device meshes
-  if (!device_path) {  // (the device path compacts inside its first mesh kernel)
-    SM_TRY(tm.begin(SM_ST_COMPACT));
-    SM_HIP(launch_compact(Sd, Lo.n_grid, &counters[0], occ, W, (int32_t*)(Sd + Lo.n_grid), s));
-    SM_TRY(tm.end());
-  }
+  SM_TRY(enqueue_census_match(L, R, W, H, stride, *p, Lo, base, b, D_f, C_f, !device_path, tm, s));
 
-  int32_t* d_mstatus = Lo.mesh_on ? (int32_t*)(base + Lo.mstatus) : nullptr;
+  int32_t* d_mstatus = b.mstatus;
   bool mesh_dev = false;  // the frame's mesh lives on the device
   int32_t mesh_init = 0;  // records of an exported host mesh, read by the first device insertion
   auto mesh_job = [&](int32_t start, int32_t p0, const int32_t* n_new) {
@@ -492,49 +619,13 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     return job;
   };
 
-  // Grid candidates: the compacted supports are in raster order, the first mesh is built on
-  // the device and every later tessellation inserts into it (each mesh kernel first compacts
-  // its new supports); the counts stay on the device (read by the raster, resampling and
-  // mesh kernels), so the frame needs one synchronisation, at its end. A frame whose device
-  // mesh fails is solved again with host meshes.
+  // Grid candidates with device meshes: the frame needs one synchronisation, at its end.
+  // A frame whose device mesh fails is solved again with host meshes.
   if (device_path) {
-    const int32_t* counts = d_mstatus;
-    SM_TRY(tm.begin(SM_ST_MESH));
-    MeshJob first = mesh_job(1, 0, (const int32_t*)(Sd + Lo.n_grid));
-    first.last = p->n_iters == 1;
-    first.compact_n = Lo.n_grid;  // the matched candidates, compacted by the kernel first
-    first.occ = occ;
-    first.compact_count = &counters[0];
-    SM_HIP(launch_mesh_insert(first, s));
-    SM_TRY(tm.end());
-    for (int it = 1; it <= p->n_iters; ++it) {
-      const int32_t sz = occ_size(*p, it);
-      const bool last = it == p->n_iters;
-      SM_TRY(tm.begin(SM_ST_RASTER));
-      SM_HIP(launch_raster(Sd, Lo.S_cap, Td, Lo.T_cap, W, H, D_it, s, counts));
-      SM_TRY(tm.end());
-      SM_TRY(tm.begin(SM_ST_VALIDATE));
-      SM_HIP(launch_validate_only(cL, cR, omega, D_it, W, H, *p, sz, nullptr, D_f, C_f, cell_g, cell_b,
-                                  last ? mask : nullptr, last ? n_valid : nullptr, s));
-      SM_TRY(tm.end());
-      if (last) break;
-      const int32_t cells = cells_of(W, H, sz);
-      SM_TRY(tm.begin(SM_ST_REMATCH));
-      SM_HIP(launch_resample(cL, cR, cell_g, cell_b, D_it, W, H, sz, *p, Sd, s, counts + kMeshSupports, Lo.S_cap));
-      SM_TRY(tm.end());
-      MeshJob job = mesh_job(0, -1, nullptr);
-      job.n_new_slot = 2 * cells;
-      job.compact_n = 2 * cells;  // the resampled supports, compacted by the kernel first
-      job.occ = occ;
-      job.compact_count = &counters[1];
-      job.last = it == p->n_iters - 1;
-      SM_TRY(tm.begin(SM_ST_MESH));
-      SM_HIP(launch_mesh_insert(job, s));
-      SM_TRY(tm.end());
-    }
+    SM_TRY(enqueue_device_meshes(*p, W, H, Lo, b, D_f, C_f, mask, tm, s));
     // counters (the valid-pixel count) and status words in one copy
     auto t1 = clk::now();
-    const size_t span = Lo.mstatus - Lo.counters + kMeshStatusWords * sizeof(int32_t);
+    const size_t span = status_span(Lo);
     uint8_t* h_span = (uint8_t*)h_S;  // free in this path
     SM_HIP(hipMemcpyAsync(h_span, base + Lo.counters, span, hipMemcpyDeviceToHost, s));
     SM_HIP(hipStreamSynchronize(s));
@@ -549,14 +640,7 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
       return r;
     }
     if (st) {
-      for (int k = 0; k < p->n_iters && k < 8; ++k) {
-        st->n_support[k] = h_mstatus[kMeshLog + 2 * k];
-        st->n_tris[k] = h_mstatus[kMeshLog + 2 * k + 1];
-      }
-      st->mesh_device = p->n_iters;
-      unsigned long long nv = 0;
-      std::memcpy(&nv, h_span + 32, sizeof(nv));  // n_valid sits 32 bytes into the counters
-      st->n_valid = (int64_t)nv;
+      device_frame_stats(*p, h_span, Lo, st);
       SM_TRY(tm.collect(st));
       st->stage_us[SM_ST_HOST_TRI] = us_host;
       st->stage_us[SM_ST_HOST_COPY] = us_xfer;
