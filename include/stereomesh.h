@@ -286,6 +286,34 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
                    const sm_params* p /* [host] */, void* ws, size_t ws_bytes, float* D_f,
                    uint8_t* C_f, uint8_t* mask, sm_stats* st /* [host] */, void* stream);
 
+/*
+ * sm_solve_noalloc -- sm_solve for callers that cannot allocate (code under HIP graph
+ *   capture, tight serving loops, harnesses that forbid allocation): the same solve of one
+ *   frame with no caller workspace, no device or host allocation (no hipMalloc, hipFree,
+ *   pinned staging, timing events or library routine that allocates) on success. The
+ *   frame's workspace is a buffer the library holds in device memory, one per GPU,
+ *   SM_NOALLOC_MAX_BYTES large; each GPU the library runs on keeps it until the process
+ *   ends. Arguments and results are those of sm_solve, except:
+ *   - the frame must take the all-device path: grid candidates (support_mode = 0) and
+ *     device meshes (host_mesh = 0), else SM_ERR_ARG;
+ *   - sm_solve_workspace_bytes(W, H, p) must not exceed SM_NOALLOC_MAX_BYTES, else
+ *     SM_ERR_CAPACITY (640x480 with disparities 0-127 needs 13 MiB, 1280x720 with 0-255
+ *     40 MiB, 1920x1080 with 0-255 88 MiB: too large);
+ *   - a frame whose device mesh cannot be finished (an array full; sm_solve would solve it
+ *     again with host meshes, which allocates) returns SM_ERR_INTERNAL and its outputs are
+ *     not valid;
+ *   - st gets the counts only (st->timing is ignored);
+ *   - `stream` must belong to the calling thread's current device.
+ *   Every call on a GPU works in that GPU's one buffer, which keeps the last call's
+ *   contents (each call initialises what it reads). Calls that overlap on one GPU -- from
+ *   other threads, or on other streams not yet synchronised -- race and give wrong
+ *   results. The call synchronises `stream` once, at the end of the frame.
+ */
+#define SM_NOALLOC_MAX_BYTES ((size_t)48 << 20)
+sm_status sm_solve_noalloc(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
+                           const sm_params* p /* [host] */, float* D_f, uint8_t* C_f, uint8_t* mask,
+                           sm_stats* st /* [host] */, void* stream);
+
 /* One frame of a batch: inputs, method parameters, outputs (all device pointers). */
 typedef struct {
   const uint8_t* L;            /* [H][stride] left image                                  */

@@ -20,6 +20,7 @@ STAGES = {"census": 0, "match": 1, "compact": 2, "raster": 3, "validate": 4, "re
           "fast": 6, "mesh": 7, "host_triangulate": 12, "host_copies": 13, "total": 14}
 N_STAGES = 16
 TIME_SELECTED = 0x40000000
+NOALLOC_MAX_BYTES = 48 << 20   # SM_NOALLOC_MAX_BYTES
 
 
 def timing_flag(timing) -> int:
@@ -69,7 +70,7 @@ class SmFrame(ctypes.Structure):
 
 EXPORTS = ("sm_census", "sm_match_support", "sm_grid_candidates", "sm_fast_candidates", "sm_triangulate",
            "sm_interpolate", "sm_cells", "sm_validate", "sm_resample",
-           "sm_solve_workspace_bytes", "sm_solve", "sm_solve_batch", "sm_solve_many_workspace_bytes",
+           "sm_solve_workspace_bytes", "sm_solve", "sm_solve_noalloc", "sm_solve_batch", "sm_solve_many_workspace_bytes",
            "sm_solve_many", "sm_solve_many_capture", "sm_many_graph_run", "sm_many_graph_destroy", "sm_autotune",
            "sm_last_error", "sm_version")
 
@@ -110,6 +111,8 @@ def load():
         "sm_solve_workspace_bytes": (c_size, [c_i32, c_i32, P(SmParams)]),
         "sm_solve": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, P(SmParams), c_vp, c_size, c_vp,
                              c_vp, c_vp, P(SmStats), c_vp]),
+        "sm_solve_noalloc": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, P(SmParams), c_vp, c_vp, c_vp,
+                                     P(SmStats), c_vp]),
         "sm_solve_batch": (c_i32, [P(SmFrame), c_i32, P(c_vp), P(c_vp), P(c_size), c_i32,
                                    P(SmStats)]),
         "sm_solve_many_workspace_bytes": (c_size, [P(SmFrame), c_i32]),

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -371,6 +372,37 @@ void device_frame_stats(const sm_params& p, const uint8_t* span, const Layout& L
   unsigned long long nv = 0;
   std::memcpy(&nv, span + 32, sizeof(nv));  // n_valid sits 32 bytes into the counters
   st->n_valid = (int64_t)nv;
+}
+
+}  // namespace
+
+// Workspace of sm_solve_noalloc: one per GPU, held until the process ends. In host code
+// `scratch` names a host-side stand-in, never the device memory: its device address comes
+// from hipGetSymbolAddress, once per device (noalloc_workspace below).
+static __device__ __align__(256) uint8_t scratch[SM_NOALLOC_MAX_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's `scratch` (looked up on the first call made with
+// that device current).
+sm_status noalloc_workspace(void** out) {
+  int dev = -1;
+  SM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(SM_ERR_ARG, "device %d outside [0, %d)", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SM_ERR_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SM_OK;
 }
 
 }  // namespace
@@ -799,6 +831,60 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   return SM_OK;
 }
 
+
+// sm_solve on the library's per-device workspace, allocating nothing: the launch sequence
+// of a device-mesh frame, then one read-back of the counters and mesh status words into
+// thread-local host memory.
+sm_status sm_solve_noalloc(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
+                           const sm_params* p, float* D_f, uint8_t* C_f, uint8_t* mask, sm_stats* st,
+                           void* stream) {
+  last_error().clear();
+  SM_TRY(check_image_args(W, H));
+  SM_TRY(check_params(p));
+  if (!L || !R || !D_f || !C_f || !mask) return fail(SM_ERR_ARG, "only st may be NULL");
+  if (stride < W) return fail(SM_ERR_ARG, "stride %d < W %d", stride, W);
+  if (p->support_mode != 0 || p->host_mesh != 0)
+    return fail(SM_ERR_ARG, "sm_solve_noalloc needs grid candidates (support_mode 0) and device meshes (host_mesh 0)");
+  const Layout Lo = layout_of(W, H, *p);
+  if (!Lo.mesh_on) return fail(SM_ERR_INTERNAL, "no device mesh in the layout");
+  if (Lo.total > SM_NOALLOC_MAX_BYTES)
+    return fail(SM_ERR_CAPACITY, "a %dx%d frame needs a %zu-byte workspace, above the %zu bytes of "
+                "sm_solve_noalloc; use sm_solve", W, H, Lo.total, (size_t)SM_NOALLOC_MAX_BYTES);
+  static thread_local uint8_t h_span[512];  // counters + mesh status words, read back
+  const size_t span = status_span(Lo);
+  if (span > sizeof(h_span)) return fail(SM_ERR_INTERNAL, "status span %zu too large", span);
+  void* ws = nullptr;
+  SM_TRY(noalloc_workspace(&ws));
+  const hipStream_t s = (hipStream_t)stream;
+  if (st) {
+    std::memset(st, 0, sizeof(*st));  // counts only: no timing events are created here
+  }
+  uint8_t* base = (uint8_t*)ws;
+  const FrameBufs b = frame_bufs(base, W, H, Lo);
+  StageTimer no_events;
+  Timer tm(no_events, s, 0);
+  SM_TRY(enqueue_census_match(L, R, W, H, stride, *p, Lo, base, b, D_f, C_f, false, tm, s));
+  SM_TRY(enqueue_device_meshes(*p, W, H, Lo, b, D_f, C_f, mask, tm, s));
+  SM_HIP(hipMemcpyAsync(h_span, base + Lo.counters, span, hipMemcpyDeviceToHost, s));
+  SM_HIP(hipStreamSynchronize(s));
+  const int32_t err = ((const int32_t*)(h_span + (Lo.mstatus - Lo.counters)))[kMeshErr];
+  // a first mesh that cannot exist (fewer than three supports, or all on one line) leaves
+  // every tessellation empty, D_it NaN and nothing validated: that is the frame's result
+  if (err != 0 && err != kMeshErrNoMesh)
+    return fail(SM_ERR_INTERNAL, "the device mesh could not finish this frame (code %d); sm_solve solves "
+                "it with host meshes", err);
+  if (st) {
+    device_frame_stats(*p, h_span, Lo, st);
+    if (err == kMeshErrNoMesh) {  // no mesh at all: the first supports stay the only ones
+      for (int k = 0; k < p->n_iters && k < 8; ++k) {
+        st->n_support[k] = st->n_support[0];
+        st->n_tris[k] = 0;
+      }
+      st->mesh_device = 0;
+    }
+  }
+  return SM_OK;
+}
 
 // Measured launch shapes for one frame size and parameter set (the autotuner of the
 // batched and per-frame solves): the frame is solved once, then each tunable launch is
