@@ -35,6 +35,11 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1511_00758_amd", "csrc", f)
                   for f in ("kernels.hip", "kernels.hpp", "mesh.hip", "mesh.hpp", "mesh_core.hpp", "mesh_start.hpp")]
 
 
+def progress(msg):
+    """One line per finished phase on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -103,25 +108,95 @@ def load_traffic(kernel, workload):
     return t.get("bytes_per_launch")
 
 
-def cpu_baseline(frames, params, gpu_results, n):
-    """Time the oracle (single thread) on ``n`` frames and check the GPU outputs of the
-    same frames bit for bit."""
-    import numpy as np
+def _cpu_worker(job):
+    """One CPU-baseline job in a worker process that imports only the oracle and the
+    scene generator, single-threaded. ("serial", seeds): every (config, frame) of the
+    list solved one after another, each timed per stage; ("timed", cfg, frame): one frame,
+    returning its start and end on the shared monotonic clock."""
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[k] = "1"
     import oracle
-    p = oracle.Params.from_dict(params)
-    t0 = time.perf_counter()
-    refs = [oracle.solve(frames[i][0], frames[i][1], p) for i in range(n)]
-    dt = time.perf_counter() - t0
-    ok = True
-    for i, ref in enumerate(refs):
-        D_f, C_f, mask = gpu_results[i]
-        ok &= bool((C_f == ref["C_f"]).all())
-        ok &= bool((mask.astype(bool) == ref["mask"]).all())
-        ok &= bool((D_f.view(np.uint32) == ref["D_f"].view(np.uint32)).all())
-    H, W = frames[0][0].shape
-    return {"value": round(n / dt, 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} frames of the same 640x480 workload, NumPy oracle, one thread, "
-                      f"{dt:.1f} s", "mpx_per_s": round(n * W * H / dt / 1e6, 4)}, ok
+    import scenes
+    if job[0] == "warm":
+        time.sleep(0.3)
+        return os.getpid()
+    if job[0] == "timed":
+        _, cfg, f = job
+        sc = scenes.make_scene(cfg, scenes.seed_of(cfg, f))
+        p = oracle.Params.from_dict(sc.params)
+        t0 = time.perf_counter()
+        oracle.solve(sc.left, sc.right, p)
+        return t0, time.perf_counter(), os.getpid()
+    out = []
+    for cfg, f in job[1]:
+        sc = scenes.make_scene(cfg, scenes.seed_of(cfg, f))
+        p = oracle.Params.from_dict(sc.params)
+        times = {}
+        t0 = time.perf_counter()
+        ref = oracle.solve(sc.left, sc.right, p, times=times)
+        dt = time.perf_counter() - t0
+        keep = (ref["D_f"], ref["C_f"], ref["mask"]) if cfg == 2 else None
+        out.append((cfg, f, sc.left.shape, dt, times, keep))
+    return out
+
+
+def cpu_baseline(seeds_per_config=5, workers=None):
+    """The oracle on the host cores, before any GPU work: (i) single-core latency per frame
+    and per stage for >= 5 seeds of each single-frame workload (320x240, 640x480,
+    1242x375), solved one after another in one worker process; (ii) throughput of N
+    worker processes (N = host cores, at most 16) each solving a distinct 640x480 frame at
+    once. Returns the record and the oracle outputs of 640x480 frames 0..seeds-1 (for the
+    GPU parity check of the same frames)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import numpy as np
+    import platform
+    nproc = os.cpu_count() or 1
+    n = workers or min(nproc, 16)
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    ctx = mp.get_context("spawn")
+    with cf.ProcessPoolExecutor(max_workers=1, mp_context=ctx) as ex:
+        serial = ex.submit(_cpu_worker, ("serial", [(c, f) for c in (1, 2, 3) for f in range(seeds_per_config)])).result()
+    single, refs = {}, {}
+    for cfg in (1, 2, 3):
+        rows = [r for r in serial if r[0] == cfg]
+        ms = np.array([r[3] for r in rows]) * 1e3
+        stages = {}
+        for r in rows:
+            for k, v in r[4].items():
+                stages[k] = stages.get(k, 0.0) + v * 1e3 / len(rows)
+        H, W = rows[0][2]
+        single[f"{W}x{H}"] = {"frames": len(rows), "seeds": [1000 * cfg + r[1] for r in rows],
+                              "ms_per_frame": {"mean": round(float(ms.mean()), 1), "p50": round(float(np.median(ms)), 1),
+                                               "max": round(float(ms.max()), 1)},
+                              "frames_per_s": round(1e3 / float(ms.mean()), 3),
+                              "stage_ms_per_frame": {k: round(v, 1) for k, v in stages.items()}}
+        if cfg == 2:
+            refs = {r[1]: r[5] for r in rows}
+    with cf.ProcessPoolExecutor(max_workers=n, mp_context=ctx) as ex:
+        list(ex.map(_cpu_worker, [("warm",)] * (2 * n)))       # start and import in every worker
+        spans = list(ex.map(_cpu_worker, [("timed", 2, 100 + i) for i in range(n)]))
+    t0 = min(sp[0] for sp in spans)
+    t1 = max(sp[1] for sp in spans)
+    fps = n / (t1 - t0)
+    rec = {"value": round(fps, 4), "unit": "frames/s", "cores": n, "kind": "oracle",
+           "sample": (f"640x480 workload: {n} worker processes, one thread each, solving {n} distinct "
+                      f"frames (seeds 2100..{2099 + n}) at once in {t1 - t0:.1f} s; single-core latencies "
+                      f"below over {seeds_per_config} seeds of each single-frame workload"),
+           "mpx_per_s": round(fps * 640 * 480 / 1e6, 4),
+           "host": {"nproc": nproc, "workers": n, "cpu_model": model,
+                    "processes_used": len({sp[2] for sp in spans})},
+           "single_core": single,
+           "context": "paper: ~120 Hz VGA (8.2 ms) at 1 iteration on one i7-3920XM thread (SSE census)"}
+    return rec, refs
 
 
 def roofline_probe(api, params, W=7680, H=4320, reps=20, dev="cuda:0"):
@@ -367,11 +442,13 @@ def batched_runs(api, vga_frames, vga_params, workers=16, batches=12, dev="cuda:
     return out
 
 
-def serving_run(api, seconds=3.0, n_streams=16, slots=8, budget_gb=12.0, dev="cuda:0", device_mesh=True):
+def serving_run(api, seconds=10.0, n_streams=16, lanes=2, max_batch=64, per_stream=8, budget_gb=48.0,
+                dev="cuda:0"):
     """16 camera streams (640x480 / 1280x720 / 1920x1080 by stream id mod 3), Poisson
     arrivals at 30 Hz each, disparities 0-255, 3 iterations, replayed in real time
     through the continuous-batching server (latency), then all at once (capacity).
-    Latency = completion - arrival, including the host-to-device upload of the pair."""
+    Latency = completion - arrival, including the host-to-device upload of the pair.
+    Beside it: each size solved alone on the plain per-frame path (sm_solve)."""
     import numpy as np
     import torch
     import scenes
@@ -394,33 +471,44 @@ def serving_run(api, seconds=3.0, n_streams=16, slots=8, budget_gb=12.0, dev="cu
         sv(l, r)
         torch.cuda.synchronize()
         ts = []
-        for _ in range(10):
+        for _ in range(20):
             t0 = time.perf_counter()
             sv(l, r)
             torch.cuda.synchronize()
             ts.append((time.perf_counter() - t0) * 1e3)
         solo[f"{W}x{H}"] = round(float(np.median(ts)), 3)
         del sv
+    mix = [solo[f"{sizes[s % 3][0]}x{sizes[s % 3][1]}"] for s in range(n_streams)]
     counter = {s: 0 for s in specs}
 
     def frames_for(s):
         counter[s] += 1
         return pairs[(s % 3, (s // 3 + counter[s]) % 2)]
 
-    out = {"streams": n_streams, "slots": slots, "budget_gb": budget_gb, "rate_hz": 30.0,
-           "meshes": "device" if device_mesh else "host", "solo_latency_ms_p50": solo}
+    out = {"streams": n_streams, "lanes": lanes, "max_batch": max_batch, "frames_per_stream": per_stream,
+           "budget_gb": budget_gb,
+           "rate_hz": 30.0, "simulated_s": seconds, "meshes": "device",
+           "batching": "continuous: each free lane takes every admissible frame (sm_solve_many)",
+           "per_frame_path": {"latency_ms_p50_alone": solo,
+                              "capacity_frames_per_s": round(1e3 / float(np.mean(mix)), 1),
+                              "note": "sm_solve one frame at a time; capacity = 1 / mean solo time over the stream mix"}}
     for mode, scale in (("realtime", 1.0), ("saturated", 0.0)):
-        server = StereoServer(specs, n_slots=slots, budget_bytes=int(budget_gb * 2**30), device=dev,
-                              device_mesh=device_mesh)
+        server = StereoServer(specs, budget_bytes=int(budget_gb * 2**30), device=dev, n_lanes=lanes,
+                              max_batch=max_batch, frames_per_stream=per_stream)
         sched = scenes.stream_schedule(seed=11, n_streams=n_streams, rate_hz=30.0, seconds=seconds)
         done, wall = replay(server, sched, frames_for, time_scale=scale)
-        lat = np.array([r.latency for r in done if r.t_arrival >= 0.2 * scale * seconds]) * 1e3
+        warm = 0.1 * scale * seconds      # the first moments of the real-time run fill the lanes
+        t_first = min(r.t_arrival for r in done)
+        lat = np.array([r.latency for r in done if r.t_arrival - t_first >= warm]) * 1e3
         npx = sum(specs[r.stream].W * specs[r.stream].H for r in done)
+        bs = np.array([b for (_, b, _) in server.batches])
         out[mode] = {"frames": len(done), "wall_s": round(wall, 3),
                      "frames_per_s": round(len(done) / wall, 1),
                      "mpx_per_s": round(npx / wall / 1e6, 1),
                      "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                                     "p99": round(float(np.percentile(lat, 99)), 3)},
+                     "batches": int(len(bs)), "frames_per_batch": {"mean": round(float(bs.mean()), 2),
+                                                                   "max": int(bs.max())},
                      "evictions": server.adm.evictions}
     out["offered_frames_per_s"] = round(n_streams * 30.0, 1)
     return out
@@ -444,7 +532,8 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--frames", type=int, default=8, help="distinct frames cycled")
-    ap.add_argument("--cpu-frames", type=int, default=3, help="oracle sample size")
+    ap.add_argument("--cpu-frames", type=int, default=5,
+                    help="oracle seeds per single-frame workload (single-core latency leg)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch-shape rules (no sm_autotune before timing)")
@@ -452,7 +541,7 @@ def main():
                     help="do not record per-kernel events in the timed region")
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the 16-stream serving run")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched (sm_solve_batch) throughput runs")
     ap.add_argument("--no-probe", action="store_true",
@@ -476,6 +565,12 @@ def main():
                           "fits one MI355X and frames/streams shard across GPUs without "
                           "collectives (see the design notes); run with --gpus 1"}))
         sys.exit(2)
+
+    cpu, cpu_refs = None, {}
+    if not args.no_cpu_baseline and not args.probe_only:
+        # the oracle on the host cores first, before anything touches the GPU
+        cpu, cpu_refs = cpu_baseline(seeds_per_config=args.cpu_frames)
+        progress(f"cpu baseline: {cpu['value']} frames/s on {cpu['cores']} processes")
 
     import numpy as np
     import torch
@@ -502,6 +597,7 @@ def main():
     # launch shapes measured on the first frame (sm_autotune) for this size, used by every
     # later launch of the run (outputs do not depend on them)
     tuned = None if args.no_autotune else solver.autotune(*dframes[0])
+    progress(f"autotune: {tuned}")
     # live timing of the dominant kernel (the mesh insertion) inside the timed region; an
     # event pair around a launch costs ~4 us of frame time, so validation and the raster are
     # timed in a pass of their own after it (--time-all times every kernel in the loop)
@@ -533,6 +629,7 @@ def main():
 
     elapsed = t1 - t0
     fps = args.steps / elapsed
+    progress(f"timed region: {args.steps} frames, {fps:.1f} frames/s")
     lat_ms = np.array(lat) * 1e3
     kernels = {}
     for name in acc_us:
@@ -571,20 +668,26 @@ def main():
                                     params["n_iters"], kernels["validate"]["launches_per_step"],
                                     traffic=load_traffic("validate", "vga_20planes"))
 
-    # outputs of the oracle sample frames (solved again, outside the timed region)
-    gpu_results = []
-    for i in range(min(args.cpu_frames, len(dframes))):
+    # the frames the oracle solved (640x480 seeds 2000..), solved again outside the timed
+    # region and compared bit for bit
+    validated = None
+    for i, ref in sorted(cpu_refs.items()):
+        if i >= len(dframes):
+            continue
         rr = solver(dframes[i][0], dframes[i][1])
         torch.cuda.synchronize()
-        gpu_results.append((rr.D_f.cpu().numpy(), rr.C_f.cpu().numpy(), rr.mask.cpu().numpy()))
+        D_f, C_f, mask = (rr.D_f.cpu().numpy(), rr.C_f.cpu().numpy(), rr.mask.cpu().numpy())
+        ok = bool((C_f == ref[1]).all() and (mask.astype(bool) == ref[2]).all()
+                  and (D_f.view(np.uint32) == ref[0].view(np.uint32)).all())
+        validated = ok if validated is None else (validated and ok)
     probe = None if args.no_probe else roofline_probe(api, params)
+    progress("roofline probe done")
     variants = None if args.no_variants else variant_runs(api, dframes, params, W, H)
+    progress("paper variants done")
     batched = None if args.no_batch else batched_runs(api, frames, params)
+    progress("batched runs done")
     serving = None if args.no_serve else serving_run(api, seconds=args.serve_seconds)
-    cpu = None
-    validated = None
-    if not args.no_cpu_baseline and args.cpu_frames > 0:
-        cpu, validated = cpu_baseline(frames, params, gpu_results, min(args.cpu_frames, len(frames)))
+    progress("serving done")
 
     out = {
         "metric": METRIC,

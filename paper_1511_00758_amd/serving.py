@@ -1,24 +1,31 @@
 """Continuous-batching request loop for many simulated camera streams.
 
-Frames arrive per camera stream; a frame is admitted to one of ``n_slots`` worker slots
-as soon as a slot is free and its stream's device state fits the HBM budget. Each
-stream keeps its state resident on the device between frames (solver workspace,
-output maps, input buffers), so a stream's frames reuse it; idle streams are evicted
-least-recently-used when a new stream needs room. Frames of one stream are solved in
-arrival order, one at a time; frames of different streams overlap on the device (each
-slot has its own HIP stream and host thread, and the solver releases the GIL).
+Frames arrive per camera stream. Whenever one of ``n_lanes`` execution lanes is free,
+every admissible waiting frame (up to ``max_batch``) is taken at once and solved as one
+stage-batched batch (``sm_solve_many``: one kernel launch per stage over all frames of
+the batch, frames of different sizes together). Frames that arrive while batches are on
+the GPU wait for the next free lane, so work keeps flowing in as the device frees up;
+with two or more lanes, batches overlap on the device (each lane has its own host
+thread, HIP stream and batch workspace, and the library releases the GIL while it
+runs).
 
-``Admission`` is the host-side policy alone (no GPU): it is driven by the server, and
-by the CPU tests with a simulated clock and a fake budget. ``StereoServer`` executes
-admitted frames with the library's ``sm_solve``; every step of the method runs in the
-library.
+Each stream keeps its state resident on the device between frames (``frames_per_stream``
+slots of an input pair and output maps, and their share of the batch workspaces in the
+budget); a stream is admitted only when that state fits the HBM budget, after evicting
+idle streams least recently used. A stream's frames are solved in arrival order: up to
+``frames_per_stream`` of its oldest waiting frames go into one batch (and complete
+together), and its next frames wait until that batch is done.
+
+``Admission`` is the host-side policy alone (no GPU): it is driven by the server, and by
+the CPU tests with a simulated clock and a fake budget. ``StereoServer`` executes
+admitted batches with the library; every step of the method runs in the library.
 """
 from __future__ import annotations
 
 import collections
 import threading
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import Callable, Dict, List, Optional, Tuple
 
 
@@ -27,12 +34,13 @@ class Request:
     rid: int
     stream: int
     t_arrival: float
-    payload: object = None          # (left, right) host arrays or device tensors
+    payload: object = None          # (left, right) host arrays or tensors
     t_admit: float = 0.0
     t_done: float = 0.0
-    slot: int = -1
+    lane: int = -1
+    batch: int = -1                 # id of the batch that solved it
+    batch_size: int = 0
     status: int = 0
-    result: object = None
 
     @property
     def latency(self) -> float:
@@ -44,10 +52,10 @@ class Admission:
 
     ``state_bytes(stream)`` gives the bytes a stream needs while resident. A request is
     admissible when its stream is not busy and either its state is resident or can be
-    made resident by allocating (budget permitting) after evicting idle resident
-    streams in least-recently-used order. Requests are considered in arrival order; a
-    request that cannot be admitted does not block later requests of other streams
-    whose state is already resident (no head-of-line blocking on memory)."""
+    made resident (budget permitting) after evicting idle resident streams in
+    least-recently-used order. Requests are considered in arrival order; a request that
+    cannot be admitted does not block later requests of other streams whose state is
+    already resident (no head-of-line blocking on memory)."""
 
     def __init__(self, budget_bytes: int, state_bytes: Callable[[int], int]):
         self.budget = int(budget_bytes)
@@ -79,29 +87,58 @@ class Admission:
 
     def next(self) -> Optional[Tuple[Request, List[int]]]:
         """Pops the next admissible request; returns it with the streams to evict."""
-        for i, r in enumerate(self.queue):
-            if r.stream in self.busy:
-                continue
-            if any(q.stream == r.stream for q in self.queue[:i]):
-                continue                            # keep each stream's frames in order
-            if r.stream in self.resident:
-                victims = []
+        batch, evicted = self.next_batch(1)
+        return (batch[0], evicted) if batch else None
+
+    def _admit(self, stream: int) -> Optional[List[int]]:
+        """Makes ``stream`` resident (evicting idle streams if needed); returns the evicted
+        streams, or None when its state does not fit beside the busy ones."""
+        if stream in self.resident:
+            victims = []
+        else:
+            victims = self._make_room(self.state_bytes(stream))
+            if victims is None:
+                return None
+        for s in victims:
+            self.used -= self.resident.pop(s)
+            self.evictions += 1
+        if stream not in self.resident:
+            b = self.state_bytes(stream)
+            self.resident[stream] = b
+            self.used += b
+        self.resident.move_to_end(stream)
+        return victims
+
+    def next_batch(self, max_frames: int, per_stream: int = 1) -> Tuple[List[Request], List[int]]:
+        """Pops up to ``max_frames`` admissible requests in arrival order: of each stream
+        that is not busy, its oldest waiting frames, at most ``per_stream`` of them (a
+        stream's frames then complete together, in order); returns them with every stream
+        evicted to make room. Their streams are busy until ``done``."""
+        batch, evicted, taken, blocked = [], [], {}, set()
+        i = 0
+        while i < len(self.queue) and len(batch) < max_frames:
+            r = self.queue[i]
+            s = r.stream
+            if s in taken:
+                ok = taken[s] < per_stream and s not in blocked
             else:
-                victims = self._make_room(self.state_bytes(r.stream))
-                if victims is None:
-                    continue
-            for s in victims:
-                self.used -= self.resident.pop(s)
-                self.evictions += 1
-            if r.stream not in self.resident:
-                b = self.state_bytes(r.stream)
-                self.resident[r.stream] = b
-                self.used += b
-            self.resident.move_to_end(r.stream)
-            self.busy.add(r.stream)
+                ok = s not in self.busy and s not in blocked
+                if ok:
+                    victims = self._admit(s)    # streams taken so far are busy: never evicted
+                    if victims is None:
+                        ok = False
+                    else:
+                        evicted += victims
+                        self.busy.add(s)
+                        taken[s] = 0
+            if not ok:
+                blocked.add(s)                  # its later frames wait behind this one
+                i += 1
+                continue
+            taken[s] += 1
+            batch.append(r)
             del self.queue[i]
-            return r, victims
-        return None
+        return batch, evicted
 
     def done(self, req: Request):
         self.busy.discard(req.stream)
@@ -115,47 +152,46 @@ class StreamSpec:
 
 
 class StereoServer:
-    """Executes admitted frames on ``n_slots`` worker slots (thread + HIP stream each).
+    """Serves camera streams by continuous batching over ``n_lanes`` execution lanes.
 
-    ``specs[stream]`` gives each camera stream's frame size and method parameters.
-    ``on_done(req, D_f, C_f, mask)`` is called on the worker thread after the frame's
-    outputs are complete (device tensors of the stream's resident state, valid until
-    that stream's next frame). ``device_mesh`` True (the default) keeps every
-    tessellation on the GPU; each is one long single-workgroup kernel, so with many more
-    slots than the device's hardware queues they wait on each other, and False
-    (triangulation on the host, overlapped with other frames' kernels) can serve more
-    frames per second there."""
+    ``specs[stream]`` gives each camera stream's frame size and method parameters (grid
+    supports; every tessellation on the device). ``on_done(req, D_f, C_f, mask)`` is
+    called on the lane's thread once the frame's outputs are complete (device tensors of
+    the stream's resident state, valid until that stream's next frame)."""
 
-    def __init__(self, specs: Dict[int, StreamSpec], n_slots: int, budget_bytes: int,
-                 device="cuda:0", on_done=None, device_mesh: bool = True):
+    def __init__(self, specs: Dict[int, StreamSpec], budget_bytes: int, device="cuda:0", on_done=None,
+                 n_lanes: int = 2, max_batch: int = 32, frames_per_stream: int = 1, host_threads: int = 4):
         import torch
         from . import api
         self._torch = torch
         self._api = api
-        specs = {s: StreamSpec(sp.W, sp.H, dict(sp.params, host_mesh=0 if device_mesh else 1))
-                 for s, sp in specs.items()}
-        self.specs = specs
+        self.specs = {s: StreamSpec(sp.W, sp.H, dict(sp.params, host_mesh=0, support_mode=0))
+                      for s, sp in specs.items()}
         self.device = device
         self.on_done = on_done
-        self.lib = api._lib.load()
-        self._ws_need = {}
-        for s, sp in specs.items():
-            self._ws_need[s] = self.lib.sm_solve_workspace_bytes(sp.W, sp.H, api.make_params(sp.params))
+        self.max_batch = int(max_batch)
+        self.per_stream = int(frames_per_stream)
+        lib = api._lib.load()
+        self._ws_need = {s: int(lib.sm_solve_workspace_bytes(sp.W, sp.H, api.make_params(sp.params)))
+                         for s, sp in self.specs.items()}
+        if any(v == 0 for v in self._ws_need.values()):
+            raise ValueError("invalid stream size or parameters")
         self.adm = Admission(budget_bytes, self.state_bytes)
-        self.n_slots = n_slots
+        self.n_lanes = int(n_lanes)
         self.cv = threading.Condition()
-        self.free_slots = list(range(n_slots))
-        self.slot_streams = [torch.cuda.Stream(device=device) for _ in range(n_slots)]
         self.state: Dict[int, dict] = {}
         self.completed: List[Request] = []
+        self.batches: List[Tuple[int, int, float]] = []   # (lane, frames, device seconds)
         self.closed = False
         self._stop = False
         self.errors: List[str] = []
         self._rid = 0
-        # one persistent thread per slot (the solver keeps per-thread host state)
-        self._slot_req: List[Optional[Request]] = [None] * n_slots
-        self._threads = [threading.Thread(target=self._slot_loop, args=(k,), daemon=True)
-                         for k in range(n_slots)]
+        self._n_batches = 0
+        self._lane_batch: List[Optional[List[Request]]] = [None] * self.n_lanes
+        self._lanes = [{"stream": torch.cuda.Stream(device=device),
+                        "solver": api.ManySolver(host_threads, device=device)} for _ in range(self.n_lanes)]
+        self._threads = [threading.Thread(target=self._lane_loop, args=(k,), daemon=True)
+                         for k in range(self.n_lanes)]
         for t in self._threads:
             t.start()
         self._dispatch = threading.Thread(target=self._dispatcher, daemon=True)
@@ -163,19 +199,24 @@ class StereoServer:
 
     # --- memory accounting -----------------------------------------------------------
     def state_bytes(self, stream: int) -> int:
+        """Per frame slot of the stream: inputs (2 B/px) and outputs (6 B/px) kept
+        resident, plus the frame's share of a batch workspace (what sm_solve would need
+        for it alone); ``frames_per_stream`` slots."""
         sp = self.specs[stream]
-        return int(self._ws_need[stream]) + sp.W * sp.H * (4 + 1 + 1 + 2)
+        return self.per_stream * (self._ws_need[stream] + sp.W * sp.H * (2 + 4 + 1 + 1))
 
-    def _ensure_state(self, stream: int, cuda_stream):
+    def _ensure_state(self, stream: int):
         st = self.state.get(stream)
         if st is None:
             torch = self._torch
             sp = self.specs[stream]
-            with torch.cuda.stream(cuda_stream):
-                solver = self._api.Solver(sp.W, sp.H, sp.params, device=self.device)
-                st = {"solver": solver,
-                      "L": torch.empty((sp.H, sp.W), dtype=torch.uint8, device=self.device),
-                      "R": torch.empty((sp.H, sp.W), dtype=torch.uint8, device=self.device)}
+            dev = self.device
+            st = [{"L": torch.empty((sp.H, sp.W), dtype=torch.uint8, device=dev),
+                   "R": torch.empty((sp.H, sp.W), dtype=torch.uint8, device=dev),
+                   "out": (torch.empty((sp.H, sp.W), dtype=torch.float32, device=dev),
+                           torch.empty((sp.H, sp.W), dtype=torch.uint8, device=dev),
+                           torch.empty((sp.H, sp.W), dtype=torch.uint8, device=dev))}
+                  for _ in range(self.per_stream)]
             self.state[stream] = st
         return st
 
@@ -190,70 +231,94 @@ class StereoServer:
         return req
 
     def _dispatcher(self):
+        torch = self._torch
         with self.cv:
             while True:
                 if self.closed and not self.adm.queue:
                     return
-                nxt = self.adm.next() if self.free_slots else None
-                if nxt is None:
-                    self.cv.wait(timeout=0.05)
+                free = [k for k in range(self.n_lanes) if self._lane_batch[k] is None]
+                batch, evicted = self.adm.next_batch(self.max_batch, self.per_stream) if free else ([], [])
+                if not batch:
+                    self.cv.wait(timeout=0.02)
                     continue
-                req, victims = nxt
-                for s in victims:          # evicted state is dropped (memory returns to torch)
+                for s in evicted:            # evicted state is dropped (memory returns to torch)
                     self.state.pop(s, None)
-                slot = self.free_slots.pop(0)
-                req.slot = slot
-                req.t_admit = time.perf_counter()
-                self._slot_req[slot] = req
+                fresh = [r.stream for r in batch if r.stream not in self.state]
+                for s in fresh:
+                    self._ensure_state(s)
+                if fresh:                    # new buffers are ready before any lane stream uses them
+                    torch.cuda.current_stream(self.device).synchronize()
+                now = time.perf_counter()
+                k = free[0]
+                for r in batch:
+                    r.t_admit = now
+                    r.lane = k
+                    r.batch = self._n_batches
+                    r.batch_size = len(batch)
+                self._n_batches += 1
+                self._lane_batch[k] = batch
                 self.cv.notify_all()
 
-    def _slot_loop(self, k: int):
+    def _lane_loop(self, k: int):
         while True:
             with self.cv:
-                while self._slot_req[k] is None:
-                    if self.closed and not self.adm.queue and len(self.free_slots) == self.n_slots \
-                            and self._stop:
+                while self._lane_batch[k] is None:
+                    if self._stop:
                         return
-                    self.cv.wait(timeout=0.05)
-                req = self._slot_req[k]
-            self._run(req)
+                    self.cv.wait(timeout=0.02)
+                batch = self._lane_batch[k]
+                states, slot = [], {}
+                for r in batch:                 # a stream's frames take its slots in order
+                    j = slot.get(r.stream, 0)
+                    slot[r.stream] = j + 1
+                    states.append(self.state[r.stream][j])
+            self._run(k, batch, states)
             with self.cv:
-                self._slot_req[k] = None
-                self.adm.done(req)
-                self.free_slots.append(req.slot)
-                self.completed.append(req)
+                for r in batch:
+                    self.adm.done(r)
+                    self.completed.append(r)
+                self._lane_batch[k] = None
                 self.cv.notify_all()
 
-    def _run(self, req: Request):
+    def _run(self, k: int, batch: List[Request], states: List[dict]):
         torch = self._torch
-        cs = self.slot_streams[req.slot]
+        lane = self._lanes[k]
+        cs = lane["stream"]
         try:
-            with self.cv:
-                st = self._ensure_state(req.stream, cs)
-            left, right = req.payload
+            t0 = time.perf_counter()
+            frames, outs = [], []
             with torch.cuda.stream(cs):
-                st["L"].copy_(torch.as_tensor(left), non_blocking=True)
-                st["R"].copy_(torch.as_tensor(right), non_blocking=True)
-                res = st["solver"](st["L"], st["R"], stream=cs)
-            cs.synchronize()
-            req.t_done = time.perf_counter()
+                for r, st in zip(batch, states):
+                    left, right = r.payload
+                    st["L"].copy_(torch.as_tensor(left), non_blocking=True)
+                    st["R"].copy_(torch.as_tensor(right), non_blocking=True)
+                    frames.append((st["L"], st["R"], self.specs[r.stream].params))
+                    outs.append(st["out"])
+                lane["solver"](frames, outputs=outs, stream=cs)   # synchronises cs at its end
+            t1 = time.perf_counter()
+            for r in batch:
+                r.t_done = t1
+            self.batches.append((k, len(batch), t1 - t0))
             if self.on_done is not None:
-                self.on_done(req, res.D_f, res.C_f, res.mask)
+                for r, st in zip(batch, states):
+                    self.on_done(r, *st["out"])
         except Exception as e:  # reported, never swallowed silently
-            req.status = -1
-            req.t_done = time.perf_counter()
-            self.errors.append(f"request {req.rid} (stream {req.stream}): {e}")
+            t1 = time.perf_counter()
+            for r in batch:
+                r.status = -1
+                r.t_done = t1
+            self.errors.append(f"batch of {len(batch)} on lane {k}: {e}")
 
     def drain(self, timeout: float = 120.0):
-        """Waits until every submitted request completed, then stops the dispatcher."""
+        """Waits until every submitted request completed, then stops the loop's threads."""
         t_end = time.perf_counter() + timeout
         with self.cv:
             self.closed = True
             self.cv.notify_all()
-            while (self.adm.queue or len(self.free_slots) < self.n_slots):
+            while self.adm.queue or any(b is not None for b in self._lane_batch):
                 if time.perf_counter() > t_end:
                     raise TimeoutError("requests still pending")
-                self.cv.wait(timeout=0.05)
+                self.cv.wait(timeout=0.02)
         self._dispatch.join(timeout=5.0)
         with self.cv:
             self._stop = True

@@ -106,3 +106,63 @@ def test_oversized_stream_rejected():
     adm = Admission(50, lambda s: 80)
     with pytest.raises(ValueError):
         adm.push(Request(0, 0, 0.0))
+
+
+def test_next_batch_takes_every_admissible_frame_once_per_stream():
+    """A free lane takes every admissible waiting frame: the oldest frame of each stream
+    that is not busy and fits the budget (after evicting idle streams), up to the batch
+    limit, in arrival order; later frames of a stream wait for its current one."""
+    sizes = {0: 10, 1: 10, 2: 10, 3: 25}
+    adm = Admission(40, lambda s: sizes[s])
+    reqs = [Request(i, s, float(i)) for i, s in enumerate([0, 0, 1, 2, 3, 1])]
+    for r in reqs:
+        adm.push(r)
+    batch, evicted = adm.next_batch(8)
+    assert [r.rid for r in batch] == [0, 2, 3]      # stream 3 does not fit beside three busy ones
+    assert evicted == [] and adm.used == 30
+    assert adm.next_batch(8) == ([], [])            # streams 0, 1, 2 are busy, 3 still waits
+    for r in batch:
+        adm.done(r)
+    batch2, _ = adm.next_batch(1)                   # the limit: the oldest admissible frame
+    assert [r.rid for r in batch2] == [1]
+    batch3, evicted3 = adm.next_batch(8)            # stream 3 evicts idle 1 and 2; then 1 cannot return
+    assert [r.rid for r in batch3] == [4] and evicted3 == [1, 2]
+    assert adm.used == 35
+    for r in batch2 + batch3:
+        adm.done(r)
+    batch4, evicted4 = adm.next_batch(8)
+    assert [r.rid for r in batch4] == [5] and evicted4 == [0]
+
+
+def test_next_batch_evicts_idle_streams_lru():
+    sizes = {s: 10 for s in range(5)}
+    adm = Admission(30, lambda s: sizes[s])
+    for i, s in enumerate([0, 1, 2]):
+        adm.push(Request(i, s, float(i)))
+    first, _ = adm.next_batch(8)
+    for r in first:
+        adm.done(r)
+    adm.push(Request(3, 3, 3.0))
+    adm.push(Request(4, 4, 4.0))
+    adm.push(Request(5, 0, 5.0))
+    batch, evicted = adm.next_batch(8)
+    assert [r.rid for r in batch] == [3, 4, 5]
+    assert evicted == [0, 1, 2] and adm.evictions == 3   # 3 evicts 0, 4 evicts 1, 0 returns evicting 2
+    assert adm.used <= 30
+
+
+def test_next_batch_several_frames_of_a_stream_in_order():
+    """With per_stream = k, a backlogged stream contributes its k oldest frames to one
+    batch (in arrival order); its later frames wait until that batch is done."""
+    adm = Admission(100, lambda s: 10)
+    order = [0, 0, 1, 0, 0, 1, 1, 1, 0]
+    reqs = [Request(i, s, float(i)) for i, s in enumerate(order)]
+    for r in reqs:
+        adm.push(r)
+    batch, _ = adm.next_batch(16, per_stream=3)
+    assert [r.rid for r in batch] == [0, 1, 2, 3, 5, 6]
+    assert adm.next_batch(16, per_stream=3) == ([], [])
+    for r in batch:
+        adm.done(r)
+    batch2, _ = adm.next_batch(16, per_stream=3)
+    assert [r.rid for r in batch2] == [4, 7, 8]
