@@ -294,11 +294,10 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
  *   frame's workspace is a buffer the library holds in device memory, one per GPU,
  *   SM_NOALLOC_MAX_BYTES large; each GPU the library runs on keeps it until the process
  *   ends. Arguments and results are those of sm_solve, except:
- *   - the frame must take the all-device path: grid candidates (support_mode = 0) and
- *     device meshes (host_mesh = 0), else SM_ERR_ARG;
+ *   - the frame must keep its meshes on the device (host_mesh = 0), else SM_ERR_ARG;
  *   - sm_solve_workspace_bytes(W, H, p) must not exceed SM_NOALLOC_MAX_BYTES, else
- *     SM_ERR_CAPACITY (640x480 with disparities 0-127 needs 13 MiB, 1280x720 with 0-255
- *     40 MiB, 1920x1080 with 0-255 88 MiB: too large);
+ *     SM_ERR_CAPACITY (640x480 with disparities 0-127 needs 7 MiB, 1920x1080 with 0-255
+ *     46 MiB, 2560x1440 with 0-255 81 MiB: too large);
  *   - a frame whose device mesh cannot be finished (an array full; sm_solve would solve it
  *     again with host meshes, which allocates) returns SM_ERR_INTERNAL and its outputs are
  *     not valid;

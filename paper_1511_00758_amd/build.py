@@ -29,6 +29,7 @@ SOURCES = [
     ("api.cpp", "hip"),
     ("batch.cpp", "hip"),
     ("mesh.hip", "hip"),
+    ("star.hip", "hip"),
     ("delaunay.cpp", "host"),
 ]
 

@@ -12,6 +12,7 @@
 #include "delaunay.hpp"
 #include "kernels.hpp"
 #include "mesh.hpp"
+#include "star.hpp"
 #include "sm_common.hpp"
 #include "stereomesh.h"
 
@@ -200,16 +201,12 @@ Layout layout_of(int32_t W, int32_t H, const sm_params& p) {
   L.S = take((size_t)L.S_cap * sizeof(sm_support));
   L.T = take((size_t)L.T_cap * sizeof(sm_tri));
   L.counters = take(64);
-  // device mesh of the frame's tessellations; its status words follow the counters, so
+  // device meshes of the frame's tessellations; their status words follow the counters, so
   // that one copy brings both back
-  L.mesh_on = p.host_mesh == 0 && (p.n_iters >= 2 || p.support_mode == 0);
+  L.mesh_on = p.host_mesh == 0;
   if (L.mesh_on) L.mstatus = take(kMeshStatusWords * sizeof(int32_t));
   L.score = p.support_mode == 1 ? take(npx) : 0;  // FAST scores
-  if (L.mesh_on) {
-    L.mpcap = 1;
-    for (int it = 1; it < p.n_iters; ++it) L.mpcap = std::max(L.mpcap, 2 * cells_of(W, H, occ_size(p, it)));
-    L.mwork = take(mesh_work_bytes(W, H, L.S_cap, L.mpcap));
-  }
+  if (L.mesh_on) L.mwork = take(star_work_bytes(W, H, L.S_cap));
   L.total = o;
   return L;
 }
@@ -227,7 +224,7 @@ struct FrameBufs {
   int32_t* counters;
   unsigned long long* n_valid;  // 32 bytes into the counters
   int32_t* mstatus;             // device mesh status words (nullptr without a device mesh)
-  MeshWork mw;
+  StarWork mw;
 };
 
 FrameBufs frame_bufs(uint8_t* base, int32_t W, int32_t H, const Layout& Lo) {
@@ -244,7 +241,7 @@ FrameBufs frame_bufs(uint8_t* base, int32_t W, int32_t H, const Layout& Lo) {
   b.counters = (int32_t*)(base + Lo.counters);
   b.n_valid = (unsigned long long*)(base + Lo.counters + 32);
   b.mstatus = Lo.mesh_on ? (int32_t*)(base + Lo.mstatus) : nullptr;
-  b.mw = Lo.mesh_on ? mesh_work_at(base + Lo.mwork, W, H, Lo.S_cap, Lo.mpcap) : MeshWork{};
+  b.mw = Lo.mesh_on ? star_work_at(base + Lo.mwork, W, H, Lo.S_cap) : StarWork{};
   return b;
 }
 
@@ -289,44 +286,34 @@ sm_status enqueue_census_match(const uint8_t* L, const uint8_t* R, int32_t W, in
   return SM_OK;
 }
 
-// The rest of a frame whose every tessellation runs on the device (grid candidates: the
-// compacted supports are in raster order, the first mesh is built on the device and every
-// later tessellation inserts into it, each mesh kernel first compacting its new supports).
+// The rest of a frame whose every tessellation runs on the device: each tessellation of
+// S_it is built from scratch by the per-point star kernels (star.hpp), after its new
+// supports are compacted (the matched candidates, then each iteration's resampled ones).
 // The counts stay on the device (read by the raster, resampling and mesh kernels), so
 // nothing here waits for the device; the caller reads the counters and status words back.
 sm_status enqueue_device_meshes(const sm_params& p, int32_t W, int32_t H, const Layout& Lo, const FrameBufs& b,
                                 float* D_f, uint8_t* C_f, uint8_t* mask, Timer& tm, hipStream_t s) {
-  auto mesh_job = [&](int32_t start, int32_t p0, const int32_t* n_new) {
-    MeshJob job;
+  auto star_job = [&](int32_t first, int32_t compact_n, int32_t* compact_count) {
+    StarJob job;
     job.S = b.S;
-    job.start = start;
-    job.p0 = p0;
-    job.n_new = n_new;
-    job.init_tv = b.mw.tv;
-    job.init_tnb = b.mw.tnb;
-    job.init_n = 0;
-    job.n_new_slot = 0;
-    job.last = 0;
-    job.compact_n = 0;
-    job.occ = nullptr;
-    job.compact_count = nullptr;
+    job.first = first;
+    job.compact_n = compact_n;
+    job.occ = b.occ;
+    job.compact_count = compact_count;
+    job.n_new = nullptr;
     job.status = b.mstatus;
     job.status_copy = nullptr;
     job.T = b.T;
     job.T_cap = Lo.T_cap;
     job.W = W;
     job.H = H;
+    job.blocks = star_blocks(Lo.S_cap);
     job.w = b.mw;
     return job;
   };
   const int32_t* counts = b.mstatus;
   SM_TRY(tm.begin(SM_ST_MESH));
-  MeshJob first = mesh_job(1, 0, (const int32_t*)(b.S + Lo.n_grid));
-  first.last = p.n_iters == 1;
-  first.compact_n = Lo.n_grid;  // the matched candidates, compacted by the kernel first
-  first.occ = b.occ;
-  first.compact_count = &b.counters[0];
-  SM_HIP(launch_mesh_insert(first, s));
+  SM_HIP(launch_star(star_job(1, Lo.n_grid, &b.counters[0]), s));  // S_1: the matched candidates
   SM_TRY(tm.end());
   for (int it = 1; it <= p.n_iters; ++it) {
     const int32_t sz = occ_size(p, it);
@@ -344,14 +331,8 @@ sm_status enqueue_device_meshes(const sm_params& p, int32_t W, int32_t H, const 
     SM_HIP(launch_resample(b.cL, b.cR, b.cell_g, b.cell_b, b.D_it, W, H, sz, p, b.S, s, counts + kMeshSupports,
                            Lo.S_cap));
     SM_TRY(tm.end());
-    MeshJob job = mesh_job(0, -1, nullptr);
-    job.n_new_slot = 2 * cells;
-    job.compact_n = 2 * cells;  // the resampled supports, compacted by the kernel first
-    job.occ = b.occ;
-    job.compact_count = &b.counters[1];
-    job.last = it == p.n_iters - 1;
-    SM_TRY(tm.begin(SM_ST_MESH));
-    SM_HIP(launch_mesh_insert(job, s));
+    SM_TRY(tm.begin(SM_ST_MESH));  // S_it+1 = S_it and the resampled supports
+    SM_HIP(launch_star(star_job(0, 2 * cells, &b.counters[1]), s));
     SM_TRY(tm.end());
   }
   return SM_OK;
@@ -366,7 +347,7 @@ void device_frame_stats(const sm_params& p, const uint8_t* span, const Layout& L
   const int32_t* ms = (const int32_t*)(span + (Lo.mstatus - Lo.counters));
   for (int k = 0; k < p.n_iters && k < 8; ++k) {
     st->n_support[k] = ms[kMeshLog + 2 * k];
-    st->n_tris[k] = ms[kMeshLog + 2 * k + 1];
+    st->n_tris[k] = star_log_tris(ms, k, p.n_iters);
   }
   st->mesh_device = p.n_iters;
   unsigned long long nv = 0;
@@ -603,56 +584,24 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   sm_tri* Td = b.T;
   int32_t* counters = b.counters;
   unsigned long long* n_valid = b.n_valid;
-  // pinned staging: [counts | supports or triangles | exported mesh | mesh status]
-  const MeshWork mw = b.mw;
+  // pinned staging: [counts | supports or triangles | mesh status]
   // (a device-mesh frame also reads its counters and status words back through this region)
   const size_t st_span = Lo.mesh_on ? status_span(Lo) : 0;
   const size_t st_main =
       align256(std::max({(size_t)Lo.S_cap * sizeof(sm_support), (size_t)Lo.T_cap * sizeof(sm_tri), st_span}));
-  const size_t st_mesh = Lo.mesh_on ? align256((size_t)mw.cap * 12) : 0;
-  SM_TRY(ensure_pinned(c, 256 + st_main + 2 * st_mesh + kMeshStatusWords * sizeof(int32_t)));
+  SM_TRY(ensure_pinned(c, 256 + st_main + kMeshStatusWords * sizeof(int32_t)));
   int32_t* h_count = (int32_t*)c.pinned;
   sm_support* h_S = (sm_support*)((uint8_t*)c.pinned + 256);
   sm_tri* h_T = (sm_tri*)((uint8_t*)c.pinned + 256);
-  int32_t* h_mtv = (int32_t*)((uint8_t*)c.pinned + 256 + st_main);
-  int32_t* h_mtnb = (int32_t*)((uint8_t*)c.pinned + 256 + st_main + st_mesh);
-  int32_t* h_mstatus = (int32_t*)((uint8_t*)c.pinned + 256 + st_main + 2 * st_mesh);
+  int32_t* h_mstatus = (int32_t*)((uint8_t*)c.pinned + 256 + st_main);
   Timer tm(c.timer, s, timing);
   float us_host = 0.f, us_xfer = 0.f;
 
-  const bool fast = p->support_mode == 1;
-  const bool device_path = Lo.mesh_on && !fast;  // grid supports, device meshes
+  const bool device_path = Lo.mesh_on;  // every tessellation on the device
   SM_TRY(enqueue_census_match(L, R, W, H, stride, *p, Lo, base, b, D_f, C_f, !device_path, tm, s));
 
-  int32_t* d_mstatus = b.mstatus;
-  bool mesh_dev = false;  // the frame's mesh lives on the device
-  int32_t mesh_init = 0;  // records of an exported host mesh, read by the first device insertion
-  auto mesh_job = [&](int32_t start, int32_t p0, const int32_t* n_new) {
-    MeshJob job;
-    job.S = Sd;
-    job.start = start;
-    job.p0 = p0;
-    job.n_new = n_new;
-    job.init_tv = mw.tv;
-    job.init_tnb = mw.tnb;
-    job.init_n = start ? 0 : mesh_init;
-    job.n_new_slot = 0;
-    job.last = 0;
-    job.compact_n = 0;
-    job.occ = nullptr;
-    job.compact_count = nullptr;
-    job.status = d_mstatus;
-    job.status_copy = nullptr;
-    job.T = Td;
-    job.T_cap = Lo.T_cap;
-    job.W = W;
-    job.H = H;
-    job.w = mw;
-    return job;
-  };
-
-  // Grid candidates with device meshes: the frame needs one synchronisation, at its end.
-  // A frame whose device mesh fails is solved again with host meshes.
+  // Device meshes: the frame needs one synchronisation, at its end. A frame whose device
+  // mesh fails is solved again with host meshes.
   if (device_path) {
     SM_TRY(enqueue_device_meshes(*p, W, H, Lo, b, D_f, C_f, mask, tm, s));
     // counters (the valid-pixel count) and status words in one copy
@@ -681,7 +630,7 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     return SM_OK;
   }
 
-  // FAST candidates or host meshes: the supports come to the host for the first mesh
+  // Host meshes (host_mesh = 1): the supports come to the host for every tessellation
   auto t0 = clk::now();
   int32_t n_S = -1, n_T = 0;
   SM_HIP(hipMemcpyAsync(h_S, Sd, (size_t)(Lo.n_grid + 1) * sizeof(sm_support), hipMemcpyDeviceToHost, s));
@@ -690,9 +639,7 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
   std::memcpy(&n_S, &h_S[Lo.n_grid], sizeof(int32_t));
   if (n_S < 0 || n_S > Lo.n_grid) return fail(SM_ERR_INTERNAL, "support count %d out of range", n_S);
 
-  int32_t host_upto = 0;  // supports S[0, host_upto) are in the host triangulation c.dl
   auto triangulate_and_upload = [&](int32_t from, int32_t to) -> sm_status {
-    host_upto = to;
     auto th = clk::now();
     try {
       if (from == 0) c.dl.reset();
@@ -726,25 +673,7 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     us_xfer += us_since(tx);
     return SM_OK;
   };
-  if (!mesh_dev) SM_TRY(triangulate_and_upload(0, n_S));
-
-  // the tessellations after the first insert their supports into the mesh kept in device
-  // memory (the triangulation is unique, so the triangles are the host's); a host mesh
-  // goes up once
-  if (Lo.mesh_on && !mesh_dev && p->n_iters >= 2) {
-    auto th = clk::now();
-    const int32_t n_rec = c.dl.export_mesh(h_mtv, h_mtnb, mw.cap);
-    us_host += us_since(th);
-    if (n_rec < 0) return fail(SM_ERR_INTERNAL, "mesh capacity exceeded");
-    if (n_rec > 0) {  // else fewer than three independent supports so far: stay on the host
-      SM_HIP(hipMemcpyAsync(mw.tv, h_mtv, (size_t)n_rec * 12, hipMemcpyHostToDevice, s));
-      SM_HIP(hipMemcpyAsync(mw.tnb, h_mtnb, (size_t)n_rec * 12, hipMemcpyHostToDevice, s));
-      SM_HIP(hipEventRecord(c.copy_done, s));
-      c.copy_pending = true;
-      mesh_dev = true;
-      mesh_init = n_rec;
-    }
-  }
+  SM_TRY(triangulate_and_upload(0, n_S));
 
   for (int it = 1; it <= p->n_iters; ++it) {
     const int32_t sz = occ_size(*p, it);
@@ -773,38 +702,6 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     SM_TRY(tm.begin(SM_ST_COMPACT));
     SM_HIP(launch_compact(region, 2 * cells, &counters[1], occ, W, (int32_t*)(region + 2 * cells), s));
     SM_TRY(tm.end());
-    if (mesh_dev) {
-      const MeshJob job = mesh_job(0, n_S, (const int32_t*)(region + 2 * cells));
-      mesh_init = 0;
-      SM_TRY(tm.begin(SM_ST_MESH));
-      SM_HIP(launch_mesh_insert(job, s));
-      SM_TRY(tm.end());
-      t0 = clk::now();
-      SM_HIP(hipMemcpyAsync(h_mstatus, d_mstatus, 32, hipMemcpyDeviceToHost, s));
-      SM_HIP(hipStreamSynchronize(s));
-      us_xfer += us_since(t0);
-      const int32_t n_new = h_mstatus[kMeshNew];
-      if (n_new < 0 || n_new > 2 * cells) return fail(SM_ERR_INTERNAL, "resample count %d out of range", n_new);
-      if (h_mstatus[kMeshErr] == 0) {
-        n_T = h_mstatus[kMeshTris];
-        if (n_T < 0 || n_T > Lo.T_cap) return fail(SM_ERR_INTERNAL, "device triangle count %d out of range", n_T);
-        n_S += n_new;
-        if (st) ++st->mesh_device;
-        continue;
-      }
-      // the device could not finish (capacity, or a support outside the mesh): bring every
-      // support the host has not seen and triangulate on the host from here on
-      if (st) ++st->mesh_fallback;
-      mesh_dev = false;
-      t0 = clk::now();
-      const int32_t m = n_S + n_new - host_upto;
-      SM_HIP(hipMemcpyAsync(h_S, Sd + host_upto, (size_t)m * sizeof(sm_support), hipMemcpyDeviceToHost, s));
-      SM_HIP(hipStreamSynchronize(s));
-      us_xfer += us_since(t0);
-      SM_TRY(triangulate_and_upload(host_upto, n_S + n_new));
-      n_S += n_new;
-      continue;
-    }
     t0 = clk::now();
     SM_HIP(hipMemcpyAsync(h_S, region, (size_t)(2 * cells + 1) * sizeof(sm_support), hipMemcpyDeviceToHost, s));
     SM_HIP(hipStreamSynchronize(s));
@@ -843,8 +740,7 @@ sm_status sm_solve_noalloc(const uint8_t* L, const uint8_t* R, int32_t W, int32_
   SM_TRY(check_params(p));
   if (!L || !R || !D_f || !C_f || !mask) return fail(SM_ERR_ARG, "only st may be NULL");
   if (stride < W) return fail(SM_ERR_ARG, "stride %d < W %d", stride, W);
-  if (p->support_mode != 0 || p->host_mesh != 0)
-    return fail(SM_ERR_ARG, "sm_solve_noalloc needs grid candidates (support_mode 0) and device meshes (host_mesh 0)");
+  if (p->host_mesh != 0) return fail(SM_ERR_ARG, "sm_solve_noalloc needs device meshes (host_mesh 0)");
   const Layout Lo = layout_of(W, H, *p);
   if (!Lo.mesh_on) return fail(SM_ERR_INTERNAL, "no device mesh in the layout");
   if (Lo.total > SM_NOALLOC_MAX_BYTES)
@@ -868,21 +764,10 @@ sm_status sm_solve_noalloc(const uint8_t* L, const uint8_t* R, int32_t W, int32_
   SM_HIP(hipMemcpyAsync(h_span, base + Lo.counters, span, hipMemcpyDeviceToHost, s));
   SM_HIP(hipStreamSynchronize(s));
   const int32_t err = ((const int32_t*)(h_span + (Lo.mstatus - Lo.counters)))[kMeshErr];
-  // a first mesh that cannot exist (fewer than three supports, or all on one line) leaves
-  // every tessellation empty, D_it NaN and nothing validated: that is the frame's result
-  if (err != 0 && err != kMeshErrNoMesh)
+  if (err != 0)
     return fail(SM_ERR_INTERNAL, "the device mesh could not finish this frame (code %d); sm_solve solves "
                 "it with host meshes", err);
-  if (st) {
-    device_frame_stats(*p, h_span, Lo, st);
-    if (err == kMeshErrNoMesh) {  // no mesh at all: the first supports stay the only ones
-      for (int k = 0; k < p->n_iters && k < 8; ++k) {
-        st->n_support[k] = st->n_support[0];
-        st->n_tris[k] = 0;
-      }
-      st->mesh_device = 0;
-    }
-  }
+  if (st) device_frame_stats(*p, h_span, Lo, st);
   return SM_OK;
 }
 
@@ -947,7 +832,7 @@ sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, 
   }
   // rasterisation with device counts (grid supports, device meshes): workgroups of the
   // bounded grid, on the frame's last mesh
-  if (Lo.mesh_on && p->support_mode == 0) {
+  if (Lo.mesh_on) {
     const int32_t* counts = (const int32_t*)(base + Lo.mstatus);
     const sm_support* Sd = (const sm_support*)(base + Lo.S);
     const sm_tri* Td = (const sm_tri*)(base + Lo.T);

@@ -17,6 +17,7 @@
 #include "delaunay.hpp"
 #include "kernels.hpp"
 #include "mesh.hpp"
+#include "star.hpp"
 #include "pool.hpp"
 #include "sm_common.hpp"
 #include "stereomesh.h"
@@ -140,7 +141,8 @@ struct ManyPlan {
   std::vector<int32_t> groups;   // distinct (rx << 8 | ry) census windows
   // device-mesh frames: their triangles (tdev_off, in triangles)
   std::vector<int32_t> tdev_off;
-  size_t desc_off = 0, off_off = 0, job_off = 0, tri_off = 0, pack_dev = 0, tdev = 0, mstat = 0, nvalid = 0, total = 0;
+  size_t desc_off = 0, off_off = 0, job_off = 0, soff_off = 0, tri_off = 0, pack_dev = 0, tdev = 0, mstat = 0,
+         nvalid = 0, total = 0;
   int32_t pack_slots = 0, tri_cap = 0, n_off_arrays = 0, tdev_cap = 0;
 };
 
@@ -183,7 +185,9 @@ sm_status plan_many(const sm_frame* frames, int32_t n, ManyPlan& P) {
   P.off_off = o;
   o += (size_t)P.n_off_arrays * (n + 1) * sizeof(int32_t);
   P.job_off = align256(o);
-  o = P.job_off + (size_t)n * sizeof(MeshJob);
+  o = P.job_off + (size_t)n * sizeof(StarJob);
+  P.soff_off = o;  // prefix sums of the star jobs' workgroups
+  o += (size_t)(n + 1) * sizeof(int32_t);
   P.tri_off = align256(o);  // desc + offsets + mesh jobs + triangles go up in one copy
   o = P.tri_off + (size_t)P.tri_cap * sizeof(sm_tri);
   P.pack_dev = align256(o);
@@ -279,7 +283,7 @@ sm_status finish_device_batch(const sm_frame* frames, int32_t n, const ManyPlan&
       st->mesh_device += iters[f];
       for (int k = 0; k < iters[f] && k < 8; ++k) {
         st->n_support[k] += w[kMeshLog + 2 * k];
-        st->n_tris[k] += w[kMeshLog + 2 * k + 1];
+        st->n_tris[k] += star_log_tris(w, k, iters[f]);
       }
     }
   }
@@ -365,8 +369,16 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
   unsigned long long* hnv = (unsigned long long*)(hp + up_bytes + pack_bytes + stat_bytes);
   uint8_t* hstage = hp + up_bytes + pack_bytes + stat_bytes + nv_bytes;
   unsigned long long* dnv = (unsigned long long*)(base + P.nvalid);
-  MeshJob* hjobs = (MeshJob*)(hp + (P.job_off - P.desc_off));
-  const MeshJob* djobs = (const MeshJob*)(base + P.job_off);
+  StarJob* hjobs = (StarJob*)(hp + (P.job_off - P.desc_off));
+  int32_t* hsoff = (int32_t*)(hp + (P.soff_off - P.desc_off));
+  const StarJob* djobs = (const StarJob*)(base + P.job_off);
+  const int32_t* dsoff = (const int32_t*)(base + P.soff_off);
+  // the workgroup offsets of jobs [0, n_jobs) (in the staged copy at h); returns their total
+  auto star_offsets = [](const StarJob* J, int32_t* o, int32_t n_jobs) {
+    o[0] = 0;
+    for (int32_t j = 0; j < n_jobs; ++j) o[j + 1] = o[j] + J[j].blocks;
+    return o[n_jobs];
+  };
   sm_tri* dTdev = (sm_tri*)(base + P.tdev);
   int32_t* dmstat = (int32_t*)(base + P.mstat);
   const BatchFrame* dF = (const BatchFrame*)(base + P.desc_off);
@@ -448,37 +460,35 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
   // in one copy
   std::vector<uint8_t> mesh_dev(n, 0), job_start;
   std::vector<int32_t> host_upto(n, 0), nT_dev(n, 0), job_frame;
-  auto add_job = [&](int32_t f, int32_t start, int32_t p0, const int32_t* n_new) {
+  auto add_job = [&](int32_t f, int32_t start, const int32_t* n_new) {
     const Layout& L = P.lay[f];
     uint8_t* b = base + P.base[f];
-    MeshJob& jb = hjobs[job_frame.size()];
+    StarJob& jb = hjobs[job_frame.size()];
     jb.S = hF[f].S;
-    jb.start = start;
-    jb.p0 = p0;
-    jb.n_new = n_new;
-    jb.init_tv = nullptr;
-    jb.init_tnb = nullptr;
-    jb.init_n = 0;
-    jb.n_new_slot = 0;
-    jb.last = 0;
+    jb.first = start;
     jb.compact_n = 0;  // the batched stages compact the supports
     jb.occ = nullptr;
     jb.compact_count = nullptr;
+    jb.n_new = n_new;
     jb.status = (int32_t*)(b + L.mstatus);
     jb.status_copy = dmstat + (size_t)kMeshStatusWords * f;
     jb.T = dTdev + P.tdev_off[f];
     jb.T_cap = L.T_cap;
     jb.W = hF[f].W;
     jb.H = hF[f].H;
-    jb.w = mesh_work_at(b + L.mwork, hF[f].W, hF[f].H, L.S_cap, L.mpcap);
+    jb.blocks = star_blocks(L.S_cap);
+    jb.w = star_work_at(b + L.mwork, hF[f].W, hF[f].H, L.S_cap);
     job_frame.push_back(f);
     job_start.push_back((uint8_t)start);
   };
   for (int32_t f = 0; f < n; ++f)
     if (P.lay[f].mesh_on) {
       mesh_dev[f] = 1;
-      add_job(f, 1, 0, (const int32_t*)(hF[f].S + hF[f].n_grid));
+      add_job(f, 1, (const int32_t*)(hF[f].S + hF[f].n_grid));
     }
+  const int32_t first_blocks = star_offsets(hjobs, hsoff, (int32_t)job_frame.size());
+  bool all_lds = true;  // every frame's star preparation fits in LDS
+  for (int32_t f = 0; f < n; ++f) all_lds &= prep_in_lds(frames[f].W, frames[f].H);
   CaptureGuard cap(s);
   if (gb) {  // everything enqueued from here to the last mesh launch goes into the graph
     SM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
@@ -501,7 +511,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
   SM_HIP(launch_batch_pack(dF, n, 0, s));
   if (!job_frame.empty()) {
     SM_TRY(arm(SM_ST_MESH));
-    SM_HIP(launch_mesh_insert_many(djobs, (int32_t)job_frame.size(), s));
+    SM_HIP(launch_star_many(djobs, dsoff, (int32_t)job_frame.size(), first_blocks, all_lds, s));
   }
 
   std::vector<int32_t> n_S(n, 0), iters(n);
@@ -522,7 +532,8 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
       std::memcpy(h, hp, P.tri_off - P.desc_off);  // static descriptors and offsets
       BatchFrame* F = (BatchFrame*)h;
       int32_t* ho = (int32_t*)(h + (P.off_off - P.desc_off));
-      MeshJob* J = (MeshJob*)(h + (P.job_off - P.desc_off));
+      StarJob* J = (StarJob*)(h + (P.job_off - P.desc_off));
+      int32_t* J_off = (int32_t*)(h + (P.soff_off - P.desc_off));
       int32_t* o_r = ho + (size_t)kRaster * (n + 1);
       int32_t* o_v = ho + (size_t)kValidate * (n + 1);
       int32_t* o_m = ho + (size_t)kRematch * (n + 1);
@@ -551,26 +562,22 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
         o_r[f + 1] = o_r[f] + (act ? kRasterUnits : 0);
         o_m[f + 1] = o_m[f] + d.region_n / 2;
         if (rs) {  // this iteration's resampled supports, compacted and inserted by the mesh kernel
-          MeshJob& jb = J[n_jobs++];
-          jb = MeshJob{};
+          StarJob& jb = J[n_jobs++];
+          jb = StarJob{};
           jb.S = d.S;
-          jb.start = 0;
-          jb.p0 = -1;  // the first new support from the status words
-          jb.n_new = nullptr;
-          jb.n_new_slot = d.region_n;
-          jb.last = it == iters[f] - 1;
+          jb.first = 0;  // the new supports start at the frame's support count on the device
           jb.compact_n = d.region_n;
           jb.occ = d.occ;
           jb.compact_count = d.counters + 1;
-          jb.init_tv = jb.init_tnb = nullptr;
-          jb.init_n = 0;
+          jb.n_new = nullptr;
           jb.status = (int32_t*)(b + L.mstatus);
           jb.status_copy = dmstat + (size_t)kMeshStatusWords * f;
           jb.T = dTdev + P.tdev_off[f];
           jb.T_cap = L.T_cap;
           jb.W = d.W;
           jb.H = d.H;
-          jb.w = mesh_work_at(b + L.mwork, d.W, d.H, L.S_cap, L.mpcap);
+          jb.blocks = star_blocks(L.S_cap);
+          jb.w = star_work_at(b + L.mwork, d.W, d.H, L.S_cap);
         }
         resample |= rs;
       }
@@ -590,6 +597,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
           &vc);
       for (int32_t f = 0; f < n; ++f)
         o_v[f + 1] = o_v[f] + (active[f] ? validate_blocks(F[f].W, F[f].H, F[f].sz, nw) : 0);
+      const int32_t it_blocks = star_offsets(J, J_off, n_jobs);
       SM_HIP(hipMemcpyAsync(base + P.desc_off, h, P.tri_off - P.desc_off, hipMemcpyHostToDevice, s));
       SM_TRY(arm(SM_ST_RASTER));
       SM_HIP(launch_batch_raster(dF, doff_arr(kRaster), n, o_r[n], s));
@@ -599,7 +607,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
       SM_TRY(arm(SM_ST_REMATCH));
       SM_HIP(launch_batch_rematch(dF, doff_arr(kRematch), n, o_m[n], s));
       SM_TRY(arm(SM_ST_MESH));
-      SM_HIP(launch_mesh_insert_many(djobs, n_jobs, s));
+      SM_HIP(launch_star_many(djobs, dsoff, n_jobs, it_blocks, all_lds, s));
     }
     if (gb) {  // the graph of the batch, then its first run
       cap.active = false;
@@ -781,7 +789,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
       d.pack_cap = d.region_n;
       d.pack = mesh_dev[f] ? nullptr : dpack + P.pack_off[f];
       if (rs && mesh_dev[f])  // this iteration's resampled supports join the device mesh
-        add_job(f, 0, n_S[f], (const int32_t*)(d.region + d.region_n));
+        add_job(f, 0, (const int32_t*)(d.region + d.region_n));
       resample |= rs;
       if (st && act && it <= 8) {
         st->n_support[it - 1] += n_S[f];
@@ -806,6 +814,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
         &vc);
     for (int32_t f = 0; f < n; ++f)
       o_v[f + 1] = o_v[f] + (active[f] ? validate_blocks(hF[f].W, hF[f].H, hF[f].sz, nw) : 0);
+    const int32_t mix_blocks = star_offsets(hjobs, hsoff, (int32_t)job_frame.size());
     t0 = std::chrono::steady_clock::now();
     SM_HIP(hipMemcpyAsync(base + P.desc_off, hp, (P.tri_off - P.desc_off) + (size_t)toff * sizeof(sm_tri),
                           hipMemcpyHostToDevice, s));
@@ -823,7 +832,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
     SM_HIP(launch_batch_pack(dF, n, 1, s));
     if (!job_frame.empty()) {
       SM_TRY(arm(SM_ST_MESH));
-      SM_HIP(launch_mesh_insert_many(djobs, (int32_t)job_frame.size(), s));
+      SM_HIP(launch_star_many(djobs, dsoff, (int32_t)job_frame.size(), mix_blocks, all_lds, s));
     }
     todo.clear();
     for (int32_t f = 0; f < n; ++f)

@@ -1,0 +1,435 @@
+// Device Delaunay triangulation by per-point stars (Sec. III-A; the steps and why they are
+// exact are in mesh_star.hpp): the preparation kernel builds the frame's bucket grid, the
+// star kernel runs one wavefront per support over the whole chip.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include "compact.hpp"
+#include "kernels.hpp"
+#include "mesh_star.hpp"
+#include "star.hpp"
+
+namespace sm {
+
+namespace {
+
+using mesh::P2;
+using star::Grid;
+using star::Region;
+
+constexpr int kPrepThreads = 1024;
+constexpr int kStarWaves = 4;      // wavefronts (supports) per star workgroup
+constexpr int kStageCap = 256;     // candidates a wavefront stages in LDS
+constexpr int32_t kNoRow = 1 << 30;
+
+__device__ __forceinline__ int32_t pack_uv(int32_t u, int32_t v) { return u | (v << 16); }
+
+// Writes the status words 0..7 and log entry k to the status and its copy (thread 0).
+__device__ void put_status(const StarJob& a, const int32_t (&w)[8], int k, int32_t log_s, int32_t log_t) {
+  for (int i = 0; i < 8; ++i) {
+    a.status[i] = w[i];
+    if (a.status_copy) a.status_copy[i] = w[i];
+  }
+  if (k >= 0 && k < 8) {
+    a.status[kMeshLog + 2 * k] = log_s;
+    a.status[kMeshLog + 2 * k + 1] = log_t;
+    if (a.status_copy) {
+      a.status_copy[kMeshLog + 2 * k] = log_s;
+      a.status_copy[kMeshLog + 2 * k + 1] = log_t;
+    }
+  }
+}
+
+// Exclusive prefix sum of cnt[0, n) into out[0, n] by one 1024-thread workgroup.
+__device__ void block_scan(const int32_t* cnt, int32_t* out, int32_t n) {
+  __shared__ int32_t wsum[kPrepThreads / 64];
+  __shared__ int32_t carry;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int32_t base = 0; base < n; base += kPrepThreads) {
+    const int32_t i = base + tid;
+    const int32_t v = i < n ? cnt[i] : 0;
+    int32_t inc = v;
+    for (int d = 1; d < 64; d <<= 1) {
+      const int32_t x = __shfl_up(inc, d);
+      if (lane >= d) inc += x;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int32_t before = carry;
+    for (int k = 0; k < w; ++k) before += wsum[k];
+    if (i < n) out[i] = before + inc - v;
+    __syncthreads();
+    if (tid == kPrepThreads - 1) carry = before + inc;
+    __syncthreads();
+  }
+  if (tid == 0) out[n] = carry;
+}
+
+// One workgroup per frame: the new supports' compaction, then the frame's bucket grid and
+// row extents over all its supports, and its status words for the star kernel. The cell
+// counts and row extents are gathered with LDS atomics when they fit (kLds), else in the
+// frame's global arrays.
+constexpr int32_t kLdsCells = 12288;  // cells (48 KiB)
+constexpr int32_t kLdsRows = 4096;    // pixel rows (2 x 16 KiB)
+
+template <bool kLds>
+__device__ void star_prep(const StarJob& a) {
+  const int tid = threadIdx.x;
+  const StarWork& w = a.w;
+  __shared__ int32_t s_p0, s_err, s_tess, s_n;
+  __shared__ int32_t s_cnt[kLds ? kLdsCells : 1];
+  __shared__ int32_t s_rmin[kLds ? kLdsRows : 1], s_rmax[kLds ? kLdsRows : 1];
+  if (tid == 0) {
+    s_p0 = a.first ? 0 : a.status[kMeshSupports];
+    s_err = a.first ? 0 : a.status[kMeshErr];
+    s_tess = a.first ? 0 : a.status[kMeshTess];
+    if (s_err == 0 && (s_p0 < 0 || s_p0 > w.S_cap || (int64_t)s_p0 + a.compact_n + 1 > w.S_cap))
+      s_err = mesh::kErrCapacity;
+  }
+  __syncthreads();
+  const int32_t p0 = s_p0;
+  if (s_err == 0 && a.compact_n > 0) {  // (a frame whose earlier tessellation failed is redone on the host)
+    compact_block(a.S + p0, a.compact_n, a.compact_count, a.occ, a.W, (int*)(a.S + p0 + a.compact_n));
+    __syncthreads();
+  }
+  if (tid == 0) {
+    int32_t n_new = 0;
+    // (no slots to compact and no device count: no new supports, e.g. a frame too small for
+    // any grid candidate)
+    if (s_err == 0) n_new = a.compact_n > 0 ? *a.compact_count : (a.n_new ? *a.n_new : 0);
+    if (s_err == 0 && (n_new < 0 || (int64_t)p0 + n_new > w.S_cap)) s_err = mesh::kErrCapacity, n_new = 0;
+    s_n = p0 + n_new;
+  }
+  __syncthreads();
+  const int32_t n = s_n;
+  const int32_t n_cells = w.gw * w.gh;
+  int32_t* cnt = kLds ? s_cnt : w.cell_cur;
+  int32_t* rmin = kLds ? s_rmin : w.row_min;
+  int32_t* rmax = kLds ? s_rmax : w.row_max;
+  if (s_err == 0) {
+    for (int32_t c = tid; c < n_cells; c += kPrepThreads) cnt[c] = 0;
+    for (int32_t v = tid; v < a.H; v += kPrepThreads) rmin[v] = kNoRow, rmax[v] = -1;
+    __syncthreads();
+    bool bad = false;
+    for (int32_t i = tid; i < n; i += kPrepThreads) {
+      const sm_support q = a.S[i];
+      if (q.u < 0 || q.v < 0 || q.u >= a.W || q.v >= a.H) {
+        bad = true;
+        continue;
+      }
+      w.uv[i] = pack_uv(q.u, q.v);
+      atomicAdd(&cnt[(q.v / star::kStarCell) * w.gw + q.u / star::kStarCell], 1);
+      atomicMin(&rmin[q.v], (int32_t)q.u);
+      atomicMax(&rmax[q.v], (int32_t)q.u);
+    }
+    if (bad) atomicCAS(&s_err, 0, mesh::kErrIndex);
+    __syncthreads();
+  }
+  if (s_err == 0) {  // (uniform: every thread reads s_err after the barrier)
+    block_scan(cnt, w.cell_start, n_cells);
+    __syncthreads();
+    for (int32_t c = tid; c < n_cells; c += kPrepThreads) cnt[c] = w.cell_start[c];  // fill cursors
+    if (kLds)
+      for (int32_t v = tid; v < a.H; v += kPrepThreads) w.row_min[v] = rmin[v], w.row_max[v] = rmax[v];
+    __syncthreads();
+    for (int32_t i = tid; i < n; i += kPrepThreads) {  // the same i as in the counting loop
+      const int32_t q = w.uv[i];
+      const int32_t c = ((q >> 16) / star::kStarCell) * w.gw + (q & 0xffff) / star::kStarCell;
+      const int32_t e = atomicAdd(&cnt[c], 1);
+      w.cell_pts[e] = i;
+      w.cell_uv[e] = q;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // the previous tessellation's triangle count is final now (kernel order): into its log
+    if (!a.first && s_tess >= 1 && s_tess <= 8) {
+      const int32_t prev = a.status[kMeshTris];
+      a.status[kMeshLog + 2 * (s_tess - 1) + 1] = prev;
+      if (a.status_copy) a.status_copy[kMeshLog + 2 * (s_tess - 1) + 1] = prev;
+    }
+    const int32_t words[8] = {0, 0, s_err, 0, n - p0, n, s_tess + 1, 0};
+    put_status(a, words, s_tess, n, 0);
+  }
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(kPrepThreads) void k_star_prep(StarJob a) {
+  star_prep<kLds>(a);
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(kPrepThreads) void k_star_prep_many(const StarJob* __restrict__ jobs) {
+  star_prep<kLds>(jobs[blockIdx.x]);
+}
+
+// A wavefront as the group of the star steps; the candidates of the current region are
+// staged in LDS when they fit.
+struct DevWave {
+  static constexpr int kN = 64;
+  int lane_;
+  int32_t* s_id;
+  int32_t* s_uv;
+  int32_t n_staged = -1;  // -1: nothing staged
+  int32_t rx0 = 0, rx1 = -1, ry0 = 0, ry1 = -1;
+
+  __device__ int lane() const { return lane_; }
+  __device__ bool any(bool b) const { return __ballot(b) != 0; }
+  __device__ uint64_t min_u64(uint64_t x) const {
+    for (int o = 32; o > 0; o >>= 1) {
+      const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, o);
+      const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), o);
+      const uint64_t y = ((uint64_t)hi << 32) | lo;
+      x = y < x ? y : x;
+    }
+    return x;
+  }
+  // every lane ends with the same winner: of two candidates, exactly one beats the other
+  __device__ void reduce_best(P2 X, P2 Y, int32_t* b, P2* B, double* t) const {
+#pragma unroll 1
+    for (int o = 32; o > 0; o >>= 1) {
+      const int32_t pb = __shfl_xor(*b, o);
+      const P2 PB{__shfl_xor(B->x, o), __shfl_xor(B->y, o)};
+      const double pt = __shfl_xor(*t, o);
+      if (star::beats(X, Y, *b, *B, *t, pb, PB, pt)) *b = pb, *B = PB, *t = pt;
+    }
+  }
+  // Visits the entries of n cell runs (row(i) gives run i), 64 runs at a time: lane i sets
+  // up run i (its two cell_start reads, all lanes at once), a prefix over the lanes places
+  // the runs end to end, and every lane then takes entries j = lane, lane + 64, ... of the
+  // chunk, finding its run by a binary search over the lanes' offsets. fn2(j, e) gets the
+  // entry's position in the chunk and its index in cell_pts / cell_uv. Control flow stays
+  // uniform (the shuffles read every lane).
+  template <class RowFn, class Fn2>
+  __device__ int32_t gather(const Grid& g, int32_t n, RowFn&& row, Fn2&& fn2) const {
+    int32_t all = 0;
+    for (int32_t base = 0; base < n; base += kN) {
+      const int32_t i = base + lane_;
+      int32_t e0 = 0, len = 0;
+      if (i < n) {
+        const star::CellRow c = row(i);
+        if (c.x0 <= c.x1) {
+          e0 = g.cell_start[c.cy * g.gw + c.x0];
+          len = g.cell_start[c.cy * g.gw + c.x1 + 1] - e0;
+        }
+      }
+      int32_t inc = len;
+      for (int d = 1; d < kN; d <<= 1) {
+        const int32_t x = __shfl_up(inc, d);
+        if (lane_ >= d) inc += x;
+      }
+      const int32_t exc = inc - len;
+      const int32_t total = __shfl(inc, kN - 1);
+      for (int32_t j0 = 0; j0 < total; j0 += kN) {
+        const int32_t j = j0 + lane_;
+        int lo = 0, hi = kN - 1;  // the last lane whose run starts at or before j
+        for (int step = 0; step < 6; ++step) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (__shfl(exc, mid) <= j) lo = mid;
+          else hi = mid - 1;
+        }
+        const int32_t e = __shfl(e0, lo) + (j - __shfl(exc, lo));
+        if (j < total) fn2(all + j, e);
+      }
+      all += total;
+    }
+    return all;
+  }
+  template <class RowFn, class Fn>
+  __device__ void for_rows(const Grid& g, int32_t n, RowFn&& row, Fn&& fn) {
+    gather(g, n, row, [&](int32_t, int32_t e) { fn(g.cell_pts[e], star::unpack(g.cell_uv[e])); });
+  }
+  // the walk's square: its points into LDS when they fit
+  __device__ void set_base(const Grid& g, const Region& r) {
+    if (n_staged >= 0 && r.x0 == rx0 && r.x1 == rx1 && r.y0 == ry0 && r.y1 == ry1) return;
+    rx0 = r.x0, rx1 = r.x1, ry0 = r.y0, ry1 = r.y1;
+    int32_t* sid = s_id;
+    int32_t* suv = s_uv;
+    n_staged = gather(g, r.y1 - r.y0 + 1, star::RegionRows{r}, [&](int32_t j, int32_t e) {
+      if (j < kStageCap) sid[j] = g.cell_pts[e], suv[j] = g.cell_uv[e];
+    });
+    // the wavefront's LDS writes before any lane reads another lane's entries
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  template <class Fn>
+  __device__ void for_candidates(const Grid& g, const Region& r, Fn&& fn) {
+    if (n_staged >= 0 && n_staged <= kStageCap && r.x0 == rx0 && r.x1 == rx1 && r.y0 == ry0 && r.y1 == ry1) {
+      for (int32_t j = lane_; j < n_staged; j += kN) fn(s_id[j], star::unpack(s_uv[j]));
+    } else {
+      for_rows(g, r.y1 - r.y0 + 1, star::RegionRows{r}, fn);
+    }
+  }
+};
+
+// Triangles of one star: lane k holds the k-th pending one; a full set of 64 (or the end)
+// reserves its slots with one atomic and is written by the lanes together.
+struct DevOut {
+  int lane;
+  int32_t p;
+  sm_tri* T;
+  int32_t T_cap;
+  int32_t* counter;
+  int32_t* counter_copy;  // nullable: the same count in the status copy
+  int32_t* err;
+  int32_t n = 0, total = 0;
+  int32_t my1 = 0, my2 = 0;
+  __device__ void begin() { n = 0; }
+  __device__ void flush() {
+    if (n == 0) return;
+    int32_t slot = 0;
+    if (lane == 0) {
+      slot = atomicAdd(counter, n);
+      if (counter_copy) atomicAdd(counter_copy, n);
+    }
+    slot = __shfl(slot, 0);
+    if (lane < n) {
+      if (slot + lane < T_cap) T[slot + lane] = sm_tri{p, my1, my2};
+      else atomicCAS(err, 0, mesh::kErrCapacity);
+    }
+    total += n;
+    n = 0;
+  }
+  __device__ void emit(int32_t i1, int32_t i2) {
+    if (lane == n) my1 = i1, my2 = i2;
+    if (++n == DevWave::kN) flush();
+  }
+  __device__ int32_t finish() {
+    flush();
+    return total;
+  }
+};
+
+__device__ void star_wave(const StarJob& a, int32_t local_wave) {
+  __shared__ int32_t s_id[kStarWaves][kStageCap];
+  __shared__ int32_t s_uv[kStarWaves][kStageCap];
+  const int lane = threadIdx.x & 63, wv_i = threadIdx.x >> 6;
+  int32_t* status = a.status;
+  const int32_t n = status[kMeshSupports];
+  const int32_t err0 = status[kMeshErr];
+  const int32_t p = local_wave;
+  if (err0 != 0 || p >= n || n > a.w.S_cap) return;
+  const StarWork& w = a.w;
+  const Grid g{w.uv, n, a.W, a.H, w.gw, w.gh, w.cell_start, w.cell_pts, w.cell_uv, w.row_min, w.row_max};
+  DevWave wv{lane, s_id[wv_i], s_uv[wv_i]};
+  DevOut out{lane, p, a.T, a.T_cap, &status[kMeshTris], a.status_copy ? &a.status_copy[kMeshTris] : nullptr,
+             &status[kMeshErr]};
+  const int32_t r = star::star_of(wv, g, p, out);
+  if (r < 0 && lane == 0) {  // the frame goes to the host
+    atomicCAS(&status[kMeshErr], 0, -r);
+    if (a.status_copy) atomicCAS(&a.status_copy[kMeshErr], 0, -r);
+  }
+}
+
+__global__ __launch_bounds__(64 * kStarWaves) void k_star(StarJob a) {
+  star_wave(a, blockIdx.x * kStarWaves + (threadIdx.x >> 6));
+}
+
+__global__ __launch_bounds__(64 * kStarWaves) void k_star_many(const StarJob* __restrict__ jobs,
+                                                               const int32_t* __restrict__ offs, int32_t n_jobs) {
+  // the job of this workgroup: the last j with offs[j] <= blockIdx.x
+  int32_t lo = 0, hi = n_jobs - 1;
+  const int32_t b = blockIdx.x;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const StarJob a = jobs[lo];
+  star_wave(a, (b - offs[lo]) * kStarWaves + (threadIdx.x >> 6));
+}
+
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Carve {
+  size_t o = 0;
+  uint8_t* base = nullptr;
+  template <class T>
+  T* take(size_t n) {
+    T* p = base ? (T*)(base + o) : nullptr;
+    o = align256(o + n * sizeof(T));
+    return p;
+  }
+};
+
+StarWork carve(Carve& c, int32_t W, int32_t H, int32_t S_cap) {
+  StarWork w;
+  w.gw = (W + star::kStarCell - 1) / star::kStarCell;
+  w.gh = (H + star::kStarCell - 1) / star::kStarCell;
+  const size_t cells = (size_t)w.gw * w.gh;
+  w.uv = c.take<int32_t>((size_t)S_cap);
+  w.cell_start = c.take<int32_t>(cells + 1);
+  w.cell_cur = c.take<int32_t>(cells);
+  w.cell_pts = c.take<int32_t>((size_t)S_cap);
+  w.cell_uv = c.take<int32_t>((size_t)S_cap);
+  w.row_min = c.take<int32_t>((size_t)H);
+  w.row_max = c.take<int32_t>((size_t)H);
+  w.S_cap = S_cap;
+  return w;
+}
+
+}  // namespace
+
+bool prep_in_lds(int32_t W, int32_t H) {
+  const int64_t cells =
+      (int64_t)((W + star::kStarCell - 1) / star::kStarCell) * ((H + star::kStarCell - 1) / star::kStarCell);
+  return cells <= kLdsCells && H <= kLdsRows;
+}
+
+size_t star_work_bytes(int32_t W, int32_t H, int32_t S_cap) {
+  Carve c;
+  carve(c, W, H, S_cap);
+  return c.o;
+}
+
+StarWork star_work_at(void* base, int32_t W, int32_t H, int32_t S_cap) {
+  Carve c;
+  c.base = (uint8_t*)base;
+  return carve(c, W, H, S_cap);
+}
+
+int32_t star_blocks(int32_t S_cap) { return (S_cap + kStarWaves - 1) / kStarWaves; }
+
+hipError_t launch_star(const StarJob& job, hipStream_t s) {
+  hipEvent_t e0, e1;
+  const bool timed = take_launch_events(&e0, &e1);
+  const bool lds = prep_in_lds(job.W, job.H);
+  if (timed)
+    hipExtLaunchKernelGGL(lds ? k_star_prep<true> : k_star_prep<false>, dim3(1), dim3(kPrepThreads), 0, s, e0,
+                          nullptr, 0u, job);
+  else
+    hipLaunchKernelGGL(lds ? k_star_prep<true> : k_star_prep<false>, dim3(1), dim3(kPrepThreads), 0, s, job);
+  if (job.blocks > 0) {
+    if (timed)
+      hipExtLaunchKernelGGL(k_star, dim3((unsigned)job.blocks), dim3(64 * kStarWaves), 0, s, nullptr, e1, 0u, job);
+    else
+      hipLaunchKernelGGL(k_star, dim3((unsigned)job.blocks), dim3(64 * kStarWaves), 0, s, job);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_star_many(const StarJob* jobs, const int32_t* offs, int32_t n, int32_t total_blocks,
+                            bool lds, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipEvent_t e0, e1;
+  const bool timed = take_launch_events(&e0, &e1);
+  if (timed)
+    hipExtLaunchKernelGGL(lds ? k_star_prep_many<true> : k_star_prep_many<false>, dim3((unsigned)n),
+                          dim3(kPrepThreads), 0, s, e0, nullptr, 0u, jobs);
+  else
+    hipLaunchKernelGGL(lds ? k_star_prep_many<true> : k_star_prep_many<false>, dim3((unsigned)n), dim3(kPrepThreads),
+                       0, s, jobs);
+  if (total_blocks > 0) {
+    if (timed)
+      hipExtLaunchKernelGGL(k_star_many, dim3((unsigned)total_blocks), dim3(64 * kStarWaves), 0, s, nullptr, e1, 0u,
+                            jobs, offs, n);
+    else
+      hipLaunchKernelGGL(k_star_many, dim3((unsigned)total_blocks), dim3(64 * kStarWaves), 0, s, jobs, offs, n);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace sm

@@ -11,6 +11,8 @@
 // stdout: per batch: "batch k n_tris status", then n_tris lines "i0 i1 i2" (sorted)
 // Mode 3 checks the predicates instead: n_batches lines of four points (a, b, c, d); each
 // output line holds the in-circle filter's verdict and the perturbed in-circle sign.
+// Mode 4 triangulates every batch's points so far from scratch by per-point stars
+// (mesh_star.hpp: bucket grid, row extents, one star per point, one lane).
 #define __host__
 #define __device__
 #include <algorithm>
@@ -21,6 +23,7 @@
 #include "delaunay.hpp"
 #include "mesh_core.hpp"
 #include "mesh_start.hpp"
+#include "mesh_star.hpp"
 
 using namespace sm;
 using namespace sm::mesh;
@@ -47,6 +50,71 @@ struct Seq {
   }
 };
 
+// One-lane group for the star steps: reductions are the identity.
+struct HostWave {
+  static constexpr int kN = 1;
+  int lane() const { return 0; }
+  bool any(bool b) const { return b; }
+  uint64_t min_u64(uint64_t x) const { return x; }
+  void reduce_best(P2, P2, int32_t*, P2*, double*) const {}
+  template <class RowFn, class Fn>
+  void for_rows(const star::Grid& g, int32_t n, RowFn&& row, Fn&& fn) const {
+    for (int32_t i = 0; i < n; ++i) {
+      const star::CellRow c = row(i);
+      if (c.x0 > c.x1) continue;
+      for (int32_t e = g.cell_start[c.cy * g.gw + c.x0]; e < g.cell_start[c.cy * g.gw + c.x1 + 1]; ++e)
+        fn(g.cell_pts[e], star::unpack(g.cell_uv[e]));
+    }
+  }
+  template <class Fn>
+  void for_candidates(const star::Grid& g, const star::Region& r, Fn&& fn) const {
+    for_rows(g, r.y1 - r.y0 + 1, star::RegionRows{r}, fn);
+  }
+  void set_base(const star::Grid&, const star::Region&) const {}
+};
+struct HostOut {  // triangles of one point's star, appended to `all` when it is complete
+  std::vector<sm_tri>* all;
+  int32_t p;
+  std::vector<sm_tri> buf;
+  void begin() { buf.clear(); }
+  void emit(int32_t i1, int32_t i2) { buf.push_back(sm_tri{p, i1, i2}); }
+  int32_t finish() {
+    all->insert(all->end(), buf.begin(), buf.end());
+    return (int32_t)buf.size();
+  }
+};
+
+// Delaunay triangles of points uv[0, n) by per-point stars; status 0 or an error code.
+int star_mesh(const std::vector<int32_t>& uv, int W, int H, std::vector<sm_tri>& out) {
+  const int32_t n = (int32_t)uv.size();
+  const int32_t C = star::kStarCell, gw = (W + C - 1) / C, gh = (H + C - 1) / C;
+  std::vector<int32_t> start(gw * gh + 1, 0), pts(n), cuv(n), rmin(H, 1 << 30), rmax(H, -1);
+  for (int32_t i = 0; i < n; ++i) {
+    const P2 q = star::unpack(uv[i]);
+    ++start[(q.y / C) * gw + q.x / C + 1];
+    rmin[q.y] = std::min(rmin[q.y], q.x);
+    rmax[q.y] = std::max(rmax[q.y], q.x);
+  }
+  for (int32_t c = 0; c < gw * gh; ++c) start[c + 1] += start[c];
+  std::vector<int32_t> cur(start.begin(), start.end() - 1);
+  for (int32_t i = n - 1; i >= 0; --i) {  // any order within a cell gives the same result
+    const P2 q = star::unpack(uv[i]);
+    const int32_t e = cur[(q.y / C) * gw + q.x / C]++;
+    pts[e] = i;
+    cuv[e] = uv[i];
+  }
+  star::Grid g{uv.data(), n, W, H, gw, gh, start.data(), pts.data(), cuv.data(), rmin.data(), rmax.data()};
+  for (int32_t p = 0; p < n; ++p) {
+    HostOut o{&out, p, {}};
+    const size_t before = out.size();
+    HostWave wv;
+    const int32_t r = star::star_of(wv, g, p, o);
+    if (r < 0) return -r;
+    if (out.size() - before != (size_t)r) return 99;
+  }
+  return 0;
+}
+
 struct Arrays {
   std::vector<int32_t> tv, tnb, own, kids, dead, fk, fs, fj, work[2], pend[2], ploc, pk, psib, uv;
   std::vector<uint64_t> vote, fkey, pkey;
@@ -63,6 +131,29 @@ int main() {
       for (auto& p : q)
         if (scanf("%d %d", &p.x, &p.y) != 2) return 2;
       printf("%d %d\n", incircle_filter(q[0], q[1], q[2], q[3]), incircle_sos(q[0], q[1], q[2], q[3]));
+    }
+    return 0;
+  }
+  if (mode == 4) {  // per-point stars over every batch's points so far
+    std::vector<int32_t> uv;
+    for (int b = 0; b < nb; ++b) {
+      int n;
+      if (scanf("%d", &n) != 1) return 2;
+      for (int i = 0; i < n; ++i) {
+        int u, v;
+        if (scanf("%d %d", &u, &v) != 2) return 2;
+        uv.push_back(pack_uv(u, v));
+      }
+      std::vector<sm_tri> out;
+      const int status = star_mesh(uv, W, H, out);
+      std::sort(out.begin(), out.end(), [](const sm_tri& x, const sm_tri& y) {
+        if (x.i0 != y.i0) return x.i0 < y.i0;
+        if (x.i1 != y.i1) return x.i1 < y.i1;
+        return x.i2 < y.i2;
+      });
+      printf("batch %d %zu %d\n", b, status ? (size_t)0 : out.size(), status);
+      if (!status)
+        for (const sm_tri& t : out) printf("%d %d %d\n", t.i0, t.i1, t.i2);
     }
     return 0;
   }

@@ -42,8 +42,7 @@ def _check(sc, prm):
         assert (a.view(np.uint8) == b.view(np.uint8)).all()
     assert host[3]["mesh_device"] == 0
     assert dev[3]["mesh_fallback"] == 0
-    if dev[3]["n_tris"][0] > 0:  # grid supports: every tessellation on the device
-        assert dev[3]["mesh_device"] == (n_iters if prm.get("support_mode", 0) == 0 else n_iters - 1)
+    assert dev[3]["mesh_device"] == n_iters  # every tessellation on the device (grid or FAST supports)
     return dev[3]
 
 

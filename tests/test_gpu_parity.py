@@ -418,11 +418,9 @@ def _compare_solve(sc, p, res, tr):
     assert np.abs(D_f - tr["D_f"]).max() <= TOL_PX
     assert (D_f.view(np.uint32) == tr["D_f"].view(np.uint32)).all()
     assert st["n_valid"] == int(tr["mask"].sum())
-    # with grid supports every tessellation ran on the device; with FAST supports every one
-    # after the first (once the first mesh existed)
+    # every tessellation ran on the device, with grid or FAST supports
     assert st["mesh_fallback"] == 0
-    if len(tr["iters"][0]["tris"]) > 0:
-        assert st["mesh_device"] == (p.n_iters if p.support_mode == 0 else p.n_iters - 1)
+    assert st["mesh_device"] == p.n_iters
 
 
 @pytest.mark.parametrize("cfg", [1, 2, 3])

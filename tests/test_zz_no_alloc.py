@@ -80,7 +80,7 @@ def test_noalloc_refuses_before_work():
     from paper_1511_00758_amd import _lib
     L = _lib.load()
     prm = scenes.params_of(5)
-    W, H = 1920, 1080
+    W, H = 2560, 1440
     assert L.sm_solve_workspace_bytes(W, H, _lib.make_params(prm)) > _lib.NOALLOC_MAX_BYTES
     img = torch.zeros((H, W), dtype=torch.uint8, device=DEV)
     out = torch.zeros((H, W), dtype=torch.float32, device=DEV)
@@ -89,7 +89,7 @@ def test_noalloc_refuses_before_work():
     st = L.sm_solve_noalloc(img.data_ptr(), img.data_ptr(), W, H, W, _lib.make_params(prm), out.data_ptr(),
                             u8.data_ptr(), u8.data_ptr(), None, s)
     assert st == _lib.SM_ERR_CAPACITY and b"sm_solve_noalloc" in L.sm_last_error()
-    for over in (dict(support_mode=1), dict(host_mesh=1)):
+    for over in (dict(host_mesh=1),):
         st = L.sm_solve_noalloc(img.data_ptr(), img.data_ptr(), 320, 240, 320,
                                 _lib.make_params(dict(scenes.params_of(1), **over)), out.data_ptr(),
                                 u8.data_ptr(), u8.data_ptr(), None, s)
