@@ -32,7 +32,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 39.32 T int32 lane-ops/s
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1511_00758_amd", "csrc", f)
-                  for f in ("kernels.hip", "kernels.hpp", "mesh.hip", "mesh.hpp", "mesh_core.hpp", "mesh_start.hpp")]
+                  for f in ("kernels.hip", "kernels.hpp", "star.hip", "star.hpp", "mesh_star.hpp", "predicates.hpp")]
 
 
 def progress(msg):
@@ -53,16 +53,16 @@ def algorithmic_work(kernel, W, H, p, n_iters, launches, stats=None):
     launches of one solve), as (bound, amount, unit_scale, unit, per_unit_note)."""
     npx = W * H
     if kernel == "mesh":
-        # one tessellation (the first mesh or an insertion): the supports read (8 B each),
-        # the live mesh records read and written once (tv + tnb, 24 B each, about one per
-        # triangle) and the triangles written (12 B each); a single workgroup whose rounds
-        # are bound by instruction issue, so the fraction of HBM peak is tiny by construction
+        # one tessellation (preparation + star kernel): the supports read (8 B each) and the
+        # triangles written (12 B each). The bucket grid the preparation writes and the star
+        # kernel reads back is the method's own overhead, not counted; the star kernel is
+        # bound by the latency of its gathers, so the fraction of HBM peak is small
         if not stats:
             return None
-        per = [8.0 * stats["n_support"][k] + 60.0 * stats["n_tris"][k] for k in range(n_iters)]
+        per = [8.0 * stats["n_support"][k] + 12.0 * stats["n_tris"][k] for k in range(n_iters)]
         amount = sum(per) / len(per)
         return "hbm", amount, 1e9, "GB/s", (f"mean over tessellations 1..{n_iters}: 8 B x supports + "
-                                            f"(2 x 24 + 12) B x triangles = {amount / 1e3:.1f} kB")
+                                            f"12 B x triangles = {amount / 1e3:.1f} kB")
     bits = p["census_w"] * p["census_h"] - 1
     if kernel == "census":
         # 2 images x (1 B read + 8 B census word written) -- but compute-bound:
@@ -547,7 +547,7 @@ def main():
     ap.add_argument("--no-probe", action="store_true",
                     help="skip the 7680x4320 interpolation/validation roofline probe")
     ap.add_argument("--time-all", action="store_true",
-                    help="time every kernel of the solve with events (default: validate, raster and the mesh insertion)")
+                    help="time every kernel of the solve with events (default: validate, raster and the mesh)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the FAST-support / 3-level variants of the 640x480 workload")
     ap.add_argument("--probe-only", action="store_true",
@@ -598,7 +598,7 @@ def main():
     # later launch of the run (outputs do not depend on them)
     tuned = None if args.no_autotune else solver.autotune(*dframes[0])
     progress(f"autotune: {tuned}")
-    # live timing of the dominant kernel (the mesh insertion) inside the timed region; an
+    # live timing of the dominant kernel (the mesh) inside the timed region; an
     # event pair around a launch costs ~4 us of frame time, so validation and the raster are
     # timed in a pass of their own after it (--time-all times every kernel in the loop)
     timing = False if args.no_timing else (True if args.time_all else ("mesh",))

@@ -81,11 +81,12 @@ typedef struct {
   int32_t fast_per_bin;        /* FAST: at most this many keypoints per bin, 1..4096;
                                   fast_bins_x * fast_bins_y * fast_per_bin <= 2^22            */
   int32_t levels;              /* disparity levels tested by cost evaluation: 1 (Alg. 2), 3, 5 */
-  int32_t host_mesh;           /* 0 = every tessellation on the device: the first mesh is built
-                                  there from the matched supports and each later tessellation
-                                  inserts the resampled supports into it (a frame the device
-                                  cannot finish is solved again with host meshes); 1 = every
-                                  tessellation on the host. Same triangles either way.        */
+  int32_t host_mesh;           /* 0 = every tessellation on the device: each one is built there
+                                  from all supports so far, one Delaunay star per support (a
+                                  frame the device cannot finish is solved again with host
+                                  meshes); 1 = every tessellation on the host, which inserts
+                                  the new supports into the previous mesh. Same triangles
+                                  either way.                                                 */
 } sm_params;
 
 /* Per-solve statistics. `timing` is an input: when non-zero, sm_solve records a pair of
@@ -103,7 +104,7 @@ typedef enum {
   SM_ST_VALIDATE = 4,        /* cost evaluation + refinement                                 */
   SM_ST_REMATCH = 5,         /* resampling: cells -> confident supports + re-matched pixels  */
   SM_ST_FAST = 6,            /* FAST scores + per-bin keypoint selection (support_mode 1)     */
-  SM_ST_MESH = 7,            /* device Delaunay tessellations (first mesh and insertions)     */
+  SM_ST_MESH = 7,            /* device Delaunay tessellations (grid and per-point stars)      */
   SM_ST_HOST_TRI = 12,       /* host triangulation (wall time)                               */
   SM_ST_HOST_COPY = 13,      /* host<->device copies and waits (wall time)                   */
   SM_ST_TOTAL = 14           /* whole sm_solve call (wall time)                              */
@@ -268,9 +269,9 @@ size_t sm_solve_workspace_bytes(int32_t W, int32_t H, const sm_params* p /* [hos
  *   support_mode = 1 the FAST keypoints of sm_fast_candidates); G(S_1); then for
  *   it = 1..n_iters:
  *   interpolation, cost evaluation, refinement with sz_occ = max(1, sz_occ0 >> (it-1)),
- *   and, unless it is the last iteration, resampling and re-triangulation (the new
- *   supports are inserted into the existing triangulation, which yields the same unique
- *   triangulation as a rebuild).
+ *   and, unless it is the last iteration, resampling and re-triangulation (the
+ *   triangulation of all supports so far is unique: the host inserts the new supports into
+ *   the previous mesh, the device rebuilds it, and both give the same triangles).
  *   L, R     [H][stride] uint8 left / right images.
  *   ws       workspace of ws_bytes >= sm_solve_workspace_bytes(W, H, p), 256-byte aligned.
  *   D_f      [H][W] float32 out (0 where never validated).
@@ -330,12 +331,9 @@ typedef struct {
 /*
  * sm_solve_batch -- Alg. 1 on many independent frames at once: n_workers host threads,
  *   each with its own stream and workspace, take frames from a shared counter and run
- *   sm_solve on them, so that the host triangulation of one frame overlaps the kernels
- *   and triangulations of the others. Each frame's result is identical to sm_solve of
- *   that frame alone. The workers persist between calls made by the same thread. With
- *   more than one worker the frames triangulate on the host (p.host_mesh is taken as 1:
- *   a device insertion is one long single-workgroup kernel per tessellation, and those of
- *   many streams would serialise on the device's hardware queues).
+ *   sm_solve on them, so that the host work of one frame overlaps the kernels of the
+ *   others. Each frame's result is identical to sm_solve of that frame alone. The workers
+ *   persist between calls made by the same thread.
  *   frames     [host] [n] frames; status, worker and latency_us are written.
  *   streams    [host] [n_workers] hipStream_t per worker (as void*).
  *   ws, ws_bytes [host] [n_workers] workspace per worker; each must cover

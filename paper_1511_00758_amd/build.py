@@ -28,7 +28,6 @@ SOURCES = [
     ("kernels.hip", "hip"),
     ("api.cpp", "hip"),
     ("batch.cpp", "hip"),
-    ("mesh.hip", "hip"),
     ("star.hip", "hip"),
     ("delaunay.cpp", "host"),
 ]

@@ -11,7 +11,6 @@
 
 #include "delaunay.hpp"
 #include "kernels.hpp"
-#include "mesh.hpp"
 #include "star.hpp"
 #include "sm_common.hpp"
 #include "stereomesh.h"
@@ -613,11 +612,10 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     us_xfer += us_since(t1);
     std::memcpy(h_mstatus, h_span + (Lo.mstatus - Lo.counters), kMeshStatusWords * sizeof(int32_t));
     if (h_mstatus[kMeshErr] != 0) {  // the frame again, every tessellation on the host
-      const bool failure = h_mstatus[kMeshErr] != kMeshErrNoMesh;
       sm_params q = *p;
       q.host_mesh = 1;
       const sm_status r = sm_solve(L, R, W, H, stride, &q, ws, ws_bytes, D_f, C_f, mask, st, stream);
-      if (st && failure) ++st->mesh_fallback;
+      if (st) ++st->mesh_fallback;
       return r;
     }
     if (st) {

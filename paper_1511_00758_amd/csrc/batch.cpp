@@ -16,7 +16,6 @@
 
 #include "delaunay.hpp"
 #include "kernels.hpp"
-#include "mesh.hpp"
 #include "star.hpp"
 #include "pool.hpp"
 #include "sm_common.hpp"
@@ -72,11 +71,7 @@ extern "C" sm_status sm_solve_batch(sm_frame* frames, int32_t n, void* const* st
       sm_stats one;
       std::memset(&one, 0, sizeof(one));
       one.timing = wst[k].timing;
-      // concurrent workers triangulate on the host: a device insertion is one long
-      // single-workgroup kernel, and those of many streams serialise on the hardware queues
-      sm_params p = f.p;
-      if (workers > 1) p.host_mesh = 1;
-      f.status = sm_solve(f.L, f.R, f.W, f.H, f.stride, &p, ws[k], ws_bytes[k], f.D_f, f.C_f, f.mask,
+      f.status = sm_solve(f.L, f.R, f.W, f.H, f.stride, &f.p, ws[k], ws_bytes[k], f.D_f, f.C_f, f.mask,
                           st ? &one : nullptr, streams[k]);
       f.worker = k;
       f.latency_us = std::chrono::duration<float, std::micro>(std::chrono::steady_clock::now() - t0).count();
@@ -269,7 +264,7 @@ sm_status finish_device_batch(const sm_frame* frames, int32_t n, const ManyPlan&
                                    fr.C_f, fr.mask, &one, s);
       if (r != SM_OK) return fail(r, "frame %d: %s", f, last_error().c_str());
       if (st) {
-        if (w[kMeshErr] != kMeshErrNoMesh) ++st->mesh_fallback;
+        ++st->mesh_fallback;
         st->n_valid += one.n_valid;
         for (int k = 0; k < iters[f] && k < 8; ++k) {
           st->n_support[k] += one.n_support[k];
@@ -722,10 +717,10 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
         if (st) ++st->mesh_device;
         continue;
       }
-      // the device could not finish this frame (or found no mesh in its first supports): its
-      // host mesh takes every support so far, and the frame stays on the host
+      // the device could not finish this frame: its host mesh takes every support so far, and
+      // the frame stays on the host
       mesh_dev[f] = 0;
-      if (st && w[kMeshErr] != kMeshErrNoMesh) ++st->mesh_fallback;
+      if (st) ++st->mesh_fallback;
       SM_TRY(host_catch_up(f, n_S[f] + n_new));
       n_S[f] += n_new;
     }

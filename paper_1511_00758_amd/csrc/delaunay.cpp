@@ -416,23 +416,4 @@ void Delaunay::emit_banded(std::vector<sm_tri>& out, int band_shift) const {
   }
 }
 
-int32_t Delaunay::export_mesh(int32_t* tv, int32_t* tnb, int32_t cap) const {
-  if (!started_) return 0;
-  remap_.assign(tri_.size(), -1);
-  int32_t n = 0;
-  for (size_t t = 0; t < tri_.size(); ++t)
-    if (alive_[t]) remap_[t] = n++;
-  if (n > cap) return -1;
-  for (size_t t = 0; t < tri_.size(); ++t) {
-    if (!alive_[t]) continue;
-    const int32_t r = remap_[t];
-    for (int k = 0; k < 3; ++k) {
-      const int32_t v = tri_[t].v[k];
-      tv[3 * r + k] = v == kGhost ? kGhost : ext_[v];
-      tnb[3 * r + k] = remap_[tri_[t].nb[k]];
-    }
-  }
-  return n;
-}
-
 }  // namespace sm

@@ -41,11 +41,6 @@ class Delaunay {
   // Same triangles ordered by the row band (top row >> band_shift) of their first
   // vertex (a counting sort): spatially coherent work for the rasteriser.
   void emit_banded(std::vector<sm_tri>& out, int band_shift) const;
-  // Writes the live triangles, ghosts included, as flat records for further insertion
-  // elsewhere: tv[3r..3r+2] = vertices as external indices (kGhost kept in slot 2 of a
-  // ghost), tnb[3r + k] = record across the edge opposite vertex k. Returns the record
-  // count: 0 while no three points are affinely independent, -1 if cap is too small.
-  int32_t export_mesh(int32_t* tv, int32_t* tnb, int32_t cap) const;
   int32_t n_points() const { return (int32_t)pt_.size(); }
   int32_t n_solid() const { return n_solid_; }
 
@@ -74,7 +69,6 @@ class Delaunay {
   std::vector<uint32_t> key_, key2_;  // insertion-order keys (radix sort buffers)
   std::vector<int32_t> idx_, idx2_;
   mutable std::vector<int32_t> band_count_;
-  mutable std::vector<int32_t> remap_;
   uint32_t gen_ = 0;
   int32_t hint_ = -1;
   int32_t n_solid_ = 0;

@@ -3,7 +3,7 @@
 // sequential CPU driver of the tests.
 //
 // The Delaunay triangulation under the perturbed in-circle test (simulation of simplicity on
-// the lifted heights, the rule of mesh_core.hpp and of the host triangulation) is unique, so
+// the lifted heights, the rule of predicates.hpp and of the host triangulation) is unique, so
 // the triangles around each point -- its star -- can be computed for every point on its own,
 // with no shared mesh and no rounds:
 //   1. the point's nearest neighbour q (smallest squared distance, then smallest id) is a
@@ -41,20 +41,28 @@
 #include <cmath>
 #include <cstdint>
 
-#include "mesh_core.hpp"
+#include "predicates.hpp"
 
 namespace sm {
 namespace star {
 
-using mesh::P2;
-using mesh::incircle_sos;
-using mesh::orient;
+using geom::P2;
+using geom::incircle_sos;
+using geom::orient;
 
 constexpr int32_t kStarCell = 16;      // bucket cell side, px
 constexpr int32_t kStarMaxSteps = 4096;  // bound on a walk around one point
 constexpr double kDiskMargin = 2.0;      // px added around a disk's computed extent
 
-enum : int32_t { kStarOk = 0, kStarErrDup = 20, kStarErrSteps = 21, kStarErrIndex = 22 };
+// error codes of a frame's status word (0: ok); any of them sends the frame's meshes to the host
+enum : int32_t {
+  kStarOk = 0,
+  kStarErrDup = 20,       // two supports on one pixel
+  kStarErrSteps = 21,     // a walk around one point did not close within kStarMaxSteps
+  kStarErrIndex = 22,     // a point id outside the frame's supports
+  kStarErrCapacity = 23,  // more supports or triangles than the frame's arrays hold
+  kStarErrSupport = 24    // a support outside the frame
+};
 
 struct Grid {
   const int32_t* uv;          // [n] packed coordinates u | v << 16

@@ -13,7 +13,7 @@ namespace sm {
 
 namespace {
 
-using mesh::P2;
+using geom::P2;
 using star::Grid;
 using star::Region;
 
@@ -86,7 +86,7 @@ __device__ void star_prep(const StarJob& a) {
     s_err = a.first ? 0 : a.status[kMeshErr];
     s_tess = a.first ? 0 : a.status[kMeshTess];
     if (s_err == 0 && (s_p0 < 0 || s_p0 > w.S_cap || (int64_t)s_p0 + a.compact_n + 1 > w.S_cap))
-      s_err = mesh::kErrCapacity;
+      s_err = star::kStarErrCapacity;
   }
   __syncthreads();
   const int32_t p0 = s_p0;
@@ -99,7 +99,7 @@ __device__ void star_prep(const StarJob& a) {
     // (no slots to compact and no device count: no new supports, e.g. a frame too small for
     // any grid candidate)
     if (s_err == 0) n_new = a.compact_n > 0 ? *a.compact_count : (a.n_new ? *a.n_new : 0);
-    if (s_err == 0 && (n_new < 0 || (int64_t)p0 + n_new > w.S_cap)) s_err = mesh::kErrCapacity, n_new = 0;
+    if (s_err == 0 && (n_new < 0 || (int64_t)p0 + n_new > w.S_cap)) s_err = star::kStarErrCapacity, n_new = 0;
     s_n = p0 + n_new;
   }
   __syncthreads();
@@ -124,7 +124,7 @@ __device__ void star_prep(const StarJob& a) {
       atomicMin(&rmin[q.v], (int32_t)q.u);
       atomicMax(&rmax[q.v], (int32_t)q.u);
     }
-    if (bad) atomicCAS(&s_err, 0, mesh::kErrIndex);
+    if (bad) atomicCAS(&s_err, 0, star::kStarErrSupport);
     __syncthreads();
   }
   if (s_err == 0) {  // (uniform: every thread reads s_err after the barrier)
@@ -288,7 +288,7 @@ struct DevOut {
     slot = __shfl(slot, 0);
     if (lane < n) {
       if (slot + lane < T_cap) T[slot + lane] = sm_tri{p, my1, my2};
-      else atomicCAS(err, 0, mesh::kErrCapacity);
+      else atomicCAS(err, 0, star::kStarErrCapacity);
     }
     total += n;
     n = 0;

@@ -15,15 +15,23 @@
 #include <cstddef>
 #include <cstdint>
 
-#include "mesh.hpp"
 #include "stereomesh.h"
 
 namespace sm {
 
-// Status words (mesh.hpp): the star kernel counts the triangles in kMeshTris (and in the
+// Status words of a frame's meshes (device, kMeshStatusWords x int32):
+//   [1] triangles of the current tessellation written to T
+//   [2] error code (0 = ok, else the star steps' code, mesh_star.hpp: the caller redoes the
+//       frame's meshes on the host; later tessellations keep the code and write nothing)
+//   [4] new supports of the current tessellation
+//   [5] supports so far
+//   [6] tessellations done
+//   [8 + 2k], [9 + 2k] supports and triangles of tessellation k (k < 8)
+// Words 0, 3 and 7 stay zero. The star kernel counts the triangles in kMeshTris (and in the
 // copy) with atomics; a tessellation's log entry gets its supports from the preparation and
 // its triangle count from the next preparation, or, for a frame's last tessellation, from
 // kMeshTris when the caller reads the words back (star_log_tris).
+enum { kMeshTris = 1, kMeshErr = 2, kMeshNew = 4, kMeshSupports = 5, kMeshTess = 6, kMeshLog = 8, kMeshStatusWords = 32 };
 inline int32_t star_log_tris(const int32_t* words, int k, int n_tess) {
   return k == n_tess - 1 ? words[kMeshTris] : words[kMeshLog + 2 * k + 1];
 }

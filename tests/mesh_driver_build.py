@@ -1,7 +1,7 @@
-"""Builds the sequential C++ driver of the device mesh steps (tests/mesh_core_driver.cpp
-with csrc/mesh_core.hpp, mesh_start.hpp and the host triangulation delaunay.cpp) for the
-CPU tests, optionally with AddressSanitizer and UndefinedBehaviorSanitizer. Helpers only:
-no test lives here."""
+"""Builds the sequential C++ driver of the triangulation code (tests/mesh_driver.cpp with
+csrc/mesh_star.hpp, predicates.hpp and the host triangulation delaunay.cpp) for the CPU
+tests, optionally with AddressSanitizer and UndefinedBehaviorSanitizer. Helpers only: no
+test lives here."""
 import os
 import shutil
 import subprocess
@@ -17,11 +17,11 @@ def build_driver(out_dir, sanitize=False):
     """Path of the built driver; None when g++ is not available."""
     if shutil.which("g++") is None:
         return None
-    out = os.path.join(str(out_dir), "mesh_core_driver" + ("_san" if sanitize else ""))
+    out = os.path.join(str(out_dir), "mesh_driver" + ("_san" if sanitize else ""))
     flags = SANITIZE if sanitize else ["-O2"]
     cmd = (["g++", "-std=c++17", "-Wall", "-Wextra"] + flags +
            [f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
-            os.path.join(ROOT, "tests", "mesh_core_driver.cpp"), os.path.join(CSRC, "delaunay.cpp"), "-o", out])
+            os.path.join(ROOT, "tests", "mesh_driver.cpp"), os.path.join(CSRC, "delaunay.cpp"), "-o", out])
     subprocess.run(cmd, check=True, capture_output=True)
     return out
 

@@ -1,4 +1,4 @@
-"""CPU pin of the device in-circle predicate (csrc/mesh_core.hpp) at the largest
+"""CPU pin of the device in-circle predicate (csrc/predicates.hpp) at the largest
 coordinates the library accepts (0..8191): the double-precision filter must never decide
 a wrong sign, must decide every determinant beyond its threshold plus its error bound,
 and must hand exact ties to the perturbation rule; the perturbed sign must equal the

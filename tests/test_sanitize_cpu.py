@@ -1,6 +1,6 @@
-"""CPU: the host triangulation (csrc/delaunay.cpp) and the device mesh steps run
-sequentially on the host (csrc/mesh_core.hpp, mesh_start.hpp, through
-tests/mesh_core_driver.cpp) built with AddressSanitizer and UndefinedBehaviorSanitizer;
+"""CPU: the host triangulation (csrc/delaunay.cpp) and the device triangulation steps run
+sequentially on the host (csrc/mesh_star.hpp and predicates.hpp, through
+tests/mesh_driver.cpp) built with AddressSanitizer and UndefinedBehaviorSanitizer;
 any out-of-bounds access, use after free, leak, signed overflow or misaligned access
 aborts the driver and fails the test. The outputs must still equal the oracle's
 triangulation (Sec. III-A)."""
@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from mesh_driver_build import build_driver, run_driver
-from test_mesh_core_cpu import _cases
+from test_star_cpu import _CASES
 from test_predicates_cpu import _cocircular_quads, _extreme_quads, _near_threshold_quads
 
 
@@ -33,17 +33,12 @@ def _env():
     return env
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 4], ids=["host", "stars"])
 def test_mesh_steps_under_sanitizers(san_driver, mode):
-    """Host first mesh + insertions (mode 0), device start steps with hash links (1) or
-    edge pairing (2), on every fourth case of the mesh-step suite."""
+    """The host triangulation (mode 0) and the per-point stars (mode 4) on every third case
+    of the triangulation suite."""
     env = _env()
-    for name, W, H, batches in _cases()[::4]:
-        if mode:
-            first = sorted(batches[0], key=lambda p: (p[1], p[0]))
-            if len({p[1] for p in first}) < 2:
-                continue
-            batches = [first] + batches[1:]
+    for name, W, H, batches in _CASES[::3]:
         lines = [f"{W} {H} {len(batches)} {mode}"]
         for b in batches:
             lines.append(str(len(b)))
