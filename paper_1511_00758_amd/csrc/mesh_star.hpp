@@ -20,22 +20,27 @@
 //      edge.
 // Points are found through a bucket grid of kStarCell px cells. The walk takes its
 // candidates from the square of cells around p's cell; the best of them, b, is then checked
-// against every cell that the disk through (p, a, b) reaches outside the square (band by
-// band of cells, from the disk's exact chord widened by a margin): the best over both is the
+// against every cell outside the square that b's cap -- the part of the disk through
+// (p, a, b) left of the edge -- can reach (band by band of cells, from the disk's exact
+// chord and the cap's bounding box, widened by a margin): the best over both is the
 // triangle's third vertex, since any point that beats it lies in a cap nested inside b's.
 // So the triangles are exact whatever the square; its size only decides how much is
-// scanned twice. A step with no candidate in the square but some point strictly left of the
-// edge -- decided exactly from the smallest and largest u of every pixel row holding a
-// point -- widens the square for that step until one is found. The nearest neighbour is
-// taken from a square that certainly holds every point nearer than the one found.
+// scanned twice. A step with no candidate in the square takes the best of the frame's row
+// extremes (the points with the smallest and the largest u of every pixel row) instead:
+// some point lies strictly left of the edge iff some row extreme does, and the hull
+// vertices that bound the long triangles of such steps are row extremes, so the cap to
+// check is usually tight. A cap that covers far more cells than the square is first
+// shrunk by the best of a square of twice the reach (next_vertex). The nearest neighbour
+// is taken from a square that certainly holds every point nearer than the one found.
 // Each triangle is written once, by its vertex with the smallest raster position (v, u),
 // as (i0, i1, i2) counter-clockwise -- the canonical form of sm_tri.
 //
 // The steps are written for a group of kN lanes (a wavefront of 64 on the device, one lane
 // on the host), the WV object: lanes share out the points of a square (wv.for_candidates;
 // the walk's square, named by wv.set_base, may be staged) or of a list of cell runs
-// (wv.for_rows), and combine their best by its reductions (any, min_u64, reduce_best);
-// every control decision is uniform across the group.
+// (wv.for_rows), and combine their best by its reductions (any, min_u64, reduce_best, and
+// pick: a value of the first lane for which a condition holds); every control decision is
+// uniform across the group.
 #pragma once
 
 #include <cmath>
@@ -64,16 +69,24 @@ enum : int32_t {
   kStarErrSupport = 24    // a support outside the frame
 };
 
+// A cell entry: a point id and its packed coordinates.
+struct alignas(8) CellEntry {
+  int32_t id, uv;
+};
+// A pixel row's extreme points: smallest and largest u (lo > hi: no point in the row) and
+// their ids.
+struct alignas(16) RowExt {
+  int32_t lo, hi, lo_id, hi_id;
+};
+
 struct Grid {
   const int32_t* uv;          // [n] packed coordinates u | v << 16
   int32_t n;
   int32_t W, H;
   int32_t gw, gh;             // cells across / down
-  const int32_t* cell_start;  // [gw * gh + 1] first entry of each cell in cell_pts
-  const int32_t* cell_pts;    // [n] point ids ordered by cell (row-major cells)
-  const int32_t* cell_uv;     // [n] their packed coordinates, in the same order
-  const int32_t* row_min;     // [H] smallest u of a point in row v (> 8191: no point)
-  const int32_t* row_max;     // [H] largest u (-1: no point)
+  const int32_t* cell_start;   // [gw * gh + 1] first entry of each cell in cell_e
+  const CellEntry* cell_e;     // [n] the points ordered by cell (row-major cells)
+  const RowExt* rows;          // [H] extreme points of every pixel row
 };
 
 __host__ __device__ inline P2 unpack(int32_t w) { return P2{w & 0xffff, (int32_t)((uint32_t)w >> 16)}; }
@@ -106,58 +119,90 @@ __host__ __device__ inline Region region_of(const Grid& g, P2 P, int32_t k) {
 
 // Candidate order of the walk. For C strictly left of x -> y, the circle through (x, y, C)
 // has its centre at m + t * perp, with m the midpoint of xy and perp = (-(y-x).y, (y-x).x);
-// t(C) = (|2C - x - y|^2 - |y - x|^2) / (4 (2C - x - y) . perp), numerator and denominator
-// exact integers in double (below 2^31), the quotient correctly rounded. The circles through
-// x and y cut nested caps out of the left half-plane, the cap growing with t, so C beats
-// B (C lies inside the circle through (x, y, B)) exactly when t(C) < t(B), and under the
-// perturbation when the two are cocircular. Two quotients that differ by more than 2^-50
-// of their size are ordered like the exact values; closer ones are decided by the exact
-// perturbed in-circle test.
-__host__ __device__ inline double cap_t(P2 X, P2 Y, P2 C) {
-  const int64_t c2x = 2 * C.x - X.x - Y.x, c2y = 2 * C.y - X.y - Y.y;
-  const int64_t ex = Y.x - X.x, ey = Y.y - X.y;
-  const int64_t num = c2x * c2x + c2y * c2y - (ex * ex + ey * ey);
-  const int64_t den = 4 * (ex * c2y - ey * c2x);  // > 0 for C strictly left of x -> y
-  return (double)num / (double)den;
+// t(C) = num / den with num = |2C - x - y|^2 - |y - x|^2 (|num| < 2^29) and
+// den = 4 (2C - x - y) . perp (0 < den < 2^30), exact in 32-bit integers. The circles
+// through x and y cut nested caps out of the left half-plane, the cap growing with t, so C
+// beats B (C lies inside the circle through (x, y, B)) exactly when t(C) < t(B), and under
+// the perturbation when the two are cocircular.
+struct CapKey {
+  int32_t num, den;
+};
+__host__ __device__ inline CapKey cap_key(P2 X, P2 Y, P2 C) {
+  const int32_t c2x = 2 * C.x - X.x - Y.x, c2y = 2 * C.y - X.y - Y.y;
+  const int32_t ex = Y.x - X.x, ey = Y.y - X.y;
+  return CapKey{c2x * c2x + c2y * c2y - (ex * ex + ey * ey), 4 * (ex * c2y - ey * c2x)};
 }
-// does candidate c (quotient tc) beat the current best b (tb)? b < 0: any candidate does
-__host__ __device__ inline bool beats(P2 X, P2 Y, int32_t b, P2 B, double tb, int32_t c, P2 C, double tc) {
+// The quotient in single precision, for the scans: num and den rounded to float (2^-24
+// relative each), the reciprocal of den (1 ulp on the device, correctly rounded on the
+// host) and the product (2^-24): within 5 * 2^-24 of t, relative. Two quotients whose
+// single-precision values differ by more than 2^-20 of the larger are thus ordered like the
+// exact values; closer ones are compared exactly (beats).
+__host__ __device__ inline float cap_tf(P2 X, P2 Y, P2 C) {
+  const CapKey k = cap_key(X, Y, C);
+#ifdef __HIP_DEVICE_COMPILE__
+  return (float)k.num * __builtin_amdgcn_rcpf((float)k.den);
+#else
+  return (float)k.num * (1.0f / (float)k.den);
+#endif
+}
+// t in double from the exact key (for the disk of a triangle, once per step)
+__host__ __device__ inline double cap_t(const CapKey& k) { return (double)k.num / (double)k.den; }
+// Does candidate c (single-precision quotient tc) beat the current best b (tb)? b < 0: any
+// candidate does. Exact: the float filter decides clear cases, the cross-multiplied keys
+// (below 2^59 in 64-bit integers) close ones, the perturbed in-circle test exact ties.
+__host__ __device__ inline bool beats(P2 X, P2 Y, int32_t b, P2 B, float tb, int32_t c, P2 C, float tc) {
   if (c < 0) return false;
   if (b < 0) return true;
-  const double tol = 0x1p-50 * (fabs(tb) > fabs(tc) ? fabs(tb) : fabs(tc));
+  const float tol = 0x1p-20f * (fabsf(tb) > fabsf(tc) ? fabsf(tb) : fabsf(tc));
   if (tc < tb - tol) return true;
   if (tc > tb + tol) return false;
+  const CapKey kb = cap_key(X, Y, B), kc = cap_key(X, Y, C);
+  const int64_t l = (int64_t)kc.num * kb.den, r = (int64_t)kb.num * kc.den;
+  if (l != r) return l < r;
   return incircle_sos(X, Y, B, C) > 0;
 }
 
-// Is some point of the frame strictly left of x -> y? Exact: in each pixel row the points
-// lie between the row's smallest and largest u, and the open half-plane meets a row in an
-// open half-line (or the whole row), so it holds a point of the row iff it holds one of
-// those two points.
+// The best row extreme strictly left of x -> y (ids ix, iy excluded), or -1 when no point
+// of the frame lies strictly left of it (then the edge is on the convex hull). Exact: in
+// each pixel row the points lie between the row's smallest and largest u, and the open
+// half-plane meets a row in an open half-line (or the whole row), so it holds a point of
+// the row iff it holds one of those two points.
 template <class WV>
-__host__ __device__ inline bool any_left(WV& wv, const Grid& g, P2 X, P2 Y) {
-  constexpr int kRowsPerLane = 8;  // rows a lane reads at once; stops at the first batch with a hit
+__host__ __device__ inline int32_t best_extreme(WV& wv, const Grid& g, int32_t ix, P2 X, int32_t iy, P2 Y,
+                                                P2* out) {
+  constexpr int kRowsPerLane = 8;  // rows a lane reads at once
+  int32_t b = -1;
+  P2 B{0, 0};
+  float tb = 0.0f;
   for (int32_t v0 = 0; v0 < g.H; v0 += WV::kN * kRowsPerLane) {
-    int32_t lo[kRowsPerLane], hi[kRowsPerLane];
+    int32_t lo[kRowsPerLane], hi[kRowsPerLane], ilo[kRowsPerLane], ihi[kRowsPerLane];
 #pragma unroll
     for (int k = 0; k < kRowsPerLane; ++k) {
       const int32_t v = v0 + k * WV::kN + wv.lane();
-      lo[k] = v < g.H ? g.row_min[v] : 1;
-      hi[k] = v < g.H ? g.row_max[v] : 0;
+      const bool in = v < g.H;
+      const RowExt e = in ? g.rows[v] : RowExt{1, 0, -1, -1};
+      lo[k] = e.lo, hi[k] = e.hi, ilo[k] = e.lo_id, ihi[k] = e.hi_id;
     }
-    bool hit = false;
 #pragma unroll
     for (int k = 0; k < kRowsPerLane; ++k) {
+      if (lo[k] > hi[k]) continue;  // an empty row
       const int32_t v = v0 + k * WV::kN + wv.lane();
-      hit = hit || (lo[k] <= hi[k] && (orient(X, Y, P2{lo[k], v}) > 0 || orient(X, Y, P2{hi[k], v}) > 0));
+      for (int e = 0; e < 2; ++e) {
+        const int32_t id = e ? ihi[k] : ilo[k];
+        const P2 C{e ? hi[k] : lo[k], v};
+        if (id == ix || id == iy || orient(X, Y, C) <= 0) continue;
+        const float tc = cap_tf(X, Y, C);
+        if (beats(X, Y, b, B, tb, id, C, tc)) b = id, B = C, tb = tc;
+      }
     }
-    if (wv.any(hit)) return true;
   }
-  return false;
+  wv.reduce_best(X, Y, &b, &B, &tb);
+  *out = B;
+  return b;
 }
 
 // A run of cells of one cell row, [x0, x1] of row cy (x0 > x1: none): its entries are
-// contiguous in cell_pts and cell_uv. Scans visit a list of such runs through the group's
+// contiguous in cell_e. Scans visit a list of such runs through the group's
 // wv.for_rows(g, n, row, fn), calling fn(id, P) for this lane's share of their points
 // (row(i) gives run i; a group may set the runs up in parallel).
 struct CellRow {
@@ -193,58 +238,47 @@ __host__ __device__ inline void left_cells(const Grid& g, P2 X, P2 Y, int32_t cy
   }
 }
 
-// The runs of square r restricted to the cells that can hold a point left of x -> y.
-struct LeftRows {
-  const Grid* g;
-  Region r;
-  P2 X, Y;
-  __host__ __device__ CellRow operator()(int32_t i) const {
-    const int32_t cy = r.y0 + i;
-    int32_t c0, c1;
-    left_cells(*g, X, Y, cy, &c0, &c1);
-    return CellRow{cy, c0 > r.x0 ? c0 : r.x0, c1 < r.x1 ? c1 : r.x1};
-  }
-};
-
-// Nearest neighbour of p among the candidates: key (d^2 << 32) | id, ~0 when none; a
-// candidate at distance 0 is reported through *dup.
+// Nearest neighbour of p among the candidates: key (d^2 << 32) | id, ~0 when none, and its
+// packed coordinates in *wq; a candidate at distance 0 is reported through *dup.
 template <class WV>
-__host__ __device__ inline uint64_t nearest(WV& wv, const Grid& g, const Region& r, int32_t p, P2 P, bool* dup) {
+__host__ __device__ inline uint64_t nearest(WV& wv, const Grid& g, const Region& r, int32_t p, P2 P, bool* dup,
+                                            int32_t* wq) {
   uint64_t best = ~0ull;
+  int32_t best_uv = 0;
   bool z = false;
   wv.for_candidates(g, r, [&](int32_t id, P2 C) {
     if (id == p) return;
-    const int64_t dx = C.x - P.x, dy = C.y - P.y;
+    const int32_t dx = C.x - P.x, dy = C.y - P.y;
     const uint64_t d2 = (uint64_t)(dx * dx + dy * dy);
     z = z || d2 == 0;
     const uint64_t key = (d2 << 32) | (uint32_t)id;
-    best = key < best ? key : best;
+    if (key < best) best = key, best_uv = C.x | (C.y << 16);
   });
   *dup = wv.any(z);
-  return wv.min_u64(best);
+  const uint64_t m = wv.min_u64(best);
+  *wq = wv.pick(best == m, best_uv);
+  return m;
 }
 
 // The best candidate of square r strictly left of x -> y (ids ix, iy excluded), or -1.
 template <class WV>
-__host__ __device__ inline int32_t best_left(WV& wv, const Grid& g, const Region& r, bool base, int32_t ix, P2 X,
-                                             int32_t iy, P2 Y, P2* out, double* t_out) {
+__host__ __device__ inline int32_t best_left(WV& wv, const Grid& g, const Region& r, int32_t ix, P2 X,
+                                             int32_t iy, P2 Y, P2* out) {
   int32_t b = -1;
   P2 B{0, 0};
-  double tb = 0.0;
+  float tb = 0.0f;
   auto fn = [&](int32_t id, P2 C) {
     if (id == ix || id == iy || orient(X, Y, C) <= 0) return;
-    const double tc = cap_t(X, Y, C);
+    const float tc = cap_tf(X, Y, C);
     if (beats(X, Y, b, B, tb, id, C, tc)) b = id, B = C, tb = tc;
   };
-  if (base) wv.for_candidates(g, r, fn);  // the walk's square (possibly staged)
-  else wv.for_rows(g, r.y1 - r.y0 + 1, LeftRows{&g, r, X, Y}, fn);  // a wider one, its left part
+  wv.for_candidates(g, r, fn);  // the walk's square (possibly staged)
   wv.reduce_best(X, Y, &b, &B, &tb);
   *out = B;
-  *t_out = tb;
   return b;
 }
 
-// Circle through x, y and the point of quotient t (cap_t): centre m + t * perp, radius
+// Circle through x, y and the point of quotient t: centre m + t * perp, radius
 // |centre - x|, in double (relative errors near 1e-16, far inside the margin the scan adds).
 struct Disk {
   double cx, cy, r;
@@ -255,28 +289,82 @@ __host__ __device__ inline Disk disk_of(P2 X, P2 Y, double t) {
   return Disk{cx, cy, sqrt(dx * dx + dy * dy)};
 }
 
-// The best point strictly left of x -> y given b, the best of square r: every cell that
-// the closed disk through (x, y, b) reaches outside r is scanned too. A point beating b lies
-// inside that disk (in the left cap); the best over both sets is final, since a point
-// beating it would lie inside its own cap, which is nested inside b's.
+// The best of b (coordinates *B) and the points strictly left of x -> y (ids ix, iy
+// excluded) in n cell runs (rows(i) gives run i).
+template <class WV, class RowFn>
+__host__ __device__ inline int32_t scan_best(WV& wv, const Grid& g, int32_t n, RowFn&& rows, int32_t ix, P2 X,
+                                             int32_t iy, P2 Y, int32_t b, P2* B) {
+  int32_t best = b;
+  P2 Bb = *B;
+  float tbest = b >= 0 ? cap_tf(X, Y, *B) : 0.0f;
+  if (n > 0)
+    wv.for_rows(g, n, rows, [&](int32_t id, P2 C) {
+      if (id == ix || id == iy || orient(X, Y, C) <= 0) return;
+      const float tc = cap_tf(X, Y, C);
+      if (beats(X, Y, best, Bb, tbest, id, C, tc)) best = id, Bb = C, tbest = tc;
+    });
+  wv.reduce_best(X, Y, &best, &Bb, &tbest);
+  *B = Bb;
+  return best;
+}
+
+// The part of the closed disk through (x, y, b) left of x -> y -- the circular segment cut
+// off by the chord xy, where every point that beats b lies: the disk and the segment's
+// bounding box, both widened by the margin m. The box holds x, y and those of the circle's
+// four axis extremes that lie on the arc left of the edge (kept when within m of the line
+// too).
+struct Cap {
+  Disk D;
+  double m, x0, x1, y0, y1;
+};
+__host__ __device__ inline Cap cap_of(P2 X, P2 Y, P2 B) {
+  Cap c;
+  c.D = disk_of(X, Y, cap_t(cap_key(X, Y, B)));
+  const Disk& D = c.D;
+  c.m = kDiskMargin + 1e-9 * D.r;
+  c.x0 = X.x < Y.x ? X.x : Y.x, c.x1 = X.x < Y.x ? Y.x : X.x;
+  c.y0 = X.y < Y.y ? X.y : Y.y, c.y1 = X.y < Y.y ? Y.y : X.y;
+  const double ex = Y.x - X.x, ey = Y.y - X.y, el = sqrt(ex * ex + ey * ey);
+  const double px[4] = {D.cx + D.r, D.cx - D.r, D.cx, D.cx};
+  const double py[4] = {D.cy, D.cy, D.cy + D.r, D.cy - D.r};
+  for (int k = 0; k < 4; ++k)
+    if (ex * (py[k] - X.y) - ey * (px[k] - X.x) > -c.m * el) {  // signed distance left of the line > -m
+      c.x0 = px[k] < c.x0 ? px[k] : c.x0;
+      c.x1 = px[k] > c.x1 ? px[k] : c.x1;
+      c.y0 = py[k] < c.y0 ? py[k] : c.y0;
+      c.y1 = py[k] > c.y1 ? py[k] : c.y1;
+    }
+  c.x0 -= c.m, c.x1 += c.m, c.y0 -= c.m, c.y1 += c.m;
+  return c;
+}
+// Cells of the frame that the cap's box covers.
+__host__ __device__ inline int64_t cap_cells(const Cap& c, const Grid& g) {
+  const double w = (c.x1 < g.W ? c.x1 : g.W) - (c.x0 > 0.0 ? c.x0 : 0.0);
+  const double h = (c.y1 < g.H ? c.y1 : g.H) - (c.y0 > 0.0 ? c.y0 : 0.0);
+  if (w <= 0.0 || h <= 0.0) return 0;
+  return (int64_t)(w / kStarCell + 2.0) * (int64_t)(h / kStarCell + 2.0);
+}
+// Does the cap lie inside square r (then no point outside r can beat b)?
+__host__ __device__ inline bool cap_inside(const Cap& c, const Grid& g, const Region& r) {
+  if (r.full) return true;
+  return (c.x0 >= (double)r.x0 * kStarCell || r.x0 == 0) && (c.x1 < (double)(r.x1 + 1) * kStarCell || r.x1 == g.gw - 1) &&
+         (c.y0 >= (double)r.y0 * kStarCell || r.y0 == 0) && (c.y1 < (double)(r.y1 + 1) * kStarCell || r.y1 == g.gh - 1);
+}
+
+// The best point strictly left of x -> y given b, the best of square r: every cell outside
+// r that b's cap can reach (the disk's chord over each band of rows, within the cap's box,
+// and the cells that can hold a point left of the edge) is scanned too. The best over both
+// sets is final, since a point beating it would lie inside its own cap, which is nested
+// inside b's.
 template <class WV>
 __host__ __device__ inline int32_t verify_left(WV& wv, const Grid& g, const Region& r, int32_t ix, P2 X, int32_t iy,
-                                               P2 Y, int32_t b, P2* B, double tb) {
-  if (r.full) return b;
-  const Disk D = disk_of(X, Y, tb);
-  const double m = kDiskMargin + 1e-9 * D.r;
-  const double fy0 = D.cy - D.r - m, fy1 = D.cy + D.r + m;
-  const double fx0 = D.cx - D.r - m, fx1 = D.cx + D.r + m;
-  // inside r, with nothing to scan: the common case
-  const double sx0 = (double)r.x0 * kStarCell, sx1 = (double)(r.x1 + 1) * kStarCell;
-  const double sy0 = (double)r.y0 * kStarCell, sy1 = (double)(r.y1 + 1) * kStarCell;
-  if ((fx0 >= sx0 || r.x0 == 0) && (fx1 < sx1 || r.x1 == g.gw - 1) && (fy0 >= sy0 || r.y0 == 0) &&
-      (fy1 < sy1 || r.y1 == g.gh - 1))
-    return b;
+                                               P2 Y, int32_t b, P2* B, const Cap& c) {
+  const Disk& D = c.D;
+  const double m = c.m;
   const double lim_y = (double)g.gh * kStarCell, lim_x = (double)g.gw * kStarCell;
-  const int32_t cy0 = fy0 <= 0.0 ? 0 : (fy0 >= lim_y ? g.gh : (int32_t)(fy0 / kStarCell));
-  const int32_t cy1 = fy1 < 0.0 ? -1 : (fy1 >= lim_y ? g.gh - 1 : (int32_t)(fy1 / kStarCell));
-  // two runs per band of cells: the band's cells the disk reaches, left and right of the
+  const int32_t cy0 = c.y0 <= 0.0 ? 0 : (c.y0 >= lim_y ? g.gh : (int32_t)(c.y0 / kStarCell));
+  const int32_t cy1 = c.y1 < 0.0 ? -1 : (c.y1 >= lim_y ? g.gh - 1 : (int32_t)(c.y1 / kStarCell));
+  // two runs per band of cells: the band's cells the cap reaches, left and right of the
   // square where the band crosses it (the whole reach as the first run otherwise)
   auto row = [&](int32_t i) -> CellRow {
     const int32_t cy = cy0 + i / 2, seg = i % 2;
@@ -287,11 +375,11 @@ __host__ __device__ inline int32_t verify_left(WV& wv, const Grid& g, const Regi
     const double h2 = D.r * D.r - dy * dy;
     if (h2 < -2.0 * m * D.r - m * m) return none;  // (the margin keeps grazing bands)
     const double hw = (h2 > 0.0 ? sqrt(h2) : 0.0) + m;
-    const double bx0 = D.cx - hw, bx1 = D.cx + hw;
-    if (bx1 < 0.0 || bx0 >= lim_x) return none;
+    const double bx0 = D.cx - hw > c.x0 ? D.cx - hw : c.x0, bx1 = D.cx + hw < c.x1 ? D.cx + hw : c.x1;
+    if (bx0 > bx1 || bx1 < 0.0 || bx0 >= lim_x) return none;
     int32_t x0 = bx0 <= 0.0 ? 0 : (int32_t)(bx0 / kStarCell);
     int32_t x1 = bx1 >= lim_x ? g.gw - 1 : (int32_t)(bx1 / kStarCell);
-    int32_t c0, c1;  // only the disk's part left of the edge can hold a better vertex
+    int32_t c0, c1;  // only the cells that can hold a point left of the edge
     left_cells(g, X, Y, cy, &c0, &c1);
     x0 = x0 > c0 ? x0 : c0;
     x1 = x1 < c1 ? x1 : c1;
@@ -300,35 +388,58 @@ __host__ __device__ inline int32_t verify_left(WV& wv, const Grid& g, const Regi
     return seg == 0 ? CellRow{cy, x0, x1 < r.x0 - 1 ? x1 : r.x0 - 1}
                     : CellRow{cy, x0 > r.x1 + 1 ? x0 : r.x1 + 1, x1};
   };
-  int32_t best = b;
-  P2 Bb = *B;
-  double tbest = tb;
-  if (cy1 >= cy0)
-    wv.for_rows(g, 2 * (cy1 - cy0 + 1), row, [&](int32_t id, P2 C) {
-      if (id == ix || id == iy || orient(X, Y, C) <= 0) return;
-      const double tc = cap_t(X, Y, C);
-      if (beats(X, Y, best, Bb, tbest, id, C, tc)) best = id, Bb = C, tbest = tc;
-    });
-  wv.reduce_best(X, Y, &best, &Bb, &tbest);
-  *B = Bb;
-  return best;
+  return scan_best(wv, g, cy1 >= cy0 ? 2 * (cy1 - cy0 + 1) : 0, row, ix, X, iy, Y, b, B);
 }
 
+// The cells of square t outside square s (s inside t) that can hold a point left of x -> y,
+// two runs per cell row of t.
+struct LeftRing {
+  const Grid* g;
+  Region t, s;
+  P2 X, Y;
+  __host__ __device__ CellRow operator()(int32_t i) const {
+    const int32_t cy = t.y0 + i / 2, seg = i % 2;
+    int32_t x0, x1;
+    if (cy < s.y0 || cy > s.y1) {
+      if (seg) return CellRow{cy, 1, 0};
+      x0 = t.x0, x1 = t.x1;
+    } else {
+      x0 = seg ? s.x1 + 1 : t.x0;
+      x1 = seg ? t.x1 : s.x0 - 1;
+    }
+    int32_t c0, c1;
+    left_cells(*g, X, Y, cy, &c0, &c1);
+    return CellRow{cy, x0 > c0 ? x0 : c0, x1 < c1 ? x1 : c1};
+  }
+};
+
 // The third vertex of the triangle left of x -> y, exactly (-1: none, the edge is on the
-// hull). Tries square r first, then squares doubling around p when r holds no candidate
-// but some point lies left of the edge. (One call site per step: the device code stays
-// small enough for the instruction cache.)
+// hull). Its first candidate is the best of square r or, when r holds none, the best row
+// extreme (on the long triangles of hull vertices it is usually the vertex itself). Then,
+// with s the square whose points have all been seen (r at first): a cap inside s is final;
+// a cap whose box covers no more cells than the square t of twice s's reach (or than
+// kBandCells) is checked by its bands outside s (verify_left); a larger one (a poor
+// candidate) first takes the best of t's ring around s, which can only shrink it, and the
+// check repeats with t as s.
+constexpr int64_t kBandCells = 512;
 template <class WV>
 __host__ __device__ inline int32_t next_vertex(WV& wv, const Grid& g, const Region& r, P2 P, int32_t ix, P2 X,
                                                int32_t iy, P2 Y, P2* out) {
-  Region rr = r;
-  for (int32_t k = r.k;; k *= 2) {
-    if (k != r.k) rr = region_of(g, P, k);
-    double tb = 0.0;
-    const int32_t b = best_left(wv, g, rr, k == r.k, ix, X, iy, Y, out, &tb);
-    if (b >= 0) return verify_left(wv, g, rr, ix, X, iy, Y, b, out, tb);
-    if (rr.full) return -1;
-    if (k == r.k && !any_left(wv, g, X, Y)) return -1;
+  int32_t b = best_left(wv, g, r, ix, X, iy, Y, out);
+  if (b < 0) {
+    if (r.full) return -1;
+    b = best_extreme(wv, g, ix, X, iy, Y, out);
+    if (b < 0) return -1;  // nothing left of the edge: a hull edge
+  }
+  for (Region s = r;;) {
+    const Cap c = cap_of(X, Y, *out);
+    if (cap_inside(c, g, s)) return b;
+    const Region t = region_of(g, P, 2 * s.k);
+    const int64_t t_cells = (int64_t)(t.x1 - t.x0 + 1) * (t.y1 - t.y0 + 1);
+    if (cap_cells(c, g) <= (t_cells > kBandCells ? t_cells : kBandCells))
+      return verify_left(wv, g, s, ix, X, iy, Y, b, out, c);
+    b = scan_best(wv, g, 2 * (t.y1 - t.y0 + 1), LeftRing{&g, t, s, X, Y}, ix, X, iy, Y, b, out);
+    s = t;
   }
 }
 
@@ -343,17 +454,19 @@ __host__ __device__ inline int32_t star_of(WV& wv, const Grid& g, int32_t p, Out
   // the nearest neighbour, from a square that holds every point nearer than it
   Region r;
   uint64_t key = ~0ull;
+  int32_t wq = 0;
   for (int32_t k = 1;; k *= 2) {
     r = region_of(g, P, k);
+    wv.set_base(g, r);  // the square of the walk, once it holds the nearest neighbour (a
+                        // group may stage its points)
     bool dup = false;
-    key = nearest(wv, g, r, p, P, &dup);
+    key = nearest(wv, g, r, p, P, &dup, &wq);
     if (dup) return -kStarErrDup;
     if (key == ~0ull && r.full) return 0;  // a lone point
     if (key != ~0ull && (r.full || (int64_t)(key >> 32) < r.R2)) break;
   }
   const int32_t q = (int32_t)(key & 0xffffffffu);
-  const P2 Q = unpack(g.uv[q]);
-  wv.set_base(g, r);  // the square of the walk (a group may stage its points)
+  const P2 Q = unpack(wq);
   out.begin();
   auto emit = [&](int32_t i1, P2 A, int32_t i2, P2 B) {
     if ((uint32_t)wp < (uint32_t)(A.x | (A.y << 16)) && (uint32_t)wp < (uint32_t)(B.x | (B.y << 16)))

@@ -24,6 +24,13 @@ constexpr int32_t kNoRow = 1 << 30;
 
 __device__ __forceinline__ int32_t pack_uv(int32_t u, int32_t v) { return u | (v << 16); }
 
+// A value the caller knows to be equal on every lane of the wavefront, as a wave-uniform
+// (scalar) value: control flow that depends on it compiles to scalar branches.
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  return ((uint64_t)(uint32_t)uniform((int32_t)(v >> 32)) << 32) | (uint32_t)uniform((int32_t)v);
+}
+
 // Writes the status words 0..7 and log entry k to the status and its copy (thread 0).
 __device__ void put_status(const StarJob& a, const int32_t (&w)[8], int k, int32_t log_s, int32_t log_t) {
   for (int i = 0; i < 8; ++i) {
@@ -131,15 +138,17 @@ __device__ void star_prep(const StarJob& a) {
     block_scan(cnt, w.cell_start, n_cells);
     __syncthreads();
     for (int32_t c = tid; c < n_cells; c += kPrepThreads) cnt[c] = w.cell_start[c];  // fill cursors
-    if (kLds)
-      for (int32_t v = tid; v < a.H; v += kPrepThreads) w.row_min[v] = rmin[v], w.row_max[v] = rmax[v];
+    for (int32_t v = tid; v < a.H; v += kPrepThreads) w.rows[v].lo = rmin[v], w.rows[v].hi = rmax[v];
     __syncthreads();
     for (int32_t i = tid; i < n; i += kPrepThreads) {  // the same i as in the counting loop
       const int32_t q = w.uv[i];
-      const int32_t c = ((q >> 16) / star::kStarCell) * w.gw + (q & 0xffff) / star::kStarCell;
+      const int32_t qu = q & 0xffff, qv = q >> 16;
+      const int32_t c = (qv / star::kStarCell) * w.gw + qu / star::kStarCell;
       const int32_t e = atomicAdd(&cnt[c], 1);
-      w.cell_pts[e] = i;
-      w.cell_uv[e] = q;
+      w.cell_e[e] = star::CellEntry{i, q};
+      // the ids of the row's extreme points (one support per pixel: one writer each)
+      if (qu == rmin[qv]) w.rows[qv].lo_id = i;
+      if (qu == rmax[qv]) w.rows[qv].hi_id = i;
     }
   }
   __syncthreads();
@@ -165,6 +174,42 @@ __global__ __launch_bounds__(kPrepThreads) void k_star_prep_many(const StarJob* 
   star_prep<kLds>(jobs[blockIdx.x]);
 }
 
+// Wavefront-wide scans and reductions on DPP: shifts by 1, 2, 4 and 8 lanes within each
+// row of 16, then the broadcasts of lanes 15 and 31 into the following rows; every step is
+// one VALU operation with no LDS round trip. All 64 lanes must be active.
+template <int Ctrl, int RowMask>
+__device__ __forceinline__ int32_t dpp(int32_t old, int32_t v) {
+  return __builtin_amdgcn_update_dpp(old, v, Ctrl, RowMask, 0xf, false);
+}
+// inclusive prefix sum over the lanes
+__device__ __forceinline__ int32_t wave_scan(int32_t v) {
+  v += dpp<0x111, 0xf>(0, v);  // row_shr:1
+  v += dpp<0x112, 0xf>(0, v);  // row_shr:2
+  v += dpp<0x114, 0xf>(0, v);  // row_shr:4
+  v += dpp<0x118, 0xf>(0, v);  // row_shr:8
+  v += dpp<0x142, 0xa>(0, v);  // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xc>(0, v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+// minimum over the lanes, as a wave-uniform value (lane 63 ends with it)
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+  int32_t v = (int32_t)x;
+  auto mn = [](int32_t a, int32_t b) { return (uint32_t)a < (uint32_t)b ? a : b; };
+  v = mn(v, dpp<0x111, 0xf>(-1, v));
+  v = mn(v, dpp<0x112, 0xf>(-1, v));
+  v = mn(v, dpp<0x114, 0xf>(-1, v));
+  v = mn(v, dpp<0x118, 0xf>(-1, v));
+  v = mn(v, dpp<0x142, 0xa>(-1, v));
+  v = mn(v, dpp<0x143, 0xc>(-1, v));
+  return (uint32_t)__builtin_amdgcn_readlane(v, 63);
+}
+// float keys as unsigned integers in the same order (non-negative floats above negative
+// ones; NaN does not occur)
+__device__ __forceinline__ uint32_t float_key(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
 // A wavefront as the group of the star steps; the candidates of the current region are
 // staged in LDS when they fit.
 struct DevWave {
@@ -172,36 +217,66 @@ struct DevWave {
   int lane_;
   int32_t* s_id;
   int32_t* s_uv;
+  int32_t* s_mark;        // [kN * kInFlight] run starts of a gather chunk
   int32_t n_staged = -1;  // -1: nothing staged
   int32_t rx0 = 0, rx1 = -1, ry0 = 0, ry1 = -1;
 
   __device__ int lane() const { return lane_; }
   __device__ bool any(bool b) const { return __ballot(b) != 0; }
   __device__ uint64_t min_u64(uint64_t x) const {
-    for (int o = 32; o > 0; o >>= 1) {
-      const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, o);
-      const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), o);
-      const uint64_t y = ((uint64_t)hi << 32) | lo;
-      x = y < x ? y : x;
-    }
-    return x;
+    const uint32_t hi = wave_min_u32((uint32_t)(x >> 32));
+    const uint32_t lo = wave_min_u32((uint32_t)(x >> 32) == hi ? (uint32_t)x : 0xffffffffu);
+    return ((uint64_t)hi << 32) | lo;
   }
-  // every lane ends with the same winner: of two candidates, exactly one beats the other
-  __device__ void reduce_best(P2 X, P2 Y, int32_t* b, P2* B, double* t) const {
-#pragma unroll 1
-    for (int o = 32; o > 0; o >>= 1) {
-      const int32_t pb = __shfl_xor(*b, o);
-      const P2 PB{__shfl_xor(B->x, o), __shfl_xor(B->y, o)};
-      const double pt = __shfl_xor(*t, o);
-      if (star::beats(X, Y, *b, *B, *t, pb, PB, pt)) *b = pb, *B = PB, *t = pt;
+  __device__ int32_t pick(bool mine, int32_t v) const {
+    const uint64_t m = __ballot(mine);
+    return __builtin_amdgcn_readlane(v, m ? __ffsll((long long)m) - 1 : 0);
+  }
+  // The group's best of the lanes' bests (every lane ends with it, wave-uniform): the
+  // smallest single-precision quotient by a DPP minimum; the other candidates within 2^-19
+  // of it (the only ones whose exact quotient can be as small, the rounding being below
+  // 5 * 2^-24 of each) are then compared exactly, one after another (usually there are none).
+  __device__ void reduce_best(P2 X, P2 Y, int32_t* b, P2* B, float* t) const {
+    const uint32_t kmin = wave_min_u32(*b >= 0 ? float_key(*t) : 0xffffffffu);
+    if (kmin == 0xffffffffu) {  // no lane has a candidate
+      *b = -1;
+      return;
     }
+    const float tmin = __uint_as_float((kmin & 0x80000000u) ? (kmin & 0x7fffffffu) : ~kmin);
+    const bool close = *b >= 0 && *t <= tmin + 0x1p-19f * fabsf(tmin);
+    const int w = __ffsll((long long)__ballot(close)) - 1;
+    int32_t wb = __builtin_amdgcn_readlane(*b, w);
+    P2 WB{__builtin_amdgcn_readlane(B->x, w), __builtin_amdgcn_readlane(B->y, w)};
+    float wt = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(*t), w));
+    // other candidates as close (many lanes can hold the same one, e.g. a scan's start)
+    uint64_t near = __ballot(close && *b != wb);
+    while (near) {
+      const int c = __ffsll((long long)near) - 1;
+      const int32_t cb = __builtin_amdgcn_readlane(*b, c);
+      near &= ~__ballot(*b == cb);  // (every lane that holds it)
+      const P2 CB{__builtin_amdgcn_readlane(B->x, c), __builtin_amdgcn_readlane(B->y, c)};
+      const float ct = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(*t), c));
+      if (star::beats(X, Y, wb, WB, wt, cb, CB, ct)) wb = cb, WB = CB, wt = ct;
+    }
+    *b = wb;
+    *B = WB;
+    *t = wt;
   }
   // Visits the entries of n cell runs (row(i) gives run i), 64 runs at a time: lane i sets
-  // up run i (its two cell_start reads, all lanes at once), a prefix over the lanes places
-  // the runs end to end, and every lane then takes entries j = lane, lane + 64, ... of the
-  // chunk, finding its run by a binary search over the lanes' offsets. fn2(j, e) gets the
-  // entry's position in the chunk and its index in cell_pts / cell_uv. Control flow stays
-  // uniform (the shuffles read every lane).
+  // up run i (its two cell_start reads, all lanes at once), a prefix sum over the lanes
+  // places the runs end to end, and every lane then takes entries j = lane, lane + 64, ...
+  // of the chunk. A lane finds the run of its entry from the chunk's run starts, marked in
+  // LDS: the last start at or before it (or the run carried over from the previous 64).
+  // The loads of kInFlight such rounds are issued before the first is used (one memory
+  // latency per 64 * kInFlight entries). fn2(j, id, uv) gets the entry's position in the
+  // chunk, its point id and its packed coordinates. Control flow stays uniform.
+  static constexpr int kInFlight = 2;
+  static constexpr int32_t kNoMark = INT32_MIN;
+  __device__ static void wave_sync() {  // a wavefront's LDS writes before its lanes read them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
   template <class RowFn, class Fn2>
   __device__ int32_t gather(const Grid& g, int32_t n, RowFn&& row, Fn2&& fn2) const {
     int32_t all = 0;
@@ -215,23 +290,44 @@ struct DevWave {
           len = g.cell_start[c.cy * g.gw + c.x1 + 1] - e0;
         }
       }
-      int32_t inc = len;
-      for (int d = 1; d < kN; d <<= 1) {
-        const int32_t x = __shfl_up(inc, d);
-        if (lane_ >= d) inc += x;
-      }
+      const int32_t inc = wave_scan(len);
       const int32_t exc = inc - len;
-      const int32_t total = __shfl(inc, kN - 1);
-      for (int32_t j0 = 0; j0 < total; j0 += kN) {
-        const int32_t j = j0 + lane_;
-        int lo = 0, hi = kN - 1;  // the last lane whose run starts at or before j
-        for (int step = 0; step < 6; ++step) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (__shfl(exc, mid) <= j) lo = mid;
-          else hi = mid - 1;
+      const int32_t total = __builtin_amdgcn_readlane(inc, kN - 1);
+      const int32_t delta = e0 - exc;  // entry j of this lane's run is cell entry j + delta
+      int32_t carry = 0;               // delta of the run that covers a chunk's first entry
+      for (int32_t j0 = 0; j0 < total; j0 += kN * kInFlight) {
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) s_mark[u * kN + lane_] = kNoMark;
+        wave_sync();
+        if (len > 0 && exc >= j0 && exc < j0 + kN * kInFlight) s_mark[exc - j0] = delta;
+        wave_sync();
+        int32_t id[kInFlight], uv[kInFlight];
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) {
+          id[u] = -1, uv[u] = 0;
+          if (j0 + u * kN >= total) continue;  // (uniform)
+          const int32_t d = s_mark[u * kN + lane_];
+          const uint64_t has = __ballot(d != kNoMark);
+          const uint64_t upto = has & (lane_ == kN - 1 ? ~0ull : ((2ull << lane_) - 1));
+          const int32_t src = upto ? 63 - __clzll((long long)upto) : 0;
+          const int32_t from = __shfl(d, src);
+          const int32_t dj = upto ? from : carry;
+          if (has) carry = __builtin_amdgcn_readlane(d, 63 - __clzll((long long)has));
+          const int32_t j = j0 + u * kN + lane_;
+          if (j < total) {
+            const star::CellEntry ce = g.cell_e[j + dj];
+            id[u] = ce.id, uv[u] = ce.uv;
+          }
         }
-        const int32_t e = __shfl(e0, lo) + (j - __shfl(exc, lo));
-        if (j < total) fn2(all + j, e);
+        // one call site of fn2: the rounds move down the registers
+#pragma unroll 1
+        for (int u = 0; u < kInFlight && j0 + u * kN < total; ++u) {
+          const int32_t j = j0 + u * kN + lane_;
+          if (j < total) fn2(all + j, id[0], uv[0]);
+#pragma unroll
+          for (int k = 0; k + 1 < kInFlight; ++k) id[k] = id[k + 1], uv[k] = uv[k + 1];
+        }
+        wave_sync();  // (the marks are rewritten by the next chunk)
       }
       all += total;
     }
@@ -239,7 +335,7 @@ struct DevWave {
   }
   template <class RowFn, class Fn>
   __device__ void for_rows(const Grid& g, int32_t n, RowFn&& row, Fn&& fn) {
-    gather(g, n, row, [&](int32_t, int32_t e) { fn(g.cell_pts[e], star::unpack(g.cell_uv[e])); });
+    gather(g, n, row, [&](int32_t, int32_t id, int32_t uv) { fn(id, star::unpack(uv)); });
   }
   // the walk's square: its points into LDS when they fit
   __device__ void set_base(const Grid& g, const Region& r) {
@@ -247,13 +343,10 @@ struct DevWave {
     rx0 = r.x0, rx1 = r.x1, ry0 = r.y0, ry1 = r.y1;
     int32_t* sid = s_id;
     int32_t* suv = s_uv;
-    n_staged = gather(g, r.y1 - r.y0 + 1, star::RegionRows{r}, [&](int32_t j, int32_t e) {
-      if (j < kStageCap) sid[j] = g.cell_pts[e], suv[j] = g.cell_uv[e];
+    n_staged = gather(g, r.y1 - r.y0 + 1, star::RegionRows{r}, [&](int32_t j, int32_t id, int32_t uv) {
+      if (j < kStageCap) sid[j] = id, suv[j] = uv;
     });
-    // the wavefront's LDS writes before any lane reads another lane's entries
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync();  // the staged entries before any lane reads another lane's
   }
   template <class Fn>
   __device__ void for_candidates(const Grid& g, const Region& r, Fn&& fn) {
@@ -265,8 +358,10 @@ struct DevWave {
   }
 };
 
-// Triangles of one star: lane k holds the k-th pending one; a full set of 64 (or the end)
-// reserves its slots with one atomic and is written by the lanes together.
+// Triangles of one star: lane k holds the k-th pending one. The workgroup reserves the
+// slots of all its stars' pending triangles at its end, with one atomic on the frame's
+// counter (every wavefront adding its own would serialise thousands of same-address
+// atomics); a star with more than 64 triangles reserves each full set of 64 on its own.
 struct DevOut {
   int lane;
   int32_t p;
@@ -278,18 +373,19 @@ struct DevOut {
   int32_t n = 0, total = 0;
   int32_t my1 = 0, my2 = 0;
   __device__ void begin() { n = 0; }
-  __device__ void flush() {
-    if (n == 0) return;
+  __device__ void write(int32_t slot) {
+    if (lane < n) {
+      if (slot + lane < T_cap) T[slot + lane] = sm_tri{p, my1, my2};
+      else atomicCAS(err, 0, star::kStarErrCapacity);
+    }
+  }
+  __device__ void flush() {  // a full set, at once
     int32_t slot = 0;
     if (lane == 0) {
       slot = atomicAdd(counter, n);
       if (counter_copy) atomicAdd(counter_copy, n);
     }
-    slot = __shfl(slot, 0);
-    if (lane < n) {
-      if (slot + lane < T_cap) T[slot + lane] = sm_tri{p, my1, my2};
-      else atomicCAS(err, 0, star::kStarErrCapacity);
-    }
+    write(uniform(__shfl(slot, 0)));
     total += n;
     n = 0;
   }
@@ -297,38 +393,59 @@ struct DevOut {
     if (lane == n) my1 = i1, my2 = i2;
     if (++n == DevWave::kN) flush();
   }
-  __device__ int32_t finish() {
-    flush();
-    return total;
-  }
+  // the star's count; its last n triangles wait for the workgroup's reservation
+  __device__ int32_t finish() { return total + n; }
 };
 
 __device__ void star_wave(const StarJob& a, int32_t local_wave) {
   __shared__ int32_t s_id[kStarWaves][kStageCap];
   __shared__ int32_t s_uv[kStarWaves][kStageCap];
-  const int lane = threadIdx.x & 63, wv_i = threadIdx.x >> 6;
+  __shared__ int32_t s_mark[kStarWaves][DevWave::kN * DevWave::kInFlight];
+  __shared__ int32_t s_cnt[kStarWaves];
+  __shared__ int32_t s_base;
+  const int lane = threadIdx.x & 63, wv_i = uniform((int32_t)threadIdx.x >> 6);
   int32_t* status = a.status;
   const int32_t n = status[kMeshSupports];
   const int32_t err0 = status[kMeshErr];
   const int32_t p = local_wave;
-  if (err0 != 0 || p >= n || n > a.w.S_cap) return;
   const StarWork& w = a.w;
-  const Grid g{w.uv, n, a.W, a.H, w.gw, w.gh, w.cell_start, w.cell_pts, w.cell_uv, w.row_min, w.row_max};
-  DevWave wv{lane, s_id[wv_i], s_uv[wv_i]};
   DevOut out{lane, p, a.T, a.T_cap, &status[kMeshTris], a.status_copy ? &a.status_copy[kMeshTris] : nullptr,
              &status[kMeshErr]};
-  const int32_t r = star::star_of(wv, g, p, out);
-  if (r < 0 && lane == 0) {  // the frame goes to the host
-    atomicCAS(&status[kMeshErr], 0, -r);
-    if (a.status_copy) atomicCAS(&a.status_copy[kMeshErr], 0, -r);
+  if (err0 == 0 && p < n && n <= a.w.S_cap) {  // (every wavefront goes on to the barriers)
+    const Grid g{w.uv, n, a.W, a.H, w.gw, w.gh, w.cell_start, w.cell_e, w.rows};
+    DevWave wv{lane, s_id[wv_i], s_uv[wv_i], s_mark[wv_i]};
+    const int32_t r = star::star_of(wv, g, p, out);
+    if (r < 0) {  // the frame goes to the host
+      out.n = 0;
+      if (lane == 0) {
+        atomicCAS(&status[kMeshErr], 0, -r);
+        if (a.status_copy) atomicCAS(&a.status_copy[kMeshErr], 0, -r);
+      }
+    }
   }
+  if (lane == 0) s_cnt[wv_i] = out.n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t sum = 0;
+    for (int k = 0; k < kStarWaves; ++k) sum += s_cnt[k];
+    int32_t base = 0;
+    if (sum > 0) {
+      base = atomicAdd(out.counter, sum);
+      if (out.counter_copy) atomicAdd(out.counter_copy, sum);
+    }
+    s_base = base;
+  }
+  __syncthreads();
+  int32_t off = s_base;
+  for (int k = 0; k < wv_i; ++k) off += s_cnt[k];
+  out.write(uniform(off));
 }
 
-__global__ __launch_bounds__(64 * kStarWaves) void k_star(StarJob a) {
-  star_wave(a, blockIdx.x * kStarWaves + (threadIdx.x >> 6));
+__global__ __launch_bounds__(64 * kStarWaves, 5) void k_star(StarJob a) {
+  star_wave(a, blockIdx.x * kStarWaves + uniform((int32_t)threadIdx.x >> 6));
 }
 
-__global__ __launch_bounds__(64 * kStarWaves) void k_star_many(const StarJob* __restrict__ jobs,
+__global__ __launch_bounds__(64 * kStarWaves, 5) void k_star_many(const StarJob* __restrict__ jobs,
                                                                const int32_t* __restrict__ offs, int32_t n_jobs) {
   // the job of this workgroup: the last j with offs[j] <= blockIdx.x
   int32_t lo = 0, hi = n_jobs - 1;
@@ -338,8 +455,7 @@ __global__ __launch_bounds__(64 * kStarWaves) void k_star_many(const StarJob* __
     if (offs[mid] <= b) lo = mid;
     else hi = mid - 1;
   }
-  const StarJob a = jobs[lo];
-  star_wave(a, (b - offs[lo]) * kStarWaves + (threadIdx.x >> 6));
+  star_wave(jobs[lo], (b - offs[lo]) * kStarWaves + uniform((int32_t)threadIdx.x >> 6));
 }
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -363,8 +479,8 @@ StarWork carve(Carve& c, int32_t W, int32_t H, int32_t S_cap) {
   w.uv = c.take<int32_t>((size_t)S_cap);
   w.cell_start = c.take<int32_t>(cells + 1);
   w.cell_cur = c.take<int32_t>(cells);
-  w.cell_pts = c.take<int32_t>((size_t)S_cap);
-  w.cell_uv = c.take<int32_t>((size_t)S_cap);
+  w.cell_e = c.take<star::CellEntry>((size_t)S_cap);
+  w.rows = c.take<star::RowExt>((size_t)H);
   w.row_min = c.take<int32_t>((size_t)H);
   w.row_max = c.take<int32_t>((size_t)H);
   w.S_cap = S_cap;

@@ -15,6 +15,7 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "mesh_star.hpp"
 #include "stereomesh.h"
 
 namespace sm {
@@ -40,10 +41,10 @@ struct StarWork {  // per-frame arrays
   int32_t* uv;          // [S_cap] packed coordinates u | v << 16
   int32_t* cell_start;  // [cells + 1]
   int32_t* cell_cur;    // [cells] fill cursors
-  int32_t* cell_pts;    // [S_cap] support ids ordered by cell
-  int32_t* cell_uv;     // [S_cap] their packed coordinates, in the same order
-  int32_t* row_min;     // [H]
-  int32_t* row_max;     // [H]
+  star::CellEntry* cell_e;  // [S_cap] the supports (id, packed coordinates) ordered by cell
+  star::RowExt* rows;       // [H] smallest and largest u of every pixel row and their supports
+  int32_t* row_min;         // [H] the preparation's counters when they are not in LDS
+  int32_t* row_max;         // [H]
   int32_t gw, gh, S_cap;
 };
 

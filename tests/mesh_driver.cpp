@@ -33,14 +33,15 @@ struct HostWave {
   int lane() const { return 0; }
   bool any(bool b) const { return b; }
   uint64_t min_u64(uint64_t x) const { return x; }
-  void reduce_best(P2, P2, int32_t*, P2*, double*) const {}
+  int32_t pick(bool, int32_t v) const { return v; }
+  void reduce_best(P2, P2, int32_t*, P2*, float*) const {}
   template <class RowFn, class Fn>
   void for_rows(const star::Grid& g, int32_t n, RowFn&& row, Fn&& fn) const {
     for (int32_t i = 0; i < n; ++i) {
       const star::CellRow c = row(i);
       if (c.x0 > c.x1) continue;
       for (int32_t e = g.cell_start[c.cy * g.gw + c.x0]; e < g.cell_start[c.cy * g.gw + c.x1 + 1]; ++e)
-        fn(g.cell_pts[e], star::unpack(g.cell_uv[e]));
+        fn(g.cell_e[e].id, star::unpack(g.cell_e[e].uv));
     }
   }
   template <class Fn>
@@ -67,22 +68,24 @@ int32_t pack_uv(int32_t u, int32_t v) { return u | (v << 16); }
 int star_mesh(const std::vector<int32_t>& uv, int W, int H, std::mt19937& rng, std::vector<sm_tri>& out) {
   const int32_t n = (int32_t)uv.size();
   const int32_t C = star::kStarCell, gw = (W + C - 1) / C, gh = (H + C - 1) / C;
-  std::vector<int32_t> start(gw * gh + 1, 0), pts(n), cuv(n), rmin(H, 1 << 30), rmax(H, -1);
+  std::vector<int32_t> start(gw * gh + 1, 0);
+  std::vector<star::CellEntry> ent(n);
+  std::vector<star::RowExt> rows(H, star::RowExt{1 << 30, -1, -1, -1});
   for (int32_t i = 0; i < n; ++i) {
     const P2 q = star::unpack(uv[i]);
     ++start[(q.y / C) * gw + q.x / C + 1];
-    rmin[q.y] = std::min(rmin[q.y], q.x);
-    rmax[q.y] = std::max(rmax[q.y], q.x);
+    star::RowExt& r = rows[q.y];
+    if (q.x < r.lo) r.lo = q.x, r.lo_id = i;
+    if (q.x > r.hi) r.hi = q.x, r.hi_id = i;
   }
   for (int32_t c = 0; c < gw * gh; ++c) start[c + 1] += start[c];
   std::vector<int32_t> cur(start.begin(), start.end() - 1);
   for (int32_t i = n - 1; i >= 0; --i) {  // any order within a cell gives the same result
     const P2 q = star::unpack(uv[i]);
     const int32_t e = cur[(q.y / C) * gw + q.x / C]++;
-    pts[e] = i;
-    cuv[e] = uv[i];
+    ent[e] = star::CellEntry{i, uv[i]};
   }
-  star::Grid g{uv.data(), n, W, H, gw, gh, start.data(), pts.data(), cuv.data(), rmin.data(), rmax.data()};
+  star::Grid g{uv.data(), n, W, H, gw, gh, start.data(), ent.data(), rows.data()};
   std::vector<int32_t> order(n);
   for (int32_t p = 0; p < n; ++p) order[p] = p;
   std::shuffle(order.begin(), order.end(), rng);
