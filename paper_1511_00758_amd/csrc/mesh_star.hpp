@@ -337,6 +337,23 @@ __host__ __device__ inline Cap cap_of(P2 X, P2 Y, P2 B) {
   c.x0 -= c.m, c.x1 += c.m, c.y0 -= c.m, c.y1 += c.m;
   return c;
 }
+// A quick sufficient test in single precision: the whole disk through (x, y, b), widened by
+// a margin far above the rounding of its centre and radius (relative errors of a few 2^-24
+// of the quotient, the coordinates and the radius), lies inside square r.
+__host__ __device__ inline bool disk_inside_f(P2 X, P2 Y, P2 B, const Grid& g, const Region& r) {
+  if (r.full) return true;
+  const CapKey k = cap_key(X, Y, B);
+  const float t = (float)k.num / (float)k.den;
+  const float ex = (float)(Y.x - X.x), ey = (float)(Y.y - X.y);
+  const float cx = 0.5f * (float)(X.x + Y.x) - t * ey, cy = 0.5f * (float)(X.y + Y.y) + t * ex;
+  const float dx = cx - (float)X.x, dy = cy - (float)X.y;
+  const float rad = sqrtf(dx * dx + dy * dy);
+  const float m = kDiskMargin + 1e-4f * (rad + fabsf(cx) + fabsf(cy));
+  return (cx - rad - m >= (float)(r.x0 * kStarCell) || r.x0 == 0) &&
+         (cx + rad + m < (float)((r.x1 + 1) * kStarCell) || r.x1 == g.gw - 1) &&
+         (cy - rad - m >= (float)(r.y0 * kStarCell) || r.y0 == 0) &&
+         (cy + rad + m < (float)((r.y1 + 1) * kStarCell) || r.y1 == g.gh - 1);
+}
 // Cells of the frame that the cap's box covers.
 __host__ __device__ inline int64_t cap_cells(const Cap& c, const Grid& g) {
   const double w = (c.x1 < g.W ? c.x1 : g.W) - (c.x0 > 0.0 ? c.x0 : 0.0);
@@ -431,6 +448,7 @@ __host__ __device__ inline int32_t next_vertex(WV& wv, const Grid& g, const Regi
     b = best_extreme(wv, g, ix, X, iy, Y, out);
     if (b < 0) return -1;  // nothing left of the edge: a hull edge
   }
+  if (disk_inside_f(X, Y, *out, g, r)) return b;  // the common case, in single precision
   for (Region s = r;;) {
     const Cap c = cap_of(X, Y, *out);
     if (cap_inside(c, g, s)) return b;

@@ -441,11 +441,11 @@ __device__ void star_wave(const StarJob& a, int32_t local_wave) {
   out.write(uniform(off));
 }
 
-__global__ __launch_bounds__(64 * kStarWaves, 5) void k_star(StarJob a) {
+__global__ __launch_bounds__(64 * kStarWaves) void k_star(StarJob a) {
   star_wave(a, blockIdx.x * kStarWaves + uniform((int32_t)threadIdx.x >> 6));
 }
 
-__global__ __launch_bounds__(64 * kStarWaves, 5) void k_star_many(const StarJob* __restrict__ jobs,
+__global__ __launch_bounds__(64 * kStarWaves) void k_star_many(const StarJob* __restrict__ jobs,
                                                                const int32_t* __restrict__ offs, int32_t n_jobs) {
   // the job of this workgroup: the last j with offs[j] <= blockIdx.x
   int32_t lo = 0, hi = n_jobs - 1;
