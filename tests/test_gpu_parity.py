@@ -259,6 +259,16 @@ def test_interpolate_supports_outside_image():
     assert _interp_compare(S, tris, W, H) == 1.0
 
 
+def test_interpolate_fan_over_small_image():
+    """A fan of 499 thin triangles from one apex far below a 12 x 3 image: every triangle's
+    box covers the image, few triangles own pixels of it."""
+    W, H = 12, 3
+    S = [(0, 100, 3.0)] + [(x, 0, float(np.float32(0.25 * x))) for x in range(500)]
+    tris = oracle.triangulate(S, 8192)
+    assert len(tris) == 499
+    assert _interp_compare(S, tris, W, H) == 1.0
+
+
 def test_interpolate_no_triangles():
     api = _api()
     D = api.interpolate(api.new_support_buffer(1, DEV), 0, np.zeros((0, 3), np.int32), 17, 9)
