@@ -412,6 +412,20 @@ def batched_runs(api, vga_frames, vga_params, workers=16, batches=12, dev="cuda:
     out["batch64_mixed_stage_batched"] = run_many(mixed, batches)
     out["vga_20planes_batch64_graph"] = run_graph(vga, batches)
     out["batch64_mixed_graph"] = run_graph(mixed, batches)
+    # the mixed batch again after sm_autotune on one frame of each size and disparity range
+    # (matcher lanes per candidate, census rows, validation and raster shapes of that size)
+    tuned = {}
+    for (l, r, prm) in base:
+        H_, W_ = l.shape
+        key = f"{W_}x{H_} d0-{prm['d_max']}"
+        if key not in tuned:
+            tuned[key] = api.Solver(W_, H_, prm, device=dev).autotune(l, r)
+    torch.cuda.synchronize()
+    out["batch64_mixed_stage_batched_tuned"] = run_many(mixed, batches)
+    out["batch64_mixed_stage_batched_tuned"]["autotune"] = tuned
+    out["batch64_mixed_stage_batched_tuned"]["change_vs_untuned"] = round(
+        out["batch64_mixed_stage_batched_tuned"]["frames_per_s"] / out["batch64_mixed_stage_batched"]["frames_per_s"],
+        3)
 
     # 256 frames: one mesh workgroup per frame fills all 256 CUs; three frames of the
     # replayed batch are compared with the per-frame solver

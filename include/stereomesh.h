@@ -396,16 +396,32 @@ void sm_many_graph_destroy(sm_many_graph* g);
  * sm_autotune -- measures the tunable launch shapes on one frame and records the fastest
  *   for its size (used by every later sm_solve / sm_solve_many launch of that size in this
  *   process; outputs do not depend on them): validation's block size in waves (1, 2, 4, 8
- *   or 16) for each iteration's cell size, and, for grid supports with device meshes, the
- *   workgroups of the rasteriser's bounded grid (512 ... 8192). Solves the frame, times
- *   each candidate over five launches on the solve's buffers, then solves the frame again,
- *   so that D_f, C_f and mask hold its results. Arguments as sm_solve.
- *   choices  [host] [9] out: validation waves per iteration (0 past n_iters), then the
- *            raster workgroups (0 when not tuned).
+ *   or 16) for each iteration's cell size; for device meshes, the workgroups of the
+ *   rasteriser's bounded grid (512 ... 8192); for grid supports, the matcher's lanes per
+ *   candidate (64, 32 or 16: 1, 2 or 4 candidates per wave, each candidate's disparity
+ *   range in chunks of that many lanes), per disparity range; and the census tile's rows
+ *   (8, 16 or 32 rows of 64 columns), per window size. Solves the frame, times each
+ *   candidate over five launches on the solve's buffers, then solves the frame again, so
+ *   that D_f, C_f and mask hold its results. Arguments as sm_solve.
+ *   choices  [host] [11] out: validation waves per iteration (0 past n_iters), the raster
+ *            workgroups, the matcher's lanes per candidate, the census rows per tile (0
+ *            where not tuned).
  */
 sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
                       const sm_params* p /* [host] */, void* ws, size_t ws_bytes, float* D_f, uint8_t* C_f,
                       uint8_t* mask, int32_t* choices /* [host] */, void* stream);
+
+/*
+ * sm_set_launch_shape -- records a launch-shape choice as sm_autotune would (value > 0) or
+ *   clears it (value = 0: the built-in rule again), for reproducible timings and for
+ *   checking that every shape gives the same results. Host only; thread-safe.
+ *   kind 0: validation waves per block (1, 2, 4, 8, 16), key = cell size sz_occ;
+ *   kind 1: raster workgroups (512, 1024, 2048, 4096, 8192), key = 0;
+ *   kind 2: matcher lanes per candidate (16, 32, 64), key = d_max - d_min + 1;
+ *   kind 3: census rows per tile (8, 16, 32), key = ((census_w-1)/2) << 8 | ((census_h-1)/2).
+ *   Returns SM_ERR_ARG for another kind, value or size.
+ */
+sm_status sm_set_launch_shape(int32_t kind, int32_t W, int32_t H, int32_t key, int32_t value);
 
 /* Message of the calling thread's last non-OK status ("" if none). */
 const char* sm_last_error(void);

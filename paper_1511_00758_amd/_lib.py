@@ -72,7 +72,7 @@ EXPORTS = ("sm_census", "sm_match_support", "sm_grid_candidates", "sm_fast_candi
            "sm_interpolate", "sm_cells", "sm_validate", "sm_resample",
            "sm_solve_workspace_bytes", "sm_solve", "sm_solve_noalloc", "sm_solve_batch", "sm_solve_many_workspace_bytes",
            "sm_solve_many", "sm_solve_many_capture", "sm_many_graph_run", "sm_many_graph_destroy", "sm_autotune",
-           "sm_last_error", "sm_version")
+           "sm_set_launch_shape", "sm_last_error", "sm_version")
 
 
 class StereoMeshError(RuntimeError):
@@ -120,6 +120,7 @@ def load():
         "sm_solve_many_capture": (c_i32, [P(SmFrame), c_i32, c_vp, c_size, P(SmStats), c_vp, P(c_vp)]),
         "sm_many_graph_run": (c_i32, [c_vp, P(SmStats), c_vp]),
         "sm_many_graph_destroy": (None, [c_vp]),
+        "sm_set_launch_shape": (c_i32, [c_i32, c_i32, c_i32, c_i32, c_i32]),
         "sm_autotune": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, P(SmParams), c_vp, c_size, c_vp, c_vp, c_vp,
                                 P(c_i32), c_vp]),
         "sm_last_error": (ctypes.c_char_p, []),

@@ -337,12 +337,22 @@ class Solver:
         check_image(left, "left", self._shape, self.D_f.device)
         check_image(right, "right", self._shape, self.D_f.device)
         L = _lib.load()
-        ch = (ctypes.c_int32 * 9)()
+        ch = (ctypes.c_int32 * 11)()
         check(L.sm_autotune(left.data_ptr(), right.data_ptr(), self.W, self.H, left.stride(0), self.p,
                             self.ws_ptr, self.ws_bytes, self.D_f.data_ptr(), self.C_f.data_ptr(),
                             self.mask.data_ptr(), ch, _stream(stream)))
         n = self.p.n_iters
-        return {"validate_waves": [int(ch[k]) for k in range(min(n, 8))], "raster_blocks": int(ch[8])}
+        return {"validate_waves": [int(ch[k]) for k in range(min(n, 8))], "raster_blocks": int(ch[8]),
+                "match_lanes": int(ch[9]), "census_rows": int(ch[10])}
+
+
+LAUNCH_SHAPES = {"validate_waves": 0, "raster_blocks": 1, "match_lanes": 2, "census_rows": 3}
+
+
+def set_launch_shape(kind: str, W: int, H: int, key: int, value: int) -> None:
+    """Records (value > 0) or clears (value = 0) a launch-shape choice for W x H frames
+    (``sm_set_launch_shape``); kinds and keys as in LAUNCH_SHAPES and the C header."""
+    check(_lib.load().sm_set_launch_shape(LAUNCH_SHAPES[kind], int(W), int(H), int(key), int(value)))
 
 
 def solve(left: torch.Tensor, right: torch.Tensor, params: dict, stats=False) -> SolveResult:

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <initializer_list>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -769,6 +770,28 @@ sm_status sm_solve_noalloc(const uint8_t* L, const uint8_t* R, int32_t W, int32_
   return SM_OK;
 }
 
+sm_status sm_set_launch_shape(int32_t kind, int32_t W, int32_t H, int32_t key, int32_t value) {
+  last_error().clear();
+  SM_TRY(check_image_args(W, H));
+  auto one_of = [&](std::initializer_list<int32_t> ok) {
+    if (value == 0) return true;
+    for (int32_t v : ok)
+      if (v == value) return true;
+    return false;
+  };
+  bool ok = false;
+  switch (kind) {
+    case kTuneValidateWaves: ok = key >= 1 && one_of({1, 2, 4, 8, 16}); break;
+    case kTuneRasterBlocks: ok = key == 0 && one_of({512, 1024, 2048, 4096, 8192}); break;
+    case kTuneMatchLanes: ok = key >= 1 && key <= 256 && one_of({16, 32, 64}); break;
+    case kTuneCensusRows: ok = key >= 0 && one_of({8, 16, 32}); break;
+    default: break;
+  }
+  if (!ok) return fail(SM_ERR_ARG, "launch shape kind %d, key %d, value %d not accepted", kind, key, value);
+  set_tuned_choice(kind, W, H, key, value);
+  return SM_OK;
+}
+
 // Measured launch shapes for one frame size and parameter set (the autotuner of the
 // batched and per-frame solves): the frame is solved once, then each tunable launch is
 // timed over its candidate shapes on the buffers of that solve, the fastest is recorded
@@ -781,7 +804,7 @@ sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, 
   SM_TRY(check_image_args(W, H));
   SM_TRY(check_params(p));
   if (!choices) return fail(SM_ERR_ARG, "choices is NULL");
-  for (int k = 0; k < 9; ++k) choices[k] = 0;
+  for (int k = 0; k < 11; ++k) choices[k] = 0;
   SM_TRY(sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, nullptr, stream));
   const Layout Lo = layout_of(W, H, *p);
   uint8_t* base = (uint8_t*)ws;
@@ -845,6 +868,47 @@ sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, 
     }
     set_tuned_choice(kTuneRasterBlocks, W, H, 0, best);
     choices[8] = best;
+  }
+  // census: rows per tile, with the solve's own arguments (every output is rewritten by the
+  // final solve)
+  {
+    const CensusJob jobs[2] = {{L, stride, (uint64_t*)cL, (uint8_t*)omega}, {R, stride, (uint64_t*)cR, nullptr}};
+    CensusExtras ex;
+    ex.D_nan = (float*)D_it;
+    ex.grid_slots = p->support_mode == 1 ? nullptr : (sm_support*)(base + Lo.S);
+    ex.step = p->support_step;
+    ex.gw = Lo.n_grid > 0 ? (W - 1 - p->support_step / 2) / p->support_step + 1 : 0;
+    ex.zero = (int32_t*)(base + Lo.counters);
+    ex.n_zero = 16;
+    int best = 0;
+    float best_ms = 0.f;
+    for (int rows : {8, 16, 32}) {
+      const float ms = time_it([&] {
+        return launch_census(jobs, 2, W, H, p->census_w, p->census_h, p->grad_thr, D_f, C_f, p->t_hi,
+                             base + Lo.occ, &ex, s, rows);
+      });
+      if (ms < 0.f) return done(fail(SM_ERR_HIP, "census timing failed"));
+      if (best == 0 || ms < best_ms) best = rows, best_ms = ms;
+    }
+    set_tuned_choice(kTuneCensusRows, W, H, ((p->census_w - 1) / 2) << 8 | ((p->census_h - 1) / 2), best);
+    choices[10] = best;
+  }
+  // matching: lanes per candidate (1, 2 or 4 candidates per wave), on the grid candidates
+  // (each timed launch first resets the slots to pending from Omega)
+  if (p->support_mode == 0 && Lo.n_grid > 0) {
+    sm_support* slots = (sm_support*)(base + Lo.S);
+    int best = 0;
+    float best_ms = 0.f;
+    for (int lanes : {64, 32, 16}) {
+      const float ms = time_it([&] {
+        const hipError_t e = launch_grid_slots(omega, W, H, p->support_step, slots, Lo.n_grid, s);
+        return e != hipSuccess ? e : launch_match_lanes(cL, cR, W, H, *p, slots, Lo.n_grid, lanes, s);
+      });
+      if (ms < 0.f) return done(fail(SM_ERR_HIP, "matching timing failed"));
+      if (best == 0 || ms < best_ms) best = lanes, best_ms = ms;
+    }
+    set_tuned_choice(kTuneMatchLanes, W, H, p->d_max - p->d_min + 1, best);
+    choices[9] = best;
   }
   // the outputs of the frame again (the timed validations refined D_f and C_f)
   return done(sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, nullptr, stream));

@@ -431,6 +431,8 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
     d.C_f = fr.C_f;
     d.mask = fr.mask;
     d.n_grid = L.n_grid;
+    d.match_lanes = match_lanes_for(fr.W, fr.H, fr.p);
+    d.census_rows = census_rows_for(fr.W, fr.H, fr.p.census_w, fr.p.census_h);
     d.gw = L.n_grid > 0 ? (fr.W - 1 - fr.p.support_step / 2) / fr.p.support_step + 1 : 0;
     d.sz = occ_size(fr.p, 1);
     d.pack = L.mesh_on ? nullptr : dpack + P.pack_off[f];  // device-mesh frames keep their supports
@@ -442,13 +444,13 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
     o[0] = 0;
     for (int32_t f = 0; f < n; ++f) {
       const int32_t key = ((frames[f].p.census_w - 1) / 2) << 8 | ((frames[f].p.census_h - 1) / 2);
-      o[f + 1] = o[f] + (key == P.groups[g] ? 2 * census_tiles(frames[f].W, frames[f].H) : 0);
+      o[f + 1] = o[f] + (key == P.groups[g] ? 2 * census_tiles(frames[f].W, frames[f].H, hF[f].census_rows) : 0);
     }
   }
   {
     int32_t* o = off_arr(kMatch);
     o[0] = 0;
-    for (int32_t f = 0; f < n; ++f) o[f + 1] = o[f] + P.lay[f].n_grid;
+    for (int32_t f = 0; f < n; ++f) o[f + 1] = o[f] + match_units(P.lay[f].n_grid, hF[f].match_lanes);
   }
   // frames whose meshes live on the device (grid supports, host_mesh = 0): the first mesh is
   // built by one launch over them right after compaction; job j's status words come back

@@ -60,27 +60,30 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
 
 // ------------------------------------------------------------------------------------
 // Census words + Omega_I (+ optional initialisation of D_f, C_f and the occupancy map).
-// Tile of 64 x 16 output pixels per 256-thread block, staged in LDS with its halo.
+// Tile of 64 x th output pixels per 256-thread block (th = 8, 16 or 32 rows: a launch-shape
+// choice of sm_autotune, 16 by default), staged in LDS with its halo.
 // ------------------------------------------------------------------------------------
-constexpr int kTW = 64, kTH = 16;
+constexpr int kTW = 64, kTH = 16, kTHMax = 32;
 
 struct CensusArgs {
   CensusJob job[2];
   int32_t W, H, grad_thr, t_hi;
+  int32_t th;  // tile rows
   float* D_f;
   uint8_t* C_f;
   uint8_t* occ;
   CensusExtras x;
 };
 
-// One 64 x 16 output tile (bx, by) of image `job` (0 = left: also Omega_I and the
+// One 64 x a.th output tile (bx, by) of image `job` (0 = left: also Omega_I and the
 // per-frame initialisation). `tile` is the block's LDS staging area.
 template <int RX, int RY>
 __device__ __forceinline__ void census_block(const CensusArgs& a, int job, int bx, int by, uint8_t* tile) {
-  constexpr int PW = kTW + 2 * RX, PH = kTH + 2 * RY;
+  constexpr int PW = kTW + 2 * RX;
+  const int th = a.th, PH = th + 2 * RY;
   const CensusJob jb = a.job[job];
   const int W = a.W, H = a.H;
-  const int gx0 = bx * kTW - RX, gy0 = by * kTH - RY;
+  const int gx0 = bx * kTW - RX, gy0 = by * th - RY;
   for (int i = threadIdx.y * kTW + threadIdx.x; i < PH * PW; i += 256) {
     int ty = i / PW, tx = i - ty * PW;
     int gx = min(max(gx0 + tx, 0), W - 1), gy = min(max(gy0 + ty, 0), H - 1);
@@ -88,10 +91,9 @@ __device__ __forceinline__ void census_block(const CensusArgs& a, int job, int b
   }
   __syncthreads();
   const int u = bx * kTW + threadIdx.x;
-#pragma unroll
-  for (int r = 0; r < kTH / 4; ++r) {
+  for (int r = 0; r < th / 4; ++r) {
     const int ly = threadIdx.y + 4 * r;
-    const int v = by * kTH + ly;
+    const int v = by * th + ly;
     if (v >= H || u >= W) break;
     const size_t idx = (size_t)v * W + u;
     const bool valid = u >= RX && u < W - RX && v >= RY && v < H - RY;
@@ -150,13 +152,13 @@ __device__ __forceinline__ void census_block(const CensusArgs& a, int job, int b
 
 template <int RX, int RY>
 __global__ __launch_bounds__(256) void k_census(CensusArgs a) {
-  __shared__ uint8_t tile[(kTH + 2 * RY) * (kTW + 2 * RX)];
+  __shared__ uint8_t tile[(kTHMax + 2 * RY) * (kTW + 2 * RX)];
   census_block<RX, RY>(a, blockIdx.z, blockIdx.x, blockIdx.y, tile);
 }
 
 template <int RX, int RY>
 hipError_t census_launch(const CensusArgs& a, int n_jobs, hipStream_t s) {
-  dim3 grid((a.W + kTW - 1) / kTW, (a.H + kTH - 1) / kTH, n_jobs);
+  dim3 grid((a.W + kTW - 1) / kTW, (a.H + a.th - 1) / a.th, n_jobs);
   SM_LAUNCH((k_census<RX, RY>), grid, dim3(kTW, 4, 1), 0, s, a);
   return hipGetLastError();
 }
@@ -419,8 +421,10 @@ __global__ __launch_bounds__(1024) void k_compact_uv(int16_t* uv, int n, int* n_
 }
 
 // ------------------------------------------------------------------------------------
-// Epipolar matching: one wave per candidate, lanes over disparities (up to 4 chunks of
-// 64), wave-shuffle argmin over packed (cost << 8 | d) keys.
+// Epipolar matching: a group of G lanes per candidate (G = 64, 32 or 16: 1, 2 or 4
+// candidates per wave), the group's lanes over the disparities in ceil(N_D / G) chunks,
+// group-shuffle argmin over packed (cost << 8 | d) keys. G is a launch-shape choice
+// (sm_autotune), the result does not depend on it.
 // ------------------------------------------------------------------------------------
 struct MatchArgs {
   const uint64_t* cL;
@@ -430,25 +434,47 @@ struct MatchArgs {
   int32_t n;
 };
 
-// Matches left pixel (u, v) (inside the census-valid region); every lane of the wave
-// must call it with the same (u, v). Returns d* or -1 when rejected.
-__device__ int match_one(const MatchArgs& a, int u, int v, int lane) {
+constexpr int kMaxDisp = 256;  // d_max - d_min + 1 (enforced by the parameter checks)
+
+template <int G>
+__device__ __forceinline__ uint32_t group_min_u32(uint32_t x) {
+#pragma unroll
+  for (int off = G / 2; off >= 1; off >>= 1) {
+    const uint32_t y = __shfl_xor(x, off, kWave);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+// any lane of this lane's group of G
+template <int G>
+__device__ __forceinline__ bool group_any(bool b, int lane) {
+  const uint64_t m = __ballot(b);
+  return G == kWave ? m != 0ull : ((m >> (lane & ~(G - 1))) & ((1ull << (G & 63)) - 1)) != 0ull;
+}
+
+// Matches left pixel (u, v) (inside the census-valid region); every lane of the group
+// must call it with the same (u, v); gl is the lane's index in its group. Returns d* or -1
+// when rejected.
+template <int G>
+__device__ int match_one_g(const MatchArgs& a, int u, int v, int gl, int lane) {
+  constexpr int kChunks = kMaxDisp / G;
+  const int chunks = (a.d_max - a.d_min + G) / G;
   const int W = a.W;
   const uint64_t* rowL = a.cL + (size_t)v * W;
   const uint64_t* rowR = a.cR + (size_t)v * W;
   const uint64_t wl = rowL[u];
-  uint32_t cost[4];
+  uint32_t cost[kChunks];
   uint32_t best = 0xffffffffu;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int d = a.d_min + lane + kWave * c;
-    const bool ok = d <= a.d_max && u - d >= a.rx;
+  for (int c = 0; c < kChunks; ++c) {
+    const int d = a.d_min + gl + G * c;
+    const bool ok = c < chunks && d <= a.d_max && u - d >= a.rx;
     const uint32_t cs = ok ? (uint32_t)__popcll(wl ^ rowR[u - d]) : 0xffu;
     cost[c] = cs;
     const uint32_t key = ok ? (cs << 8 | (uint32_t)d) : 0xffffffffu;
     best = key < best ? key : best;
   }
-  best = wave_min_u32(best);
+  best = group_min_u32<G>(best);
   if (best == 0xffffffffu) return -1;  // no admissible disparity
   const int dstar = (int)(best & 0xffu);
   const uint32_t cstar = best >> 8;
@@ -456,47 +482,61 @@ __device__ int match_one(const MatchArgs& a, int u, int v, int lane) {
   if (a.uniq > 0) {
     bool bad = false;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int d = a.d_min + lane + kWave * c;
-      const bool ok = d <= a.d_max && u - d >= a.rx;
+    for (int c = 0; c < kChunks; ++c) {
+      const int d = a.d_min + gl + G * c;
+      const bool ok = c < chunks && d <= a.d_max && u - d >= a.rx;
       const int dd = d - dstar;
       bad |= ok && (dd >= 2 || dd <= -2) && cost[c] < cstar + (uint32_t)a.uniq;
     }
-    if (__ballot(bad) != 0ull) return -1;
+    if (group_any<G>(bad, lane)) return -1;
   }
   // left-right check from the matched right pixel
   const int ur = u - dstar;
   const uint64_t wr = rowR[ur];
   uint32_t best2 = 0xffffffffu;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int d = a.d_min + lane + kWave * c;
-    const bool ok = d <= a.d_max && ur + d <= W - 1 - a.rx;
+  for (int c = 0; c < kChunks; ++c) {
+    const int d = a.d_min + gl + G * c;
+    const bool ok = c < chunks && d <= a.d_max && ur + d <= W - 1 - a.rx;
     const uint32_t key = ok ? ((uint32_t)__popcll(wr ^ rowL[ur + d]) << 8 | (uint32_t)d) : 0xffffffffu;
     best2 = key < best2 ? key : best2;
   }
-  best2 = wave_min_u32(best2);
+  best2 = group_min_u32<G>(best2);
   const int diff = (int)(best2 & 0xffu) - dstar;
   return (diff <= a.lr_tol && -diff <= a.lr_tol) ? dstar : -1;
+}
+
+// one whole wave per pixel (the re-match of a cell)
+__device__ __forceinline__ int match_one(const MatchArgs& a, int u, int v, int lane) {
+  return match_one_g<kWave>(a, u, v, lane, lane);
 }
 
 __device__ __forceinline__ bool match_inside(const MatchArgs& a, int u, int v) {
   return u >= a.rx && u < a.W - a.rx && v >= a.ry && v < a.H - a.ry;
 }
 
-// Matches candidate slot `slot` if it is pending (the whole wave calls it).
+// Matches candidate slot `slot` if it is pending (the whole group calls it).
+template <int G>
 __device__ __forceinline__ void match_slot(const MatchArgs& a, int slot, int lane) {
   const sm_support s = a.slots[slot];
   if (s.d != kPending) return;
-  const int d = match_inside(a, s.u, s.v) ? match_one(a, s.u, s.v, lane) : -1;
-  if (lane == 0) a.slots[slot].d = d >= 0 ? (float)d : kRejected;
+  const int gl = lane & (G - 1);
+  const int d = match_inside(a, s.u, s.v) ? match_one_g<G>(a, s.u, s.v, gl, lane) : -1;
+  if (gl == 0) a.slots[slot].d = d >= 0 ? (float)d : kRejected;
 }
 
+// slot of this lane's group: waves of 256-thread blocks, kWave / G groups per wave
+template <int G>
+__device__ __forceinline__ int match_unit_slot(int wave_unit, int lane) {
+  return wave_unit * (kWave / G) + lane / G;
+}
+
+template <int G>
 __global__ __launch_bounds__(256) void k_match(MatchArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int slot = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (slot >= a.n) return;
-  match_slot(a, slot, lane);
+  const int slot = match_unit_slot<G>(blockIdx.x * 4 + (threadIdx.x >> 6), lane);
+  if (slot >= a.n) return;  // (whole groups: a group's lanes share the slot)
+  match_slot<G>(a, slot, lane);
 }
 
 // Resampling (Alg. 4) fused with the re-match: one wave per cell. Slot c receives the
@@ -951,8 +991,11 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
 
 hipError_t launch_census(const CensusJob* jobs, int n_jobs, int32_t W, int32_t H, int32_t cw,
                          int32_t ch, int32_t grad_thr, float* D_f, uint8_t* C_f, int32_t t_hi,
-                         uint8_t* occ, const CensusExtras* extras, hipStream_t s) {
+                         uint8_t* occ, const CensusExtras* extras, hipStream_t s, int32_t rows) {
+  if (rows == 0) rows = census_rows_for(W, H, cw, ch);
+  if (rows != 8 && rows != 16 && rows != 32) return hipErrorInvalidValue;
   CensusArgs a{};
+  a.th = rows;
   if (extras) a.x = *extras;
   for (int i = 0; i < n_jobs; ++i) a.job[i] = jobs[i];
   a.W = W;
@@ -1017,12 +1060,30 @@ hipError_t launch_list_slots(const int16_t* uv, int32_t n, sm_support* slots, hi
   return hipGetLastError();
 }
 
-hipError_t launch_match(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
-                        const sm_params& p, sm_support* slots, int32_t n, hipStream_t s) {
+int32_t match_lanes_for(int32_t W, int32_t H, const sm_params& p) {
+  const int32_t tuned = tuned_choice(kTuneMatchLanes, W, H, p.d_max - p.d_min + 1);
+  return tuned == 16 || tuned == 32 ? tuned : kWave;
+}
+
+int32_t match_units(int32_t n, int32_t lanes) { return (n + kWave / lanes - 1) / (kWave / lanes); }
+
+hipError_t launch_match_lanes(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H, const sm_params& p,
+                              sm_support* slots, int32_t n, int32_t lanes, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const MatchArgs a = match_args(cL, cR, W, H, p, slots, n);
-  SM_LAUNCH(k_match, dim3(blocks_for(n, 4)), dim3(256), 0, s, a);
+  const dim3 grid(blocks_for(match_units(n, lanes), 4));
+  switch (lanes) {
+    case 16: SM_LAUNCH(k_match<16>, grid, dim3(256), 0, s, a); break;
+    case 32: SM_LAUNCH(k_match<32>, grid, dim3(256), 0, s, a); break;
+    case kWave: SM_LAUNCH(k_match<kWave>, grid, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
+}
+
+hipError_t launch_match(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
+                        const sm_params& p, sm_support* slots, int32_t n, hipStream_t s) {
+  return launch_match_lanes(cL, cR, W, H, p, slots, n, match_lanes_for(W, H, p), s);
 }
 
 hipError_t launch_compact(sm_support* slots, int32_t n, int32_t* n_out, uint8_t* occ, int32_t W,
@@ -1144,7 +1205,8 @@ int32_t tuned_choice(int kind, int32_t W, int32_t H, int32_t sz) {
 
 void set_tuned_choice(int kind, int32_t W, int32_t H, int32_t sz, int32_t value) {
   std::lock_guard<std::mutex> lk(g_tune_m);
-  g_tune[std::make_tuple(kind, W, H, sz)] = value;
+  if (value == 0) g_tune.erase(std::make_tuple(kind, W, H, sz));
+  else g_tune[std::make_tuple(kind, W, H, sz)] = value;
 }
 
 hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
@@ -1226,11 +1288,11 @@ __device__ __forceinline__ int frame_of(const int32_t* off, int n, int unit) {
 
 template <int RX, int RY>
 __global__ __launch_bounds__(256) void k_batch_census(const BatchFrame* F, const int32_t* off, int n) {
-  __shared__ uint8_t tile[(kTH + 2 * RY) * (kTW + 2 * RX)];
+  __shared__ uint8_t tile[(kTHMax + 2 * RY) * (kTW + 2 * RX)];
   const int f = frame_of(off, n, blockIdx.x);
   const BatchFrame& fr = F[f];
   const int local = blockIdx.x - off[f];
-  const int tx = (fr.W + kTW - 1) / kTW, ty = (fr.H + kTH - 1) / kTH;
+  const int tx = (fr.W + kTW - 1) / kTW, ty = (fr.H + fr.census_rows - 1) / fr.census_rows;
   const int job = local / (tx * ty), t = local - job * tx * ty;
   CensusArgs a{};
   a.job[0] = CensusJob{fr.L, fr.stride, fr.cL, fr.omega};
@@ -1239,6 +1301,7 @@ __global__ __launch_bounds__(256) void k_batch_census(const BatchFrame* F, const
   a.H = fr.H;
   a.grad_thr = fr.p.grad_thr;
   a.t_hi = fr.p.t_hi;
+  a.th = fr.census_rows;
   a.D_f = fr.D_f;
   a.C_f = fr.C_f;
   a.occ = fr.occ;
@@ -1251,6 +1314,7 @@ __global__ __launch_bounds__(256) void k_batch_census(const BatchFrame* F, const
   census_block<RX, RY>(a, job, t % tx, t / tx, tile);
 }
 
+// a unit is one wave of the frame's candidates, kWave / match_lanes per wave
 __global__ __launch_bounds__(256) void k_batch_match(const BatchFrame* F, const int32_t* off, int n, int total) {
   const int lane = threadIdx.x & (kWave - 1);
   const int unit = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -1258,7 +1322,17 @@ __global__ __launch_bounds__(256) void k_batch_match(const BatchFrame* F, const 
   const int f = frame_of(off, n, unit);
   const BatchFrame& fr = F[f];
   const MatchArgs a = match_args(fr.cL, fr.cR, fr.W, fr.H, fr.p, fr.S, fr.n_grid);
-  match_slot(a, unit - off[f], lane);
+  const int u = unit - off[f];
+  if (fr.match_lanes == 16) {
+    const int slot = match_unit_slot<16>(u, lane);
+    if (slot < a.n) match_slot<16>(a, slot, lane);
+  } else if (fr.match_lanes == 32) {
+    const int slot = match_unit_slot<32>(u, lane);
+    if (slot < a.n) match_slot<32>(a, slot, lane);
+  } else {
+    const int slot = match_unit_slot<kWave>(u, lane);
+    if (slot < a.n) match_slot<kWave>(a, slot, lane);
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_batch_compact(const BatchFrame* F, int mode) {
@@ -1329,7 +1403,14 @@ __global__ __launch_bounds__(256) void k_batch_rematch(const BatchFrame* F, cons
 
 }  // namespace
 
-int32_t census_tiles(int32_t W, int32_t H) { return (int32_t)(blocks_for(W, kTW) * blocks_for(H, kTH)); }
+int32_t census_tiles(int32_t W, int32_t H, int32_t rows) {
+  return (int32_t)(blocks_for(W, kTW) * blocks_for(H, (unsigned)rows));
+}
+
+int32_t census_rows_for(int32_t W, int32_t H, int32_t cw, int32_t ch) {
+  const int32_t tuned = tuned_choice(kTuneCensusRows, W, H, ((cw - 1) / 2) << 8 | ((ch - 1) / 2));
+  return tuned == 8 || tuned == 32 ? tuned : kTH;
+}
 
 hipError_t launch_batch_census(const BatchFrame* F, const int32_t* off, int32_t n, int32_t total, int rx, int ry,
                                hipStream_t s) {

@@ -42,7 +42,7 @@ struct CensusExtras {
 // When D_f / C_f / occ are non-null they are initialised (0, t_hi, 0) on the way.
 hipError_t launch_census(const CensusJob* jobs, int n_jobs, int32_t W, int32_t H, int32_t cw,
                          int32_t ch, int32_t grad_thr, float* D_f, uint8_t* C_f, int32_t t_hi,
-                         uint8_t* occ, const CensusExtras* extras, hipStream_t s);
+                         uint8_t* occ, const CensusExtras* extras, hipStream_t s, int32_t rows = 0);
 
 // Candidate slots: grid nodes (omega-filtered) or an explicit (u, v) list.
 hipError_t launch_grid_slots(const uint8_t* omega, int32_t W, int32_t H, int32_t step,
@@ -60,6 +60,13 @@ hipError_t launch_fast_select(const uint8_t* score, int32_t W, int32_t H, const 
 hipError_t launch_compact_uv(int16_t* uv, int32_t n, int32_t* n_out, hipStream_t s);
 
 // Epipolar matching with left-right check of every pending slot, in place.
+// Lanes per candidate of the matcher for a W x H frame with these parameters (16, 32 or
+// 64: the sm_autotune choice, else 64), the waves that n candidates take, and the launch
+// with an explicit choice (launch_match uses match_lanes_for).
+int32_t match_lanes_for(int32_t W, int32_t H, const sm_params& p);
+int32_t match_units(int32_t n, int32_t lanes);
+hipError_t launch_match_lanes(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H, const sm_params& p,
+                              sm_support* slots, int32_t n, int32_t lanes, hipStream_t s);
 hipError_t launch_match(const uint64_t* cL, const uint64_t* cR, int32_t W, int32_t H,
                         const sm_params& p, sm_support* slots, int32_t n, hipStream_t s);
 
@@ -100,9 +107,9 @@ hipError_t launch_validate_only(const uint64_t* cL, const uint64_t* cR, const ui
 // Launch shapes measured by sm_autotune, consulted before the built-in rules (a choice
 // changes speed only: every shape gives the same outputs). Keys: the kernel, the frame
 // size and, for validation, the occupancy cell size.
-enum TuneKind { kTuneValidateWaves = 0, kTuneRasterBlocks = 1 };
+enum TuneKind { kTuneValidateWaves = 0, kTuneRasterBlocks = 1, kTuneMatchLanes = 2, kTuneCensusRows = 3 };
 int32_t tuned_choice(int kind, int32_t W, int32_t H, int32_t sz);  // -1: none
-void set_tuned_choice(int kind, int32_t W, int32_t H, int32_t sz, int32_t value);
+void set_tuned_choice(int kind, int32_t W, int32_t H, int32_t sz, int32_t value);  // 0: clear
 // Validation with a given block size in waves (1, 2, 4, 8 or 16) instead of the rule.
 hipError_t launch_validate_nw(const uint64_t* cL, const uint64_t* cR, const uint8_t* omega,
                               const float* D_it, int32_t W, int32_t H, const sm_params& p,
@@ -159,6 +166,8 @@ struct BatchFrame {
   uint8_t* C_f;
   uint8_t* mask;
   int32_t n_grid, gw;        // grid candidate slots, grid nodes per row
+  int32_t match_lanes;       // lanes per candidate of the matcher (match_lanes_for)
+  int32_t census_rows;       // rows of a census tile (census_rows_for)
   // state of the current iteration, rewritten before its launches
   const sm_tri* T;
   int32_t n_T, n_S, sz, last;  // last: this iteration writes the mask
@@ -173,7 +182,10 @@ struct BatchFrame {
   int32_t S_cap, T_cap;
 };
 
-int32_t census_tiles(int32_t W, int32_t H);
+// census tiles of a W x H image at `rows` rows per tile, and the rows a W x H image with a
+// cw x ch window uses (the sm_autotune choice, else 16)
+int32_t census_tiles(int32_t W, int32_t H, int32_t rows);
+int32_t census_rows_for(int32_t W, int32_t H, int32_t cw, int32_t ch);
 int32_t validate_blocks(int32_t W, int32_t H, int32_t sz, int nw);
 // smallest block size (waves) whose batched grid still holds enough waves
 int validate_pick_nw(int64_t (*waves)(int nw, void* ctx), void* ctx);

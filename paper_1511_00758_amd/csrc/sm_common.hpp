@@ -67,11 +67,9 @@ inline int32_t grid_count(int32_t W, int32_t H, int32_t step) {
 struct Layout {
   size_t cL, cR, omega, occ, D_it, cell_g, cell_b, S, T, counters, score, total;
   int32_t n_grid, S_cap, T_cap, cells_max;  // n_grid: initial candidate slots (grid or FAST)
-  // device mesh (n_iters >= 2 and host_mesh == 0): status words and the frame's mesh
-  // arrays for at most mpcap new supports per tessellation
+  // device meshes (host_mesh == 0): the status words and the star kernels' arrays
   bool mesh_on;
   size_t mstatus, mwork;
-  int32_t mpcap;
 };
 Layout layout_of(int32_t W, int32_t H, const sm_params& p);  // p must have passed check_params
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

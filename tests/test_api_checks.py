@@ -95,3 +95,18 @@ def test_wrappers_reject_host_tensors_before_the_library():
         api.ManySolver(device="cpu")([(_img(), _img(), {})])
     with pytest.raises(ValueError, match="triangle indices"):
         api.interpolate(torch.zeros(16, dtype=torch.uint8), 2, np.array([[0, 1, 2]]), 32, 24)
+
+
+def test_set_launch_shape_checks():
+    """sm_set_launch_shape accepts the documented kinds, keys and values, clears with 0, and
+    rejects anything else with SM_ERR_ARG (host only: no GPU needed)."""
+    from paper_1511_00758_amd import _lib
+    L = _lib.load()
+    ok = [(0, 4, 8), (1, 0, 2048), (2, 128, 32), (3, 3 << 8 | 3, 8), (2, 128, 0), (3, 3 << 8 | 3, 0)]
+    for kind, key, value in ok:
+        assert L.sm_set_launch_shape(kind, 640, 480, key, value) == 0, (kind, key, value)
+    bad = [(0, 4, 3), (1, 1, 2048), (1, 0, 100), (2, 0, 32), (2, 300, 32), (2, 128, 48), (3, 0, 12), (4, 0, 8),
+           (-1, 0, 8)]
+    for kind, key, value in bad:
+        assert L.sm_set_launch_shape(kind, 640, 480, key, value) != 0, (kind, key, value)
+    assert L.sm_set_launch_shape(2, 0, 480, 128, 32) != 0  # (no such frame size)
