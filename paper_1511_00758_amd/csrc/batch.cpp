@@ -455,6 +455,10 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
   // frames whose meshes live on the device (grid supports, host_mesh = 0): the first mesh is
   // built by one launch over them right after compaction; job j's status words come back
   // in one copy
+  int64_t mesh_candidates = 0;  // star kernel layout of the batch (star_grouped)
+  for (int32_t f = 0; f < n; ++f)
+    if (P.lay[f].mesh_on) mesh_candidates += P.lay[f].n_grid;
+  const bool grouped = star_grouped(mesh_candidates);
   std::vector<uint8_t> mesh_dev(n, 0), job_start;
   std::vector<int32_t> host_upto(n, 0), nT_dev(n, 0), job_frame;
   auto add_job = [&](int32_t f, int32_t start, const int32_t* n_new) {
@@ -473,7 +477,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
     jb.T_cap = L.T_cap;
     jb.W = hF[f].W;
     jb.H = hF[f].H;
-    jb.blocks = star_blocks(L.S_cap);
+    jb.blocks = star_blocks_many(L.S_cap, grouped);
     jb.w = star_work_at(b + L.mwork, hF[f].W, hF[f].H, L.S_cap);
     job_frame.push_back(f);
     job_start.push_back((uint8_t)start);
@@ -508,7 +512,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
   SM_HIP(launch_batch_pack(dF, n, 0, s));
   if (!job_frame.empty()) {
     SM_TRY(arm(SM_ST_MESH));
-    SM_HIP(launch_star_many(djobs, dsoff, (int32_t)job_frame.size(), first_blocks, all_lds, s));
+    SM_HIP(launch_star_many(djobs, dsoff, (int32_t)job_frame.size(), first_blocks, all_lds, grouped, s));
   }
 
   std::vector<int32_t> n_S(n, 0), iters(n);
@@ -573,7 +577,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
           jb.T_cap = L.T_cap;
           jb.W = d.W;
           jb.H = d.H;
-          jb.blocks = star_blocks(L.S_cap);
+          jb.blocks = star_blocks_many(L.S_cap, grouped);
           jb.w = star_work_at(b + L.mwork, d.W, d.H, L.S_cap);
         }
         resample |= rs;
@@ -604,7 +608,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
       SM_TRY(arm(SM_ST_REMATCH));
       SM_HIP(launch_batch_rematch(dF, doff_arr(kRematch), n, o_m[n], s));
       SM_TRY(arm(SM_ST_MESH));
-      SM_HIP(launch_star_many(djobs, dsoff, n_jobs, it_blocks, all_lds, s));
+      SM_HIP(launch_star_many(djobs, dsoff, n_jobs, it_blocks, all_lds, grouped, s));
     }
     if (gb) {  // the graph of the batch, then its first run
       cap.active = false;
@@ -829,7 +833,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
     SM_HIP(launch_batch_pack(dF, n, 1, s));
     if (!job_frame.empty()) {
       SM_TRY(arm(SM_ST_MESH));
-      SM_HIP(launch_star_many(djobs, dsoff, (int32_t)job_frame.size(), mix_blocks, all_lds, s));
+      SM_HIP(launch_star_many(djobs, dsoff, (int32_t)job_frame.size(), mix_blocks, all_lds, grouped, s));
     }
     todo.clear();
     for (int32_t f = 0; f < n; ++f)

@@ -1,6 +1,8 @@
 // Device Delaunay triangulation by per-point stars (Sec. III-A; the steps and why they are
 // exact are in mesh_star.hpp): the preparation kernel builds the frame's bucket grid, the
-// star kernel runs one wavefront per support over the whole chip.
+// star kernel runs one star per wavefront (one frame: latency) or per 16-lane group (the
+// stage-batched solve: four stars per wavefront, fewer instructions per star) over the
+// whole chip.
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
@@ -358,12 +360,170 @@ struct DevWave {
   }
 };
 
+// DPP all-reduce within each row of 16 lanes (every lane of the row ends with the result):
+// adjacent pairs, quads, the mirrored half-rows, the mirrored rows.
+__device__ __forceinline__ uint32_t row_min_u32(uint32_t x) {
+  int32_t v = (int32_t)x;
+  auto mn = [](int32_t a, int32_t b) { return (uint32_t)a < (uint32_t)b ? a : b; };
+  v = mn(v, dpp<0xb1, 0xf>(-1, v));   // quad_perm [1, 0, 3, 2]
+  v = mn(v, dpp<0x4e, 0xf>(-1, v));   // quad_perm [2, 3, 0, 1]
+  v = mn(v, dpp<0x141, 0xf>(-1, v));  // row_half_mirror
+  v = mn(v, dpp<0x140, 0xf>(-1, v));  // row_mirror
+  return (uint32_t)v;
+}
+// inclusive prefix sum within each row of 16 lanes
+__device__ __forceinline__ int32_t row_scan(int32_t v) {
+  v += dpp<0x111, 0xf>(0, v);  // row_shr:1
+  v += dpp<0x112, 0xf>(0, v);  // row_shr:2
+  v += dpp<0x114, 0xf>(0, v);  // row_shr:4
+  v += dpp<0x118, 0xf>(0, v);  // row_shr:8
+  return v;
+}
+
+// A group of 16 lanes -- one DPP row -- as the group of the star steps: four stars per
+// wavefront, for throughput (the stage-batched solve). Control flow is uniform per group,
+// not per wavefront, so nothing here is made wave-uniform; values move between lanes of a
+// group by DPP within the row or by ds_bpermute.
+struct DevGroup16 {
+  static constexpr int kN = 16;
+  static constexpr int kInFlight = 2;
+  static constexpr int kCap = 128;  // candidates a group stages in LDS
+  int lane_;                        // 0..15
+  int gbase;                        // first lane of the group in the wavefront
+  int32_t* s_id;
+  int32_t* s_uv;
+  int32_t* s_mark;                  // [kN * kInFlight]
+  int32_t n_staged = -1;
+  int32_t rx0 = 0, rx1 = -1, ry0 = 0, ry1 = -1;
+
+  __device__ int lane() const { return lane_; }
+  __device__ uint32_t mask(bool b) const { return (uint32_t)((__ballot(b) >> gbase) & 0xffffu); }
+  __device__ bool any(bool b) const { return mask(b) != 0u; }
+  __device__ uint64_t min_u64(uint64_t x) const {
+    const uint32_t hi = row_min_u32((uint32_t)(x >> 32));
+    const uint32_t lo = row_min_u32((uint32_t)(x >> 32) == hi ? (uint32_t)x : 0xffffffffu);
+    return ((uint64_t)hi << 32) | lo;
+  }
+  __device__ int32_t pick(bool mine, int32_t v) const {
+    const uint32_t m = mask(mine);
+    return __shfl(v, gbase + (m ? __ffs(m) - 1 : 0));
+  }
+  // as DevWave::reduce_best, within the group
+  __device__ void reduce_best(P2 X, P2 Y, int32_t* b, P2* B, float* t) const {
+    const uint32_t kmin = row_min_u32(*b >= 0 ? float_key(*t) : 0xffffffffu);
+    if (kmin == 0xffffffffu) {
+      *b = -1;
+      return;
+    }
+    const float tmin = __uint_as_float((kmin & 0x80000000u) ? (kmin & 0x7fffffffu) : ~kmin);
+    const bool close = *b >= 0 && *t <= tmin + 0x1p-19f * fabsf(tmin);
+    const int w = gbase + __ffs(mask(close)) - 1;
+    int32_t wb = __shfl(*b, w);
+    P2 WB{__shfl(B->x, w), __shfl(B->y, w)};
+    float wt = __shfl(*t, w);
+    uint32_t near = mask(close && *b != wb);
+    while (near) {
+      const int c = gbase + __ffs(near) - 1;
+      const int32_t cb = __shfl(*b, c);
+      const P2 CB{__shfl(B->x, c), __shfl(B->y, c)};
+      const float ct = __shfl(*t, c);
+      near &= ~mask(*b == cb);
+      if (star::beats(X, Y, wb, WB, wt, cb, CB, ct)) wb = cb, WB = CB, wt = ct;
+    }
+    *b = wb;
+    *B = WB;
+    *t = wt;
+  }
+  // as DevWave::gather, 16 runs and 16 entries per round
+  template <class RowFn, class Fn2>
+  __device__ int32_t gather(const Grid& g, int32_t n, RowFn&& row, Fn2&& fn2) const {
+    int32_t all = 0;
+    for (int32_t base = 0; base < n; base += kN) {
+      const int32_t i = base + lane_;
+      int32_t e0 = 0, len = 0;
+      if (i < n) {
+        const star::CellRow c = row(i);
+        if (c.x0 <= c.x1) {
+          e0 = g.cell_start[c.cy * g.gw + c.x0];
+          len = g.cell_start[c.cy * g.gw + c.x1 + 1] - e0;
+        }
+      }
+      const int32_t inc = row_scan(len);
+      const int32_t exc = inc - len;
+      const int32_t total = __shfl(inc, gbase + kN - 1);
+      const int32_t delta = e0 - exc;
+      int32_t carry = 0;
+      for (int32_t j0 = 0; j0 < total; j0 += kN * kInFlight) {
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) s_mark[u * kN + lane_] = kNoMark16;
+        DevWave::wave_sync();
+        if (len > 0 && exc >= j0 && exc < j0 + kN * kInFlight) s_mark[exc - j0] = delta;
+        DevWave::wave_sync();
+        int32_t id[kInFlight], uv[kInFlight];
+#pragma unroll
+        for (int u = 0; u < kInFlight; ++u) {
+          id[u] = -1, uv[u] = 0;
+          if (j0 + u * kN >= total) continue;  // (uniform in the group)
+          const int32_t d = s_mark[u * kN + lane_];
+          const uint32_t has = mask(d != kNoMark16);
+          const uint32_t upto = has & (lane_ == kN - 1 ? 0xffffu : ((2u << lane_) - 1));
+          const int32_t from = __shfl(d, gbase + (upto ? 31 - __clz(upto) : 0));
+          const int32_t last = __shfl(d, gbase + (has ? 31 - __clz(has) : 0));
+          const int32_t dj = upto ? from : carry;
+          if (has) carry = last;
+          const int32_t j = j0 + u * kN + lane_;
+          if (j < total) {
+            const star::CellEntry ce = g.cell_e[j + dj];
+            id[u] = ce.id, uv[u] = ce.uv;
+          }
+        }
+#pragma unroll 1
+        for (int u = 0; u < kInFlight && j0 + u * kN < total; ++u) {
+          const int32_t j = j0 + u * kN + lane_;
+          if (j < total) fn2(all + j, id[0], uv[0]);
+#pragma unroll
+          for (int k = 0; k + 1 < kInFlight; ++k) id[k] = id[k + 1], uv[k] = uv[k + 1];
+        }
+        DevWave::wave_sync();
+      }
+      all += total;
+    }
+    return all;
+  }
+  static constexpr int32_t kNoMark16 = INT32_MIN;
+  template <class RowFn, class Fn>
+  __device__ void for_rows(const Grid& g, int32_t n, RowFn&& row, Fn&& fn) {
+    gather(g, n, row, [&](int32_t, int32_t id, int32_t uv) { fn(id, star::unpack(uv)); });
+  }
+  __device__ void set_base(const Grid& g, const Region& r) {
+    if (n_staged >= 0 && r.x0 == rx0 && r.x1 == rx1 && r.y0 == ry0 && r.y1 == ry1) return;
+    rx0 = r.x0, rx1 = r.x1, ry0 = r.y0, ry1 = r.y1;
+    int32_t* sid = s_id;
+    int32_t* suv = s_uv;
+    n_staged = gather(g, r.y1 - r.y0 + 1, star::RegionRows{r}, [&](int32_t j, int32_t id, int32_t uv) {
+      if (j < kCap) sid[j] = id, suv[j] = uv;
+    });
+    DevWave::wave_sync();
+  }
+  template <class Fn>
+  __device__ void for_candidates(const Grid& g, const Region& r, Fn&& fn) {
+    if (n_staged >= 0 && n_staged <= kCap && r.x0 == rx0 && r.x1 == rx1 && r.y0 == ry0 && r.y1 == ry1) {
+      for (int32_t j = lane_; j < n_staged; j += kN) fn(s_id[j], star::unpack(s_uv[j]));
+    } else {
+      for_rows(g, r.y1 - r.y0 + 1, star::RegionRows{r}, fn);
+    }
+  }
+};
+
 // Triangles of one star: lane k holds the k-th pending one. The workgroup reserves the
 // slots of all its stars' pending triangles at its end, with one atomic on the frame's
 // counter (every wavefront adding its own would serialise thousands of same-address
-// atomics); a star with more than 64 triangles reserves each full set of 64 on its own.
+// atomics); a star with more triangles than its group has lanes reserves each full set
+// on its own.
+template <int G>
 struct DevOut {
-  int lane;
+  int lane;   // in the group
+  int gbase;  // first lane of the group in the wavefront
   int32_t p;
   sm_tri* T;
   int32_t T_cap;
@@ -385,13 +545,14 @@ struct DevOut {
       slot = atomicAdd(counter, n);
       if (counter_copy) atomicAdd(counter_copy, n);
     }
-    write(uniform(__shfl(slot, 0)));
+    slot = __shfl(slot, gbase);
+    write(G == 64 ? uniform(slot) : slot);
     total += n;
     n = 0;
   }
   __device__ void emit(int32_t i1, int32_t i2) {
     if (lane == n) my1 = i1, my2 = i2;
-    if (++n == DevWave::kN) flush();
+    if (++n == G) flush();
   }
   // the star's count; its last n triangles wait for the workgroup's reservation
   __device__ int32_t finish() { return total + n; }
@@ -409,8 +570,8 @@ __device__ void star_wave(const StarJob& a, int32_t local_wave) {
   const int32_t err0 = status[kMeshErr];
   const int32_t p = local_wave;
   const StarWork& w = a.w;
-  DevOut out{lane, p, a.T, a.T_cap, &status[kMeshTris], a.status_copy ? &a.status_copy[kMeshTris] : nullptr,
-             &status[kMeshErr]};
+  DevOut<64> out{lane, 0, p, a.T, a.T_cap, &status[kMeshTris], a.status_copy ? &a.status_copy[kMeshTris] : nullptr,
+                 &status[kMeshErr]};
   if (err0 == 0 && p < n && n <= a.w.S_cap) {  // (every wavefront goes on to the barriers)
     const Grid g{w.uv, n, a.W, a.H, w.gw, w.gh, w.cell_start, w.cell_e, w.rows};
     DevWave wv{lane, s_id[wv_i], s_uv[wv_i], s_mark[wv_i]};
@@ -441,21 +602,86 @@ __device__ void star_wave(const StarJob& a, int32_t local_wave) {
   out.write(uniform(off));
 }
 
+// Sixteen stars per workgroup, one 16-lane group each (the stage-batched solve): the same
+// steps as star_wave, the workgroup's triangle slots reserved the same way.
+constexpr int kGroupStars = 16;
+// grouped stars pay off once the batch's stars far exceed the wavefronts the chip holds
+// at once (measured: a 640x480 frame alone is faster a star per wavefront, 64 of them
+// 18% faster a star per group; serving batches of a few frames keep a star per wavefront
+// for their latency)
+constexpr int64_t kGroupedMinCandidates = 65536;
+__device__ void star_group16(const StarJob& a, int32_t star0) {
+  __shared__ int32_t s_id[kGroupStars][DevGroup16::kCap];
+  __shared__ int32_t s_uv[kGroupStars][DevGroup16::kCap];
+  __shared__ int32_t s_mark[kGroupStars][DevGroup16::kN * DevGroup16::kInFlight];
+  __shared__ int32_t s_cnt[kGroupStars];
+  __shared__ int32_t s_base;
+  const int gi = threadIdx.x >> 4, lane = threadIdx.x & 15, gbase = (threadIdx.x & 63) & ~15;
+  int32_t* status = a.status;
+  const int32_t n = status[kMeshSupports];
+  const int32_t err0 = status[kMeshErr];
+  const int32_t p = star0 + gi;
+  const StarWork& w = a.w;
+  DevOut<16> out{lane, gbase, p, a.T, a.T_cap, &status[kMeshTris],
+                 a.status_copy ? &a.status_copy[kMeshTris] : nullptr, &status[kMeshErr]};
+  if (err0 == 0 && p < n && n <= a.w.S_cap) {  // (every group goes on to the barriers)
+    const Grid g{w.uv, n, a.W, a.H, w.gw, w.gh, w.cell_start, w.cell_e, w.rows};
+    DevGroup16 wv{lane, gbase, s_id[gi], s_uv[gi], s_mark[gi]};
+    const int32_t r = star::star_of(wv, g, p, out);
+    if (r < 0) {  // the frame goes to the host
+      out.n = 0;
+      if (lane == 0) {
+        atomicCAS(&status[kMeshErr], 0, -r);
+        if (a.status_copy) atomicCAS(&a.status_copy[kMeshErr], 0, -r);
+      }
+    }
+  }
+  if (lane == 0) s_cnt[gi] = out.n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t sum = 0;
+    for (int k = 0; k < kGroupStars; ++k) sum += s_cnt[k];
+    int32_t base = 0;
+    if (sum > 0) {
+      base = atomicAdd(out.counter, sum);
+      if (out.counter_copy) atomicAdd(out.counter_copy, sum);
+    }
+    s_base = base;
+  }
+  __syncthreads();
+  int32_t off = s_base;
+  for (int k = 0; k < gi; ++k) off += s_cnt[k];
+  out.write(off);
+}
+
 __global__ __launch_bounds__(64 * kStarWaves) void k_star(StarJob a) {
   star_wave(a, blockIdx.x * kStarWaves + uniform((int32_t)threadIdx.x >> 6));
 }
 
-__global__ __launch_bounds__(64 * kStarWaves) void k_star_many(const StarJob* __restrict__ jobs,
-                                                               const int32_t* __restrict__ offs, int32_t n_jobs) {
-  // the job of this workgroup: the last j with offs[j] <= blockIdx.x
+// the job of workgroup b: the last j with offs[j] <= b
+__device__ __forceinline__ int32_t job_of(const int32_t* __restrict__ offs, int32_t n_jobs, int32_t b) {
   int32_t lo = 0, hi = n_jobs - 1;
-  const int32_t b = blockIdx.x;
   while (lo < hi) {
     const int32_t mid = (lo + hi + 1) >> 1;
     if (offs[mid] <= b) lo = mid;
     else hi = mid - 1;
   }
-  star_wave(jobs[lo], (b - offs[lo]) * kStarWaves + uniform((int32_t)threadIdx.x >> 6));
+  return lo;
+}
+
+// a star per wavefront, as k_star (batches whose stars fit the chip at once)
+__global__ __launch_bounds__(64 * kStarWaves) void k_star_many(const StarJob* __restrict__ jobs,
+                                                               const int32_t* __restrict__ offs, int32_t n_jobs) {
+  const int32_t b = blockIdx.x, j = job_of(offs, n_jobs, b);
+  star_wave(jobs[j], (b - offs[j]) * kStarWaves + uniform((int32_t)threadIdx.x >> 6));
+}
+
+// a star per 16-lane group (larger batches; three waves per SIMD: the most that fits its
+// registers without spilling)
+__global__ __launch_bounds__(64 * kStarWaves, 3) void k_star_many16(const StarJob* __restrict__ jobs,
+                                                                 const int32_t* __restrict__ offs, int32_t n_jobs) {
+  const int32_t b = blockIdx.x, j = job_of(offs, n_jobs, b);
+  star_group16(jobs[j], (b - offs[j]) * kGroupStars);
 }
 
 constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -508,6 +734,11 @@ StarWork star_work_at(void* base, int32_t W, int32_t H, int32_t S_cap) {
 }
 
 int32_t star_blocks(int32_t S_cap) { return (S_cap + kStarWaves - 1) / kStarWaves; }
+bool star_grouped(int64_t candidates) { return candidates > kGroupedMinCandidates; }
+int32_t star_blocks_many(int32_t S_cap, bool grouped) {
+  const int32_t per = grouped ? kGroupStars : kStarWaves;
+  return (S_cap + per - 1) / per;
+}
 
 hipError_t launch_star(const StarJob& job, hipStream_t s) {
   hipEvent_t e0, e1;
@@ -528,7 +759,7 @@ hipError_t launch_star(const StarJob& job, hipStream_t s) {
 }
 
 hipError_t launch_star_many(const StarJob* jobs, const int32_t* offs, int32_t n, int32_t total_blocks,
-                            bool lds, hipStream_t s) {
+                            bool lds, bool grouped, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipEvent_t e0, e1;
   const bool timed = take_launch_events(&e0, &e1);
@@ -539,11 +770,12 @@ hipError_t launch_star_many(const StarJob* jobs, const int32_t* offs, int32_t n,
     hipLaunchKernelGGL(lds ? k_star_prep_many<true> : k_star_prep_many<false>, dim3((unsigned)n), dim3(kPrepThreads),
                        0, s, jobs);
   if (total_blocks > 0) {
+    auto kernel = grouped ? k_star_many16 : k_star_many;
     if (timed)
-      hipExtLaunchKernelGGL(k_star_many, dim3((unsigned)total_blocks), dim3(64 * kStarWaves), 0, s, nullptr, e1, 0u,
+      hipExtLaunchKernelGGL(kernel, dim3((unsigned)total_blocks), dim3(64 * kStarWaves), 0, s, nullptr, e1, 0u,
                             jobs, offs, n);
     else
-      hipLaunchKernelGGL(k_star_many, dim3((unsigned)total_blocks), dim3(64 * kStarWaves), 0, s, jobs, offs, n);
+      hipLaunchKernelGGL(kernel, dim3((unsigned)total_blocks), dim3(64 * kStarWaves), 0, s, jobs, offs, n);
   }
   return hipGetLastError();
 }

@@ -5,9 +5,10 @@
 // Each tessellation of a frame is two launches: a preparation kernel (one 1024-thread
 // workgroup per frame: the new supports' compaction, packed coordinates, a bucket grid of
 // 16 x 16 px cells, the smallest and largest u of every pixel row, the frame's status
-// words) and the star kernel (one wavefront per support, over as many workgroups as the
-// frame has supports: each writes the triangles of its star in which it is the first
-// vertex). Nothing is kept from one tessellation to the next besides the supports.
+// words) and the star kernel (one wavefront per support for one frame, one 16-lane group
+// per support for the batched launch; each writes the triangles of its star in which it
+// is the first vertex). Nothing is kept from one tessellation to the next besides the
+// supports.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -64,19 +65,24 @@ struct StarJob {
   sm_tri* T;
   int32_t T_cap;
   int32_t W, H;
-  int32_t blocks;           // star-kernel workgroups of this frame (4 supports each)
+  int32_t blocks;           // star-kernel workgroups of this frame (star_blocks / star_blocks_many)
   StarWork w;
 };
 
-// Star-kernel workgroups for a frame of at most S_cap supports.
+// Star-kernel workgroups for a frame of at most S_cap supports: of launch_star (four stars
+// per workgroup, a wavefront each) and of launch_star_many (the same, or sixteen stars, a
+// 16-lane group each, when `grouped`); whether a batch whose frames start from
+// `candidates` support candidates in total takes the grouped kernel.
 int32_t star_blocks(int32_t S_cap);
+int32_t star_blocks_many(int32_t S_cap, bool grouped);
+bool star_grouped(int64_t candidates);
 
 hipError_t launch_star(const StarJob& job, hipStream_t s);
 // the jobs of a device array: preparation, one workgroup per job, then the star kernel over
 // every job's supports; offs [n + 1] holds the prefix sums of the jobs' `blocks`; lds: every
 // job's frame passes prep_in_lds
 hipError_t launch_star_many(const StarJob* jobs, const int32_t* offs, int32_t n, int32_t total_blocks, bool lds,
-                            hipStream_t s);
+                            bool grouped, hipStream_t s);
 // whether the preparation of a W x H frame keeps its counts in LDS
 bool prep_in_lds(int32_t W, int32_t H);
 

@@ -140,3 +140,21 @@ def test_many_device_mesh_equals_host_mesh(mixed):
     assert dev_st["mesh_device"] == expect and dev_st["mesh_fallback"] == 0
     assert runs["host"][1]["mesh_device"] == 0
     assert dev_st["stage_launches"]["mesh"] == 3
+
+
+def test_many_large_batch_grouped_stars_equal_solo():
+    """A batch of 24 frames of the 640x480 workload: enough support candidates (about 74k)
+    that the batched star kernel takes one star per 16-lane group; every frame bit-equal to
+    its solo solve (one star per wavefront)."""
+    from paper_1511_00758_amd import api
+    scs = [scenes.make_scene(2, scenes.seed_of(2, 60 + f)) for f in range(4)]
+    frames = [(_dev(scs[i % 4].left), _dev(scs[i % 4].right), scs[i % 4].params) for i in range(24)]
+    solo = [_solo(sc.left, sc.right, sc.params) for sc in scs]
+    _note("many grouped", len(frames))
+    outs = api.ManySolver(8, device=DEV)(frames)
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        got = tuple(t.cpu().numpy() for t in o)
+        exp = solo[i % 4]
+        assert (got[0].view(np.uint32) == exp[0].view(np.uint32)).all(), i
+        assert (got[1] == exp[1]).all() and (got[2] == exp[2]).all(), i
