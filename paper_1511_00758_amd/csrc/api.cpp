@@ -328,7 +328,7 @@ sm_status enqueue_device_meshes(const sm_params& p, int32_t W, int32_t H, const 
     if (last) break;
     const int32_t cells = cells_of(W, H, sz);
     SM_TRY(tm.begin(SM_ST_REMATCH));
-    SM_HIP(launch_resample(b.cL, b.cR, b.cell_g, b.cell_b, b.D_it, W, H, sz, p, b.S, s, counts + kMeshSupports,
+    SM_HIP(launch_resample(b.cL, b.cR, b.cell_g, b.cell_b, b.D_it, W, H, sz, p, b.S, b.occ, s, counts + kMeshSupports,
                            Lo.S_cap));
     SM_TRY(tm.end());
     SM_TRY(tm.begin(SM_ST_MESH));  // S_it+1 = S_it and the resampled supports
@@ -541,7 +541,7 @@ sm_status sm_resample(const uint64_t* cL, const uint64_t* cR, const float* D_it,
   if (cap < 2 * cells) return fail(SM_ERR_CAPACITY, "cap %d < 2 * %d cells", cap, cells);
   hipStream_t s = (hipStream_t)stream;
   SM_HIP(launch_mark(S, n_S, occ, W, H, s));
-  SM_HIP(launch_resample(cL, cR, cell_g, cell_b, D_it, W, H, sz_occ, *p, out, s));
+  SM_HIP(launch_resample(cL, cR, cell_g, cell_b, D_it, W, H, sz_occ, *p, out, occ, s));
   SM_HIP(launch_compact(out, 2 * cells, n_out, occ, W, nullptr, s));
   return SM_OK;
 }
@@ -696,7 +696,7 @@ sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int
     if (n_S + 2 * cells + 1 > Lo.S_cap) return fail(SM_ERR_INTERNAL, "support capacity exceeded");
     sm_support* region = Sd + n_S;
     SM_TRY(tm.begin(SM_ST_REMATCH));
-    SM_HIP(launch_resample(cL, cR, cell_g, cell_b, D_it, W, H, sz, *p, region, s));
+    SM_HIP(launch_resample(cL, cR, cell_g, cell_b, D_it, W, H, sz, *p, region, occ, s));
     SM_TRY(tm.end());
     SM_TRY(tm.begin(SM_ST_COMPACT));
     SM_HIP(launch_compact(region, 2 * cells, &counters[1], occ, W, (int32_t*)(region + 2 * cells), s));

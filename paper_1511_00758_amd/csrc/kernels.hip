@@ -540,14 +540,18 @@ __global__ __launch_bounds__(256) void k_match(MatchArgs a) {
 }
 
 // Resampling (Alg. 4) fused with the re-match: one wave per cell. Slot c receives the
-// confident support of cell c, slot n_cells + c its re-matched invalid pixel.
+// confident support of cell c, slot n_cells + c its re-matched invalid pixel; a pixel that
+// occ (non-null: the occupancy of the current supports) marks is already a support, so its
+// slot stays empty (and is not matched).
 __device__ __forceinline__ void rematch_cell(const MatchArgs& a, const uint64_t* cell_g, const uint64_t* cell_b,
-                                             const float* D_it, int n_cells, uint64_t ginit, uint64_t binit,
-                                             int c, int lane) {
+                                             const float* D_it, const uint8_t* occ, int n_cells, uint64_t ginit,
+                                             uint64_t binit, int c, int lane) {
   const uint64_t g = cell_g[c], b = cell_b[c];
+  const bool g_new = g != ginit && !(occ && occ[(uint32_t)g]);
+  const bool b_new = b != binit && !(occ && occ[(uint32_t)b]);
   if (lane == 0) {
     sm_support sg;
-    if (g != ginit) {
+    if (g_new) {
       const uint32_t idx = (uint32_t)g;
       sg.u = (int16_t)(idx % (uint32_t)a.W);
       sg.v = (int16_t)(idx / (uint32_t)a.W);
@@ -561,7 +565,7 @@ __device__ __forceinline__ void rematch_cell(const MatchArgs& a, const uint64_t*
   sm_support sb;
   sb.u = sb.v = 0;
   sb.d = kRejected;
-  if (b != binit) {
+  if (b_new) {
     const uint32_t idx = (uint32_t)b;
     const int u = (int)(idx % (uint32_t)a.W), v = (int)(idx / (uint32_t)a.W);
     sb.u = (int16_t)u;
@@ -574,8 +578,8 @@ __device__ __forceinline__ void rematch_cell(const MatchArgs& a, const uint64_t*
 
 __global__ __launch_bounds__(256) void k_rematch_cells(MatchArgs a, const uint64_t* cell_g,
                                                        const uint64_t* cell_b, const float* D_it,
-                                                       int n_cells, uint64_t ginit, uint64_t binit,
-                                                       const int32_t* slot_off, int slot_cap) {
+                                                       const uint8_t* occ, int n_cells, uint64_t ginit,
+                                                       uint64_t binit, const int32_t* slot_off, int slot_cap) {
   const int lane = threadIdx.x & (kWave - 1);
   const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= n_cells) return;
@@ -584,7 +588,7 @@ __global__ __launch_bounds__(256) void k_rematch_cells(MatchArgs a, const uint64
     if (off < 0 || (int64_t)off + 2 * n_cells + 1 > slot_cap) return;  // a failed mesh: nothing to add
     a.slots += off;
   }
-  rematch_cell(a, cell_g, cell_b, D_it, n_cells, ginit, binit, c, lane);
+  rematch_cell(a, cell_g, cell_b, D_it, occ, n_cells, ginit, binit, c, lane);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1260,12 +1264,12 @@ hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t
 
 hipError_t launch_resample(const uint64_t* cL, const uint64_t* cR, const uint64_t* cell_g,
                            const uint64_t* cell_b, const float* D_it, int32_t W, int32_t H, int32_t sz,
-                           const sm_params& p, sm_support* slots, hipStream_t s, const int32_t* slot_off,
-                           int32_t slot_cap) {
+                           const sm_params& p, sm_support* slots, const uint8_t* occ, hipStream_t s,
+                           const int32_t* slot_off, int32_t slot_cap) {
   const int n_cells = ((W + sz - 1) / sz) * ((H + sz - 1) / sz);
   const uint64_t ginit = (uint64_t)p.t_lo << 32, binit = (uint64_t)(255 - p.t_hi) << 32;
   const MatchArgs a = match_args(cL, cR, W, H, p, slots, 2 * n_cells);
-  SM_LAUNCH(k_rematch_cells, dim3(blocks_for(n_cells, 4)), dim3(256), 0, s, a, cell_g, cell_b, D_it,
+  SM_LAUNCH(k_rematch_cells, dim3(blocks_for(n_cells, 4)), dim3(256), 0, s, a, cell_g, cell_b, D_it, occ,
             n_cells, ginit, binit, slot_off, (int)slot_cap);
   return hipGetLastError();
 }
@@ -1397,7 +1401,7 @@ __global__ __launch_bounds__(256) void k_batch_rematch(const BatchFrame* F, cons
     region = fr.S + o;
   }
   const MatchArgs a = match_args(fr.cL, fr.cR, fr.W, fr.H, fr.p, region, fr.region_n);
-  rematch_cell(a, fr.cell_g, fr.cell_b, fr.D_it, n_cells, (uint64_t)fr.p.t_lo << 32,
+  rematch_cell(a, fr.cell_g, fr.cell_b, fr.D_it, fr.occ, n_cells, (uint64_t)fr.p.t_lo << 32,
                (uint64_t)(255 - fr.p.t_hi) << 32, unit - off[f], lane);
 }
 

@@ -133,12 +133,13 @@ hipError_t launch_validate(const uint64_t* cL, const uint64_t* cR, const uint8_t
                            hipStream_t s);
 
 // Resampling fused with the re-match: confident supports of the cells at
-// slots[0, cells), re-matched invalid pixels at slots[cells, 2 cells); with slot_off
-// non-null the slots start *slot_off entries after `slots` (nothing happens unless the
-// 2 cells + 1 slots lie below slot_cap).
+// slots[0, cells), re-matched invalid pixels at slots[cells, 2 cells); pixels that occ
+// (nullable: the occupancy of the current supports) marks leave their slot empty; with
+// slot_off non-null the slots start *slot_off entries after `slots` (nothing happens unless
+// the 2 cells + 1 slots lie below slot_cap).
 hipError_t launch_resample(const uint64_t* cL, const uint64_t* cR, const uint64_t* cell_g,
                            const uint64_t* cell_b, const float* D_it, int32_t W, int32_t H, int32_t sz,
-                           const sm_params& p, sm_support* slots, hipStream_t s,
+                           const sm_params& p, sm_support* slots, const uint8_t* occ, hipStream_t s,
                            const int32_t* slot_off = nullptr, int32_t slot_cap = 0);
 
 // ---------------------------------------------------------------------------------

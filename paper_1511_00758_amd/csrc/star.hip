@@ -6,7 +6,6 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
-#include "compact.hpp"
 #include "kernels.hpp"
 #include "mesh_star.hpp"
 #include "star.hpp"
@@ -31,149 +30,6 @@ __device__ __forceinline__ int32_t pack_uv(int32_t u, int32_t v) { return u | (v
 __device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t uniform64(uint64_t v) {
   return ((uint64_t)(uint32_t)uniform((int32_t)(v >> 32)) << 32) | (uint32_t)uniform((int32_t)v);
-}
-
-// Writes the status words 0..7 and log entry k to the status and its copy (thread 0).
-__device__ void put_status(const StarJob& a, const int32_t (&w)[8], int k, int32_t log_s, int32_t log_t) {
-  for (int i = 0; i < 8; ++i) {
-    a.status[i] = w[i];
-    if (a.status_copy) a.status_copy[i] = w[i];
-  }
-  if (k >= 0 && k < 8) {
-    a.status[kMeshLog + 2 * k] = log_s;
-    a.status[kMeshLog + 2 * k + 1] = log_t;
-    if (a.status_copy) {
-      a.status_copy[kMeshLog + 2 * k] = log_s;
-      a.status_copy[kMeshLog + 2 * k + 1] = log_t;
-    }
-  }
-}
-
-// Exclusive prefix sum of cnt[0, n) into out[0, n] by one 1024-thread workgroup.
-__device__ void block_scan(const int32_t* cnt, int32_t* out, int32_t n) {
-  __shared__ int32_t wsum[kPrepThreads / 64];
-  __shared__ int32_t carry;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid == 0) carry = 0;
-  __syncthreads();
-  for (int32_t base = 0; base < n; base += kPrepThreads) {
-    const int32_t i = base + tid;
-    const int32_t v = i < n ? cnt[i] : 0;
-    int32_t inc = v;
-    for (int d = 1; d < 64; d <<= 1) {
-      const int32_t x = __shfl_up(inc, d);
-      if (lane >= d) inc += x;
-    }
-    if (lane == 63) wsum[w] = inc;
-    __syncthreads();
-    int32_t before = carry;
-    for (int k = 0; k < w; ++k) before += wsum[k];
-    if (i < n) out[i] = before + inc - v;
-    __syncthreads();
-    if (tid == kPrepThreads - 1) carry = before + inc;
-    __syncthreads();
-  }
-  if (tid == 0) out[n] = carry;
-}
-
-// One workgroup per frame: the new supports' compaction, then the frame's bucket grid and
-// row extents over all its supports, and its status words for the star kernel. The cell
-// counts and row extents are gathered with LDS atomics when they fit (kLds), else in the
-// frame's global arrays.
-constexpr int32_t kLdsCells = 12288;  // cells (48 KiB)
-constexpr int32_t kLdsRows = 4096;    // pixel rows (2 x 16 KiB)
-
-template <bool kLds>
-__device__ void star_prep(const StarJob& a) {
-  const int tid = threadIdx.x;
-  const StarWork& w = a.w;
-  __shared__ int32_t s_p0, s_err, s_tess, s_n;
-  __shared__ int32_t s_cnt[kLds ? kLdsCells : 1];
-  __shared__ int32_t s_rmin[kLds ? kLdsRows : 1], s_rmax[kLds ? kLdsRows : 1];
-  if (tid == 0) {
-    s_p0 = a.first ? 0 : a.status[kMeshSupports];
-    s_err = a.first ? 0 : a.status[kMeshErr];
-    s_tess = a.first ? 0 : a.status[kMeshTess];
-    if (s_err == 0 && (s_p0 < 0 || s_p0 > w.S_cap || (int64_t)s_p0 + a.compact_n + 1 > w.S_cap))
-      s_err = star::kStarErrCapacity;
-  }
-  __syncthreads();
-  const int32_t p0 = s_p0;
-  if (s_err == 0 && a.compact_n > 0) {  // (a frame whose earlier tessellation failed is redone on the host)
-    compact_block(a.S + p0, a.compact_n, a.compact_count, a.occ, a.W, (int*)(a.S + p0 + a.compact_n));
-    __syncthreads();
-  }
-  if (tid == 0) {
-    int32_t n_new = 0;
-    // (no slots to compact and no device count: no new supports, e.g. a frame too small for
-    // any grid candidate)
-    if (s_err == 0) n_new = a.compact_n > 0 ? *a.compact_count : (a.n_new ? *a.n_new : 0);
-    if (s_err == 0 && (n_new < 0 || (int64_t)p0 + n_new > w.S_cap)) s_err = star::kStarErrCapacity, n_new = 0;
-    s_n = p0 + n_new;
-  }
-  __syncthreads();
-  const int32_t n = s_n;
-  const int32_t n_cells = w.gw * w.gh;
-  int32_t* cnt = kLds ? s_cnt : w.cell_cur;
-  int32_t* rmin = kLds ? s_rmin : w.row_min;
-  int32_t* rmax = kLds ? s_rmax : w.row_max;
-  if (s_err == 0) {
-    for (int32_t c = tid; c < n_cells; c += kPrepThreads) cnt[c] = 0;
-    for (int32_t v = tid; v < a.H; v += kPrepThreads) rmin[v] = kNoRow, rmax[v] = -1;
-    __syncthreads();
-    bool bad = false;
-    for (int32_t i = tid; i < n; i += kPrepThreads) {
-      const sm_support q = a.S[i];
-      if (q.u < 0 || q.v < 0 || q.u >= a.W || q.v >= a.H) {
-        bad = true;
-        continue;
-      }
-      w.uv[i] = pack_uv(q.u, q.v);
-      atomicAdd(&cnt[(q.v / star::kStarCell) * w.gw + q.u / star::kStarCell], 1);
-      atomicMin(&rmin[q.v], (int32_t)q.u);
-      atomicMax(&rmax[q.v], (int32_t)q.u);
-    }
-    if (bad) atomicCAS(&s_err, 0, star::kStarErrSupport);
-    __syncthreads();
-  }
-  if (s_err == 0) {  // (uniform: every thread reads s_err after the barrier)
-    block_scan(cnt, w.cell_start, n_cells);
-    __syncthreads();
-    for (int32_t c = tid; c < n_cells; c += kPrepThreads) cnt[c] = w.cell_start[c];  // fill cursors
-    for (int32_t v = tid; v < a.H; v += kPrepThreads) w.rows[v].lo = rmin[v], w.rows[v].hi = rmax[v];
-    __syncthreads();
-    for (int32_t i = tid; i < n; i += kPrepThreads) {  // the same i as in the counting loop
-      const int32_t q = w.uv[i];
-      const int32_t qu = q & 0xffff, qv = q >> 16;
-      const int32_t c = (qv / star::kStarCell) * w.gw + qu / star::kStarCell;
-      const int32_t e = atomicAdd(&cnt[c], 1);
-      w.cell_e[e] = star::CellEntry{i, q};
-      // the ids of the row's extreme points (one support per pixel: one writer each)
-      if (qu == rmin[qv]) w.rows[qv].lo_id = i;
-      if (qu == rmax[qv]) w.rows[qv].hi_id = i;
-    }
-  }
-  __syncthreads();
-  if (tid == 0) {
-    // the previous tessellation's triangle count is final now (kernel order): into its log
-    if (!a.first && s_tess >= 1 && s_tess <= 8) {
-      const int32_t prev = a.status[kMeshTris];
-      a.status[kMeshLog + 2 * (s_tess - 1) + 1] = prev;
-      if (a.status_copy) a.status_copy[kMeshLog + 2 * (s_tess - 1) + 1] = prev;
-    }
-    const int32_t words[8] = {0, 0, s_err, 0, n - p0, n, s_tess + 1, 0};
-    put_status(a, words, s_tess, n, 0);
-  }
-}
-
-template <bool kLds>
-__global__ __launch_bounds__(kPrepThreads) void k_star_prep(StarJob a) {
-  star_prep<kLds>(a);
-}
-
-template <bool kLds>
-__global__ __launch_bounds__(kPrepThreads) void k_star_prep_many(const StarJob* __restrict__ jobs) {
-  star_prep<kLds>(jobs[blockIdx.x]);
 }
 
 // Wavefront-wide scans and reductions on DPP: shifts by 1, 2, 4 and 8 lanes within each
@@ -210,6 +66,288 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
 __device__ __forceinline__ uint32_t float_key(float f) {
   const uint32_t b = __float_as_uint(f);
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// Writes the status words 0..7 and log entry k to the status and its copy (thread 0).
+__device__ void put_status(const StarJob& a, const int32_t (&w)[8], int k, int32_t log_s, int32_t log_t) {
+  for (int i = 0; i < 8; ++i) {
+    a.status[i] = w[i];
+    if (a.status_copy) a.status_copy[i] = w[i];
+  }
+  if (k >= 0 && k < 8) {
+    a.status[kMeshLog + 2 * k] = log_s;
+    a.status[kMeshLog + 2 * k + 1] = log_t;
+    if (a.status_copy) {
+      a.status_copy[kMeshLog + 2 * k] = log_s;
+      a.status_copy[kMeshLog + 2 * k + 1] = log_t;
+    }
+  }
+}
+
+// The preparation's loops give thread t the items base + j * kPrepThreads + t, j < kPrepPer,
+// of each pass, and issue every load of a pass before the first is used: one memory latency
+// per pass instead of one per kPrepThreads items.
+constexpr int kPrepPer = 16;
+constexpr int32_t kPrepPass = kPrepPer * kPrepThreads;
+constexpr int kPrepWaves = kPrepThreads / 64;
+
+// Exclusive prefix sum of cnt[0, n) (LDS or global) into out[0, n] and into cnt itself (the
+// fill cursors) by one 1024-thread workgroup: thread t sums its run of consecutive counts,
+// a DPP scan and the wave totals place the runs.
+__device__ void block_scan(int32_t* cnt, int32_t* out, int32_t n) {
+  __shared__ int32_t wsum[kPrepWaves];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int32_t per = (n + kPrepThreads - 1) / kPrepThreads, c0 = tid * per, c1 = min(c0 + per, n);
+  int32_t sum = 0;
+  for (int32_t c = c0; c < c1; ++c) sum += cnt[c];
+  const int32_t inc = wave_scan(sum);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int32_t run = inc - sum;
+  for (int k = 0; k < w; ++k) run += wsum[k];
+  for (int32_t c = c0; c < c1; ++c) {
+    const int32_t v = cnt[c];
+    out[c] = run;
+    cnt[c] = run;
+    run += v;
+  }
+  if (tid == kPrepThreads - 1) out[n] = run;
+}
+
+// The preparation's per-support steps. A support's (u, v) is the first word of its record,
+// u in the low half; a support inside the frame has it equal to its packed coordinates.
+__device__ __forceinline__ int32_t support_word(const sm_support* S, int32_t i) {
+  return reinterpret_cast<const int32_t*>(S)[2 * i];
+}
+__device__ __forceinline__ bool word_inside(int32_t q, int32_t W, int32_t H) {
+  const int32_t u = (int16_t)(q & 0xffff), v = q >> 16;
+  return u >= 0 && v >= 0 && u < W && v < H;
+}
+// Row extremes of the lanes' supports (q >= 0: packed coordinates) by LDS atomics: the lanes
+// on the first such lane's row (most of them, for supports in raster order) are reduced over
+// the wavefront first and take one atomic each way. All 64 lanes must be active.
+__device__ __forceinline__ void row_extremes(int32_t q, int32_t* rmin, int32_t* rmax) {
+  const bool ok = q >= 0;
+  const uint64_t vm = __ballot(ok);
+  if (!vm) return;
+  const int32_t qv = q >> 16, qu = q & 0xffff;
+  const int32_t rv = __builtin_amdgcn_readlane(qv, __ffsll((long long)vm) - 1);
+  const bool same = ok && qv == rv;
+  const uint32_t lo = wave_min_u32(same ? (uint32_t)qu : 0xffffffffu);
+  const uint32_t hi = ~wave_min_u32(same ? ~(uint32_t)qu : 0xffffffffu);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&rmin[rv], (int32_t)lo);
+    atomicMax(&rmax[rv], (int32_t)hi);
+  }
+  if (ok && !same) {
+    atomicMin(&rmin[qv], qu);
+    atomicMax(&rmax[qv], qu);
+  }
+}
+__device__ __forceinline__ void count_cell(const StarWork& w, int32_t q, int32_t* cnt) {
+  atomicAdd(&cnt[((q >> 16) / star::kStarCell) * w.gw + (q & 0xffff) / star::kStarCell], 1);
+}
+
+// Order-preserving compaction of the slots S[p0, p0 + compact_n) in place, as compact_block
+// (slots that hold a match move to the front in order), a pass of kPrepPass slots at a time
+// with all their loads in flight together; each kept support is then counted into the
+// bucket grid and the row extremes, its packed coordinates written and its pixel marked in
+// occ. A slot's place is the count of kept slots before it: earlier passes, then, in its
+// pass, earlier rounds j, earlier wavefronts of round j and earlier lanes. Slots whose pixel
+// is already a support were emptied by their producer (the re-match reads the occupancy).
+// Returns the count (every thread); `bad` is set for a support outside the frame.
+__device__ int32_t prep_compact(const StarJob& a, int32_t p0, int32_t* cnt, int32_t* rmin, int32_t* rmax,
+                                bool& bad) {
+  __shared__ int32_t s_off[kPrepPer * kPrepWaves];  // kept per (round, wavefront), then their offsets
+  __shared__ int32_t s_total;
+  sm_support* slots = a.S + p0;
+  const int32_t n = a.compact_n;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+  int32_t base = 0;
+  for (int32_t start = 0; start < n; start += kPrepPass) {
+    sm_support s[kPrepPer];
+#pragma unroll
+    for (int j = 0; j < kPrepPer; ++j) {
+      const int32_t i = start + j * kPrepThreads + tid;
+      s[j] = i < n ? slots[i] : sm_support{0, 0, kRejected};
+    }
+    uint32_t keep = 0;
+#pragma unroll
+    for (int j = 0; j < kPrepPer; ++j) {
+      const bool k = s[j].d != kPending && s[j].d != kRejected;
+      keep |= (uint32_t)k << j;
+      const uint64_t m = __ballot(k);
+      if (lane == 0) s_off[j * kPrepWaves + w] = __popcll(m);
+    }
+    __syncthreads();
+    if (w == 0) {  // exclusive prefix of the (round, wavefront) counts in that order
+      constexpr int kPer = kPrepPer * kPrepWaves / 64;
+      int32_t v[kPer], sum = 0;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) v[k] = s_off[lane * kPer + k], sum += v[k];
+      const int32_t inc = wave_scan(sum);
+      int32_t run = inc - sum;
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) s_off[lane * kPer + k] = run, run += v[k];
+      if (lane == 63) s_total = inc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPrepPer; ++j) {
+      const bool k = (keep >> j) & 1u;
+      const uint64_t m = __ballot(k);
+      int32_t q = -1;
+      if (k) {
+        const int32_t pos = base + s_off[j * kPrepWaves + w] + __popcll(m & below);
+        slots[pos] = s[j];
+        const int32_t word = (int32_t)(uint16_t)s[j].u | ((int32_t)s[j].v << 16);
+        if (word_inside(word, a.W, a.H)) {
+          q = word;
+          a.w.uv[p0 + pos] = q;
+          if (a.occ) a.occ[(size_t)s[j].v * a.W + s[j].u] = 1;
+          count_cell(a.w, q, cnt);
+        } else {
+          bad = true;
+        }
+      }
+      row_extremes(q, rmin, rmax);
+    }
+    base += s_total;
+    __syncthreads();  // (s_off and s_total are rewritten by the next pass)
+  }
+  return base;
+}
+
+// One workgroup per frame: the new supports' compaction, then the frame's bucket grid and
+// row extents over all its supports, and its status words for the star kernel. The cell
+// counts and row extents are gathered with LDS atomics when they fit (kLds), else in the
+// frame's global arrays. The loads of the supports before the new ones are issued first and
+// are in flight during the compaction.
+constexpr int32_t kLdsCells = 12288;  // cells (48 KiB)
+constexpr int32_t kLdsRows = 4096;    // pixel rows (2 x 16 KiB)
+
+template <bool kLds>
+__device__ void star_prep(const StarJob& a) {
+  const int tid = threadIdx.x;
+  const StarWork& w = a.w;
+  __shared__ int32_t s_p0, s_err, s_tess, s_n;
+  __shared__ int32_t s_cnt[kLds ? kLdsCells : 1];
+  __shared__ int32_t s_rmin[kLds ? kLdsRows : 1], s_rmax[kLds ? kLdsRows : 1];
+  if (tid == 0) {
+    s_p0 = a.first ? 0 : a.status[kMeshSupports];
+    s_err = a.first ? 0 : a.status[kMeshErr];
+    s_tess = a.first ? 0 : a.status[kMeshTess];
+    if (s_err == 0 && (s_p0 < 0 || s_p0 > w.S_cap || (int64_t)s_p0 + a.compact_n + 1 > w.S_cap))
+      s_err = star::kStarErrCapacity;
+    // without slots to compact the new supports are in place already, counted on the device
+    // (no count: none, e.g. a frame too small for any grid candidate)
+    int32_t n_new = 0;
+    if (s_err == 0 && a.compact_n == 0) {
+      n_new = a.n_new ? *a.n_new : 0;
+      if (n_new < 0 || (int64_t)s_p0 + n_new > w.S_cap) s_err = star::kStarErrCapacity, n_new = 0;
+    }
+    s_n = s_p0 + n_new;  // (with slots: completed after the compaction)
+  }
+  __syncthreads();
+  // (a frame whose earlier tessellation failed is redone on the host: uniform from here)
+  if (s_err == 0) {
+    const int32_t p0 = s_p0;
+    const int32_t n_cells = w.gw * w.gh;
+    int32_t* cnt = kLds ? s_cnt : w.cell_cur;
+    int32_t* rmin = kLds ? s_rmin : w.row_min;
+    int32_t* rmax = kLds ? s_rmax : w.row_max;
+    const int32_t n_read = a.compact_n > 0 ? p0 : s_n;  // the supports the counting loop reads
+    int32_t q[kPrepPer];
+#pragma unroll
+    for (int j = 0; j < kPrepPer; ++j) {  // its first pass, in flight from here
+      const int32_t i = j * kPrepThreads + tid;
+      q[j] = i < n_read ? support_word(a.S, i) : 0;
+    }
+    for (int32_t c = tid; c < n_cells; c += kPrepThreads) cnt[c] = 0;
+    for (int32_t v = tid; v < a.H; v += kPrepThreads) rmin[v] = kNoRow, rmax[v] = -1;
+    __syncthreads();
+    bool bad = false;
+    if (a.compact_n > 0) {
+      const int32_t kept = prep_compact(a, p0, cnt, rmin, rmax, bad);
+      if (tid == 0) {
+        *a.compact_count = kept;
+        *(int32_t*)(a.S + p0 + a.compact_n) = kept;
+        s_n = p0 + kept;
+      }
+    }
+    for (int32_t start = 0; start < n_read; start += kPrepPass) {
+      if (start > 0) {
+#pragma unroll
+        for (int j = 0; j < kPrepPer; ++j) {
+          const int32_t i = start + j * kPrepThreads + tid;
+          q[j] = i < n_read ? support_word(a.S, i) : 0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kPrepPer; ++j) {
+        const int32_t i = start + j * kPrepThreads + tid;
+        int32_t qj = -1;
+        if (i < n_read) {
+          if (word_inside(q[j], a.W, a.H)) {
+            qj = q[j];
+            w.uv[i] = qj;
+            count_cell(w, qj, cnt);
+          } else {
+            bad = true;
+          }
+        }
+        row_extremes(qj, rmin, rmax);
+      }
+    }
+    if (bad) atomicCAS(&s_err, 0, star::kStarErrSupport);
+    __syncthreads();
+    const int32_t n = s_n;
+    if (s_err == 0) {  // (uniform: every thread reads s_err after the barrier)
+      block_scan(cnt, w.cell_start, n_cells);
+      for (int32_t v = tid; v < a.H; v += kPrepThreads) w.rows[v].lo = rmin[v], w.rows[v].hi = rmax[v];
+      __syncthreads();
+      for (int32_t start = 0; start < n; start += kPrepPass) {
+#pragma unroll
+        for (int j = 0; j < kPrepPer; ++j) {
+          const int32_t i = start + j * kPrepThreads + tid;
+          q[j] = i < n ? w.uv[i] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < kPrepPer; ++j) {
+          const int32_t i = start + j * kPrepThreads + tid;
+          if (q[j] < 0) continue;
+          const int32_t qu = q[j] & 0xffff, qv = q[j] >> 16;
+          const int32_t e = atomicAdd(&cnt[(qv / star::kStarCell) * w.gw + qu / star::kStarCell], 1);
+          w.cell_e[e] = star::CellEntry{i, q[j]};
+          // the ids of the row's extreme points (one support per pixel: one writer each)
+          if (qu == rmin[qv]) w.rows[qv].lo_id = i;
+          if (qu == rmax[qv]) w.rows[qv].hi_id = i;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    // the previous tessellation's triangle count is final now (kernel order): into its log
+    if (!a.first && s_tess >= 1 && s_tess <= 8) {
+      const int32_t prev = a.status[kMeshTris];
+      a.status[kMeshLog + 2 * (s_tess - 1) + 1] = prev;
+      if (a.status_copy) a.status_copy[kMeshLog + 2 * (s_tess - 1) + 1] = prev;
+    }
+    const int32_t words[8] = {0, 0, s_err, 0, s_n - s_p0, s_n, s_tess + 1, 0};
+    put_status(a, words, s_tess, s_n, 0);
+  }
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(kPrepThreads) void k_star_prep(StarJob a) {
+  star_prep<kLds>(a);
+}
+
+template <bool kLds>
+__global__ __launch_bounds__(kPrepThreads) void k_star_prep_many(const StarJob* __restrict__ jobs) {
+  star_prep<kLds>(jobs[blockIdx.x]);
 }
 
 // A wavefront as the group of the star steps; the candidates of the current region are
