@@ -437,21 +437,25 @@ struct LeftRing {
 // a cap whose box covers no more cells than the square t of twice s's reach (or than
 // kBandCells) is checked by its bands outside s (verify_left); a larger one (a poor
 // candidate) first takes the best of t's ring around s, which can only shrink it, and the
-// check repeats with t as s.
+// check repeats with t as s. *far is set when the answer needed points outside r (a row
+// extreme, or cells around r).
 constexpr int64_t kBandCells = 512;
 template <class WV>
 __host__ __device__ inline int32_t next_vertex(WV& wv, const Grid& g, const Region& r, P2 P, int32_t ix, P2 X,
-                                               int32_t iy, P2 Y, P2* out) {
+                                               int32_t iy, P2 Y, P2* out, bool* far) {
+  *far = false;
   int32_t b = best_left(wv, g, r, ix, X, iy, Y, out);
   if (b < 0) {
     if (r.full) return -1;
     b = best_extreme(wv, g, ix, X, iy, Y, out);
     if (b < 0) return -1;  // nothing left of the edge: a hull edge
+    *far = true;
   }
   if (disk_inside_f(X, Y, *out, g, r)) return b;  // the common case, in single precision
   for (Region s = r;;) {
     const Cap c = cap_of(X, Y, *out);
     if (cap_inside(c, g, s)) return b;
+    *far = true;
     const Region t = region_of(g, P, 2 * s.k);
     const int64_t t_cells = (int64_t)(t.x1 - t.x0 + 1) * (t.y1 - t.y0 + 1);
     if (cap_cells(c, g) <= (t_cells > kBandCells ? t_cells : kBandCells))
@@ -460,6 +464,12 @@ __host__ __device__ inline int32_t next_vertex(WV& wv, const Grid& g, const Regi
     s = t;
   }
 }
+
+// Cells around p's cell up to which the walk's square grows: a step that needed points
+// outside the square (a vertex across a hole, or a hull fan) doubles it for the steps after
+// it, whose vertices are then usually inside (any square gives the same triangles).
+// (measured at 640x480: 2, 4 and 8 cut the slowest stars, 4 the most)
+constexpr int32_t kWalkMaxK = 4;
 
 // Triangles of p's star in which p has the smallest raster position, as (p, i1, i2)
 // counter-clockwise, handed to out.emit(i1, i2) (uniform calls; out.finish() writes what
@@ -500,7 +510,12 @@ __host__ __device__ inline int32_t star_of(WV& wv, const Grid& g, int32_t p, Out
     P2 B;
     const int32_t ix = ccw ? p : a, iy = ccw ? a : p;
     const P2 X = ccw ? P : A, Y = ccw ? A : P;
-    const int32_t b = next_vertex(wv, g, r, P, ix, X, iy, Y, &B);
+    bool far = false;
+    const int32_t b = next_vertex(wv, g, r, P, ix, X, iy, Y, &B, &far);
+    if (far && r.k < kWalkMaxK && !r.full) {
+      r = region_of(g, P, 2 * r.k);
+      wv.set_base(g, r);
+    }
     if (b < 0) {
       if (!ccw) break;  // the second hull edge
       ccw = false;      // the first hull edge: back to q, the other way
