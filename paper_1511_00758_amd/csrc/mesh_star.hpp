@@ -431,8 +431,10 @@ struct LeftRing {
 };
 
 // The third vertex of the triangle left of x -> y, exactly (-1: none, the edge is on the
-// hull). Its first candidate is the best of square r or, when r holds none, the best row
-// extreme (on the long triangles of hull vertices it is usually the vertex itself). Then,
+// hull). Its first candidate is the best of square r or, when r holds none, the best of the
+// square around the edge's end other than p or, when that holds none either, the best row
+// extreme (on the long triangles of hull vertices it is usually the vertex itself); any
+// point left of the edge serves, the checks below find the best. Then,
 // with s the square whose points have all been seen (r at first): a cap inside s is final;
 // a cap whose box covers no more cells than the square t of twice s's reach (or than
 // kBandCells) is checked by its bands outside s (verify_left); a larger one (a poor
@@ -447,9 +449,13 @@ __host__ __device__ inline int32_t next_vertex(WV& wv, const Grid& g, const Regi
   int32_t b = best_left(wv, g, r, ix, X, iy, Y, out);
   if (b < 0) {
     if (r.full) return -1;
-    b = best_extreme(wv, g, ix, X, iy, Y, out);
-    if (b < 0) return -1;  // nothing left of the edge: a hull edge
     *far = true;
+    // the square around the edge's other end first (the long edges of a fan: the vertex
+    // is usually next to that end), then the row extremes
+    const P2 F = X.x == P.x && X.y == P.y ? Y : X;
+    b = best_left(wv, g, region_of(g, F, 1), ix, X, iy, Y, out);
+    if (b < 0) b = best_extreme(wv, g, ix, X, iy, Y, out);
+    if (b < 0) return -1;  // nothing left of the edge: a hull edge
   }
   if (disk_inside_f(X, Y, *out, g, r)) return b;  // the common case, in single precision
   for (Region s = r;;) {
