@@ -817,17 +817,22 @@ sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, 
     return r;
   };
   if (hipEventCreate(&e1) != hipSuccess) return done(fail(SM_ERR_HIP, "hipEventCreate failed"));
-  // mean device time of `reps` launches of fn after one untimed launch, in ms (< 0: error)
+  // device time of fn in ms (< 0: error): after one untimed launch, the smallest mean of
+  // three runs of `reps` launches (kernels of a few microseconds: one run alone is noisy)
   auto time_it = [&](auto&& fn) -> float {
-    constexpr int reps = 5;
+    constexpr int reps = 10, trials = 3;
     if (fn() != hipSuccess) return -1.f;
-    if (hipEventRecord(e0, s) != hipSuccess) return -1.f;
-    for (int r = 0; r < reps; ++r)
-      if (fn() != hipSuccess) return -1.f;
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.f;
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
-    return ms / reps;
+    float best = -1.f;
+    for (int t = 0; t < trials; ++t) {
+      if (hipEventRecord(e0, s) != hipSuccess) return -1.f;
+      for (int r = 0; r < reps; ++r)
+        if (fn() != hipSuccess) return -1.f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.f;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
+      if (best < 0.f || ms / reps < best) best = ms / reps;
+    }
+    return best;
   };
   const uint64_t* cL = (const uint64_t*)(base + Lo.cL);
   const uint64_t* cR = (const uint64_t*)(base + Lo.cR);
@@ -835,15 +840,18 @@ sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, 
   const float* D_it = (const float*)(base + Lo.D_it);
   uint64_t* cell_g = (uint64_t*)(base + Lo.cell_g);
   uint64_t* cell_b = (uint64_t*)(base + Lo.cell_b);
-  // validation: block size in waves, per cell size of the iterations
+  // validation: block size in waves, per cell size of the iterations (the last one as the
+  // solve runs it, with the mask and its count)
+  unsigned long long* n_valid = (unsigned long long*)(base + Lo.counters + 32);
   for (int it = 1; it <= p->n_iters && it <= 8; ++it) {
     const int32_t sz = occ_size(*p, it);
+    const bool last = it == p->n_iters;
     int best = 0;
     float best_ms = 0.f;
     for (int nw : {1, 2, 4, 8, 16}) {
       const float ms = time_it([&] {
-        return launch_validate_nw(cL, cR, omega, D_it, W, H, *p, sz, nullptr, D_f, C_f, cell_g, cell_b, nullptr,
-                                  nullptr, nw, s);
+        return launch_validate_nw(cL, cR, omega, D_it, W, H, *p, sz, nullptr, D_f, C_f, cell_g, cell_b,
+                                  last ? mask : nullptr, last ? n_valid : nullptr, nw, s);
       });
       if (ms < 0.f) return done(fail(SM_ERR_HIP, "validation timing failed"));
       if (best == 0 || ms < best_ms) best = nw, best_ms = ms;

@@ -928,8 +928,12 @@ __device__ __forceinline__ void validate_block(const ValidateArgs& a, int bx, in
   }
   sg[w][lane] = kg;
   sb[w][lane] = kb;
+  if (a.mask) {  // the wave's count, one LDS atomic per wave
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) nvalid += __shfl_xor(nvalid, off, kWave);
+  }
   __syncthreads();  // s_valid initialised, keys visible
-  if (a.mask && nvalid) atomicAdd(&s_valid, nvalid);
+  if (a.mask && lane == 0 && nvalid) atomicAdd(&s_valid, nvalid);
   // thread (w, lane): cell row w of the tile, cell column seg (segment heads only)
   const bool head = lane == 0 || (a.sz <= kWave && (lane - 1) / a.sz != seg);
   if (w < a.crows && head && seg < a.cpr) {
