@@ -400,9 +400,11 @@ void sm_many_graph_destroy(sm_many_graph* g);
  *   rasteriser's bounded grid (512 ... 8192); for grid supports, the matcher's lanes per
  *   candidate (64, 32 or 16: 1, 2 or 4 candidates per wave, each candidate's disparity
  *   range in chunks of that many lanes), per disparity range; and the census tile's rows
- *   (8, 16 or 32 rows of 64 columns), per window size. Solves the frame, times each
- *   candidate over five launches on the solve's buffers, then solves the frame again, so
- *   that D_f, C_f and mask hold its results. Arguments as sm_solve.
+ *   (8, 16 or 32 rows of 64 columns), per window size. Times each candidate inside whole
+ *   solves of the frame (one launch after another, the others at their best so far; the
+ *   best of four runs of four solves), so that every kernel meets its inputs as the solve
+ *   leaves them; the last solve leaves the frame's results in D_f, C_f and mask. About 100
+ *   solves of the frame. Arguments as sm_solve.
  *   choices  [host] [11] out: validation waves per iteration (0 past n_iters), the raster
  *            workgroups, the matcher's lanes per candidate, the census rows per tile (0
  *            where not tuned).

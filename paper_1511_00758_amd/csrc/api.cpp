@@ -793,10 +793,12 @@ sm_status sm_set_launch_shape(int32_t kind, int32_t W, int32_t H, int32_t key, i
 }
 
 // Measured launch shapes for one frame size and parameter set (the autotuner of the
-// batched and per-frame solves): the frame is solved once, then each tunable launch is
-// timed over its candidate shapes on the buffers of that solve, the fastest is recorded
-// for (W, H[, sz]) and later launches of that size use it; the frame is solved again so
-// that D_f, C_f and mask hold its results.
+// batched and per-frame solves). Each tunable launch's candidates are timed inside whole
+// solves of the frame -- every kernel then sees its inputs and the caches as the solve
+// leaves them (timed alone, back to back, a kernel finds its inputs in its own L2 and the
+// order of the candidates can differ) -- one launch after another, the others at their
+// current best; the fastest is recorded for (W, H[, key]) and later solves of that size use
+// it. The last solve leaves the frame's results in D_f, C_f and mask.
 sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
                       const sm_params* p, void* ws, size_t ws_bytes, float* D_f, uint8_t* C_f, uint8_t* mask,
                       int32_t* choices, void* stream) {
@@ -805,121 +807,49 @@ sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, 
   SM_TRY(check_params(p));
   if (!choices) return fail(SM_ERR_ARG, "choices is NULL");
   for (int k = 0; k < 11; ++k) choices[k] = 0;
-  SM_TRY(sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, nullptr, stream));
   const Layout Lo = layout_of(W, H, *p);
-  uint8_t* base = (uint8_t*)ws;
-  hipStream_t s = (hipStream_t)stream;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  SM_HIP(hipEventCreate(&e0));
-  auto done = [&](sm_status r) {
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    return r;
+  struct Knob {
+    int kind;
+    int32_t key;
+    std::vector<int> values;
+    int slot;  // in choices
   };
-  if (hipEventCreate(&e1) != hipSuccess) return done(fail(SM_ERR_HIP, "hipEventCreate failed"));
-  // device time of fn in ms (< 0: error): after one untimed launch, the smallest mean of
-  // three runs of `reps` launches (kernels of a few microseconds: one run alone is noisy)
-  auto time_it = [&](auto&& fn) -> float {
-    constexpr int reps = 10, trials = 3;
-    if (fn() != hipSuccess) return -1.f;
-    float best = -1.f;
-    for (int t = 0; t < trials; ++t) {
-      if (hipEventRecord(e0, s) != hipSuccess) return -1.f;
-      for (int r = 0; r < reps; ++r)
-        if (fn() != hipSuccess) return -1.f;
-      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.f;
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
-      if (best < 0.f || ms / reps < best) best = ms / reps;
+  std::vector<Knob> knobs;
+  knobs.push_back({kTuneCensusRows, ((p->census_w - 1) / 2) << 8 | ((p->census_h - 1) / 2), {8, 16, 32}, 10});
+  if (p->support_mode == 0 && Lo.n_grid > 0)
+    knobs.push_back({kTuneMatchLanes, p->d_max - p->d_min + 1, {64, 32, 16}, 9});
+  if (Lo.mesh_on) knobs.push_back({kTuneRasterBlocks, 0, {512, 1024, 2048, 4096, 8192}, 8});
+  for (int it = 1; it <= p->n_iters && it <= 8; ++it)
+    knobs.push_back({kTuneValidateWaves, occ_size(*p, it), {1, 2, 4, 8, 16}, it - 1});
+  for (const Knob& k : knobs) set_tuned_choice(k.kind, W, H, k.key, 0);  // the built-in rules to start
+  SM_TRY(sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, nullptr, stream));
+  // wall time of one solve in seconds: the best of 4 runs of 4 solves (each solve waits for
+  // its frame)
+  auto time_solve = [&](double* t) -> sm_status {
+    using clk = std::chrono::steady_clock;
+    *t = -1.0;
+    for (int run = 0; run < 4; ++run) {
+      const auto t0 = clk::now();
+      for (int r = 0; r < 4; ++r) SM_TRY(sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, nullptr, stream));
+      const double dt = std::chrono::duration<double>(clk::now() - t0).count() / 4;
+      if (*t < 0.0 || dt < *t) *t = dt;
     }
-    return best;
+    return SM_OK;
   };
-  const uint64_t* cL = (const uint64_t*)(base + Lo.cL);
-  const uint64_t* cR = (const uint64_t*)(base + Lo.cR);
-  const uint8_t* omega = base + Lo.omega;
-  const float* D_it = (const float*)(base + Lo.D_it);
-  uint64_t* cell_g = (uint64_t*)(base + Lo.cell_g);
-  uint64_t* cell_b = (uint64_t*)(base + Lo.cell_b);
-  // validation: block size in waves, per cell size of the iterations (the last one as the
-  // solve runs it, with the mask and its count)
-  unsigned long long* n_valid = (unsigned long long*)(base + Lo.counters + 32);
-  for (int it = 1; it <= p->n_iters && it <= 8; ++it) {
-    const int32_t sz = occ_size(*p, it);
-    const bool last = it == p->n_iters;
+  for (const Knob& k : knobs) {
     int best = 0;
-    float best_ms = 0.f;
-    for (int nw : {1, 2, 4, 8, 16}) {
-      const float ms = time_it([&] {
-        return launch_validate_nw(cL, cR, omega, D_it, W, H, *p, sz, nullptr, D_f, C_f, cell_g, cell_b,
-                                  last ? mask : nullptr, last ? n_valid : nullptr, nw, s);
-      });
-      if (ms < 0.f) return done(fail(SM_ERR_HIP, "validation timing failed"));
-      if (best == 0 || ms < best_ms) best = nw, best_ms = ms;
+    double best_t = 0.0;
+    for (int v : k.values) {
+      set_tuned_choice(k.kind, W, H, k.key, v);
+      double t = 0.0;
+      SM_TRY(time_solve(&t));
+      if (best == 0 || t < best_t) best = v, best_t = t;
     }
-    set_tuned_choice(kTuneValidateWaves, W, H, sz, best);
-    choices[it - 1] = best;
+    set_tuned_choice(k.kind, W, H, k.key, best);
+    choices[k.slot] = best;
   }
-  // rasterisation with device counts (grid supports, device meshes): workgroups of the
-  // bounded grid, on the frame's last mesh
-  if (Lo.mesh_on) {
-    const int32_t* counts = (const int32_t*)(base + Lo.mstatus);
-    const sm_support* Sd = (const sm_support*)(base + Lo.S);
-    const sm_tri* Td = (const sm_tri*)(base + Lo.T);
-    float* D_w = (float*)(base + Lo.D_it);
-    int best = 0;
-    float best_ms = 0.f;
-    for (int blocks : {512, 1024, 2048, 4096, 8192}) {
-      const float ms =
-          time_it([&] { return launch_raster_blocks(Sd, Lo.S_cap, Td, Lo.T_cap, W, H, D_w, s, counts, blocks); });
-      if (ms < 0.f) return done(fail(SM_ERR_HIP, "raster timing failed"));
-      if (best == 0 || ms < best_ms) best = blocks, best_ms = ms;
-    }
-    set_tuned_choice(kTuneRasterBlocks, W, H, 0, best);
-    choices[8] = best;
-  }
-  // census: rows per tile, with the solve's own arguments (every output is rewritten by the
-  // final solve)
-  {
-    const CensusJob jobs[2] = {{L, stride, (uint64_t*)cL, (uint8_t*)omega}, {R, stride, (uint64_t*)cR, nullptr}};
-    CensusExtras ex;
-    ex.D_nan = (float*)D_it;
-    ex.grid_slots = p->support_mode == 1 ? nullptr : (sm_support*)(base + Lo.S);
-    ex.step = p->support_step;
-    ex.gw = Lo.n_grid > 0 ? (W - 1 - p->support_step / 2) / p->support_step + 1 : 0;
-    ex.zero = (int32_t*)(base + Lo.counters);
-    ex.n_zero = 16;
-    int best = 0;
-    float best_ms = 0.f;
-    for (int rows : {8, 16, 32}) {
-      const float ms = time_it([&] {
-        return launch_census(jobs, 2, W, H, p->census_w, p->census_h, p->grad_thr, D_f, C_f, p->t_hi,
-                             base + Lo.occ, &ex, s, rows);
-      });
-      if (ms < 0.f) return done(fail(SM_ERR_HIP, "census timing failed"));
-      if (best == 0 || ms < best_ms) best = rows, best_ms = ms;
-    }
-    set_tuned_choice(kTuneCensusRows, W, H, ((p->census_w - 1) / 2) << 8 | ((p->census_h - 1) / 2), best);
-    choices[10] = best;
-  }
-  // matching: lanes per candidate (1, 2 or 4 candidates per wave), on the grid candidates
-  // (each timed launch first resets the slots to pending from Omega)
-  if (p->support_mode == 0 && Lo.n_grid > 0) {
-    sm_support* slots = (sm_support*)(base + Lo.S);
-    int best = 0;
-    float best_ms = 0.f;
-    for (int lanes : {64, 32, 16}) {
-      const float ms = time_it([&] {
-        const hipError_t e = launch_grid_slots(omega, W, H, p->support_step, slots, Lo.n_grid, s);
-        return e != hipSuccess ? e : launch_match_lanes(cL, cR, W, H, *p, slots, Lo.n_grid, lanes, s);
-      });
-      if (ms < 0.f) return done(fail(SM_ERR_HIP, "matching timing failed"));
-      if (best == 0 || ms < best_ms) best = lanes, best_ms = ms;
-    }
-    set_tuned_choice(kTuneMatchLanes, W, H, p->d_max - p->d_min + 1, best);
-    choices[9] = best;
-  }
-  // the outputs of the frame again (the timed validations refined D_f and C_f)
-  return done(sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, nullptr, stream));
+  // the frame's results with the chosen shapes
+  return sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, nullptr, stream);
 }
 
 }  // extern "C"
