@@ -75,19 +75,32 @@ struct CensusArgs {
   CensusExtras x;
 };
 
-// One 64 x a.th output tile (bx, by) of image `job` (0 = left: also Omega_I and the
-// per-frame initialisation). `tile` is the block's LDS staging area.
+// One 64 x a.th output tile (bx, by) of image jb (left: also Omega_I and the per-frame
+// initialisation). `tile` is the block's LDS staging area.
 template <int RX, int RY>
-__device__ __forceinline__ void census_block(const CensusArgs& a, int job, int bx, int by, uint8_t* tile) {
+__device__ __forceinline__ void census_block(const CensusArgs& a, const CensusJob& jb, bool left, int bx, int by,
+                                             uint8_t* tile) {
   constexpr int PW = kTW + 2 * RX;
   const int th = a.th, PH = th + 2 * RY;
-  const CensusJob jb = a.job[job];
   const int W = a.W, H = a.H;
   const int gx0 = bx * kTW - RX, gy0 = by * th - RY;
-  for (int i = threadIdx.y * kTW + threadIdx.x; i < PH * PW; i += 256) {
-    int ty = i / PW, tx = i - ty * PW;
-    int gx = min(max(gx0 + tx, 0), W - 1), gy = min(max(gy0 + ty, 0), H - 1);
-    tile[i] = jb.img[(size_t)gy * jb.stride + gx];
+  // the tile and its halo, every load of a thread in flight before the first LDS store
+  constexpr int kStage = ((kTHMax + 2 * RY) * PW + 255) / 256;
+  const int tid = threadIdx.y * kTW + threadIdx.x;
+  uint8_t px[kStage];
+#pragma unroll
+  for (int k = 0; k < kStage; ++k) {
+    const int i = tid + 256 * k;
+    if (i < PH * PW) {
+      const int ty = i / PW, tx = i - ty * PW;
+      const int gx = min(max(gx0 + tx, 0), W - 1), gy = min(max(gy0 + ty, 0), H - 1);
+      px[k] = jb.img[(size_t)gy * jb.stride + gx];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kStage; ++k) {
+    const int i = tid + 256 * k;
+    if (i < PH * PW) tile[i] = px[k];
   }
   __syncthreads();
   const int u = bx * kTW + threadIdx.x;
@@ -124,7 +137,7 @@ __device__ __forceinline__ void census_block(const CensusArgs& a, int job, int b
       }
       jb.omega[idx] = om;
     }
-    if (job == 0) {
+    if (left) {
       if (a.D_f) a.D_f[idx] = 0.0f;
       if (a.C_f) a.C_f[idx] = (uint8_t)a.t_hi;
       if (a.occ) a.occ[idx] = 0;
@@ -144,7 +157,7 @@ __device__ __forceinline__ void census_block(const CensusArgs& a, int job, int b
       }
     }
   }
-  if (a.x.zero && bx == 0 && by == 0 && job == 0) {
+  if (a.x.zero && bx == 0 && by == 0 && left) {
     const int t = threadIdx.y * kTW + threadIdx.x;
     if (t < a.x.n_zero) a.x.zero[t] = 0;
   }
@@ -153,7 +166,7 @@ __device__ __forceinline__ void census_block(const CensusArgs& a, int job, int b
 template <int RX, int RY>
 __global__ __launch_bounds__(256) void k_census(CensusArgs a) {
   __shared__ uint8_t tile[(kTHMax + 2 * RY) * (kTW + 2 * RX)];
-  census_block<RX, RY>(a, blockIdx.z, blockIdx.x, blockIdx.y, tile);
+  census_block<RX, RY>(a, a.job[blockIdx.z], blockIdx.z == 0, blockIdx.x, blockIdx.y, tile);
 }
 
 template <int RX, int RY>
@@ -1302,9 +1315,8 @@ __global__ __launch_bounds__(256) void k_batch_census(const BatchFrame* F, const
   const int local = blockIdx.x - off[f];
   const int tx = (fr.W + kTW - 1) / kTW, ty = (fr.H + fr.census_rows - 1) / fr.census_rows;
   const int job = local / (tx * ty), t = local - job * tx * ty;
-  CensusArgs a{};
-  a.job[0] = CensusJob{fr.L, fr.stride, fr.cL, fr.omega};
-  a.job[1] = CensusJob{fr.R, fr.stride, fr.cR, nullptr};
+  CensusArgs a{};  // (the image's job passed on its own: no indexed local array)
+  const CensusJob jb = job == 0 ? CensusJob{fr.L, fr.stride, fr.cL, fr.omega} : CensusJob{fr.R, fr.stride, fr.cR, nullptr};
   a.W = fr.W;
   a.H = fr.H;
   a.grad_thr = fr.p.grad_thr;
@@ -1319,7 +1331,7 @@ __global__ __launch_bounds__(256) void k_batch_census(const BatchFrame* F, const
   a.x.gw = fr.gw;
   a.x.zero = fr.counters;
   a.x.n_zero = 16;
-  census_block<RX, RY>(a, job, t % tx, t / tx, tile);
+  census_block<RX, RY>(a, jb, job == 0, t % tx, t / tx, tile);
 }
 
 // a unit is one wave of the frame's candidates, kWave / match_lanes per wave
