@@ -29,11 +29,38 @@ def kernel_stats_rows(path):
     return rows
 
 
-def kernel_stats_md(path, cmd, title):
-    rows = kernel_stats_rows(path)
-    out = [f"# {title}", "", "Command:", "", "```", cmd, "```", "",
-           "| kernel | calls | avg us | min us | max us | total us | % |",
-           "|---|---:|---:|---:|---:|---:|---:|"]
+def trace_stats_rows(path, skip_solves):
+    """Per-kernel statistics of a ``--kernel-trace`` CSV over the dispatches after the
+    ``skip_solves``-th end-of-solve read-back (one ``copyBuffer`` per solve): the frames of
+    a run, without the solves of the autotuner before them."""
+    recs = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            recs.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    recs.sort()
+    seen, start = 0, 0
+    for i, (_, _, name) in enumerate(recs):
+        if seen == skip_solves:
+            start = i
+            break
+        if "copyBuffer" in name:
+            seen += 1
+    per = {}
+    for t0, t1, name in recs[start:]:
+        per.setdefault(short_name(name), []).append((t1 - t0) / 1e3)
+    total = sum(sum(v) for v in per.values()) or 1.0
+    rows = [{"name": k, "calls": len(v), "avg_us": sum(v) / len(v), "min_us": min(v), "max_us": max(v),
+             "total_us": sum(v), "pct": 100.0 * sum(v) / total} for k, v in per.items()]
+    return sorted(rows, key=lambda r: -r["total_us"])
+
+
+def kernel_stats_md(path, cmd, title, rows=None, note=None):
+    rows = kernel_stats_rows(path) if rows is None else rows
+    out = [f"# {title}", "", "Command:", "", "```", cmd, "```", ""]
+    if note:
+        out += [note, ""]
+    out += ["| kernel | calls | avg us | min us | max us | total us | % |",
+            "|---|---:|---:|---:|---:|---:|---:|"]
     for r in rows:
         out.append(f"| {r['name']} | {r['calls']} | {r['avg_us']:.2f} | {r['min_us']:.2f} | "
                    f"{r['max_us']:.2f} | {r['total_us']:.0f} | {r['pct']:.1f} |")
@@ -75,6 +102,9 @@ def main(argv=None):
     s.add_argument("csv")
     s.add_argument("--cmd", required=True)
     s.add_argument("--title", default="rocprofv3 kernel statistics")
+    s.add_argument("--trace", default=None, help="kernel_trace.csv: statistics from the trace instead")
+    s.add_argument("--skip-solves", type=int, default=0,
+                   help="with --trace: only the dispatches after this many solves (the autotuner's)")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -87,7 +117,12 @@ def main(argv=None):
     t.add_argument("--cmd", default="")
     a = ap.parse_args(argv)
     if a.action == "stats":
-        sys.stdout.write(kernel_stats_md(a.csv, a.cmd, a.title))
+        if a.trace:
+            note = (f"From the kernel trace, after the first {a.skip_solves} solves (the autotuner's, "
+                    "on the run's first frame): the frames of the run.")
+            sys.stdout.write(kernel_stats_md(a.csv, a.cmd, a.title, trace_stats_rows(a.trace, a.skip_solves), note))
+        else:
+            sys.stdout.write(kernel_stats_md(a.csv, a.cmd, a.title))
     else:
         res = traffic(a.fetch, a.write, a.kernel, a.calib_fetch, a.calib_write, a.calib_kernel,
                       a.calib_bytes)
