@@ -94,6 +94,15 @@ def _cases():
     cases.append(("one", 50, 50, [[(7, 9)]]))
     cases.append(("none", 50, 50, [[]]))
     cases.append(("two_rows", 300, 40, [[(x, 10) for x in range(0, 300, 5)] + [(x, 30) for x in range(2, 300, 7)]]))
+    # fans at a frame border: two points on the first column and a second column with a long
+    # gap, then a lattice: the border points' walks step along long thin triangles (squares
+    # without a point left of the edge, the other end's square, the walk's square growing)
+    fan = [(5, 35), (5, 45)] + [(15, y) for y in range(35, 190, 10)] + [(15, y) for y in range(425, 480, 10)]
+    fan += [(x, y) for y in range(5, 480, 10) for x in range(35, 200, 10)]
+    cases.append(("border_fan", 240, 480, [fan, [(5, 300), (25, 250)]]))
+    holes = [(x, y) for y in range(5, 200, 10) for x in range(5, 300, 10)
+             if (x - 150) ** 2 + (y - 100) ** 2 > 70 ** 2 or (x, y) in ((150, 105), (145, 95))]
+    cases.append(("hole_hub", 300, 200, [holes]))
     return cases
 
 
