@@ -261,9 +261,11 @@ struct FastSelectArgs {
 // earlier raster neighbours score lower and later ones do not score higher.
 __device__ __forceinline__ bool fast_keypoint(const uint8_t* score, int W, int u, int v, int sc, int t) {
   if (sc <= t) return false;
-  const uint8_t* c = score + (size_t)v * W + u;
-  return c[-W - 1] < sc && c[-W] < sc && c[-W + 1] < sc && c[-1] < sc && c[1] <= sc &&
-         c[W - 1] <= sc && c[W] <= sc && c[W + 1] <= sc;
+  const uint8_t* c = score + (size_t)v * W + u;  // (all eight loads at once: no short circuit)
+  const int n0 = c[-W - 1], n1 = c[-W], n2 = c[-W + 1], n3 = c[-1];
+  const int n4 = c[1], n5 = c[W - 1], n6 = c[W], n7 = c[W + 1];
+  return ((n0 < sc) & (n1 < sc) & (n2 < sc) & (n3 < sc) & (n4 <= sc) & (n5 <= sc) & (n6 <= sc) &
+          (n7 <= sc)) != 0;
 }
 
 constexpr int kFastThreads = 1024, kFastWaves = kFastThreads / kWave;
@@ -306,10 +308,24 @@ __global__ __launch_bounds__(kFastThreads) void k_fast_select(FastSelectArgs a) 
   const int bw = max(u1 - u0, 0), n = bw * max(v1 - v0, 0);
   if (threadIdx.x < 256) hist[threadIdx.x] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += kFastThreads) {
-    const int v = v0 + i / bw, u = u0 + i % bw;
-    const int sc = a.score[(size_t)v * a.W + u];
-    if (fast_keypoint(a.score, a.W, u, v, sc, a.t)) atomicAdd(&hist[sc], 1);
+  constexpr int kHistPer = 4;  // pixels per thread and pass, their loads in flight together
+  for (int start = 0; start < n; start += kHistPer * kFastThreads) {
+    int sc[kHistPer];
+    bool kp[kHistPer];
+#pragma unroll
+    for (int k = 0; k < kHistPer; ++k) {
+      const int i = start + k * kFastThreads + threadIdx.x;
+      const int v = v0 + (i < n ? i / bw : 0), u = u0 + (i < n ? i % bw : 0);
+      sc[k] = i < n ? a.score[(size_t)v * a.W + u] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kHistPer; ++k) {
+      const int i = start + k * kFastThreads + threadIdx.x;
+      kp[k] = i < n && fast_keypoint(a.score, a.W, u0 + i % bw, v0 + i / bw, sc[k], a.t);
+    }
+#pragma unroll
+    for (int k = 0; k < kHistPer; ++k)
+      if (kp[k]) atomicAdd(&hist[sc[k]], 1);
   }
   __syncthreads();  // histogram complete
   if (threadIdx.x == 0) {  // default: every keypoint (score >= 1 > 0) is kept
@@ -345,41 +361,53 @@ __global__ __launch_bounds__(kFastThreads) void k_fast_select(FastSelectArgs a) 
   const int thr = s_thr, take = s_take;
   const size_t out0 = (size_t)b * a.per_bin;
   int base_eq = 0, base_sel = 0;
-  for (int start = 0; start < n && base_sel < a.per_bin; start += kFastThreads) {  // block-uniform
-    const int i = start + threadIdx.x;
-    int u = 0, v = 0, sc = 0;
-    bool kp = false;
-    if (i < n) {
-      v = v0 + i / bw;
-      u = u0 + i % bw;
-      sc = a.score[(size_t)v * a.W + u];
-      kp = fast_keypoint(a.score, a.W, u, v, sc, a.t);
+  constexpr int kSelPer = 4;  // chunks of kFastThreads pixels whose loads go out together
+  for (int start0 = 0; start0 < n && base_sel < a.per_bin; start0 += kSelPer * kFastThreads) {  // block-uniform
+    int scs[kSelPer];
+    bool kps[kSelPer];
+#pragma unroll
+    for (int k = 0; k < kSelPer; ++k) {
+      const int i = start0 + k * kFastThreads + threadIdx.x;
+      scs[k] = i < n ? a.score[(size_t)(v0 + i / bw) * a.W + u0 + i % bw] : 0;
     }
-    // keypoints above the threshold are all kept; at the threshold, the first `take` in
-    // raster order (their rank needs the prefix of the at-threshold flags)
-    const bool above = kp && sc > thr, eq = kp && sc == thr;
-    int p_above, p_eq, n_above, n_eq;
-    block_prefix2(above, eq, wsum, p_above, p_eq, n_above, n_eq);
-    const int rank = base_eq + p_eq;
-    const bool eq_sel = eq && rank < take;
-    // output position: kept keypoints before this one in raster order
-    const int eq_before = min(max(take - base_eq, 0), p_eq);  // kept at-threshold ones before i
-    const bool sel = above || eq_sel;
-    const int pos = base_sel + p_above + eq_before;
-    if (sel) {
-      if (a.slots) {
-        sm_support sp;
-        sp.u = (int16_t)u;
-        sp.v = (int16_t)v;
-        sp.d = kPending;
-        a.slots[out0 + pos] = sp;
-      } else {
-        a.uv[2 * (out0 + pos)] = (int16_t)u;
-        a.uv[2 * (out0 + pos) + 1] = (int16_t)v;
+#pragma unroll
+    for (int k = 0; k < kSelPer; ++k) {
+      const int i = start0 + k * kFastThreads + threadIdx.x;
+      kps[k] = i < n && fast_keypoint(a.score, a.W, u0 + i % bw, v0 + i / bw, scs[k], a.t);
+    }
+#pragma unroll
+    for (int k = 0; k < kSelPer; ++k) {
+      const int start = start0 + k * kFastThreads;
+      if (start >= n || base_sel >= a.per_bin) break;  // (block-uniform)
+      const int i = start + threadIdx.x;
+      const int v = v0 + (i < n ? i / bw : 0), u = u0 + (i < n ? i % bw : 0), sc = scs[k];
+      const bool kp = kps[k];
+      // keypoints above the threshold are all kept; at the threshold, the first `take` in
+      // raster order (their rank needs the prefix of the at-threshold flags)
+      const bool above = kp && sc > thr, eq = kp && sc == thr;
+      int p_above, p_eq, n_above, n_eq;
+      block_prefix2(above, eq, wsum, p_above, p_eq, n_above, n_eq);
+      const int rank = base_eq + p_eq;
+      const bool eq_sel = eq && rank < take;
+      // output position: kept keypoints before this one in raster order
+      const int eq_before = min(max(take - base_eq, 0), p_eq);  // kept at-threshold ones before i
+      const bool sel = above || eq_sel;
+      const int pos = base_sel + p_above + eq_before;
+      if (sel) {
+        if (a.slots) {
+          sm_support sp;
+          sp.u = (int16_t)u;
+          sp.v = (int16_t)v;
+          sp.d = kPending;
+          a.slots[out0 + pos] = sp;
+        } else {
+          a.uv[2 * (out0 + pos)] = (int16_t)u;
+          a.uv[2 * (out0 + pos) + 1] = (int16_t)v;
+        }
       }
+      base_sel += n_above + min(max(take - base_eq, 0), n_eq);
+      base_eq += n_eq;
     }
-    base_sel += n_above + min(max(take - base_eq, 0), n_eq);
-    base_eq += n_eq;
   }
   for (int j = base_sel + threadIdx.x; j < a.per_bin; j += kFastThreads) {  // empty slots
     if (a.slots) {
@@ -623,9 +651,18 @@ __global__ void k_fill_u8(uint8_t* p, size_t n, uint8_t val) {
   if (i < n) p[i] = val;
 }
 
-__global__ void k_fill_f32(float* p, size_t n, float val) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = val;
+// p[0, n) = val: 16-byte stores from the first 16-byte boundary on (a grid-stride loop),
+// single floats before it and after the last full 16 bytes.
+__global__ __launch_bounds__(256) void k_fill_f32(float* p, size_t n, float val) {
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (size_t)gridDim.x * blockDim.x;
+  const size_t head = min((size_t)(((16 - ((uintptr_t)p & 15)) & 15) / 4), n);
+  if (tid < head) p[tid] = val;
+  float4* q = reinterpret_cast<float4*>(p + head);
+  const size_t n4 = (n - head) / 4;
+  const float4 v = make_float4(val, val, val, val);
+  for (size_t i = tid; i < n4; i += nt) q[i] = v;
+  const size_t tail = head + 4 * n4;
+  if (tid < n - tail) p[tail + tid] = val;
 }
 
 __global__ void k_mark(const sm_support* S, int n, uint8_t* occ, int W, int H) {
@@ -1125,7 +1162,8 @@ hipError_t launch_mark(const sm_support* S, int32_t n, uint8_t* occ, int32_t W, 
 
 hipError_t launch_fill_nan(float* D, size_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  SM_LAUNCH(k_fill_f32, dim3(blocks_for(n, 256)), dim3(256), 0, s, D, n, __builtin_nanf(""));
+  SM_LAUNCH(k_fill_f32, dim3(std::min<unsigned>(blocks_for((n + 3) / 4, 256), 8192u)), dim3(256), 0, s, D, n,
+            __builtin_nanf(""));
   return hipGetLastError();
 }
 
