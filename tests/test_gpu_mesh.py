@@ -89,6 +89,15 @@ def test_device_mesh_serving_sizes(W, H):
     assert st["n_support"][-1] > 10000 or W < 1920
 
 
+@pytest.mark.parametrize("W,H", [(320, 4200), (2560, 1440)])
+def test_device_mesh_counts_outside_lds(W, H):
+    """Frames whose rows (more than 4096) or bucket cells (more than 12288) do not fit the
+    preparation kernel's LDS: its counts and row extremes go to global memory."""
+    _note("prep in global memory", W, H)
+    sc = scenes.make_rect_scene(W, H, seed=W + H, dlo=2.0, dhi=120.0)
+    _check(sc, scenes.params_of(3) if W > 640 else scenes.params_of(2))
+
+
 def test_device_mesh_repeated_solves_reuse_workspace():
     """One solver, frames of different content in a row: nothing of the previous frame's
     mesh survives in the workspace."""
