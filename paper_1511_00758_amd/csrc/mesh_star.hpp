@@ -474,8 +474,12 @@ __host__ __device__ inline int32_t next_vertex(WV& wv, const Grid& g, const Regi
 // Cells around p's cell up to which the walk's square grows: a step that needed points
 // outside the square (a vertex across a hole, or a hull fan) doubles it for the steps after
 // it, whose vertices are then usually inside (any square gives the same triangles).
-// (measured at 640x480: 2, 4 and 8 cut the slowest stars, 4 the most)
-constexpr int32_t kWalkMaxK = 4;
+// (measured at 640x480: 2, 4 and 8 cut the slowest stars, 4 the most for a wavefront; a
+// 16-lane group, whose staging holds half as many candidates, does best with 2)
+template <class WV>
+__host__ __device__ constexpr int32_t walk_max_k() {
+  return WV::kN >= 64 ? 4 : 2;
+}
 
 // Triangles of p's star in which p has the smallest raster position, as (p, i1, i2)
 // counter-clockwise, handed to out.emit(i1, i2) (uniform calls; out.finish() writes what
@@ -518,7 +522,7 @@ __host__ __device__ inline int32_t star_of(WV& wv, const Grid& g, int32_t p, Out
     const P2 X = ccw ? P : A, Y = ccw ? A : P;
     bool far = false;
     const int32_t b = next_vertex(wv, g, r, P, ix, X, iy, Y, &B, &far);
-    if (far && r.k < kWalkMaxK && !r.full) {
+    if (far && r.k < walk_max_k<WV>() && !r.full) {
       r = region_of(g, P, 2 * r.k);
       wv.set_base(g, r);
     }
