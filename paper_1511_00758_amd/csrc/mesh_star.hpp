@@ -510,9 +510,18 @@ __host__ __device__ inline int32_t star_of(WV& wv, const Grid& g, int32_t p, Out
     if ((uint32_t)wp < (uint32_t)(A.x | (A.y << 16)) && (uint32_t)wp < (uint32_t)(B.x | (B.y << 16)))
       out.emit(i1, i2);  // p is the triangle's i0
   };
-  // counter-clockwise from q, then (at a hull edge) clockwise from q to the other hull edge;
-  // the triangle of each step lies left of p -> a (counter-clockwise) or of a -> p
-  bool ccw = true;
+  // The triangles p writes are those whose two other vertices come after p in raster
+  // order; those vertices lie in a half-plane through p (the rows below p's and its row right
+  // of it), so they are one contiguous run of p's neighbours in angular order. The walk goes
+  // around p from q one way (counter-clockwise: the triangle of each step lies left of
+  // p -> a; clockwise: left of a -> p), then, when needed, from q the other way: it stops
+  // at a hull edge, and once past the run's end (for good when q is outside the run: the
+  // whole run has been passed). With q outside the run the first way is the one that meets
+  // the run's nearer end (the run starts at p's row: counter-clockwise from q's side right
+  // of p, clockwise from its left).
+  auto later = [&](P2 C) { return (uint32_t)wp < (uint32_t)(C.x | (C.y << 16)); };
+  const bool q_in = later(Q);
+  bool ccw = q_in || Q.x >= P.x, second = false, in_run = q_in;
   int32_t a = q;
   P2 A = Q;
   for (int32_t steps = 0;; ++steps) {
@@ -526,18 +535,28 @@ __host__ __device__ inline int32_t star_of(WV& wv, const Grid& g, int32_t p, Out
       r = region_of(g, P, 2 * r.k);
       wv.set_base(g, r);
     }
-    if (b < 0) {
-      if (!ccw) break;  // the second hull edge
-      ccw = false;      // the first hull edge: back to q, the other way
+    bool turn;
+    if (b < 0) {  // a hull edge: the run ends here when q is outside it and it has been met
+      if (second || (in_run && !q_in)) break;
+      turn = true;
+    } else {
+      if (ccw) emit(a, A, b, B);
+      else emit(b, B, a, A);
+      const bool b_in = later(B);
+      turn = in_run && !b_in;  // past the run's end this way
+      if (turn && (second || !q_in)) break;
+      in_run = b_in;
+      a = b;
+      A = B;
+      if (!turn && a == q) break;  // around: an interior point
+    }
+    if (turn) {  // from q, the other way
+      second = true;
+      ccw = !ccw;
       a = q;
       A = Q;
-      continue;
+      in_run = q_in;
     }
-    if (ccw) emit(a, A, b, B);
-    else emit(b, B, a, A);
-    a = b;
-    A = B;
-    if (ccw && a == q) break;  // around: an interior point
   }
   return out.finish();
 }
