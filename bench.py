@@ -32,7 +32,8 @@ PEAK_HBM_GBS = 8000.0
 PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 39.32 T int32 lane-ops/s
 
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1511_00758_amd", "csrc", f)
-                  for f in ("kernels.hip", "kernels.hpp", "star.hip", "star.hpp", "mesh_star.hpp", "predicates.hpp")]
+                  for f in ("kernels.hip", "kernels.hpp", "star.hip", "star.hpp", "mesh_star.hpp", "predicates.hpp",
+                            "raster.hpp")]
 
 
 def progress(msg):
@@ -53,16 +54,18 @@ def algorithmic_work(kernel, W, H, p, n_iters, launches, stats=None):
     launches of one solve), as (bound, amount, unit_scale, unit, per_unit_note)."""
     npx = W * H
     if kernel == "mesh":
-        # one tessellation (preparation + star kernel): the supports read (8 B each) and the
-        # triangles written (12 B each). The bucket grid the preparation writes and the star
-        # kernel reads back is the method's own overhead, not counted; the star kernel is
-        # bound by the latency of its gathers, so the fraction of HBM peak is small
+        # one tessellation (preparation + star kernel): the supports read (8 B each), the
+        # triangles written (12 B each) and D_it, which the star kernel's workgroups write as
+        # they rasterise their triangles (4 B per pixel: an upper bound, covered pixels only).
+        # The bucket grid the preparation writes and the star kernel reads back is the
+        # method's own overhead, not counted; the star kernel is bound by the latency of its
+        # gathers, so the fraction of HBM peak is small
         if not stats:
             return None
-        per = [8.0 * stats["n_support"][k] + 12.0 * stats["n_tris"][k] for k in range(n_iters)]
+        per = [8.0 * stats["n_support"][k] + 12.0 * stats["n_tris"][k] + 4.0 * npx for k in range(n_iters)]
         amount = sum(per) / len(per)
         return "hbm", amount, 1e9, "GB/s", (f"mean over tessellations 1..{n_iters}: 8 B x supports + "
-                                            f"12 B x triangles = {amount / 1e3:.1f} kB")
+                                            f"12 B x triangles + 4 B x {npx} px (D_it) = {amount / 1e3:.1f} kB")
     bits = p["census_w"] * p["census_h"] - 1
     if kernel == "census":
         # 2 images x (1 B read + 8 B census word written) -- but compute-bound:

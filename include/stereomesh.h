@@ -100,7 +100,8 @@ typedef enum {
   SM_ST_CENSUS = 0,          /* census + Omega_I of both images, per-frame initialisation     */
   SM_ST_MATCH = 1,           /* epipolar matching of the support-grid candidates              */
   SM_ST_COMPACT = 2,         /* order-preserving compaction of matched / resampled supports   */
-  SM_ST_RASTER = 3,          /* plane fit + per-triangle rasterisation (interpolation)        */
+  SM_ST_RASTER = 3,          /* plane fit + per-triangle rasterisation (interpolation); none  */
+                             /* with device meshes: their star kernel rasterises (SM_ST_MESH) */
   SM_ST_VALIDATE = 4,        /* cost evaluation + refinement                                 */
   SM_ST_REMATCH = 5,         /* resampling: cells -> confident supports + re-matched pixels  */
   SM_ST_FAST = 6,            /* FAST scores + per-bin keypoint selection (support_mode 1)     */
@@ -281,7 +282,9 @@ size_t sm_solve_workspace_bytes(int32_t W, int32_t H, const sm_params* p /* [hos
  *   Synchronisation: with grid candidates and device meshes (host_mesh = 0) the counts
  *   stay on the device and `stream` is synchronised once, at the end of the frame (a frame
  *   whose device mesh fails is solved again with host meshes, counted in
- *   st->mesh_fallback); otherwise once per triangulation (n_iters times).
+ *   st->mesh_fallback); otherwise once per triangulation (n_iters times). With device
+ *   meshes the interpolation has no launch of its own: each workgroup of the star kernel
+ *   rasterises the triangles its stars found (timed with the mesh stage).
  */
 sm_status sm_solve(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
                    const sm_params* p /* [host] */, void* ws, size_t ws_bytes, float* D_f,

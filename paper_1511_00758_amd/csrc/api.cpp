@@ -288,9 +288,11 @@ sm_status enqueue_census_match(const uint8_t* L, const uint8_t* R, int32_t W, in
 
 // The rest of a frame whose every tessellation runs on the device: each tessellation of
 // S_it is built from scratch by the per-point star kernels (star.hpp), after its new
-// supports are compacted (the matched candidates, then each iteration's resampled ones).
-// The counts stay on the device (read by the raster, resampling and mesh kernels), so
-// nothing here waits for the device; the caller reads the counters and status words back.
+// supports are compacted (the matched candidates, then each iteration's resampled ones),
+// and every star rasterises its own triangles into D_it as soon as it has them (the
+// interpolation of Alg. 1 needs no launch of its own). The counts stay on the device (read
+// by the resampling and mesh kernels), so nothing here waits for the device; the caller
+// reads the counters and status words back.
 sm_status enqueue_device_meshes(const sm_params& p, int32_t W, int32_t H, const Layout& Lo, const FrameBufs& b,
                                 float* D_f, uint8_t* C_f, uint8_t* mask, Timer& tm, hipStream_t s) {
   auto star_job = [&](int32_t first, int32_t compact_n, int32_t* compact_count) {
@@ -309,6 +311,7 @@ sm_status enqueue_device_meshes(const sm_params& p, int32_t W, int32_t H, const 
     job.H = H;
     job.blocks = star_blocks(Lo.S_cap);
     job.w = b.mw;
+    job.D = b.D_it;  // each star rasterises its triangles: no raster launch
     return job;
   };
   const int32_t* counts = b.mstatus;
@@ -318,9 +321,6 @@ sm_status enqueue_device_meshes(const sm_params& p, int32_t W, int32_t H, const 
   for (int it = 1; it <= p.n_iters; ++it) {
     const int32_t sz = occ_size(p, it);
     const bool last = it == p.n_iters;
-    SM_TRY(tm.begin(SM_ST_RASTER));
-    SM_HIP(launch_raster(b.S, Lo.S_cap, b.T, Lo.T_cap, W, H, b.D_it, s, counts));
-    SM_TRY(tm.end());
     SM_TRY(tm.begin(SM_ST_VALIDATE));
     SM_HIP(launch_validate_only(b.cL, b.cR, b.omega, b.D_it, W, H, p, sz, nullptr, D_f, C_f, b.cell_g, b.cell_b,
                                 last ? mask : nullptr, last ? b.n_valid : nullptr, s));

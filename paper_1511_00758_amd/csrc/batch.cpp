@@ -478,6 +478,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
     jb.W = hF[f].W;
     jb.H = hF[f].H;
     jb.blocks = star_blocks_many(L.S_cap, grouped);
+    jb.D = nullptr;  // (the batched raster stage rasterises the meshes)
     jb.w = star_work_at(b + L.mwork, hF[f].W, hF[f].H, L.S_cap);
     job_frame.push_back(f);
     job_start.push_back((uint8_t)start);

@@ -8,6 +8,7 @@
 
 #include "kernels.hpp"
 #include "mesh_star.hpp"
+#include "raster.hpp"
 #include "star.hpp"
 
 namespace sm {
@@ -670,6 +671,7 @@ struct DevOut {
   int32_t* err;
   int32_t n = 0, total = 0;
   int32_t my1 = 0, my2 = 0;
+  int32_t fl = 0, nfl = 0;  // a wavefront's full sets written so far: lane k holds set k's first slot
   __device__ void begin() { n = 0; }
   __device__ void write(int32_t slot) {
     if (lane < n) {
@@ -685,6 +687,10 @@ struct DevOut {
     }
     slot = __shfl(slot, gbase);
     write(G == 64 ? uniform(slot) : slot);
+    if constexpr (G == 64) {
+      if (lane == nfl) fl = slot;
+      ++nfl;
+    }
     total += n;
     n = 0;
   }
@@ -696,12 +702,38 @@ struct DevOut {
   __device__ int32_t finish() { return total + n; }
 };
 
+// Rasterisation of the triangles of a workgroup's stars (the job names D_it), once its
+// last walk has ended: the triangles its reservation placed in T[base, base + n), sixteen
+// at a time, a 16-lane group each taking every 16th row of one (the waves that finished
+// early share the slow stars' long triangles), after each wavefront's full sets written
+// earlier (a star with more triangles than lanes). Every pixel is owned by one triangle of
+// the mesh, so D_it does not depend on which lanes write it, or when.
+__device__ void raster_sets(const StarJob& a, const DevOut<64>& out, int32_t n_support, int lane) {
+  const int gi = lane >> 4, rl = lane & 15;
+  for (int32_t f = 0; f < out.nfl && f < 64; ++f) {
+    const int32_t slot = __builtin_amdgcn_readlane(out.fl, f);
+    for (int32_t k0 = 0; k0 < 64; k0 += 4) {
+      const int32_t t = slot + k0 + gi;
+      if (t < a.T_cap) raster_rows(raster_setup(a.S, n_support, a.T, t, a.W, a.H), rl, 16, a.W, a.D);
+    }
+  }
+}
+__device__ void raster_block(const StarJob& a, int32_t base, int32_t n, int32_t n_support) {
+  constexpr int kTris = 64 * kStarWaves / 16;
+  const int rl = threadIdx.x & 15;
+  for (int32_t k0 = 0; k0 < n; k0 += kTris) {
+    const int32_t k = k0 + (int32_t)(threadIdx.x >> 4);
+    if (k < n && base + k < a.T_cap)
+      raster_rows(raster_setup(a.S, n_support, a.T, base + k, a.W, a.H), rl, 16, a.W, a.D);
+  }
+}
+
 __device__ void star_wave(const StarJob& a, int32_t local_wave) {
   __shared__ int32_t s_id[kStarWaves][kStageCap];
   __shared__ int32_t s_uv[kStarWaves][kStageCap];
   __shared__ int32_t s_mark[kStarWaves][DevWave::kN * DevWave::kInFlight];
   __shared__ int32_t s_cnt[kStarWaves];
-  __shared__ int32_t s_base;
+  __shared__ int32_t s_base, s_sum;
   const int lane = threadIdx.x & 63, wv_i = uniform((int32_t)threadIdx.x >> 6);
   int32_t* status = a.status;
   const int32_t n = status[kMeshSupports];
@@ -720,6 +752,11 @@ __device__ void star_wave(const StarJob& a, int32_t local_wave) {
         atomicCAS(&status[kMeshErr], 0, -r);
         if (a.status_copy) atomicCAS(&a.status_copy[kMeshErr], 0, -r);
       }
+    } else if (a.D && out.nfl > 0) {
+      // the wavefront's own writes to T before its lanes read each other's
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      raster_sets(a, out, n, lane);
     }
   }
   if (lane == 0) s_cnt[wv_i] = out.n;
@@ -733,11 +770,16 @@ __device__ void star_wave(const StarJob& a, int32_t local_wave) {
       if (out.counter_copy) atomicAdd(out.counter_copy, sum);
     }
     s_base = base;
+    s_sum = sum;
   }
   __syncthreads();
   int32_t off = s_base;
   for (int k = 0; k < wv_i; ++k) off += s_cnt[k];
   out.write(uniform(off));
+  if (a.D) {        // (the job's: uniform over the workgroup)
+    __syncthreads();  // every wavefront's triangles in T before any lane reads them
+    raster_block(a, s_base, s_sum, n);
+  }
 }
 
 // Sixteen stars per workgroup, one 16-lane group each (the stage-batched solve): the same

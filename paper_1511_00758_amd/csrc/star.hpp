@@ -7,8 +7,8 @@
 // 16 x 16 px cells, the smallest and largest u of every pixel row, the frame's status
 // words) and the star kernel (one wavefront per support for one frame, one 16-lane group
 // per support for the batched launch; each writes the triangles of its star in which it
-// is the first vertex). Nothing is kept from one tessellation to the next besides the
-// supports.
+// is the first vertex, and, when the job names D_it, rasterises them into it). Nothing is
+// kept from one tessellation to the next besides the supports.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -67,6 +67,8 @@ struct StarJob {
   int32_t W, H;
   int32_t blocks;           // star-kernel workgroups of this frame (star_blocks / star_blocks_many)
   StarWork w;
+  float* D = nullptr;       // nullable: D_it [H][W]; the star kernel (a star per wavefront) then
+                            // rasterises every triangle it writes into it
 };
 
 // Star-kernel workgroups for a frame of at most S_cap supports: of launch_star (four stars

@@ -509,14 +509,15 @@ def test_solve_deterministic(frames):
 
 def test_solve_selected_stage_timing(frames):
     """Timing only the validation and rasterisation kernels: the same outputs, events on
-    those launches only."""
+    those launches only. With device meshes every star rasterises its own triangles, so
+    the frame has no raster launch to time."""
     sc, p, tr = frames[2]
     a = _solve_gpu(sc, sc.params)
     b = _solve_gpu(sc, sc.params, timing=("validate", "raster"))
     for x, y in zip(a[:3], b[:3]):
         assert (x.view(np.uint8) == y.view(np.uint8)).all()
     st = b[3]
-    assert st["stage_launches"]["validate"] == p.n_iters and st["stage_launches"]["raster"] == p.n_iters
+    assert st["stage_launches"]["validate"] == p.n_iters and st["stage_launches"]["raster"] == 0
     assert st["stage_launches"]["census"] == 0 and st["stage_launches"]["match"] == 0
     assert st["stage_us"]["validate"] > 0 and st["stage_us"]["census"] == 0
 
