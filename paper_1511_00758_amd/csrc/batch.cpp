@@ -459,6 +459,11 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
   for (int32_t f = 0; f < n; ++f)
     if (P.lay[f].mesh_on) mesh_candidates += P.lay[f].n_grid;
   const bool grouped = star_grouped(mesh_candidates);
+  // every frame's meshes on the device, a star per wavefront: the star kernel's workgroups
+  // rasterise the triangles they find, and the batch has no raster stage
+  bool all_dev = true;
+  for (int32_t f = 0; f < n; ++f) all_dev &= P.lay[f].mesh_on;
+  const bool star_raster = all_dev && !grouped;
   std::vector<uint8_t> mesh_dev(n, 0), job_start;
   std::vector<int32_t> host_upto(n, 0), nT_dev(n, 0), job_frame;
   auto add_job = [&](int32_t f, int32_t start, const int32_t* n_new) {
@@ -478,7 +483,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
     jb.W = hF[f].W;
     jb.H = hF[f].H;
     jb.blocks = star_blocks_many(L.S_cap, grouped);
-    jb.D = nullptr;  // (the batched raster stage rasterises the meshes)
+    jb.D = star_raster ? hF[f].D_it : nullptr;
     jb.w = star_work_at(b + L.mwork, hF[f].W, hF[f].H, L.S_cap);
     job_frame.push_back(f);
     job_start.push_back((uint8_t)start);
@@ -525,8 +530,6 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
   // supports), so the batch runs without a synchronisation until its end. Every iteration's
   // descriptors are staged in a host buffer of their own, since earlier uploads may still be
   // pending. A frame whose device mesh failed is then solved again alone, with host meshes.
-  bool all_dev = true;
-  for (int32_t f = 0; f < n; ++f) all_dev &= P.lay[f].mesh_on;
   if (all_dev) {
     constexpr int32_t kRasterUnits = 1024;  // waves per frame, striding over its triangles
     for (int it = 1; it <= max_iters; ++it) {
@@ -580,6 +583,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
           jb.H = d.H;
           jb.blocks = star_blocks_many(L.S_cap, grouped);
           jb.w = star_work_at(b + L.mwork, d.W, d.H, L.S_cap);
+          jb.D = star_raster ? d.D_it : nullptr;
         }
         resample |= rs;
       }
@@ -601,8 +605,10 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
         o_v[f + 1] = o_v[f] + (active[f] ? validate_blocks(F[f].W, F[f].H, F[f].sz, nw) : 0);
       const int32_t it_blocks = star_offsets(J, J_off, n_jobs);
       SM_HIP(hipMemcpyAsync(base + P.desc_off, h, P.tri_off - P.desc_off, hipMemcpyHostToDevice, s));
-      SM_TRY(arm(SM_ST_RASTER));
-      SM_HIP(launch_batch_raster(dF, doff_arr(kRaster), n, o_r[n], s));
+      if (!star_raster) {
+        SM_TRY(arm(SM_ST_RASTER));
+        SM_HIP(launch_batch_raster(dF, doff_arr(kRaster), n, o_r[n], s));
+      }
       SM_TRY(arm(SM_ST_VALIDATE));
       SM_HIP(launch_batch_validate(dF, doff_arr(kValidate), n, o_v[n], nw, s));
       if (!resample) break;

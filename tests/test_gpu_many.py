@@ -72,9 +72,11 @@ def test_many_equals_solo(mixed, threads):
         assert (M.cpu().numpy() == sM).all(), i
         total_valid += int(sM.sum())
     assert st["n_valid"] == total_valid
-    # one launch per stage: two census windows, matching once, 3 iterations at most
+    # one launch per stage: two census windows, matching once, 3 iterations at most; the
+    # batch is small enough for a star per wavefront (22.6k support candidates), so its star
+    # kernels rasterise their own triangles and it has no raster stage
     assert st["stage_launches"]["census"] == 2 and st["stage_launches"]["match"] == 1
-    assert st["stage_launches"]["validate"] == 3 and st["stage_launches"]["raster"] == 3
+    assert st["stage_launches"]["validate"] == 3 and st["stage_launches"]["raster"] == 0
 
 
 def test_many_against_oracle(mixed):
