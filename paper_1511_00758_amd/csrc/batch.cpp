@@ -459,11 +459,11 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
   for (int32_t f = 0; f < n; ++f)
     if (P.lay[f].mesh_on) mesh_candidates += P.lay[f].n_grid;
   const bool grouped = star_grouped(mesh_candidates);
-  // every frame's meshes on the device, a star per wavefront: the star kernel's workgroups
-  // rasterise the triangles they find, and the batch has no raster stage
+  // every frame's meshes on the device: the star kernel's workgroups rasterise the triangles
+  // they find, and the batch has no raster stage
   bool all_dev = true;
   for (int32_t f = 0; f < n; ++f) all_dev &= P.lay[f].mesh_on;
-  const bool star_raster = all_dev && !grouped;
+  const bool star_raster = all_dev;
   std::vector<uint8_t> mesh_dev(n, 0), job_start;
   std::vector<int32_t> host_upto(n, 0), nT_dev(n, 0), job_frame;
   auto add_job = [&](int32_t f, int32_t start, const int32_t* n_new) {

@@ -659,6 +659,7 @@ struct DevGroup16 {
 // counter (every wavefront adding its own would serialise thousands of same-address
 // atomics); a star with more triangles than its group has lanes reserves each full set
 // on its own.
+constexpr int kFlushSets = 15;  // full sets a 16-lane group's star records for its rasterisation
 template <int G>
 struct DevOut {
   int lane;   // in the group
@@ -672,6 +673,8 @@ struct DevOut {
   int32_t n = 0, total = 0;
   int32_t my1 = 0, my2 = 0;
   int32_t fl = 0, nfl = 0;  // a wavefront's full sets written so far: lane k holds set k's first slot
+  int32_t* fl_list = nullptr;  // a 16-lane group's (nullable, in LDS): [0] its full sets written
+                               // so far, [1 + k] set k's first slot (k < kFlushSets)
   __device__ void begin() { n = 0; }
   __device__ void write(int32_t slot) {
     if (lane < n) {
@@ -690,6 +693,12 @@ struct DevOut {
     if constexpr (G == 64) {
       if (lane == nfl) fl = slot;
       ++nfl;
+    } else {
+      if (fl_list && lane == 0) {
+        const int32_t k = fl_list[0];
+        if (k < kFlushSets) fl_list[1 + k] = slot;
+        fl_list[0] = k + 1;
+      }
     }
     total += n;
     n = 0;
@@ -719,7 +728,7 @@ __device__ void raster_sets(const StarJob& a, const DevOut<64>& out, int32_t n_s
   }
 }
 __device__ void raster_block(const StarJob& a, int32_t base, int32_t n, int32_t n_support) {
-  constexpr int kTris = 64 * kStarWaves / 16;
+  constexpr int kTris = 64 * kStarWaves / 16;  // (a star workgroup: 256 lanes)
   const int rl = threadIdx.x & 15;
   for (int32_t k0 = 0; k0 < n; k0 += kTris) {
     const int32_t k = k0 + (int32_t)(threadIdx.x >> 4);
@@ -795,7 +804,8 @@ __device__ void star_group16(const StarJob& a, int32_t star0) {
   __shared__ int32_t s_uv[kGroupStars][DevGroup16::kCap];
   __shared__ int32_t s_mark[kGroupStars][DevGroup16::kN * DevGroup16::kInFlight];
   __shared__ int32_t s_cnt[kGroupStars];
-  __shared__ int32_t s_base;
+  __shared__ int32_t s_base, s_sum;
+  __shared__ int32_t s_fl[kGroupStars][1 + kFlushSets];
   const int gi = threadIdx.x >> 4, lane = threadIdx.x & 15, gbase = (threadIdx.x & 63) & ~15;
   int32_t* status = a.status;
   const int32_t n = status[kMeshSupports];
@@ -804,6 +814,10 @@ __device__ void star_group16(const StarJob& a, int32_t star0) {
   const StarWork& w = a.w;
   DevOut<16> out{lane, gbase, p, a.T, a.T_cap, &status[kMeshTris],
                  a.status_copy ? &a.status_copy[kMeshTris] : nullptr, &status[kMeshErr]};
+  if (a.D) {
+    if (lane == 0) s_fl[gi][0] = 0;
+    out.fl_list = s_fl[gi];
+  }
   if (err0 == 0 && p < n && n <= a.w.S_cap) {  // (every group goes on to the barriers)
     const Grid g{w.uv, n, a.W, a.H, w.gw, w.gh, w.cell_start, w.cell_e, w.rows};
     DevGroup16 wv{lane, gbase, s_id[gi], s_uv[gi], s_mark[gi]};
@@ -827,11 +841,27 @@ __device__ void star_group16(const StarJob& a, int32_t star0) {
       if (out.counter_copy) atomicAdd(out.counter_copy, sum);
     }
     s_base = base;
+    s_sum = sum;
   }
   __syncthreads();
   int32_t off = s_base;
   for (int k = 0; k < gi; ++k) off += s_cnt[k];
   out.write(off);
+  if (a.D) {        // (the job's: uniform over the workgroup)
+    __syncthreads();  // every group's triangles in T before any lane reads them
+    // a group's full sets written earlier, a lane per triangle; a star with more of them
+    // than the group records sends the frame to the host
+    const int32_t nfl = s_fl[gi][0];
+    for (int32_t f = 0; f < nfl && f < kFlushSets; ++f) {
+      const int32_t t = s_fl[gi][1 + f] + lane;
+      if (t < a.T_cap) raster_rows(raster_setup(a.S, n, a.T, t, a.W, a.H), 0, 1, a.W, a.D);
+    }
+    if (nfl > kFlushSets && lane == 0) {
+      atomicCAS(&status[kMeshErr], 0, star::kStarErrCapacity);
+      if (a.status_copy) atomicCAS(&a.status_copy[kMeshErr], 0, star::kStarErrCapacity);
+    }
+    raster_block(a, s_base, s_sum, n);
+  }
 }
 
 __global__ __launch_bounds__(64 * kStarWaves) void k_star(StarJob a) {
