@@ -363,7 +363,8 @@ sm_status sm_solve_batch(sm_frame* frames, int32_t n, void* const* streams, void
  *   Synchronisation: when every frame keeps its meshes on the device (host_mesh = 0) the
  *   counts stay on the device and `stream` is synchronised once, at the end (a frame whose
  *   device mesh failed is then solved again alone with host meshes); otherwise once per
- *   triangulation round (max n_iters times).
+ *   triangulation round (max n_iters times). With every mesh on the device the batch has
+ *   no rasterisation launch: the star kernels rasterise the triangles they find.
  */
 size_t sm_solve_many_workspace_bytes(const sm_frame* frames /* [host] */, int32_t n);
 sm_status sm_solve_many(sm_frame* frames /* [host] */, int32_t n, void* ws, size_t ws_bytes,
