@@ -370,6 +370,21 @@ def fronto_shift(W, H, d, seed=0) -> Scene:
     return Scene(l, r, dd, vis, tex, {}, "fronto_shift", seed)
 
 
+def fan_pair(W, H, d=20, seed=0) -> Tuple[np.ndarray, np.ndarray]:
+    """A flat grey pair with two random-textured spots that both shift by ``d``: a band of
+    15 rows around row 405 and a 9 x 9 patch at the top of the centre column. The support
+    grid then finds one point at the top and one row of points near row 405 (nothing in
+    between), whose Delaunay mesh is a fan of about W / 10 long triangles around the top
+    point: the case of a mesh vertex with far more triangles than any natural scene."""
+    rng = np.random.default_rng(seed)
+    left = np.full((H, W), 128, np.uint8)
+    left[398:413, :] = rng.integers(0, 256, size=(15, W), dtype=np.uint8)
+    left[1:10, W // 2 + 1:W // 2 + 10] = rng.integers(0, 256, size=(9, 9), dtype=np.uint8)
+    right = np.full((H, W), 128, np.uint8)
+    right[:, :W - d] = left[:, d:]
+    return left, right
+
+
 def random_pair(W, H, seed) -> Tuple[np.ndarray, np.ndarray]:
     """Two independent uniform-random uint8 images (for census/matching edge cases)."""
     rng = np.random.default_rng(seed)

@@ -115,3 +115,45 @@ def test_device_mesh_repeated_solves_reuse_workspace():
     assert outs[0][1] == ref[3]["n_tris"] == outs[2][1]
     assert (outs[0][0].view(np.uint32) == ref[0].view(np.uint32)).all()
     assert (outs[2][0].view(np.uint32) == outs[0][0].view(np.uint32)).all()
+
+
+def test_device_mesh_fan_hub_against_oracle():
+    """One mesh vertex owning 122 triangles of the first tessellation (a fan from a single
+    point over a row of points): the star kernel writes them in full sets and rasterises
+    those sets after its walk; D_f, C_f and mask equal the oracle's bit for bit."""
+    import oracle
+    from paper_1511_00758_amd import api
+    left, right = scenes.fan_pair(1280, 480, seed=77)
+    prm = scenes.params_of(2)
+    _note("fan hub 1280x480")
+    r = api.Solver(1280, 480, prm, device=DEV)(_dev(left), _dev(right), stats=True)
+    torch.cuda.synchronize()
+    assert r.stats["n_tris"][0] == 122 and r.stats["mesh_device"] == prm["n_iters"]
+    assert r.stats["mesh_fallback"] == 0
+    ref = oracle.solve(left, right, oracle.Params.from_dict(prm))
+    assert (r.D_f.cpu().numpy().view(np.uint32) == ref["D_f"].view(np.uint32)).all()
+    assert (r.C_f.cpu().numpy() == ref["C_f"]).all()
+    assert (r.mask.cpu().numpy().astype(bool) == ref["mask"]).all()
+
+
+@pytest.mark.parametrize("W,n", [(1280, 12), (3200, 5)])
+def test_device_mesh_fan_hub_batches(W, n):
+    """Batches of fan frames large enough (over 64k support candidates) for a star per
+    16-lane group: a group records its full sets of 16 triangles for the rasterisation, up
+    to 15 of them; the 3200-column fan's hub owns about 310 triangles, more than that, so
+    those frames go to the host meshes. Every frame equals its solo solve."""
+    from paper_1511_00758_amd import api
+    left, right = scenes.fan_pair(W, 480, seed=78)
+    prm = scenes.params_of(2)
+    _note("fan batch", W, n)
+    solo = api.Solver(W, 480, prm, device=DEV)(_dev(left), _dev(right))
+    torch.cuda.synchronize()
+    exp = (solo.D_f.cpu().numpy(), solo.C_f.cpu().numpy(), solo.mask.cpu().numpy())
+    frames = [(_dev(left), _dev(right), prm) for _ in range(n)]
+    outs, st = api.ManySolver(4, device=DEV)(frames, stats=True)
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        got = tuple(t.cpu().numpy() for t in o)
+        assert (got[0].view(np.uint32) == exp[0].view(np.uint32)).all(), i
+        assert (got[1] == exp[1]).all() and (got[2] == exp[2]).all(), i
+    assert st["mesh_fallback"] == (n if W > 2048 else 0)
