@@ -400,18 +400,19 @@ void sm_many_graph_destroy(sm_many_graph* g);
  * sm_autotune -- measures the tunable launch shapes on one frame and records the fastest
  *   for its size (used by every later sm_solve / sm_solve_many launch of that size in this
  *   process; outputs do not depend on them): validation's block size in waves (1, 2, 4, 8
- *   or 16) for each iteration's cell size; for device meshes, the workgroups of the
- *   rasteriser's bounded grid (512 ... 8192); for grid supports, the matcher's lanes per
+ *   or 16) for each iteration's cell size; for grid supports, the matcher's lanes per
  *   candidate (64, 32 or 16: 1, 2 or 4 candidates per wave, each candidate's disparity
  *   range in chunks of that many lanes), per disparity range; and the census tile's rows
- *   (8, 16 or 32 rows of 64 columns), per window size. Times each candidate inside whole
- *   solves of the frame (one launch after another, the others at their best so far; the
- *   best of four runs of four solves), so that every kernel meets its inputs as the solve
- *   leaves them; the last solve leaves the frame's results in D_f, C_f and mask. About 100
- *   solves of the frame. Arguments as sm_solve.
+ *   (8, 16 or 32 rows of 64 columns), per window size. Times each candidate by the device
+ *   time of the launches it shapes, with events on those launches inside whole solves of
+ *   the frame (one launch after another, the others at their best so far; the best of four
+ *   runs of four solves), so that every kernel meets its inputs as the solve leaves them;
+ *   the last solve leaves the frame's results in D_f, C_f and mask. About 340 solves of
+ *   the frame. Arguments as sm_solve. (The rasteriser's bounded grid, kind 1 of
+ *   sm_set_launch_shape, is not tuned: no solve launches it, the star kernels rasterise.)
  *   choices  [host] [11] out: validation waves per iteration (0 past n_iters), the raster
- *            workgroups, the matcher's lanes per candidate, the census rows per tile (0
- *            where not tuned).
+ *            workgroups (0: not tuned), the matcher's lanes per candidate, the census rows
+ *            per tile (0 where not tuned).
  */
 sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
                       const sm_params* p /* [host] */, void* ws, size_t ws_bytes, float* D_f, uint8_t* C_f,

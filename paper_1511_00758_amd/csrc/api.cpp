@@ -796,9 +796,11 @@ sm_status sm_set_launch_shape(int32_t kind, int32_t W, int32_t H, int32_t key, i
 // batched and per-frame solves). Each tunable launch's candidates are timed inside whole
 // solves of the frame -- every kernel then sees its inputs and the caches as the solve
 // leaves them (timed alone, back to back, a kernel finds its inputs in its own L2 and the
-// order of the candidates can differ) -- one launch after another, the others at their
-// current best; the fastest is recorded for (W, H[, key]) and later solves of that size use
-// it. The last solve leaves the frame's results in D_f, C_f and mask.
+// order of the candidates can differ) -- by the device time of the launches they shape
+// (events on that stage only: a solve's wall time varies by more than the few microseconds
+// between candidates), one launch after another, the others at their current best; the
+// fastest is recorded for (W, H[, key]) and later solves of that size use it. The last
+// solve leaves the frame's results in D_f, C_f and mask.
 sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, int32_t stride,
                       const sm_params* p, void* ws, size_t ws_bytes, float* D_f, uint8_t* C_f, uint8_t* mask,
                       int32_t* choices, void* stream) {
@@ -812,27 +814,31 @@ sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, 
     int kind;
     int32_t key;
     std::vector<int> values;
-    int slot;  // in choices
+    int slot;   // in choices
+    int stage;  // the sm_stage of the launches it shapes
   };
   std::vector<Knob> knobs;
-  knobs.push_back({kTuneCensusRows, ((p->census_w - 1) / 2) << 8 | ((p->census_h - 1) / 2), {8, 16, 32}, 10});
+  knobs.push_back({kTuneCensusRows, ((p->census_w - 1) / 2) << 8 | ((p->census_h - 1) / 2), {8, 16, 32}, 10,
+                   SM_ST_CENSUS});
   if (p->support_mode == 0 && Lo.n_grid > 0)
-    knobs.push_back({kTuneMatchLanes, p->d_max - p->d_min + 1, {64, 32, 16}, 9});
-  if (Lo.mesh_on) knobs.push_back({kTuneRasterBlocks, 0, {512, 1024, 2048, 4096, 8192}, 8});
+    knobs.push_back({kTuneMatchLanes, p->d_max - p->d_min + 1, {64, 32, 16}, 9, SM_ST_MATCH});
   for (int it = 1; it <= p->n_iters && it <= 8; ++it)
-    knobs.push_back({kTuneValidateWaves, occ_size(*p, it), {1, 2, 4, 8, 16}, it - 1});
+    knobs.push_back({kTuneValidateWaves, occ_size(*p, it), {1, 2, 4, 8, 16}, it - 1, SM_ST_VALIDATE});
   for (const Knob& k : knobs) set_tuned_choice(k.kind, W, H, k.key, 0);  // the built-in rules to start
   SM_TRY(sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, nullptr, stream));
-  // wall time of one solve in seconds: the best of 4 runs of 4 solves (each solve waits for
-  // its frame)
-  auto time_solve = [&](double* t) -> sm_status {
-    using clk = std::chrono::steady_clock;
+  // device time of a stage's launches in one solve, from events on those launches only (the
+  // rest of the solve runs as usual): the best of 4 runs of 4 solves
+  auto time_stage = [&](int stage, double* t) -> sm_status {
     *t = -1.0;
     for (int run = 0; run < 4; ++run) {
-      const auto t0 = clk::now();
-      for (int r = 0; r < 4; ++r) SM_TRY(sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, nullptr, stream));
-      const double dt = std::chrono::duration<double>(clk::now() - t0).count() / 4;
-      if (*t < 0.0 || dt < *t) *t = dt;
+      double sum = 0.0;
+      for (int r = 0; r < 4; ++r) {
+        sm_stats st{};
+        st.timing = SM_TIME_SELECTED | (1 << stage);
+        SM_TRY(sm_solve(L, R, W, H, stride, p, ws, ws_bytes, D_f, C_f, mask, &st, stream));
+        sum += st.stage_us[stage];
+      }
+      if (*t < 0.0 || sum < *t) *t = sum;
     }
     return SM_OK;
   };
@@ -842,7 +848,7 @@ sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, 
     for (int v : k.values) {
       set_tuned_choice(k.kind, W, H, k.key, v);
       double t = 0.0;
-      SM_TRY(time_solve(&t));
+      SM_TRY(time_stage(k.stage, &t));
       if (best == 0 || t < best_t) best = v, best_t = t;
     }
     set_tuned_choice(k.kind, W, H, k.key, best);

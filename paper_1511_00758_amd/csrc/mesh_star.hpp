@@ -66,7 +66,9 @@ enum : int32_t {
   kStarErrSteps = 21,     // a walk around one point did not close within kStarMaxSteps
   kStarErrIndex = 22,     // a point id outside the frame's supports
   kStarErrCapacity = 23,  // more supports or triangles than the frame's arrays hold
-  kStarErrSupport = 24    // a support outside the frame
+  kStarErrSupport = 24,   // a support outside the frame
+  kStarErrSets = 25       // a star with more full triangle sets than its 16-lane group records
+                          // for their rasterisation
 };
 
 // A cell entry: a point id and its packed coordinates.

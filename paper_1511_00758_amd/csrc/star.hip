@@ -857,8 +857,8 @@ __device__ void star_group16(const StarJob& a, int32_t star0) {
       if (t < a.T_cap) raster_rows(raster_setup(a.S, n, a.T, t, a.W, a.H), 0, 1, a.W, a.D);
     }
     if (nfl > kFlushSets && lane == 0) {
-      atomicCAS(&status[kMeshErr], 0, star::kStarErrCapacity);
-      if (a.status_copy) atomicCAS(&a.status_copy[kMeshErr], 0, star::kStarErrCapacity);
+      atomicCAS(&status[kMeshErr], 0, star::kStarErrSets);
+      if (a.status_copy) atomicCAS(&a.status_copy[kMeshErr], 0, star::kStarErrSets);
     }
     raster_block(a, s_base, s_sum, n);
   }

@@ -67,8 +67,8 @@ struct StarJob {
   int32_t W, H;
   int32_t blocks;           // star-kernel workgroups of this frame (star_blocks / star_blocks_many)
   StarWork w;
-  float* D = nullptr;       // nullable: D_it [H][W]; the star kernel (a star per wavefront) then
-                            // rasterises every triangle it writes into it
+  float* D = nullptr;       // nullable: D_it [H][W]; the star kernels then rasterise every
+                            // triangle they write into it
 };
 
 // Star-kernel workgroups for a frame of at most S_cap supports: of launch_star (four stars
