@@ -423,7 +423,8 @@ sm_status sm_autotune(const uint8_t* L, const uint8_t* R, int32_t W, int32_t H, 
  *   clears it (value = 0: the built-in rule again), for reproducible timings and for
  *   checking that every shape gives the same results. Host only; thread-safe.
  *   kind 0: validation waves per block (1, 2, 4, 8, 16), key = cell size sz_occ;
- *   kind 1: raster workgroups (512, 1024, 2048, 4096, 8192), key = 0;
+ *   kind 1: raster workgroups (512, 1024, 2048, 4096, 8192), key = 0 (accepted, but no
+ *           current launch reads it: the solves' star kernels rasterise their meshes);
  *   kind 2: matcher lanes per candidate (16, 32, 64), key = d_max - d_min + 1;
  *   kind 3: census rows per tile (8, 16, 32), key = ((census_w-1)/2) << 8 | ((census_h-1)/2).
  *   Returns SM_ERR_ARG for another kind, value or size.
