@@ -432,7 +432,7 @@ sm_status many_impl(sm_frame* frames, int32_t n, void* ws, size_t ws_bytes, int3
     d.mask = fr.mask;
     d.n_grid = L.n_grid;
     d.match_lanes = match_lanes_for(fr.W, fr.H, fr.p);
-    d.census_rows = census_rows_for(fr.W, fr.H, fr.p.census_w, fr.p.census_h);
+    d.census_rows = census_rows_for(fr.W, fr.H, fr.p.census_w, fr.p.census_h, true);
     d.gw = L.n_grid > 0 ? (fr.W - 1 - fr.p.support_step / 2) / fr.p.support_step + 1 : 0;
     d.sz = occ_size(fr.p, 1);
     d.pack = L.mesh_on ? nullptr : dpack + P.pack_off[f];  // device-mesh frames keep their supports

@@ -184,9 +184,10 @@ struct BatchFrame {
 };
 
 // census tiles of a W x H image at `rows` rows per tile, and the rows a W x H image with a
-// cw x ch window uses (the sm_autotune choice, else 16)
+// cw x ch window uses (the sm_autotune choice, else 8 in a single frame's launch and 16 in
+// the batched census)
 int32_t census_tiles(int32_t W, int32_t H, int32_t rows);
-int32_t census_rows_for(int32_t W, int32_t H, int32_t cw, int32_t ch);
+int32_t census_rows_for(int32_t W, int32_t H, int32_t cw, int32_t ch, bool batched);
 int32_t validate_blocks(int32_t W, int32_t H, int32_t sz, int nw);
 // smallest block size (waves) whose batched grid still holds enough waves
 int validate_pick_nw(int64_t (*waves)(int nw, void* ctx), void* ctx);
